@@ -1,0 +1,388 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix (CPU).
+
+None of these re-types an oracle formula: each compares the oracle with a
+closed form, an independent formulation (four-index pair space, the GF2
+direct term of Eq. sigma2, explicit (ij|kl) integrals), a limit (MP2) or an
+invariant.
+"""
+import itertools
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import gw
+from synth import configs, grid as gridmod, systems
+
+
+def _km(kmesh):
+    return gw.KMesh(kmesh)
+
+
+def _V4(V, km, k1, k2, k3, k4):
+    """(k1 i, k2 j | k3 k, k4 l) = sum_Q V^{k1,k2}_{ij}(Q) V^{k3,k4}_{kl}(Q)  (Eq. CoulombDF)."""
+    A = gw.V_pair(V, km, k1, k2)
+    B = gw.V_pair(V, km, k3, k4)
+    return np.einsum("Qij,Qkl->ijkl", A, B)
+
+
+# ============================================================================ brute force (tiny)
+@pytest.fixture(scope="module")
+def tiny8():
+    sp = configs.tiny(kmesh=(2, 2, 2), nao=2, naux=3, ntau=6, beta=5.0, seed=31)
+    s = systems.make_system(sp)
+    G = systems.random_green(77, 1, sp.ntau, sp.nk, sp.nao, scale=0.3)
+    return s, G
+
+
+def test_polarization_brute_force(tiny8):
+    """Six-index loop over (k, a, b, c, d) per (q, t, Q, Q') with explicit momentum lookups."""
+    s, G = tiny8
+    km = _km(s.spec.kmesh)
+    P = gw.polarization(s.V, G, s.spec.kmesh)
+    nk, ntau, naux, nao = s.spec.nk, s.spec.ntau, s.spec.naux, s.spec.nao
+    for q, t in [(0, 0), (3, 2), (7, 5), (5, 1)]:
+        ref = np.zeros((naux, naux), dtype=complex)
+        for Q, Qp, k in itertools.product(range(naux), range(naux), range(nk)):
+            kq = km.add(k, q)
+            Vl = gw.V_pair(s.V, km, k, kq)[Q]
+            Vr = gw.V_pair(s.V, km, kq, k)[Qp]
+            acc = 0.0
+            for a, b, c, d in itertools.product(range(nao), repeat=4):
+                acc += Vl[d, a] * G[0, ntau - 1 - t, k][c, d] * G[0, t, kq][a, b] * Vr[b, c]
+            ref[Q, Qp] += -2.0 / nk * acc
+        assert np.allclose(P[q, t], ref, atol=1e-14, rtol=1e-13)
+
+
+def test_selfenergy_brute_force(tiny8):
+    """Explicit four-index W~_{iabj} = sum_QQ' V V P V, then Sigma = -(1/Nk) sum_q sum_ab G W~ (Eq. sigma_gw)."""
+    s, G = tiny8
+    km = _km(s.spec.kmesh)
+    nk, nao = s.spec.nk, s.spec.nao
+    Pt = systems.random_polarization(5, nk, s.spec.ntau, s.spec.naux, scale=0.2)
+    Sig = gw.selfenergy(s.V, G, Pt, s.spec.kmesh)
+    for k, t in [(0, 0), (6, 3), (3, 5)]:
+        ref = np.zeros((nao, nao), dtype=complex)
+        for q in range(nk):
+            kmq = km.sub(k, q)
+            W = np.einsum("Qia,QR,Rbj->iabj", gw.V_pair(s.V, km, k, kmq), Pt[q, t], gw.V_pair(s.V, km, kmq, k))
+            for i, j, a, b in itertools.product(range(nao), repeat=4):
+                ref[i, j] += -1.0 / nk * G[0, t, kmq][a, b] * W[i, a, b, j]
+        assert np.allclose(Sig[0, t, k], ref, atol=1e-15, rtol=1e-13)
+
+
+def test_sigma_inf_against_explicit_coulomb(tiny8):
+    """Eq. sigma_inf from explicit (ij|kl) integrals: J - K with G(0^-) = -G(beta^-)."""
+    s, G = tiny8
+    km = _km(s.spec.kmesh)
+    nk, nao = s.spec.nk, s.spec.nao
+    Sinf = gw.sigma_inf(s.V, G, s.spec.kmesh)
+    gam = -G[0, -1]
+    for k in range(nk):
+        ref = np.zeros((nao, nao), dtype=complex)
+        for kp in range(nk):
+            J = _V4(s.V, km, k, k, kp, kp)  # (k i, k j | k' b, k' a)
+            K = _V4(s.V, km, k, kp, kp, k)  # (k i, k' a | k' b, k j)
+            ref += 2.0 / nk * np.einsum("ijba,ab->ij", J, gam[kp])
+            ref -= 1.0 / nk * np.einsum("iabj,ab->ij", K, gam[kp])
+        assert np.allclose(Sinf[0, k], ref, atol=1e-15, rtol=1e-13)
+
+
+def test_unrestricted_spin_sums():
+    """nspin = 2 with two equal channels reproduces the restricted run (spin factor reading)."""
+    sp = configs.tiny(kmesh=(2, 1, 1), nao=3, naux=4, ntau=8, beta=6.0, seed=12)
+    s = systems.make_system(sp)
+    G1 = s.G0
+    G2 = np.concatenate([G1, G1], axis=0)
+    assert np.allclose(gw.polarization(s.V, G1, sp.kmesh), gw.polarization(s.V, G2, sp.kmesh), atol=1e-15)
+    S1 = gw.sigma_inf(s.V, G1, sp.kmesh)
+    S2 = gw.sigma_inf(s.V, G2, sp.kmesh)
+    assert np.allclose(S2[0], S1[0], atol=1e-15) and np.allclose(S2[1], S1[0], atol=1e-15)
+
+
+# ============================================================================ closed forms
+def test_single_level_closed_form():
+    """Nk = nao = naux = 1, real v, level e, mu = 0:
+    P0 = -2 v^2 f (1-f) (constant), P~(tau) = P0 / (1 - beta P0), Sigma~(tau) = (1-f) e^{-e tau} v^2 P~."""
+    for beta, eps, v, ntau in [(10.0, 0.3, 0.4, 8), (50.0, -0.05, 0.7, 20), (20.0, 0.0, 1.1, 12)]:
+        g = gridmod.make_grid(ntau, beta)
+        H0 = np.full((1, 1, 1, 1), eps, dtype=complex)
+        S = np.ones((1, 1, 1), dtype=complex)
+        V = np.full((1, 1, 1, 1, 1), v, dtype=complex)
+        G0 = systems.noninteracting_G(H0, S, g.tau, beta, 0.0)
+        f = 1.0 / (1.0 + np.exp(beta * eps))
+        p0 = -2.0 * v * v * f * (1.0 - f)
+        P0 = gw.polarization(V, G0, (1, 1, 1))
+        assert np.allclose(P0[0, :, 0, 0], p0, rtol=1e-13, atol=1e-15)
+        Pt = gw.from_bosonic(gw.screen(gw.to_bosonic(P0, g.TB_t2w)), g.TB_w2t)
+        pt = p0 / (1.0 - beta * p0)
+        assert np.allclose(Pt[0, :, 0, 0], pt, rtol=1e-11, atol=1e-15)
+        Sig = gw.selfenergy(V, G0, Pt, (1, 1, 1))
+        ref = (1.0 - f) * np.exp(-eps * g.tau) * v * v * pt
+        assert np.allclose(Sig[0, :, 0, 0, 0], ref, rtol=1e-11, atol=1e-16)
+
+
+def test_lindhard_closed_form():
+    """Non-interacting bubble: P0^q(i W_n) = (2/Nk) sum_k sum_{a in k+q, c in k}
+    M^Q_{ca} conj(M^{Q'}_{ca}) (f_a - f_c)/(e_a - e_c - i W_n), M^Q = C_c^H V^{k,k+q}(Q) C'_a,
+    with the limit -beta f(1-f) at e_a = e_c, W = 0."""
+    sp = configs.tiny(kmesh=(2, 2, 1), nao=3, naux=4, ntau=48, beta=10.0, band=1.0, seed=41)
+    s = systems.make_system(sp)
+    km = _km(sp.kmesh)
+    P0 = gw.polarization(s.V, s.G0, sp.kmesh)
+    Pw = gw.to_bosonic(P0, s.grid.TB_t2w)
+    eig = [scipy.linalg.eigh(s.H0[0, k], s.S[k]) for k in range(sp.nk)]
+    beta = sp.beta
+    for q in range(sp.nk):
+        for m in [0, len(s.grid.nb) // 2, len(s.grid.nb) // 2 + 3, len(s.grid.nb) - 1]:
+            W = s.grid.wb[m]
+            ref = np.zeros((sp.naux, sp.naux), dtype=complex)
+            for k in range(sp.nk):
+                kq = km.add(k, q)
+                ec, Cc = eig[k]
+                ea, Ca = eig[kq]
+                fc = systems.fermi(ec, beta)
+                fa = systems.fermi(ea, beta)
+                M = np.einsum("ic,Qij,ja->Qca", Cc.conj(), gw.V_pair(s.V, km, k, kq), Ca)
+                den = ea[None, :] - ec[:, None] - 1j * W
+                with np.errstate(divide="ignore", invalid="ignore"):
+                    fac = (fa[None, :] - fc[:, None]) / den
+                deg = np.abs(den) < 1e-12
+                fac[deg] = (-beta * fa[None, :] * (1 - fa[None, :]) * np.ones_like(den))[deg]
+                ref += 2.0 / sp.nk * np.einsum("Qca,Rca,ca->QR", M, M.conj(), fac)
+            assert np.max(np.abs(Pw[q, m] - ref)) < 1e-11 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_pair_space_bubble_series():
+    """RPA in the four-index pair space, with no auxiliary index: W~ = U_L chi [I - U chi]^{-1} U_R.
+
+    For each q and bosonic node, chi^q_{(k',d,a),(k',b,c)}(i W) is the Fourier image of
+    -(2/Nk) G^{k'}_{cd}(beta - tau) G^{k'+q}_{ab}(tau) and U, U_L, U_R are explicit (ij|kl)
+    integrals.  By the push-through identity this equals sum_QQ' V P~ V of Eq. tilde_W_DF2.
+    Sigma~ = -(1/Nk) sum_q sum_ab G^{k-q}(tau) W~(tau) is compared with the oracle.
+    """
+    sp = configs.tiny(kmesh=(2, 1, 1), nao=2, naux=3, ntau=12, beta=4.0, seed=51, v_scale=0.6)
+    s = systems.make_system(sp)
+    km = _km(sp.kmesh)
+    nk, nao, ntau = sp.nk, sp.nao, sp.ntau
+    g = s.grid
+    G = s.G0
+    Sinf, Sig, inter = gw.sigma_eval(s.V, G, sp.kmesh, g)
+    npair = nk * nao * nao
+    Wt = np.zeros((nk, nk, ntau, nao, nao, nao, nao), dtype=complex)  # [k][q][t][i][a][b][j]
+    for q in range(nk):
+        # chi(tau) in pair space, block diagonal over k'
+        chi_t = np.zeros((ntau, npair, npair), dtype=complex)
+        for kp in range(nk):
+            kq = km.add(kp, q)
+            for t in range(ntau):
+                blk = -2.0 / nk * np.einsum("cd,ab->dabc", G[0, ntau - 1 - t, kp], G[0, t, kq])
+                sl = slice(kp * nao * nao, (kp + 1) * nao * nao)
+                chi_t[t, sl, sl] = blk.reshape(nao * nao, nao * nao)
+        chi_w = np.einsum("mt,tab->mab", g.TB_t2w, chi_t)
+        # U[(k',b,c),(k'',d,a)] = (k'+q b, k' c | k'' d, k''+q a)
+        U = np.zeros((npair, npair), dtype=complex)
+        for k1 in range(nk):
+            for k2 in range(nk):
+                blk = _V4(s.V, km, km.add(k1, q), k1, k2, km.add(k2, q))  # [b][c][d][a]
+                U[k1 * nao * nao:(k1 + 1) * nao * nao, k2 * nao * nao:(k2 + 1) * nao * nao] = blk.reshape(
+                    nao * nao, nao * nao)
+        for k in range(nk):
+            kmq = km.sub(k, q)
+            # UL[(i,a),(k'',d,a')] = (k i, k-q a | k'' d, k''+q a');  UR[(k',b,c),(b',j)] = (k'+q b, k' c | k-q b', k j)
+            UL = np.zeros((nao * nao, npair), dtype=complex)
+            UR = np.zeros((npair, nao * nao), dtype=complex)
+            for k2 in range(nk):
+                UL[:, k2 * nao * nao:(k2 + 1) * nao * nao] = _V4(s.V, km, k, kmq, k2, km.add(k2, q)).reshape(
+                    nao * nao, nao * nao)
+                UR[k2 * nao * nao:(k2 + 1) * nao * nao, :] = _V4(s.V, km, km.add(k2, q), k2, kmq, k).reshape(
+                    nao * nao, nao * nao)
+            Ww = np.stack([UL @ chi_w[m] @ np.linalg.solve(np.eye(npair) - U @ chi_w[m], UR)
+                           for m in range(chi_w.shape[0])])
+            Wtau = np.einsum("tm,mab->tab", g.TB_w2t, Ww)  # [t][(i,a)][(b,j)]
+            Wt[k, q] = Wtau.reshape(ntau, nao, nao, nao, nao)
+    ref = np.zeros_like(Sig)
+    for k in range(nk):
+        for q in range(nk):
+            kmq = km.sub(k, q)
+            ref[0, :, k] += -1.0 / nk * np.einsum("tab,tiabj->tij", G[0, :, kmq], Wt[k, q])
+    assert np.max(np.abs(Sig - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("kmesh", [(1, 1, 1), (2, 2, 2)])
+def test_first_order_equals_gf2_direct(kmesh):
+    """Feeding P~ := P0(tau) into Sigma~ gives the direct term of Eq. sigma2, evaluated literally with
+    the antiperiodic G(-tau) = -G(beta - tau) and the lattice delta read as Nk times a Kronecker delta."""
+    sp = configs.tiny(kmesh=kmesh, nao=2, naux=2, ntau=6, beta=3.0, seed=61)
+    s = systems.make_system(sp)
+    km = _km(kmesh)
+    G = systems.random_green(8, 1, sp.ntau, sp.nk, sp.nao, scale=0.4)
+    nk, nao, ntau = sp.nk, sp.nao, sp.ntau
+    P0 = gw.polarization(s.V, G, kmesh)
+    Sig = gw.selfenergy(s.V, G, P0, kmesh)
+    for k, t in [(0, 1), (nk - 1, 4), (nk // 2, 0)]:
+        ref = np.zeros((nao, nao), dtype=complex)
+        for k1, k2, k3 in itertools.product(range(nk), repeat=3):
+            if km.add(k, k3) != km.add(k1, k2):
+                continue
+            Gm = -G[0, ntau - 1 - t, k3]  # G^{k3}(-tau)
+            for Q, Qp in itertools.product(range(sp.naux), repeat=2):
+                Va = gw.V_pair(s.V, km, k1, k)[Qp]  # V^{k1 k}_{qj}(Q')
+                Vb = gw.V_pair(s.V, km, k2, k3)[Qp]  # V^{k2 k3}_{ln}(Q')
+                Vc = gw.V_pair(s.V, km, k, k1)[Q]  # V^{k k1}_{ip}(Q)
+                Vd = gw.V_pair(s.V, km, k3, k2)[Q]  # V^{k3 k2}_{mk}(Q)
+                for i, j in itertools.product(range(nao), repeat=2):
+                    acc = 0.0
+                    for kk, l, m, n, p, qq in itertools.product(range(nao), repeat=6):
+                        acc += (Va[qq, j] * Vb[l, n] * Vc[i, p] * Vd[m, kk]
+                                * G[0, t, k1][p, qq] * G[0, t, k2][kk, l] * Gm[n, m])
+                    ref[i, j] += 2.0 * acc  # sum over sigma' (restricted)
+        ref *= -1.0 / nk ** 2  # 1/Nk^3 times the lattice delta Nk
+        assert np.allclose(Sig[0, t, k], ref, atol=1e-15, rtol=1e-12)
+
+
+def test_mp2_direct_limit():
+    """Gapped G0, Nk = 1, beta = 100: E_corr[Sigma^(1)[G0], G0] -> 2 E_MP2(direct),
+    E_MP2(direct) = -2 sum_{ij occ, ab virt} (ia|jb)(ai|bj)/(e_a + e_b - e_i - e_j)
+    (the Galitskii-Migdal interaction energy is twice the second-order energy)."""
+    beta, ntau = 100.0, 104
+    g = gridmod.make_grid(ntau, beta)
+    rng = np.random.default_rng(3)
+    e = np.array([-0.9, -0.55, -0.3, 0.3, 0.6, 1.0])
+    n = len(e)
+    U = np.linalg.qr(rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n)))[0]
+    H0 = ((U * e) @ U.conj().T)[None, None]
+    S = np.eye(n, dtype=complex)[None]
+    Z = (rng.normal(size=(4, n, n)) + 1j * rng.normal(size=(4, n, n))) * 0.1
+    V = (0.5 * (Z + np.conj(np.swapaxes(Z, 1, 2))))[None, None]
+    G0 = systems.noninteracting_G(H0, S, g.tau, beta, 0.0)
+    P0 = gw.polarization(V, G0, (1, 1, 1))
+    Sig = gw.selfenergy(V, G0, P0, (1, 1, 1))
+    E = gw.energy(G0, H0, np.zeros_like(H0), Sig, beta)
+    Vmo = np.einsum("ia,Qij,jb->Qab", U.conj(), V[0, 0], U)
+    occ, vir = [0, 1, 2], [3, 4, 5]
+    emp2 = 0.0
+    for i, j, a, b in itertools.product(occ, occ, vir, vir):
+        iajb = np.sum(Vmo[:, i, a] * Vmo[:, j, b])
+        aibj = np.sum(Vmo[:, a, i] * Vmo[:, b, j])
+        emp2 += -2.0 * (iajb * aibj).real / (e[a] + e[b] - e[i] - e[j])
+    assert abs(E["e_corr"] - 2.0 * emp2) < 1e-9 * abs(emp2) + 1e-13
+
+
+def test_two_level_worked_example():
+    """One occupied and one virtual level, one auxiliary function with V_ia = V_ai = v:
+    E_corr -> -2 v^4 / (e_a - e_i) (twice the MP2 value -v^4 / (e_a - e_i))."""
+    beta, ntau = 100.0, 104
+    g = gridmod.make_grid(ntau, beta)
+    ei, ea, v = -0.5, 0.4, 0.3
+    H0 = np.diag([ei, ea]).astype(complex)[None, None]
+    V = np.array([[[0.0, v], [v, 0.0]]], dtype=complex)[None, None]
+    S = np.eye(2, dtype=complex)[None]
+    G0 = systems.noninteracting_G(H0, S, g.tau, beta, 0.0)
+    Sig = gw.selfenergy(V, G0, gw.polarization(V, G0, (1, 1, 1)), (1, 1, 1))
+    E = gw.energy(G0, H0, np.zeros_like(H0), Sig, beta)
+    assert abs(E["e_corr"] - (-2.0 * v ** 4 / (ea - ei))) < 1e-11
+
+
+def test_energy_integral_closed_form():
+    """int_0^beta Tr[F(tau) H(beta - tau)] for F = e^{-x tau}, H = e^{-y tau} (1x1): closed form."""
+    beta, ntau = 20.0, 64
+    g = gridmod.make_grid(ntau, beta)
+    x, y = 0.3, -0.2
+    F = np.exp(-x * g.tau)[:, None, None, None].astype(complex)
+    H = np.exp(-y * g.tau)[:, None, None, None].astype(complex)
+    got = gw.tau_integral_product(F, H, beta)
+    # int_0^beta e^{-x tau} e^{-y (beta - tau)} = e^{-y beta} (e^{(y - x) beta} - 1) / (y - x)
+    ref = np.exp(-y * beta) * (np.exp((y - x) * beta) - 1.0) / (y - x)
+    assert abs(got - ref) < 1e-11 * abs(ref)
+
+
+def test_noninteracting_dyson_closed_form():
+    """Sigma = 0: Dyson + mu search + TF_w2t reproduce G0(tau) = -C diag(e^{-x tau}/(1+e^{-beta x})) C^H
+    for a general overlap S, N(mu*) = N_target, and G(0+) + G(beta-) = -S^{-1}."""
+    sp = configs.tiny(kmesh=(2, 1, 1), nao=5, naux=3, ntau=48, beta=50.0, band=1.0, s_identity=False, seed=71)
+    s = systems.make_system(sp)
+    zero_inf = np.zeros_like(s.H0)
+    zero_tau = np.zeros((1, sp.ntau, sp.nk, sp.nao, sp.nao), dtype=complex)
+    G, mu, n = gw.solve_dyson(s.H0, s.S, zero_inf, zero_tau, s.grid, sp.nspin, 0.37, s.n_target)
+    assert abs(n - s.n_target) <= 1e-12 * s.n_target
+    assert abs(mu - 0.0) < 1e-8
+    assert np.max(np.abs(G - s.G0)) < 1e-10
+    for k in range(sp.nk):
+        assert np.allclose(G[0, 0, k] + G[0, -1, k], -np.linalg.inv(s.S[k]), atol=1e-10)
+
+
+def test_mu_search_hits_target():
+    """Shifting the target electron count moves mu to the closed-form root of sum_a f(e_a - mu)."""
+    sp = configs.tiny(kmesh=(1, 1, 1), nao=6, naux=3, ntau=48, beta=20.0, band=1.0, seed=81)
+    s = systems.make_system(sp)
+    e = np.linalg.eigvalsh(s.H0[0, 0])
+    target = 2.0 * np.sum(systems.fermi(e - 0.123, sp.beta))
+    z_inf = np.zeros_like(s.H0)
+    z_tau = np.zeros((1, sp.ntau, 1, sp.nao, sp.nao), dtype=complex)
+    G, mu, n = gw.solve_dyson(s.H0, s.S, z_inf, z_tau, s.grid, 1, 0.0, target)
+    assert abs(mu - 0.123) < 1e-9
+    assert abs(n - target) < 1e-11
+
+
+# ============================================================================ invariants
+@pytest.fixture(scope="module")
+def physical():
+    sp = configs.tiny(kmesh=(3, 1, 1), nao=4, naux=6, ntau=32, beta=10.0, band=1.5, seed=91, v_scale=0.3,
+                      v_time_reversal=True)
+    s = systems.make_system(sp)
+    Sinf, Sig, inter = gw.sigma_eval(s.V, s.G0, sp.kmesh, s.grid)
+    return s, Sinf, Sig, inter
+
+
+def test_polarization_invariants(physical):
+    s, _, _, inter = physical
+    P0, Pw = inter["P0"], inter["Pw"]
+    km = _km(s.spec.kmesh)
+    neg = systems.k_neg(s.spec.kmesh)
+    ntau = s.spec.ntau
+    sc = np.max(np.abs(P0))
+    # Hermitian in (Q, Q') at every tau
+    assert np.max(np.abs(P0 - np.conj(np.swapaxes(P0, -1, -2)))) < 1e-14 * sc * 10
+    # P0^q(beta - tau) = P0^{-q}(tau)^T
+    for q in range(km.nk):
+        assert np.max(np.abs(P0[q, ::-1] - np.swapaxes(P0[neg[q]], -1, -2))) < 1e-13 * sc
+    # non-positive diagonal, and Hermitian part of P0(i W) negative semidefinite
+    assert np.all(np.einsum("qtaa->qta", P0).real <= 1e-15)
+    for q in range(km.nk):
+        for m in range(Pw.shape[1]):
+            h = 0.5 * (Pw[q, m] + Pw[q, m].conj().T)
+            assert np.max(np.linalg.eigvalsh(h)) < 1e-12
+            assert np.min(np.linalg.svd(np.eye(h.shape[0]) - Pw[q, m], compute_uv=False)) > 1.0 - 1e-12
+    del ntau
+
+
+def test_screening_residual(physical):
+    _, _, _, inter = physical
+    Pw, Ptw = inter["Pw"], inter["Ptw"]
+    res = Ptw - Pw - np.matmul(Pw, Ptw)
+    assert np.max(np.abs(res)) < 1e-14 * max(1.0, np.max(np.abs(Ptw)))
+
+
+def test_selfenergy_symmetries(physical):
+    """Hermiticity, causality (diagonal <= 0 with S = I) and time reversal Sigma^{-k} = conj Sigma^k."""
+    s, Sinf, Sig, _ = physical
+    sc = np.max(np.abs(Sig))
+    assert np.max(np.abs(Sig - np.conj(np.swapaxes(Sig, -1, -2)))) < 1e-12 * sc
+    assert np.all(np.einsum("stkii->stki", Sig).real <= 1e-15)
+    neg = systems.k_neg(s.spec.kmesh)
+    for k in range(s.spec.nk):
+        assert np.max(np.abs(Sig[:, :, neg[k]] - np.conj(Sig[:, :, k]))) < 1e-12 * sc
+        assert np.max(np.abs(Sinf[:, neg[k]] - np.conj(Sinf[:, k]))) < 1e-13
+
+
+def test_iteration_runs_and_contracts():
+    """Config-0-shaped system: 10 iterations, fixed N, shrinking max|dSigma|."""
+    s = systems.make_system(configs.MOLECULE)
+    st = gw.State(s.G0, None, None, 0.0)
+    d = []
+    for _ in range(10):
+        st, rep, _ = gw.iterate(s, st)
+        assert abs(rep["n_elec"] - s.n_target) < 1e-11
+        d.append(rep["max_dsigma"])
+    assert d[-1] < 1e-2 * d[1]
