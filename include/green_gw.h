@@ -1,0 +1,187 @@
+/*
+ * green_gw.h -- C ABI of the MI355X (gfx950) GW self-energy hot path.
+ *
+ * The library evaluates one fully self-consistent GW iteration as described in
+ * Iskakov et al., "Green/WeakCoupling" (Sec. 2: Eqs. sigma_inf, sigma_gw,
+ * tilde_W_DF2, tilde_P_omega, P0t_to_P0w, tilde_P0_tau, dyson; Sec. 2.3 for the
+ * loop, Sec. 4.2.2 for iteration mixing) on one GPU.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All arrays are row-major.  "complex" means interleaved (re, im) doubles,
+ *    i.e. the memory layout of C99 double _Complex and of torch.complex128.
+ *  - Atomic units: energies in Hartree, beta in 1/Hartree.
+ *  - k-mesh: Gamma-centred m0 x m1 x m2 Monkhorst-Pack mesh, nk = m0*m1*m2,
+ *    k = (i0, i1, i2) has flat index (i0*m1 + i1)*m2 + i2; k+q, k-q, -k are
+ *    taken component-wise modulo the mesh.
+ *  - Layouts (device memory, complex):
+ *        V      [nk(q)][nk(k)][naux][nao][nao]   V[q][k] = V^{k,k+q}_{ij}(Q)
+ *        G      [nspin][ntau][nk][nao][nao]      G^k_s(tau_t)
+ *        H0     [nspin][nk][nao][nao]            H^{k,(0)}
+ *        S      [nk][nao][nao]                   overlap S^k
+ *        Sinf   [nspin][nk][nao][nao]            Sigma^{inf,k}_s
+ *        Sigma  [nspin][ntau][nk][nao][nao]      dynamic Sigma~^k_s(tau_t)
+ *        P0, Pt [nk(q)][ntau][naux][naux]        P~0^q(tau_t), P~^q(tau_t)
+ *    V must hold every ordered pair (k1, k2) with the Hermitian pairing
+ *    V^{k2,k1}_{ij}(Q) = conj V^{k1,k2}_{ji}(Q) (real auxiliary basis).
+ *  - tau grid: symmetric (tau_t + tau_{ntau-1-t} = beta) Chebyshev-Lobatto
+ *    nodes, tau_0 = 0+ and tau_{ntau-1} = beta-.  G(beta - tau_t) is node
+ *    ntau-1-t and G(0^-) = -G(beta^-).
+ *  - nspin = 1 is a spin-restricted run (one stored channel standing for two
+ *    equal spins: the spin sums of Eqs. tilde_P0_tau and sigma_inf's Hartree
+ *    term count it twice); nspin = 2 is unrestricted.
+ *
+ * Ownership: the caller owns every buffer, including the workspace, whose size
+ * green_workspace_bytes() reports.  The library never allocates device memory.
+ * The plan is host-only state.  The first call with a given workspace uploads
+ * the grid matrices and k-index tables into it (ordered on the given stream).
+ *
+ * Synchronisation: green_gw_polarization, green_gw_screen and
+ * green_gw_selfenergy only enqueue work on `stream`.  green_dyson and
+ * green_gw_iterate return host scalars and synchronise `stream`.
+ *
+ * Errors: every entry point returns a green_status.  Argument errors are
+ * detected before any launch.  Numerical failures (a zero pivot in a batched
+ * inversion, a non-finite result, a chemical potential that cannot be
+ * bracketed or converged) are reported by the next synchronising call.
+ */
+#ifndef GREEN_GW_H
+#define GREEN_GW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GREEN_OK = 0,
+  GREEN_EINVAL = -1,      /* bad argument: null pointer, bad dimension, unsupported size */
+  GREEN_ENOMEM = -2,      /* workspace smaller than green_workspace_bytes() */
+  GREEN_EHIP = -3,        /* a HIP runtime call failed */
+  GREEN_ESINGULAR = -4,   /* zero pivot in a batched inversion */
+  GREEN_ENOCONV = -5,     /* chemical potential not bracketed / not converged */
+  GREEN_ENAN = -6,        /* non-finite value in a result */
+  GREEN_EUNSUPPORTED = -7 /* valid request this build cannot serve */
+} green_status;
+
+/* Arithmetic of the two dominant contractions (P~0 and Sigma~).  Inputs and
+ * outputs stay complex FP64; only the contraction arithmetic changes. */
+typedef enum {
+  GREEN_FP64 = 0,  /* complex FP64 on v_mfma_f64_16x16x4 (4M)                       */
+  GREEN_FP32 = 1,  /* complex FP32 on MFMA with FP32 accumulation                      */
+  GREEN_BF16X3 = 2 /* split BF16 (hi + lo, three products) with FP32 accumulation      */
+} green_prec;
+
+typedef struct {
+  int32_t kmesh[3]; /* Monkhorst-Pack mesh m0, m1, m2                                   */
+  int32_t nao;      /* orbitals per k-point                                              */
+  int32_t naux;     /* auxiliary (density-fitting) functions Q                            */
+  int32_t ntau;     /* imaginary-time nodes (even, >= 4)                                 */
+  int32_t nw_f;     /* fermionic Matsubara nodes of the grid                              */
+  int32_t nw_b;     /* bosonic Matsubara nodes of the grid                                */
+  int32_t nspin;    /* 1 = restricted, 2 = unrestricted                                   */
+  double beta;      /* inverse temperature                                                */
+} green_dims;
+
+/* Grid data (the method's "grid file", Sec. 4.2).  Host pointers, copied by
+ * green_plan_create; complex matrices are row-major.
+ *   X(i w_m)  = sum_t TF_t2w[m][t] X(tau_t)   (fermionic, exact Fourier integral of the interpolant)
+ *   X(tau_t)  = sum_m TF_w2t[t][m] X(i w_m)   (its least-squares inverse)
+ *   TB_t2w / TB_w2t: the same for bosonic frequencies (Eq. P0t_to_P0w and its inverse). */
+typedef struct {
+  const double* tau;  /* [ntau] nodes, Chebyshev-Lobatto on [0, beta]                  */
+  const double* wf;   /* [nw_f] fermionic Matsubara frequencies w_m = (2n+1) pi / beta   */
+  const double* wb;   /* [nw_b] bosonic Matsubara frequencies  W_m = 2 n pi / beta       */
+  const void* TF_t2w; /* complex [nw_f][ntau] */
+  const void* TF_w2t; /* complex [ntau][nw_f] */
+  const void* TB_t2w; /* complex [nw_b][ntau] */
+  const void* TB_w2t; /* complex [ntau][nw_b] */
+} green_grid;
+
+/* Result of one iteration (host). */
+typedef struct {
+  double e_1b;       /* (2/ns)(1/nk) sum Re Tr[gamma H0]                                  */
+  double e_hf;       /* (1/ns)(1/nk) sum Re Tr[gamma Sigma^inf]                           */
+  double e_corr;     /* -(1/ns)(1/nk) sum int_0^beta Re Tr[Sigma~(tau) G(beta - tau)]     */
+  double e_tot;      /* e_1b + e_hf + e_corr (Galitskii-Migdal, no nuclear term)          */
+  double n_elec;     /* electron count of the new G                                       */
+  double mu;         /* chemical potential                                                */
+  double max_dsigma; /* max |Sigma~_new - Sigma~_old| (after mixing)                      */
+  double herm_err;   /* max |Sigma~ - Sigma~^H|                                           */
+  int32_t mu_evals;  /* electron-count evaluations in the mu search                       */
+  int32_t pad;
+  float ms[8];       /* stage times (ms): 0 HF, 1 P0, 2 screen, 3 Sigma, 4 mix, 5 Dyson+mu, 6 energy, 7 total */
+} green_report;
+
+typedef struct green_plan green_plan;
+
+/* Create a plan for fixed dimensions and grid; `prec` selects the contraction
+ * arithmetic.  chunk_bytes bounds the workspace used for contraction
+ * intermediates (0 = default 1 GiB).  Returns GREEN_EINVAL for inconsistent
+ * dims (nao > 512, naux > 512, odd ntau, nw_f != ntau, nw_b != ntau + 1 ...). */
+int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, size_t chunk_bytes,
+                      green_plan** out);
+void green_plan_destroy(green_plan* plan);
+
+/* Workspace bytes for every entry point of this plan (green_gw_iterate needs all of it). */
+size_t green_workspace_bytes(const green_plan* plan);
+
+/* P~0^q_{QQ'}(tau) of Eq. tilde_P0_tau (with G^k(-tau) taken as the stored
+ * G^k(beta - tau), see the header notes):
+ *   P0^q_{QQ'}(tau) = -(1/nk) sum_{k,s} sum_{abcd} V^{k,k+q}_{da}(Q) G^k_{s,cd}(beta - tau)
+ *                                                   G^{k+q}_{s,ab}(tau) V^{k+q,k}_{bc}(Q')
+ * V, G: inputs (device).  P0: output [nk][ntau][naux][naux] (device).  Async. */
+int green_gw_polarization(green_plan* plan, const void* V, const void* G, void* P0, void* ws, void* stream);
+
+/* Screening (Eqs. P0t_to_P0w, tilde_P_omega and the inverse transform):
+ *   P0(i W_m) = sum_t TB_t2w[m][t] P0(tau_t)
+ *   P~(i W_m) = [I - P0(i W_m)]^{-1} P0(i W_m)      (batched Gauss-Jordan, partial pivoting)
+ *   P~(tau_t) = sum_m TB_w2t[t][m] P~(i W_m)
+ * P0: input, Pt: output, both [nk][ntau][naux][naux] (device; may not alias).  Async. */
+int green_gw_screen(green_plan* plan, const void* P0, void* Pt, void* ws, void* stream);
+
+/* Sigma~ of Eqs. sigma_gw and tilde_W_DF2 with W~ = V P~(tau) V never formed:
+ *   Sigma~^k_{s,ij}(tau) = -(1/nk) sum_q sum_ab G^{k-q}_{s,ab}(tau)
+ *                          sum_{QQ'} V^{k,k-q}_{ia}(Q) P~^q_{QQ'}(tau) V^{k-q,k}_{bj}(Q')
+ * V, G, Pt: inputs.  Sigma: output [nspin][ntau][nk][nao][nao] (overwritten).  Async. */
+int green_gw_selfenergy(green_plan* plan, const void* V, const void* G, const void* Pt, void* Sigma, void* ws,
+                        void* stream);
+
+/* Hartree-Fock static self-energy, Eq. sigma_inf, from G(0^-) = -G(beta^-):
+ *   Sinf^k_s = (1/nk) sum_{k' s' Q} V^{k,k}(Q) Tr[G^{k'}_{s'}(0^-) V^{k',k'}(Q)]
+ *            - (1/nk) sum_{k' Q} V^{k,k'}(Q) G^{k'}_s(0^-) V^{k',k}(Q)
+ * Output Sinf [nspin][nk][nao][nao].  Async. */
+int green_hf_static(green_plan* plan, const void* V, const void* G, void* Sinf, void* ws, void* stream);
+
+/* Dyson equation (Eq. dyson) and chemical potential (Sec. 2.3, step 3):
+ *   G^k_s(i w_m) = [(i w_m + mu) S^k - H0^k_s - Sinf^k_s - Sigma~^k_s(i w_m)]^{-1},
+ *   Sigma~(i w_m) = sum_t TF_t2w[m][t] Sigma~(tau_t),  G(tau_t) = sum_m TF_w2t[t][m] G(i w_m).
+ * If n_target >= 0, *mu (in: start, out: result) is adjusted so that
+ *   N(mu) = -(2/nspin)(1/nk) sum_{k,s} Re Tr[G^k_s(beta^-) S^k] = n_target
+ * (bracket by doubling from +-1 Eh up to 60 times, then Illinois regula falsi; stop at
+ * |N - n_target| <= 1e-12 max(1, n_target) or a bracket below 1e-14; at most 200 steps).
+ * If n_target < 0, *mu is kept.  G: output [nspin][ntau][nk][nao][nao].
+ * n_out / evals_out (host, optional): final electron count and number of N evaluations.
+ * Synchronises `stream`. */
+int green_dyson(green_plan* plan, const void* H0, const void* S, const void* Sinf, const void* Sigma, double n_target,
+                double* mu, void* G, double* n_out, int32_t* evals_out, void* ws, void* stream);
+
+/* One self-consistent iteration (Sec. 2.3):
+ *   (1) Sinf_new = HF(G), Sigma_new = GW(G) [polarization, screen, selfenergy];
+ *   (2) mixing Sinf = alpha Sinf_new + (1-alpha) Sinf, Sigma = alpha Sigma_new + (1-alpha) Sigma
+ *       (alpha = 1: no mixing; Sinf / Sigma are read only when alpha != 1);
+ *   (3) chemical potential for n_target (kept if n_target < 0);
+ *   (4) Dyson -> new G (overwrites G), energy and diagnostics into *report.
+ * G, Sinf, Sigma: in/out (device).  mu: in/out (host).  Synchronises `stream`. */
+int green_gw_iterate(green_plan* plan, const void* V, const void* H0, const void* S, void* G, void* Sinf, void* Sigma,
+                     double* mu, double n_target, double alpha, green_report* report, void* ws, void* stream);
+
+/* Human-readable text for a green_status. */
+const char* green_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GREEN_GW_H */

@@ -1,0 +1,800 @@
+// C ABI of libgreen_gw: plan, workspace layout and the orchestration of one
+// self-consistent GW iteration (Sec. 2.3) from the batched kernels.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/green_gw.h"
+#include "aux.h"
+#include "internal.h"
+
+using green::BatchMap;
+using green::IdxMap;
+using green::ZGemm;
+using green::ZOp;
+
+namespace {
+
+constexpr int kNumEvents = 9;
+
+struct Region {
+  size_t off = 0, bytes = 0;
+};
+
+}  // namespace
+
+struct green_plan {
+  green_dims d{};
+  int nk = 0;
+  int prec = GREEN_FP64;
+  int tc = 1;  // tau nodes per contraction chunk
+  std::vector<double> tau, wf, wb;
+  std::vector<double2> TF_t2w, TF_w2t, TB_t2w, TB_w2t, Emass;
+  std::vector<int32_t> kadd, ksub, kneg;  // [q][k]: k+q, k-q; [q]: -q
+  // workspace regions
+  Region r_TF_t2w, r_TF_w2t, r_TB_t2w, r_TB_w2t, r_Emass, r_wf, r_kadd, r_ksub, r_status, r_scal, r_partial;
+  Region r_P, r_Pw, r_T1, r_T2, r_gam, r_gamT, r_D, r_Sinfn, r_Sign, r_Sw, r_A, r_tr;
+  size_t ws_bytes = 0;
+  void* bound_ws = nullptr;
+  hipEvent_t ev[kNumEvents]{};
+  bool events = false;
+};
+
+namespace {
+
+template <typename T>
+T* at(void* ws, const Region& r) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + r.off);
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? GREEN_OK : GREEN_EHIP; }
+
+#define HIP_TRY(expr)                          \
+  do {                                         \
+    hipError_t e_ = (expr);                    \
+    if (e_ != hipSuccess) return GREEN_EHIP;   \
+  } while (0)
+
+#define GREEN_TRY(expr)              \
+  do {                               \
+    int r_ = (expr);                 \
+    if (r_ != GREEN_OK) return r_;   \
+  } while (0)
+
+// Chebyshev-Lobatto check and energy quadrature E[t][t'] = int_0^beta l_t(tau) l_t'(tau) dtau
+// (l_t: Lagrange basis of the nodes), from the DCT-I coefficients and W_lm = int T_l T_m dx.
+bool build_mass_matrix(const std::vector<double>& tau, double beta, std::vector<double2>& E) {
+  const int n = (int)tau.size();
+  const int N = n - 1;
+  for (int t = 0; t < n; ++t) {
+    const double ref = 0.5 * beta * (1.0 - std::cos(M_PI * t / N));
+    if (std::fabs(tau[t] - ref) > 1e-10 * beta) return false;
+  }
+  // C[l][t]: coefficient l of the interpolant from the value at node t; node t sits at x = cos(pi (N - t) / N)
+  std::vector<double> C((size_t)n * n);
+  for (int l = 0; l < n; ++l)
+    for (int t = 0; t < n; ++t) {
+      const int j = N - t;
+      double c = (2.0 / N) * std::cos(M_PI * (double)l * j / N);
+      if (j == 0 || j == N) c *= 0.5;
+      if (l == 0 || l == N) c *= 0.5;
+      C[(size_t)l * n + t] = c;
+    }
+  std::vector<double> W((size_t)n * n, 0.0);
+  for (int l = 0; l < n; ++l)
+    for (int m = 0; m < n; ++m)
+      if (((l + m) & 1) == 0) {
+        const double s = l + m, d = l - m;
+        W[(size_t)l * n + m] = 1.0 / (1.0 - s * s) + 1.0 / (1.0 - d * d);
+      }
+  std::vector<double> WC((size_t)n * n, 0.0);  // W C
+  for (int l = 0; l < n; ++l)
+    for (int m = 0; m < n; ++m) {
+      const double w = W[(size_t)l * n + m];
+      if (w == 0.0) continue;
+      for (int t = 0; t < n; ++t) WC[(size_t)l * n + t] += w * C[(size_t)m * n + t];
+    }
+  E.assign((size_t)n * n, make_double2(0.0, 0.0));
+  for (int t = 0; t < n; ++t)
+    for (int u = 0; u < n; ++u) {
+      double acc = 0.0;
+      for (int l = 0; l < n; ++l) acc += C[(size_t)l * n + t] * WC[(size_t)l * n + u];
+      E[(size_t)t * n + u] = make_double2(0.5 * beta * acc, 0.0);
+    }
+  return true;
+}
+
+void kpoint(const int32_t* m, int k, int& a, int& b, int& c) {
+  c = k % m[2];
+  b = (k / m[2]) % m[1];
+  a = k / (m[1] * m[2]);
+}
+int kflat(const int32_t* m, int a, int b, int c) {
+  a = ((a % m[0]) + m[0]) % m[0];
+  b = ((b % m[1]) + m[1]) % m[1];
+  c = ((c % m[2]) + m[2]) % m[2];
+  return (a * m[1] + b) * m[2] + c;
+}
+
+int ensure_bound(green_plan* p, void* ws, hipStream_t s) {
+  if (p->bound_ws == ws) return GREEN_OK;
+  if (green::dryrun()) return GREEN_OK;
+  auto up = [&](const Region& r, const void* src) {
+    return hipMemcpyAsync(static_cast<char*>(ws) + r.off, src, r.bytes, hipMemcpyHostToDevice, s);
+  };
+  HIP_TRY(up(p->r_TF_t2w, p->TF_t2w.data()));
+  HIP_TRY(up(p->r_TF_w2t, p->TF_w2t.data()));
+  HIP_TRY(up(p->r_TB_t2w, p->TB_t2w.data()));
+  HIP_TRY(up(p->r_TB_w2t, p->TB_w2t.data()));
+  HIP_TRY(up(p->r_Emass, p->Emass.data()));
+  HIP_TRY(up(p->r_wf, p->wf.data()));
+  HIP_TRY(up(p->r_kadd, p->kadd.data()));
+  HIP_TRY(up(p->r_ksub, p->ksub.data()));
+  HIP_TRY(hipMemsetAsync(static_cast<char*>(ws) + p->r_status.off, 0, p->r_status.bytes, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  p->bound_ws = ws;
+  return GREEN_OK;
+}
+
+inline double2 cplx(double re, double im = 0.0) { return make_double2(re, im); }
+
+ZOp op(const void* ptr, IdxMap r, IdxMap c, BatchMap b, int conj = 0) {
+  ZOp o;
+  o.p = static_cast<const double2*>(ptr);
+  o.r = r;
+  o.c = c;
+  o.b = b;
+  o.conj = conj;
+  return o;
+}
+
+int gemm(const char* label, const ZOp& A, const green::Span& sa, const ZOp& B, const green::Span& sb, void* C,
+         const green::Span& sc, IdxMap cr, IdxMap cc, BatchMap cb, int M, int N, int K, int batch, double2 alpha,
+         double2 beta, hipStream_t s) {
+  ZGemm g;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.batch = batch;
+  g.A = A;
+  g.B = B;
+  g.C = static_cast<double2*>(C);
+  g.cr = cr;
+  g.cc = cc;
+  g.cb = cb;
+  g.alpha = alpha;
+  g.beta = beta;
+  char why[256];
+  if (!green::zgemm_in_bounds(g, sa, sb, sc, why, sizeof(why))) {
+    std::fprintf(stderr, "green_gw: contraction '%s' rejected: %s\n", label, why);
+    return GREEN_EINVAL;
+  }
+  return hip_status(green::zgemm(g, s));
+}
+
+green::Span span(const void* base, int64_t count) { return green::Span{base, count}; }
+green::Span span_ws(void* ws, const Region& r) {
+  return green::Span{static_cast<char*>(ws) + r.off, (int64_t)(r.bytes / sizeof(double2))};
+}
+
+using green::bflat;
+using green::bnone;
+using green::btwo;
+using green::flat;
+using green::two;
+
+// Extents (complex elements) of the caller's tensors.
+struct Extents {
+  int64_t V, G, P, H, S, Sig;
+};
+Extents extents(const green_plan* p) {
+  const green_dims& d = p->d;
+  const int64_t nk = p->nk, nG = (int64_t)d.nao * d.nao, nV = (int64_t)d.naux * nG;
+  Extents e;
+  e.V = nk * nk * nV;
+  e.G = (int64_t)d.nspin * d.ntau * nk * nG;
+  e.P = nk * d.ntau * (int64_t)d.naux * d.naux;
+  e.H = (int64_t)d.nspin * nk * nG;
+  e.S = nk * nG;
+  e.Sig = e.G;
+  return e;
+}
+
+// ---------------------------------------------------------------- polarization
+int run_polarization(green_plan* p, const void* V, const void* G, void* P0, void* ws, hipStream_t s) {
+  const green_dims& d = p->d;
+  const int nk = p->nk, nao = d.nao, naux = d.naux, ntau = d.ntau, ns = d.nspin;
+  const int64_t nG = (int64_t)nao * nao, nV = (int64_t)naux * nG, slab = (int64_t)nk * nV;
+  const Extents ex = extents(p);
+  const int32_t* kadd = at<int32_t>(ws, p->r_kadd);
+  const int32_t* hadd = p->kadd.data();
+  double2* T1 = at<double2>(ws, p->r_T1);
+  double2* T2 = at<double2>(ws, p->r_T2);
+  const green::Span sV = span(V, ex.V), sG = span(G, ex.G), sP = span(P0, ex.P);
+  const green::Span sT1 = span_ws(ws, p->r_T1), sT2 = span_ws(ws, p->r_T2);
+  const double2* Vp = static_cast<const double2*>(V);
+  const double2* Gp = static_cast<const double2*>(G);
+  double2* Pp = static_cast<double2*>(P0);
+  const double w = ns == 1 ? 2.0 : 1.0;
+  for (int q = 0; q < nk; ++q) {
+    const int qn = p->kneg[q];
+    for (int t0 = 0; t0 < ntau; t0 += p->tc) {
+      const int tcn = std::min(p->tc, ntau - t0);
+      for (int sp = 0; sp < ns; ++sp) {
+        // T1[tt][k][(Q,d)][b] = sum_a V^{k,k+q}_{da}(Q) G^{k+q}_{ab}(tau)
+        GREEN_TRY(gemm("P0.VG", op(Vp + q * slab, flat(nao), flat(1), btwo(nk, nV, nullptr, 0)), sV,
+                       op(Gp + ((int64_t)sp * ntau + t0) * nk * nG, flat(nao), flat(1),
+                          btwo(nk, nG, kadd + q * nk, (int64_t)nk * nG, hadd + q * nk)),
+                       sG, T1, sT1, flat(nao), flat(1), bflat(nV), naux * nao, nao, nao, tcn * nk, cplx(1),
+                       cplx(0), s));
+        // T2[tt][k][Q'][d][b] = sum_c V^{k+q,k}_{bc}(Q') G^k_{cd}(beta - tau)   (stored transposed in (b, d))
+        GREEN_TRY(gemm("P0.VGrev", op(Vp + qn * slab, flat(nao), flat(1), btwo(nk, nV, kadd + q * nk, 0, hadd + q * nk)),
+                       sV,
+                       op(Gp + ((int64_t)sp * ntau + (ntau - 1 - t0)) * nk * nG, flat(nao), flat(1),
+                          btwo(nk, nG, nullptr, -(int64_t)nk * nG)),
+                       sG, T2, sT2, two(nao, 1, nG), flat(nao), bflat(nV), naux * nao, nao, nao, tcn * nk,
+                       cplx(1), cplx(0), s));
+        // P0[q][t][Q][Q'] (+)= -(w/nk) sum_{k,(d,b)} T1[tt][k][Q][(d,b)] T2[tt][k][Q'][(d,b)]
+        GREEN_TRY(gemm("P0.contract", op(T1, flat(nG), two((int32_t)nG, 1, nV), bflat((int64_t)nk * nV)), sT1,
+                       op(T2, two((int32_t)nG, 1, nV), flat(nG), bflat((int64_t)nk * nV)), sT2,
+                       Pp + ((int64_t)q * ntau + t0) * naux * naux, sP, flat(naux), flat(1),
+                       bflat((int64_t)naux * naux), naux, naux, (int)(nk * nG), tcn, cplx(-w / nk),
+                       cplx(sp == 0 ? 0.0 : 1.0), s));
+      }
+    }
+  }
+  return GREEN_OK;
+}
+
+// ---------------------------------------------------------------- screening
+int run_screen(green_plan* p, const void* P0, void* Pt, void* ws, hipStream_t s) {
+  const green_dims& d = p->d;
+  const int nk = p->nk, naux = d.naux, ntau = d.ntau, nwb = d.nw_b;
+  const int64_t nP = (int64_t)naux * naux;
+  const Extents ex = extents(p);
+  double2* Pw = at<double2>(ws, p->r_Pw);
+  const green::Span sPw = span_ws(ws, p->r_Pw);
+  // P0(i W_m) = sum_t TB_t2w[m][t] P0(tau_t)
+  GREEN_TRY(gemm("screen.t2w", op(at<double2>(ws, p->r_TB_t2w), flat(ntau), flat(1), bnone()),
+                 span_ws(ws, p->r_TB_t2w), op(P0, flat(nP), flat(1), bflat((int64_t)ntau * nP)), span(P0, ex.P), Pw,
+                 sPw, flat(nP), flat(1), bflat((int64_t)nwb * nP), nwb, (int)nP, ntau, nk, cplx(1), cplx(0), s));
+  // P~(i W) = [I - P0]^{-1} P0 = [I - P0]^{-1} - I
+  if ((int64_t)nk * nwb * nP * 16 > (int64_t)p->r_Pw.bytes) return GREEN_EINVAL;
+  if (!green::dryrun()) {
+    HIP_TRY(green::launch_one_minus(Pw, naux, (int64_t)nk * nwb, s));
+    HIP_TRY(green::zinv_batched(Pw, naux, nP, nk * nwb, at<int>(ws, p->r_status), s));
+    HIP_TRY(green::launch_minus_one(Pw, naux, (int64_t)nk * nwb, s));
+  }
+  // P~(tau_t) = sum_m TB_w2t[t][m] P~(i W_m)
+  GREEN_TRY(gemm("screen.w2t", op(at<double2>(ws, p->r_TB_w2t), flat(nwb), flat(1), bnone()),
+                 span_ws(ws, p->r_TB_w2t), op(Pw, flat(nP), flat(1), bflat((int64_t)nwb * nP)), sPw, Pt,
+                 span(Pt, ex.P), flat(nP), flat(1), bflat((int64_t)ntau * nP), ntau, (int)nP, nwb, nk, cplx(1),
+                 cplx(0), s));
+  return GREEN_OK;
+}
+
+// ---------------------------------------------------------------- self-energy
+int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, void* Sig, void* ws, hipStream_t s) {
+  const green_dims& d = p->d;
+  const int nk = p->nk, nao = d.nao, naux = d.naux, ntau = d.ntau, ns = d.nspin;
+  const int64_t nG = (int64_t)nao * nao, nV = (int64_t)naux * nG, slab = (int64_t)nk * nV;
+  const int64_t nP = (int64_t)naux * naux;
+  const Extents ex = extents(p);
+  const int32_t* ksub = at<int32_t>(ws, p->r_ksub);
+  const int32_t* hsub = p->ksub.data();
+  double2* T1 = at<double2>(ws, p->r_T1);
+  double2* T2 = at<double2>(ws, p->r_T2);
+  const green::Span sV = span(V, ex.V), sG = span(G, ex.G), sP = span(Pt, ex.P), sS = span(Sig, ex.Sig);
+  const green::Span sT1 = span_ws(ws, p->r_T1), sT2 = span_ws(ws, p->r_T2);
+  const double2* Vp = static_cast<const double2*>(V);
+  const double2* Gp = static_cast<const double2*>(G);
+  const double2* Pp = static_cast<const double2*>(Pt);
+  double2* Sp = static_cast<double2*>(Sig);
+  if (!green::dryrun()) HIP_TRY(green::launch_zero(Sp, ex.Sig, s));
+  for (int q = 0; q < nk; ++q) {
+    const int qn = p->kneg[q];
+    for (int t0 = 0; t0 < ntau; t0 += p->tc) {
+      const int tcn = std::min(p->tc, ntau - t0);
+      // X[tt][k][Q'][(i,a)] = sum_Q P~^q_{QQ'}(tau) V^{k,k-q}_{ia}(Q)
+      GREEN_TRY(gemm("Sigma.PV", op(Pp + ((int64_t)q * ntau + t0) * nP, flat(1), flat(naux), bflat(nP)), sP,
+                     op(Vp + qn * slab, flat(nG), two((int32_t)nG, 1, nV), bnone()), sV, T1, sT1, flat(nG),
+                     two((int32_t)nG, 1, nV), bflat((int64_t)nk * nV), naux, (int)(nk * nG), naux, tcn, cplx(1),
+                     cplx(0), s));
+      for (int sp = 0; sp < ns; ++sp) {
+        // Y[tt][k][(Q',i)][b] = sum_a X[tt][k][(Q',i)][a] G^{k-q}_{ab}(tau)
+        GREEN_TRY(gemm("Sigma.XG", op(T1, flat(nao), flat(1), bflat(nV)), sT1,
+                       op(Gp + ((int64_t)sp * ntau + t0) * nk * nG, flat(nao), flat(1),
+                          btwo(nk, nG, ksub + q * nk, (int64_t)nk * nG, hsub + q * nk)),
+                       sG, T2, sT2, flat(nao), flat(1), bflat(nV), naux * nao, nao, nao, tcn * nk, cplx(1), cplx(0),
+                       s));
+        // Sigma[s][t][k][i][j] += -(1/nk) sum_{(Q',b)} Y[tt][k][Q'][i][b] V^{k-q,k}_{bj}(Q')
+        GREEN_TRY(gemm("Sigma.YV", op(T2, flat(nao), two(nao, 1, nG), bflat(nV)), sT2,
+                       op(Vp + q * slab, two(nao, nao, nG), flat(1), btwo(nk, nV, ksub + q * nk, 0, hsub + q * nk)),
+                       sV, Sp + ((int64_t)sp * ntau + t0) * nk * nG, sS, flat(nao), flat(1), bflat(nG), nao, nao,
+                       naux * nao, tcn * nk, cplx(-1.0 / nk), cplx(1.0), s));
+      }
+    }
+  }
+  return GREEN_OK;
+}
+
+// ---------------------------------------------------------------- Hartree-Fock
+int run_hf(green_plan* p, const void* V, const void* G, void* Sinf, void* ws, hipStream_t s) {
+  const green_dims& d = p->d;
+  const int nk = p->nk, nao = d.nao, naux = d.naux, ntau = d.ntau, ns = d.nspin;
+  const int64_t nG = (int64_t)nao * nao, nV = (int64_t)naux * nG, slab = (int64_t)nk * nV;
+  const Extents ex = extents(p);
+  const int32_t* ksub = at<int32_t>(ws, p->r_ksub);
+  const int32_t* hsub = p->ksub.data();
+  double2* gam = at<double2>(ws, p->r_gam);
+  double2* gamT = at<double2>(ws, p->r_gamT);
+  double2* D = at<double2>(ws, p->r_D);
+  double2* T2 = at<double2>(ws, p->r_T2);
+  const green::Span sV = span(V, ex.V), sH = span(Sinf, ex.H), sGam = span_ws(ws, p->r_gam),
+                    sGamT = span_ws(ws, p->r_gamT), sD = span_ws(ws, p->r_D), sT2 = span_ws(ws, p->r_T2);
+  const double2* Vp = static_cast<const double2*>(V);
+  double2* Sp = static_cast<double2*>(Sinf);
+  const double w = ns == 1 ? 2.0 : 1.0;
+  if (!green::dryrun())
+    HIP_TRY(green::launch_density(static_cast<const double2*>(G), gam, gamT, ns, ntau, nk, nao, s));
+  // Hartree density D[Q] = (w/nk) sum_{s,k'} sum_{ab} V^{k'k'}_{ba}(Q) gamma^{k'}_{ab}
+  for (int sp = 0; sp < ns; ++sp)
+    GREEN_TRY(gemm("HF.density", op(Vp, flat(nG), two((int32_t)nG, 1, nV), bnone()), sV,
+                   op(gamT + (int64_t)sp * nk * nG, flat(1), flat(0), bnone()), sGamT, D, sD, flat(1), flat(0),
+                   bnone(), naux, 1, (int)(nk * nG), 1, cplx(w / nk), cplx(sp == 0 ? 0.0 : 1.0), s));
+  // Hartree term Sinf[s][k] = sum_Q D[Q] V^{kk}(Q)
+  for (int sp = 0; sp < ns; ++sp)
+    GREEN_TRY(gemm("HF.hartree", op(D, flat(0), flat(1), bnone()), sD,
+                   op(Vp, flat(nG), two((int32_t)nG, 1, nV), bnone()), sV, Sp + (int64_t)sp * nk * nG, sH, flat(0),
+                   flat(1), bnone(), 1, (int)(nk * nG), naux, 1, cplx(1), cplx(0), s));
+  // exchange: Sinf[s][k] -= (1/nk) sum_q sum_Q V^{k,k-q}(Q) gamma^{k-q} V^{k-q,k}(Q)
+  for (int q = 0; q < nk; ++q) {
+    const int qn = p->kneg[q];
+    for (int sp = 0; sp < ns; ++sp) {
+      GREEN_TRY(gemm("HF.Vgamma", op(Vp + qn * slab, flat(nao), flat(1), bflat(nV)), sV,
+                     op(gam + (int64_t)sp * nk * nG, flat(nao), flat(1), btwo(nk, nG, ksub + q * nk, 0, hsub + q * nk)),
+                     sGam, T2, sT2, flat(nao), flat(1), bflat(nV), naux * nao, nao, nao, nk, cplx(1), cplx(0), s));
+      GREEN_TRY(gemm("HF.exchange", op(T2, flat(nao), two(nao, 1, nG), bflat(nV)), sT2,
+                     op(Vp + q * slab, two(nao, nao, nG), flat(1), btwo(nk, nV, ksub + q * nk, 0, hsub + q * nk)),
+                     sV, Sp + (int64_t)sp * nk * nG, sH, flat(nao), flat(1), bflat(nG), nao, nao, naux * nao, nk,
+                     cplx(-1.0 / nk), cplx(1.0), s));
+    }
+  }
+  return GREEN_OK;
+}
+
+// ---------------------------------------------------------------- Dyson + mu
+int read_status(green_plan* p, void* ws, hipStream_t s) {
+  if (green::dryrun()) return GREEN_OK;
+  int st = 0;
+  HIP_TRY(hipMemcpyAsync(&st, at<int>(ws, p->r_status), sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (st) {
+    HIP_TRY(hipMemsetAsync(at<int>(ws, p->r_status), 0, sizeof(int), s));
+    return GREEN_ESINGULAR;
+  }
+  return GREEN_OK;
+}
+
+struct DysonCtx {
+  green_plan* p;
+  void* ws;
+  hipStream_t s;
+  const double2 *H0, *S, *Sinf;
+  double nt;  // dry runs only: a stand-in electron count
+};
+
+// N(mu) = -(2/ns)(1/nk) sum_{s,m,k} Re( TF_w2t[ntau-1][m] Tr[G^k_s(i w_m; mu) S^k] )
+int electron_count(const DysonCtx& c, double mu, double* n_out) {
+  green_plan* p = c.p;
+  const green_dims& d = p->d;
+  const int nk = p->nk, nao = d.nao, ns = d.nspin, nw = d.nw_f, ntau = d.ntau;
+  const int64_t nG = (int64_t)nao * nao;
+  const int64_t nb = (int64_t)ns * nw * nk;
+  if (green::dryrun()) {
+    *n_out = (c.nt < 0 ? 1.0 : c.nt) + 0.5 * std::tanh(mu);
+    return GREEN_OK;
+  }
+  double2* A = at<double2>(c.ws, p->r_A);
+  double2* tr = at<double2>(c.ws, p->r_tr);
+  double* scal = at<double>(c.ws, p->r_scal);
+  HIP_TRY(green::launch_dyson_form(A, c.S, c.H0, c.Sinf, at<double2>(c.ws, p->r_Sw), at<double>(c.ws, p->r_wf), mu,
+                                   ns, nw, nk, nao, c.s));
+  HIP_TRY(green::zinv_batched(A, nao, nG, (int)nb, at<int>(c.ws, p->r_status), c.s));
+  HIP_TRY(green::launch_trace_prod(A, nG, c.S, 1, nk, nG, 0, nao, nb, tr, c.s));
+  const double2* row = at<double2>(c.ws, p->r_TF_w2t) + (int64_t)(ntau - 1) * nw;
+  HIP_TRY(green::launch_weighted_sum(tr, nb, row, nk, nw, 1, -(2.0 / ns) / nk, scal, c.s));
+  HIP_TRY(hipMemcpyAsync(n_out, scal, sizeof(double), hipMemcpyDeviceToHost, c.s));
+  HIP_TRY(hipStreamSynchronize(c.s));
+  return GREEN_OK;
+}
+
+// Bracketing by doubling, then Illinois regula falsi (Sec. 2.3 step 3: fixed particle number).
+int find_mu(const DysonCtx& c, double mu0, double nt, double* mu_out, double* n_out, int* evals) {
+  const double tol = 1e-12 * std::max(1.0, std::fabs(nt));
+  double n0;
+  GREEN_TRY(electron_count(c, mu0, &n0));
+  *evals = 1;
+  if (!std::isfinite(n0)) return GREEN_ENAN;
+  if (std::fabs(n0 - nt) <= tol) {
+    *mu_out = mu0;
+    *n_out = n0;
+    return GREEN_OK;
+  }
+  double dlt = 1.0, lo = 0, hi = 0, nlo = 0, nhi = 0;
+  bool ok = false;
+  for (int i = 0; i < 60; ++i) {
+    lo = mu0 - dlt;
+    hi = mu0 + dlt;
+    GREEN_TRY(electron_count(c, lo, &nlo));
+    GREEN_TRY(electron_count(c, hi, &nhi));
+    *evals += 2;
+    if (!std::isfinite(nlo) || !std::isfinite(nhi)) return GREEN_ENAN;
+    if (nlo <= nt && nt <= nhi) {
+      ok = true;
+      break;
+    }
+    dlt *= 2.0;
+  }
+  if (!ok) return GREEN_ENOCONV;
+  double flo = nlo - nt, fhi = nhi - nt;
+  if (std::fabs(flo) <= tol) {
+    *mu_out = lo;
+    *n_out = nlo;
+    return GREEN_OK;
+  }
+  if (std::fabs(fhi) <= tol) {
+    *mu_out = hi;
+    *n_out = nhi;
+    return GREEN_OK;
+  }
+  int side = 0;
+  for (int it = 0; it < 200; ++it) {
+    if (hi - lo < 1e-14) {
+      const double mu = 0.5 * (lo + hi);
+      double n;
+      GREEN_TRY(electron_count(c, mu, &n));
+      *evals += 1;
+      *mu_out = mu;
+      *n_out = n;
+      return GREEN_OK;
+    }
+    double mu = (fhi != flo) ? (lo * fhi - hi * flo) / (fhi - flo) : 0.5 * (lo + hi);
+    if (!(lo < mu && mu < hi)) mu = 0.5 * (lo + hi);
+    double n;
+    GREEN_TRY(electron_count(c, mu, &n));
+    *evals += 1;
+    if (!std::isfinite(n)) return GREEN_ENAN;
+    const double f = n - nt;
+    if (std::fabs(f) <= tol) {
+      *mu_out = mu;
+      *n_out = n;
+      return GREEN_OK;
+    }
+    if (f < 0) {
+      lo = mu;
+      flo = f;
+      if (side == -1) fhi *= 0.5;
+      side = -1;
+    } else {
+      hi = mu;
+      fhi = f;
+      if (side == 1) flo *= 0.5;
+      side = 1;
+    }
+  }
+  return GREEN_ENOCONV;
+}
+
+int run_dyson(green_plan* p, const void* H0, const void* S, const void* Sinf, const void* Sig, double nt, double* mu,
+              void* G, double* n_out, int32_t* evals_out, void* ws, hipStream_t s) {
+  const green_dims& d = p->d;
+  const int nk = p->nk, nao = d.nao, ns = d.nspin, nw = d.nw_f, ntau = d.ntau;
+  const int64_t nG = (int64_t)nao * nao, nkG = (int64_t)nk * nG;
+  const Extents ex = extents(p);
+  double2* Sw = at<double2>(ws, p->r_Sw);
+  // Sigma~(i w_m) = sum_t TF_t2w[m][t] Sigma~(tau_t)
+  GREEN_TRY(gemm("dyson.t2w", op(at<double2>(ws, p->r_TF_t2w), flat(ntau), flat(1), bnone()),
+                 span_ws(ws, p->r_TF_t2w), op(Sig, flat(nkG), flat(1), bflat((int64_t)ntau * nkG)),
+                 span(Sig, ex.Sig), Sw, span_ws(ws, p->r_Sw), flat(nkG), flat(1), bflat((int64_t)nw * nkG), nw,
+                 (int)nkG, ntau, ns, cplx(1), cplx(0), s));
+  DysonCtx c{p, ws, s, static_cast<const double2*>(H0), static_cast<const double2*>(S),
+             static_cast<const double2*>(Sinf), nt};
+  double m = *mu, n = 0.0;
+  int evals = 0;
+  if (nt >= 0) {
+    GREEN_TRY(find_mu(c, *mu, nt, &m, &n, &evals));
+  }
+  // final Dyson at mu, then G(tau_t) = sum_m TF_w2t[t][m] G(i w_m)
+  double nfinal;
+  GREEN_TRY(electron_count(c, m, &nfinal));
+  GREEN_TRY(gemm("dyson.w2t", op(at<double2>(ws, p->r_TF_w2t), flat(nw), flat(1), bnone()),
+                 span_ws(ws, p->r_TF_w2t), op(at<double2>(ws, p->r_A), flat(nkG), flat(1), bflat((int64_t)nw * nkG)),
+                 span_ws(ws, p->r_A), G, span(G, ex.G), flat(nkG), flat(1), bflat((int64_t)ntau * nkG), ntau,
+                 (int)nkG, nw, ns, cplx(1), cplx(0), s));
+  GREEN_TRY(read_status(p, ws, s));
+  *mu = m;
+  if (n_out) *n_out = nfinal;
+  if (evals_out) *evals_out = evals + 1;
+  if (!std::isfinite(nfinal)) return GREEN_ENAN;
+  return GREEN_OK;
+}
+
+// ---------------------------------------------------------------- energy (Galitskii-Migdal, with the new G)
+int run_energy(green_plan* p, const void* H0, const void* G, const void* Sinf, const void* Sig, void* ws,
+               hipStream_t s, green_report* rep) {
+  const green_dims& d = p->d;
+  const int nk = p->nk, nao = d.nao, ns = d.nspin, ntau = d.ntau;
+  const int64_t nG = (int64_t)nao * nao, nkG = (int64_t)nk * nG;
+  const Extents ex = extents(p);
+  double2* gam = at<double2>(ws, p->r_gam);
+  double2* tr = at<double2>(ws, p->r_tr);
+  double* scal = at<double>(ws, p->r_scal);
+  double2* Hm = at<double2>(ws, p->r_T1);
+  const double2* Gp = static_cast<const double2*>(G);
+  // Hm[s][t] = sum_t' E[t][t'] G[s][ntau-1-t']  (the interpolant of G(beta - tau) weighted by the mass matrix)
+  GREEN_TRY(gemm("energy.mass", op(at<double2>(ws, p->r_Emass), flat(ntau), flat(1), bnone()),
+                 span_ws(ws, p->r_Emass), op(Gp + (int64_t)(ntau - 1) * nkG, flat(-nkG), flat(1),
+                                              bflat((int64_t)ntau * nkG)),
+                 span(G, ex.G), Hm, span_ws(ws, p->r_T1), flat(nkG), flat(1), bflat((int64_t)ntau * nkG), ntau,
+                 (int)nkG, ntau, ns, cplx(1), cplx(0), s));
+  if (green::dryrun()) return GREEN_OK;
+  HIP_TRY(green::launch_density(Gp, gam, nullptr, ns, ntau, nk, nao, s));
+  // E_1b = (2/ns)(1/nk) sum Re Tr[gamma H0];  E_HF = (1/ns)(1/nk) sum Re Tr[gamma Sinf]
+  HIP_TRY(green::launch_trace_prod(gam, nG, static_cast<const double2*>(H0), 1, (int64_t)ns * nk, nG, 0, nao,
+                                   (int64_t)ns * nk, tr, s));
+  HIP_TRY(green::launch_weighted_sum(tr, (int64_t)ns * nk, nullptr, 1, 1, 0, (2.0 / ns) / nk, scal + 0, s));
+  HIP_TRY(green::launch_trace_prod(gam, nG, static_cast<const double2*>(Sinf), 1, (int64_t)ns * nk, nG, 0, nao,
+                                   (int64_t)ns * nk, tr, s));
+  HIP_TRY(green::launch_weighted_sum(tr, (int64_t)ns * nk, nullptr, 1, 1, 0, (1.0 / ns) / nk, scal + 1, s));
+  // E_corr = -(1/ns)(1/nk) sum_{s,t,k} Re Tr[Sigma(tau_t) Hm[s][t]]
+  const int64_t nb = (int64_t)ns * ntau * nk;
+  HIP_TRY(green::launch_trace_prod(static_cast<const double2*>(Sig), nG, Hm, 1, nb, nG, 0, nao, nb, tr, s));
+  HIP_TRY(green::launch_weighted_sum(tr, nb, nullptr, 1, 1, 0, -(1.0 / ns) / nk, scal + 2, s));
+  HIP_TRY(green::launch_herm(static_cast<const double2*>(Sig), nb, nao, at<double>(ws, p->r_partial), scal + 3, s));
+  double h[4];
+  HIP_TRY(hipMemcpyAsync(h, scal, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  rep->e_1b = h[0];
+  rep->e_hf = h[1];
+  rep->e_corr = h[2];
+  rep->e_tot = h[0] + h[1] + h[2];
+  rep->herm_err = h[3];
+  (void)ex;
+  return GREEN_OK;
+}
+
+int check_plan(green_plan* p, void* ws) {
+  if (!p || !ws) return GREEN_EINVAL;
+  return GREEN_OK;
+}
+
+}  // namespace
+
+// ====================================================================== exported
+extern "C" {
+
+const char* green_strerror(int st) {
+  switch (st) {
+    case GREEN_OK: return "success";
+    case GREEN_EINVAL: return "invalid argument";
+    case GREEN_ENOMEM: return "workspace too small";
+    case GREEN_EHIP: return "HIP runtime error";
+    case GREEN_ESINGULAR: return "singular matrix in a batched inversion";
+    case GREEN_ENOCONV: return "chemical potential not bracketed or not converged";
+    case GREEN_ENAN: return "non-finite value";
+    case GREEN_EUNSUPPORTED: return "unsupported request";
+    default: return "unknown status";
+  }
+}
+
+int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, size_t chunk_bytes,
+                      green_plan** out) {
+  if (!dims || !grid || !out) return GREEN_EINVAL;
+  *out = nullptr;
+  const green_dims d = *dims;
+  if (d.kmesh[0] < 1 || d.kmesh[1] < 1 || d.kmesh[2] < 1) return GREEN_EINVAL;
+  if (d.nao < 1 || d.nao > 512 || d.naux < 1 || d.naux > 512) return GREEN_EINVAL;
+  if (d.ntau < 4 || (d.ntau & 1) || d.nw_f != d.ntau || d.nw_b != d.ntau + 1) return GREEN_EINVAL;
+  if (d.nspin != 1 && d.nspin != 2) return GREEN_EINVAL;
+  if (!(d.beta > 0.0) || !std::isfinite(d.beta)) return GREEN_EINVAL;
+  if (!grid->tau || !grid->wf || !grid->wb || !grid->TF_t2w || !grid->TF_w2t || !grid->TB_t2w || !grid->TB_w2t)
+    return GREEN_EINVAL;
+  if (prec != GREEN_FP64) return GREEN_EUNSUPPORTED;
+  green_plan* p = new (std::nothrow) green_plan();
+  if (!p) return GREEN_ENOMEM;
+  p->d = d;
+  p->nk = d.kmesh[0] * d.kmesh[1] * d.kmesh[2];
+  p->prec = prec;
+  const int nk = p->nk, ntau = d.ntau, nwf = d.nw_f, nwb = d.nw_b;
+  p->tau.assign(grid->tau, grid->tau + ntau);
+  p->wf.assign(grid->wf, grid->wf + nwf);
+  p->wb.assign(grid->wb, grid->wb + nwb);
+  auto cp = [](const void* src, size_t n, std::vector<double2>& dst) {
+    dst.resize(n);
+    std::memcpy(dst.data(), src, n * sizeof(double2));
+  };
+  cp(grid->TF_t2w, (size_t)nwf * ntau, p->TF_t2w);
+  cp(grid->TF_w2t, (size_t)ntau * nwf, p->TF_w2t);
+  cp(grid->TB_t2w, (size_t)nwb * ntau, p->TB_t2w);
+  cp(grid->TB_w2t, (size_t)ntau * nwb, p->TB_w2t);
+  for (int t = 0; t < ntau; ++t)
+    if (std::fabs(p->tau[t] + p->tau[ntau - 1 - t] - d.beta) > 1e-10 * d.beta) {
+      delete p;
+      return GREEN_EINVAL;
+    }
+  if (!build_mass_matrix(p->tau, d.beta, p->Emass)) {
+    delete p;
+    return GREEN_EUNSUPPORTED;
+  }
+  p->kadd.resize((size_t)nk * nk);
+  p->ksub.resize((size_t)nk * nk);
+  p->kneg.resize(nk);
+  for (int q = 0; q < nk; ++q) {
+    int qa, qb, qc;
+    kpoint(d.kmesh, q, qa, qb, qc);
+    p->kneg[q] = kflat(d.kmesh, -qa, -qb, -qc);
+    for (int k = 0; k < nk; ++k) {
+      int a, b, c;
+      kpoint(d.kmesh, k, a, b, c);
+      p->kadd[(size_t)q * nk + k] = kflat(d.kmesh, a + qa, b + qb, c + qc);
+      p->ksub[(size_t)q * nk + k] = kflat(d.kmesh, a - qa, b - qb, c - qc);
+    }
+  }
+  // ---- workspace layout
+  const int64_t nao = d.nao, naux = d.naux, ns = d.nspin;
+  const int64_t nG = nao * nao, nV = naux * nG, nP = naux * naux;
+  if (chunk_bytes == 0) chunk_bytes = (size_t)1 << 30;
+  const size_t per_t = (size_t)2 * nk * nV * sizeof(double2);
+  int tc = (int)std::max<size_t>(1, chunk_bytes / per_t);
+  tc = std::min(tc, ntau);
+  p->tc = tc;
+  size_t off = 0;
+  auto take = [&](Region& r, size_t bytes) {
+    r.off = off;
+    r.bytes = bytes;
+    off += (bytes + 255) & ~(size_t)255;
+  };
+  take(p->r_TF_t2w, (size_t)nwf * ntau * 16);
+  take(p->r_TF_w2t, (size_t)ntau * nwf * 16);
+  take(p->r_TB_t2w, (size_t)nwb * ntau * 16);
+  take(p->r_TB_w2t, (size_t)ntau * nwb * 16);
+  take(p->r_Emass, (size_t)ntau * ntau * 16);
+  take(p->r_wf, (size_t)nwf * 8);
+  take(p->r_kadd, (size_t)nk * nk * 4);
+  take(p->r_ksub, (size_t)nk * nk * 4);
+  take(p->r_status, 64);
+  take(p->r_scal, 64 * 8);
+  take(p->r_partial, 1024 * 8);
+  take(p->r_P, (size_t)nk * ntau * nP * 16);
+  take(p->r_Pw, (size_t)nk * nwb * nP * 16);
+  const size_t tbuf = std::max<size_t>((size_t)tc * nk * nV * 16, (size_t)ns * ntau * nk * nG * 16);
+  take(p->r_T1, tbuf);
+  take(p->r_T2, std::max<size_t>((size_t)tc * nk * nV * 16, (size_t)nk * nV * 16));
+  take(p->r_gam, (size_t)ns * nk * nG * 16);
+  take(p->r_gamT, (size_t)ns * nk * nG * 16);
+  take(p->r_D, (size_t)naux * 16);
+  take(p->r_Sinfn, (size_t)ns * nk * nG * 16);
+  take(p->r_Sign, (size_t)ns * ntau * nk * nG * 16);
+  take(p->r_Sw, (size_t)ns * nwf * nk * nG * 16);
+  take(p->r_A, (size_t)ns * nwf * nk * nG * 16);
+  take(p->r_tr, (size_t)std::max<int64_t>(ns * nwf * nk, ns * ntau * nk) * 16);
+  p->ws_bytes = off;
+  *out = p;
+  return GREEN_OK;
+}
+
+void green_plan_destroy(green_plan* p) {
+  if (!p) return;
+  if (p->events)
+    for (int i = 0; i < kNumEvents; ++i) (void)hipEventDestroy(p->ev[i]);
+  delete p;
+}
+
+size_t green_workspace_bytes(const green_plan* p) { return p ? p->ws_bytes : 0; }
+
+int green_gw_polarization(green_plan* p, const void* V, const void* G, void* P0, void* ws, void* stream) {
+  GREEN_TRY(check_plan(p, ws));
+  if (!V || !G || !P0) return GREEN_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  GREEN_TRY(ensure_bound(p, ws, s));
+  return run_polarization(p, V, G, P0, ws, s);
+}
+
+int green_gw_screen(green_plan* p, const void* P0, void* Pt, void* ws, void* stream) {
+  GREEN_TRY(check_plan(p, ws));
+  if (!P0 || !Pt) return GREEN_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  GREEN_TRY(ensure_bound(p, ws, s));
+  return run_screen(p, P0, Pt, ws, s);
+}
+
+int green_gw_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, void* Sigma, void* ws,
+                        void* stream) {
+  GREEN_TRY(check_plan(p, ws));
+  if (!V || !G || !Pt || !Sigma) return GREEN_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  GREEN_TRY(ensure_bound(p, ws, s));
+  return run_selfenergy(p, V, G, Pt, Sigma, ws, s);
+}
+
+int green_hf_static(green_plan* p, const void* V, const void* G, void* Sinf, void* ws, void* stream) {
+  GREEN_TRY(check_plan(p, ws));
+  if (!V || !G || !Sinf) return GREEN_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  GREEN_TRY(ensure_bound(p, ws, s));
+  return run_hf(p, V, G, Sinf, ws, s);
+}
+
+int green_dyson(green_plan* p, const void* H0, const void* S, const void* Sinf, const void* Sigma, double n_target,
+                double* mu, void* G, double* n_out, int32_t* evals_out, void* ws, void* stream) {
+  GREEN_TRY(check_plan(p, ws));
+  if (!H0 || !S || !Sinf || !Sigma || !mu || !G || !std::isfinite(*mu)) return GREEN_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  GREEN_TRY(ensure_bound(p, ws, s));
+  return run_dyson(p, H0, S, Sinf, Sigma, n_target, mu, G, n_out, evals_out, ws, s);
+}
+
+int green_gw_iterate(green_plan* p, const void* V, const void* H0, const void* S, void* G, void* Sinf, void* Sigma,
+                     double* mu, double n_target, double alpha, green_report* rep, void* ws, void* stream) {
+  GREEN_TRY(check_plan(p, ws));
+  if (!V || !H0 || !S || !G || !Sinf || !Sigma || !mu || !rep || !std::isfinite(*mu)) return GREEN_EINVAL;
+  if (!(alpha > 0.0 && alpha < 2.0)) return GREEN_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  GREEN_TRY(ensure_bound(p, ws, s));
+  std::memset(rep, 0, sizeof(*rep));
+  const green_dims& d = p->d;
+  const int64_t nG = (int64_t)d.nao * d.nao;
+  const int64_t nsig = (int64_t)d.nspin * d.ntau * p->nk * nG, ninf = (int64_t)d.nspin * p->nk * nG;
+  double2* P = at<double2>(ws, p->r_P);
+  double2* Sinfn = at<double2>(ws, p->r_Sinfn);
+  double2* Sign = at<double2>(ws, p->r_Sign);
+  double* scal = at<double>(ws, p->r_scal);
+  const bool dry = green::dryrun();
+  if (!dry && !p->events) {
+    for (int i = 0; i < kNumEvents; ++i)
+      if (hipEventCreate(&p->ev[i]) != hipSuccess) {
+        for (int j = 0; j < i; ++j) (void)hipEventDestroy(p->ev[j]);
+        return GREEN_EHIP;
+      }
+    p->events = true;
+  }
+  auto mark = [&](int i) { return dry ? hipSuccess : hipEventRecord(p->ev[i], s); };
+  HIP_TRY(mark(0));
+  GREEN_TRY(run_hf(p, V, G, Sinfn, ws, s));
+  HIP_TRY(mark(1));
+  GREEN_TRY(run_polarization(p, V, G, P, ws, s));
+  HIP_TRY(mark(2));
+  GREEN_TRY(run_screen(p, P, P, ws, s));
+  HIP_TRY(mark(3));
+  GREEN_TRY(run_selfenergy(p, V, G, P, Sign, ws, s));
+  HIP_TRY(mark(4));
+  if (!dry) {
+    HIP_TRY(green::launch_mix(static_cast<double2*>(Sinf), Sinfn, alpha, ninf, nullptr, nullptr, s));
+    HIP_TRY(green::launch_mix(static_cast<double2*>(Sigma), Sign, alpha, nsig, at<double>(ws, p->r_partial),
+                              scal + 8, s));
+  }
+  HIP_TRY(mark(5));
+  double n = 0.0;
+  int32_t evals = 0;
+  GREEN_TRY(run_dyson(p, H0, S, Sinf, Sigma, n_target, mu, G, &n, &evals, ws, s));
+  HIP_TRY(mark(6));
+  GREEN_TRY(run_energy(p, H0, G, Sinf, Sigma, ws, s, rep));
+  HIP_TRY(mark(7));
+  double dsig = 0.0;
+  rep->n_elec = n;
+  rep->mu = *mu;
+  rep->mu_evals = evals;
+  if (dry) return GREEN_OK;
+  HIP_TRY(hipMemcpyAsync(&dsig, scal + 8, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  rep->max_dsigma = dsig;
+  for (int i = 0; i < 7; ++i) HIP_TRY(hipEventElapsedTime(&rep->ms[i], p->ev[i], p->ev[i + 1]));
+  HIP_TRY(hipEventElapsedTime(&rep->ms[7], p->ev[0], p->ev[7]));
+  if (!std::isfinite(rep->e_tot) || !std::isfinite(dsig) || !std::isfinite(rep->herm_err)) return GREEN_ENAN;
+  return GREEN_OK;
+}
+
+}  // extern "C"

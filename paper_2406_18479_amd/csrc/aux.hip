@@ -1,0 +1,274 @@
+// Small element-wise and reduction kernels of the GW iteration.
+//
+// Reductions are deterministic: a first pass writes one partial per block (a
+// fixed tree inside the block), a second single-block pass combines the
+// partials in index order, so results are bitwise reproducible for a given
+// problem size.
+#include "aux.h"
+
+namespace green {
+namespace {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+template <typename T, typename Op>
+__device__ T block_reduce(T v, Op op, T* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s) sh[tid] = op(sh[tid], sh[tid + s]);
+    __syncthreads();
+  }
+  const T r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+struct AddD {
+  __device__ double operator()(double a, double b) const { return a + b; }
+};
+struct MaxD {
+  __device__ double operator()(double a, double b) const { return a > b ? a : b; }
+};
+
+// gam[s][k] = -G[s][ntau-1][k];  gamT[s][k] = gam[s][k]^T   (G(0^-) = -G(beta^-))
+__global__ void k_density(const double2* __restrict__ G, double2* __restrict__ gam, double2* __restrict__ gamT,
+                          int ns, int ntau, int nk, int nao) {
+  const int64_t nG = (int64_t)nao * nao;
+  const int64_t total = (int64_t)ns * nk * nG;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t sk = x / nG;
+    const int e = (int)(x - sk * nG);
+    const int i = e / nao, j = e - (e / nao) * nao;
+    const int s = (int)(sk / nk), k = (int)(sk - (int64_t)s * nk);
+    const double2 v = G[(((int64_t)s * ntau + (ntau - 1)) * nk + k) * nG + e];
+    const double2 g = make_double2(-v.x, -v.y);
+    gam[x] = g;
+    if (gamT) gamT[sk * nG + (int64_t)j * nao + i] = g;
+  }
+}
+
+// A[b] = I - A[b]  (n x n, batch stride n*n)
+__global__ void k_one_minus(double2* __restrict__ A, int n, int64_t batch) {
+  const int64_t nn = (int64_t)n * n;
+  const int64_t total = nn * batch;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+    const int e = (int)(x % nn);
+    const bool diag = (e / n) == (e % n);
+    double2 v = A[x];
+    v.x = (diag ? 1.0 : 0.0) - v.x;
+    v.y = -v.y;
+    A[x] = v;
+  }
+}
+
+// A[b] = A[b] - I
+__global__ void k_minus_one(double2* __restrict__ A, int n, int64_t batch) {
+  const int64_t nn = (int64_t)n * n;
+  const int64_t total = nn * batch;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+    const int e = (int)(x % nn);
+    if ((e / n) == (e % n)) A[x].x -= 1.0;
+  }
+}
+
+// Dyson matrices A[s][m][k] = (i w_m + mu) S[k] - H0[s][k] - Sinf[s][k] - Sw[s][m][k]
+__global__ void k_dyson_form(double2* __restrict__ A, const double2* __restrict__ S, const double2* __restrict__ H0,
+                             const double2* __restrict__ Sinf, const double2* __restrict__ Sw,
+                             const double* __restrict__ wf, double mu, int ns, int nw, int nk, int nao) {
+  const int64_t nG = (int64_t)nao * nao;
+  const int64_t total = (int64_t)ns * nw * nk * nG;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = x / nG;
+    const int64_t e = x - b * nG;
+    const int k = (int)(b % nk);
+    const int64_t sm = b / nk;
+    const int m = (int)(sm % nw);
+    const int s = (int)(sm / nw);
+    const double2 sv = S[(int64_t)k * nG + e];
+    const double2 h = H0[((int64_t)s * nk + k) * nG + e];
+    const double2 si = Sinf[((int64_t)s * nk + k) * nG + e];
+    const double2 sw = Sw[x];
+    const double w = wf[m];
+    double2 v;
+    // (mu + i w) * S
+    v.x = mu * sv.x - w * sv.y;
+    v.y = mu * sv.y + w * sv.x;
+    v.x -= h.x + si.x + sw.x;
+    v.y -= h.y + si.y + sw.y;
+    A[x] = v;
+  }
+}
+
+// tr[b] = sum_ij X_b[i][j] Y_{b'}[j][i],  X_b at X + xoff(b), Y at Y + yoff(b)
+//   xoff(b) = b * xs;  yoff(b) = ((b / ydiv) % ymod) * ys + (b / (ydiv * ymod)) * ys2
+__global__ __launch_bounds__(256) void k_trace_prod(const double2* __restrict__ X, int64_t xs,
+                                                    const double2* __restrict__ Y, int64_t ydiv, int64_t ymod,
+                                                    int64_t ys, int64_t ys2, int nao, double2* __restrict__ tr) {
+  __shared__ double sh[256];
+  const int64_t b = blockIdx.x;
+  const double2* x = X + b * xs;
+  const double2* y = Y + ((b / ydiv) % ymod) * ys + (b / (ydiv * ymod)) * ys2;
+  double re = 0.0, im = 0.0;
+  const int nn = nao * nao;
+  for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+    const int i = e / nao, j = e - (e / nao) * nao;
+    const double2 p = cmul(x[e], y[j * nao + i]);
+    re += p.x;
+    im += p.y;
+  }
+  re = block_reduce(re, AddD(), sh);
+  im = block_reduce(im, AddD(), sh);
+  if (threadIdx.x == 0) tr[b] = make_double2(re, im);
+}
+
+// out = scale * sum_b Re(w[(b / wdiv) % wmod] * tr[b])   (w == nullptr: weight 1); single block, fixed order.
+__global__ __launch_bounds__(256) void k_weighted_sum(const double2* __restrict__ tr, int64_t n,
+                                                      const double2* __restrict__ w, int64_t wdiv, int64_t wmod,
+                                                      int64_t wstride, double scale, double* __restrict__ out) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int64_t b = threadIdx.x; b < n; b += blockDim.x) {
+    double2 t = tr[b];
+    if (w) t = cmul(w[((b / wdiv) % wmod) * wstride], t);
+    acc += t.x;
+  }
+  acc = block_reduce(acc, AddD(), sh);
+  if (threadIdx.x == 0) *out = scale * acc;
+}
+
+// Mixing with diagnostics: S = alpha * Snew + (1 - alpha) * S; partial[block] = max |S_out - S_in|
+__global__ __launch_bounds__(256) void k_mix(double2* __restrict__ S, const double2* __restrict__ Snew, double alpha,
+                                             int64_t n, double* __restrict__ partial) {
+  __shared__ double sh[256];
+  double mx = 0.0;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+    const double2 o = S[x];
+    const double2 a = Snew[x];
+    double2 v;
+    if (alpha == 1.0) {
+      v = a;
+    } else {
+      v.x = alpha * a.x + (1.0 - alpha) * o.x;
+      v.y = alpha * a.y + (1.0 - alpha) * o.y;
+    }
+    const double dx = v.x - o.x, dy = v.y - o.y;
+    const double d = sqrt(dx * dx + dy * dy);
+    mx = (d > mx || d != d) ? d : mx;
+    S[x] = v;
+  }
+  mx = block_reduce(mx, MaxD(), sh);
+  if (partial && threadIdx.x == 0) partial[blockIdx.x] = mx;
+}
+
+// partial[block] = max |X_b[i][j] - conj X_b[j][i]| over matrices of size nao
+__global__ __launch_bounds__(256) void k_herm(const double2* __restrict__ X, int64_t nmat, int nao,
+                                              double* __restrict__ partial) {
+  __shared__ double sh[256];
+  const int64_t nG = (int64_t)nao * nao;
+  const int64_t total = nmat * nG;
+  double mx = 0.0;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = x / nG;
+    const int e = (int)(x - b * nG);
+    const int i = e / nao, j = e - (e / nao) * nao;
+    const double2 a = X[x];
+    const double2 c = X[b * nG + (int64_t)j * nao + i];
+    const double dx = a.x - c.x, dy = a.y + c.y;
+    const double d = sqrt(dx * dx + dy * dy);
+    mx = (d > mx || d != d) ? d : mx;
+  }
+  mx = block_reduce(mx, MaxD(), sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = mx;
+}
+
+__global__ __launch_bounds__(256) void k_max_partials(const double* __restrict__ partial, int n,
+                                                      double* __restrict__ out) {
+  __shared__ double sh[256];
+  double mx = 0.0;
+  for (int b = threadIdx.x; b < n; b += blockDim.x) {
+    const double v = partial[b];
+    mx = (v > mx || v != v) ? v : mx;
+  }
+  mx = block_reduce(mx, MaxD(), sh);
+  if (threadIdx.x == 0) *out = mx;
+}
+
+__global__ void k_zero(double2* __restrict__ X, int64_t n) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
+    X[x] = make_double2(0.0, 0.0);
+}
+
+inline unsigned grid_for(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+}  // namespace
+
+hipError_t launch_density(const double2* G, double2* gam, double2* gamT, int ns, int ntau, int nk, int nao,
+                          hipStream_t s) {
+  const int64_t n = (int64_t)ns * nk * nao * nao;
+  hipLaunchKernelGGL(k_density, dim3(grid_for(n)), dim3(256), 0, s, G, gam, gamT, ns, ntau, nk, nao);
+  return hipGetLastError();
+}
+
+hipError_t launch_one_minus(double2* A, int n, int64_t batch, hipStream_t s) {
+  hipLaunchKernelGGL(k_one_minus, dim3(grid_for((int64_t)n * n * batch)), dim3(256), 0, s, A, n, batch);
+  return hipGetLastError();
+}
+
+hipError_t launch_minus_one(double2* A, int n, int64_t batch, hipStream_t s) {
+  hipLaunchKernelGGL(k_minus_one, dim3(grid_for((int64_t)n * n * batch)), dim3(256), 0, s, A, n, batch);
+  return hipGetLastError();
+}
+
+hipError_t launch_dyson_form(double2* A, const double2* S, const double2* H0, const double2* Sinf,
+                             const double2* Sw, const double* wf, double mu, int ns, int nw, int nk, int nao,
+                             hipStream_t s) {
+  const int64_t n = (int64_t)ns * nw * nk * nao * nao;
+  hipLaunchKernelGGL(k_dyson_form, dim3(grid_for(n)), dim3(256), 0, s, A, S, H0, Sinf, Sw, wf, mu, ns, nw, nk, nao);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace_prod(const double2* X, int64_t xs, const double2* Y, int64_t ydiv, int64_t ymod, int64_t ys,
+                             int64_t ys2, int nao, int64_t nb, double2* tr, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_trace_prod, dim3((unsigned)nb), dim3(256), 0, s, X, xs, Y, ydiv, ymod, ys, ys2, nao, tr);
+  return hipGetLastError();
+}
+
+hipError_t launch_weighted_sum(const double2* tr, int64_t n, const double2* w, int64_t wdiv, int64_t wmod,
+                               int64_t wstride, double scale, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_weighted_sum, dim3(1), dim3(256), 0, s, tr, n, w, wdiv, wmod, wstride, scale, out);
+  return hipGetLastError();
+}
+
+int mix_blocks(int64_t n) { return (int)grid_for(n) > 1024 ? 1024 : (int)grid_for(n); }
+
+hipError_t launch_mix(double2* S, const double2* Snew, double alpha, int64_t n, double* partial, double* out,
+                      hipStream_t s) {
+  const int nb = mix_blocks(n);
+  hipLaunchKernelGGL(k_mix, dim3(nb), dim3(256), 0, s, S, Snew, alpha, n, partial);
+  if (partial && out) hipLaunchKernelGGL(k_max_partials, dim3(1), dim3(256), 0, s, partial, nb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_herm(const double2* X, int64_t nmat, int nao, double* partial, double* out, hipStream_t s) {
+  const int nb = mix_blocks(nmat * nao * nao);
+  hipLaunchKernelGGL(k_herm, dim3(nb), dim3(256), 0, s, X, nmat, nao, partial);
+  hipLaunchKernelGGL(k_max_partials, dim3(1), dim3(256), 0, s, partial, nb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(double2* X, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero, dim3(grid_for(n)), dim3(256), 0, s, X, n);
+  return hipGetLastError();
+}
+
+}  // namespace green

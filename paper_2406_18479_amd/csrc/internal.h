@@ -1,0 +1,75 @@
+// Internal declarations shared by the HIP translation units of libgreen_gw.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace green {
+
+// Logical index x -> (x % ext) * s_in + (x / ext) * s_out  (a two-level strided map).
+// A plain strided index uses ext = kFlat.
+struct IdxMap {
+  int32_t ext;
+  int64_t s_in;
+  int64_t s_out;
+};
+constexpr int32_t kFlat = 0x7fffffff;
+
+static inline IdxMap flat(int64_t s) { return IdxMap{kFlat, s, 0}; }
+static inline IdxMap two(int32_t ext, int64_t s_in, int64_t s_out) { return IdxMap{ext, s_in, s_out}; }
+
+// Batch index b -> offset: lo = b % ext_lo, hi = b / ext_lo;
+// offset = (tab ? tab[lo] : lo) * s_lo + hi * s_hi.
+struct BatchMap {
+  int32_t ext_lo;
+  int64_t s_lo;
+  const int32_t* tab;   // device, optional
+  int64_t s_hi;
+  const int32_t* htab;  // host mirror of tab (bounds validation only)
+};
+static inline BatchMap bnone() { return BatchMap{1, 0, nullptr, 0, nullptr}; }
+static inline BatchMap bflat(int64_t s) { return BatchMap{kFlat, s, nullptr, 0, nullptr}; }
+static inline BatchMap btwo(int32_t ext_lo, int64_t s_lo, const int32_t* tab, int64_t s_hi,
+                            const int32_t* htab = nullptr) {
+  return BatchMap{ext_lo, s_lo, tab, s_hi, htab};
+}
+
+// Complex operand of a batched GEMM: element (r, c) of batch b at p[batch(b) + r_map(r) + c_map(c)].
+struct ZOp {
+  const double2* p;
+  IdxMap r, c;
+  BatchMap b;
+  int32_t conj;
+};
+
+// C[b] = alpha * op(A[b]) * op(B[b]) + beta * C[b]   (A: M x K, B: K x N, complex FP64).
+// beta == 0 means C is not read.
+struct ZGemm {
+  int32_t M, N, K, batch;
+  ZOp A, B;
+  double2* C;
+  IdxMap cr, cc;
+  BatchMap cb;
+  double2 alpha, beta;
+};
+
+hipError_t zgemm(const ZGemm& g, hipStream_t s);
+
+// Extent of a buffer in complex elements: every element an operand touches must lie in [base, base + count).
+struct Span {
+  const void* base;
+  int64_t count;
+};
+
+// Host-side bounds check of a GEMM descriptor against the buffers its operands point into (conservative:
+// the box spanned by the index maps).  Returns false and fills `why` when an access could leave a buffer.
+bool zgemm_in_bounds(const ZGemm& g, const Span& a, const Span& b, const Span& c, char* why, int why_len);
+
+// GREEN_DRYRUN=1 in the environment: validate every launch and skip it (no device access at all).
+bool dryrun();
+
+// In-place inversion of `batch` complex n x n matrices at A + b*stride (row-major), Gauss-Jordan with
+// partial pivoting.  A zero or non-finite pivot sets bit 0 of *status (the matrix is left finite).
+hipError_t zinv_batched(double2* A, int n, int64_t stride, int batch, int* status, hipStream_t s);
+
+}  // namespace green

@@ -1,0 +1,150 @@
+"""Torch-facing wrappers of the GW entry points of libgreen_gw.
+
+A :class:`Plan` owns the library plan and a workspace tensor; its methods
+take device tensors (complex128, contiguous, on the plan's device) in the
+layouts of include/green_gw.h and launch on the current torch stream.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ptr(t: torch.Tensor, shape: tuple, name: str, device) -> int:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch.Tensor")
+    if t.dtype != torch.complex128:
+        raise TypeError(f"{name}: expected complex128, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if t.device != device:
+        raise ValueError(f"{name}: on {t.device}, plan is on {device}")
+    return t.data_ptr()
+
+
+class Plan:
+    """Plan + workspace for fixed dimensions and grid (one GPU)."""
+
+    def __init__(self, kmesh, nao, naux, grid, nspin=1, prec="fp64", chunk_bytes=0, device="cuda:0"):
+        self.device = torch.device(device)
+        self.kmesh = tuple(int(x) for x in kmesh)
+        self.nk = int(np.prod(self.kmesh))
+        self.nao, self.naux, self.nspin = int(nao), int(naux), int(nspin)
+        self.ntau = int(grid.ntau)
+        self.nw_f, self.nw_b = len(grid.nf), len(grid.nb)
+        self.beta = float(grid.beta)
+        d = _lib.Dims((ctypes.c_int32 * 3)(*self.kmesh), self.nao, self.naux, self.ntau, self.nw_f, self.nw_b,
+                      self.nspin, self.beta)
+        keep = [np.ascontiguousarray(a) for a in (grid.tau, grid.wf, grid.wb)]
+        keep += [np.ascontiguousarray(a, dtype=np.complex128) for a in
+                 (grid.TF_t2w, grid.TF_w2t, grid.TB_t2w, grid.TB_w2t)]
+        g = _lib.GridC(*[a.ctypes.data for a in keep])
+        h = ctypes.c_void_p()
+        _lib.check(_lib.LIB.green_plan_create(ctypes.byref(d), ctypes.byref(g), _lib.PREC[prec], int(chunk_bytes),
+                                              ctypes.byref(h)), "green_plan_create")
+        self._h = h
+        self.ws_bytes = int(_lib.LIB.green_workspace_bytes(h))
+        with torch.cuda.device(self.device):
+            self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+
+    # shapes
+    @property
+    def shape_V(self):
+        return (self.nk, self.nk, self.naux, self.nao, self.nao)
+
+    @property
+    def shape_G(self):
+        return (self.nspin, self.ntau, self.nk, self.nao, self.nao)
+
+    @property
+    def shape_P(self):
+        return (self.nk, self.ntau, self.naux, self.naux)
+
+    @property
+    def shape_H(self):
+        return (self.nspin, self.nk, self.nao, self.nao)
+
+    @property
+    def shape_S(self):
+        return (self.nk, self.nao, self.nao)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.LIB.green_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # entry points ------------------------------------------------------------------
+    def polarization(self, V, G, P0=None):
+        P0 = torch.empty(self.shape_P, dtype=torch.complex128, device=self.device) if P0 is None else P0
+        _lib.check(_lib.LIB.green_gw_polarization(self._h, _ptr(V, self.shape_V, "V", self.device),
+                                                  _ptr(G, self.shape_G, "G", self.device),
+                                                  _ptr(P0, self.shape_P, "P0", self.device), self.ws.data_ptr(),
+                                                  _stream(self.device)), "green_gw_polarization")
+        return P0
+
+    def screen(self, P0, Pt=None):
+        Pt = torch.empty(self.shape_P, dtype=torch.complex128, device=self.device) if Pt is None else Pt
+        _lib.check(_lib.LIB.green_gw_screen(self._h, _ptr(P0, self.shape_P, "P0", self.device),
+                                            _ptr(Pt, self.shape_P, "Pt", self.device), self.ws.data_ptr(),
+                                            _stream(self.device)), "green_gw_screen")
+        return Pt
+
+    def selfenergy(self, V, G, Pt, Sigma=None):
+        Sigma = torch.empty(self.shape_G, dtype=torch.complex128, device=self.device) if Sigma is None else Sigma
+        _lib.check(_lib.LIB.green_gw_selfenergy(self._h, _ptr(V, self.shape_V, "V", self.device),
+                                                _ptr(G, self.shape_G, "G", self.device),
+                                                _ptr(Pt, self.shape_P, "Pt", self.device),
+                                                _ptr(Sigma, self.shape_G, "Sigma", self.device), self.ws.data_ptr(),
+                                                _stream(self.device)), "green_gw_selfenergy")
+        return Sigma
+
+    def hf_static(self, V, G, Sinf=None):
+        Sinf = torch.empty(self.shape_H, dtype=torch.complex128, device=self.device) if Sinf is None else Sinf
+        _lib.check(_lib.LIB.green_hf_static(self._h, _ptr(V, self.shape_V, "V", self.device),
+                                            _ptr(G, self.shape_G, "G", self.device),
+                                            _ptr(Sinf, self.shape_H, "Sinf", self.device), self.ws.data_ptr(),
+                                            _stream(self.device)), "green_hf_static")
+        return Sinf
+
+    def dyson(self, H0, S, Sinf, Sigma, mu, n_target=-1.0, G=None):
+        G = torch.empty(self.shape_G, dtype=torch.complex128, device=self.device) if G is None else G
+        m = ctypes.c_double(mu)
+        n = ctypes.c_double(0.0)
+        ev = ctypes.c_int32(0)
+        _lib.check(_lib.LIB.green_dyson(self._h, _ptr(H0, self.shape_H, "H0", self.device),
+                                        _ptr(S, self.shape_S, "S", self.device),
+                                        _ptr(Sinf, self.shape_H, "Sinf", self.device),
+                                        _ptr(Sigma, self.shape_G, "Sigma", self.device), float(n_target),
+                                        ctypes.byref(m), _ptr(G, self.shape_G, "G", self.device), ctypes.byref(n),
+                                        ctypes.byref(ev), self.ws.data_ptr(), _stream(self.device)), "green_dyson")
+        return G, m.value, n.value, ev.value
+
+    def iterate(self, V, H0, S, G, Sinf, Sigma, mu, n_target, alpha=1.0):
+        """One self-consistent iteration; G, Sinf, Sigma are updated in place.  Returns (mu, report dict)."""
+        m = ctypes.c_double(mu)
+        rep = _lib.Report()
+        _lib.check(_lib.LIB.green_gw_iterate(self._h, _ptr(V, self.shape_V, "V", self.device),
+                                             _ptr(H0, self.shape_H, "H0", self.device),
+                                             _ptr(S, self.shape_S, "S", self.device),
+                                             _ptr(G, self.shape_G, "G", self.device),
+                                             _ptr(Sinf, self.shape_H, "Sinf", self.device),
+                                             _ptr(Sigma, self.shape_G, "Sigma", self.device), ctypes.byref(m),
+                                             float(n_target), float(alpha), ctypes.byref(rep), self.ws.data_ptr(),
+                                             _stream(self.device)), "green_gw_iterate")
+        return m.value, rep.as_dict()

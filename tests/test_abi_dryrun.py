@@ -1,0 +1,75 @@
+"""Every contraction the library would launch stays inside its buffers (CPU, no device access).
+
+With GREEN_DRYRUN=1 the library validates each batched-GEMM descriptor against
+the extents of the buffers its operands point into and skips every launch.
+The pointers below are fake, widely spaced addresses that are never
+dereferenced, so production shapes (up to the 4x4x4, nao=78, naux=420 case)
+are checked without allocating their memory.
+"""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+from synth import grid as gridmod
+
+CASES = [
+    dict(kmesh=(1, 1, 1), nao=8, naux=32, ntau=20, beta=50.0, nspin=1, chunk=0),
+    dict(kmesh=(2, 2, 2), nao=26, naux=180, ntau=104, beta=100.0, nspin=1, chunk=0),
+    dict(kmesh=(2, 2, 2), nao=26, naux=180, ntau=104, beta=100.0, nspin=1, chunk=50_000_000),
+    dict(kmesh=(3, 3, 3), nao=52, naux=300, ntau=136, beta=100.0, nspin=1, chunk=0),
+    dict(kmesh=(4, 4, 4), nao=78, naux=420, ntau=160, beta=200.0, nspin=2, chunk=0),
+    dict(kmesh=(3, 1, 1), nao=3, naux=70, ntau=8, beta=6.0, nspin=2, chunk=1),
+    dict(kmesh=(2, 1, 1), nao=17, naux=33, ntau=12, beta=6.0, nspin=1, chunk=1),
+]
+
+BASE = 1 << 44
+STEP = 1 << 40  # 1 TiB apart: no two fake buffers overlap
+
+
+@pytest.fixture
+def lib(monkeypatch):
+    monkeypatch.setenv("GREEN_DRYRUN", "1")
+    from paper_2406_18479_amd import _lib
+    return _lib
+
+
+def _plan(lib, c):
+    g = gridmod.make_grid(c["ntau"], c["beta"])
+    d = lib.Dims((ctypes.c_int32 * 3)(*c["kmesh"]), c["nao"], c["naux"], c["ntau"], len(g.nf), len(g.nb),
+                 c["nspin"], c["beta"])
+    keep = [np.ascontiguousarray(a) for a in (g.tau, g.wf, g.wb)]
+    keep += [np.ascontiguousarray(a, dtype=np.complex128) for a in (g.TF_t2w, g.TF_w2t, g.TB_t2w, g.TB_w2t)]
+    gc = lib.GridC(*[a.ctypes.data for a in keep])
+    h = ctypes.c_void_p()
+    st = lib.LIB.green_plan_create(ctypes.byref(d), ctypes.byref(gc), 0, c["chunk"], ctypes.byref(h))
+    assert st == 0, st
+    return h
+
+
+@pytest.mark.parametrize("c", CASES, ids=lambda c: f"k{c['kmesh']}_nao{c['nao']}_naux{c['naux']}_ns{c['nspin']}_ch{c['chunk']}")
+def test_all_launches_in_bounds(lib, c):
+    assert os.environ.get("GREEN_DRYRUN") == "1"
+    h = _plan(lib, c)
+    try:
+        ws_bytes = lib.LIB.green_workspace_bytes(h)
+        assert ws_bytes > 0
+        ptr = [BASE + i * STEP for i in range(10)]
+        V, G, P0, Pt, Sig, H0, S, Sinf, G2, ws = ptr
+        L = lib.LIB
+        assert L.green_gw_polarization(h, V, G, P0, ws, None) == 0
+        assert L.green_gw_screen(h, P0, Pt, ws, None) == 0
+        assert L.green_gw_selfenergy(h, V, G, Pt, Sig, ws, None) == 0
+        assert L.green_hf_static(h, V, G, Sinf, ws, None) == 0
+        mu = ctypes.c_double(0.0)
+        n = ctypes.c_double(0.0)
+        ev = ctypes.c_int32(0)
+        assert L.green_dyson(h, H0, S, Sinf, Sig, 3.0, ctypes.byref(mu), G2, ctypes.byref(n), ctypes.byref(ev), ws,
+                             None) == 0
+        rep = lib.Report()
+        mu = ctypes.c_double(0.0)
+        assert L.green_gw_iterate(h, V, H0, S, G, Sinf, Sig, ctypes.byref(mu), 3.0, 1.0, ctypes.byref(rep), ws,
+                                  None) == 0
+    finally:
+        lib.LIB.green_plan_destroy(h)
