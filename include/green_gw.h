@@ -113,13 +113,19 @@ typedef struct {
   int32_t mu_evals;  /* electron-count evaluations in the mu search                       */
   int32_t pad;
   float ms[8];       /* stage times (ms): 0 HF, 1 P0, 2 screen, 3 Sigma, 4 mix, 5 Dyson+mu, 6 energy, 7 total */
+  /* HIP-event timing of the two dominant contraction launches, [0] = P~0 stage 2 (sum over k and
+   * orbital pairs into naux x naux), [1] = Sigma~ stage 1 (P~(tau)^T times V over Q):
+   * summed launch time (ms), algorithmic real flops (4M complex counting) and launch count. */
+  double kern_ms[2];
+  double kern_flops[2];
+  int32_t kern_launches[2];
 } green_report;
 
 typedef struct green_plan green_plan;
 
 /* Create a plan for fixed dimensions and grid; `prec` selects the contraction
  * arithmetic.  chunk_bytes bounds the workspace used for contraction
- * intermediates (0 = default 1 GiB).  Returns GREEN_EINVAL for inconsistent
+ * intermediates (0 = default 8 GiB).  Returns GREEN_EINVAL for inconsistent
  * dims (nao > 512, naux > 512, odd ntau, nw_f != ntau, nw_b != ntau + 1 ...). */
 int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, size_t chunk_bytes,
                       green_plan** out);

@@ -43,11 +43,16 @@ class Report(ctypes.Structure):
     _fields_ = [("e_1b", ctypes.c_double), ("e_hf", ctypes.c_double), ("e_corr", ctypes.c_double),
                 ("e_tot", ctypes.c_double), ("n_elec", ctypes.c_double), ("mu", ctypes.c_double),
                 ("max_dsigma", ctypes.c_double), ("herm_err", ctypes.c_double), ("mu_evals", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("ms", ctypes.c_float * 8)]
+                ("pad", ctypes.c_int32), ("ms", ctypes.c_float * 8), ("kern_ms", ctypes.c_double * 2),
+                ("kern_flops", ctypes.c_double * 2), ("kern_launches", ctypes.c_int32 * 2)]
 
     def as_dict(self) -> dict:
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("ms", "pad")}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("ms", "pad", "kern_ms", "kern_flops",
+                                                                         "kern_launches")}
         d["ms"] = list(self.ms)
+        d["kern_ms"] = list(self.kern_ms)
+        d["kern_flops"] = list(self.kern_flops)
+        d["kern_launches"] = list(self.kern_launches)
         return d
 
 

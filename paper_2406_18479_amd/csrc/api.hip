@@ -35,11 +35,12 @@ struct green_plan {
   std::vector<int32_t> kadd, ksub, kneg;  // [q][k]: k+q, k-q; [q]: -q
   // workspace regions
   Region r_TF_t2w, r_TF_w2t, r_TB_t2w, r_TB_w2t, r_Emass, r_wf, r_kadd, r_ksub, r_status, r_scal, r_partial;
-  Region r_P, r_Pw, r_T1, r_T2, r_gam, r_gamT, r_D, r_Sinfn, r_Sign, r_Sw, r_A, r_tr;
+  Region r_P, r_Pw, r_T1, r_T2, r_gam, r_gamT, r_D, r_Sinfn, r_Sign, r_Sw, r_A, r_tr, r_split;
   size_t ws_bytes = 0;
   void* bound_ws = nullptr;
   hipEvent_t ev[kNumEvents]{};
   bool events = false;
+  void* clock = nullptr;  // KernelClock, created with the events
 };
 
 namespace {
@@ -118,7 +119,16 @@ int kflat(const int32_t* m, int a, int b, int c) {
   return (a * m[1] + b) * m[2] + c;
 }
 
+// Split-K scratch of the current call (a workspace region), set by every entry point.
+struct SplitBuf {
+  double2* ptr = nullptr;
+  int64_t cap = 0;  // complex elements
+};
+thread_local SplitBuf tl_split;
+
 int ensure_bound(green_plan* p, void* ws, hipStream_t s) {
+  tl_split.ptr = reinterpret_cast<double2*>(static_cast<char*>(ws) + p->r_split.off);
+  tl_split.cap = (int64_t)(p->r_split.bytes / sizeof(double2));
   if (p->bound_ws == ws) return GREEN_OK;
   if (green::dryrun()) return GREEN_OK;
   auto up = [&](const Region& r, const void* src) {
@@ -140,6 +150,61 @@ int ensure_bound(green_plan* p, void* ws, hipStream_t s) {
 
 inline double2 cplx(double re, double im = 0.0) { return make_double2(re, im); }
 
+// HIP-event timing of the two hot contraction launches (P~0 stage 2 and Sigma~ stage 1) inside
+// green_gw_iterate: one event pair per launch, read after the iteration's final synchronisation.
+struct KernelClock {
+  std::vector<hipEvent_t> ev[2];
+  int used[2] = {0, 0};
+  double flops[2] = {0.0, 0.0};
+  int begin(int slot, hipStream_t s) {
+    const size_t need = 2 * (size_t)used[slot] + 2;
+    while (ev[slot].size() < need) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return GREEN_EHIP;
+      ev[slot].push_back(e);
+    }
+    return hip_status(hipEventRecord(ev[slot][2 * used[slot]], s));
+  }
+  int end(int slot, hipStream_t s, double f) {
+    flops[slot] += f;
+    const int e = hip_status(hipEventRecord(ev[slot][2 * used[slot] + 1], s));
+    used[slot] += 1;
+    return e;
+  }
+  void reset() {
+    used[0] = used[1] = 0;
+    flops[0] = flops[1] = 0.0;
+  }
+  int read(int slot, double* ms) const {
+    double tot = 0.0;
+    for (int i = 0; i < used[slot]; ++i) {
+      float m = 0.f;
+      if (hipEventElapsedTime(&m, ev[slot][2 * i], ev[slot][2 * i + 1]) != hipSuccess) return GREEN_EHIP;
+      tot += m;
+    }
+    *ms = tot;
+    return GREEN_OK;
+  }
+  ~KernelClock() {
+    for (auto& v : ev)
+      for (hipEvent_t e : v) (void)hipEventDestroy(e);
+  }
+};
+thread_local KernelClock* tl_clock = nullptr;
+
+
+// Split the K range when the output tiles alone cannot fill the GPU (256 CUs): aim for ~2048
+// workgroups, keep every slice at least 64 deep, and fit the partial sums into the scratch region.
+int choose_ksplit(int M, int N, int K, int batch) {
+  const int bm = M <= 32 ? 32 : 64, bn = N <= 32 ? 32 : 64;
+  const int64_t tiles = (int64_t)((M + bm - 1) / bm) * ((N + bn - 1) / bn) * batch;
+  if (tiles >= 1024) return 1;
+  int ks = (int)std::min<int64_t>((2048 + tiles - 1) / tiles, 32);
+  ks = std::min(ks, std::max(1, K / 64));
+  while (ks > 1 && (int64_t)ks * batch * M * N > tl_split.cap) --ks;
+  return std::max(ks, 1);
+}
+
 ZOp op(const void* ptr, IdxMap r, IdxMap c, BatchMap b, int conj = 0) {
   ZOp o;
   o.p = static_cast<const double2*>(ptr);
@@ -150,10 +215,11 @@ ZOp op(const void* ptr, IdxMap r, IdxMap c, BatchMap b, int conj = 0) {
   return o;
 }
 
-int gemm(const char* label, const ZOp& A, const green::Span& sa, const ZOp& B, const green::Span& sb, void* C,
+int gemm(green::Site site, const char* label, const ZOp& A, const green::Span& sa, const ZOp& B, const green::Span& sb, void* C,
          const green::Span& sc, IdxMap cr, IdxMap cc, BatchMap cb, int M, int N, int K, int batch, double2 alpha,
          double2 beta, hipStream_t s) {
   ZGemm g;
+  g.site = site;
   g.M = M;
   g.N = N;
   g.K = K;
@@ -166,10 +232,21 @@ int gemm(const char* label, const ZOp& A, const green::Span& sa, const ZOp& B, c
   g.cb = cb;
   g.alpha = alpha;
   g.beta = beta;
+  g.ksplit = choose_ksplit(M, N, K, batch);
+  g.partial = g.ksplit > 1 ? tl_split.ptr : nullptr;
   char why[256];
+  if (g.ksplit > 1 && (int64_t)g.ksplit * batch * M * N > tl_split.cap) return GREEN_EINVAL;
   if (!green::zgemm_in_bounds(g, sa, sb, sc, why, sizeof(why))) {
     std::fprintf(stderr, "green_gw: contraction '%s' rejected: %s\n", label, why);
     return GREEN_EINVAL;
+  }
+  const int slot = site == green::Site::P0_Contract ? 0 : (site == green::Site::Sig_PV ? 1 : -1);
+  KernelClock* clk = tl_clock;
+  if (clk && slot >= 0 && !green::dryrun()) {
+    GREEN_TRY(clk->begin(slot, s));
+    GREEN_TRY(hip_status(green::zgemm(g, s)));
+    GREEN_TRY(clk->end(slot, s, 8.0 * M * (double)N * K * batch));
+    return GREEN_OK;
   }
   return hip_status(green::zgemm(g, s));
 }
@@ -224,20 +301,20 @@ int run_polarization(green_plan* p, const void* V, const void* G, void* P0, void
       const int tcn = std::min(p->tc, ntau - t0);
       for (int sp = 0; sp < ns; ++sp) {
         // T1[tt][k][(Q,d)][b] = sum_a V^{k,k+q}_{da}(Q) G^{k+q}_{ab}(tau)
-        GREEN_TRY(gemm("P0.VG", op(Vp + q * slab, flat(nao), flat(1), btwo(nk, nV, nullptr, 0)), sV,
+        GREEN_TRY(gemm(green::Site::P0_VG, "P0.VG", op(Vp + q * slab, flat(nao), flat(1), btwo(nk, nV, nullptr, 0)), sV,
                        op(Gp + ((int64_t)sp * ntau + t0) * nk * nG, flat(nao), flat(1),
                           btwo(nk, nG, kadd + q * nk, (int64_t)nk * nG, hadd + q * nk)),
                        sG, T1, sT1, flat(nao), flat(1), bflat(nV), naux * nao, nao, nao, tcn * nk, cplx(1),
                        cplx(0), s));
         // T2[tt][k][Q'][d][b] = sum_c V^{k+q,k}_{bc}(Q') G^k_{cd}(beta - tau)   (stored transposed in (b, d))
-        GREEN_TRY(gemm("P0.VGrev", op(Vp + qn * slab, flat(nao), flat(1), btwo(nk, nV, kadd + q * nk, 0, hadd + q * nk)),
+        GREEN_TRY(gemm(green::Site::P0_VGrev, "P0.VGrev", op(Vp + qn * slab, flat(nao), flat(1), btwo(nk, nV, kadd + q * nk, 0, hadd + q * nk)),
                        sV,
                        op(Gp + ((int64_t)sp * ntau + (ntau - 1 - t0)) * nk * nG, flat(nao), flat(1),
                           btwo(nk, nG, nullptr, -(int64_t)nk * nG)),
                        sG, T2, sT2, two(nao, 1, nG), flat(nao), bflat(nV), naux * nao, nao, nao, tcn * nk,
                        cplx(1), cplx(0), s));
         // P0[q][t][Q][Q'] (+)= -(w/nk) sum_{k,(d,b)} T1[tt][k][Q][(d,b)] T2[tt][k][Q'][(d,b)]
-        GREEN_TRY(gemm("P0.contract", op(T1, flat(nG), two((int32_t)nG, 1, nV), bflat((int64_t)nk * nV)), sT1,
+        GREEN_TRY(gemm(green::Site::P0_Contract, "P0.contract", op(T1, flat(nG), two((int32_t)nG, 1, nV), bflat((int64_t)nk * nV)), sT1,
                        op(T2, two((int32_t)nG, 1, nV), flat(nG), bflat((int64_t)nk * nV)), sT2,
                        Pp + ((int64_t)q * ntau + t0) * naux * naux, sP, flat(naux), flat(1),
                        bflat((int64_t)naux * naux), naux, naux, (int)(nk * nG), tcn, cplx(-w / nk),
@@ -257,7 +334,7 @@ int run_screen(green_plan* p, const void* P0, void* Pt, void* ws, hipStream_t s)
   double2* Pw = at<double2>(ws, p->r_Pw);
   const green::Span sPw = span_ws(ws, p->r_Pw);
   // P0(i W_m) = sum_t TB_t2w[m][t] P0(tau_t)
-  GREEN_TRY(gemm("screen.t2w", op(at<double2>(ws, p->r_TB_t2w), flat(ntau), flat(1), bnone()),
+  GREEN_TRY(gemm(green::Site::Transform, "screen.t2w", op(at<double2>(ws, p->r_TB_t2w), flat(ntau), flat(1), bnone()),
                  span_ws(ws, p->r_TB_t2w), op(P0, flat(nP), flat(1), bflat((int64_t)ntau * nP)), span(P0, ex.P), Pw,
                  sPw, flat(nP), flat(1), bflat((int64_t)nwb * nP), nwb, (int)nP, ntau, nk, cplx(1), cplx(0), s));
   // P~(i W) = [I - P0]^{-1} P0 = [I - P0]^{-1} - I
@@ -268,7 +345,7 @@ int run_screen(green_plan* p, const void* P0, void* Pt, void* ws, hipStream_t s)
     HIP_TRY(green::launch_minus_one(Pw, naux, (int64_t)nk * nwb, s));
   }
   // P~(tau_t) = sum_m TB_w2t[t][m] P~(i W_m)
-  GREEN_TRY(gemm("screen.w2t", op(at<double2>(ws, p->r_TB_w2t), flat(nwb), flat(1), bnone()),
+  GREEN_TRY(gemm(green::Site::Transform, "screen.w2t", op(at<double2>(ws, p->r_TB_w2t), flat(nwb), flat(1), bnone()),
                  span_ws(ws, p->r_TB_w2t), op(Pw, flat(nP), flat(1), bflat((int64_t)nwb * nP)), sPw, Pt,
                  span(Pt, ex.P), flat(nP), flat(1), bflat((int64_t)ntau * nP), ntau, (int)nP, nwb, nk, cplx(1),
                  cplx(0), s));
@@ -298,19 +375,19 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
     for (int t0 = 0; t0 < ntau; t0 += p->tc) {
       const int tcn = std::min(p->tc, ntau - t0);
       // X[tt][k][Q'][(i,a)] = sum_Q P~^q_{QQ'}(tau) V^{k,k-q}_{ia}(Q)
-      GREEN_TRY(gemm("Sigma.PV", op(Pp + ((int64_t)q * ntau + t0) * nP, flat(1), flat(naux), bflat(nP)), sP,
+      GREEN_TRY(gemm(green::Site::Sig_PV, "Sigma.PV", op(Pp + ((int64_t)q * ntau + t0) * nP, flat(1), flat(naux), bflat(nP)), sP,
                      op(Vp + qn * slab, flat(nG), two((int32_t)nG, 1, nV), bnone()), sV, T1, sT1, flat(nG),
                      two((int32_t)nG, 1, nV), bflat((int64_t)nk * nV), naux, (int)(nk * nG), naux, tcn, cplx(1),
                      cplx(0), s));
       for (int sp = 0; sp < ns; ++sp) {
         // Y[tt][k][(Q',i)][b] = sum_a X[tt][k][(Q',i)][a] G^{k-q}_{ab}(tau)
-        GREEN_TRY(gemm("Sigma.XG", op(T1, flat(nao), flat(1), bflat(nV)), sT1,
+        GREEN_TRY(gemm(green::Site::Sig_XG, "Sigma.XG", op(T1, flat(nao), flat(1), bflat(nV)), sT1,
                        op(Gp + ((int64_t)sp * ntau + t0) * nk * nG, flat(nao), flat(1),
                           btwo(nk, nG, ksub + q * nk, (int64_t)nk * nG, hsub + q * nk)),
                        sG, T2, sT2, flat(nao), flat(1), bflat(nV), naux * nao, nao, nao, tcn * nk, cplx(1), cplx(0),
                        s));
         // Sigma[s][t][k][i][j] += -(1/nk) sum_{(Q',b)} Y[tt][k][Q'][i][b] V^{k-q,k}_{bj}(Q')
-        GREEN_TRY(gemm("Sigma.YV", op(T2, flat(nao), two(nao, 1, nG), bflat(nV)), sT2,
+        GREEN_TRY(gemm(green::Site::Sig_YV, "Sigma.YV", op(T2, flat(nao), two(nao, 1, nG), bflat(nV)), sT2,
                        op(Vp + q * slab, two(nao, nao, nG), flat(1), btwo(nk, nV, ksub + q * nk, 0, hsub + q * nk)),
                        sV, Sp + ((int64_t)sp * ntau + t0) * nk * nG, sS, flat(nao), flat(1), bflat(nG), nao, nao,
                        naux * nao, tcn * nk, cplx(-1.0 / nk), cplx(1.0), s));
@@ -341,22 +418,22 @@ int run_hf(green_plan* p, const void* V, const void* G, void* Sinf, void* ws, hi
     HIP_TRY(green::launch_density(static_cast<const double2*>(G), gam, gamT, ns, ntau, nk, nao, s));
   // Hartree density D[Q] = (w/nk) sum_{s,k'} sum_{ab} V^{k'k'}_{ba}(Q) gamma^{k'}_{ab}
   for (int sp = 0; sp < ns; ++sp)
-    GREEN_TRY(gemm("HF.density", op(Vp, flat(nG), two((int32_t)nG, 1, nV), bnone()), sV,
+    GREEN_TRY(gemm(green::Site::HF, "HF.density", op(Vp, flat(nG), two((int32_t)nG, 1, nV), bnone()), sV,
                    op(gamT + (int64_t)sp * nk * nG, flat(1), flat(0), bnone()), sGamT, D, sD, flat(1), flat(0),
                    bnone(), naux, 1, (int)(nk * nG), 1, cplx(w / nk), cplx(sp == 0 ? 0.0 : 1.0), s));
   // Hartree term Sinf[s][k] = sum_Q D[Q] V^{kk}(Q)
   for (int sp = 0; sp < ns; ++sp)
-    GREEN_TRY(gemm("HF.hartree", op(D, flat(0), flat(1), bnone()), sD,
+    GREEN_TRY(gemm(green::Site::HF, "HF.hartree", op(D, flat(0), flat(1), bnone()), sD,
                    op(Vp, flat(nG), two((int32_t)nG, 1, nV), bnone()), sV, Sp + (int64_t)sp * nk * nG, sH, flat(0),
                    flat(1), bnone(), 1, (int)(nk * nG), naux, 1, cplx(1), cplx(0), s));
   // exchange: Sinf[s][k] -= (1/nk) sum_q sum_Q V^{k,k-q}(Q) gamma^{k-q} V^{k-q,k}(Q)
   for (int q = 0; q < nk; ++q) {
     const int qn = p->kneg[q];
     for (int sp = 0; sp < ns; ++sp) {
-      GREEN_TRY(gemm("HF.Vgamma", op(Vp + qn * slab, flat(nao), flat(1), bflat(nV)), sV,
+      GREEN_TRY(gemm(green::Site::HF, "HF.Vgamma", op(Vp + qn * slab, flat(nao), flat(1), bflat(nV)), sV,
                      op(gam + (int64_t)sp * nk * nG, flat(nao), flat(1), btwo(nk, nG, ksub + q * nk, 0, hsub + q * nk)),
                      sGam, T2, sT2, flat(nao), flat(1), bflat(nV), naux * nao, nao, nao, nk, cplx(1), cplx(0), s));
-      GREEN_TRY(gemm("HF.exchange", op(T2, flat(nao), two(nao, 1, nG), bflat(nV)), sT2,
+      GREEN_TRY(gemm(green::Site::HF, "HF.exchange", op(T2, flat(nao), two(nao, 1, nG), bflat(nV)), sT2,
                      op(Vp + q * slab, two(nao, nao, nG), flat(1), btwo(nk, nV, ksub + q * nk, 0, hsub + q * nk)),
                      sV, Sp + (int64_t)sp * nk * nG, sH, flat(nao), flat(1), bflat(nG), nao, nao, naux * nao, nk,
                      cplx(-1.0 / nk), cplx(1.0), s));
@@ -496,7 +573,7 @@ int run_dyson(green_plan* p, const void* H0, const void* S, const void* Sinf, co
   const Extents ex = extents(p);
   double2* Sw = at<double2>(ws, p->r_Sw);
   // Sigma~(i w_m) = sum_t TF_t2w[m][t] Sigma~(tau_t)
-  GREEN_TRY(gemm("dyson.t2w", op(at<double2>(ws, p->r_TF_t2w), flat(ntau), flat(1), bnone()),
+  GREEN_TRY(gemm(green::Site::Transform, "dyson.t2w", op(at<double2>(ws, p->r_TF_t2w), flat(ntau), flat(1), bnone()),
                  span_ws(ws, p->r_TF_t2w), op(Sig, flat(nkG), flat(1), bflat((int64_t)ntau * nkG)),
                  span(Sig, ex.Sig), Sw, span_ws(ws, p->r_Sw), flat(nkG), flat(1), bflat((int64_t)nw * nkG), nw,
                  (int)nkG, ntau, ns, cplx(1), cplx(0), s));
@@ -510,7 +587,7 @@ int run_dyson(green_plan* p, const void* H0, const void* S, const void* Sinf, co
   // final Dyson at mu, then G(tau_t) = sum_m TF_w2t[t][m] G(i w_m)
   double nfinal;
   GREEN_TRY(electron_count(c, m, &nfinal));
-  GREEN_TRY(gemm("dyson.w2t", op(at<double2>(ws, p->r_TF_w2t), flat(nw), flat(1), bnone()),
+  GREEN_TRY(gemm(green::Site::Transform, "dyson.w2t", op(at<double2>(ws, p->r_TF_w2t), flat(nw), flat(1), bnone()),
                  span_ws(ws, p->r_TF_w2t), op(at<double2>(ws, p->r_A), flat(nkG), flat(1), bflat((int64_t)nw * nkG)),
                  span_ws(ws, p->r_A), G, span(G, ex.G), flat(nkG), flat(1), bflat((int64_t)ntau * nkG), ntau,
                  (int)nkG, nw, ns, cplx(1), cplx(0), s));
@@ -535,7 +612,7 @@ int run_energy(green_plan* p, const void* H0, const void* G, const void* Sinf, c
   double2* Hm = at<double2>(ws, p->r_T1);
   const double2* Gp = static_cast<const double2*>(G);
   // Hm[s][t] = sum_t' E[t][t'] G[s][ntau-1-t']  (the interpolant of G(beta - tau) weighted by the mass matrix)
-  GREEN_TRY(gemm("energy.mass", op(at<double2>(ws, p->r_Emass), flat(ntau), flat(1), bnone()),
+  GREEN_TRY(gemm(green::Site::Transform, "energy.mass", op(at<double2>(ws, p->r_Emass), flat(ntau), flat(1), bnone()),
                  span_ws(ws, p->r_Emass), op(Gp + (int64_t)(ntau - 1) * nkG, flat(-nkG), flat(1),
                                               bflat((int64_t)ntau * nkG)),
                  span(G, ex.G), Hm, span_ws(ws, p->r_T1), flat(nkG), flat(1), bflat((int64_t)ntau * nkG), ntau,
@@ -646,7 +723,7 @@ int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, 
   // ---- workspace layout
   const int64_t nao = d.nao, naux = d.naux, ns = d.nspin;
   const int64_t nG = nao * nao, nV = naux * nG, nP = naux * naux;
-  if (chunk_bytes == 0) chunk_bytes = (size_t)1 << 30;
+  if (chunk_bytes == 0) chunk_bytes = (size_t)8 << 30;
   const size_t per_t = (size_t)2 * nk * nV * sizeof(double2);
   int tc = (int)std::max<size_t>(1, chunk_bytes / per_t);
   tc = std::min(tc, ntau);
@@ -681,6 +758,7 @@ int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, 
   take(p->r_Sw, (size_t)ns * nwf * nk * nG * 16);
   take(p->r_A, (size_t)ns * nwf * nk * nG * 16);
   take(p->r_tr, (size_t)std::max<int64_t>(ns * nwf * nk, ns * ntau * nk) * 16);
+  take(p->r_split, (size_t)256 << 20);
   p->ws_bytes = off;
   *out = p;
   return GREEN_OK;
@@ -690,6 +768,7 @@ void green_plan_destroy(green_plan* p) {
   if (!p) return;
   if (p->events)
     for (int i = 0; i < kNumEvents; ++i) (void)hipEventDestroy(p->ev[i]);
+  delete static_cast<KernelClock*>(p->clock);
   delete p;
 }
 
@@ -762,6 +841,16 @@ int green_gw_iterate(green_plan* p, const void* V, const void* H0, const void* S
     p->events = true;
   }
   auto mark = [&](int i) { return dry ? hipSuccess : hipEventRecord(p->ev[i], s); };
+  KernelClock* clk = nullptr;
+  if (!dry) {
+    if (!p->clock) p->clock = new (std::nothrow) KernelClock();
+    clk = static_cast<KernelClock*>(p->clock);
+    if (clk) clk->reset();
+  }
+  struct ClockScope {
+    explicit ClockScope(KernelClock* c) { tl_clock = c; }
+    ~ClockScope() { tl_clock = nullptr; }
+  } clock_scope(clk);
   HIP_TRY(mark(0));
   GREEN_TRY(run_hf(p, V, G, Sinfn, ws, s));
   HIP_TRY(mark(1));
@@ -793,6 +882,12 @@ int green_gw_iterate(green_plan* p, const void* V, const void* H0, const void* S
   rep->max_dsigma = dsig;
   for (int i = 0; i < 7; ++i) HIP_TRY(hipEventElapsedTime(&rep->ms[i], p->ev[i], p->ev[i + 1]));
   HIP_TRY(hipEventElapsedTime(&rep->ms[7], p->ev[0], p->ev[7]));
+  if (clk)
+    for (int slot = 0; slot < 2; ++slot) {
+      GREEN_TRY(clk->read(slot, &rep->kern_ms[slot]));
+      rep->kern_flops[slot] = clk->flops[slot];
+      rep->kern_launches[slot] = clk->used[slot];
+    }
   if (!std::isfinite(rep->e_tot) || !std::isfinite(dsig) || !std::isfinite(rep->herm_err)) return GREEN_ENAN;
   return GREEN_OK;
 }

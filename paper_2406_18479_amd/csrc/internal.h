@@ -42,15 +42,36 @@ struct ZOp {
   int32_t conj;
 };
 
+// Call sites of the batched GEMM.  Each site is its own kernel instantiation so that
+// profilers attribute time per contraction.
+enum class Site : int32_t {
+  Generic = 0,
+  P0_VG,        // P~0 stage 1: V^{k,k+q}(Q) G^{k+q}(tau)
+  P0_VGrev,     // P~0 stage 1: V^{k+q,k}(Q') G^k(beta - tau)
+  P0_Contract,  // P~0 stage 2: sum over (k, orbital pair) -> naux x naux
+  Sig_PV,       // Sigma~ stage 1: P~(tau)^T V^{k,k-q}
+  Sig_XG,       // Sigma~ stage 2: X G^{k-q}(tau)
+  Sig_YV,       // Sigma~ stage 3: Y V^{k-q,k} summed over (Q', b)
+  HF,           // Hartree-Fock terms
+  Transform,    // Matsubara transforms and the energy quadrature
+};
+
 // C[b] = alpha * op(A[b]) * op(B[b]) + beta * C[b]   (A: M x K, B: K x N, complex FP64).
 // beta == 0 means C is not read.
+//
+// Split-K: with ksplit > 1 the K range is cut into ksplit slices; each slice writes its raw sum to
+// partial[((slice * batch + b) * M + m) * N + n] and a second pass adds the slices in slice order
+// (deterministic) and applies alpha, beta and the C maps.
 struct ZGemm {
+  Site site;
   int32_t M, N, K, batch;
   ZOp A, B;
   double2* C;
   IdxMap cr, cc;
   BatchMap cb;
   double2 alpha, beta;
+  int32_t ksplit;
+  double2* partial;
 };
 
 hipError_t zgemm(const ZGemm& g, hipStream_t s);

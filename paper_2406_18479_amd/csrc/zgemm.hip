@@ -40,7 +40,7 @@ __device__ __forceinline__ int64_t batch_off(const BatchMap& b, int32_t x) {
   return l * b.s_lo + (int64_t)hi * b.s_hi;
 }
 
-template <int WM, int WN>
+template <int WM, int WN, Site SITE>
 __global__ __launch_bounds__(256) void zgemm_f64_kernel(const ZGemm g) {
   constexpr int BM = 32 * WM, BN = 32 * WN, BK = 8;
   constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
@@ -53,11 +53,17 @@ __global__ __launch_bounds__(256) void zgemm_f64_kernel(const ZGemm g) {
   const int tiles_m = (g.M + BM - 1) / BM;
   const int tiles_n = (g.N + BN - 1) / BN;
   const int64_t per_batch = (int64_t)tiles_m * tiles_n;
-  const int32_t batch = (int32_t)(blockIdx.x / per_batch);
-  const int32_t tile = (int32_t)(blockIdx.x - (int64_t)batch * per_batch);
+  const int64_t group = blockIdx.x / per_batch;  // = batch * ksplit + slice
+  const int32_t tile = (int32_t)(blockIdx.x - group * per_batch);
+  const int32_t batch = (int32_t)(group / g.ksplit);
+  const int32_t slice = (int32_t)(group - (int64_t)batch * g.ksplit);
   const int tm = tile % tiles_m;
   const int tn = tile / tiles_m;
   const int m0 = tm * BM, n0 = tn * BN;
+  // K range of this slice (slices are multiples of BK)
+  const int kchunk = ((g.K + g.ksplit - 1) / g.ksplit + BK - 1) / BK * BK;
+  const int kbeg = slice * kchunk;
+  const int kend = min(g.K, kbeg + kchunk);
 
   const double2* __restrict__ Ap = g.A.p + batch_off(g.A.b, batch);
   const double2* __restrict__ Bp = g.B.p + batch_off(g.B.b, batch);
@@ -106,7 +112,7 @@ __global__ __launch_bounds__(256) void zgemm_f64_kernel(const ZGemm g) {
     for (int e = 0; e < EA; ++e) {
       const int gk = k0 + a_k[e];
       double2 v = make_double2(0.0, 0.0);
-      if (a_ok[e] && gk < g.K) v = Ap[a_ro[e] + map_idx(g.A.c, gk)];
+      if (a_ok[e] && gk < kend) v = Ap[a_ro[e] + map_idx(g.A.c, gk)];
       v.y *= asgn;
       ra[e] = v;
     }
@@ -114,7 +120,7 @@ __global__ __launch_bounds__(256) void zgemm_f64_kernel(const ZGemm g) {
     for (int e = 0; e < EB; ++e) {
       const int gk = k0 + b_k[e];
       double2 v = make_double2(0.0, 0.0);
-      if (b_ok[e] && gk < g.K) v = Bp[map_idx(g.B.r, gk) + b_co[e]];
+      if (b_ok[e] && gk < kend) v = Bp[map_idx(g.B.r, gk) + b_co[e]];
       v.y *= bsgn;
       rb[e] = v;
     }
@@ -137,13 +143,13 @@ __global__ __launch_bounds__(256) void zgemm_f64_kernel(const ZGemm g) {
 
   const int wr = wave & 1, wc = wave >> 1;
   const int rowb = wr * 16 * WM, colb = wc * 16 * WN;
-  const int nkt = (g.K + BK - 1) / BK;
-  load(0);
+  const int nkt = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  load(kbeg);
   stage(0);
   __syncthreads();
   for (int it = 0; it < nkt; ++it) {
     const int buf = it & 1;
-    if (it + 1 < nkt) load((it + 1) * BK);
+    if (it + 1 < nkt) load(kbeg + (it + 1) * BK);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       const int kr = 4 * s + (lane >> 4);
@@ -152,13 +158,19 @@ __global__ __launch_bounds__(256) void zgemm_f64_kernel(const ZGemm g) {
       for (int i = 0; i < WM; ++i) af[i] = As[buf][kr][rowb + 16 * i + (lane & 15)];
 #pragma unroll
       for (int j = 0; j < WN; ++j) bf[j] = Bs[buf][kr][colb + 16 * j + (lane & 15)];
+      // two passes over the blocks so that consecutive MFMAs never chain on one accumulator
 #pragma unroll
       for (int i = 0; i < WM; ++i)
 #pragma unroll
         for (int j = 0; j < WN; ++j) {
           acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i].x, bf[j].x, acc_re[i][j], 0, 0, 0);
-          acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-af[i].y, bf[j].y, acc_re[i][j], 0, 0, 0);
           acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i].x, bf[j].y, acc_im[i][j], 0, 0, 0);
+        }
+#pragma unroll
+      for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+          acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-af[i].y, bf[j].y, acc_re[i][j], 0, 0, 0);
           acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i].y, bf[j].x, acc_im[i][j], 0, 0, 0);
         }
     }
@@ -168,6 +180,20 @@ __global__ __launch_bounds__(256) void zgemm_f64_kernel(const ZGemm g) {
 
   // ---- epilogue: v_mfma_f64_16x16x4f64 leaves row (lane/16) + 4 r, column lane % 16 of each 16 x 16 block
   //      in element r of the lane's accumulator
+  if (g.ksplit > 1) {
+    double2* __restrict__ Pp = g.partial + ((int64_t)slice * g.batch + batch) * (int64_t)g.M * g.N;
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+      for (int j = 0; j < WN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gm = m0 + rowb + 16 * i + (lane >> 4) + 4 * r;
+          const int gn = n0 + colb + 16 * j + (lane & 15);
+          if (gm < g.M && gn < g.N) Pp[(int64_t)gm * g.N + gn] = make_double2(acc_re[i][j][r], acc_im[i][j][r]);
+        }
+    return;
+  }
   double2* __restrict__ Cp = g.C + batch_off(g.cb, batch);
   const bool use_beta = g.beta.x != 0.0 || g.beta.y != 0.0;
 #pragma unroll
@@ -192,6 +218,35 @@ __global__ __launch_bounds__(256) void zgemm_f64_kernel(const ZGemm g) {
           Cp[off] = o;
         }
       }
+}
+
+// Second pass of split-K: C = alpha * sum_slices partial + beta * C, slices added in order.
+__global__ __launch_bounds__(256) void zgemm_splitk_reduce(const ZGemm g) {
+  const int64_t mn = (int64_t)g.M * g.N;
+  const int64_t total = mn * g.batch;
+  const bool use_beta = g.beta.x != 0.0 || g.beta.y != 0.0;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t b = (int32_t)(x / mn);
+    const int64_t e = x - (int64_t)b * mn;
+    const int32_t gm = (int32_t)(e / g.N), gn = (int32_t)(e - (int64_t)(e / g.N) * g.N);
+    double vr = 0.0, vi = 0.0;
+    for (int sl = 0; sl < g.ksplit; ++sl) {
+      const double2 v = g.partial[((int64_t)sl * g.batch + b) * mn + e];
+      vr += v.x;
+      vi += v.y;
+    }
+    double2* Cp = g.C + batch_off(g.cb, b);
+    const int64_t off = map_idx(g.cr, gm) + map_idx(g.cc, gn);
+    double2 o;
+    o.x = g.alpha.x * vr - g.alpha.y * vi;
+    o.y = g.alpha.x * vi + g.alpha.y * vr;
+    if (use_beta) {
+      const double2 c = Cp[off];
+      o.x += g.beta.x * c.x - g.beta.y * c.y;
+      o.y += g.beta.x * c.y + g.beta.y * c.x;
+    }
+    Cp[off] = o;
+  }
 }
 
 }  // namespace
@@ -277,6 +332,10 @@ bool zgemm_in_bounds(const ZGemm& g, const Span& a, const Span& b, const Span& c
     std::snprintf(why, why_len, "empty or negative extent M=%d N=%d K=%d batch=%d", g.M, g.N, g.K, g.batch);
     return false;
   }
+  if (g.ksplit < 1) {
+    std::snprintf(why, why_len, "ksplit < 1");
+    return false;
+  }
   return check_operand("A", g.A.p, map_range(g.A.r, g.M), map_range(g.A.c, g.K), ba, a, why, why_len) &&
          check_operand("B", g.B.p, map_range(g.B.r, g.K), map_range(g.B.c, g.N), bb, b, why, why_len) &&
          check_operand("C", g.C, map_range(g.cr, g.M), map_range(g.cc, g.N), bc, c, why, why_len);
@@ -286,15 +345,41 @@ hipError_t zgemm(const ZGemm& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
   if (g.K <= 0) return hipErrorInvalidValue;
   if (dryrun()) return hipSuccess;
-  const bool small = g.M <= 32 && g.N <= 32;
-  if (small) {
-    const int64_t tiles = (int64_t)((g.M + 31) / 32) * ((g.N + 31) / 32);
-    const int64_t blocks = tiles * g.batch;
-    zgemm_f64_kernel<1, 1><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(g);
-  } else {
-    const int64_t tiles = (int64_t)((g.M + 63) / 64) * ((g.N + 63) / 64);
-    const int64_t blocks = tiles * g.batch;
-    zgemm_f64_kernel<2, 2><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(g);
+  if (g.ksplit < 1) return hipErrorInvalidValue;
+  if (g.ksplit > 1 && !g.partial) return hipErrorInvalidValue;
+  // tile shape: 32 x 32, 64 x 32, 32 x 64 or 64 x 64 (a dimension <= 32 gets a 32-wide tile)
+  const int wm = g.M <= 32 ? 1 : 2, wn = g.N <= 32 ? 1 : 2;
+  const int bm = 32 * wm, bn = 32 * wn;
+  const int64_t tiles = (int64_t)((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn);
+  const dim3 grid((unsigned)(tiles * g.batch * g.ksplit)), block(256);
+  const int shape = (wm - 1) * 2 + (wn - 1);
+#define GREEN_SITE(S)                                                     \
+  case Site::S:                                                          \
+    switch (shape) {                                                     \
+      case 0: zgemm_f64_kernel<1, 1, Site::S><<<grid, block, 0, s>>>(g); break; \
+      case 1: zgemm_f64_kernel<1, 2, Site::S><<<grid, block, 0, s>>>(g); break; \
+      case 2: zgemm_f64_kernel<2, 1, Site::S><<<grid, block, 0, s>>>(g); break; \
+      default: zgemm_f64_kernel<2, 2, Site::S><<<grid, block, 0, s>>>(g); break; \
+    }                                                                    \
+    break;
+  switch (g.site) {
+    GREEN_SITE(P0_VG)
+    GREEN_SITE(P0_VGrev)
+    GREEN_SITE(P0_Contract)
+    GREEN_SITE(Sig_PV)
+    GREEN_SITE(Sig_XG)
+    GREEN_SITE(Sig_YV)
+    GREEN_SITE(HF)
+    GREEN_SITE(Transform)
+    default:
+      GREEN_SITE(Generic)
+  }
+#undef GREEN_SITE
+  if (g.ksplit > 1) {
+    const int64_t total = (int64_t)g.M * g.N * g.batch;
+    int64_t nb = (total + 255) / 256;
+    if (nb > 65536) nb = 65536;
+    zgemm_splitk_reduce<<<dim3((unsigned)nb), dim3(256), 0, s>>>(g);
   }
   return hipGetLastError();
 }
