@@ -27,7 +27,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "GW Sigma-eval TFLOP/s + s/iteration, mixed vs FP64 on 1 GPU at <=1e-6 Eh"
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}  # MI355X dense matrix-core peaks
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}  # MI355X dense matrix-core peaks per dtype
 
 
 def contraction_flops(nk, nao, naux, ntau, nspin) -> float:
@@ -72,13 +72,82 @@ def cpu_baseline(system, target_s: float):
             "seconds": dt}
 
 
+def run_precision(system, prec, steps, warmup):
+    """Time `steps` iterations (after `warmup`) at one contraction precision; returns a summary dict."""
+    import numpy as np
+    import torch
+
+    from paper_2406_18479_amd.gw import Plan
+
+    spec = system.spec
+    plan = Plan(spec.kmesh, spec.nao, spec.naux, system.grid, nspin=spec.nspin, prec=prec)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")  # noqa: E731
+    V, H0, S = dev(system.V), dev(system.H0), dev(system.S)
+
+    def fresh():
+        return (dev(system.G0), torch.zeros(plan.shape_H, dtype=torch.complex128, device="cuda:0"),
+                torch.zeros(plan.shape_G, dtype=torch.complex128, device="cuda:0"))
+
+    # accuracy reference point: one iteration from the common starting G
+    G, Sinf, Sig = fresh()
+    _, rep0 = plan.iterate(V, H0, S, G, Sinf, Sig, 0.0, system.n_target, 1.0)
+    first = {"sigma": Sig.cpu().numpy(), "e_tot": rep0["e_tot"]}
+    # timed run
+    G, Sinf, Sig = fresh()
+    mu = 0.0
+    for _ in range(warmup):
+        mu, _ = plan.iterate(V, H0, S, G, Sinf, Sig, mu, system.n_target, 1.0)
+    torch.cuda.synchronize()
+    reps = []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        mu, rep = plan.iterate(V, H0, S, G, Sinf, Sig, mu, system.n_target, 1.0)
+        reps.append(rep)
+        print(f"[bench] {prec} step {i}: {rep['ms'][7]:.1f} ms  E_tot={rep['e_tot']:.10f}", file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    plan.close()
+    del plan, V, H0, S, G, Sinf, Sig
+    torch.cuda.empty_cache()
+
+    flops = contraction_flops(spec.nk, spec.nao, spec.naux, spec.ntau, spec.nspin)
+    sig_eval_s = sum((r["ms"][1] + r["ms"][2] + r["ms"][3]) for r in reps) / 1e3
+    kern = []
+    for slot in range(2):
+        ms = sum(r["kern_ms"][slot] for r in reps)
+        fl = sum(r["kern_flops"][slot] for r in reps)
+        n = sum(r["kern_launches"][slot] for r in reps)
+        kern.append(dict(ms=ms, flops=fl, launches=n, tflops=fl / (ms / 1e3) / 1e12 if ms > 0 else 0.0))
+    return {
+        "prec": prec,
+        "sigma_eval_tflops": flops * steps / sig_eval_s / 1e12,
+        "s_per_iteration": wall / steps,
+        "sigma_eval_s_per_iteration": sig_eval_s / steps,
+        "stage_ms": {k: round(sum(r["ms"][i] for r in reps) / steps, 3) for i, k in
+                     enumerate(["hf", "polarization", "screen", "selfenergy", "mix", "dyson_mu", "energy",
+                                "total"])},
+        "kern": kern,
+        "last": reps[-1],
+        "first": first,
+    }
+
+
+KERNEL_NAME = {"fp64": "zgemm_f64_kernel<2,2,Site::P0_Contract>",
+               "fp32": "zgemm_mx_kernel<1,2,2,Site::P0_Contract>",
+               "bf16x3": "zgemm_mx_kernel<2,2,2,Site::P0_Contract>"}
+# hardware MFMA products issued per algorithmic (4M) flop
+MFMA_PER_ALG = {"fp64": 1.0, "fp32": 1.0, "bf16x3": 3.0}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="periodic2", choices=sorted(workloads()))
-    ap.add_argument("--prec", default="fp64", choices=["fp64"])
+    ap.add_argument("--precisions", default="fp64,fp32,bf16x3",
+                    help="comma list; fp64 is always run first as the accuracy reference")
     ap.add_argument("--cpu-baseline-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -89,72 +158,59 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
 
-    from paper_2406_18479_amd.gw import Plan
     from synth import systems
 
     spec = workloads()[args.workload]
     system = systems.make_system(spec)
-    plan = Plan(spec.kmesh, spec.nao, spec.naux, system.grid, nspin=spec.nspin, prec=args.prec)
-    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")  # noqa: E731
-    V, H0, S = dev(system.V), dev(system.H0), dev(system.S)
-    G = dev(system.G0)
-    Sinf = torch.zeros(plan.shape_H, dtype=torch.complex128, device="cuda:0")
-    Sig = torch.zeros(plan.shape_G, dtype=torch.complex128, device="cuda:0")
-    mu = 0.0
-    for _ in range(args.warmup):
-        mu, _ = plan.iterate(V, H0, S, G, Sinf, Sig, mu, system.n_target, 1.0)
-    torch.cuda.synchronize()
-    reps = []
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        mu, rep = plan.iterate(V, H0, S, G, Sinf, Sig, mu, system.n_target, 1.0)
-        reps.append(rep)
-        print(f"[bench] step {i}: {rep['ms'][7]:.1f} ms  E_tot={rep['e_tot']:.10f}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-
-    flops = contraction_flops(spec.nk, spec.nao, spec.naux, spec.ntau, spec.nspin)
-    sig_eval_s = sum((r["ms"][1] + r["ms"][2] + r["ms"][3]) for r in reps) / 1e3
-    value = flops * args.steps / sig_eval_s / 1e12
-    # dominant kernel: the P~0 stage-2 contraction (event-timed launches inside the iterations)
-    k_ms = sum(r["kern_ms"][0] for r in reps)
-    k_fl = sum(r["kern_flops"][0] for r in reps)
-    k_n = sum(r["kern_launches"][0] for r in reps)
-    achieved = k_fl / (k_ms / 1e3) / 1e12 if k_ms > 0 else 0.0
-    peak = PEAK_TFLOPS[args.prec]
-    s2_ms = sum(r["kern_ms"][1] for r in reps)
-    s2_fl = sum(r["kern_flops"][1] for r in reps)
+    precs = ["fp64"] + [p for p in args.precisions.split(",") if p and p != "fp64"]
+    res = {p: run_precision(system, p, args.steps, args.warmup) for p in precs}
+    ref = res["fp64"]["first"]
+    for p, r in res.items():
+        r["d_energy"] = abs(r["first"]["e_tot"] - ref["e_tot"])
+        r["max_dsigma_vs_fp64"] = float(np.max(np.abs(r["first"]["sigma"] - ref["sigma"])))
+        r["meets_bar"] = r["d_energy"] <= 1e-6 and r["max_dsigma_vs_fp64"] <= 1e-5
+    # headline: the fastest precision that meets the accuracy bar (fp64 always does)
+    head = min((p for p in precs if res[p]["meets_bar"]), key=lambda p: res[p]["s_per_iteration"])
+    h = res[head]
+    k = h["kern"][0]
+    peak = PEAK_TFLOPS[head]
+    achieved = k["tflops"]
     out = {
         "metric": METRIC,
-        "value": round(value, 4),
+        "value": round(h["sigma_eval_tflops"], 4),
         "unit": "TFLOP/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "ms_per_step": round(h["s_per_iteration"] * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[head],
         "data": "synthetic",
         "config": {"workload": spec.name, "nk": spec.nk, "kmesh": list(spec.kmesh), "nao": spec.nao,
                    "naux": spec.naux, "ntau": spec.ntau, "nspin": spec.nspin, "beta": spec.beta,
-                   "precision": args.prec},
-        "s_per_iteration": round(wall / args.steps, 6),
-        "sigma_eval_s_per_iteration": round(sig_eval_s / args.steps, 6),
-        "stage_ms": {k: round(sum(r["ms"][i] for r in reps) / args.steps, 3) for i, k in
-                     enumerate(["hf", "polarization", "screen", "selfenergy", "mix", "dyson_mu", "energy",
-                                "total"])},
-        "sigma_contraction_tflops": round(s2_fl / (s2_ms / 1e3) / 1e12, 4) if s2_ms > 0 else None,
-        "energy": {"e_tot": reps[-1]["e_tot"], "e_corr": reps[-1]["e_corr"], "mu": reps[-1]["mu"],
-                   "n_elec": reps[-1]["n_elec"], "max_dsigma": reps[-1]["max_dsigma"]},
-        "roofline": {"bound": "mfma", "kernel": "zgemm_f64_kernel<2,2,Site::P0_Contract>",
-                     "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": None,
-                     "launches": k_n, "avg_launch_ms": round(k_ms / max(k_n, 1), 4),
-                     "flops_per_launch": k_fl / max(k_n, 1)},
+                   "precision": head},
+        "s_per_iteration": round(h["s_per_iteration"], 6),
+        "fp64_s_per_iteration": round(res["fp64"]["s_per_iteration"], 6),
+        "speedup_vs_fp64": round(res["fp64"]["s_per_iteration"] / h["s_per_iteration"], 3),
+        "precisions": {p: {"sigma_eval_tflops": round(r["sigma_eval_tflops"], 4),
+                           "s_per_iteration": round(r["s_per_iteration"], 6),
+                           "d_energy_eh": r["d_energy"], "max_dsigma_vs_fp64_eh": r["max_dsigma_vs_fp64"],
+                           "meets_bar": r["meets_bar"], "stage_ms": r["stage_ms"],
+                           "p0_contraction_tflops": round(r["kern"][0]["tflops"], 4),
+                           "sigma_contraction_tflops": round(r["kern"][1]["tflops"], 4),
+                           "p0_contraction_mfma_frac": round(r["kern"][0]["tflops"] * MFMA_PER_ALG[p]
+                                                             / PEAK_TFLOPS[p], 4)}
+                       for p, r in res.items()},
+        "energy": {"e_tot": h["last"]["e_tot"], "e_corr": h["last"]["e_corr"], "mu": h["last"]["mu"],
+                   "n_elec": h["last"]["n_elec"], "max_dsigma": h["last"]["max_dsigma"]},
+        "roofline": {"bound": "mfma", "kernel": KERNEL_NAME[head], "achieved": round(achieved, 4), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                     "mfma_frac": round(achieved * MFMA_PER_ALG[head] / peak, 4), "traffic": None,
+                     "launches": k["launches"], "avg_launch_ms": round(k["ms"] / max(k["launches"], 1), 4),
+                     "flops_per_launch": k["flops"] / max(k["launches"], 1)},
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:

@@ -35,7 +35,7 @@ struct green_plan {
   std::vector<int32_t> kadd, ksub, kneg;  // [q][k]: k+q, k-q; [q]: -q
   // workspace regions
   Region r_TF_t2w, r_TF_w2t, r_TB_t2w, r_TB_w2t, r_Emass, r_wf, r_kadd, r_ksub, r_status, r_scal, r_partial;
-  Region r_P, r_Pw, r_T1, r_T2, r_gam, r_gamT, r_D, r_Sinfn, r_Sign, r_Sw, r_A, r_tr, r_split;
+  Region r_P, r_Pw, r_T1, r_T2, r_gam, r_gamT, r_D, r_Sinfn, r_Sign, r_Sw, r_A, r_tr, r_split, r_Vx;
   size_t ws_bytes = 0;
   void* bound_ws = nullptr;
   hipEvent_t ev[kNumEvents]{};
@@ -119,16 +119,19 @@ int kflat(const int32_t* m, int a, int b, int c) {
   return (a * m[1] + b) * m[2] + c;
 }
 
-// Split-K scratch of the current call (a workspace region), set by every entry point.
+// Split-K scratch (a workspace region) and contraction precision of the current call, set by every
+// entry point.
 struct SplitBuf {
   double2* ptr = nullptr;
   int64_t cap = 0;  // complex elements
+  int prec = 0;     // arithmetic of the P~0 stage-2 and Sigma~ stage-1 contractions
 };
 thread_local SplitBuf tl_split;
 
 int ensure_bound(green_plan* p, void* ws, hipStream_t s) {
   tl_split.ptr = reinterpret_cast<double2*>(static_cast<char*>(ws) + p->r_split.off);
   tl_split.cap = (int64_t)(p->r_split.bytes / sizeof(double2));
+  tl_split.prec = p->prec;
   if (p->bound_ws == ws) return GREEN_OK;
   if (green::dryrun()) return GREEN_OK;
   auto up = [&](const Region& r, const void* src) {
@@ -205,19 +208,20 @@ int choose_ksplit(int M, int N, int K, int batch) {
   return std::max(ks, 1);
 }
 
-ZOp op(const void* ptr, IdxMap r, IdxMap c, BatchMap b, int conj = 0) {
+ZOp op(const void* ptr, IdxMap r, IdxMap c, BatchMap b, int etype = green::kC64, int conj = 0) {
   ZOp o;
   o.p = static_cast<const double2*>(ptr);
   o.r = r;
   o.c = c;
   o.b = b;
   o.conj = conj;
+  o.etype = etype;
   return o;
 }
 
 int gemm(green::Site site, const char* label, const ZOp& A, const green::Span& sa, const ZOp& B, const green::Span& sb, void* C,
          const green::Span& sc, IdxMap cr, IdxMap cc, BatchMap cb, int M, int N, int K, int batch, double2 alpha,
-         double2 beta, hipStream_t s) {
+         double2 beta, hipStream_t s, int prec = 0, int ctype = green::kC64) {
   ZGemm g;
   g.site = site;
   g.M = M;
@@ -233,6 +237,8 @@ int gemm(green::Site site, const char* label, const ZOp& A, const green::Span& s
   g.alpha = alpha;
   g.beta = beta;
   g.ksplit = choose_ksplit(M, N, K, batch);
+  g.prec = prec;
+  g.ctype = ctype;
   g.partial = g.ksplit > 1 ? tl_split.ptr : nullptr;
   char why[256];
   if (g.ksplit > 1 && (int64_t)g.ksplit * batch * M * N > tl_split.cap) return GREEN_EINVAL;
@@ -251,10 +257,13 @@ int gemm(green::Site site, const char* label, const ZOp& A, const green::Span& s
   return hip_status(green::zgemm(g, s));
 }
 
-green::Span span(const void* base, int64_t count) { return green::Span{base, count}; }
+// extents in bytes: caller tensors are complex FP64 (count elements), workspace regions are raw bytes
+green::Span span(const void* base, int64_t count) { return green::Span{base, count * (int64_t)sizeof(double2)}; }
 green::Span span_ws(void* ws, const Region& r) {
-  return green::Span{static_cast<char*>(ws) + r.off, (int64_t)(r.bytes / sizeof(double2))};
+  return green::Span{static_cast<char*>(ws) + r.off, (int64_t)r.bytes};
 }
+// element type of the contraction intermediates for a plan precision
+int inter_type(int prec) { return prec == GREEN_FP64 ? green::kC64 : (prec == GREEN_FP32 ? green::kC32 : green::kCB16); }
 
 using green::bflat;
 using green::bnone;
@@ -295,30 +304,36 @@ int run_polarization(green_plan* p, const void* V, const void* G, void* P0, void
   const double2* Gp = static_cast<const double2*>(G);
   double2* Pp = static_cast<double2*>(P0);
   const double w = ns == 1 ? 2.0 : 1.0;
+  // mixed plans: stage 1 in FP32 writing the stage-2 operands in the contraction's storage type
+  const int stage1 = p->prec == GREEN_FP64 ? 0 : 1;
+  const int tt = inter_type(p->prec);
   for (int q = 0; q < nk; ++q) {
     const int qn = p->kneg[q];
     for (int t0 = 0; t0 < ntau; t0 += p->tc) {
       const int tcn = std::min(p->tc, ntau - t0);
       for (int sp = 0; sp < ns; ++sp) {
-        // T1[tt][k][(Q,d)][b] = sum_a V^{k,k+q}_{da}(Q) G^{k+q}_{ab}(tau)
-        GREEN_TRY(gemm(green::Site::P0_VG, "P0.VG", op(Vp + q * slab, flat(nao), flat(1), btwo(nk, nV, nullptr, 0)), sV,
-                       op(Gp + ((int64_t)sp * ntau + t0) * nk * nG, flat(nao), flat(1),
-                          btwo(nk, nG, kadd + q * nk, (int64_t)nk * nG, hadd + q * nk)),
-                       sG, T1, sT1, flat(nao), flat(1), bflat(nV), naux * nao, nao, nao, tcn * nk, cplx(1),
-                       cplx(0), s));
-        // T2[tt][k][Q'][d][b] = sum_c V^{k+q,k}_{bc}(Q') G^k_{cd}(beta - tau)   (stored transposed in (b, d))
-        GREEN_TRY(gemm(green::Site::P0_VGrev, "P0.VGrev", op(Vp + qn * slab, flat(nao), flat(1), btwo(nk, nV, kadd + q * nk, 0, hadd + q * nk)),
-                       sV,
-                       op(Gp + ((int64_t)sp * ntau + (ntau - 1 - t0)) * nk * nG, flat(nao), flat(1),
-                          btwo(nk, nG, nullptr, -(int64_t)nk * nG)),
-                       sG, T2, sT2, two(nao, 1, nG), flat(nao), bflat(nV), naux * nao, nao, nao, tcn * nk,
-                       cplx(1), cplx(0), s));
+        // T1[tt][k][(Q,d)][b] = sum_a V^{k,k+q}_{da}(Q) G^{k+q}_{ab}(tau_tt): one GEMM per k with the tau
+        // nodes of the chunk folded into N = (tt, b), so each V block is read once per chunk
+        GREEN_TRY(gemm(green::Site::P0_VG, "P0.VG", op(Vp + q * slab, flat(nao), flat(1), bflat(nV)), sV,
+                       op(Gp + ((int64_t)sp * ntau + t0) * nk * nG, flat(nao), two(nao, 1, (int64_t)nk * nG),
+                          btwo(nk, nG, kadd + q * nk, 0, hadd + q * nk)),
+                       sG, T1, sT1, flat(nao), two(nao, 1, (int64_t)nk * nV), bflat(nV), naux * nao, tcn * nao, nao,
+                       nk, cplx(1), cplx(0), s, stage1, tt));
+        // T2[tt][k][Q'][d][b] = sum_c V^{k+q,k}_{bc}(Q') G^k_{cd}(beta - tau_tt)   (stored transposed in (b, d));
+        // N = (tt, d), G(beta - tau) walks the grid backwards
+        GREEN_TRY(gemm(green::Site::P0_VGrev, "P0.VGrev",
+                       op(Vp + qn * slab, flat(nao), flat(1), btwo(nk, nV, kadd + q * nk, 0, hadd + q * nk)), sV,
+                       op(Gp + ((int64_t)sp * ntau + (ntau - 1 - t0)) * nk * nG, flat(nao),
+                          two(nao, 1, -(int64_t)nk * nG), btwo(nk, nG, nullptr, 0)),
+                       sG, T2, sT2, two(nao, 1, nG), two(nao, nao, (int64_t)nk * nV), bflat(nV), naux * nao,
+                       tcn * nao, nao, nk, cplx(1), cplx(0), s, stage1, tt));
         // P0[q][t][Q][Q'] (+)= -(w/nk) sum_{k,(d,b)} T1[tt][k][Q][(d,b)] T2[tt][k][Q'][(d,b)]
-        GREEN_TRY(gemm(green::Site::P0_Contract, "P0.contract", op(T1, flat(nG), two((int32_t)nG, 1, nV), bflat((int64_t)nk * nV)), sT1,
-                       op(T2, two((int32_t)nG, 1, nV), flat(nG), bflat((int64_t)nk * nV)), sT2,
+        GREEN_TRY(gemm(green::Site::P0_Contract, "P0.contract",
+                       op(T1, flat(nG), two((int32_t)nG, 1, nV), bflat((int64_t)nk * nV), tt), sT1,
+                       op(T2, two((int32_t)nG, 1, nV), flat(nG), bflat((int64_t)nk * nV), tt), sT2,
                        Pp + ((int64_t)q * ntau + t0) * naux * naux, sP, flat(naux), flat(1),
                        bflat((int64_t)naux * naux), naux, naux, (int)(nk * nG), tcn, cplx(-w / nk),
-                       cplx(sp == 0 ? 0.0 : 1.0), s));
+                       cplx(sp == 0 ? 0.0 : 1.0), s, p->prec, green::kC64));
       }
     }
   }
@@ -370,27 +385,42 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
   const double2* Pp = static_cast<const double2*>(Pt);
   double2* Sp = static_cast<double2*>(Sig);
   if (!green::dryrun()) HIP_TRY(green::launch_zero(Sp, ex.Sig, s));
+  const bool mixed = p->prec != GREEN_FP64;
+  const int vt = inter_type(p->prec);           // storage of the rounded V slab
+  const int xt = mixed ? green::kC32 : green::kC64;  // X and Y intermediates
+  const int stage = mixed ? 1 : 0;
+  void* Vx = at<void>(ws, p->r_Vx);
+  const green::Span sVx = span_ws(ws, p->r_Vx);
   for (int q = 0; q < nk; ++q) {
     const int qn = p->kneg[q];
+    if (mixed) {
+      if ((int64_t)p->r_Vx.bytes < slab * green::elem_bytes(vt)) return GREEN_EINVAL;
+      HIP_TRY(green::convert_c64(Vp + qn * slab, Vx, vt, slab, s));
+    }
     for (int t0 = 0; t0 < ntau; t0 += p->tc) {
       const int tcn = std::min(p->tc, ntau - t0);
       // X[tt][k][Q'][(i,a)] = sum_Q P~^q_{QQ'}(tau) V^{k,k-q}_{ia}(Q)
-      GREEN_TRY(gemm(green::Site::Sig_PV, "Sigma.PV", op(Pp + ((int64_t)q * ntau + t0) * nP, flat(1), flat(naux), bflat(nP)), sP,
-                     op(Vp + qn * slab, flat(nG), two((int32_t)nG, 1, nV), bnone()), sV, T1, sT1, flat(nG),
-                     two((int32_t)nG, 1, nV), bflat((int64_t)nk * nV), naux, (int)(nk * nG), naux, tcn, cplx(1),
-                     cplx(0), s));
+      GREEN_TRY(gemm(green::Site::Sig_PV, "Sigma.PV", op(Pp + ((int64_t)q * ntau + t0) * nP, flat(1), flat(naux), bflat(nP)),
+                     sP,
+                     mixed ? op(Vx, flat(nG), two((int32_t)nG, 1, nV), bnone(), vt)
+                           : op(Vp + qn * slab, flat(nG), two((int32_t)nG, 1, nV), bnone()),
+                     mixed ? sVx : sV, T1, sT1, flat(nG), two((int32_t)nG, 1, nV), bflat((int64_t)nk * nV), naux,
+                     (int)(nk * nG), naux, tcn, cplx(1), cplx(0), s, p->prec, xt));
       for (int sp = 0; sp < ns; ++sp) {
         // Y[tt][k][(Q',i)][b] = sum_a X[tt][k][(Q',i)][a] G^{k-q}_{ab}(tau)
-        GREEN_TRY(gemm(green::Site::Sig_XG, "Sigma.XG", op(T1, flat(nao), flat(1), bflat(nV)), sT1,
+        GREEN_TRY(gemm(green::Site::Sig_XG, "Sigma.XG", op(T1, flat(nao), flat(1), bflat(nV), xt), sT1,
                        op(Gp + ((int64_t)sp * ntau + t0) * nk * nG, flat(nao), flat(1),
                           btwo(nk, nG, ksub + q * nk, (int64_t)nk * nG, hsub + q * nk)),
                        sG, T2, sT2, flat(nao), flat(1), bflat(nV), naux * nao, nao, nao, tcn * nk, cplx(1), cplx(0),
-                       s));
-        // Sigma[s][t][k][i][j] += -(1/nk) sum_{(Q',b)} Y[tt][k][Q'][i][b] V^{k-q,k}_{bj}(Q')
-        GREEN_TRY(gemm(green::Site::Sig_YV, "Sigma.YV", op(T2, flat(nao), two(nao, 1, nG), bflat(nV)), sT2,
+                       s, stage, xt));
+        // Sigma[s][t][k][i][j] += -(1/nk) sum_{(Q',b)} Y[tt][k][Q'][i][b] V^{k-q,k}_{bj}(Q'): one GEMM per k
+        // with the tau nodes folded into M = (tt, i), so each V block is read once per chunk
+        GREEN_TRY(gemm(green::Site::Sig_YV, "Sigma.YV",
+                       op(T2, two(nao, nao, (int64_t)nk * nV), two(nao, 1, nG), bflat(nV), xt), sT2,
                        op(Vp + q * slab, two(nao, nao, nG), flat(1), btwo(nk, nV, ksub + q * nk, 0, hsub + q * nk)),
-                       sV, Sp + ((int64_t)sp * ntau + t0) * nk * nG, sS, flat(nao), flat(1), bflat(nG), nao, nao,
-                       naux * nao, tcn * nk, cplx(-1.0 / nk), cplx(1.0), s));
+                       sV, Sp + ((int64_t)sp * ntau + t0) * nk * nG, sS, two(nao, nao, (int64_t)nk * nG), flat(1),
+                       bflat(nG), tcn * nao, nao, naux * nao, nk, cplx(-1.0 / nk), cplx(1.0), s, stage,
+                       green::kC64));
       }
     }
   }
@@ -679,7 +709,7 @@ int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, 
   if (!(d.beta > 0.0) || !std::isfinite(d.beta)) return GREEN_EINVAL;
   if (!grid->tau || !grid->wf || !grid->wb || !grid->TF_t2w || !grid->TF_w2t || !grid->TB_t2w || !grid->TB_w2t)
     return GREEN_EINVAL;
-  if (prec != GREEN_FP64) return GREEN_EUNSUPPORTED;
+  if (prec != GREEN_FP64 && prec != GREEN_FP32 && prec != GREEN_BF16X3) return GREEN_EUNSUPPORTED;
   green_plan* p = new (std::nothrow) green_plan();
   if (!p) return GREEN_ENOMEM;
   p->d = d;
@@ -759,6 +789,7 @@ int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, 
   take(p->r_A, (size_t)ns * nwf * nk * nG * 16);
   take(p->r_tr, (size_t)std::max<int64_t>(ns * nwf * nk, ns * ntau * nk) * 16);
   take(p->r_split, (size_t)256 << 20);
+  take(p->r_Vx, prec == GREEN_FP64 ? 0 : (size_t)nk * nV * 8);
   p->ws_bytes = off;
   *out = p;
   return GREEN_OK;

@@ -34,12 +34,22 @@ static inline BatchMap btwo(int32_t ext_lo, int64_t s_lo, const int32_t* tab, in
   return BatchMap{ext_lo, s_lo, tab, s_hi, htab};
 }
 
-// Complex operand of a batched GEMM: element (r, c) of batch b at p[batch(b) + r_map(r) + c_map(c)].
+// Storage type of a complex element.
+enum ElemType : int32_t {
+  kC64 = 0,   // double2 (re, im)                                         16 bytes
+  kC32 = 1,   // float2 (re, im)                                           8 bytes
+  kCB16 = 2,  // uint2 {hi, lo}: bf16 pairs (re | im << 16), x = hi + lo   8 bytes
+};
+static inline int64_t elem_bytes(int32_t t) { return t == kC64 ? 16 : 8; }
+
+// Complex operand of a batched GEMM: element (r, c) of batch b at p[batch(b) + r_map(r) + c_map(c)]
+// (offsets in elements of type `etype`).
 struct ZOp {
   const double2* p;
   IdxMap r, c;
   BatchMap b;
   int32_t conj;
+  int32_t etype;
 };
 
 // Call sites of the batched GEMM.  Each site is its own kernel instantiation so that
@@ -72,15 +82,21 @@ struct ZGemm {
   double2 alpha, beta;
   int32_t ksplit;
   double2* partial;
+  int32_t prec;   // 0: FP64 MFMA, 1: FP32 MFMA, 2: split BF16 (hi + lo, three products) MFMA; prec 1 and 2
+                  // accumulate in FP32 within a K slice, slices are combined in FP64
+  int32_t ctype;  // ElemType of C (kCB16 requires beta == 0); prec 0 requires kC64 operands and output
 };
 
 hipError_t zgemm(const ZGemm& g, hipStream_t s);
 
-// Extent of a buffer in complex elements: every element an operand touches must lie in [base, base + count).
+// Extent of a buffer in bytes: every element an operand touches must lie in [base, base + bytes).
 struct Span {
   const void* base;
-  int64_t count;
+  int64_t bytes;
 };
+
+// Round a complex FP64 array to FP32 (kC32) or to split BF16 (kCB16), element for element.
+hipError_t convert_c64(const double2* in, void* out, int32_t etype, int64_t n, hipStream_t s);
 
 // Host-side bounds check of a GEMM descriptor against the buffers its operands point into (conservative:
 // the box spanned by the index maps).  Returns false and fills `why` when an access could leave a buffer.

@@ -40,6 +40,32 @@ __device__ __forceinline__ int64_t batch_off(const BatchMap& b, int32_t x) {
   return l * b.s_lo + (int64_t)hi * b.s_hi;
 }
 
+// Running position k -> (k % ext, k / ext) of one staged element; advanced by a fixed step without
+// divisions (the step never exceeds... any extent: the while loop handles ext < step).
+struct KPos {
+  int32_t k, lo, hi;
+  __device__ __forceinline__ void init(const IdxMap& m, int32_t k0) {
+    k = k0;
+    if (m.ext == kFlat) {
+      lo = k0;
+      hi = 0;
+    } else {
+      hi = k0 / m.ext;
+      lo = k0 - hi * m.ext;
+    }
+  }
+  __device__ __forceinline__ int64_t off(const IdxMap& m) const { return (int64_t)lo * m.s_in + (int64_t)hi * m.s_out; }
+  __device__ __forceinline__ void step(const IdxMap& m, int32_t d) {
+    k += d;
+    lo += d;
+    if (m.ext != kFlat)
+      while (lo >= m.ext) {
+        lo -= m.ext;
+        ++hi;
+      }
+  }
+};
+
 template <int WM, int WN, Site SITE>
 __global__ __launch_bounds__(256) void zgemm_f64_kernel(const ZGemm g) {
   constexpr int BM = 32 * WM, BN = 32 * WN, BK = 8;
@@ -107,22 +133,28 @@ __global__ __launch_bounds__(256) void zgemm_f64_kernel(const ZGemm g) {
   const double bsgn = g.B.conj ? -1.0 : 1.0;
 
   double2 ra[EA], rb[EB];
-  auto load = [&](int k0) {
+  KPos apos[EA], bpos[EB];
+#pragma unroll
+  for (int e = 0; e < EA; ++e) apos[e].init(g.A.c, kbeg + a_k[e]);
+#pragma unroll
+  for (int e = 0; e < EB; ++e) bpos[e].init(g.B.r, kbeg + b_k[e]);
+  // loads the next stage and advances the positions by BK
+  auto load = [&]() {
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
-      const int gk = k0 + a_k[e];
       double2 v = make_double2(0.0, 0.0);
-      if (a_ok[e] && gk < kend) v = Ap[a_ro[e] + map_idx(g.A.c, gk)];
+      if (a_ok[e] && apos[e].k < kend) v = Ap[a_ro[e] + apos[e].off(g.A.c)];
       v.y *= asgn;
       ra[e] = v;
+      apos[e].step(g.A.c, BK);
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
-      const int gk = k0 + b_k[e];
       double2 v = make_double2(0.0, 0.0);
-      if (b_ok[e] && gk < kend) v = Bp[map_idx(g.B.r, gk) + b_co[e]];
+      if (b_ok[e] && bpos[e].k < kend) v = Bp[bpos[e].off(g.B.r) + b_co[e]];
       v.y *= bsgn;
       rb[e] = v;
+      bpos[e].step(g.B.r, BK);
     }
   };
   auto stage = [&](int buf) {
@@ -144,12 +176,12 @@ __global__ __launch_bounds__(256) void zgemm_f64_kernel(const ZGemm g) {
   const int wr = wave & 1, wc = wave >> 1;
   const int rowb = wr * 16 * WM, colb = wc * 16 * WN;
   const int nkt = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
-  load(kbeg);
+  load();
   stage(0);
   __syncthreads();
   for (int it = 0; it < nkt; ++it) {
     const int buf = it & 1;
-    if (it + 1 < nkt) load(kbeg + (it + 1) * BK);
+    if (it + 1 < nkt) load();
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       const int kr = 4 * s + (lane >> 4);
@@ -196,16 +228,24 @@ __global__ __launch_bounds__(256) void zgemm_f64_kernel(const ZGemm g) {
   }
   double2* __restrict__ Cp = g.C + batch_off(g.cb, batch);
   const bool use_beta = g.beta.x != 0.0 || g.beta.y != 0.0;
+  int64_t coff[WN];
+#pragma unroll
+  for (int j = 0; j < WN; ++j) {
+    const int gn = n0 + colb + 16 * j + (lane & 15);
+    coff[j] = gn < g.N ? map_idx(g.cc, gn) : 0;
+  }
 #pragma unroll
   for (int i = 0; i < WM; ++i)
 #pragma unroll
-    for (int j = 0; j < WN; ++j)
+    for (int r = 0; r < 4; ++r) {
+      const int gm = m0 + rowb + 16 * i + (lane >> 4) + 4 * r;
+      if (gm >= g.M) continue;
+      const int64_t roff = map_idx(g.cr, gm);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int gm = m0 + rowb + 16 * i + (lane >> 4) + 4 * r;
+      for (int j = 0; j < WN; ++j) {
         const int gn = n0 + colb + 16 * j + (lane & 15);
-        if (gm < g.M && gn < g.N) {
-          const int64_t off = map_idx(g.cr, gm) + map_idx(g.cc, gn);
+        if (gn < g.N) {
+          const int64_t off = roff + coff[j];
           const double vr = acc_re[i][j][r], vi = acc_im[i][j][r];
           double2 o;
           o.x = g.alpha.x * vr - g.alpha.y * vi;
@@ -218,13 +258,337 @@ __global__ __launch_bounds__(256) void zgemm_f64_kernel(const ZGemm g) {
           Cp[off] = o;
         }
       }
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Mixed-precision variant: the same operands (complex FP64 in memory) are rounded while staging to
+// LDS, either to FP32 (MODE 1, v_mfma_f32_16x16x4f32) or to a BF16 pair hi + lo with
+// hi = bf16(x), lo = bf16(x - hi) (MODE 2, v_mfma_f32_16x16x32_bf16, products hi*hi + hi*lo + lo*hi).
+// Complex numbers are laid out as (re, im) pairs along K, so one real MFMA chain gives
+//   C_re = sum_k (re_a re_b - im_a im_b)   from A' = (re, -im) and B = (re, im),
+//   C_im = sum_k (re_a im_b + im_a re_b)   from A  = (re,  im) and B' = (im, re).
+// Accumulation is FP32 within a K slice (the split-K slices are combined in FP64).  For split BF16 the
+// per-product rounding (about 2^-17 relative) is two orders above FP32 accumulation error.
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+  const __bf16 h = (__bf16)x;
+  return (uint32_t)__builtin_bit_cast(unsigned short, h);
+}
+__device__ __forceinline__ float bf16_value(uint32_t b) {
+  return __builtin_bit_cast(float, b << 16);
+}
+// (hi, lo) words of a complex value: low half = re, high half = im
+__device__ __forceinline__ void split_pair(double re, double im, uint32_t& hi, uint32_t& lo) {
+  const uint32_t hr = bf16_bits((float)re), hm = bf16_bits((float)im);
+  const uint32_t lr = bf16_bits((float)(re - (double)bf16_value(hr)));
+  const uint32_t lm = bf16_bits((float)(im - (double)bf16_value(hm)));
+  hi = hr | (hm << 16);
+  lo = lr | (lm << 16);
+}
+__device__ __forceinline__ u4 neg_im(u4 v) { return v ^ u4{0x80000000u, 0x80000000u, 0x80000000u, 0x80000000u}; }
+__device__ __forceinline__ u4 swap_re_im(u4 v) {
+  return u4{(v.x >> 16) | (v.x << 16), (v.y >> 16) | (v.y << 16), (v.z >> 16) | (v.z << 16),
+            (v.w >> 16) | (v.w << 16)};
+}
+__device__ __forceinline__ bf8 as_bf8(u4 v) { return __builtin_bit_cast(bf8, v); }
+__device__ __forceinline__ int64_t elem_bytes_dev(int t) { return t == kC64 ? 16 : 8; }
+__device__ __forceinline__ void split_pair_f(float re, float im, uint32_t& hi, uint32_t& lo) {
+  const uint32_t hr = bf16_bits(re), hm = bf16_bits(im);
+  hi = hr | (hm << 16);
+  lo = bf16_bits(re - bf16_value(hr)) | (bf16_bits(im - bf16_value(hm)) << 16);
+}
+// C element store by the descriptor's ctype: v is the raw sum, alpha/beta applied here
+__device__ __forceinline__ void store_c(const ZGemm& g, int64_t off, double2 v) {
+  double2 o;
+  o.x = g.alpha.x * v.x - g.alpha.y * v.y;
+  o.y = g.alpha.x * v.y + g.alpha.y * v.x;
+  const bool use_beta = g.beta.x != 0.0 || g.beta.y != 0.0;
+  if (g.ctype == kC64) {
+    double2* C = g.C + off;
+    if (use_beta) {
+      const double2 c = *C;
+      o.x += g.beta.x * c.x - g.beta.y * c.y;
+      o.y += g.beta.x * c.y + g.beta.y * c.x;
+    }
+    *C = o;
+  } else if (g.ctype == kC32) {
+    float2* C = reinterpret_cast<float2*>(g.C) + off;
+    if (use_beta) {
+      const float2 c = *C;
+      o.x += g.beta.x * c.x - g.beta.y * c.y;
+      o.y += g.beta.x * c.y + g.beta.y * c.x;
+    }
+    *C = make_float2((float)o.x, (float)o.y);
+  } else {
+    uint2 w;
+    split_pair(o.x, o.y, w.x, w.y);
+    reinterpret_cast<uint2*>(g.C)[off] = w;
+  }
+}
+
+template <int MODE, int WM, int WN, Site SITE>
+__global__ __launch_bounds__(256) void zgemm_mx_kernel(const ZGemm g) {
+  constexpr int BM = 32 * WM, BN = 32 * WN, BK = 16;  // BK complex K per stage
+  constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
+  // LDS rows hold K contiguously, padded to spread banks
+  constexpr int PW = MODE == 2 ? BK + 4 : 2 * BK + 4;  // row length in 32-bit words
+  constexpr int APLANE = BM * PW, BPLANE = BN * PW;
+  constexpr int NPL = MODE == 2 ? 2 : 1;  // planes per operand (hi, lo)
+  __shared__ uint32_t As[2][NPL][APLANE];
+  __shared__ uint32_t Bs[2][NPL][BPLANE];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int tiles_m = (g.M + BM - 1) / BM;
+  const int tiles_n = (g.N + BN - 1) / BN;
+  const int64_t per_batch = (int64_t)tiles_m * tiles_n;
+  const int64_t group = blockIdx.x / per_batch;
+  const int32_t tile = (int32_t)(blockIdx.x - group * per_batch);
+  const int32_t batch = (int32_t)(group / g.ksplit);
+  const int32_t slice = (int32_t)(group - (int64_t)batch * g.ksplit);
+  const int tm = tile % tiles_m;
+  const int tn = tile / tiles_m;
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int kchunk = ((g.K + g.ksplit - 1) / g.ksplit + BK - 1) / BK * BK;
+  const int kbeg = slice * kchunk;
+  const int kend = min(g.K, kbeg + kchunk);
+
+  const bool a_kc = g.A.c.s_in == 1 && g.A.c.ext >= BK;
+  const bool b_kc = !(g.B.c.s_in == 1 && g.B.c.ext >= 16) && g.B.r.s_in == 1;
+  int a_m[EA], a_k[EA];
+  int64_t a_ro[EA];
+  bool a_ok[EA];
+#pragma unroll
+  for (int e = 0; e < EA; ++e) {
+    if (a_kc) {
+      a_k[e] = tid & (BK - 1);
+      a_m[e] = (tid >> 4) + 16 * e;
+    } else {
+      a_m[e] = tid % BM;
+      a_k[e] = tid / BM + (256 / BM) * e;
+    }
+    const int gm = m0 + a_m[e];
+    a_ok[e] = gm < g.M;
+    a_ro[e] = a_ok[e] ? map_idx(g.A.r, gm) : 0;
+  }
+  int b_n[EB], b_k[EB];
+  int64_t b_co[EB];
+  bool b_ok[EB];
+#pragma unroll
+  for (int e = 0; e < EB; ++e) {
+    if (b_kc) {
+      b_k[e] = tid & (BK - 1);
+      b_n[e] = (tid >> 4) + 16 * e;
+    } else {
+      b_n[e] = tid % BN;
+      b_k[e] = tid / BN + (256 / BN) * e;
+    }
+    const int gn = n0 + b_n[e];
+    b_ok[e] = gn < g.N;
+    b_co[e] = b_ok[e] ? map_idx(g.B.c, gn) : 0;
+  }
+  // raw element registers: a complex FP64 value, or the 8 bytes of a kC32 / kCB16 element in .x
+  double2 ra[EA], rb[EB];
+  const int ta = g.A.etype, tb = g.B.etype;
+  auto fetch = [&](const char* base, int t, int64_t off) -> double2 {
+    if (t == kC64) return reinterpret_cast<const double2*>(base)[off];
+    const uint2 w = reinterpret_cast<const uint2*>(base)[off];
+    return make_double2(__builtin_bit_cast(double, w), 0.0);
+  };
+  const char* Ab = reinterpret_cast<const char*>(g.A.p) + batch_off(g.A.b, batch) * elem_bytes_dev(ta);
+  const char* Bb = reinterpret_cast<const char*>(g.B.p) + batch_off(g.B.b, batch) * elem_bytes_dev(tb);
+  KPos apos[EA], bpos[EB];
+#pragma unroll
+  for (int e = 0; e < EA; ++e) apos[e].init(g.A.c, kbeg + a_k[e]);
+#pragma unroll
+  for (int e = 0; e < EB; ++e) bpos[e].init(g.B.r, kbeg + b_k[e]);
+  auto load = [&]() {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      ra[e] = (a_ok[e] && apos[e].k < kend) ? fetch(Ab, ta, a_ro[e] + apos[e].off(g.A.c)) : make_double2(0.0, 0.0);
+      apos[e].step(g.A.c, BK);
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      rb[e] = (b_ok[e] && bpos[e].k < kend) ? fetch(Bb, tb, bpos[e].off(g.B.r) + b_co[e]) : make_double2(0.0, 0.0);
+      bpos[e].step(g.B.r, BK);
+    }
+  };
+  // raw element -> LDS words (conjugation applied here)
+  auto put = [&](uint32_t* plane0, uint32_t* plane1, int idx, int t, double2 v, bool conj) {
+    if (MODE == 2) {
+      uint32_t hi, lo;
+      if (t == kC64) {
+        split_pair(v.x, conj ? -v.y : v.y, hi, lo);
+      } else if (t == kC32) {
+        const float2 f = __builtin_bit_cast(float2, v.x);
+        split_pair_f(f.x, conj ? -f.y : f.y, hi, lo);
+      } else {
+        const uint2 w = __builtin_bit_cast(uint2, v.x);
+        hi = conj ? (w.x ^ 0x80000000u) : w.x;
+        lo = conj ? (w.y ^ 0x80000000u) : w.y;
+      }
+      plane0[idx] = hi;
+      plane1[idx] = lo;
+    } else {
+      float re, im;
+      if (t == kC64) {
+        re = (float)v.x;
+        im = (float)v.y;
+      } else if (t == kC32) {
+        const float2 f = __builtin_bit_cast(float2, v.x);
+        re = f.x;
+        im = f.y;
+      } else {
+        const uint2 w = __builtin_bit_cast(uint2, v.x);
+        re = bf16_value(w.x & 0xffffu) + bf16_value(w.y & 0xffffu);
+        im = bf16_value(w.x >> 16) + bf16_value(w.y >> 16);
+      }
+      plane0[2 * idx] = __builtin_bit_cast(uint32_t, re);
+      plane0[2 * idx + 1] = __builtin_bit_cast(uint32_t, conj ? -im : im);
+    }
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int idx = MODE == 2 ? a_m[e] * PW + a_k[e] : (a_m[e] * PW) / 2 + a_k[e];
+      put(As[buf][0], As[buf][NPL - 1], idx, ta, ra[e], g.A.conj != 0);
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int idx = MODE == 2 ? b_n[e] * PW + b_k[e] : (b_n[e] * PW) / 2 + b_k[e];
+      put(Bs[buf][0], Bs[buf][NPL - 1], idx, tb, rb[e], g.B.conj != 0);
+    }
+  };
+
+  f4 acc_re[WM][WN], acc_im[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      acc_re[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      acc_im[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+
+  const int wr = wave & 1, wc = wave >> 1;
+  const int rowb = wr * 16 * WM, colb = wc * 16 * WN;
+  const int nkt = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  load();
+  stage(0);
+  __syncthreads();
+  for (int it = 0; it < nkt; ++it) {
+    const int buf = it & 1;
+    if (it + 1 < nkt) load();
+    if (MODE == 2) {
+      const int koff = 4 * (lane >> 4);  // complex k offset of this lane's 8 bf16
+      u4 ah[WM], al[WM], bh[WN], bl[WN];
+#pragma unroll
+      for (int i = 0; i < WM; ++i) {
+        const int row = rowb + 16 * i + (lane & 15);
+        ah[i] = *reinterpret_cast<const u4*>(&As[buf][0][row * PW + koff]);
+        al[i] = *reinterpret_cast<const u4*>(&As[buf][1][row * PW + koff]);
+      }
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        const int col = colb + 16 * j + (lane & 15);
+        bh[j] = *reinterpret_cast<const u4*>(&Bs[buf][0][col * PW + koff]);
+        bl[j] = *reinterpret_cast<const u4*>(&Bs[buf][1][col * PW + koff]);
+      }
+#pragma unroll
+      for (int i = 0; i < WM; ++i) {
+        const bf8 anh = as_bf8(neg_im(ah[i])), anl = as_bf8(neg_im(al[i]));
+        const bf8 aph = as_bf8(ah[i]), apl = as_bf8(al[i]);
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+          const bf8 bph = as_bf8(bh[j]), bpl = as_bf8(bl[j]);
+          const bf8 bsh = as_bf8(swap_re_im(bh[j])), bsl = as_bf8(swap_re_im(bl[j]));
+          acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(anh, bph, acc_re[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aph, bsh, acc_im[i][j], 0, 0, 0);
+          acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(anh, bpl, acc_re[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aph, bsl, acc_im[i][j], 0, 0, 0);
+          acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(anl, bph, acc_re[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(apl, bsh, acc_im[i][j], 0, 0, 0);
+        }
+      }
+    } else {
+      const int kr = lane >> 4;  // real k within a 4-deep MFMA step
+      const float sneg = (kr & 1) ? -1.0f : 1.0f;
+#pragma unroll
+      for (int st = 0; st < BK / 2; ++st) {
+        const int w = 4 * st + kr;  // word index (re, im interleaved) of this lane's k
+        float av[WM], an[WM], bv[WN], bw[WN];
+#pragma unroll
+        for (int i = 0; i < WM; ++i) {
+          const int row = rowb + 16 * i + (lane & 15);
+          av[i] = __builtin_bit_cast(float, As[buf][0][row * PW + w]);
+          an[i] = sneg * av[i];
+        }
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+          const int col = colb + 16 * j + (lane & 15);
+          bv[j] = __builtin_bit_cast(float, Bs[buf][0][col * PW + w]);
+          bw[j] = __builtin_bit_cast(float, Bs[buf][0][col * PW + (w ^ 1)]);
+        }
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+          for (int j = 0; j < WN; ++j) {
+            acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(an[i], bv[j], acc_re[i][j], 0, 0, 0);
+            acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bw[j], acc_im[i][j], 0, 0, 0);
+          }
+      }
+    }
+    if (it + 1 < nkt) stage(buf ^ 1);
+    __syncthreads();
+  }
+
+  // epilogue: v_mfma_f32_16x16x4f32 / 16x16x32_bf16 leave row 4 (lane/16) + r, column lane % 16
+  if (g.ksplit > 1) {
+    double2* __restrict__ Pp = g.partial + ((int64_t)slice * g.batch + batch) * (int64_t)g.M * g.N;
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+      for (int j = 0; j < WN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gm = m0 + rowb + 16 * i + 4 * (lane >> 4) + r;
+          const int gn = n0 + colb + 16 * j + (lane & 15);
+          if (gm < g.M && gn < g.N)
+            Pp[(int64_t)gm * g.N + gn] = make_double2((double)acc_re[i][j][r], (double)acc_im[i][j][r]);
+        }
+    return;
+  }
+  const int64_t cb = batch_off(g.cb, batch);
+  int64_t coff[WN];
+#pragma unroll
+  for (int j = 0; j < WN; ++j) {
+    const int gn = n0 + colb + 16 * j + (lane & 15);
+    coff[j] = gn < g.N ? map_idx(g.cc, gn) : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gm = m0 + rowb + 16 * i + 4 * (lane >> 4) + r;
+      if (gm >= g.M) continue;
+      const int64_t roff = cb + map_idx(g.cr, gm);
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        const int gn = n0 + colb + 16 * j + (lane & 15);
+        if (gn < g.N) store_c(g, roff + coff[j], make_double2((double)acc_re[i][j][r], (double)acc_im[i][j][r]));
+      }
+    }
 }
 
 // Second pass of split-K: C = alpha * sum_slices partial + beta * C, slices added in order.
 __global__ __launch_bounds__(256) void zgemm_splitk_reduce(const ZGemm g) {
   const int64_t mn = (int64_t)g.M * g.N;
   const int64_t total = mn * g.batch;
-  const bool use_beta = g.beta.x != 0.0 || g.beta.y != 0.0;
   for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
     const int32_t b = (int32_t)(x / mn);
     const int64_t e = x - (int64_t)b * mn;
@@ -235,17 +599,21 @@ __global__ __launch_bounds__(256) void zgemm_splitk_reduce(const ZGemm g) {
       vr += v.x;
       vi += v.y;
     }
-    double2* Cp = g.C + batch_off(g.cb, b);
-    const int64_t off = map_idx(g.cr, gm) + map_idx(g.cc, gn);
-    double2 o;
-    o.x = g.alpha.x * vr - g.alpha.y * vi;
-    o.y = g.alpha.x * vi + g.alpha.y * vr;
-    if (use_beta) {
-      const double2 c = Cp[off];
-      o.x += g.beta.x * c.x - g.beta.y * c.y;
-      o.y += g.beta.x * c.y + g.beta.y * c.x;
+    store_c(g, batch_off(g.cb, b) + map_idx(g.cr, gm) + map_idx(g.cc, gn), make_double2(vr, vi));
+  }
+}
+
+// Elementwise rounding of a complex FP64 array to kC32 or kCB16.
+__global__ void k_convert_c64(const double2* __restrict__ in, void* __restrict__ out, int32_t t, int64_t n) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+    const double2 v = in[x];
+    if (t == kC32) {
+      reinterpret_cast<float2*>(out)[x] = make_float2((float)v.x, (float)v.y);
+    } else {
+      uint2 w;
+      split_pair(v.x, v.y, w.x, w.y);
+      reinterpret_cast<uint2*>(out)[x] = w;
     }
-    Cp[off] = o;
   }
 }
 
@@ -292,22 +660,26 @@ Range batch_range(const BatchMap& b, int64_t n, bool* ok) {
   return {std::min(a1, a2) + std::min<int64_t>(0, h), std::max(a1, a2) + std::max<int64_t>(0, h)};
 }
 
-bool check_operand(const char* name, const void* p, const Range& r1, const Range& r2, const Range& rb,
-                   const Span& sp, char* why, int why_len) {
+bool check_operand(const char* name, const void* p, int32_t etype, const Range& r1, const Range& r2,
+                   const Range& rb, const Span& sp, char* why, int why_len) {
   if (!sp.base) {
     std::snprintf(why, why_len, "%s: no extent", name);
     return false;
   }
+  if (etype < kC64 || etype > kCB16) {
+    std::snprintf(why, why_len, "%s: bad element type", name);
+    return false;
+  }
+  const int64_t esz = elem_bytes(etype);
   const int64_t base = (static_cast<const char*>(p) - static_cast<const char*>(sp.base));
-  if (base % 16) {
+  if (base % esz) {
     std::snprintf(why, why_len, "%s: misaligned", name);
     return false;
   }
-  const int64_t b0 = base / 16;
-  const int64_t lo = b0 + r1.lo + r2.lo + rb.lo, hi = b0 + r1.hi + r2.hi + rb.hi;
-  if (lo < 0 || hi >= sp.count) {
-    std::snprintf(why, why_len, "%s: touches [%lld, %lld] of a %lld-element buffer", name, (long long)lo,
-                  (long long)hi, (long long)sp.count);
+  const int64_t lo = base + (r1.lo + r2.lo + rb.lo) * esz, hi = base + (r1.hi + r2.hi + rb.hi) * esz + esz;
+  if (lo < 0 || hi > sp.bytes) {
+    std::snprintf(why, why_len, "%s: touches bytes [%lld, %lld) of a %lld-byte buffer", name, (long long)lo,
+                  (long long)hi, (long long)sp.bytes);
     return false;
   }
   return true;
@@ -336,16 +708,25 @@ bool zgemm_in_bounds(const ZGemm& g, const Span& a, const Span& b, const Span& c
     std::snprintf(why, why_len, "ksplit < 1");
     return false;
   }
-  return check_operand("A", g.A.p, map_range(g.A.r, g.M), map_range(g.A.c, g.K), ba, a, why, why_len) &&
-         check_operand("B", g.B.p, map_range(g.B.r, g.K), map_range(g.B.c, g.N), bb, b, why, why_len) &&
-         check_operand("C", g.C, map_range(g.cr, g.M), map_range(g.cc, g.N), bc, c, why, why_len);
+  if (g.prec == 0 && (g.A.etype != kC64 || g.B.etype != kC64 || g.ctype != kC64)) {
+    std::snprintf(why, why_len, "FP64 contraction with non-FP64 operands");
+    return false;
+  }
+  if (g.ctype == kCB16 && (g.beta.x != 0.0 || g.beta.y != 0.0)) {
+    std::snprintf(why, why_len, "split-BF16 output cannot accumulate");
+    return false;
+  }
+  return check_operand("A", g.A.p, g.A.etype, map_range(g.A.r, g.M), map_range(g.A.c, g.K), ba, a, why, why_len) &&
+         check_operand("B", g.B.p, g.B.etype, map_range(g.B.r, g.K), map_range(g.B.c, g.N), bb, b, why, why_len) &&
+         check_operand("C", g.C, g.ctype, map_range(g.cr, g.M), map_range(g.cc, g.N), bc, c, why, why_len);
 }
 
 hipError_t zgemm(const ZGemm& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
   if (g.K <= 0) return hipErrorInvalidValue;
   if (dryrun()) return hipSuccess;
-  if (g.ksplit < 1) return hipErrorInvalidValue;
+  if (g.ksplit < 1 || g.prec < 0 || g.prec > 2) return hipErrorInvalidValue;
+  if (g.prec == 0 && (g.A.etype != kC64 || g.B.etype != kC64 || g.ctype != kC64)) return hipErrorInvalidValue;
   if (g.ksplit > 1 && !g.partial) return hipErrorInvalidValue;
   // tile shape: 32 x 32, 64 x 32, 32 x 64 or 64 x 64 (a dimension <= 32 gets a 32-wide tile)
   const int wm = g.M <= 32 ? 1 : 2, wn = g.N <= 32 ? 1 : 2;
@@ -362,6 +743,36 @@ hipError_t zgemm(const ZGemm& g, hipStream_t s) {
       default: zgemm_f64_kernel<2, 2, Site::S><<<grid, block, 0, s>>>(g); break; \
     }                                                                    \
     break;
+  if (g.prec == 1 || g.prec == 2) {
+#define GREEN_MX(MODE, S)                                                                       \
+  switch (shape) {                                                                              \
+    case 0: zgemm_mx_kernel<MODE, 1, 1, Site::S><<<grid, block, 0, s>>>(g); break;              \
+    case 1: zgemm_mx_kernel<MODE, 1, 2, Site::S><<<grid, block, 0, s>>>(g); break;              \
+    case 2: zgemm_mx_kernel<MODE, 2, 1, Site::S><<<grid, block, 0, s>>>(g); break;              \
+    default: zgemm_mx_kernel<MODE, 2, 2, Site::S><<<grid, block, 0, s>>>(g); break;             \
+  }
+#define GREEN_MX_SITE(MODE)                                            \
+  switch (g.site) {                                                    \
+    case Site::P0_VG: GREEN_MX(MODE, P0_VG) break;                     \
+    case Site::P0_VGrev: GREEN_MX(MODE, P0_VGrev) break;               \
+    case Site::P0_Contract: GREEN_MX(MODE, P0_Contract) break;         \
+    case Site::Sig_PV: GREEN_MX(MODE, Sig_PV) break;                   \
+    case Site::Sig_XG: GREEN_MX(MODE, Sig_XG) break;                   \
+    case Site::Sig_YV: GREEN_MX(MODE, Sig_YV) break;                   \
+    default: GREEN_MX(MODE, Generic) break;                            \
+  }
+    if (g.prec == 1) {
+      GREEN_MX_SITE(1)
+    } else if (g.site == Site::P0_Contract) {
+      GREEN_MX(2, P0_Contract)
+    } else if (g.site == Site::Sig_PV) {
+      GREEN_MX(2, Sig_PV)
+    } else {
+      GREEN_MX(2, Generic)
+    }
+#undef GREEN_MX_SITE
+#undef GREEN_MX
+  } else
   switch (g.site) {
     GREEN_SITE(P0_VG)
     GREEN_SITE(P0_VGrev)
@@ -381,6 +792,16 @@ hipError_t zgemm(const ZGemm& g, hipStream_t s) {
     if (nb > 65536) nb = 65536;
     zgemm_splitk_reduce<<<dim3((unsigned)nb), dim3(256), 0, s>>>(g);
   }
+  return hipGetLastError();
+}
+
+hipError_t convert_c64(const double2* in, void* out, int32_t etype, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (etype != kC32 && etype != kCB16) return hipErrorInvalidValue;
+  if (dryrun()) return hipSuccess;
+  int64_t nb = (n + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  k_convert_c64<<<dim3((unsigned)nb), dim3(256), 0, s>>>(in, out, etype, n);
   return hipGetLastError();
 }
 

@@ -16,6 +16,8 @@
 // After the last panel the columns are unscrambled (swaps undone in reverse order).
 // Each panel reads and writes the matrix once, so the traffic is
 // (n / nb) * 2 * 16 n^2 bytes per matrix.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace green {
@@ -222,12 +224,18 @@ __global__ __launch_bounds__(256) void zinv_kernel(double2* __restrict__ A, int 
   }
 }
 
+// LDS per workgroup for the panel.  Measured on MI355X: a wider panel (up to 150 KiB) cuts the number of
+// full-matrix passes but costs occupancy and lengthens the serial column steps, and was slower for
+// naux = 180 than this 56 KiB budget (which also needs no raised dynamic-LDS limit).
+size_t lds_budget() { return 56 * 1024; }
+
 }  // namespace
 
 hipError_t zinv_batched(double2* A, int n, int64_t stride, int batch, int* status, hipStream_t s) {
   if (batch <= 0) return hipSuccess;
   if (n <= 0 || n > kMaxN) return hipErrorInvalidValue;
-  const size_t budget = 56 * 1024;  // keep the workgroup's LDS within 64 KiB
+  if (dryrun()) return hipSuccess;
+  const size_t budget = lds_budget();
   int nb = (int)((budget - 32 * (size_t)n) / (16 * (size_t)n));
   nb = nb < 1 ? 1 : (nb > 32 ? 32 : nb);
   if (nb > n) nb = n;

@@ -35,7 +35,7 @@ def lib(monkeypatch):
     return _lib
 
 
-def _plan(lib, c):
+def _plan(lib, c, prec=0):
     g = gridmod.make_grid(c["ntau"], c["beta"])
     d = lib.Dims((ctypes.c_int32 * 3)(*c["kmesh"]), c["nao"], c["naux"], c["ntau"], len(g.nf), len(g.nb),
                  c["nspin"], c["beta"])
@@ -43,15 +43,16 @@ def _plan(lib, c):
     keep += [np.ascontiguousarray(a, dtype=np.complex128) for a in (g.TF_t2w, g.TF_w2t, g.TB_t2w, g.TB_w2t)]
     gc = lib.GridC(*[a.ctypes.data for a in keep])
     h = ctypes.c_void_p()
-    st = lib.LIB.green_plan_create(ctypes.byref(d), ctypes.byref(gc), 0, c["chunk"], ctypes.byref(h))
+    st = lib.LIB.green_plan_create(ctypes.byref(d), ctypes.byref(gc), prec, c["chunk"], ctypes.byref(h))
     assert st == 0, st
     return h
 
 
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("c", CASES, ids=lambda c: f"k{c['kmesh']}_nao{c['nao']}_naux{c['naux']}_ns{c['nspin']}_ch{c['chunk']}")
-def test_all_launches_in_bounds(lib, c):
+def test_all_launches_in_bounds(lib, c, prec):
     assert os.environ.get("GREEN_DRYRUN") == "1"
-    h = _plan(lib, c)
+    h = _plan(lib, c, prec)
     try:
         ws_bytes = lib.LIB.green_workspace_bytes(h)
         assert ws_bytes > 0

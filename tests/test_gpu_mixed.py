@@ -1,0 +1,88 @@
+"""Mixed-precision contractions (FP32 and split-BF16 hi+lo on MFMA, FP32 accumulation flushed to FP64)
+against the FP64 path on the same inputs.
+
+The contraction error bound follows from the arithmetic: FP32 rounds each
+operand to 2^-24 relative; split BF16 keeps hi + lo to 2^-18 relative and
+drops the lo*lo term, so each product carries up to ~3 * 2^-18 ~ 1.1e-5
+relative error.  Sums of such products stay within that relative error of
+the sum of magnitudes; the tests allow a factor ~3 margin on the max-norm.
+The acceptance bar for a full iteration is |dE| <= 1e-6 Eh and
+max|dSigma| <= 1e-5 Eh (checked on the 2x2x2 workload).
+"""
+import numpy as np
+import pytest
+
+from synth import configs, systems
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+REL = {"fp32": 3e-6, "bf16x3": 4e-5}
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def plan(s, prec):
+    from paper_2406_18479_amd.gw import Plan
+    sp = s.spec
+    return Plan(sp.kmesh, sp.nao, sp.naux, s.grid, nspin=sp.nspin, prec=prec)
+
+
+@pytest.fixture(scope="module")
+def small():
+    sp = configs.tiny(kmesh=(2, 2, 1), nao=11, naux=53, ntau=12, beta=8.0, seed=201, v_scale=0.1)
+    return systems.make_system(sp)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_mixed_polarization_and_selfenergy(small, prec):
+    _require_gpu()
+    s = small
+    print("[gpu-case] mixed contractions", prec, flush=True)
+    V, G = dev(s.V), dev(s.G0)
+    p64, pmx = plan(s, "fp64"), plan(s, prec)
+    P64 = host(p64.polarization(V, G))
+    Pmx = host(pmx.polarization(V, G))
+    assert rel(Pmx, P64) <= REL[prec]
+    Pt = dev(systems.random_polarization(7, s.spec.nk, s.spec.ntau, s.spec.naux, scale=0.1))
+    S64 = host(p64.selfenergy(V, G, Pt))
+    Smx = host(pmx.selfenergy(V, G, Pt))
+    assert rel(Smx, S64) <= REL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_mixed_iteration_periodic_2x2x2(prec):
+    """One iteration of the 2x2x2 workload from identical inputs: |dE| <= 1e-6 Eh, max|dSigma| <= 1e-5 Eh."""
+    _require_gpu()
+    s = systems.make_system(configs.PERIODIC_2)
+    out = {}
+    for pr in ("fp64", prec):
+        print("[gpu-case] mixed iteration", pr, flush=True)
+        p = plan(s, pr)
+        G = dev(s.G0)
+        Sinf = torch.zeros(p.shape_H, dtype=torch.complex128, device="cuda:0")
+        Sig = torch.zeros(p.shape_G, dtype=torch.complex128, device="cuda:0")
+        mu, rep = p.iterate(dev(s.V), dev(s.H0), dev(s.S), G, Sinf, Sig, 0.0, s.n_target, 1.0)
+        out[pr] = (host(Sig), rep)
+        del p
+    dE = abs(out[prec][1]["e_tot"] - out["fp64"][1]["e_tot"])
+    dS = float(np.max(np.abs(out[prec][0] - out["fp64"][0])))
+    print(f"[gpu-case] {prec}: |dE| = {dE:.3e} Eh, max|dSigma| = {dS:.3e} Eh", flush=True)
+    assert dE <= 1e-6
+    assert dS <= 1e-5
