@@ -72,7 +72,7 @@ def cpu_baseline(system, target_s: float):
             "seconds": dt}
 
 
-def run_precision(system, prec, steps, warmup):
+def run_precision(system, prec, steps, warmup, chunk_bytes=0):
     """Time `steps` iterations (after `warmup`) at one contraction precision; returns a summary dict."""
     import numpy as np
     import torch
@@ -80,7 +80,7 @@ def run_precision(system, prec, steps, warmup):
     from paper_2406_18479_amd.gw import Plan
 
     spec = system.spec
-    plan = Plan(spec.kmesh, spec.nao, spec.naux, system.grid, nspin=spec.nspin, prec=prec)
+    plan = Plan(spec.kmesh, spec.nao, spec.naux, system.grid, nspin=spec.nspin, prec=prec, chunk_bytes=chunk_bytes)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")  # noqa: E731
     V, H0, S = dev(system.V), dev(system.H0), dev(system.S)
 
@@ -152,6 +152,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reference", action="store_true",
                     help="skip the FP64 reference run (profiling runs of one precision; no accuracy fields)")
+    ap.add_argument("--chunk-mib", type=int, default=0,
+                    help="workspace bound for the contraction intermediates (0: library default)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -178,7 +180,7 @@ def main():
     system = systems.make_system(spec)
     asked = [p for p in args.precisions.split(",") if p]
     precs = asked if args.no_reference else ["fp64"] + [p for p in asked if p != "fp64"]
-    res = {p: run_precision(system, p, args.steps, args.warmup) for p in precs}
+    res = {p: run_precision(system, p, args.steps, args.warmup, args.chunk_mib << 20) for p in precs}
     ref = res["fp64"]["first"] if "fp64" in res else None
     for p, r in res.items():
         if ref is None:

@@ -35,7 +35,7 @@ struct green_plan {
   std::vector<int32_t> kadd, ksub, kneg;  // [q][k]: k+q, k-q; [q]: -q
   // workspace regions
   Region r_TF_t2w, r_TF_w2t, r_TB_t2w, r_TB_w2t, r_Emass, r_wf, r_kadd, r_ksub, r_status, r_scal, r_partial;
-  Region r_P, r_Pw, r_T1, r_T2, r_gam, r_gamT, r_D, r_Sinfn, r_Sign, r_Sw, r_A, r_tr, r_split, r_Vx;
+  Region r_P, r_Pw, r_T1, r_T2, r_gam, r_gamT, r_D, r_Sinfn, r_Sign, r_Sw, r_A, r_tr, r_split, r_Vx, r_Ptx;
   size_t ws_bytes = 0;
   void* bound_ws = nullptr;
   hipEvent_t ev[kNumEvents]{};
@@ -198,11 +198,15 @@ thread_local KernelClock* tl_clock = nullptr;
 
 // Split the K range when the output tiles alone cannot fill the GPU (256 CUs): aim for ~2048
 // workgroups, keep every slice at least 64 deep, and fit the partial sums into the scratch region.
-int choose_ksplit(int M, int N, int K, int batch) {
-  const int bm = M <= 32 ? 32 : 64, bn = N <= 32 ? 32 : 64;
+int choose_ksplit(const ZGemm& g) {
+  const int M = g.M, N = g.N, K = g.K, batch = g.batch;
+  int bm, bn, threads;
+  green::zgemm_tile(g, &bm, &bn, &threads);
   const int64_t tiles = (int64_t)((M + bm - 1) / bm) * ((N + bn - 1) / bn) * batch;
-  if (tiles >= 1024) return 1;
-  int ks = (int)std::min<int64_t>((2048 + tiles - 1) / tiles, 32);
+  // 256-thread tiles: aim for ~2048 workgroups; 512-thread large tiles (one per CU): ~1024
+  const int64_t target = threads == 512 ? 1024 : 2048;
+  if (tiles >= target / 2) return 1;
+  int ks = (int)std::min<int64_t>((target + tiles - 1) / tiles, 32);
   ks = std::min(ks, std::max(1, K / 64));
   while (ks > 1 && (int64_t)ks * batch * M * N > tl_split.cap) --ks;
   return std::max(ks, 1);
@@ -221,7 +225,7 @@ ZOp op(const void* ptr, IdxMap r, IdxMap c, BatchMap b, int etype = green::kC64,
 
 int gemm(green::Site site, const char* label, const ZOp& A, const green::Span& sa, const ZOp& B, const green::Span& sb, void* C,
          const green::Span& sc, IdxMap cr, IdxMap cc, BatchMap cb, int M, int N, int K, int batch, double2 alpha,
-         double2 beta, hipStream_t s, int prec = 0, int ctype = green::kC64) {
+         double2 beta, hipStream_t s, int prec = 0, int ctype = green::kC64, int big = 0) {
   ZGemm g;
   g.site = site;
   g.M = M;
@@ -236,9 +240,11 @@ int gemm(green::Site site, const char* label, const ZOp& A, const green::Span& s
   g.cb = cb;
   g.alpha = alpha;
   g.beta = beta;
-  g.ksplit = choose_ksplit(M, N, K, batch);
   g.prec = prec;
   g.ctype = ctype;
+  g.big = big;
+  g.ksplit = 1;
+  g.ksplit = choose_ksplit(g);
   g.partial = g.ksplit > 1 ? tl_split.ptr : nullptr;
   char why[256];
   if (g.ksplit > 1 && (int64_t)g.ksplit * batch * M * N > tl_split.cap) return GREEN_EINVAL;
@@ -333,7 +339,7 @@ int run_polarization(green_plan* p, const void* V, const void* G, void* P0, void
                        op(T2, two((int32_t)nG, 1, nV), flat(nG), bflat((int64_t)nk * nV), tt), sT2,
                        Pp + ((int64_t)q * ntau + t0) * naux * naux, sP, flat(naux), flat(1),
                        bflat((int64_t)naux * naux), naux, naux, (int)(nk * nG), tcn, cplx(-w / nk),
-                       cplx(sp == 0 ? 0.0 : 1.0), s, p->prec, green::kC64));
+                       cplx(sp == 0 ? 0.0 : 1.0), s, p->prec, green::kC64, p->prec == GREEN_BF16X3 ? 1 : 0));
       }
     }
   }
@@ -391,21 +397,32 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
   const int stage = mixed ? 1 : 0;
   void* Vx = at<void>(ws, p->r_Vx);
   const green::Span sVx = span_ws(ws, p->r_Vx);
+  const bool bf = p->prec == GREEN_BF16X3;
+  void* Ptx = at<void>(ws, p->r_Ptx);
+  const green::Span sPtx = span_ws(ws, p->r_Ptx);
   for (int q = 0; q < nk; ++q) {
     const int qn = p->kneg[q];
     if (mixed) {
       if ((int64_t)p->r_Vx.bytes < slab * green::elem_bytes(vt)) return GREEN_EINVAL;
       HIP_TRY(green::convert_c64(Vp + qn * slab, Vx, vt, slab, s));
     }
+    if (bf) {
+      // P~^q(tau)^T rounded to split BF16 for the large-tile kernel (K-contiguous rows)
+      if ((int64_t)p->r_Ptx.bytes < (int64_t)ntau * nP * 8) return GREEN_EINVAL;
+      HIP_TRY(green::convert_c64_t(Pp + (int64_t)q * ntau * nP, Ptx, green::kCB16, naux, ntau, s));
+    }
     for (int t0 = 0; t0 < ntau; t0 += p->tc) {
       const int tcn = std::min(p->tc, ntau - t0);
       // X[tt][k][Q'][(i,a)] = sum_Q P~^q_{QQ'}(tau) V^{k,k-q}_{ia}(Q)
-      GREEN_TRY(gemm(green::Site::Sig_PV, "Sigma.PV", op(Pp + ((int64_t)q * ntau + t0) * nP, flat(1), flat(naux), bflat(nP)),
-                     sP,
+      GREEN_TRY(gemm(green::Site::Sig_PV, "Sigma.PV",
+                     bf ? op(static_cast<char*>(Ptx) + (int64_t)t0 * nP * 8, flat(naux), flat(1), bflat(nP),
+                             green::kCB16)
+                        : op(Pp + ((int64_t)q * ntau + t0) * nP, flat(1), flat(naux), bflat(nP)),
+                     bf ? sPtx : sP,
                      mixed ? op(Vx, flat(nG), two((int32_t)nG, 1, nV), bnone(), vt)
                            : op(Vp + qn * slab, flat(nG), two((int32_t)nG, 1, nV), bnone()),
                      mixed ? sVx : sV, T1, sT1, flat(nG), two((int32_t)nG, 1, nV), bflat((int64_t)nk * nV), naux,
-                     (int)(nk * nG), naux, tcn, cplx(1), cplx(0), s, p->prec, xt));
+                     (int)(nk * nG), naux, tcn, cplx(1), cplx(0), s, p->prec, xt, bf ? 2 : 0));
       for (int sp = 0; sp < ns; ++sp) {
         // Y[tt][k][(Q',i)][b] = sum_a X[tt][k][(Q',i)][a] G^{k-q}_{ab}(tau)
         GREEN_TRY(gemm(green::Site::Sig_XG, "Sigma.XG", op(T1, flat(nao), flat(1), bflat(nV), xt), sT1,
@@ -788,8 +805,9 @@ int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, 
   take(p->r_Sw, (size_t)ns * nwf * nk * nG * 16);
   take(p->r_A, (size_t)ns * nwf * nk * nG * 16);
   take(p->r_tr, (size_t)std::max<int64_t>(ns * nwf * nk, ns * ntau * nk) * 16);
-  take(p->r_split, (size_t)256 << 20);
+  take(p->r_split, (size_t)1 << 30);
   take(p->r_Vx, prec == GREEN_FP64 ? 0 : (size_t)nk * nV * 8);
+  take(p->r_Ptx, prec == GREEN_BF16X3 ? (size_t)ntau * nP * 8 : 0);
   p->ws_bytes = off;
   *out = p;
   return GREEN_OK;

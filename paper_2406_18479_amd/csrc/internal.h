@@ -85,7 +85,11 @@ struct ZGemm {
   int32_t prec;   // 0: FP64 MFMA, 1: FP32 MFMA, 2: split BF16 (hi + lo, three products) MFMA; prec 1 and 2
                   // accumulate in FP32 within a K slice, slices are combined in FP64
   int32_t ctype;  // ElemType of C (kCB16 requires beta == 0); prec 0 requires kC64 operands and output
+  int32_t big;    // prec 2 with kCB16 operands: 1 = 192 x 96 tiles, 2 = 192 x 64 tiles (large-tile kernel)
 };
+
+// Tile of the GEMM variant the launcher will pick (for choosing split-K counts).
+void zgemm_tile(const ZGemm& g, int* bm, int* bn, int* threads);
 
 hipError_t zgemm(const ZGemm& g, hipStream_t s);
 
@@ -97,6 +101,8 @@ struct Span {
 
 // Round a complex FP64 array to FP32 (kC32) or to split BF16 (kCB16), element for element.
 hipError_t convert_c64(const double2* in, void* out, int32_t etype, int64_t n, hipStream_t s);
+// out[b][j][i] = round(in[b][i][j]) for `batch` n x n matrices (kC32 or kCB16)
+hipError_t convert_c64_t(const double2* in, void* out, int32_t etype, int n, int64_t batch, hipStream_t s);
 
 // Host-side bounds check of a GEMM descriptor against the buffers its operands point into (conservative:
 // the box spanned by the index maps).  Returns false and fills `why` when an access could leave a buffer.

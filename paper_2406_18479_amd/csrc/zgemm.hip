@@ -585,6 +585,198 @@ __global__ __launch_bounds__(256) void zgemm_mx_kernel(const ZGemm g) {
     }
 }
 
+// ------------------------------------------------------------------------------------------------
+// Large-tile split-BF16 variant for the two dominant contractions.  512 threads (8 waves, 4 along M x
+// 2 along N), each wave owning FM x FN blocks of 16 x 16, so a tile is (64 FM) x (32 FN): with FM = 3,
+// FN = 3 a 192 x 96 tile covers naux <= 192 along M and half of it along N, so each K slice of the
+// operands is fetched once (A) or twice (B) instead of once per 64-wide tile.  (A 192 x 192 tile needs
+// 144 accumulator registers per lane and spills.)  Operands are stored pre-split (kCB16) and go to LDS unchanged.  A is K-contiguous;
+// B is K-contiguous or N-contiguous.  Workgroups are renumbered so that each XCD (8 on MI355X, blocks
+// dispatched round-robin) processes a contiguous range of tiles, whose operands then share its L2.
+constexpr int kXcd = 8;
+
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t n) {
+  const int64_t full = (n / kXcd) * kXcd;
+  if (b >= full) return b;
+  return (b % kXcd) * (n / kXcd) + b / kXcd;
+}
+
+template <int FM, int FN, Site SITE>
+__global__ __launch_bounds__(512) void zgemm_bt_kernel(const ZGemm g) {
+  constexpr int BM = 64 * FM, BN = 32 * FN, BK = 16;
+  constexpr int PW = BK + 4;  // words per LDS row (hi or lo plane), padded
+  constexpr int EA = BM * BK / 512;
+  constexpr int EB = BN * BK / 512;
+  __shared__ uint32_t As[2][2][BM * PW];
+  __shared__ uint32_t Bs[2][2][BN * PW];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int tiles_m = (g.M + BM - 1) / BM;
+  const int tiles_n = (g.N + BN - 1) / BN;
+  const int64_t per_batch = (int64_t)tiles_m * tiles_n;
+  const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t group = bid / per_batch;
+  const int32_t tile = (int32_t)(bid - group * per_batch);
+  const int32_t batch = (int32_t)(group / g.ksplit);
+  const int32_t slice = (int32_t)(group - (int64_t)batch * g.ksplit);
+  const int tm = tile % tiles_m;
+  const int tn = tile / tiles_m;
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int kchunk = ((g.K + g.ksplit - 1) / g.ksplit + BK - 1) / BK * BK;
+  const int kbeg = slice * kchunk;
+  const int kend = min(g.K, kbeg + kchunk);
+
+  const uint2* __restrict__ Ap = reinterpret_cast<const uint2*>(g.A.p) + batch_off(g.A.b, batch);
+  const uint2* __restrict__ Bp = reinterpret_cast<const uint2*>(g.B.p) + batch_off(g.B.b, batch);
+  const bool b_kc = !(g.B.c.s_in == 1 && g.B.c.ext >= 16);
+  int a_m[EA];
+  int64_t a_ro[EA];
+  bool a_ok[EA];
+  const int a_k = tid & (BK - 1);
+#pragma unroll
+  for (int e = 0; e < EA; ++e) {
+    a_m[e] = (tid >> 4) + 32 * e;
+    const int gm = m0 + a_m[e];
+    a_ok[e] = gm < g.M;
+    a_ro[e] = a_ok[e] ? map_idx(g.A.r, gm) : 0;
+  }
+  int b_n[EB], b_k[EB];
+  int64_t b_co[EB];
+  bool b_ok[EB];
+#pragma unroll
+  for (int e = 0; e < EB; ++e) {
+    if (b_kc) {
+      b_k[e] = tid & (BK - 1);
+      b_n[e] = (tid >> 4) + 32 * e;
+    } else {
+      b_n[e] = tid % BN;
+      b_k[e] = tid / BN + (512 / BN) * e;
+    }
+    const int gn = n0 + b_n[e];
+    b_ok[e] = gn < g.N;
+    b_co[e] = b_ok[e] ? map_idx(g.B.c, gn) : 0;
+  }
+  KPos apos, bpos[EB];
+  apos.init(g.A.c, kbeg + a_k);
+#pragma unroll
+  for (int e = 0; e < EB; ++e) bpos[e].init(g.B.r, kbeg + b_k[e]);
+  const uint32_t aflip = g.A.conj ? 0x80000000u : 0u, bflip = g.B.conj ? 0x80000000u : 0u;
+
+  uint2 ra[EA], rb[EB];
+  auto load = [&]() {
+    const bool ak = apos.k < kend;
+    const int64_t aoff = apos.off(g.A.c);
+#pragma unroll
+    for (int e = 0; e < EA; ++e) ra[e] = (a_ok[e] && ak) ? Ap[a_ro[e] + aoff] : make_uint2(0u, 0u);
+    apos.step(g.A.c, BK);
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      rb[e] = (b_ok[e] && bpos[e].k < kend) ? Bp[bpos[e].off(g.B.r) + b_co[e]] : make_uint2(0u, 0u);
+      bpos[e].step(g.B.r, BK);
+    }
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      As[buf][0][a_m[e] * PW + a_k] = ra[e].x ^ aflip;
+      As[buf][1][a_m[e] * PW + a_k] = ra[e].y ^ aflip;
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      Bs[buf][0][b_n[e] * PW + b_k[e]] = rb[e].x ^ bflip;
+      Bs[buf][1][b_n[e] * PW + b_k[e]] = rb[e].y ^ bflip;
+    }
+  };
+
+  f4 acc_re[FM][FN], acc_im[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      acc_re[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      acc_im[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+  const int wm = wave & 3, wn = wave >> 2;
+  const int rowb = wm * 16 * FM, colb = wn * 16 * FN;
+  const int nkt = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  load();
+  stage(0);
+  __syncthreads();
+  const int koff = 4 * (lane >> 4);
+  for (int it = 0; it < nkt; ++it) {
+    const int buf = it & 1;
+    if (it + 1 < nkt) load();
+    u4 bh[FN], bl[FN];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int col = colb + 16 * j + (lane & 15);
+      bh[j] = *reinterpret_cast<const u4*>(&Bs[buf][0][col * PW + koff]);
+      bl[j] = *reinterpret_cast<const u4*>(&Bs[buf][1][col * PW + koff]);
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+      const int row = rowb + 16 * i + (lane & 15);
+      const u4 ah = *reinterpret_cast<const u4*>(&As[buf][0][row * PW + koff]);
+      const u4 al = *reinterpret_cast<const u4*>(&As[buf][1][row * PW + koff]);
+      const bf8 anh = as_bf8(neg_im(ah)), anl = as_bf8(neg_im(al));
+      const bf8 aph = as_bf8(ah), apl = as_bf8(al);
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const bf8 bph = as_bf8(bh[j]), bpl = as_bf8(bl[j]);
+        const bf8 bsh = as_bf8(swap_re_im(bh[j])), bsl = as_bf8(swap_re_im(bl[j]));
+        acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(anh, bph, acc_re[i][j], 0, 0, 0);
+        acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aph, bsh, acc_im[i][j], 0, 0, 0);
+        acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(anh, bpl, acc_re[i][j], 0, 0, 0);
+        acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aph, bsl, acc_im[i][j], 0, 0, 0);
+        acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(anl, bph, acc_re[i][j], 0, 0, 0);
+        acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(apl, bsh, acc_im[i][j], 0, 0, 0);
+      }
+    }
+    if (it + 1 < nkt) stage(buf ^ 1);
+    __syncthreads();
+  }
+
+  if (g.ksplit > 1) {
+    double2* __restrict__ Pp = g.partial + ((int64_t)slice * g.batch + batch) * (int64_t)g.M * g.N;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + rowb + 16 * i + 4 * (lane >> 4) + r;
+        if (gm >= g.M) continue;
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const int gn = n0 + colb + 16 * j + (lane & 15);
+          if (gn < g.N)
+            Pp[(int64_t)gm * g.N + gn] = make_double2((double)acc_re[i][j][r], (double)acc_im[i][j][r]);
+        }
+      }
+    return;
+  }
+  const int64_t cb = batch_off(g.cb, batch);
+  int64_t coff[FN];
+#pragma unroll
+  for (int j = 0; j < FN; ++j) {
+    const int gn = n0 + colb + 16 * j + (lane & 15);
+    coff[j] = gn < g.N ? map_idx(g.cc, gn) : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gm = m0 + rowb + 16 * i + 4 * (lane >> 4) + r;
+      if (gm >= g.M) continue;
+      const int64_t roff = cb + map_idx(g.cr, gm);
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int gn = n0 + colb + 16 * j + (lane & 15);
+        if (gn < g.N) store_c(g, roff + coff[j], make_double2((double)acc_re[i][j][r], (double)acc_im[i][j][r]));
+      }
+    }
+}
+
 // Second pass of split-K: C = alpha * sum_slices partial + beta * C, slices added in order.
 __global__ __launch_bounds__(256) void zgemm_splitk_reduce(const ZGemm g) {
   const int64_t mn = (int64_t)g.M * g.N;
@@ -600,6 +792,25 @@ __global__ __launch_bounds__(256) void zgemm_splitk_reduce(const ZGemm g) {
       vi += v.y;
     }
     store_c(g, batch_off(g.cb, b) + map_idx(g.cr, gm) + map_idx(g.cc, gn), make_double2(vr, vi));
+  }
+}
+
+// Transposing rounding: out[b][j][i] = round(in[b][i][j]).
+__global__ void k_convert_c64_t(const double2* __restrict__ in, void* __restrict__ out, int32_t t, int n,
+                                int64_t batch) {
+  const int64_t nn = (int64_t)n * n, tot = nn * batch;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < tot; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = x / nn;
+    const int e = (int)(x - b * nn);
+    const int j = e / n, i = e - (e / n) * n;  // output element (j, i) <- input (i, j)
+    const double2 v = in[b * nn + (int64_t)i * n + j];
+    if (t == kC32) {
+      reinterpret_cast<float2*>(out)[x] = make_float2((float)v.x, (float)v.y);
+    } else {
+      uint2 w;
+      split_pair(v.x, v.y, w.x, w.y);
+      reinterpret_cast<uint2*>(out)[x] = w;
+    }
   }
 }
 
@@ -721,6 +932,29 @@ bool zgemm_in_bounds(const ZGemm& g, const Span& a, const Span& b, const Span& c
          check_operand("C", g.C, g.ctype, map_range(g.cr, g.M), map_range(g.cc, g.N), bc, c, why, why_len);
 }
 
+// The large-tile kernel needs pre-split operands, a K-contiguous A, and B either K-contiguous or
+// N-contiguous with the tile width dividing the 512 threads.
+static bool big_ok(const ZGemm& g) {
+  if (g.big != 1 && g.big != 2) return false;
+  if (g.A.etype != kCB16 || g.B.etype != kCB16) return false;
+  if (!(g.A.c.s_in == 1 && g.A.c.ext >= 16)) return false;
+  const bool b_nc = g.B.c.s_in == 1 && g.B.c.ext >= 16;
+  if (!b_nc && g.B.r.s_in != 1) return false;
+  return true;
+}
+
+void zgemm_tile(const ZGemm& g, int* bm, int* bn, int* threads) {
+  if (g.prec == 2 && big_ok(g)) {
+    *bm = 192;
+    *bn = g.big == 1 ? 96 : 64;
+    *threads = 512;
+    return;
+  }
+  *bm = g.M <= 32 ? 32 : 64;
+  *bn = g.N <= 32 ? 32 : 64;
+  *threads = 256;
+}
+
 hipError_t zgemm(const ZGemm& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
   if (g.K <= 0) return hipErrorInvalidValue;
@@ -728,9 +962,11 @@ hipError_t zgemm(const ZGemm& g, hipStream_t s) {
   if (g.ksplit < 1 || g.prec < 0 || g.prec > 2) return hipErrorInvalidValue;
   if (g.prec == 0 && (g.A.etype != kC64 || g.B.etype != kC64 || g.ctype != kC64)) return hipErrorInvalidValue;
   if (g.ksplit > 1 && !g.partial) return hipErrorInvalidValue;
-  // tile shape: 32 x 32, 64 x 32, 32 x 64 or 64 x 64 (a dimension <= 32 gets a 32-wide tile)
+  // tile shape: 32 x 32, 64 x 32, 32 x 64 or 64 x 64 (a dimension <= 32 gets a 32-wide tile), or the
+  // large-tile kernel's 192 x 192 / 192 x 64
+  int bm, bn, nthreads;
+  zgemm_tile(g, &bm, &bn, &nthreads);
   const int wm = g.M <= 32 ? 1 : 2, wn = g.N <= 32 ? 1 : 2;
-  const int bm = 32 * wm, bn = 32 * wn;
   const int64_t tiles = (int64_t)((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn);
   const dim3 grid((unsigned)(tiles * g.batch * g.ksplit)), block(256);
   const int shape = (wm - 1) * 2 + (wn - 1);
@@ -743,7 +979,19 @@ hipError_t zgemm(const ZGemm& g, hipStream_t s) {
       default: zgemm_f64_kernel<2, 2, Site::S><<<grid, block, 0, s>>>(g); break; \
     }                                                                    \
     break;
-  if (g.prec == 1 || g.prec == 2) {
+  if (g.prec == 2 && big_ok(g)) {
+    if (g.big == 1) {
+      if (g.site == Site::P0_Contract)
+        zgemm_bt_kernel<3, 3, Site::P0_Contract><<<grid, dim3(512), 0, s>>>(g);
+      else
+        zgemm_bt_kernel<3, 3, Site::Generic><<<grid, dim3(512), 0, s>>>(g);
+    } else {
+      if (g.site == Site::Sig_PV)
+        zgemm_bt_kernel<3, 2, Site::Sig_PV><<<grid, dim3(512), 0, s>>>(g);
+      else
+        zgemm_bt_kernel<3, 2, Site::Generic><<<grid, dim3(512), 0, s>>>(g);
+    }
+  } else if (g.prec == 1 || g.prec == 2) {
 #define GREEN_MX(MODE, S)                                                                       \
   switch (shape) {                                                                              \
     case 0: zgemm_mx_kernel<MODE, 1, 1, Site::S><<<grid, block, 0, s>>>(g); break;              \
@@ -792,6 +1040,17 @@ hipError_t zgemm(const ZGemm& g, hipStream_t s) {
     if (nb > 65536) nb = 65536;
     zgemm_splitk_reduce<<<dim3((unsigned)nb), dim3(256), 0, s>>>(g);
   }
+  return hipGetLastError();
+}
+
+hipError_t convert_c64_t(const double2* in, void* out, int32_t etype, int n, int64_t batch, hipStream_t s) {
+  if (n <= 0 || batch <= 0) return hipSuccess;
+  if (etype != kC32 && etype != kCB16) return hipErrorInvalidValue;
+  if (dryrun()) return hipSuccess;
+  const int64_t tot = (int64_t)n * n * batch;
+  int64_t nb = (tot + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  k_convert_c64_t<<<dim3((unsigned)nb), dim3(256), 0, s>>>(in, out, etype, n, batch);
   return hipGetLastError();
 }
 

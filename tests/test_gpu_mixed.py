@@ -44,17 +44,18 @@ def plan(s, prec):
     return Plan(sp.kmesh, sp.nao, sp.naux, s.grid, nspin=sp.nspin, prec=prec)
 
 
-@pytest.fixture(scope="module")
-def small():
-    sp = configs.tiny(kmesh=(2, 2, 1), nao=11, naux=53, ntau=12, beta=8.0, seed=201, v_scale=0.1)
-    return systems.make_system(sp)
+SMALL = [dict(kmesh=(2, 2, 1), nao=11, naux=53, ntau=12, seed=201),     # skinny stage-1 path, K <= 32
+         dict(kmesh=(2, 1, 1), nao=40, naux=70, ntau=8, seed=202),      # K <= 64
+         dict(kmesh=(1, 1, 1), nao=6, naux=200, ntau=6, seed=203)]      # naux > 192: two large tiles along M
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-def test_mixed_polarization_and_selfenergy(small, prec):
+@pytest.mark.parametrize("c", SMALL, ids=lambda c: f"nao{c['nao']}_naux{c['naux']}")
+def test_mixed_polarization_and_selfenergy(c, prec):
     _require_gpu()
-    s = small
-    print("[gpu-case] mixed contractions", prec, flush=True)
+    s = systems.make_system(configs.tiny(kmesh=c["kmesh"], nao=c["nao"], naux=c["naux"], ntau=c["ntau"], beta=8.0,
+                                         seed=c["seed"], v_scale=0.5 / c["nao"] ** 0.5))
+    print("[gpu-case] mixed contractions", prec, c, flush=True)
     V, G = dev(s.V), dev(s.G0)
     p64, pmx = plan(s, "fp64"), plan(s, prec)
     P64 = host(p64.polarization(V, G))
