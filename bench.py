@@ -39,7 +39,8 @@ def contraction_flops(nk, nao, naux, ntau, nspin) -> float:
 
 def workloads():
     from synth import configs
-    return {"molecule": configs.MOLECULE, "periodic2": configs.PERIODIC_2, "periodic3": configs.PERIODIC_3}
+    return {"molecule": configs.MOLECULE, "periodic2": configs.PERIODIC_2, "periodic3": configs.PERIODIC_3,
+            "large4": configs.LARGE_4}
 
 
 def cpu_baseline(system, target_s: float):
@@ -82,7 +83,8 @@ def run_precision(system, prec, steps, warmup, chunk_bytes=0):
     spec = system.spec
     plan = Plan(spec.kmesh, spec.nao, spec.naux, system.grid, nspin=spec.nspin, prec=prec, chunk_bytes=chunk_bytes)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")  # noqa: E731
-    V, H0, S = dev(system.V), dev(system.H0), dev(system.S)
+    V = system.V_dev
+    H0, S = dev(system.H0), dev(system.S)
 
     def fresh():
         return (dev(system.G0), torch.zeros(plan.shape_H, dtype=torch.complex128, device="cuda:0"),
@@ -108,7 +110,7 @@ def run_precision(system, prec, steps, warmup, chunk_bytes=0):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     plan.close()
-    del plan, V, H0, S, G, Sinf, Sig
+    del plan, H0, S, G, Sinf, Sig
     torch.cuda.empty_cache()
 
     flops = contraction_flops(spec.nk, spec.nao, spec.naux, spec.ntau, spec.nspin)
@@ -176,8 +178,13 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    import torch
+
+    from synth import device as dgen
     spec = workloads()[args.workload]
-    system = systems.make_system(spec)
+    system = systems.make_system(spec, with_V=False)
+    system.V_dev = dgen.make_V(spec, device="cuda:0")  # generated in HBM (same draws as the host generator)
+    torch.cuda.synchronize()
     asked = [p for p in args.precisions.split(",") if p]
     precs = asked if args.no_reference else ["fp64"] + [p for p in asked if p != "fp64"]
     res = {p: run_precision(system, p, args.steps, args.warmup, args.chunk_mib << 20) for p in precs}
@@ -234,6 +241,7 @@ def main():
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
+        system.V = system.V_dev.cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(system, args.cpu_baseline_seconds)
     print(json.dumps(out), flush=True)
 

@@ -1,0 +1,96 @@
+"""Device-resident generation of the synthetic integrals V (same draws as ``synth.systems.make_V``).
+
+The large workloads (3x3x3: 9.5 GB of V, 4x4x4: 167 GB) are generated directly
+in device memory with torch: the SplitMix64 counter stream is reproduced
+bit for bit in int64 arithmetic (two's-complement multiply, logical shifts by
+masking), so every block uses the same integers as the NumPy generator; the
+uniform -> normal transform (Box-Muller) runs in float64 torch ops and agrees
+with the NumPy values to rounding.
+
+Nothing here evaluates the GW method.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import rng
+from .systems import SystemSpec, k_add_table
+
+_MASK64 = (1 << 64) - 1
+
+
+def _i64(x: int) -> int:
+    x &= _MASK64
+    return x - (1 << 64) if x >= (1 << 63) else x
+
+
+_GOLDEN = _i64(0x9E3779B97F4A7C15)
+_M1 = _i64(0xBF58476D1CE4E5B9)
+_M2 = _i64(0x94D049BB133111EB)
+
+
+def _srl(x: torch.Tensor, s: int) -> torch.Tensor:
+    """Logical right shift of int64 values."""
+    return (x >> s) & ((1 << (64 - s)) - 1)
+
+
+def splitmix64(x: torch.Tensor) -> torch.Tensor:
+    z = x + _GOLDEN
+    z = (z ^ _srl(z, 30)) * _M1
+    z = (z ^ _srl(z, 27)) * _M2
+    return z ^ _srl(z, 31)
+
+
+def uniforms(key: int, count: int, device) -> torch.Tensor:
+    idx = torch.arange(count, dtype=torch.int64, device=device)
+    u = splitmix64(idx + _i64(int(key)))
+    return _srl(u, 11).to(torch.float64) * (1.0 / 9007199254740992.0)
+
+
+def complex_normals(key: int, shape, device) -> torch.Tensor:
+    n = int(np.prod(shape))
+    u = uniforms(key, 4 * n, device).view(2 * n, 2)
+    g = torch.sqrt(-2.0 * torch.log1p(-u[:, 0])) * torch.cos(2.0 * np.pi * u[:, 1])
+    g = g.view(n, 2)
+    z = torch.complex(g[:, 0], g[:, 1]) * np.sqrt(0.5)
+    return z.view(shape)
+
+
+def _block(spec: SystemSpec, k1: int, k2: int, env: torch.Tensor, device) -> torch.Tensor:
+    key = int(rng.stream_key(spec.seed, rng.TAG_V, 0, k1, k2))
+    Z = complex_normals(key, (spec.naux, spec.nao, spec.nao), device)
+    return Z * env[:, None, None]
+
+
+def make_V(spec: SystemSpec, device="cuda:0", out: torch.Tensor | None = None) -> torch.Tensor:
+    """V[q][k] = V^{k,k+q}(Q) on `device`, identical in construction to synth.systems.make_V
+    (no time-reversal variant)."""
+    if spec.v_time_reversal:
+        raise NotImplementedError("the time-reversal-symmetric variant is generated on the host")
+    nk = spec.nk
+    add = k_add_table(spec.kmesh)
+    env = (spec.amp * torch.exp(-spec.v_decay * torch.arange(spec.naux, dtype=torch.float64))).to(device)
+    if out is None:
+        out = torch.empty((nk, nk, spec.naux, spec.nao, spec.nao), dtype=torch.complex128, device=device)
+    for q in range(nk):
+        for k in range(nk):
+            k2 = int(add[k, q])
+            if k == k2:
+                Z = _block(spec, k, k, env, device)
+                out[q, k] = 0.5 * (Z + Z.conj().transpose(1, 2))
+            elif k < k2:
+                out[q, k] = _block(spec, k, k2, env, device)
+            else:
+                out[q, k] = _block(spec, k2, k, env, device).conj().transpose(1, 2)
+    return out
+
+
+def random_polarization(seed: int, nk: int, ntau: int, naux: int, scale: float = 0.05, device="cuda:0"):
+    """Device twin of synth.systems.random_polarization (same counter streams)."""
+    P = torch.empty((nk, ntau, naux, naux), dtype=torch.complex128, device=device)
+    for q in range(nk):
+        for t in range(ntau):
+            z = complex_normals(int(rng.stream_key(seed, rng.TAG_P, 0, q, t)), (naux, naux), device)
+            P[q, t] = -scale * 0.5 * (z + z.conj().T) / np.sqrt(naux)
+    return P

@@ -162,3 +162,22 @@ def test_grid_noninteracting_representation():
     assert np.max(np.abs(Gw - ref)) < 1e-10
     # and back
     assert np.max(np.abs(np.einsum("tm,mij->tij", g.TF_w2t, ref) - G0[0, :, 0])) < 1e-9
+
+
+# ----------------------------------------------------------------------------- device generator
+def test_device_generator_matches_host():
+    """The torch generator reproduces the NumPy integer stream bit for bit and V to rounding."""
+    import torch
+
+    from synth import device
+    key = rng.stream_key(11, rng.TAG_V, 0, 1, 2)
+    idx = np.arange(1000, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        ref = rng.splitmix64(idx + key).astype(np.int64)
+    got = device.splitmix64(torch.arange(1000, dtype=torch.int64) + device._i64(int(key))).numpy()
+    assert np.array_equal(ref, got)
+    assert np.array_equal(rng.uniforms(key, 0, 1000), device.uniforms(int(key), 1000, "cpu").numpy())
+    sp = configs.tiny(kmesh=(2, 2, 1), nao=3, naux=5, ntau=8, seed=19)
+    Vh = systems.make_V(sp)
+    Vd = device.make_V(sp, device="cpu").numpy()
+    assert np.max(np.abs(Vh - Vd)) < 1e-14 * np.max(np.abs(Vh))
