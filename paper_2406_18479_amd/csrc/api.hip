@@ -2,6 +2,7 @@
 // self-consistent GW iteration (Sec. 2.3) from the batched kernels.
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -30,12 +31,14 @@ struct green_plan {
   int nk = 0;
   int prec = GREEN_FP64;
   int tc = 1;  // tau nodes per contraction chunk
+  int big_stage1 = 1;  // split-BF16 stage-1 kernel: 0 = 64 x 64 tiles, 1 = 192 x 96, 2 = 192 x 64
+  int big_p0 = 1;      // split-BF16 P~0 stage-2 kernel: 1 = 192 x 96 tiles, 2 = 192 x 64
   std::vector<double> tau, wf, wb;
   std::vector<double2> TF_t2w, TF_w2t, TB_t2w, TB_w2t, Emass;
   std::vector<int32_t> kadd, ksub, kneg;  // [q][k]: k+q, k-q; [q]: -q
   // workspace regions
   Region r_TF_t2w, r_TF_w2t, r_TB_t2w, r_TB_w2t, r_Emass, r_wf, r_kadd, r_ksub, r_status, r_scal, r_partial;
-  Region r_P, r_Pw, r_T1, r_T2, r_gam, r_gamT, r_D, r_Sinfn, r_Sign, r_Sw, r_A, r_tr, r_split, r_Vx, r_Ptx;
+  Region r_P, r_Pw, r_T1, r_T2, r_gam, r_gamT, r_D, r_Sinfn, r_Sign, r_Sw, r_A, r_tr, r_split, r_Vx, r_Ptx, r_Gx;
   size_t ws_bytes = 0;
   void* bound_ws = nullptr;
   hipEvent_t ev[kNumEvents]{};
@@ -270,6 +273,11 @@ green::Span span_ws(void* ws, const Region& r) {
 }
 // element type of the contraction intermediates for a plan precision
 int inter_type(int prec) { return prec == GREEN_FP64 ? green::kC64 : (prec == GREEN_FP32 ? green::kC32 : green::kCB16); }
+// address of element `off` of an array of element type `etype`
+const void* eptr(const void* base, int etype, int64_t off) {
+  return static_cast<const char*>(base) + off * green::elem_bytes(etype);
+}
+void* eptr(void* base, int etype, int64_t off) { return static_cast<char*>(base) + off * green::elem_bytes(etype); }
 
 using green::bflat;
 using green::bnone;
@@ -304,42 +312,63 @@ int run_polarization(green_plan* p, const void* V, const void* G, void* P0, void
   const int32_t* hadd = p->kadd.data();
   double2* T1 = at<double2>(ws, p->r_T1);
   double2* T2 = at<double2>(ws, p->r_T2);
-  const green::Span sV = span(V, ex.V), sG = span(G, ex.G), sP = span(P0, ex.P);
+  const green::Span sP = span(P0, ex.P);
   const green::Span sT1 = span_ws(ws, p->r_T1), sT2 = span_ws(ws, p->r_T2);
-  const double2* Vp = static_cast<const double2*>(V);
-  const double2* Gp = static_cast<const double2*>(G);
   double2* Pp = static_cast<double2*>(P0);
   const double w = ns == 1 ? 2.0 : 1.0;
-  // mixed plans: stage 1 in FP32 writing the stage-2 operands in the contraction's storage type
-  const int stage1 = p->prec == GREEN_FP64 ? 0 : 1;
-  const int tt = inter_type(p->prec);
+  // Stage-1 operands: FP64 plans read V and G as given; FP32 plans round them while staging; split-BF16
+  // plans round G once per call and each V slab once per q into the workspace, so that stage 1 runs on
+  // the split-BF16 matrix cores as well.
+  const bool bf = p->prec == GREEN_BF16X3;
+  const int stage1 = p->prec == GREEN_FP64 ? 0 : (bf ? 2 : 1);
+  const int st = bf ? green::kCB16 : green::kC64;  // storage of the stage-1 operands
+  const int tt = inter_type(p->prec);              // storage of the stage-2 operands
+  const void* Gs = G;
+  green::Span sGs = span(G, ex.G);
+  if (bf) {
+    if ((int64_t)p->r_Gx.bytes < ex.G * 8 || (int64_t)p->r_Vx.bytes < 2 * slab * 8) return GREEN_EINVAL;
+    HIP_TRY(green::convert_c64(static_cast<const double2*>(G), at<void>(ws, p->r_Gx), green::kCB16, ex.G, s));
+    Gs = at<void>(ws, p->r_Gx);
+    sGs = span_ws(ws, p->r_Gx);
+  }
   for (int q = 0; q < nk; ++q) {
     const int qn = p->kneg[q];
+    const void *Vq = eptr(V, green::kC64, q * slab), *Vqn = eptr(V, green::kC64, qn * slab);
+    green::Span sVs = span(V, ex.V);
+    if (bf) {
+      void* Vx = at<void>(ws, p->r_Vx);
+      HIP_TRY(green::convert_c64(static_cast<const double2*>(Vq), Vx, green::kCB16, slab, s));
+      if (qn != q) HIP_TRY(green::convert_c64(static_cast<const double2*>(Vqn), eptr(Vx, green::kCB16, slab),
+                                              green::kCB16, slab, s));
+      Vq = Vx;
+      Vqn = qn != q ? eptr(Vx, green::kCB16, slab) : Vx;
+      sVs = span_ws(ws, p->r_Vx);
+    }
     for (int t0 = 0; t0 < ntau; t0 += p->tc) {
       const int tcn = std::min(p->tc, ntau - t0);
       for (int sp = 0; sp < ns; ++sp) {
         // T1[tt][k][(Q,d)][b] = sum_a V^{k,k+q}_{da}(Q) G^{k+q}_{ab}(tau_tt): one GEMM per k with the tau
         // nodes of the chunk folded into N = (tt, b), so each V block is read once per chunk
-        GREEN_TRY(gemm(green::Site::P0_VG, "P0.VG", op(Vp + q * slab, flat(nao), flat(1), bflat(nV)), sV,
-                       op(Gp + ((int64_t)sp * ntau + t0) * nk * nG, flat(nao), two(nao, 1, (int64_t)nk * nG),
-                          btwo(nk, nG, kadd + q * nk, 0, hadd + q * nk)),
-                       sG, T1, sT1, flat(nao), two(nao, 1, (int64_t)nk * nV), bflat(nV), naux * nao, tcn * nao, nao,
-                       nk, cplx(1), cplx(0), s, stage1, tt));
+        GREEN_TRY(gemm(green::Site::P0_VG, "P0.VG", op(Vq, flat(nao), flat(1), bflat(nV), st), sVs,
+                       op(eptr(Gs, st, ((int64_t)sp * ntau + t0) * nk * nG), flat(nao), two(nao, 1, (int64_t)nk * nG),
+                          btwo(nk, nG, kadd + q * nk, 0, hadd + q * nk), st),
+                       sGs, T1, sT1, flat(nao), two(nao, 1, (int64_t)nk * nV), bflat(nV), naux * nao, tcn * nao, nao,
+                       nk, cplx(1), cplx(0), s, stage1, tt, bf ? p->big_stage1 : 0));
         // T2[tt][k][Q'][d][b] = sum_c V^{k+q,k}_{bc}(Q') G^k_{cd}(beta - tau_tt)   (stored transposed in (b, d));
         // N = (tt, d), G(beta - tau) walks the grid backwards
         GREEN_TRY(gemm(green::Site::P0_VGrev, "P0.VGrev",
-                       op(Vp + qn * slab, flat(nao), flat(1), btwo(nk, nV, kadd + q * nk, 0, hadd + q * nk)), sV,
-                       op(Gp + ((int64_t)sp * ntau + (ntau - 1 - t0)) * nk * nG, flat(nao),
-                          two(nao, 1, -(int64_t)nk * nG), btwo(nk, nG, nullptr, 0)),
-                       sG, T2, sT2, two(nao, 1, nG), two(nao, nao, (int64_t)nk * nV), bflat(nV), naux * nao,
-                       tcn * nao, nao, nk, cplx(1), cplx(0), s, stage1, tt));
+                       op(Vqn, flat(nao), flat(1), btwo(nk, nV, kadd + q * nk, 0, hadd + q * nk), st), sVs,
+                       op(eptr(Gs, st, ((int64_t)sp * ntau + (ntau - 1 - t0)) * nk * nG), flat(nao),
+                          two(nao, 1, -(int64_t)nk * nG), btwo(nk, nG, nullptr, 0), st),
+                       sGs, T2, sT2, two(nao, 1, nG), two(nao, nao, (int64_t)nk * nV), bflat(nV), naux * nao,
+                       tcn * nao, nao, nk, cplx(1), cplx(0), s, stage1, tt, bf ? p->big_stage1 : 0));
         // P0[q][t][Q][Q'] (+)= -(w/nk) sum_{k,(d,b)} T1[tt][k][Q][(d,b)] T2[tt][k][Q'][(d,b)]
         GREEN_TRY(gemm(green::Site::P0_Contract, "P0.contract",
                        op(T1, flat(nG), two((int32_t)nG, 1, nV), bflat((int64_t)nk * nV), tt), sT1,
                        op(T2, two((int32_t)nG, 1, nV), flat(nG), bflat((int64_t)nk * nV), tt), sT2,
                        Pp + ((int64_t)q * ntau + t0) * naux * naux, sP, flat(naux), flat(1),
                        bflat((int64_t)naux * naux), naux, naux, (int)(nk * nG), tcn, cplx(-w / nk),
-                       cplx(sp == 0 ? 0.0 : 1.0), s, p->prec, green::kC64, p->prec == GREEN_BF16X3 ? 1 : 0));
+                       cplx(sp == 0 ? 0.0 : 1.0), s, p->prec, green::kC64, bf ? p->big_p0 : 0));
       }
     }
   }
@@ -384,27 +413,47 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
   const int32_t* hsub = p->ksub.data();
   double2* T1 = at<double2>(ws, p->r_T1);
   double2* T2 = at<double2>(ws, p->r_T2);
-  const green::Span sV = span(V, ex.V), sG = span(G, ex.G), sP = span(Pt, ex.P), sS = span(Sig, ex.Sig);
+  const green::Span sP = span(Pt, ex.P), sS = span(Sig, ex.Sig);
   const green::Span sT1 = span_ws(ws, p->r_T1), sT2 = span_ws(ws, p->r_T2);
-  const double2* Vp = static_cast<const double2*>(V);
-  const double2* Gp = static_cast<const double2*>(G);
   const double2* Pp = static_cast<const double2*>(Pt);
   double2* Sp = static_cast<double2*>(Sig);
   if (!green::dryrun()) HIP_TRY(green::launch_zero(Sp, ex.Sig, s));
+  // FP32 plans round the V slab of X = P~^T V to FP32 once per q and round the other operands while
+  // staging; split-BF16 plans round G once per call, both V slabs of a q once, and keep X and Y in split
+  // BF16, so every stage runs on the split-BF16 matrix cores.
   const bool mixed = p->prec != GREEN_FP64;
-  const int vt = inter_type(p->prec);           // storage of the rounded V slab
-  const int xt = mixed ? green::kC32 : green::kC64;  // X and Y intermediates
-  const int stage = mixed ? 1 : 0;
+  const bool bf = p->prec == GREEN_BF16X3;
+  const int vt = inter_type(p->prec);                                          // rounded V slabs
+  const int xt = bf ? green::kCB16 : (mixed ? green::kC32 : green::kC64);      // X and Y
+  const int gt = bf ? green::kCB16 : green::kC64;                              // G and the V of stage 3
+  const int stage = p->prec == GREEN_FP64 ? 0 : (bf ? 2 : 1);
   void* Vx = at<void>(ws, p->r_Vx);
   const green::Span sVx = span_ws(ws, p->r_Vx);
-  const bool bf = p->prec == GREEN_BF16X3;
   void* Ptx = at<void>(ws, p->r_Ptx);
   const green::Span sPtx = span_ws(ws, p->r_Ptx);
+  const void* Gs = G;
+  green::Span sGs = span(G, ex.G);
+  if (bf) {
+    if ((int64_t)p->r_Gx.bytes < ex.G * 8) return GREEN_EINVAL;
+    HIP_TRY(green::convert_c64(static_cast<const double2*>(G), at<void>(ws, p->r_Gx), green::kCB16, ex.G, s));
+    Gs = at<void>(ws, p->r_Gx);
+    sGs = span_ws(ws, p->r_Gx);
+  }
   for (int q = 0; q < nk; ++q) {
     const int qn = p->kneg[q];
+    const void* Vqn = eptr(V, green::kC64, qn * slab);  // V^{k,k-q}: X = P~^T V
+    const void* Vq = eptr(V, green::kC64, q * slab);    // V^{k-q,k}: Sigma += Y V
+    green::Span sVa = span(V, ex.V), sVb = span(V, ex.V);
     if (mixed) {
-      if ((int64_t)p->r_Vx.bytes < slab * green::elem_bytes(vt)) return GREEN_EINVAL;
-      HIP_TRY(green::convert_c64(Vp + qn * slab, Vx, vt, slab, s));
+      if ((int64_t)p->r_Vx.bytes < (bf ? 2 : 1) * slab * green::elem_bytes(vt)) return GREEN_EINVAL;
+      HIP_TRY(green::convert_c64(static_cast<const double2*>(Vqn), Vx, vt, slab, s));
+      Vqn = Vx;
+      sVa = sVx;
+      if (bf) {
+        if (q != qn) HIP_TRY(green::convert_c64(static_cast<const double2*>(Vq), eptr(Vx, vt, slab), vt, slab, s));
+        Vq = q != qn ? eptr(Vx, vt, slab) : Vx;
+        sVb = sVx;
+      }
     }
     if (bf) {
       // P~^q(tau)^T rounded to split BF16 for the large-tile kernel (K-contiguous rows)
@@ -415,27 +464,24 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
       const int tcn = std::min(p->tc, ntau - t0);
       // X[tt][k][Q'][(i,a)] = sum_Q P~^q_{QQ'}(tau) V^{k,k-q}_{ia}(Q)
       GREEN_TRY(gemm(green::Site::Sig_PV, "Sigma.PV",
-                     bf ? op(static_cast<char*>(Ptx) + (int64_t)t0 * nP * 8, flat(naux), flat(1), bflat(nP),
-                             green::kCB16)
+                     bf ? op(eptr(Ptx, green::kCB16, (int64_t)t0 * nP), flat(naux), flat(1), bflat(nP), green::kCB16)
                         : op(Pp + ((int64_t)q * ntau + t0) * nP, flat(1), flat(naux), bflat(nP)),
-                     bf ? sPtx : sP,
-                     mixed ? op(Vx, flat(nG), two((int32_t)nG, 1, nV), bnone(), vt)
-                           : op(Vp + qn * slab, flat(nG), two((int32_t)nG, 1, nV), bnone()),
-                     mixed ? sVx : sV, T1, sT1, flat(nG), two((int32_t)nG, 1, nV), bflat((int64_t)nk * nV), naux,
+                     bf ? sPtx : sP, op(Vqn, flat(nG), two((int32_t)nG, 1, nV), bnone(), mixed ? vt : green::kC64),
+                     sVa, T1, sT1, flat(nG), two((int32_t)nG, 1, nV), bflat((int64_t)nk * nV), naux,
                      (int)(nk * nG), naux, tcn, cplx(1), cplx(0), s, p->prec, xt, bf ? 2 : 0));
       for (int sp = 0; sp < ns; ++sp) {
         // Y[tt][k][(Q',i)][b] = sum_a X[tt][k][(Q',i)][a] G^{k-q}_{ab}(tau)
         GREEN_TRY(gemm(green::Site::Sig_XG, "Sigma.XG", op(T1, flat(nao), flat(1), bflat(nV), xt), sT1,
-                       op(Gp + ((int64_t)sp * ntau + t0) * nk * nG, flat(nao), flat(1),
-                          btwo(nk, nG, ksub + q * nk, (int64_t)nk * nG, hsub + q * nk)),
-                       sG, T2, sT2, flat(nao), flat(1), bflat(nV), naux * nao, nao, nao, tcn * nk, cplx(1), cplx(0),
+                       op(eptr(Gs, gt, ((int64_t)sp * ntau + t0) * nk * nG), flat(nao), flat(1),
+                          btwo(nk, nG, ksub + q * nk, (int64_t)nk * nG, hsub + q * nk), gt),
+                       sGs, T2, sT2, flat(nao), flat(1), bflat(nV), naux * nao, nao, nao, tcn * nk, cplx(1), cplx(0),
                        s, stage, xt));
         // Sigma[s][t][k][i][j] += -(1/nk) sum_{(Q',b)} Y[tt][k][Q'][i][b] V^{k-q,k}_{bj}(Q'): one GEMM per k
         // with the tau nodes folded into M = (tt, i), so each V block is read once per chunk
         GREEN_TRY(gemm(green::Site::Sig_YV, "Sigma.YV",
                        op(T2, two(nao, nao, (int64_t)nk * nV), two(nao, 1, nG), bflat(nV), xt), sT2,
-                       op(Vp + q * slab, two(nao, nao, nG), flat(1), btwo(nk, nV, ksub + q * nk, 0, hsub + q * nk)),
-                       sV, Sp + ((int64_t)sp * ntau + t0) * nk * nG, sS, two(nao, nao, (int64_t)nk * nG), flat(1),
+                       op(Vq, two(nao, nao, nG), flat(1), btwo(nk, nV, ksub + q * nk, 0, hsub + q * nk), gt), sVb,
+                       Sp + ((int64_t)sp * ntau + t0) * nk * nG, sS, two(nao, nao, (int64_t)nk * nG), flat(1),
                        bflat(nG), tcn * nao, nao, naux * nao, nk, cplx(-1.0 / nk), cplx(1.0), s, stage,
                        green::kC64));
       }
@@ -771,10 +817,13 @@ int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, 
   const int64_t nao = d.nao, naux = d.naux, ns = d.nspin;
   const int64_t nG = nao * nao, nV = naux * nG, nP = naux * naux;
   if (chunk_bytes == 0) chunk_bytes = (size_t)8 << 30;
-  const size_t per_t = (size_t)2 * nk * nV * sizeof(double2);
+  const size_t isz = prec == GREEN_FP64 ? 16 : 8;  // bytes of a stored contraction intermediate
+  const size_t per_t = (size_t)2 * nk * nV * isz;
   int tc = (int)std::max<size_t>(1, chunk_bytes / per_t);
   tc = std::min(tc, ntau);
   p->tc = tc;
+  if (const char* e = std::getenv("GREEN_STAGE1_BIG")) p->big_stage1 = std::atoi(e);
+  if (const char* e = std::getenv("GREEN_P0_BIG")) p->big_p0 = std::atoi(e);
   size_t off = 0;
   auto take = [&](Region& r, size_t bytes) {
     r.off = off;
@@ -794,9 +843,9 @@ int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, 
   take(p->r_partial, 1024 * 8);
   take(p->r_P, (size_t)nk * ntau * nP * 16);
   take(p->r_Pw, (size_t)nk * nwb * nP * 16);
-  const size_t tbuf = std::max<size_t>((size_t)tc * nk * nV * 16, (size_t)ns * ntau * nk * nG * 16);
+  const size_t tbuf = std::max<size_t>((size_t)tc * nk * nV * isz, (size_t)ns * ntau * nk * nG * 16);
   take(p->r_T1, tbuf);
-  take(p->r_T2, std::max<size_t>((size_t)tc * nk * nV * 16, (size_t)nk * nV * 16));
+  take(p->r_T2, std::max<size_t>((size_t)tc * nk * nV * isz, (size_t)nk * nV * 16));
   take(p->r_gam, (size_t)ns * nk * nG * 16);
   take(p->r_gamT, (size_t)ns * nk * nG * 16);
   take(p->r_D, (size_t)naux * 16);
@@ -806,7 +855,8 @@ int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, 
   take(p->r_A, (size_t)ns * nwf * nk * nG * 16);
   take(p->r_tr, (size_t)std::max<int64_t>(ns * nwf * nk, ns * ntau * nk) * 16);
   take(p->r_split, (size_t)1 << 30);
-  take(p->r_Vx, prec == GREEN_FP64 ? 0 : (size_t)nk * nV * 8);
+  take(p->r_Vx, prec == GREEN_FP64 ? 0 : (size_t)(prec == GREEN_BF16X3 ? 2 : 1) * nk * nV * 8);
+  take(p->r_Gx, prec == GREEN_BF16X3 ? (size_t)ns * ntau * nk * nG * 8 : 0);
   take(p->r_Ptx, prec == GREEN_BF16X3 ? (size_t)ntau * nP * 8 : 0);
   p->ws_bytes = off;
   *out = p;

@@ -586,13 +586,14 @@ __global__ __launch_bounds__(256) void zgemm_mx_kernel(const ZGemm g) {
 }
 
 // ------------------------------------------------------------------------------------------------
-// Large-tile split-BF16 variant for the two dominant contractions.  512 threads (8 waves, 4 along M x
-// 2 along N), each wave owning FM x FN blocks of 16 x 16, so a tile is (64 FM) x (32 FN): with FM = 3,
-// FN = 3 a 192 x 96 tile covers naux <= 192 along M and half of it along N, so each K slice of the
-// operands is fetched once (A) or twice (B) instead of once per 64-wide tile.  (A 192 x 192 tile needs
-// 144 accumulator registers per lane and spills.)  Operands are stored pre-split (kCB16) and go to LDS unchanged.  A is K-contiguous;
-// B is K-contiguous or N-contiguous.  Workgroups are renumbered so that each XCD (8 on MI355X, blocks
-// dispatched round-robin) processes a contiguous range of tiles, whose operands then share its L2.
+// Large-tile split-BF16 variant for the dominant contractions.  512 threads (8 waves, 4 along M x 2
+// along N), each wave owning FM x FN blocks of 16 x 16, so a tile is (64 FM) x (32 FN).  Operands are
+// stored pre-split (kCB16) and go to LDS unchanged, 32 complex K per stage (two MFMA K steps), double
+// buffered (147 KB of LDS at 192 x 96).  The LDS rows are 128 bytes per plane with the 16-byte chunks
+// XOR-swizzled by row, so the fragment reads of 16 rows at one K offset hit distinct banks.  A is
+// K-contiguous with a flat row map; B is K-contiguous with a flat column map, or N-contiguous with a flat
+// K map.  Workgroups are renumbered so that each XCD (8 on MI355X, blocks dispatched round-robin)
+// processes a contiguous range of tiles, whose operands then share its L2.
 constexpr int kXcd = 8;
 
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t n) {
@@ -601,14 +602,43 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t n) {
   return (b % kXcd) * (n / kXcd) + b / kXcd;
 }
 
-template <int FM, int FN, Site SITE>
+// Offset of the K index of a staged element under a two-level map, advanced by a fixed step with no
+// multiplications: the step and wrap increments are computed once per launch.
+struct KCur {
+  int32_t k, lo;
+  int64_t off;
+  __device__ __forceinline__ void init(const IdxMap& m, int32_t k0) {
+    k = k0;
+    if (m.ext == kFlat) {
+      lo = k0;
+      off = (int64_t)k0 * m.s_in;
+    } else {
+      const int32_t hi = k0 / m.ext;
+      lo = k0 - hi * m.ext;
+      off = (int64_t)lo * m.s_in + (int64_t)hi * m.s_out;
+    }
+  }
+  __device__ __forceinline__ void step(const IdxMap& m, int32_t d, int64_t d_in, int64_t wrap) {
+    k += d;
+    lo += d;
+    off += d_in;
+    while (lo >= m.ext) {
+      lo -= m.ext;
+      off += wrap;
+    }
+  }
+};
+
+// word index of (row r, complex k) in a 32-word LDS plane row with swizzled 16-byte chunks
+__device__ __forceinline__ int bt_word(int r, int k) { return r * 32 + ((((k >> 2) ^ (r >> 1)) & 7) << 2) + (k & 3); }
+
+template <int FM, int FN, bool BNC, Site SITE>
 __global__ __launch_bounds__(512) void zgemm_bt_kernel(const ZGemm g) {
-  constexpr int BM = 64 * FM, BN = 32 * FN, BK = 16;
-  constexpr int PW = BK + 4;  // words per LDS row (hi or lo plane), padded
+  constexpr int BM = 64 * FM, BN = 32 * FN, BK = 32;
   constexpr int EA = BM * BK / 512;
   constexpr int EB = BN * BK / 512;
-  __shared__ uint32_t As[2][2][BM * PW];
-  __shared__ uint32_t Bs[2][2][BN * PW];
+  __shared__ uint32_t As[2][2][BM * 32];
+  __shared__ uint32_t Bs[2][2][BN * 32];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -630,63 +660,84 @@ __global__ __launch_bounds__(512) void zgemm_bt_kernel(const ZGemm g) {
 
   const uint2* __restrict__ Ap = reinterpret_cast<const uint2*>(g.A.p) + batch_off(g.A.b, batch);
   const uint2* __restrict__ Bp = reinterpret_cast<const uint2*>(g.B.p) + batch_off(g.B.b, batch);
-  const bool b_kc = !(g.B.c.s_in == 1 && g.B.c.ext >= 16);
-  int a_m[EA];
-  int64_t a_ro[EA];
-  bool a_ok[EA];
+  constexpr bool b_kc = !BNC;  // BNC: B is N-contiguous, else K-contiguous
+  // Rows (columns) beyond M (N) read row M-1 (column N-1) and lanes whose K index runs past the slice
+  // read the slice's first K index: every load stays in bounds and carries no branch; such elements
+  // are zeroed when staged.
   const int a_k = tid & (BK - 1);
-#pragma unroll
-  for (int e = 0; e < EA; ++e) {
-    a_m[e] = (tid >> 4) + 32 * e;
-    const int gm = m0 + a_m[e];
-    a_ok[e] = gm < g.M;
-    a_ro[e] = a_ok[e] ? map_idx(g.A.r, gm) : 0;
-  }
+  const int a_r0 = tid >> 5;  // rows a_r0 + 16 e
+  // K-contiguous B: like A (32 consecutive K of 16 columns per wave).  N-contiguous B: a wave stages
+  // 16 consecutive columns at 4 consecutive K, so its LDS writes fall on distinct banks.
   int b_n[EB], b_k[EB];
-  int64_t b_co[EB];
-  bool b_ok[EB];
 #pragma unroll
   for (int e = 0; e < EB; ++e) {
-    if (b_kc) {
+    if constexpr (b_kc) {
       b_k[e] = tid & (BK - 1);
-      b_n[e] = (tid >> 4) + 32 * e;
+      b_n[e] = (tid >> 5) + 16 * e;
     } else {
-      b_n[e] = tid % BN;
-      b_k[e] = tid / BN + (512 / BN) * e;
+      const int c = wave * EB + e;
+      b_n[e] = 16 * (c % (BN / 16)) + (lane & 15);
+      b_k[e] = 4 * (c / (BN / 16)) + (lane >> 4);
     }
-    const int gn = n0 + b_n[e];
-    b_ok[e] = gn < g.N;
-    b_co[e] = b_ok[e] ? map_idx(g.B.c, gn) : 0;
   }
-  KPos apos, bpos[EB];
-  apos.init(g.A.c, kbeg + a_k);
+  // flat maps: A rows, B columns (K-contiguous B) or B K rows (N-contiguous B)
+  const int64_t a_rs = g.A.r.s_in;
+  const int64_t b_cs = g.B.c.s_in;
+  int64_t b_col[BNC ? EB : 1];  // N-contiguous B: column offsets
 #pragma unroll
-  for (int e = 0; e < EB; ++e) bpos[e].init(g.B.r, kbeg + b_k[e]);
+  for (int e = 0; e < (BNC ? EB : 1); ++e) b_col[e] = BNC ? map_idx(g.B.c, min(n0 + b_n[e], g.N - 1)) : 0;
+  const int64_t a_din = (int64_t)BK * g.A.c.s_in, a_wrap = g.A.c.s_out - (int64_t)g.A.c.ext * g.A.c.s_in;
+  const int64_t b_din = (int64_t)BK * g.B.r.s_in, b_wrap = g.B.r.s_out - (int64_t)g.B.r.ext * g.B.r.s_in;
+  KCur acur, bcur;
+  acur.init(g.A.c, kbeg + a_k);
+  // K-contiguous B: every element sits at this K; N-contiguous B: element e at this K + b_k[e] - (lane >> 4)
+  bcur.init(g.B.r, kbeg + (b_kc ? b_k[0] : (lane >> 4)));
+  const int64_t a_first = map_idx(g.A.c, kbeg), b_first = map_idx(g.B.r, kbeg);
   const uint32_t aflip = g.A.conj ? 0x80000000u : 0u, bflip = g.B.conj ? 0x80000000u : 0u;
+  const int nkt = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
 
   uint2 ra[EA], rb[EB];
+  uint32_t okm = 0;  // bit 0: A elements inside the K range; bit 1 + e: B element e
   auto load = [&]() {
-    const bool ak = apos.k < kend;
-    const int64_t aoff = apos.off(g.A.c);
+    const bool ak = acur.k < kend;
+    const int64_t ao = ak ? acur.off : a_first;
+    uint32_t m = ak ? 1u : 0u;
 #pragma unroll
-    for (int e = 0; e < EA; ++e) ra[e] = (a_ok[e] && ak) ? Ap[a_ro[e] + aoff] : make_uint2(0u, 0u);
-    apos.step(g.A.c, BK);
+    for (int e = 0; e < EA; ++e) ra[e] = Ap[(int64_t)min(m0 + a_r0 + 16 * e, g.M - 1) * a_rs + ao];
+    if constexpr (b_kc) {
+      const bool bk = bcur.k < kend;
+      const int64_t bo = bk ? bcur.off : b_first;
 #pragma unroll
-    for (int e = 0; e < EB; ++e) {
-      rb[e] = (b_ok[e] && bpos[e].k < kend) ? Bp[bpos[e].off(g.B.r) + b_co[e]] : make_uint2(0u, 0u);
-      bpos[e].step(g.B.r, BK);
+      for (int e = 0; e < EB; ++e) rb[e] = Bp[bo + (int64_t)min(n0 + b_n[e], g.N - 1) * b_cs];
+      m |= bk ? (((1u << EB) - 1u) << 1) : 0u;
+    } else {
+      // N-contiguous B: K rows bcur.k + (b_k[e] - (lane >> 4)) under a flat K map
+#pragma unroll
+      for (int e = 0; e < EB; ++e) {
+        const int dk = b_k[e] - (lane >> 4);
+        const bool bk = bcur.k + dk < kend;
+        rb[e] = Bp[(bk ? bcur.off + (int64_t)dk * g.B.r.s_in : b_first) + b_col[e]];
+        m |= bk ? (2u << e) : 0u;
+      }
     }
+    okm = m;
+    acur.step(g.A.c, BK, a_din, a_wrap);
+    bcur.step(g.B.r, BK, b_din, b_wrap);
   };
   auto stage = [&](int buf) {
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
-      As[buf][0][a_m[e] * PW + a_k] = ra[e].x ^ aflip;
-      As[buf][1][a_m[e] * PW + a_k] = ra[e].y ^ aflip;
+      const bool keep = (m0 + a_r0 + 16 * e < g.M) && (okm & 1u);
+      const int w = bt_word(a_r0 + 16 * e, a_k);
+      As[buf][0][w] = keep ? (ra[e].x ^ aflip) : 0u;
+      As[buf][1][w] = keep ? (ra[e].y ^ aflip) : 0u;
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
-      Bs[buf][0][b_n[e] * PW + b_k[e]] = rb[e].x ^ bflip;
-      Bs[buf][1][b_n[e] * PW + b_k[e]] = rb[e].y ^ bflip;
+      const bool keep = (n0 + b_n[e] < g.N) && (okm & (2u << e));
+      const int w = bt_word(b_n[e], b_k[e]);
+      Bs[buf][0][w] = keep ? (rb[e].x ^ bflip) : 0u;
+      Bs[buf][1][w] = keep ? (rb[e].y ^ bflip) : 0u;
     }
   };
 
@@ -700,42 +751,54 @@ __global__ __launch_bounds__(512) void zgemm_bt_kernel(const ZGemm g) {
     }
   const int wm = wave & 3, wn = wave >> 2;
   const int rowb = wm * 16 * FM, colb = wn * 16 * FN;
-  const int nkt = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
-  load();
-  stage(0);
-  __syncthreads();
-  const int koff = 4 * (lane >> 4);
-  for (int it = 0; it < nkt; ++it) {
-    const int buf = it & 1;
-    if (it + 1 < nkt) load();
-    u4 bh[FN], bl[FN];
-#pragma unroll
-    for (int j = 0; j < FN; ++j) {
-      const int col = colb + 16 * j + (lane & 15);
-      bh[j] = *reinterpret_cast<const u4*>(&Bs[buf][0][col * PW + koff]);
-      bl[j] = *reinterpret_cast<const u4*>(&Bs[buf][1][col * PW + koff]);
-    }
-#pragma unroll
-    for (int i = 0; i < FM; ++i) {
-      const int row = rowb + 16 * i + (lane & 15);
-      const u4 ah = *reinterpret_cast<const u4*>(&As[buf][0][row * PW + koff]);
-      const u4 al = *reinterpret_cast<const u4*>(&As[buf][1][row * PW + koff]);
-      const bf8 anh = as_bf8(neg_im(ah)), anl = as_bf8(neg_im(al));
-      const bf8 aph = as_bf8(ah), apl = as_bf8(al);
+  auto compute = [&](int buf, int sub) {
+    {
+      const int kq = 16 * sub + 4 * (lane >> 4);  // first complex K of this lane's 8 bf16
+      u4 bh[FN], bl[FN];
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
-        const bf8 bph = as_bf8(bh[j]), bpl = as_bf8(bl[j]);
-        const bf8 bsh = as_bf8(swap_re_im(bh[j])), bsl = as_bf8(swap_re_im(bl[j]));
-        acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(anh, bph, acc_re[i][j], 0, 0, 0);
-        acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aph, bsh, acc_im[i][j], 0, 0, 0);
-        acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(anh, bpl, acc_re[i][j], 0, 0, 0);
-        acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aph, bsl, acc_im[i][j], 0, 0, 0);
-        acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(anl, bph, acc_re[i][j], 0, 0, 0);
-        acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(apl, bsh, acc_im[i][j], 0, 0, 0);
+        const int w = bt_word(colb + 16 * j + (lane & 15), kq);
+        bh[j] = *reinterpret_cast<const u4*>(&Bs[buf][0][w]);
+        bl[j] = *reinterpret_cast<const u4*>(&Bs[buf][1][w]);
+      }
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        const int w = bt_word(rowb + 16 * i + (lane & 15), kq);
+        const u4 ah = *reinterpret_cast<const u4*>(&As[buf][0][w]);
+        const u4 al = *reinterpret_cast<const u4*>(&As[buf][1][w]);
+        const bf8 anh = as_bf8(neg_im(ah)), anl = as_bf8(neg_im(al));
+        const bf8 aph = as_bf8(ah), apl = as_bf8(al);
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const bf8 bph = as_bf8(bh[j]), bpl = as_bf8(bl[j]);
+          const bf8 bsh = as_bf8(swap_re_im(bh[j])), bsl = as_bf8(swap_re_im(bl[j]));
+          acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(anh, bph, acc_re[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aph, bsh, acc_im[i][j], 0, 0, 0);
+          acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(anh, bpl, acc_re[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aph, bsl, acc_im[i][j], 0, 0, 0);
+          acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(anl, bph, acc_re[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(apl, bsh, acc_im[i][j], 0, 0, 0);
+        }
       }
     }
-    if (it + 1 < nkt) stage(buf ^ 1);
+  };
+
+  // The next step's elements are staged into the other LDS buffer between the two MFMA K steps of the
+  // current one (that buffer was last read before the previous barrier), and the loads of the step
+  // after are issued right behind, so every load has a full iteration to land.
+  if (nkt > 0) {
+    load();
+    stage(0);
     __syncthreads();
+    if (nkt > 1) load();
+    for (int it = 0; it < nkt; ++it) {
+      const int buf = it & 1;
+      compute(buf, 0);
+      if (it + 1 < nkt) stage(buf ^ 1);
+      if (it + 2 < nkt) load();
+      compute(buf, 1);
+      __syncthreads();
+    }
   }
 
   if (g.ksplit > 1) {
@@ -940,6 +1003,11 @@ static bool big_ok(const ZGemm& g) {
   if (!(g.A.c.s_in == 1 && g.A.c.ext >= 16)) return false;
   const bool b_nc = g.B.c.s_in == 1 && g.B.c.ext >= 16;
   if (!b_nc && g.B.r.s_in != 1) return false;
+  // row offsets of A, column offsets of a K-contiguous B and K offsets of an N-contiguous B are computed
+  // as index * stride
+  if (g.A.r.ext != kFlat) return false;
+  if (!b_nc && g.B.c.ext != kFlat) return false;
+  if (b_nc && g.B.r.ext != kFlat) return false;
   return true;
 }
 
@@ -980,17 +1048,32 @@ hipError_t zgemm(const ZGemm& g, hipStream_t s) {
     }                                                                    \
     break;
   if (g.prec == 2 && big_ok(g)) {
+    const bool bnc = g.B.c.s_in == 1 && g.B.c.ext >= 16;
+#define GREEN_BT(FM, FN, S)                                                         \
+  if (bnc)                                                                          \
+    zgemm_bt_kernel<FM, FN, true, Site::S><<<grid, dim3(512), 0, s>>>(g);           \
+  else                                                                              \
+    zgemm_bt_kernel<FM, FN, false, Site::S><<<grid, dim3(512), 0, s>>>(g);
     if (g.big == 1) {
-      if (g.site == Site::P0_Contract)
-        zgemm_bt_kernel<3, 3, Site::P0_Contract><<<grid, dim3(512), 0, s>>>(g);
-      else
-        zgemm_bt_kernel<3, 3, Site::Generic><<<grid, dim3(512), 0, s>>>(g);
+      if (g.site == Site::P0_Contract) {
+        GREEN_BT(3, 3, P0_Contract)
+      } else {
+        GREEN_BT(3, 3, Generic)
+      }
     } else {
-      if (g.site == Site::Sig_PV)
-        zgemm_bt_kernel<3, 2, Site::Sig_PV><<<grid, dim3(512), 0, s>>>(g);
-      else
-        zgemm_bt_kernel<3, 2, Site::Generic><<<grid, dim3(512), 0, s>>>(g);
+      if (g.site == Site::Sig_PV) {
+        GREEN_BT(3, 2, Sig_PV)
+      } else if (g.site == Site::P0_Contract) {
+        GREEN_BT(3, 2, P0_Contract)
+      } else if (g.site == Site::P0_VG) {
+        GREEN_BT(3, 2, P0_VG)
+      } else if (g.site == Site::P0_VGrev) {
+        GREEN_BT(3, 2, P0_VGrev)
+      } else {
+        GREEN_BT(3, 2, Generic)
+      }
     }
+#undef GREEN_BT
   } else if (g.prec == 1 || g.prec == 2) {
 #define GREEN_MX(MODE, S)                                                                       \
   switch (shape) {                                                                              \
@@ -1011,12 +1094,8 @@ hipError_t zgemm(const ZGemm& g, hipStream_t s) {
   }
     if (g.prec == 1) {
       GREEN_MX_SITE(1)
-    } else if (g.site == Site::P0_Contract) {
-      GREEN_MX(2, P0_Contract)
-    } else if (g.site == Site::Sig_PV) {
-      GREEN_MX(2, Sig_PV)
     } else {
-      GREEN_MX(2, Generic)
+      GREEN_MX_SITE(2)
     }
 #undef GREEN_MX_SITE
 #undef GREEN_MX
