@@ -184,6 +184,56 @@ int green_dyson(green_plan* plan, const void* H0, const void* S, const void* Sin
 int green_gw_iterate(green_plan* plan, const void* V, const void* H0, const void* S, void* G, void* Sinf, void* Sigma,
                      double* mu, double n_target, double alpha, green_report* report, void* ws, void* stream);
 
+/* Plan options (green_plan_set_option):
+ *   GREEN_OPT_TUNE  1: autotune.  Every contraction shape met on later calls is run once with each of
+ *                   its candidate kernels (tile shape, large-tile kernel, split-K count; every candidate
+ *                   computes the same contraction, differing only in summation order), timed with HIP
+ *                   events, and the fastest is kept for all further calls of that shape on this plan.
+ *                   Synchronises `stream` once per shape when its last candidate has run.
+ *                   2: forget earlier choices and tune again.  0: stop tuning (choices are kept).
+ *   GREEN_OPT_GRAPH 1: green_gw_iterate captures its Sigma evaluation (Hartree-Fock, polarization,
+ *                   screening, self-energy, mixing) into a HIP graph on first use and replays it while
+ *                   (V, G, Sinf, Sigma, ws, alpha) stay the same; not while tuning is pending and not
+ *                   on the default (null) stream, which cannot be captured: there it runs eagerly.  The
+ *                   per-stage times are then not separated: ms[0] holds the replay, ms[1..4] are 0.
+ * Returns GREEN_EINVAL for an unknown option or value. */
+#define GREEN_OPT_TUNE 1
+#define GREEN_OPT_GRAPH 2
+int green_plan_set_option(green_plan* plan, int option, int value);
+
+/* Text table of the autotuner's decisions (one line per contraction shape) into buf (host, len bytes,
+ * NUL-terminated; GREEN_ENOMEM when truncated). */
+int green_plan_tuning_report(const green_plan* plan, char* buf, size_t len);
+
+/* One system of a batched iteration: the arguments of green_gw_iterate (device pointers; mu host,
+ * in/out) and that system's own workspace of green_workspace_bytes(plan) bytes. */
+typedef struct {
+  const void* V;
+  const void* H0;
+  const void* S;
+  void* G;
+  void* Sinf;
+  void* Sigma;
+  double mu;
+  double n_target;
+  void* ws;
+} green_system;
+
+/* Device bytes of the descriptor tables of a batched iteration over these plans. */
+size_t green_batch_workspace_bytes(int nsys, green_plan* const* plans);
+
+/* One self-consistent iteration (as green_gw_iterate) of nsys independent systems of any sizes, each
+ * with its own plan and workspace.  The Sigma evaluations of all systems are issued together: the
+ * r-th contraction of every system goes into one persistent launch per kernel variant (a grid that
+ * walks the concatenated tile ranges of all of them), so small systems share the GPU instead of
+ * running one after another; then every system's Dyson step, chemical potential and energy follow.
+ * Results equal those of green_gw_iterate on each system with the same kernel choices.
+ * batch_ws: device buffer of batch_ws_bytes >= green_batch_workspace_bytes(nsys, plans) bytes.
+ * reports: nsys entries; ms[7] of each holds the Sigma evaluation time of the whole batch.
+ * Synchronises `stream`.  GREEN_EINVAL when two systems share a plan or a workspace. */
+int green_gw_iterate_batched(int nsys, green_plan* const* plans, green_system* systems, double alpha,
+                             green_report* reports, void* batch_ws, size_t batch_ws_bytes, void* stream);
+
 /* Human-readable text for a green_status. */
 const char* green_strerror(int status);
 

@@ -56,9 +56,19 @@ class Report(ctypes.Structure):
         return d
 
 
+class System(ctypes.Structure):
+    _fields_ = [("V", ctypes.c_void_p), ("H0", ctypes.c_void_p), ("S", ctypes.c_void_p), ("G", ctypes.c_void_p),
+                ("Sinf", ctypes.c_void_p), ("Sigma", ctypes.c_void_p), ("mu", ctypes.c_double),
+                ("n_target", ctypes.c_double), ("ws", ctypes.c_void_p)]
+
+
+OPT_TUNE = 1
+OPT_GRAPH = 2
+
 EXPORTS = ["green_plan_create", "green_plan_destroy", "green_workspace_bytes", "green_gw_polarization",
            "green_gw_screen", "green_gw_selfenergy", "green_hf_static", "green_dyson", "green_gw_iterate",
-           "green_strerror"]
+           "green_plan_set_option", "green_plan_tuning_report", "green_batch_workspace_bytes",
+           "green_gw_iterate_batched", "green_strerror"]
 
 
 def _load():
@@ -88,6 +98,15 @@ def _load():
     lib.green_gw_iterate.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(dbl), dbl, dbl,
                                      ctypes.POINTER(Report), vp, vp]
     lib.green_gw_iterate.restype = i32
+    lib.green_plan_set_option.argtypes = [vp, i32, i32]
+    lib.green_plan_set_option.restype = i32
+    lib.green_plan_tuning_report.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
+    lib.green_plan_tuning_report.restype = i32
+    lib.green_batch_workspace_bytes.argtypes = [i32, ctypes.POINTER(vp)]
+    lib.green_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.green_gw_iterate_batched.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(System), dbl,
+                                             ctypes.POINTER(Report), vp, ctypes.c_size_t, vp]
+    lib.green_gw_iterate_batched.restype = i32
     lib.green_strerror.argtypes = [i32]
     lib.green_strerror.restype = ctypes.c_char_p
     return lib

@@ -1,6 +1,10 @@
 // C ABI of libgreen_gw: plan, workspace layout and the orchestration of one
 // self-consistent GW iteration (Sec. 2.3) from the batched kernels.
+#include <algorithm>
 #include <cmath>
+#include <functional>
+#include <map>
+#include <string>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -24,6 +28,25 @@ struct Region {
   size_t off = 0, bytes = 0;
 };
 
+// Autotuner: a contraction shape is identified by its call site, extents, arithmetic and element types;
+// a candidate is a kernel tile choice plus a split-K count.
+struct TuneKey {
+  int32_t v[11];
+  bool operator<(const TuneKey& o) const { return std::lexicographical_compare(v, v + 11, o.v, o.v + 11); }
+};
+struct TuneCand {
+  int32_t shape, big, ksplit;
+};
+struct TuneEntry {
+  std::vector<TuneCand> cands;
+  std::vector<float> ms;  // time of each candidate's trial launch
+  std::vector<hipEvent_t> ev;
+  int trial = 0;
+  bool done = false;
+  int chosen = 0;
+  int64_t calls = 0;
+};
+
 }  // namespace
 
 struct green_plan {
@@ -44,6 +67,16 @@ struct green_plan {
   hipEvent_t ev[kNumEvents]{};
   bool events = false;
   void* clock = nullptr;  // KernelClock, created with the events
+  // options
+  int tune = 0;       // time the candidate kernels of every new contraction shape on its next calls
+  int use_graph = 0;  // replay the Sigma evaluation of green_gw_iterate from a captured HIP graph
+  std::map<TuneKey, TuneEntry> tuner;
+  int64_t nops = 0;  // contractions of one Sigma evaluation
+  // captured Sigma evaluation and the arguments it was captured with
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  const void* gargs[6] = {};
+  double galpha = 0.0;
 };
 
 namespace {
@@ -130,6 +163,9 @@ struct SplitBuf {
   int prec = 0;     // arithmetic of the P~0 stage-2 and Sigma~ stage-1 contractions
 };
 thread_local SplitBuf tl_split;
+// plan of the current call (autotuner state) and whether launches are being captured into a graph
+thread_local green_plan* tl_plan = nullptr;
+thread_local bool tl_capturing = false;
 
 int ensure_bound(green_plan* p, void* ws, hipStream_t s) {
   tl_split.ptr = reinterpret_cast<double2*>(static_cast<char*>(ws) + p->r_split.off);
@@ -199,6 +235,28 @@ struct KernelClock {
 thread_local KernelClock* tl_clock = nullptr;
 
 
+// Recording: while tl_rec is set, gemm() and aux() append the launches of a call to a list instead of
+// issuing them (the batched iteration replays the lists of several systems round by round).
+struct Op {
+  bool is_gemm = false;
+  ZGemm g{};
+  std::function<hipError_t(hipStream_t)> aux;
+};
+thread_local std::vector<Op>* tl_rec = nullptr;
+
+// An auxiliary (non-GEMM) launch: issued now, or recorded.
+template <class F>
+int aux(hipStream_t s, F&& f) {
+  if (tl_rec) {
+    Op o;
+    o.aux = std::function<hipError_t(hipStream_t)>(std::forward<F>(f));
+    tl_rec->push_back(std::move(o));
+    return GREEN_OK;
+  }
+  if (green::dryrun()) return GREEN_OK;
+  return hip_status(f(s));
+}
+
 // Split the K range when the output tiles alone cannot fill the GPU (256 CUs): aim for ~2048
 // workgroups, keep every slice at least 64 deep, and fit the partial sums into the scratch region.
 int choose_ksplit(const ZGemm& g) {
@@ -213,6 +271,44 @@ int choose_ksplit(const ZGemm& g) {
   ks = std::min(ks, std::max(1, K / 64));
   while (ks > 1 && (int64_t)ks * batch * M * N > tl_split.cap) --ks;
   return std::max(ks, 1);
+}
+
+void apply_cand(ZGemm& g, const TuneCand& c) {
+  g.shape = c.shape;
+  g.big = c.big;
+  g.ksplit = c.ksplit;
+  g.partial = c.ksplit > 1 ? tl_split.ptr : nullptr;
+}
+
+// Candidates for one contraction: the large-tile kernel (both tile widths) where the operands allow it,
+// the 256-thread kernel at the size-picked tile and at 64 x 64, each at the default split-K count, twice
+// and half of it.  The first candidate is the default choice.
+std::vector<TuneCand> tune_candidates(const ZGemm& g0) {
+  std::vector<TuneCand> out;
+  auto add = [&](int shape, int big) {
+    ZGemm g = g0;
+    g.shape = shape;
+    g.big = big;
+    if (big && green::zgemm_variant(g).family != 3) return;
+    g.ksplit = 1;
+    const int ks0 = choose_ksplit(g);
+    const int opts[3] = {ks0, std::min(2 * ks0, 32), ks0 / 2};
+    for (int ks : opts) {
+      if (ks < 1 || ks > std::max(1, g.K / 16)) continue;
+      if (ks > 1 && (int64_t)ks * g.batch * g.M * g.N > tl_split.cap) continue;
+      bool dup = false;
+      for (const TuneCand& c : out) dup = dup || (c.shape == shape && c.big == big && c.ksplit == ks);
+      if (!dup) out.push_back(TuneCand{shape, big, ks});
+    }
+  };
+  add(g0.shape, g0.big);  // the default (size-picked tile, requested large tile)
+  if (g0.prec == 2) {
+    add(0, 1);
+    add(0, 2);
+  }
+  add(0, 0);
+  add(4, 0);
+  return out;
 }
 
 ZOp op(const void* ptr, IdxMap r, IdxMap c, BatchMap b, int etype = green::kC64, int conj = 0) {
@@ -246,6 +342,7 @@ int gemm(green::Site site, const char* label, const ZOp& A, const green::Span& s
   g.prec = prec;
   g.ctype = ctype;
   g.big = big;
+  g.shape = 0;
   g.ksplit = 1;
   g.ksplit = choose_ksplit(g);
   g.partial = g.ksplit > 1 ? tl_split.ptr : nullptr;
@@ -254,6 +351,52 @@ int gemm(green::Site site, const char* label, const ZOp& A, const green::Span& s
   if (!green::zgemm_in_bounds(g, sa, sb, sc, why, sizeof(why))) {
     std::fprintf(stderr, "green_gw: contraction '%s' rejected: %s\n", label, why);
     return GREEN_EINVAL;
+  }
+  // autotuned choice for this shape, or one trial launch of a candidate while tuning
+  TuneEntry* te = nullptr;
+  if (tl_plan) {
+    const TuneKey key{{(int32_t)site, M, N, K, batch, prec, g.A.etype, g.B.etype, ctype, big, 0}};
+    auto it = tl_plan->tuner.find(key);
+    if (it != tl_plan->tuner.end() && it->second.done) {
+      apply_cand(g, it->second.cands[it->second.chosen]);
+    } else if (tl_plan->tune && !tl_rec && !tl_capturing && !green::dryrun()) {
+      te = &tl_plan->tuner[key];
+      if (te->cands.empty()) {
+        te->cands = tune_candidates(g);
+        te->ms.assign(te->cands.size(), 0.f);
+      }
+      apply_cand(g, te->cands[te->trial]);
+    }
+  }
+  if (te) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return GREEN_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      return GREEN_EHIP;
+    }
+    te->ev.push_back(e0);
+    te->ev.push_back(e1);
+    HIP_TRY(hipEventRecord(e0, s));
+    HIP_TRY(green::zgemm(g, s));
+    HIP_TRY(hipEventRecord(e1, s));
+    te->trial += 1;
+    if (te->trial == (int)te->cands.size()) {
+      HIP_TRY(hipEventSynchronize(e1));
+      for (int c = 0; c < te->trial; ++c) HIP_TRY(hipEventElapsedTime(&te->ms[c], te->ev[2 * c], te->ev[2 * c + 1]));
+      for (hipEvent_t e : te->ev) (void)hipEventDestroy(e);
+      te->ev.clear();
+      te->chosen = (int)(std::min_element(te->ms.begin(), te->ms.end()) - te->ms.begin());
+      te->done = true;
+    }
+    return GREEN_OK;
+  }
+  if (tl_rec) {
+    Op o;
+    o.is_gemm = true;
+    o.g = g;
+    tl_rec->push_back(std::move(o));
+    return GREEN_OK;
   }
   const int slot = site == green::Site::P0_Contract ? 0 : (site == green::Site::Sig_PV ? 1 : -1);
   KernelClock* clk = tl_clock;
@@ -327,7 +470,7 @@ int run_polarization(green_plan* p, const void* V, const void* G, void* P0, void
   green::Span sGs = span(G, ex.G);
   if (bf) {
     if ((int64_t)p->r_Gx.bytes < ex.G * 8 || (int64_t)p->r_Vx.bytes < 2 * slab * 8) return GREEN_EINVAL;
-    HIP_TRY(green::convert_c64(static_cast<const double2*>(G), at<void>(ws, p->r_Gx), green::kCB16, ex.G, s));
+    GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64(static_cast<const double2*>(G), at<void>(ws, p->r_Gx), green::kCB16, ex.G, st_); }));
     Gs = at<void>(ws, p->r_Gx);
     sGs = span_ws(ws, p->r_Gx);
   }
@@ -337,9 +480,9 @@ int run_polarization(green_plan* p, const void* V, const void* G, void* P0, void
     green::Span sVs = span(V, ex.V);
     if (bf) {
       void* Vx = at<void>(ws, p->r_Vx);
-      HIP_TRY(green::convert_c64(static_cast<const double2*>(Vq), Vx, green::kCB16, slab, s));
-      if (qn != q) HIP_TRY(green::convert_c64(static_cast<const double2*>(Vqn), eptr(Vx, green::kCB16, slab),
-                                              green::kCB16, slab, s));
+      GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64(static_cast<const double2*>(Vq), Vx, green::kCB16, slab, st_); }));
+      if (qn != q) GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64(static_cast<const double2*>(Vqn), eptr(Vx, green::kCB16, slab),
+                                              green::kCB16, slab, st_); }));
       Vq = Vx;
       Vqn = qn != q ? eptr(Vx, green::kCB16, slab) : Vx;
       sVs = span_ws(ws, p->r_Vx);
@@ -389,11 +532,11 @@ int run_screen(green_plan* p, const void* P0, void* Pt, void* ws, hipStream_t s)
                  sPw, flat(nP), flat(1), bflat((int64_t)nwb * nP), nwb, (int)nP, ntau, nk, cplx(1), cplx(0), s));
   // P~(i W) = [I - P0]^{-1} P0 = [I - P0]^{-1} - I
   if ((int64_t)nk * nwb * nP * 16 > (int64_t)p->r_Pw.bytes) return GREEN_EINVAL;
-  if (!green::dryrun()) {
-    HIP_TRY(green::launch_one_minus(Pw, naux, (int64_t)nk * nwb, s));
-    HIP_TRY(green::zinv_batched(Pw, naux, nP, nk * nwb, at<int>(ws, p->r_status), s));
-    HIP_TRY(green::launch_minus_one(Pw, naux, (int64_t)nk * nwb, s));
-  }
+  GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::launch_one_minus(Pw, naux, (int64_t)nk * nwb, st_); }));
+  GREEN_TRY(aux(s, [=](hipStream_t st_) {
+    return green::zinv_batched(Pw, naux, nP, nk * nwb, at<int>(ws, p->r_status), st_);
+  }));
+  GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::launch_minus_one(Pw, naux, (int64_t)nk * nwb, st_); }));
   // P~(tau_t) = sum_m TB_w2t[t][m] P~(i W_m)
   GREEN_TRY(gemm(green::Site::Transform, "screen.w2t", op(at<double2>(ws, p->r_TB_w2t), flat(nwb), flat(1), bnone()),
                  span_ws(ws, p->r_TB_w2t), op(Pw, flat(nP), flat(1), bflat((int64_t)nwb * nP)), sPw, Pt,
@@ -417,7 +560,7 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
   const green::Span sT1 = span_ws(ws, p->r_T1), sT2 = span_ws(ws, p->r_T2);
   const double2* Pp = static_cast<const double2*>(Pt);
   double2* Sp = static_cast<double2*>(Sig);
-  if (!green::dryrun()) HIP_TRY(green::launch_zero(Sp, ex.Sig, s));
+  GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::launch_zero(Sp, ex.Sig, st_); }));
   // FP32 plans round the V slab of X = P~^T V to FP32 once per q and round the other operands while
   // staging; split-BF16 plans round G once per call, both V slabs of a q once, and keep X and Y in split
   // BF16, so every stage runs on the split-BF16 matrix cores.
@@ -435,7 +578,7 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
   green::Span sGs = span(G, ex.G);
   if (bf) {
     if ((int64_t)p->r_Gx.bytes < ex.G * 8) return GREEN_EINVAL;
-    HIP_TRY(green::convert_c64(static_cast<const double2*>(G), at<void>(ws, p->r_Gx), green::kCB16, ex.G, s));
+    GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64(static_cast<const double2*>(G), at<void>(ws, p->r_Gx), green::kCB16, ex.G, st_); }));
     Gs = at<void>(ws, p->r_Gx);
     sGs = span_ws(ws, p->r_Gx);
   }
@@ -446,11 +589,11 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
     green::Span sVa = span(V, ex.V), sVb = span(V, ex.V);
     if (mixed) {
       if ((int64_t)p->r_Vx.bytes < (bf ? 2 : 1) * slab * green::elem_bytes(vt)) return GREEN_EINVAL;
-      HIP_TRY(green::convert_c64(static_cast<const double2*>(Vqn), Vx, vt, slab, s));
+      GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64(static_cast<const double2*>(Vqn), Vx, vt, slab, st_); }));
       Vqn = Vx;
       sVa = sVx;
       if (bf) {
-        if (q != qn) HIP_TRY(green::convert_c64(static_cast<const double2*>(Vq), eptr(Vx, vt, slab), vt, slab, s));
+        if (q != qn) GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64(static_cast<const double2*>(Vq), eptr(Vx, vt, slab), vt, slab, st_); }));
         Vq = q != qn ? eptr(Vx, vt, slab) : Vx;
         sVb = sVx;
       }
@@ -458,7 +601,7 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
     if (bf) {
       // P~^q(tau)^T rounded to split BF16 for the large-tile kernel (K-contiguous rows)
       if ((int64_t)p->r_Ptx.bytes < (int64_t)ntau * nP * 8) return GREEN_EINVAL;
-      HIP_TRY(green::convert_c64_t(Pp + (int64_t)q * ntau * nP, Ptx, green::kCB16, naux, ntau, s));
+      GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64_t(Pp + (int64_t)q * ntau * nP, Ptx, green::kCB16, naux, ntau, st_); }));
     }
     for (int t0 = 0; t0 < ntau; t0 += p->tc) {
       const int tcn = std::min(p->tc, ntau - t0);
@@ -507,8 +650,7 @@ int run_hf(green_plan* p, const void* V, const void* G, void* Sinf, void* ws, hi
   const double2* Vp = static_cast<const double2*>(V);
   double2* Sp = static_cast<double2*>(Sinf);
   const double w = ns == 1 ? 2.0 : 1.0;
-  if (!green::dryrun())
-    HIP_TRY(green::launch_density(static_cast<const double2*>(G), gam, gamT, ns, ntau, nk, nao, s));
+  GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::launch_density(static_cast<const double2*>(G), gam, gamT, ns, ntau, nk, nao, st_); }));
   // Hartree density D[Q] = (w/nk) sum_{s,k'} sum_{ab} V^{k'k'}_{ba}(Q) gamma^{k'}_{ab}
   for (int sp = 0; sp < ns; ++sp)
     GREEN_TRY(gemm(green::Site::HF, "HF.density", op(Vp, flat(nG), two((int32_t)nG, 1, nV), bnone()), sV,
@@ -741,6 +883,116 @@ int check_plan(green_plan* p, void* ws) {
   return GREEN_OK;
 }
 
+// Sets the plan whose autotuner state gemm() consults for the lifetime of the scope.
+struct PlanScope {
+  green_plan* prev;
+  explicit PlanScope(green_plan* p) : prev(tl_plan) { tl_plan = p; }
+  ~PlanScope() { tl_plan = prev; }
+};
+
+int ensure_events(green_plan* p) {
+  if (green::dryrun() || p->events) return GREEN_OK;
+  for (int i = 0; i < kNumEvents; ++i)
+    if (hipEventCreate(&p->ev[i]) != hipSuccess) {
+      for (int j = 0; j < i; ++j) (void)hipEventDestroy(p->ev[j]);
+      return GREEN_EHIP;
+    }
+  p->events = true;
+  return GREEN_OK;
+}
+
+bool tuning_pending(const green_plan* p) {
+  if (!p->tune) return false;
+  if (p->tuner.empty()) return true;
+  for (const auto& kv : p->tuner)
+    if (!kv.second.done) return true;
+  return false;
+}
+
+void drop_graph(green_plan* p) {
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->gexec = nullptr;
+  p->graph = nullptr;
+}
+
+using MarkFn = std::function<hipError_t(int)>;
+
+// The Sigma evaluation of one iteration (no host synchronisation, so it can be captured or recorded):
+// Sigma^inf and Sigma~(tau) from (V, G) into the workspace, then mixed into the caller's Sinf and Sigma
+// with weight alpha; max |Sigma~_new - Sigma~_old| lands in the scalar slot 8.
+int sigma_eval(green_plan* p, const void* V, const void* G, void* Sinf, void* Sigma, double alpha, void* ws,
+               hipStream_t s, const MarkFn* mark) {
+  const green_dims& d = p->d;
+  const int64_t nG = (int64_t)d.nao * d.nao;
+  const int64_t nsig = (int64_t)d.nspin * d.ntau * p->nk * nG, ninf = (int64_t)d.nspin * p->nk * nG;
+  double2* P = at<double2>(ws, p->r_P);
+  double2* Sinfn = at<double2>(ws, p->r_Sinfn);
+  double2* Sign = at<double2>(ws, p->r_Sign);
+  double* scal = at<double>(ws, p->r_scal);
+  double* part = at<double>(ws, p->r_partial);
+  auto m = [&](int i) { return mark ? hip_status((*mark)(i)) : GREEN_OK; };
+  GREEN_TRY(run_hf(p, V, G, Sinfn, ws, s));
+  GREEN_TRY(m(1));
+  GREEN_TRY(run_polarization(p, V, G, P, ws, s));
+  GREEN_TRY(m(2));
+  GREEN_TRY(run_screen(p, P, P, ws, s));
+  GREEN_TRY(m(3));
+  GREEN_TRY(run_selfenergy(p, V, G, P, Sign, ws, s));
+  GREEN_TRY(m(4));
+  double2* Si = static_cast<double2*>(Sinf);
+  double2* Sg = static_cast<double2*>(Sigma);
+  GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::launch_mix(Si, Sinfn, alpha, ninf, nullptr, nullptr, st_); }));
+  GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::launch_mix(Sg, Sign, alpha, nsig, part, scal + 8, st_); }));
+  return GREEN_OK;
+}
+
+// The rest of an iteration after the Sigma evaluation: Dyson with the chemical-potential search, the
+// energy and the report (synchronises).
+int close_iteration(green_plan* p, const void* H0, const void* S, void* G, void* Sinf, void* Sigma, double* mu,
+                    double n_target, green_report* rep, void* ws, hipStream_t s, const MarkFn* mark = nullptr) {
+  double n = 0.0;
+  int32_t evals = 0;
+  GREEN_TRY(run_dyson(p, H0, S, Sinf, Sigma, n_target, mu, G, &n, &evals, ws, s));
+  if (mark) HIP_TRY((*mark)(6));
+  GREEN_TRY(run_energy(p, H0, G, Sinf, Sigma, ws, s, rep));
+  if (mark) HIP_TRY((*mark)(7));
+  rep->n_elec = n;
+  rep->mu = *mu;
+  rep->mu_evals = evals;
+  if (green::dryrun()) return GREEN_OK;
+  double dsig = 0.0;
+  HIP_TRY(hipMemcpyAsync(&dsig, at<double>(ws, p->r_scal) + 8, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  rep->max_dsigma = dsig;
+  return GREEN_OK;
+}
+
+// Number of contractions the Sigma evaluation records (sizes the batched descriptor tables): a recording
+// pass over stand-in addresses that are never dereferenced.
+int count_ops(green_plan* p) {
+  std::vector<Op> ops;
+  char* fake = reinterpret_cast<char*>((uintptr_t)1 << 44);
+  const SplitBuf saved = tl_split;
+  tl_split.ptr = reinterpret_cast<double2*>(fake + p->r_split.off);
+  tl_split.cap = (int64_t)(p->r_split.bytes / sizeof(double2));
+  tl_split.prec = p->prec;
+  green_plan* prev = tl_plan;
+  tl_plan = nullptr;
+  tl_rec = &ops;
+  char* big = fake + ((uintptr_t)1 << 42);
+  const int64_t step = (int64_t)1 << 40;
+  const int st = sigma_eval(p, big, big + step, big + 2 * step, big + 3 * step, 1.0, fake, nullptr, nullptr);
+  tl_rec = nullptr;
+  tl_plan = prev;
+  tl_split = saved;
+  if (st != GREEN_OK) return st;
+  int64_t n = 0;
+  for (const Op& o : ops) n += o.is_gemm ? 1 : 0;
+  p->nops = n;
+  return GREEN_OK;
+}
+
 }  // namespace
 
 // ====================================================================== exported
@@ -859,12 +1111,19 @@ int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, 
   take(p->r_Gx, prec == GREEN_BF16X3 ? (size_t)ns * ntau * nk * nG * 8 : 0);
   take(p->r_Ptx, prec == GREEN_BF16X3 ? (size_t)ntau * nP * 8 : 0);
   p->ws_bytes = off;
+  if (count_ops(p) != GREEN_OK) {
+    delete p;
+    return GREEN_EINVAL;
+  }
   *out = p;
   return GREEN_OK;
 }
 
 void green_plan_destroy(green_plan* p) {
   if (!p) return;
+  drop_graph(p);
+  for (auto& kv : p->tuner)
+    for (hipEvent_t e : kv.second.ev) (void)hipEventDestroy(e);
   if (p->events)
     for (int i = 0; i < kNumEvents; ++i) (void)hipEventDestroy(p->ev[i]);
   delete static_cast<KernelClock*>(p->clock);
@@ -877,6 +1136,7 @@ int green_gw_polarization(green_plan* p, const void* V, const void* G, void* P0,
   GREEN_TRY(check_plan(p, ws));
   if (!V || !G || !P0) return GREEN_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  PlanScope scope(p);
   GREEN_TRY(ensure_bound(p, ws, s));
   return run_polarization(p, V, G, P0, ws, s);
 }
@@ -885,6 +1145,7 @@ int green_gw_screen(green_plan* p, const void* P0, void* Pt, void* ws, void* str
   GREEN_TRY(check_plan(p, ws));
   if (!P0 || !Pt) return GREEN_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  PlanScope scope(p);
   GREEN_TRY(ensure_bound(p, ws, s));
   return run_screen(p, P0, Pt, ws, s);
 }
@@ -894,6 +1155,7 @@ int green_gw_selfenergy(green_plan* p, const void* V, const void* G, const void*
   GREEN_TRY(check_plan(p, ws));
   if (!V || !G || !Pt || !Sigma) return GREEN_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  PlanScope scope(p);
   GREEN_TRY(ensure_bound(p, ws, s));
   return run_selfenergy(p, V, G, Pt, Sigma, ws, s);
 }
@@ -902,6 +1164,7 @@ int green_hf_static(green_plan* p, const void* V, const void* G, void* Sinf, voi
   GREEN_TRY(check_plan(p, ws));
   if (!V || !G || !Sinf) return GREEN_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  PlanScope scope(p);
   GREEN_TRY(ensure_bound(p, ws, s));
   return run_hf(p, V, G, Sinf, ws, s);
 }
@@ -911,6 +1174,7 @@ int green_dyson(green_plan* p, const void* H0, const void* S, const void* Sinf, 
   GREEN_TRY(check_plan(p, ws));
   if (!H0 || !S || !Sinf || !Sigma || !mu || !G || !std::isfinite(*mu)) return GREEN_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  PlanScope scope(p);
   GREEN_TRY(ensure_bound(p, ws, s));
   return run_dyson(p, H0, S, Sinf, Sigma, n_target, mu, G, n_out, evals_out, ws, s);
 }
@@ -921,27 +1185,16 @@ int green_gw_iterate(green_plan* p, const void* V, const void* H0, const void* S
   if (!V || !H0 || !S || !G || !Sinf || !Sigma || !mu || !rep || !std::isfinite(*mu)) return GREEN_EINVAL;
   if (!(alpha > 0.0 && alpha < 2.0)) return GREEN_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  PlanScope scope(p);
   GREEN_TRY(ensure_bound(p, ws, s));
   std::memset(rep, 0, sizeof(*rep));
-  const green_dims& d = p->d;
-  const int64_t nG = (int64_t)d.nao * d.nao;
-  const int64_t nsig = (int64_t)d.nspin * d.ntau * p->nk * nG, ninf = (int64_t)d.nspin * p->nk * nG;
-  double2* P = at<double2>(ws, p->r_P);
-  double2* Sinfn = at<double2>(ws, p->r_Sinfn);
-  double2* Sign = at<double2>(ws, p->r_Sign);
-  double* scal = at<double>(ws, p->r_scal);
   const bool dry = green::dryrun();
-  if (!dry && !p->events) {
-    for (int i = 0; i < kNumEvents; ++i)
-      if (hipEventCreate(&p->ev[i]) != hipSuccess) {
-        for (int j = 0; j < i; ++j) (void)hipEventDestroy(p->ev[j]);
-        return GREEN_EHIP;
-      }
-    p->events = true;
-  }
-  auto mark = [&](int i) { return dry ? hipSuccess : hipEventRecord(p->ev[i], s); };
+  GREEN_TRY(ensure_events(p));
+  const MarkFn mark = [&](int i) { return dry ? hipSuccess : hipEventRecord(p->ev[i], s); };
   KernelClock* clk = nullptr;
-  if (!dry) {
+  // the graph replays the Sigma evaluation once every contraction shape has its tuned kernel
+  const bool graph = p->use_graph && !dry && s != nullptr && !tuning_pending(p);
+  if (!dry && !graph) {
     if (!p->clock) p->clock = new (std::nothrow) KernelClock();
     clk = static_cast<KernelClock*>(p->clock);
     if (clk) clk->reset();
@@ -951,34 +1204,41 @@ int green_gw_iterate(green_plan* p, const void* V, const void* H0, const void* S
     ~ClockScope() { tl_clock = nullptr; }
   } clock_scope(clk);
   HIP_TRY(mark(0));
-  GREEN_TRY(run_hf(p, V, G, Sinfn, ws, s));
-  HIP_TRY(mark(1));
-  GREEN_TRY(run_polarization(p, V, G, P, ws, s));
-  HIP_TRY(mark(2));
-  GREEN_TRY(run_screen(p, P, P, ws, s));
-  HIP_TRY(mark(3));
-  GREEN_TRY(run_selfenergy(p, V, G, P, Sign, ws, s));
-  HIP_TRY(mark(4));
-  if (!dry) {
-    HIP_TRY(green::launch_mix(static_cast<double2*>(Sinf), Sinfn, alpha, ninf, nullptr, nullptr, s));
-    HIP_TRY(green::launch_mix(static_cast<double2*>(Sigma), Sign, alpha, nsig, at<double>(ws, p->r_partial),
-                              scal + 8, s));
+  if (graph) {
+    const void* args[6] = {V, G, Sinf, Sigma, ws, nullptr};
+    bool same = p->gexec != nullptr && p->galpha == alpha;
+    for (int i = 0; i < 6 && same; ++i) same = p->gargs[i] == args[i];
+    if (!same) {
+      drop_graph(p);
+      hipGraph_t gr = nullptr;
+      HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      tl_capturing = true;
+      const int st = sigma_eval(p, V, G, Sinf, Sigma, alpha, ws, s, nullptr);
+      tl_capturing = false;
+      const hipError_t ce = hipStreamEndCapture(s, &gr);
+      if (st != GREEN_OK) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return st;
+      }
+      if (ce != hipSuccess) return GREEN_EHIP;
+      hipGraphExec_t ex = nullptr;
+      if (hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(gr);
+        return GREEN_EHIP;
+      }
+      p->graph = gr;
+      p->gexec = ex;
+      for (int i = 0; i < 6; ++i) p->gargs[i] = args[i];
+      p->galpha = alpha;
+    }
+    HIP_TRY(hipGraphLaunch(p->gexec, s));
+    for (int i = 1; i <= 4; ++i) HIP_TRY(mark(i));
+  } else {
+    GREEN_TRY(sigma_eval(p, V, G, Sinf, Sigma, alpha, ws, s, &mark));
   }
   HIP_TRY(mark(5));
-  double n = 0.0;
-  int32_t evals = 0;
-  GREEN_TRY(run_dyson(p, H0, S, Sinf, Sigma, n_target, mu, G, &n, &evals, ws, s));
-  HIP_TRY(mark(6));
-  GREEN_TRY(run_energy(p, H0, G, Sinf, Sigma, ws, s, rep));
-  HIP_TRY(mark(7));
-  double dsig = 0.0;
-  rep->n_elec = n;
-  rep->mu = *mu;
-  rep->mu_evals = evals;
+  GREEN_TRY(close_iteration(p, H0, S, G, Sinf, Sigma, mu, n_target, rep, ws, s, &mark));
   if (dry) return GREEN_OK;
-  HIP_TRY(hipMemcpyAsync(&dsig, scal + 8, sizeof(double), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  rep->max_dsigma = dsig;
   for (int i = 0; i < 7; ++i) HIP_TRY(hipEventElapsedTime(&rep->ms[i], p->ev[i], p->ev[i + 1]));
   HIP_TRY(hipEventElapsedTime(&rep->ms[7], p->ev[0], p->ev[7]));
   if (clk)
@@ -987,7 +1247,176 @@ int green_gw_iterate(green_plan* p, const void* V, const void* H0, const void* S
       rep->kern_flops[slot] = clk->flops[slot];
       rep->kern_launches[slot] = clk->used[slot];
     }
-  if (!std::isfinite(rep->e_tot) || !std::isfinite(dsig) || !std::isfinite(rep->herm_err)) return GREEN_ENAN;
+  if (!std::isfinite(rep->e_tot) || !std::isfinite(rep->max_dsigma) || !std::isfinite(rep->herm_err))
+    return GREEN_ENAN;
+  return GREEN_OK;
+}
+
+int green_plan_set_option(green_plan* p, int option, int value) {
+  if (!p) return GREEN_EINVAL;
+  switch (option) {
+    case GREEN_OPT_TUNE:
+      if (value < 0 || value > 2) return GREEN_EINVAL;
+      if (value == 2) p->tuner.clear();
+      p->tune = value != 0;
+      drop_graph(p);
+      return GREEN_OK;
+    case GREEN_OPT_GRAPH:
+      if (value < 0 || value > 1) return GREEN_EINVAL;
+      p->use_graph = value;
+      if (!value) drop_graph(p);
+      return GREEN_OK;
+    default:
+      return GREEN_EINVAL;
+  }
+}
+
+int green_plan_tuning_report(const green_plan* p, char* buf, size_t len) {
+  if (!p || !buf || len == 0) return GREEN_EINVAL;
+  std::string out;
+  static const char* names[] = {"Generic", "P0_VG", "P0_VGrev", "P0_Contract", "Sig_PV", "Sig_XG", "Sig_YV",
+                                "HF", "Transform"};
+  for (const auto& kv : p->tuner) {
+    const TuneKey& k = kv.first;
+    const TuneEntry& e = kv.second;
+    char line[256];
+    const int site = k.v[0] >= 0 && k.v[0] <= 8 ? k.v[0] : 0;
+    if (!e.done) {
+      std::snprintf(line, sizeof(line), "%-12s M=%d N=%d K=%d batch=%d prec=%d: tuning (%d of %zu tried)\n",
+                    names[site], k.v[1], k.v[2], k.v[3], k.v[4], k.v[5], e.trial, e.cands.size());
+    } else {
+      const TuneCand& c = e.cands[e.chosen];
+      std::snprintf(line, sizeof(line),
+                    "%-12s M=%d N=%d K=%d batch=%d prec=%d: shape=%d big=%d ksplit=%d %.1f us (default %.1f us)\n",
+                    names[site], k.v[1], k.v[2], k.v[3], k.v[4], k.v[5], c.shape, c.big, c.ksplit,
+                    1000.0 * e.ms[e.chosen], 1000.0 * e.ms[0]);
+    }
+    out += line;
+  }
+  std::snprintf(buf, len, "%s", out.c_str());
+  return out.size() + 1 > len ? GREEN_ENOMEM : GREEN_OK;
+}
+
+// ---------------------------------------------------------------- batched iteration
+size_t green_batch_workspace_bytes(int nsys, green_plan* const* plans) {
+  if (nsys <= 0 || !plans) return 0;
+  size_t n = 0;
+  for (int i = 0; i < nsys; ++i) {
+    if (!plans[i]) return 0;
+    n += (size_t)plans[i]->nops;
+  }
+  // one descriptor and one tile offset per recorded contraction, plus one closing offset per group
+  return 256 + n * (sizeof(ZGemm) + 2 * sizeof(int64_t)) + 4096;
+}
+
+int green_gw_iterate_batched(int nsys, green_plan* const* plans, green_system* sys, double alpha,
+                             green_report* reps, void* batch_ws, size_t batch_ws_bytes, void* stream) {
+  if (nsys <= 0 || !plans || !sys || !reps || !batch_ws) return GREEN_EINVAL;
+  if (!(alpha > 0.0 && alpha < 2.0)) return GREEN_EINVAL;
+  if (batch_ws_bytes < green_batch_workspace_bytes(nsys, plans)) return GREEN_ENOMEM;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool dry = green::dryrun();
+  for (int i = 0; i < nsys; ++i) {
+    green_system& y = sys[i];
+    GREEN_TRY(check_plan(plans[i], y.ws));
+    if (!y.V || !y.H0 || !y.S || !y.G || !y.Sinf || !y.Sigma || !std::isfinite(y.mu)) return GREEN_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == plans[i] || sys[j].ws == y.ws) return GREEN_EINVAL;  // systems need their own plan and workspace
+    std::memset(&reps[i], 0, sizeof(green_report));
+  }
+  // 1. record the Sigma evaluation of every system
+  std::vector<std::vector<Op>> ops(nsys);
+  size_t rounds = 0;
+  for (int i = 0; i < nsys; ++i) {
+    PlanScope scope(plans[i]);
+    GREEN_TRY(ensure_bound(plans[i], sys[i].ws, s));
+    tl_rec = &ops[i];
+    const int st = sigma_eval(plans[i], sys[i].V, sys[i].G, sys[i].Sinf, sys[i].Sigma, alpha, sys[i].ws, s, nullptr);
+    tl_rec = nullptr;
+    GREEN_TRY(st);
+    rounds = std::max(rounds, ops[i].size());
+  }
+  // 2. schedule: round r holds the r-th launch of every system; its contractions are grouped by kernel variant
+  struct Group {
+    size_t first, count;  // descriptors [first, first + count) in `descs`
+    size_t start_off;     // offsets [start_off, start_off + count] in `starts`
+  };
+  std::vector<ZGemm> descs;
+  std::vector<int64_t> starts;
+  std::vector<std::vector<Group>> groups(rounds);
+  for (size_t r = 0; r < rounds; ++r) {
+    std::vector<int> pending;
+    for (int i = 0; i < nsys; ++i)
+      if (r < ops[i].size() && ops[i][r].is_gemm && ops[i][r].g.M > 0 && ops[i][r].g.N > 0) pending.push_back(i);
+    while (!pending.empty()) {
+      const green::Variant v = green::zgemm_variant(ops[pending[0]][r].g);
+      Group gr{descs.size(), 0, starts.size()};
+      std::vector<int> rest;
+      int64_t tiles = 0;
+      starts.push_back(0);
+      for (int i : pending) {
+        const ZGemm& g = ops[i][r].g;
+        if (!green::same_variant(v, green::zgemm_variant(g))) {
+          rest.push_back(i);
+          continue;
+        }
+        descs.push_back(g);
+        tiles += green::zgemm_blocks(g);
+        starts.push_back(tiles);
+        gr.count += 1;
+      }
+      groups[r].push_back(gr);
+      pending.swap(rest);
+    }
+  }
+  const size_t need = 256 + descs.size() * sizeof(ZGemm) + starts.size() * sizeof(int64_t);
+  if (need > batch_ws_bytes) return GREEN_ENOMEM;
+  char* base = static_cast<char*>(batch_ws);
+  ZGemm* ddesc = reinterpret_cast<ZGemm*>(base);
+  int64_t* dstart = reinterpret_cast<int64_t*>(base + ((descs.size() * sizeof(ZGemm) + 255) & ~(size_t)255));
+  if (!dry && !descs.empty()) {
+    HIP_TRY(hipMemcpyAsync(ddesc, descs.data(), descs.size() * sizeof(ZGemm), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(dstart, starts.data(), starts.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  }
+  // 3. replay round by round: one persistent launch per kernel variant, auxiliary launches per system
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (!dry) {
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      return GREEN_EHIP;
+    }
+  }
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  } guard{e0, e1};
+  if (!dry) HIP_TRY(hipEventRecord(e0, s));
+  for (size_t r = 0; r < rounds; ++r) {
+    for (const Group& gr : groups[r])
+      HIP_TRY(green::zgemm_group(descs.data() + gr.first, (int)gr.count, ddesc + gr.first, dstart + gr.start_off, s));
+    for (int i = 0; i < nsys; ++i)
+      if (r < ops[i].size() && !ops[i][r].is_gemm && !dry) HIP_TRY(ops[i][r].aux(s));
+  }
+  if (!dry) HIP_TRY(hipEventRecord(e1, s));
+  // 4. close every system's iteration: Dyson, chemical potential, energy
+  for (int i = 0; i < nsys; ++i) {
+    PlanScope scope(plans[i]);
+    GREEN_TRY(ensure_bound(plans[i], sys[i].ws, s));
+    GREEN_TRY(close_iteration(plans[i], sys[i].H0, sys[i].S, sys[i].G, sys[i].Sinf, sys[i].Sigma, &sys[i].mu,
+                              sys[i].n_target, &reps[i], sys[i].ws, s));
+  }
+  if (dry) return GREEN_OK;
+  HIP_TRY(hipStreamSynchronize(s));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  for (int i = 0; i < nsys; ++i) {
+    reps[i].ms[7] = ms;  // Sigma evaluation of the whole batch
+    if (!std::isfinite(reps[i].e_tot) || !std::isfinite(reps[i].max_dsigma)) return GREEN_ENAN;
+  }
   return GREEN_OK;
 }
 

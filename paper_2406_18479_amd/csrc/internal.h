@@ -86,12 +86,29 @@ struct ZGemm {
                   // accumulate in FP32 within a K slice, slices are combined in FP64
   int32_t ctype;  // ElemType of C (kCB16 requires beta == 0); prec 0 requires kC64 operands and output
   int32_t big;    // prec 2 with kCB16 operands: 1 = 192 x 96 tiles, 2 = 192 x 64 tiles (large-tile kernel)
+  int32_t shape;  // 256-thread kernels: 0 = by size, 1..4 = 32x32, 32x64, 64x32, 64x64 tiles
 };
+
+// Kernel variant a descriptor launches: family 0 FP64, 1 FP32, 2 split BF16 (256 threads), 3 split BF16
+// large tiles (512 threads); tile (bm, bn) = (32 p1, 32 p2) or (64 p1, 32 p2) for family 3.
+struct Variant {
+  int32_t family, p1, p2;
+  bool bnc;  // family 3: B is N-contiguous
+  int32_t threads, bm, bn;
+};
+Variant zgemm_variant(const ZGemm& g);
+bool same_variant(const Variant& a, const Variant& b);
+int64_t zgemm_blocks(const ZGemm& g);
 
 // Tile of the GEMM variant the launcher will pick (for choosing split-K counts).
 void zgemm_tile(const ZGemm& g, int* bm, int* bn, int* threads);
 
 hipError_t zgemm(const ZGemm& g, hipStream_t s);
+
+// n independent GEMMs of one variant in one persistent launch (plus one grouped split-K pass when any
+// has ksplit > 1).  `host` mirrors the n descriptors at `dev`; dev_start[i] is the first tile of
+// descriptor i in the concatenated tile range (n + 1 entries, dev_start[0] = 0).
+hipError_t zgemm_group(const ZGemm* host, int n, const ZGemm* dev, const int64_t* dev_start, hipStream_t s);
 
 // Extent of a buffer in bytes: every element an operand touches must lie in [base, base + bytes).
 struct Span {

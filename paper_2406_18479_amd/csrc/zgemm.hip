@@ -66,8 +66,8 @@ struct KPos {
   }
 };
 
-template <int WM, int WN, Site SITE>
-__global__ __launch_bounds__(256) void zgemm_f64_kernel(const ZGemm g) {
+template <int WM, int WN>
+__device__ __forceinline__ void f64_body(const ZGemm& g, int64_t bid) {
   constexpr int BM = 32 * WM, BN = 32 * WN, BK = 8;
   constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
   __shared__ double2 As[2][BK][BM];
@@ -79,8 +79,8 @@ __global__ __launch_bounds__(256) void zgemm_f64_kernel(const ZGemm g) {
   const int tiles_m = (g.M + BM - 1) / BM;
   const int tiles_n = (g.N + BN - 1) / BN;
   const int64_t per_batch = (int64_t)tiles_m * tiles_n;
-  const int64_t group = blockIdx.x / per_batch;  // = batch * ksplit + slice
-  const int32_t tile = (int32_t)(blockIdx.x - group * per_batch);
+  const int64_t group = bid / per_batch;  // = batch * ksplit + slice
+  const int32_t tile = (int32_t)(bid - group * per_batch);
   const int32_t batch = (int32_t)(group / g.ksplit);
   const int32_t slice = (int32_t)(group - (int64_t)batch * g.ksplit);
   const int tm = tile % tiles_m;
@@ -330,8 +330,8 @@ __device__ __forceinline__ void store_c(const ZGemm& g, int64_t off, double2 v) 
   }
 }
 
-template <int MODE, int WM, int WN, Site SITE>
-__global__ __launch_bounds__(256) void zgemm_mx_kernel(const ZGemm g) {
+template <int MODE, int WM, int WN>
+__device__ __forceinline__ void mx_body(const ZGemm& g, int64_t bid) {
   constexpr int BM = 32 * WM, BN = 32 * WN, BK = 16;  // BK complex K per stage
   constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
   // LDS rows hold K contiguously, padded to spread banks
@@ -347,8 +347,8 @@ __global__ __launch_bounds__(256) void zgemm_mx_kernel(const ZGemm g) {
   const int tiles_m = (g.M + BM - 1) / BM;
   const int tiles_n = (g.N + BN - 1) / BN;
   const int64_t per_batch = (int64_t)tiles_m * tiles_n;
-  const int64_t group = blockIdx.x / per_batch;
-  const int32_t tile = (int32_t)(blockIdx.x - group * per_batch);
+  const int64_t group = bid / per_batch;
+  const int32_t tile = (int32_t)(bid - group * per_batch);
   const int32_t batch = (int32_t)(group / g.ksplit);
   const int32_t slice = (int32_t)(group - (int64_t)batch * g.ksplit);
   const int tm = tile % tiles_m;
@@ -632,8 +632,8 @@ struct KCur {
 // word index of (row r, complex k) in a 32-word LDS plane row with swizzled 16-byte chunks
 __device__ __forceinline__ int bt_word(int r, int k) { return r * 32 + ((((k >> 2) ^ (r >> 1)) & 7) << 2) + (k & 3); }
 
-template <int FM, int FN, bool BNC, Site SITE>
-__global__ __launch_bounds__(512) void zgemm_bt_kernel(const ZGemm g) {
+template <int FM, int FN, bool BNC>
+__device__ __forceinline__ void bt_body(const ZGemm& g, int64_t bid0, int64_t nblk) {
   constexpr int BM = 64 * FM, BN = 32 * FN, BK = 32;
   constexpr int EA = BM * BK / 512;
   constexpr int EB = BN * BK / 512;
@@ -646,7 +646,7 @@ __global__ __launch_bounds__(512) void zgemm_bt_kernel(const ZGemm g) {
   const int tiles_m = (g.M + BM - 1) / BM;
   const int tiles_n = (g.N + BN - 1) / BN;
   const int64_t per_batch = (int64_t)tiles_m * tiles_n;
-  const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t bid = xcd_block(bid0, nblk);
   const int64_t group = bid / per_batch;
   const int32_t tile = (int32_t)(bid - group * per_batch);
   const int32_t batch = (int32_t)(group / g.ksplit);
@@ -841,10 +841,10 @@ __global__ __launch_bounds__(512) void zgemm_bt_kernel(const ZGemm g) {
 }
 
 // Second pass of split-K: C = alpha * sum_slices partial + beta * C, slices added in order.
-__global__ __launch_bounds__(256) void zgemm_splitk_reduce(const ZGemm g) {
+__device__ __forceinline__ void splitk_body(const ZGemm& g, int64_t x0, int64_t stride) {
   const int64_t mn = (int64_t)g.M * g.N;
   const int64_t total = mn * g.batch;
-  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t x = x0; x < total; x += stride) {
     const int32_t b = (int32_t)(x / mn);
     const int64_t e = x - (int64_t)b * mn;
     const int32_t gm = (int32_t)(e / g.N), gn = (int32_t)(e - (int64_t)(e / g.N) * g.N);
@@ -856,6 +856,59 @@ __global__ __launch_bounds__(256) void zgemm_splitk_reduce(const ZGemm g) {
     }
     store_c(g, batch_off(g.cb, b) + map_idx(g.cr, gm) + map_idx(g.cc, gn), make_double2(vr, vi));
   }
+}
+
+__global__ __launch_bounds__(256) void zgemm_splitk_reduce(const ZGemm g) {
+  splitk_body(g, blockIdx.x * (int64_t)blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Kernels: one GEMM per launch (the call site is a template argument so that profilers attribute time
+// per contraction), or a group of independent GEMMs of one variant in one persistent launch: a grid of
+// workgroups walks the concatenated tile ranges of all descriptors.
+template <int WM, int WN, Site SITE>
+__global__ __launch_bounds__(256) void zgemm_f64_kernel(const ZGemm g) {
+  f64_body<WM, WN>(g, blockIdx.x);
+}
+template <int MODE, int WM, int WN, Site SITE>
+__global__ __launch_bounds__(256) void zgemm_mx_kernel(const ZGemm g) {
+  mx_body<MODE, WM, WN>(g, blockIdx.x);
+}
+template <int FM, int FN, bool BNC, Site SITE>
+__global__ __launch_bounds__(512) void zgemm_bt_kernel(const ZGemm g) {
+  bt_body<FM, FN, BNC>(g, blockIdx.x, gridDim.x);
+}
+
+struct GroupArgs {
+  const ZGemm* gs;       // device array of n descriptors
+  const int64_t* start;  // device array of n + 1 tile offsets
+  int32_t n;
+  int64_t total;
+};
+template <class F>
+__device__ __forceinline__ void group_loop(const GroupArgs& a, F&& body) {
+  for (int64_t t = blockIdx.x; t < a.total; t += gridDim.x) {
+    int d = 0;
+    while (d + 1 < a.n && a.start[d + 1] <= t) ++d;
+    body(a.gs[d], t - a.start[d], a.start[d + 1] - a.start[d]);
+  }
+}
+template <int WM, int WN>
+__global__ __launch_bounds__(256) void zgemm_f64_group(const GroupArgs a) {
+  group_loop(a, [](const ZGemm& g, int64_t b, int64_t) { f64_body<WM, WN>(g, b); });
+}
+template <int MODE, int WM, int WN>
+__global__ __launch_bounds__(256) void zgemm_mx_group(const GroupArgs a) {
+  group_loop(a, [](const ZGemm& g, int64_t b, int64_t) { mx_body<MODE, WM, WN>(g, b); });
+}
+template <int FM, int FN, bool BNC>
+__global__ __launch_bounds__(512) void zgemm_bt_group(const GroupArgs a) {
+  group_loop(a, [](const ZGemm& g, int64_t b, int64_t n) { bt_body<FM, FN, BNC>(g, b, n); });
+}
+// split-K second pass of a group: descriptor blockIdx.y, elements strided over blockIdx.x
+__global__ __launch_bounds__(256) void zgemm_splitk_reduce_group(const ZGemm* __restrict__ gs) {
+  const ZGemm& g = gs[blockIdx.y];
+  if (g.ksplit > 1) splitk_body(g, blockIdx.x * (int64_t)blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
 }
 
 // Transposing rounding: out[b][j][i] = round(in[b][i][j]).
@@ -1011,113 +1064,202 @@ static bool big_ok(const ZGemm& g) {
   return true;
 }
 
-void zgemm_tile(const ZGemm& g, int* bm, int* bn, int* threads) {
+// Kernel variant of a descriptor: family (0: FP64, 1: FP32, 2: split BF16 64-wide tiles, 3: split BF16
+// large tiles) and tile parameters.  g.shape (1..4) forces a 32/64-wide tile of the 256-thread kernels,
+// 0 picks 32 along a dimension of at most 32, else 64.
+Variant zgemm_variant(const ZGemm& g) {
+  Variant v{};
   if (g.prec == 2 && big_ok(g)) {
-    *bm = 192;
-    *bn = g.big == 1 ? 96 : 64;
-    *threads = 512;
-    return;
+    v.family = 3;
+    v.p1 = 3;
+    v.p2 = g.big == 1 ? 3 : 2;
+    v.bnc = g.B.c.s_in == 1 && g.B.c.ext >= 16;
+    v.threads = 512;
+    v.bm = 64 * v.p1;
+    v.bn = 32 * v.p2;
+    return v;
   }
-  *bm = g.M <= 32 ? 32 : 64;
-  *bn = g.N <= 32 ? 32 : 64;
-  *threads = 256;
+  v.family = g.prec;  // 0, 1, 2
+  if (g.shape >= 1 && g.shape <= 4) {
+    v.p1 = (g.shape - 1) / 2 + 1;
+    v.p2 = (g.shape - 1) % 2 + 1;
+  } else {
+    v.p1 = g.M <= 32 ? 1 : 2;
+    v.p2 = g.N <= 32 ? 1 : 2;
+  }
+  v.bnc = false;
+  v.threads = 256;
+  v.bm = 32 * v.p1;
+  v.bn = 32 * v.p2;
+  return v;
 }
+
+bool same_variant(const Variant& a, const Variant& b) {
+  return a.family == b.family && a.p1 == b.p1 && a.p2 == b.p2 && a.bnc == b.bnc;
+}
+
+void zgemm_tile(const ZGemm& g, int* bm, int* bn, int* threads) {
+  const Variant v = zgemm_variant(g);
+  *bm = v.bm;
+  *bn = v.bn;
+  *threads = v.threads;
+}
+
+int64_t zgemm_blocks(const ZGemm& g) {
+  const Variant v = zgemm_variant(g);
+  return (int64_t)((g.M + v.bm - 1) / v.bm) * ((g.N + v.bn - 1) / v.bn) * g.batch * g.ksplit;
+}
+
+namespace {
+
+#define GREEN_SITES(X)     \
+  switch (g.site) {        \
+    case Site::P0_VG: X(P0_VG); break;             \
+    case Site::P0_VGrev: X(P0_VGrev); break;       \
+    case Site::P0_Contract: X(P0_Contract); break; \
+    case Site::Sig_PV: X(Sig_PV); break;           \
+    case Site::Sig_XG: X(Sig_XG); break;           \
+    case Site::Sig_YV: X(Sig_YV); break;           \
+    case Site::HF: X(HF); break;                   \
+    case Site::Transform: X(Transform); break;     \
+    default: X(Generic); break;                    \
+  }
+
+template <int WM, int WN>
+void launch_f64(const ZGemm& g, dim3 grid, hipStream_t s) {
+#define X(S) zgemm_f64_kernel<WM, WN, Site::S><<<grid, dim3(256), 0, s>>>(g)
+  GREEN_SITES(X)
+#undef X
+}
+template <int MODE, int WM, int WN>
+void launch_mx(const ZGemm& g, dim3 grid, hipStream_t s) {
+#define X(S) zgemm_mx_kernel<MODE, WM, WN, Site::S><<<grid, dim3(256), 0, s>>>(g)
+  GREEN_SITES(X)
+#undef X
+}
+template <int FM, int FN, bool BNC>
+void launch_bt(const ZGemm& g, dim3 grid, hipStream_t s) {
+  switch (g.site) {
+    case Site::P0_VG: zgemm_bt_kernel<FM, FN, BNC, Site::P0_VG><<<grid, dim3(512), 0, s>>>(g); break;
+    case Site::P0_VGrev: zgemm_bt_kernel<FM, FN, BNC, Site::P0_VGrev><<<grid, dim3(512), 0, s>>>(g); break;
+    case Site::P0_Contract: zgemm_bt_kernel<FM, FN, BNC, Site::P0_Contract><<<grid, dim3(512), 0, s>>>(g); break;
+    case Site::Sig_PV: zgemm_bt_kernel<FM, FN, BNC, Site::Sig_PV><<<grid, dim3(512), 0, s>>>(g); break;
+    default: zgemm_bt_kernel<FM, FN, BNC, Site::Generic><<<grid, dim3(512), 0, s>>>(g); break;
+  }
+}
+
+void launch_single(const Variant& v, const ZGemm& g, dim3 grid, hipStream_t s) {
+  const int sh = (v.p1 - 1) * 2 + (v.p2 - 1);
+  switch (v.family) {
+    case 0:
+      if (sh == 0) launch_f64<1, 1>(g, grid, s);
+      else if (sh == 1) launch_f64<1, 2>(g, grid, s);
+      else if (sh == 2) launch_f64<2, 1>(g, grid, s);
+      else launch_f64<2, 2>(g, grid, s);
+      break;
+    case 1:
+      if (sh == 0) launch_mx<1, 1, 1>(g, grid, s);
+      else if (sh == 1) launch_mx<1, 1, 2>(g, grid, s);
+      else if (sh == 2) launch_mx<1, 2, 1>(g, grid, s);
+      else launch_mx<1, 2, 2>(g, grid, s);
+      break;
+    case 2:
+      if (sh == 0) launch_mx<2, 1, 1>(g, grid, s);
+      else if (sh == 1) launch_mx<2, 1, 2>(g, grid, s);
+      else if (sh == 2) launch_mx<2, 2, 1>(g, grid, s);
+      else launch_mx<2, 2, 2>(g, grid, s);
+      break;
+    default:
+      if (v.p2 == 3) {
+        if (v.bnc) launch_bt<3, 3, true>(g, grid, s);
+        else launch_bt<3, 3, false>(g, grid, s);
+      } else {
+        if (v.bnc) launch_bt<3, 2, true>(g, grid, s);
+        else launch_bt<3, 2, false>(g, grid, s);
+      }
+      break;
+  }
+}
+
+void launch_group(const Variant& v, const GroupArgs& a, dim3 grid, hipStream_t s) {
+  const int sh = (v.p1 - 1) * 2 + (v.p2 - 1);
+  const dim3 b256(256), b512(512);
+  switch (v.family) {
+    case 0:
+      if (sh == 0) zgemm_f64_group<1, 1><<<grid, b256, 0, s>>>(a);
+      else if (sh == 1) zgemm_f64_group<1, 2><<<grid, b256, 0, s>>>(a);
+      else if (sh == 2) zgemm_f64_group<2, 1><<<grid, b256, 0, s>>>(a);
+      else zgemm_f64_group<2, 2><<<grid, b256, 0, s>>>(a);
+      break;
+    case 1:
+      if (sh == 0) zgemm_mx_group<1, 1, 1><<<grid, b256, 0, s>>>(a);
+      else if (sh == 1) zgemm_mx_group<1, 1, 2><<<grid, b256, 0, s>>>(a);
+      else if (sh == 2) zgemm_mx_group<1, 2, 1><<<grid, b256, 0, s>>>(a);
+      else zgemm_mx_group<1, 2, 2><<<grid, b256, 0, s>>>(a);
+      break;
+    case 2:
+      if (sh == 0) zgemm_mx_group<2, 1, 1><<<grid, b256, 0, s>>>(a);
+      else if (sh == 1) zgemm_mx_group<2, 1, 2><<<grid, b256, 0, s>>>(a);
+      else if (sh == 2) zgemm_mx_group<2, 2, 1><<<grid, b256, 0, s>>>(a);
+      else zgemm_mx_group<2, 2, 2><<<grid, b256, 0, s>>>(a);
+      break;
+    default:
+      if (v.p2 == 3) {
+        if (v.bnc) zgemm_bt_group<3, 3, true><<<grid, b512, 0, s>>>(a);
+        else zgemm_bt_group<3, 3, false><<<grid, b512, 0, s>>>(a);
+      } else {
+        if (v.bnc) zgemm_bt_group<3, 2, true><<<grid, b512, 0, s>>>(a);
+        else zgemm_bt_group<3, 2, false><<<grid, b512, 0, s>>>(a);
+      }
+      break;
+  }
+}
+
+bool launchable(const ZGemm& g) {
+  if (g.ksplit < 1 || g.prec < 0 || g.prec > 2) return false;
+  if (g.prec == 0 && (g.A.etype != kC64 || g.B.etype != kC64 || g.ctype != kC64)) return false;
+  if (g.ksplit > 1 && !g.partial) return false;
+  return true;
+}
+
+}  // namespace
 
 hipError_t zgemm(const ZGemm& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
   if (g.K <= 0) return hipErrorInvalidValue;
   if (dryrun()) return hipSuccess;
-  if (g.ksplit < 1 || g.prec < 0 || g.prec > 2) return hipErrorInvalidValue;
-  if (g.prec == 0 && (g.A.etype != kC64 || g.B.etype != kC64 || g.ctype != kC64)) return hipErrorInvalidValue;
-  if (g.ksplit > 1 && !g.partial) return hipErrorInvalidValue;
-  // tile shape: 32 x 32, 64 x 32, 32 x 64 or 64 x 64 (a dimension <= 32 gets a 32-wide tile), or the
-  // large-tile kernel's 192 x 192 / 192 x 64
-  int bm, bn, nthreads;
-  zgemm_tile(g, &bm, &bn, &nthreads);
-  const int wm = g.M <= 32 ? 1 : 2, wn = g.N <= 32 ? 1 : 2;
-  const int64_t tiles = (int64_t)((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn);
-  const dim3 grid((unsigned)(tiles * g.batch * g.ksplit)), block(256);
-  const int shape = (wm - 1) * 2 + (wn - 1);
-#define GREEN_SITE(S)                                                     \
-  case Site::S:                                                          \
-    switch (shape) {                                                     \
-      case 0: zgemm_f64_kernel<1, 1, Site::S><<<grid, block, 0, s>>>(g); break; \
-      case 1: zgemm_f64_kernel<1, 2, Site::S><<<grid, block, 0, s>>>(g); break; \
-      case 2: zgemm_f64_kernel<2, 1, Site::S><<<grid, block, 0, s>>>(g); break; \
-      default: zgemm_f64_kernel<2, 2, Site::S><<<grid, block, 0, s>>>(g); break; \
-    }                                                                    \
-    break;
-  if (g.prec == 2 && big_ok(g)) {
-    const bool bnc = g.B.c.s_in == 1 && g.B.c.ext >= 16;
-#define GREEN_BT(FM, FN, S)                                                         \
-  if (bnc)                                                                          \
-    zgemm_bt_kernel<FM, FN, true, Site::S><<<grid, dim3(512), 0, s>>>(g);           \
-  else                                                                              \
-    zgemm_bt_kernel<FM, FN, false, Site::S><<<grid, dim3(512), 0, s>>>(g);
-    if (g.big == 1) {
-      if (g.site == Site::P0_Contract) {
-        GREEN_BT(3, 3, P0_Contract)
-      } else {
-        GREEN_BT(3, 3, Generic)
-      }
-    } else {
-      if (g.site == Site::Sig_PV) {
-        GREEN_BT(3, 2, Sig_PV)
-      } else if (g.site == Site::P0_Contract) {
-        GREEN_BT(3, 2, P0_Contract)
-      } else if (g.site == Site::P0_VG) {
-        GREEN_BT(3, 2, P0_VG)
-      } else if (g.site == Site::P0_VGrev) {
-        GREEN_BT(3, 2, P0_VGrev)
-      } else {
-        GREEN_BT(3, 2, Generic)
-      }
-    }
-#undef GREEN_BT
-  } else if (g.prec == 1 || g.prec == 2) {
-#define GREEN_MX(MODE, S)                                                                       \
-  switch (shape) {                                                                              \
-    case 0: zgemm_mx_kernel<MODE, 1, 1, Site::S><<<grid, block, 0, s>>>(g); break;              \
-    case 1: zgemm_mx_kernel<MODE, 1, 2, Site::S><<<grid, block, 0, s>>>(g); break;              \
-    case 2: zgemm_mx_kernel<MODE, 2, 1, Site::S><<<grid, block, 0, s>>>(g); break;              \
-    default: zgemm_mx_kernel<MODE, 2, 2, Site::S><<<grid, block, 0, s>>>(g); break;             \
-  }
-#define GREEN_MX_SITE(MODE)                                            \
-  switch (g.site) {                                                    \
-    case Site::P0_VG: GREEN_MX(MODE, P0_VG) break;                     \
-    case Site::P0_VGrev: GREEN_MX(MODE, P0_VGrev) break;               \
-    case Site::P0_Contract: GREEN_MX(MODE, P0_Contract) break;         \
-    case Site::Sig_PV: GREEN_MX(MODE, Sig_PV) break;                   \
-    case Site::Sig_XG: GREEN_MX(MODE, Sig_XG) break;                   \
-    case Site::Sig_YV: GREEN_MX(MODE, Sig_YV) break;                   \
-    default: GREEN_MX(MODE, Generic) break;                            \
-  }
-    if (g.prec == 1) {
-      GREEN_MX_SITE(1)
-    } else {
-      GREEN_MX_SITE(2)
-    }
-#undef GREEN_MX_SITE
-#undef GREEN_MX
-  } else
-  switch (g.site) {
-    GREEN_SITE(P0_VG)
-    GREEN_SITE(P0_VGrev)
-    GREEN_SITE(P0_Contract)
-    GREEN_SITE(Sig_PV)
-    GREEN_SITE(Sig_XG)
-    GREEN_SITE(Sig_YV)
-    GREEN_SITE(HF)
-    GREEN_SITE(Transform)
-    default:
-      GREEN_SITE(Generic)
-  }
-#undef GREEN_SITE
+  if (!launchable(g)) return hipErrorInvalidValue;
+  const Variant v = zgemm_variant(g);
+  launch_single(v, g, dim3((unsigned)zgemm_blocks(g)), s);
   if (g.ksplit > 1) {
     const int64_t total = (int64_t)g.M * g.N * g.batch;
     int64_t nb = (total + 255) / 256;
     if (nb > 65536) nb = 65536;
     zgemm_splitk_reduce<<<dim3((unsigned)nb), dim3(256), 0, s>>>(g);
+  }
+  return hipGetLastError();
+}
+
+hipError_t zgemm_group(const ZGemm* host, int n, const ZGemm* dev, const int64_t* dev_start, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (dryrun()) return hipSuccess;
+  const Variant v = zgemm_variant(host[0]);
+  int64_t total = 0, reduce_elems = 0;
+  for (int i = 0; i < n; ++i) {
+    const ZGemm& g = host[i];
+    if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return hipErrorInvalidValue;
+    if (!launchable(g) || !same_variant(v, zgemm_variant(g))) return hipErrorInvalidValue;
+    total += zgemm_blocks(g);
+    if (g.ksplit > 1) reduce_elems = std::max<int64_t>(reduce_elems, (int64_t)g.M * g.N * g.batch);
+  }
+  GroupArgs a{dev, dev_start, n, total};
+  // persistent grid: at most 8 workgroups per CU resident over 256 CUs
+  const int64_t cap = (v.threads == 512 ? 1 : 4) * 256 * 8;
+  launch_group(v, a, dim3((unsigned)std::min<int64_t>(total, cap)), s);
+  if (reduce_elems > 0) {
+    int64_t nb = (reduce_elems + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    zgemm_splitk_reduce_group<<<dim3((unsigned)nb, (unsigned)n), dim3(256), 0, s>>>(dev);
   }
   return hipGetLastError();
 }

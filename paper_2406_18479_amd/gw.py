@@ -78,6 +78,16 @@ class Plan:
     def shape_S(self):
         return (self.nk, self.nao, self.nao)
 
+    def set_option(self, option: str, value: int) -> None:
+        """option "tune" (0, 1, 2) or "graph" (0, 1); see green_plan_set_option."""
+        code = {"tune": _lib.OPT_TUNE, "graph": _lib.OPT_GRAPH}[option]
+        _lib.check(_lib.LIB.green_plan_set_option(self._h, code, int(value)), "green_plan_set_option")
+
+    def tuning_report(self) -> str:
+        buf = ctypes.create_string_buffer(1 << 16)
+        _lib.check(_lib.LIB.green_plan_tuning_report(self._h, buf, len(buf)), "green_plan_tuning_report")
+        return buf.value.decode()
+
     def close(self):
         if getattr(self, "_h", None):
             _lib.LIB.green_plan_destroy(self._h)
@@ -148,3 +158,32 @@ class Plan:
                                              float(n_target), float(alpha), ctypes.byref(rep), self.ws.data_ptr(),
                                              _stream(self.device)), "green_gw_iterate")
         return m.value, rep.as_dict()
+
+
+def iterate_batched(plans, systems, alpha=1.0):
+    """One iteration of several independent systems (green_gw_iterate_batched).
+
+    plans: list of Plan (one per system, each with its own workspace), all on one device.
+    systems: list of dicts with keys V, H0, S, G, Sinf, Sigma (tensors; G, Sinf, Sigma updated in place),
+    mu (float) and n_target (float).  Returns (list of mu, list of report dicts).
+    """
+    if len(plans) != len(systems) or not plans:
+        raise ValueError("plans and systems must be non-empty lists of equal length")
+    dev = plans[0].device
+    n = len(plans)
+    handles = (ctypes.c_void_p * n)(*[p._h.value for p in plans])
+    arr = (_lib.System * n)()
+    for i, (p, y) in enumerate(zip(plans, systems)):
+        if p.device != dev:
+            raise ValueError("all plans must be on one device")
+        arr[i] = _lib.System(_ptr(y["V"], p.shape_V, "V", dev), _ptr(y["H0"], p.shape_H, "H0", dev),
+                             _ptr(y["S"], p.shape_S, "S", dev), _ptr(y["G"], p.shape_G, "G", dev),
+                             _ptr(y["Sinf"], p.shape_H, "Sinf", dev), _ptr(y["Sigma"], p.shape_G, "Sigma", dev),
+                             float(y["mu"]), float(y["n_target"]), p.ws.data_ptr())
+    nbytes = int(_lib.LIB.green_batch_workspace_bytes(n, handles))
+    with torch.cuda.device(dev):
+        bws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    reps = (_lib.Report * n)()
+    _lib.check(_lib.LIB.green_gw_iterate_batched(n, handles, arr, float(alpha), reps, bws.data_ptr(), nbytes,
+                                                 _stream(dev)), "green_gw_iterate_batched")
+    return [arr[i].mu for i in range(n)], [reps[i].as_dict() for i in range(n)]

@@ -74,3 +74,49 @@ def test_all_launches_in_bounds(lib, c, prec):
                                   None) == 0
     finally:
         lib.LIB.green_plan_destroy(h)
+
+
+@pytest.mark.parametrize("prec", [0, 2], ids=["fp64", "bf16x3"])
+def test_batched_iteration_in_bounds(lib, prec):
+    """The batched iteration records every system's contractions with the same validation and
+    groups them; with fake addresses nothing is launched."""
+    cases = [CASES[0], CASES[1], CASES[5], CASES[6]]
+    hs = [_plan(lib, c, prec) for c in cases]
+    try:
+        n = len(hs)
+        handles = (ctypes.c_void_p * n)(*[h.value for h in hs])
+        need = lib.LIB.green_batch_workspace_bytes(n, handles)
+        assert need > 0
+        systems = (lib.System * n)()
+        for i in range(n):
+            b = BASE + i * 16 * STEP
+            systems[i] = lib.System(b, b + STEP, b + 2 * STEP, b + 3 * STEP, b + 4 * STEP, b + 5 * STEP, 0.0, 3.0,
+                                    b + 6 * STEP)
+        reps = (lib.Report * n)()
+        bws = BASE + 100 * STEP
+        L = lib.LIB
+        assert L.green_gw_iterate_batched(n, handles, systems, 1.0, reps, bws, need, None) == 0
+        assert L.green_gw_iterate_batched(n, handles, systems, 1.0, reps, bws, need - 1, None) == -2  # ENOMEM
+        same_ws = (lib.System * 2)(systems[0], systems[0])
+        two = (ctypes.c_void_p * 2)(hs[0].value, hs[1].value)
+        assert L.green_gw_iterate_batched(2, two, same_ws, 1.0, reps, bws, need, None) == -1  # shared workspace
+        assert L.green_gw_iterate_batched(n, handles, systems, 2.5, reps, bws, need, None) == -1  # alpha
+    finally:
+        for h in hs:
+            lib.LIB.green_plan_destroy(h)
+
+
+def test_plan_options_and_tuning_report(lib):
+    h = _plan(lib, CASES[0], 0)
+    try:
+        L = lib.LIB
+        assert L.green_plan_set_option(h, lib.OPT_TUNE, 1) == 0
+        assert L.green_plan_set_option(h, lib.OPT_TUNE, 3) == -1
+        assert L.green_plan_set_option(h, lib.OPT_GRAPH, 1) == 0
+        assert L.green_plan_set_option(h, lib.OPT_GRAPH, 2) == -1
+        assert L.green_plan_set_option(h, 99, 0) == -1
+        buf = ctypes.create_string_buffer(4096)
+        assert L.green_plan_tuning_report(h, buf, len(buf)) == 0
+        assert buf.value == b""  # nothing tuned without device runs
+    finally:
+        lib.LIB.green_plan_destroy(h)
