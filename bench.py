@@ -73,7 +73,20 @@ def cpu_baseline(system, target_s: float):
             "seconds": dt}
 
 
-def run_precision(system, prec, steps, warmup, chunk_bytes=0):
+def tune_plan(plan, step, max_iters=60):
+    """Run untimed iterations with the autotuner on until every contraction shape has its kernel."""
+    plan.set_option("tune", 1)
+    for i in range(max_iters):
+        step()
+        rep = plan.tuning_report()
+        if rep and "tuning" not in rep:
+            break
+    plan.set_option("tune", 0)
+    print(f"[bench] tuned in {i + 1} iterations:\n{plan.tuning_report()}", file=sys.stderr, flush=True)
+    return i + 1
+
+
+def run_precision(system, prec, steps, warmup, chunk_bytes=0, tune=False, graph=False):
     """Time `steps` iterations (after `warmup`) at one contraction precision; returns a summary dict."""
     import numpy as np
     import torch
@@ -90,6 +103,17 @@ def run_precision(system, prec, steps, warmup, chunk_bytes=0):
         return (dev(system.G0), torch.zeros(plan.shape_H, dtype=torch.complex128, device="cuda:0"),
                 torch.zeros(plan.shape_G, dtype=torch.complex128, device="cuda:0"))
 
+    tuned = 0
+    if tune:
+        Gt, St, Sgt = fresh()
+        box = [0.0]
+
+        def tstep():
+            box[0], _ = plan.iterate(V, H0, S, Gt, St, Sgt, box[0], system.n_target, 1.0)
+        tuned = tune_plan(plan, tstep)
+        del Gt, St, Sgt
+    if graph:
+        plan.set_option("graph", 1)
     # accuracy reference point: one iteration from the common starting G
     G, Sinf, Sig = fresh()
     _, rep0 = plan.iterate(V, H0, S, G, Sinf, Sig, 0.0, system.n_target, 1.0)
@@ -114,7 +138,8 @@ def run_precision(system, prec, steps, warmup, chunk_bytes=0):
     torch.cuda.empty_cache()
 
     flops = contraction_flops(spec.nk, spec.nao, spec.naux, spec.ntau, spec.nspin)
-    sig_eval_s = sum((r["ms"][1] + r["ms"][2] + r["ms"][3]) for r in reps) / 1e3
+    # Sigma evaluation: polarization + screening + self-energy stages (with a graph: the whole replay)
+    sig_eval_s = sum((r["ms"][0] if graph else r["ms"][1] + r["ms"][2] + r["ms"][3]) for r in reps) / 1e3
     kern = []
     for slot in range(2):
         ms = sum(r["kern_ms"][slot] for r in reps)
@@ -132,12 +157,134 @@ def run_precision(system, prec, steps, warmup, chunk_bytes=0):
         "kern": kern,
         "last": reps[-1],
         "first": first,
+        "tune_iterations": tuned,
     }
 
 
 KERNEL_NAME = {"fp64": "zgemm_f64_kernel<2,2,Site::P0_Contract>",
                "fp32": "zgemm_mx_kernel<1,2,2,Site::P0_Contract>",
-               "bf16x3": "zgemm_mx_kernel<2,2,2,Site::P0_Contract>"}
+               "bf16x3": "zgemm_bt_kernel<3,3,false,Site::P0_Contract>"}
+
+
+def run_batch(args):
+    """The batching form: 16 independent systems of uneven sizes, one batched iteration per step (grouped
+    persistent launches, optionally replayed from a HIP graph), against 16 sequential FP64 solves."""
+    import numpy as np
+    import torch
+
+    from paper_2406_18479_amd.gw import Batch, Plan
+    from synth import configs, systems
+    from synth import device as dgen
+
+    specs = configs.batch_specs()
+    syss = []
+    for sp in specs:
+        y = systems.make_system(sp, with_V=False)
+        y.V_dev = dgen.make_V(sp, device="cuda:0")
+        syss.append(y)
+    torch.cuda.synchronize()
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")  # noqa: E731
+    chunk = 1 << 30
+
+    def fresh(y, p):
+        return dict(V=y.V_dev, H0=dev(y.H0), S=dev(y.S), G=dev(y.G0),
+                    Sinf=torch.zeros(p.shape_H, dtype=torch.complex128, device="cuda:0"),
+                    Sigma=torch.zeros(p.shape_G, dtype=torch.complex128, device="cuda:0"), mu=0.0,
+                    n_target=y.n_target)
+
+    def step1(p, st):
+        st["mu"], rep = p.iterate(st["V"], st["H0"], st["S"], st["G"], st["Sinf"], st["Sigma"], st["mu"],
+                                  st["n_target"], 1.0)
+        return rep
+
+    flops = sum(contraction_flops(sp.nk, sp.nao, sp.naux, sp.ntau, sp.nspin) for sp in specs)
+    # 16 sequential FP64 solves (plain per-system iterations, library-default kernels)
+    seq = 0.0
+    for y in syss:
+        sp = y.spec
+        p = Plan(sp.kmesh, sp.nao, sp.naux, y.grid, nspin=sp.nspin, prec="fp64", chunk_bytes=chunk)
+        st = fresh(y, p)
+        for _ in range(args.warmup):
+            step1(p, st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step1(p, st)
+        torch.cuda.synchronize()
+        seq += (time.perf_counter() - t0) / args.steps
+        p.close()
+        del p, st
+    print(f"[bench] 16 sequential FP64 solves: {seq:.3f} s/iteration", file=sys.stderr, flush=True)
+    res = {}
+    precs = ["fp64"] + [q for q in args.precisions.split(",") if q and q != "fp64"]
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        for prec in precs:
+            plans = [Plan(y.spec.kmesh, y.spec.nao, y.spec.naux, y.grid, nspin=y.spec.nspin, prec=prec,
+                          chunk_bytes=chunk) for y in syss]
+            if args.tune:
+                for p, y in zip(plans, syss):
+                    st = fresh(y, p)
+                    tune_plan(p, lambda: step1(p, st))
+                    del st
+            # accuracy point: one batched iteration from the common starting G of every system
+            states = [fresh(y, p) for y, p in zip(syss, plans)]
+            b = Batch(plans, states, use_graph=args.graph)
+            reps = b.iterate()
+            first = [(st["Sigma"].cpu().numpy(), r["e_tot"]) for st, r in zip(states, reps)]
+            b.close()
+            states = [fresh(y, p) for y, p in zip(syss, plans)]
+            b = Batch(plans, states, use_graph=args.graph)
+            for _ in range(args.warmup):
+                b.iterate()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sig_ms = 0.0
+            for i in range(args.steps):
+                reps = b.iterate()
+                sig_ms += reps[0]["ms"][7]
+                print(f"[bench] batched {prec} step {i}: Sigma-eval {reps[0]['ms'][7]:.1f} ms", file=sys.stderr,
+                      flush=True)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / args.steps
+            b.close()
+            for p in plans:
+                p.close()
+            del b, plans, states
+            torch.cuda.empty_cache()
+            res[prec] = dict(s_per_iteration=wall, sigma_eval_s=sig_ms / 1e3 / args.steps, first=first)
+    ref = res["fp64"]["first"]
+    for prec, r in res.items():
+        dE = max(abs(a[1] - b[1]) for a, b in zip(r["first"], ref))
+        dS = max(float(np.max(np.abs(a[0] - b[0]))) for a, b in zip(r["first"], ref))
+        r.update(d_energy_eh=dE, max_dsigma_vs_fp64_eh=dS, meets_bar=dE <= 1e-6 and dS <= 1e-5,
+                 sigma_eval_tflops=flops / r["sigma_eval_s"] / 1e12)
+    head = min((q for q in precs if res[q]["meets_bar"]), key=lambda q: res[q]["s_per_iteration"])
+    h = res[head]
+    return {
+        "metric": METRIC,
+        "value": round(h["sigma_eval_tflops"], 4),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(h["s_per_iteration"] * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[head],
+        "data": "synthetic",
+        "config": {"workload": "batch16_uneven_ntau104", "systems": [sp.name for sp in specs], "precision": head,
+                   "graph": bool(args.graph), "tuned": bool(args.tune)},
+        "s_per_iteration": round(h["s_per_iteration"], 6),
+        "sequential_fp64_s_per_iteration": round(seq, 6),
+        "speedup_vs_sequential_fp64": round(seq / h["s_per_iteration"], 3),
+        "aggregate_flops_per_iteration": flops,
+        "precisions": {q: {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items() if k != "first"}
+                       for q, r in res.items()},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
 # hardware MFMA products issued per algorithmic (4M) flop
 MFMA_PER_ALG = {"fp64": 1.0, "fp32": 1.0, "bf16x3": 3.0}
 
@@ -145,9 +292,12 @@ MFMA_PER_ALG = {"fp64": 1.0, "fp32": 1.0, "bf16x3": 3.0}
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="periodic2", choices=sorted(workloads()))
+    ap.add_argument("--workload", default="periodic3", choices=sorted(workloads()) + ["batch16"])
+    ap.add_argument("--tune", action="store_true", help="autotune every plan (untimed iterations) first")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay the Sigma evaluation from a HIP graph (runs on a non-default stream)")
     ap.add_argument("--precisions", default="fp64,fp32,bf16x3",
                     help="comma list; fp64 is always run first as the accuracy reference")
     ap.add_argument("--cpu-baseline-seconds", type=float, default=15.0)
@@ -180,6 +330,9 @@ def main():
         del src, dst
     import torch
 
+    if args.workload == "batch16":
+        print(json.dumps(run_batch(args)), flush=True)
+        return
     from synth import device as dgen
     spec = workloads()[args.workload]
     system = systems.make_system(spec, with_V=False)
@@ -187,7 +340,10 @@ def main():
     torch.cuda.synchronize()
     asked = [p for p in args.precisions.split(",") if p]
     precs = asked if args.no_reference else ["fp64"] + [p for p in asked if p != "fp64"]
-    res = {p: run_precision(system, p, args.steps, args.warmup, args.chunk_mib << 20) for p in precs}
+    side = torch.cuda.Stream() if args.graph else torch.cuda.current_stream()
+    with torch.cuda.stream(side):
+        res = {p: run_precision(system, p, args.steps, args.warmup, args.chunk_mib << 20, tune=args.tune,
+                                graph=args.graph) for p in precs}
     ref = res["fp64"]["first"] if "fp64" in res else None
     for p, r in res.items():
         if ref is None:
@@ -218,7 +374,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": spec.name, "nk": spec.nk, "kmesh": list(spec.kmesh), "nao": spec.nao,
                    "naux": spec.naux, "ntau": spec.ntau, "nspin": spec.nspin, "beta": spec.beta,
-                   "precision": head},
+                   "precision": head, "tuned": bool(args.tune), "graph": bool(args.graph)},
         "s_per_iteration": round(h["s_per_iteration"], 6),
         "fp64_s_per_iteration": round(res["fp64"]["s_per_iteration"], 6) if "fp64" in res else None,
         "speedup_vs_fp64": round(res["fp64"]["s_per_iteration"] / h["s_per_iteration"], 3) if "fp64" in res else None,

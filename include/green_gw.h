@@ -234,6 +234,18 @@ size_t green_batch_workspace_bytes(int nsys, green_plan* const* plans);
 int green_gw_iterate_batched(int nsys, green_plan* const* plans, green_system* systems, double alpha,
                              green_report* reports, void* batch_ws, size_t batch_ws_bytes, void* stream);
 
+/* Batch handle: the batched iteration of green_gw_iterate_batched recorded once for fixed systems and
+ * buffers, optionally replayed from a captured HIP graph (use_graph = 1; not on the default stream,
+ * where it replays eagerly).  The descriptor tables are uploaded into batch_ws at creation (device,
+ * caller-owned, must outlive the handle).  green_batch_iterate takes the same systems (same buffers,
+ * mu may change) and runs one iteration of all of them; reports as for green_gw_iterate_batched.
+ * Tuning choices of the plans are frozen at creation. */
+typedef struct green_batch green_batch;
+int green_batch_create(int nsys, green_plan* const* plans, const green_system* systems, double alpha, int use_graph,
+                       void* batch_ws, size_t batch_ws_bytes, void* stream, green_batch** out);
+int green_batch_iterate(green_batch* batch, green_system* systems, green_report* reports, void* stream);
+void green_batch_destroy(green_batch* batch);
+
 /* Human-readable text for a green_status. */
 const char* green_strerror(int status);
 

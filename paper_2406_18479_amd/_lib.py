@@ -68,7 +68,8 @@ OPT_GRAPH = 2
 EXPORTS = ["green_plan_create", "green_plan_destroy", "green_workspace_bytes", "green_gw_polarization",
            "green_gw_screen", "green_gw_selfenergy", "green_hf_static", "green_dyson", "green_gw_iterate",
            "green_plan_set_option", "green_plan_tuning_report", "green_batch_workspace_bytes",
-           "green_gw_iterate_batched", "green_strerror"]
+           "green_gw_iterate_batched", "green_batch_create", "green_batch_iterate", "green_batch_destroy",
+           "green_strerror"]
 
 
 def _load():
@@ -107,6 +108,13 @@ def _load():
     lib.green_gw_iterate_batched.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(System), dbl,
                                              ctypes.POINTER(Report), vp, ctypes.c_size_t, vp]
     lib.green_gw_iterate_batched.restype = i32
+    lib.green_batch_create.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(System), dbl, i32, vp,
+                                       ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    lib.green_batch_create.restype = i32
+    lib.green_batch_iterate.argtypes = [vp, ctypes.POINTER(System), ctypes.POINTER(Report), vp]
+    lib.green_batch_iterate.restype = i32
+    lib.green_batch_destroy.argtypes = [vp]
+    lib.green_batch_destroy.restype = None
     lib.green_strerror.argtypes = [i32]
     lib.green_strerror.restype = ctypes.c_char_p
     return lib

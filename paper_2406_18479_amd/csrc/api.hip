@@ -4,6 +4,7 @@
 #include <cmath>
 #include <functional>
 #include <map>
+#include <memory>
 #include <string>
 #include <cstdio>
 #include <cstdlib>
@@ -995,6 +996,33 @@ int count_ops(green_plan* p) {
 
 }  // namespace
 
+// A recorded batched Sigma evaluation: per-system launch lists, the grouped schedule and its device tables.
+struct BatchGroup {
+  size_t first, count;  // descriptors [first, first + count)
+  size_t start_off;     // tile offsets [start_off, start_off + count]
+};
+
+struct green_batch {
+  std::vector<green_plan*> plans;
+  std::vector<green_system> sys;
+  double alpha = 1.0;
+  std::vector<std::vector<Op>> ops;
+  std::vector<ZGemm> descs;
+  std::vector<std::vector<BatchGroup>> groups;
+  ZGemm* ddesc = nullptr;
+  int64_t* dstart = nullptr;
+  int use_graph = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ~green_batch() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+};
+
 // ====================================================================== exported
 extern "C" {
 
@@ -1309,115 +1337,166 @@ size_t green_batch_workspace_bytes(int nsys, green_plan* const* plans) {
   return 256 + n * (sizeof(ZGemm) + 2 * sizeof(int64_t)) + 4096;
 }
 
-int green_gw_iterate_batched(int nsys, green_plan* const* plans, green_system* sys, double alpha,
-                             green_report* reps, void* batch_ws, size_t batch_ws_bytes, void* stream) {
-  if (nsys <= 0 || !plans || !sys || !reps || !batch_ws) return GREEN_EINVAL;
-  if (!(alpha > 0.0 && alpha < 2.0)) return GREEN_EINVAL;
+int green_batch_create(int nsys, green_plan* const* plans, const green_system* sys, double alpha, int use_graph,
+                       void* batch_ws, size_t batch_ws_bytes, void* stream, green_batch** out) {
+  if (!out) return GREEN_EINVAL;
+  *out = nullptr;
+  if (nsys <= 0 || !plans || !sys || !batch_ws) return GREEN_EINVAL;
+  if (!(alpha > 0.0 && alpha < 2.0) || (use_graph != 0 && use_graph != 1)) return GREEN_EINVAL;
   if (batch_ws_bytes < green_batch_workspace_bytes(nsys, plans)) return GREEN_ENOMEM;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool dry = green::dryrun();
   for (int i = 0; i < nsys; ++i) {
-    green_system& y = sys[i];
+    const green_system& y = sys[i];
     GREEN_TRY(check_plan(plans[i], y.ws));
     if (!y.V || !y.H0 || !y.S || !y.G || !y.Sinf || !y.Sigma || !std::isfinite(y.mu)) return GREEN_EINVAL;
     for (int j = 0; j < i; ++j)
       if (plans[j] == plans[i] || sys[j].ws == y.ws) return GREEN_EINVAL;  // systems need their own plan and workspace
-    std::memset(&reps[i], 0, sizeof(green_report));
   }
+  std::unique_ptr<green_batch> bt(new (std::nothrow) green_batch());
+  if (!bt) return GREEN_ENOMEM;
+  bt->plans.assign(plans, plans + nsys);
+  bt->sys.assign(sys, sys + nsys);
+  bt->alpha = alpha;
   // 1. record the Sigma evaluation of every system
-  std::vector<std::vector<Op>> ops(nsys);
+  bt->ops.resize(nsys);
   size_t rounds = 0;
   for (int i = 0; i < nsys; ++i) {
     PlanScope scope(plans[i]);
     GREEN_TRY(ensure_bound(plans[i], sys[i].ws, s));
-    tl_rec = &ops[i];
+    tl_rec = &bt->ops[i];
     const int st = sigma_eval(plans[i], sys[i].V, sys[i].G, sys[i].Sinf, sys[i].Sigma, alpha, sys[i].ws, s, nullptr);
     tl_rec = nullptr;
     GREEN_TRY(st);
-    rounds = std::max(rounds, ops[i].size());
+    rounds = std::max(rounds, bt->ops[i].size());
   }
   // 2. schedule: round r holds the r-th launch of every system; its contractions are grouped by kernel variant
-  struct Group {
-    size_t first, count;  // descriptors [first, first + count) in `descs`
-    size_t start_off;     // offsets [start_off, start_off + count] in `starts`
-  };
-  std::vector<ZGemm> descs;
   std::vector<int64_t> starts;
-  std::vector<std::vector<Group>> groups(rounds);
+  bt->groups.resize(rounds);
   for (size_t r = 0; r < rounds; ++r) {
     std::vector<int> pending;
-    for (int i = 0; i < nsys; ++i)
-      if (r < ops[i].size() && ops[i][r].is_gemm && ops[i][r].g.M > 0 && ops[i][r].g.N > 0) pending.push_back(i);
+    for (int i = 0; i < nsys; ++i) {
+      const auto& ops = bt->ops[i];
+      if (r < ops.size() && ops[r].is_gemm && ops[r].g.M > 0 && ops[r].g.N > 0) pending.push_back(i);
+    }
     while (!pending.empty()) {
-      const green::Variant v = green::zgemm_variant(ops[pending[0]][r].g);
-      Group gr{descs.size(), 0, starts.size()};
+      const green::Variant v = green::zgemm_variant(bt->ops[pending[0]][r].g);
+      BatchGroup gr{bt->descs.size(), 0, starts.size()};
       std::vector<int> rest;
       int64_t tiles = 0;
       starts.push_back(0);
       for (int i : pending) {
-        const ZGemm& g = ops[i][r].g;
+        const ZGemm& g = bt->ops[i][r].g;
         if (!green::same_variant(v, green::zgemm_variant(g))) {
           rest.push_back(i);
           continue;
         }
-        descs.push_back(g);
+        bt->descs.push_back(g);
         tiles += green::zgemm_blocks(g);
         starts.push_back(tiles);
         gr.count += 1;
       }
-      groups[r].push_back(gr);
+      bt->groups[r].push_back(gr);
       pending.swap(rest);
     }
   }
-  const size_t need = 256 + descs.size() * sizeof(ZGemm) + starts.size() * sizeof(int64_t);
-  if (need > batch_ws_bytes) return GREEN_ENOMEM;
+  const size_t dbytes = (bt->descs.size() * sizeof(ZGemm) + 255) & ~(size_t)255;
+  if (dbytes + starts.size() * sizeof(int64_t) > batch_ws_bytes) return GREEN_ENOMEM;
   char* base = static_cast<char*>(batch_ws);
-  ZGemm* ddesc = reinterpret_cast<ZGemm*>(base);
-  int64_t* dstart = reinterpret_cast<int64_t*>(base + ((descs.size() * sizeof(ZGemm) + 255) & ~(size_t)255));
-  if (!dry && !descs.empty()) {
-    HIP_TRY(hipMemcpyAsync(ddesc, descs.data(), descs.size() * sizeof(ZGemm), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(dstart, starts.data(), starts.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  bt->ddesc = reinterpret_cast<ZGemm*>(base);
+  bt->dstart = reinterpret_cast<int64_t*>(base + dbytes);
+  if (!dry && !bt->descs.empty()) {
+    HIP_TRY(hipMemcpyAsync(bt->ddesc, bt->descs.data(), bt->descs.size() * sizeof(ZGemm), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(bt->dstart, starts.data(), starts.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
   }
-  // 3. replay round by round: one persistent launch per kernel variant, auxiliary launches per system
-  hipEvent_t e0 = nullptr, e1 = nullptr;
+  bt->use_graph = use_graph && !dry && s != nullptr;
   if (!dry) {
-    HIP_TRY(hipEventCreate(&e0));
-    if (hipEventCreate(&e1) != hipSuccess) {
-      (void)hipEventDestroy(e0);
-      return GREEN_EHIP;
-    }
+    HIP_TRY(hipEventCreate(&bt->e0));
+    HIP_TRY(hipEventCreate(&bt->e1));
   }
-  struct EvGuard {
-    hipEvent_t a, b;
-    ~EvGuard() {
-      if (a) (void)hipEventDestroy(a);
-      if (b) (void)hipEventDestroy(b);
-    }
-  } guard{e0, e1};
-  if (!dry) HIP_TRY(hipEventRecord(e0, s));
-  for (size_t r = 0; r < rounds; ++r) {
-    for (const Group& gr : groups[r])
-      HIP_TRY(green::zgemm_group(descs.data() + gr.first, (int)gr.count, ddesc + gr.first, dstart + gr.start_off, s));
-    for (int i = 0; i < nsys; ++i)
-      if (r < ops[i].size() && !ops[i][r].is_gemm && !dry) HIP_TRY(ops[i][r].aux(s));
-  }
-  if (!dry) HIP_TRY(hipEventRecord(e1, s));
-  // 4. close every system's iteration: Dyson, chemical potential, energy
+  *out = bt.release();
+  return GREEN_OK;
+}
+
+int green_batch_iterate(green_batch* bt, green_system* sys, green_report* reps, void* stream) {
+  if (!bt || !sys || !reps) return GREEN_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool dry = green::dryrun();
+  const int nsys = (int)bt->plans.size();
   for (int i = 0; i < nsys; ++i) {
-    PlanScope scope(plans[i]);
-    GREEN_TRY(ensure_bound(plans[i], sys[i].ws, s));
-    GREEN_TRY(close_iteration(plans[i], sys[i].H0, sys[i].S, sys[i].G, sys[i].Sinf, sys[i].Sigma, &sys[i].mu,
+    const green_system& a = sys[i];
+    const green_system& b = bt->sys[i];
+    if (a.V != b.V || a.H0 != b.H0 || a.S != b.S || a.G != b.G || a.Sinf != b.Sinf || a.Sigma != b.Sigma ||
+        a.ws != b.ws || !std::isfinite(a.mu))
+      return GREEN_EINVAL;  // the schedule was recorded for these buffers
+    std::memset(&reps[i], 0, sizeof(green_report));
+  }
+  // replay round by round: one persistent launch per kernel variant, auxiliary launches per system
+  auto replay = [&]() -> int {
+    for (size_t r = 0; r < bt->groups.size(); ++r) {
+      for (const BatchGroup& gr : bt->groups[r])
+        HIP_TRY(green::zgemm_group(bt->descs.data() + gr.first, (int)gr.count, bt->ddesc + gr.first,
+                                   bt->dstart + gr.start_off, s));
+      for (int i = 0; i < nsys; ++i)
+        if (r < bt->ops[i].size() && !bt->ops[i][r].is_gemm && !dry) HIP_TRY(bt->ops[i][r].aux(s));
+    }
+    return GREEN_OK;
+  };
+  for (int i = 0; i < nsys; ++i) GREEN_TRY(ensure_bound(bt->plans[i], sys[i].ws, s));
+  if (!dry) HIP_TRY(hipEventRecord(bt->e0, s));
+  if (bt->use_graph) {
+    if (!bt->gexec) {
+      hipGraph_t gr = nullptr;
+      HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      tl_capturing = true;
+      const int st = replay();
+      tl_capturing = false;
+      const hipError_t ce = hipStreamEndCapture(s, &gr);
+      if (st != GREEN_OK) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return st;
+      }
+      if (ce != hipSuccess) return GREEN_EHIP;
+      if (hipGraphInstantiate(&bt->gexec, gr, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(gr);
+        return GREEN_EHIP;
+      }
+      bt->graph = gr;
+    }
+    HIP_TRY(hipGraphLaunch(bt->gexec, s));
+  } else {
+    GREEN_TRY(replay());
+  }
+  if (!dry) HIP_TRY(hipEventRecord(bt->e1, s));
+  // close every system's iteration: Dyson, chemical potential, energy
+  for (int i = 0; i < nsys; ++i) {
+    PlanScope scope(bt->plans[i]);
+    GREEN_TRY(ensure_bound(bt->plans[i], sys[i].ws, s));
+    GREEN_TRY(close_iteration(bt->plans[i], sys[i].H0, sys[i].S, sys[i].G, sys[i].Sinf, sys[i].Sigma, &sys[i].mu,
                               sys[i].n_target, &reps[i], sys[i].ws, s));
   }
   if (dry) return GREEN_OK;
   HIP_TRY(hipStreamSynchronize(s));
   float ms = 0.f;
-  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  HIP_TRY(hipEventElapsedTime(&ms, bt->e0, bt->e1));
   for (int i = 0; i < nsys; ++i) {
     reps[i].ms[7] = ms;  // Sigma evaluation of the whole batch
     if (!std::isfinite(reps[i].e_tot) || !std::isfinite(reps[i].max_dsigma)) return GREEN_ENAN;
   }
   return GREEN_OK;
+}
+
+void green_batch_destroy(green_batch* bt) { delete bt; }
+
+int green_gw_iterate_batched(int nsys, green_plan* const* plans, green_system* sys, double alpha,
+                             green_report* reps, void* batch_ws, size_t batch_ws_bytes, void* stream) {
+  if (nsys <= 0 || !plans || !sys || !reps) return GREEN_EINVAL;
+  green_batch* bt = nullptr;
+  GREEN_TRY(green_batch_create(nsys, plans, sys, alpha, 0, batch_ws, batch_ws_bytes, stream, &bt));
+  const int st = green_batch_iterate(bt, sys, reps, stream);
+  green_batch_destroy(bt);
+  return st;
 }
 
 }  // extern "C"

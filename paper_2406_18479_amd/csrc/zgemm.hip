@@ -890,7 +890,11 @@ __device__ __forceinline__ void group_loop(const GroupArgs& a, F&& body) {
   for (int64_t t = blockIdx.x; t < a.total; t += gridDim.x) {
     int d = 0;
     while (d + 1 < a.n && a.start[d + 1] <= t) ++d;
-    body(a.gs[d], t - a.start[d], a.start[d + 1] - a.start[d]);
+    // read the descriptor through the constant address space: its fields are invariant for the launch,
+    // so they stay in scalar registers or the scalar cache across the body's barriers
+    typedef const __attribute__((address_space(4))) ZGemm CZ;
+    CZ* cg = (CZ*)(a.gs);
+    body(*(const ZGemm*)(cg + d), t - a.start[d], a.start[d + 1] - a.start[d]);
   }
 }
 template <int WM, int WN>

@@ -160,18 +160,11 @@ class Plan:
         return m.value, rep.as_dict()
 
 
-def iterate_batched(plans, systems, alpha=1.0):
-    """One iteration of several independent systems (green_gw_iterate_batched).
-
-    plans: list of Plan (one per system, each with its own workspace), all on one device.
-    systems: list of dicts with keys V, H0, S, G, Sinf, Sigma (tensors; G, Sinf, Sigma updated in place),
-    mu (float) and n_target (float).  Returns (list of mu, list of report dicts).
-    """
+def _systems_array(plans, systems):
     if len(plans) != len(systems) or not plans:
         raise ValueError("plans and systems must be non-empty lists of equal length")
     dev = plans[0].device
     n = len(plans)
-    handles = (ctypes.c_void_p * n)(*[p._h.value for p in plans])
     arr = (_lib.System * n)()
     for i, (p, y) in enumerate(zip(plans, systems)):
         if p.device != dev:
@@ -180,6 +173,19 @@ def iterate_batched(plans, systems, alpha=1.0):
                              _ptr(y["S"], p.shape_S, "S", dev), _ptr(y["G"], p.shape_G, "G", dev),
                              _ptr(y["Sinf"], p.shape_H, "Sinf", dev), _ptr(y["Sigma"], p.shape_G, "Sigma", dev),
                              float(y["mu"]), float(y["n_target"]), p.ws.data_ptr())
+    return dev, arr
+
+
+def iterate_batched(plans, systems, alpha=1.0):
+    """One iteration of several independent systems (green_gw_iterate_batched).
+
+    plans: list of Plan (one per system, each with its own workspace), all on one device.
+    systems: list of dicts with keys V, H0, S, G, Sinf, Sigma (tensors; G, Sinf, Sigma updated in place),
+    mu (float) and n_target (float).  Returns (list of mu, list of report dicts).
+    """
+    dev, arr = _systems_array(plans, systems)
+    n = len(plans)
+    handles = (ctypes.c_void_p * n)(*[p._h.value for p in plans])
     nbytes = int(_lib.LIB.green_batch_workspace_bytes(n, handles))
     with torch.cuda.device(dev):
         bws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
@@ -187,3 +193,44 @@ def iterate_batched(plans, systems, alpha=1.0):
     _lib.check(_lib.LIB.green_gw_iterate_batched(n, handles, arr, float(alpha), reps, bws.data_ptr(), nbytes,
                                                  _stream(dev)), "green_gw_iterate_batched")
     return [arr[i].mu for i in range(n)], [reps[i].as_dict() for i in range(n)]
+
+
+class Batch:
+    """A batched iteration recorded once for fixed systems (green_batch_create); `iterate` runs one
+    iteration of every system, replayed from a HIP graph when use_graph (on a non-default stream)."""
+
+    def __init__(self, plans, systems, alpha=1.0, use_graph=False):
+        self.plans, self.systems = list(plans), list(systems)
+        self.device, arr = _systems_array(self.plans, self.systems)
+        n = len(self.plans)
+        self._handles = (ctypes.c_void_p * n)(*[p._h.value for p in self.plans])
+        nbytes = int(_lib.LIB.green_batch_workspace_bytes(n, self._handles))
+        with torch.cuda.device(self.device):
+            self.ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        _lib.check(_lib.LIB.green_batch_create(n, self._handles, arr, float(alpha), int(bool(use_graph)),
+                                               self.ws.data_ptr(), nbytes, _stream(self.device), ctypes.byref(h)),
+                   "green_batch_create")
+        self._h = h
+
+    def iterate(self):
+        """One iteration of all systems; updates G, Sinf, Sigma in place and each system's "mu".
+        Returns the list of report dicts."""
+        _, arr = _systems_array(self.plans, self.systems)
+        n = len(self.plans)
+        reps = (_lib.Report * n)()
+        _lib.check(_lib.LIB.green_batch_iterate(self._h, arr, reps, _stream(self.device)), "green_batch_iterate")
+        for i, y in enumerate(self.systems):
+            y["mu"] = arr[i].mu
+        return [reps[i].as_dict() for i in range(n)]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.LIB.green_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
