@@ -86,10 +86,20 @@ def tune_plan(plan, step, max_iters=60):
     return i + 1
 
 
-def run_precision(system, prec, steps, warmup, chunk_bytes=0, tune=False, graph=False):
+def run_precision(system, prec, steps, warmup, chunk_bytes=0, tune=False, graph=False, accuracy_point=True,
+                  sample_max_bytes=1 << 30):
     """Time `steps` iterations (after `warmup`) at one contraction precision; returns a summary dict."""
     import numpy as np
     import torch
+
+    def sample(Sig):
+        """Sigma~ on the host: all of it, or for large systems a fixed subset of (spin, tau, k) blocks."""
+        if Sig.numel() * 16 <= sample_max_bytes:
+            return Sig.cpu().numpy()
+        ns, nt, nk = Sig.shape[:3]
+        ts = sorted({0, nt // 3, nt // 2, nt - 1})
+        ks = sorted({0, nk // 2, nk - 1})
+        return Sig[:, ts][:, :, ks].cpu().numpy()
 
     from paper_2406_18479_amd.gw import Plan
 
@@ -114,10 +124,14 @@ def run_precision(system, prec, steps, warmup, chunk_bytes=0, tune=False, graph=
         del Gt, St, Sgt
     if graph:
         plan.set_option("graph", 1)
-    # accuracy reference point: one iteration from the common starting G
-    G, Sinf, Sig = fresh()
-    _, rep0 = plan.iterate(V, H0, S, G, Sinf, Sig, 0.0, system.n_target, 1.0)
-    first = {"sigma": Sig.cpu().numpy(), "e_tot": rep0["e_tot"]}
+    # accuracy reference point: one iteration from the common starting G (with warmup = 0 and no separate
+    # accuracy point, the first timed step is that iteration)
+    first = None
+    if accuracy_point or warmup > 0:
+        G, Sinf, Sig = fresh()
+        _, rep0 = plan.iterate(V, H0, S, G, Sinf, Sig, 0.0, system.n_target, 1.0)
+        first = {"sigma": sample(Sig), "e_tot": rep0["e_tot"], "mu": rep0["mu"]}
+        del G, Sinf, Sig
     # timed run
     G, Sinf, Sig = fresh()
     mu = 0.0
@@ -129,6 +143,8 @@ def run_precision(system, prec, steps, warmup, chunk_bytes=0, tune=False, graph=
     for i in range(steps):
         mu, rep = plan.iterate(V, H0, S, G, Sinf, Sig, mu, system.n_target, 1.0)
         reps.append(rep)
+        if first is None:
+            first = {"sigma": sample(Sig), "e_tot": rep["e_tot"], "mu": rep["mu"]}
         print(f"[bench] {prec} step {i}: {rep['ms'][7]:.1f} ms  E_tot={rep['e_tot']:.10f}", file=sys.stderr,
               flush=True)
     torch.cuda.synchronize()
@@ -296,6 +312,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="periodic3", choices=sorted(workloads()) + ["batch16"])
     ap.add_argument("--tune", action="store_true", help="autotune every plan (untimed iterations) first")
+    ap.add_argument("--save-sample", default="",
+                    help="write the first-iteration energy and Sigma~ sample of each precision to this .npz")
+    ap.add_argument("--reference-sample", default="",
+                    help="FP64 first-iteration sample (.npz from --save-sample) to measure the errors against, "
+                         "for workloads whose FP64 run is made in a separate process")
     ap.add_argument("--graph", action="store_true",
                     help="replay the Sigma evaluation from a HIP graph (runs on a non-default stream)")
     ap.add_argument("--precisions", default="fp64,fp32,bf16x3",
@@ -336,15 +357,26 @@ def main():
     from synth import device as dgen
     spec = workloads()[args.workload]
     system = systems.make_system(spec, with_V=False)
+    t0 = time.perf_counter()
     system.V_dev = dgen.make_V(spec, device="cuda:0")  # generated in HBM (same draws as the host generator)
     torch.cuda.synchronize()
+    print(f"[bench] {spec.name}: V ({system.V_dev.numel() * 16 / 1e9:.1f} GB) generated on the device in "
+          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     asked = [p for p in args.precisions.split(",") if p]
     precs = asked if args.no_reference else ["fp64"] + [p for p in asked if p != "fp64"]
     side = torch.cuda.Stream() if args.graph else torch.cuda.current_stream()
     with torch.cuda.stream(side):
         res = {p: run_precision(system, p, args.steps, args.warmup, args.chunk_mib << 20, tune=args.tune,
-                                graph=args.graph) for p in precs}
+                                graph=args.graph, accuracy_point=not args.no_reference) for p in precs}
+    if args.save_sample:
+        np.savez(args.save_sample, **{f"{p}_{k}": np.asarray(v) for p, r in res.items() for k, v in r["first"].items()},
+                 **{f"{p}_s_per_iteration": r["s_per_iteration"] for p, r in res.items()})
     ref = res["fp64"]["first"] if "fp64" in res else None
+    fp64_spi = res["fp64"]["s_per_iteration"] if "fp64" in res else None
+    if ref is None and args.reference_sample:
+        z = np.load(args.reference_sample)
+        ref = {"sigma": z["fp64_sigma"], "e_tot": float(z["fp64_e_tot"])}
+        fp64_spi = float(z["fp64_s_per_iteration"])
     for p, r in res.items():
         if ref is None:
             r["d_energy"] = r["max_dsigma_vs_fp64"] = None
@@ -376,8 +408,8 @@ def main():
                    "naux": spec.naux, "ntau": spec.ntau, "nspin": spec.nspin, "beta": spec.beta,
                    "precision": head, "tuned": bool(args.tune), "graph": bool(args.graph)},
         "s_per_iteration": round(h["s_per_iteration"], 6),
-        "fp64_s_per_iteration": round(res["fp64"]["s_per_iteration"], 6) if "fp64" in res else None,
-        "speedup_vs_fp64": round(res["fp64"]["s_per_iteration"] / h["s_per_iteration"], 3) if "fp64" in res else None,
+        "fp64_s_per_iteration": round(fp64_spi, 6) if fp64_spi else None,
+        "speedup_vs_fp64": round(fp64_spi / h["s_per_iteration"], 3) if fp64_spi else None,
         "precisions": {p: {"sigma_eval_tflops": round(r["sigma_eval_tflops"], 4),
                            "s_per_iteration": round(r["s_per_iteration"], 6),
                            "d_energy_eh": r["d_energy"], "max_dsigma_vs_fp64_eh": r["max_dsigma_vs_fp64"],

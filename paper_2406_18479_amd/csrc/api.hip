@@ -168,6 +168,7 @@ thread_local SplitBuf tl_split;
 thread_local green_plan* tl_plan = nullptr;
 thread_local bool tl_capturing = false;
 
+
 int ensure_bound(green_plan* p, void* ws, hipStream_t s) {
   tl_split.ptr = reinterpret_cast<double2*>(static_cast<char*>(ws) + p->r_split.off);
   tl_split.cap = (int64_t)(p->r_split.bytes / sizeof(double2));
@@ -256,6 +257,19 @@ int aux(hipStream_t s, F&& f) {
   }
   if (green::dryrun()) return GREEN_OK;
   return hip_status(f(s));
+}
+
+// GREEN_PROGRESS=1: long stages wait for each q-slab and report it on stderr (for runs of many minutes).
+int progress(const char* stage, int q, int nq, hipStream_t s) {
+  static const bool on = [] {
+    const char* e = std::getenv("GREEN_PROGRESS");
+    return e && e[0] == '1';
+  }();
+  if (!on || tl_rec || tl_capturing || green::dryrun()) return GREEN_OK;
+  if (hipStreamSynchronize(s) != hipSuccess) return GREEN_EHIP;
+  std::fprintf(stderr, "[green] %s q-slab %d/%d done\n", stage, q + 1, nq);
+  std::fflush(stderr);
+  return GREEN_OK;
 }
 
 // Split the K range when the output tiles alone cannot fill the GPU (256 CUs): aim for ~2048
@@ -515,6 +529,7 @@ int run_polarization(green_plan* p, const void* V, const void* G, void* P0, void
                        cplx(sp == 0 ? 0.0 : 1.0), s, p->prec, green::kC64, bf ? p->big_p0 : 0));
       }
     }
+    GREEN_TRY(progress("polarization", q, nk, s));
   }
   return GREEN_OK;
 }
@@ -630,6 +645,7 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
                        green::kC64));
       }
     }
+    GREEN_TRY(progress("self-energy", q, nk, s));
   }
   return GREEN_OK;
 }

@@ -1,4 +1,4 @@
-// Batched complex FP64 GEMM on CDNA matrix cores (v_mfma_f64_16x16x4f64), 4M form.
+// Batched complex FP64 GEMM on CDNA matrix cores (v_mfma_f64_16x16x4f64), 3M form.
 //
 // Every contraction of the GW hot path (the P~0 and Sigma~ stages, the
 // Matsubara transforms, the Hartree-Fock terms) is a batched GEMM whose
@@ -9,9 +9,10 @@
 // Tiling: a 256-thread workgroup (4 waves in a 2 x 2 grid) computes a
 // (32 WM) x (32 WN) tile; each wave owns WM x WN blocks of 16 x 16.  The K
 // loop stages 8-deep complex slabs of A and B through LDS (double buffered,
-// conjugation applied when staging), and each 4-deep sub-slab issues four
-// real MFMAs per block:
-//   C_re += A_re B_re - A_im B_im,   C_im += A_re B_im + A_im B_re.
+// conjugation applied when staging), and each 4-deep sub-slab issues three
+// real MFMAs per block (3M form):
+//   t1 += A_re B_re,  t2 += A_im B_im,  t3 += (A_re + A_im)(B_re + B_im);
+//   C_re = t1 - t2,   C_im = t3 - t1 - t2.
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -164,13 +165,17 @@ __device__ __forceinline__ void f64_body(const ZGemm& g, int64_t bid) {
     for (int e = 0; e < EB; ++e) Bs[buf][b_k[e]][b_n[e]] = rb[e];
   };
 
-  d4 acc_re[WM][WN], acc_im[WM][WN];
+  // 3M complex product (three real MFMA chains instead of four):
+  //   t1 = sum a_re b_re,  t2 = sum a_im b_im,  t3 = sum (a_re + a_im)(b_re + b_im),
+  //   C_re = t1 - t2,      C_im = t3 - t1 - t2.
+  d4 t1[WM][WN], t2[WM][WN], t3[WM][WN];
 #pragma unroll
   for (int i = 0; i < WM; ++i)
 #pragma unroll
     for (int j = 0; j < WN; ++j) {
-      acc_re[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-      acc_im[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      t1[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      t2[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      t3[i][j] = d4{0.0, 0.0, 0.0, 0.0};
     }
 
   const int wr = wave & 1, wc = wave >> 1;
@@ -186,29 +191,42 @@ __device__ __forceinline__ void f64_body(const ZGemm& g, int64_t bid) {
     for (int s = 0; s < 2; ++s) {
       const int kr = 4 * s + (lane >> 4);
       double2 af[WM], bf[WN];
+      double as[WM], bs[WN];
 #pragma unroll
-      for (int i = 0; i < WM; ++i) af[i] = As[buf][kr][rowb + 16 * i + (lane & 15)];
+      for (int i = 0; i < WM; ++i) {
+        af[i] = As[buf][kr][rowb + 16 * i + (lane & 15)];
+        as[i] = af[i].x + af[i].y;
+      }
 #pragma unroll
-      for (int j = 0; j < WN; ++j) bf[j] = Bs[buf][kr][colb + 16 * j + (lane & 15)];
-      // two passes over the blocks so that consecutive MFMAs never chain on one accumulator
+      for (int j = 0; j < WN; ++j) {
+        bf[j] = Bs[buf][kr][colb + 16 * j + (lane & 15)];
+        bs[j] = bf[j].x + bf[j].y;
+      }
+      // one pass per chain so that consecutive MFMAs never chain on one accumulator
 #pragma unroll
       for (int i = 0; i < WM; ++i)
 #pragma unroll
-        for (int j = 0; j < WN; ++j) {
-          acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i].x, bf[j].x, acc_re[i][j], 0, 0, 0);
-          acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i].x, bf[j].y, acc_im[i][j], 0, 0, 0);
-        }
+        for (int j = 0; j < WN; ++j) t1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i].x, bf[j].x, t1[i][j], 0, 0, 0);
 #pragma unroll
       for (int i = 0; i < WM; ++i)
 #pragma unroll
-        for (int j = 0; j < WN; ++j) {
-          acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-af[i].y, bf[j].y, acc_re[i][j], 0, 0, 0);
-          acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i].y, bf[j].x, acc_im[i][j], 0, 0, 0);
-        }
+        for (int j = 0; j < WN; ++j) t2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i].y, bf[j].y, t2[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) t3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(as[i], bs[j], t3[i][j], 0, 0, 0);
     }
     if (it + 1 < nkt) stage(buf ^ 1);
     __syncthreads();
   }
+  d4 acc_re[WM][WN], acc_im[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      acc_re[i][j] = t1[i][j] - t2[i][j];
+      acc_im[i][j] = t3[i][j] - t1[i][j] - t2[i][j];
+    }
 
   // ---- epilogue: v_mfma_f64_16x16x4f64 leaves row (lane/16) + 4 r, column lane % 16 of each 16 x 16 block
   //      in element r of the lane's accumulator
@@ -867,7 +885,7 @@ __global__ __launch_bounds__(256) void zgemm_splitk_reduce(const ZGemm g) {
 // per contraction), or a group of independent GEMMs of one variant in one persistent launch: a grid of
 // workgroups walks the concatenated tile ranges of all descriptors.
 template <int WM, int WN, Site SITE>
-__global__ __launch_bounds__(256) void zgemm_f64_kernel(const ZGemm g) {
+__global__ __launch_bounds__(256, 2) void zgemm_f64_kernel(const ZGemm g) {
   f64_body<WM, WN>(g, blockIdx.x);
 }
 template <int MODE, int WM, int WN, Site SITE>
