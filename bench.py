@@ -311,7 +311,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="periodic3", choices=sorted(workloads()) + ["batch16"])
-    ap.add_argument("--tune", action="store_true", help="autotune every plan (untimed iterations) first")
+    ap.add_argument("--no-tune", dest="tune", action="store_false",
+                    help="skip the autotuner (by default every plan is tuned in untimed iterations first)")
     ap.add_argument("--save-sample", default="",
                     help="write the first-iteration energy and Sigma~ sample of each precision to this .npz")
     ap.add_argument("--reference-sample", default="",

@@ -42,7 +42,7 @@ struct TuneEntry {
   std::vector<TuneCand> cands;
   std::vector<float> ms;  // time of each candidate's trial launch
   std::vector<hipEvent_t> ev;
-  int trial = 0;
+  int trial = 0;          // next candidate to time; -1 before the untimed first call
   bool done = false;
   int chosen = 0;
   int64_t calls = 0;
@@ -379,8 +379,14 @@ int gemm(green::Site site, const char* label, const ZOp& A, const green::Span& s
       if (te->cands.empty()) {
         te->cands = tune_candidates(g);
         te->ms.assign(te->cands.size(), 0.f);
+        te->trial = -1;  // the first call runs the default untimed (code loading, first touch)
       }
-      apply_cand(g, te->cands[te->trial]);
+      if (te->trial < 0) {
+        te->trial = 0;
+        te = nullptr;
+      } else {
+        apply_cand(g, te->cands[te->trial]);
+      }
     }
   }
   if (te) {
@@ -627,14 +633,14 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
                         : op(Pp + ((int64_t)q * ntau + t0) * nP, flat(1), flat(naux), bflat(nP)),
                      bf ? sPtx : sP, op(Vqn, flat(nG), two((int32_t)nG, 1, nV), bnone(), mixed ? vt : green::kC64),
                      sVa, T1, sT1, flat(nG), two((int32_t)nG, 1, nV), bflat((int64_t)nk * nV), naux,
-                     (int)(nk * nG), naux, tcn, cplx(1), cplx(0), s, p->prec, xt, bf ? 2 : 0));
+                     (int)(nk * nG), naux, tcn, cplx(1), cplx(0), s, p->prec, xt, bf ? 1 : 0));
       for (int sp = 0; sp < ns; ++sp) {
         // Y[tt][k][(Q',i)][b] = sum_a X[tt][k][(Q',i)][a] G^{k-q}_{ab}(tau)
         GREEN_TRY(gemm(green::Site::Sig_XG, "Sigma.XG", op(T1, flat(nao), flat(1), bflat(nV), xt), sT1,
                        op(eptr(Gs, gt, ((int64_t)sp * ntau + t0) * nk * nG), flat(nao), flat(1),
                           btwo(nk, nG, ksub + q * nk, (int64_t)nk * nG, hsub + q * nk), gt),
                        sGs, T2, sT2, flat(nao), flat(1), bflat(nV), naux * nao, nao, nao, tcn * nk, cplx(1), cplx(0),
-                       s, stage, xt));
+                       s, stage, xt, bf ? 2 : 0));
         // Sigma[s][t][k][i][j] += -(1/nk) sum_{(Q',b)} Y[tt][k][Q'][i][b] V^{k-q,k}_{bj}(Q'): one GEMM per k
         // with the tau nodes folded into M = (tt, i), so each V block is read once per chunk
         GREEN_TRY(gemm(green::Site::Sig_YV, "Sigma.YV",
