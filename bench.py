@@ -305,6 +305,20 @@ def run_batch(args):
 MFMA_PER_ALG = {"fp64": 1.0, "fp32": 1.0, "bf16x3": 3.0}
 
 
+def measured_traffic(workload: str, precision: str, kernel: str):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary (FETCH_SIZE +
+    WRITE_SIZE, copy-calibrated), when it covers this workload, precision and kernel; else None."""
+    import glob
+    for f in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.md")):
+        for line in open(f):
+            if line.startswith("traffic_bytes_per_launch:"):
+                tok = line.split()
+                kv = dict(t.split("=", 1) for t in tok[2:])
+                if kv.get("workload") == workload and kv.get("precision") == precision and kv.get("kernel") == kernel:
+                    return float(tok[1])
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -424,7 +438,8 @@ def main():
                    "n_elec": h["last"]["n_elec"], "max_dsigma": h["last"]["max_dsigma"]},
         "roofline": {"bound": "mfma", "kernel": KERNEL_NAME[head], "achieved": round(achieved, 4), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                     "mfma_frac": round(achieved * MFMA_PER_ALG[head] / peak, 4), "traffic": None,
+                     "mfma_frac": round(achieved * MFMA_PER_ALG[head] / peak, 4),
+                     "traffic": measured_traffic(spec.name, head, KERNEL_NAME[head]) if args.tune else None,
                      "launches": k["launches"], "avg_launch_ms": round(k["ms"] / max(k["launches"], 1), 4),
                      "flops_per_launch": k["flops"] / max(k["launches"], 1)},
         "cpu_baseline": None,
