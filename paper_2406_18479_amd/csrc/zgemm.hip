@@ -348,6 +348,20 @@ __device__ __forceinline__ void store_c(const ZGemm& g, int64_t off, double2 v) 
   }
 }
 
+// Store of an FP32 accumulator pair by the descriptor's ctype.  A split-BF16 output (beta == 0) is scaled and
+// split in FP32 (the accumulator carries FP32 precision; hi + lo keeps 2^-17 of it); other outputs go through
+// the FP64 path below.
+__device__ __forceinline__ void store_cf(const ZGemm& g, int64_t off, float re, float im) {
+  if (g.ctype == kCB16) {
+    const float ar = (float)g.alpha.x, ai = (float)g.alpha.y;
+    const float o_re = ar * re - ai * im, o_im = ar * im + ai * re;
+    uint2 w;
+    split_pair_f(o_re, o_im, w.x, w.y);
+    reinterpret_cast<uint2*>(g.C)[off] = w;
+  } else {
+    store_c(g, off, make_double2((double)re, (double)im));
+  }
+}
 template <int MODE, int WM, int WN>
 __device__ __forceinline__ void mx_body(const ZGemm& g, int64_t bid) {
   constexpr int BM = 32 * WM, BN = 32 * WN, BK = 16;  // BK complex K per stage
@@ -598,7 +612,7 @@ __device__ __forceinline__ void mx_body(const ZGemm& g, int64_t bid) {
 #pragma unroll
       for (int j = 0; j < WN; ++j) {
         const int gn = n0 + colb + 16 * j + (lane & 15);
-        if (gn < g.N) store_c(g, roff + coff[j], make_double2((double)acc_re[i][j][r], (double)acc_im[i][j][r]));
+        if (gn < g.N) store_cf(g, roff + coff[j], acc_re[i][j][r], acc_im[i][j][r]);
       }
     }
 }
@@ -853,7 +867,7 @@ __device__ __forceinline__ void bt_body(const ZGemm& g, int64_t bid0, int64_t nb
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
         const int gn = n0 + colb + 16 * j + (lane & 15);
-        if (gn < g.N) store_c(g, roff + coff[j], make_double2((double)acc_re[i][j][r], (double)acc_im[i][j][r]));
+        if (gn < g.N) store_cf(g, roff + coff[j], acc_re[i][j][r], acc_im[i][j][r]);
       }
     }
 }
