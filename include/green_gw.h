@@ -184,6 +184,33 @@ int green_dyson(green_plan* plan, const void* H0, const void* S, const void* Sin
 int green_gw_iterate(green_plan* plan, const void* V, const void* H0, const void* S, void* G, void* Sinf, void* Sigma,
                      double* mu, double n_target, double alpha, green_report* report, void* ws, void* stream);
 
+/* DIIS convergence acceleration (Sec. 4.2.2): the self-energy entering Dyson is a linear combination of the
+ * self-energies of the last iterations, Sigma_n = sum_i c_i Sigma[G_{i-1}], with sum_i c_i = 1 and c minimising
+ * |sum_i c_i r_i|^2 over the residuals r_i = Sigma[G_{i-1}] - Sigma_{i-1} (both Sigma^inf and Sigma~(tau),
+ * Frobenius inner product, real part; the Gram matrix is scaled by its largest diagonal element and the
+ * (m + 1)-dimensional Lagrange system solved on the host by elimination with partial pivoting).  Iterations
+ * before `start` use the static mixing of green_gw_iterate (alpha) but are stored.
+ * The caller owns the state (zero it, then set size in [2, 16] and start >= 0) and a device history buffer of
+ * green_diis_history_bytes(plan, size) bytes that persists across the iterations. */
+typedef struct {
+  int32_t size;      /* most stored self-energies                                          */
+  int32_t start;     /* first iteration (0-based) that extrapolates                       */
+  int32_t count;     /* stored self-energies (updated by the library)                     */
+  int32_t next;      /* ring slot of the next one (library)                               */
+  int32_t iter;      /* iterations done (library)                                         */
+  int32_t pad;
+  double B[16][16];  /* Gram matrix of the stored residuals, by ring slot (library)       */
+  double coef[16];   /* coefficients of the last extrapolation, oldest first (library)    */
+} green_diis;
+
+size_t green_diis_history_bytes(const green_plan* plan, int size);
+
+/* One iteration as green_gw_iterate, with the mixing step replaced by DIIS.  GREEN_ESINGULAR when the
+ * Lagrange system is singular (for instance two identical residuals); GREEN_ENOMEM for a short history. */
+int green_gw_iterate_diis(green_plan* plan, const void* V, const void* H0, const void* S, void* G, void* Sinf,
+                          void* Sigma, double* mu, double n_target, double alpha, green_diis* diis, void* history,
+                          size_t history_bytes, green_report* report, void* ws, void* stream);
+
 /* Plan options (green_plan_set_option):
  *   GREEN_OPT_TUNE  1: autotune.  Every contraction shape met on later calls is run once with each of
  *                   its candidate kernels (tile shape, large-tile kernel, split-K count; every candidate

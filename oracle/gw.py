@@ -435,3 +435,68 @@ def iterate(system, state: State, alpha: float = 1.0):
     herm = float(np.max(np.abs(Sig - np.conj(np.swapaxes(Sig, -1, -2)))))
     report = dict(e, n_elec=n, mu=mu, max_dsigma=dsig, herm_err=herm)
     return State(G, Sinf, Sig, mu), report, inter
+
+
+# ----------------------------------------------------------------------------- DIIS (Sec. 4.2.2)
+@dataclasses.dataclass
+class DiisHistory:
+    """Self-energies of the last iterations for the DIIS extrapolation of Sec. 4.2.2.
+
+    size: most stored vectors; start: first iteration (0-based) that extrapolates (earlier ones mix with
+    alpha).  xs[i] = (Sinf, Sigma~) computed from G_{i-1}; rs[i] = xs[i] minus the self-energy that produced
+    G_{i-1} (zero before the first iteration), the quantity that vanishes at self-consistency.
+    """
+    size: int
+    start: int
+    xs: list = dataclasses.field(default_factory=list)
+    rs: list = dataclasses.field(default_factory=list)
+    n: int = 0
+
+
+def diis_coefficients(rs) -> np.ndarray:
+    """Pulay's extrapolation: c minimises |sum_i c_i r_i|^2 subject to sum_i c_i = 1, from the Lagrange system
+    [[B, 1], [1^T, 0]] [c, l] = [0, 1] with B_ij = Re <r_i, r_j> (both parts of each residual).  B is scaled by
+    its largest diagonal element first (the solution does not change)."""
+    m = len(rs)
+    B = np.empty((m, m))
+    for i in range(m):
+        for j in range(m):
+            B[i, j] = sum(float(np.vdot(a, b).real) for a, b in zip(rs[i], rs[j]))
+    B = B / np.max(np.diag(B))
+    A = np.zeros((m + 1, m + 1))
+    A[:m, :m] = B
+    A[:m, m] = 1.0
+    A[m, :m] = 1.0
+    rhs = np.zeros(m + 1)
+    rhs[m] = 1.0
+    return np.linalg.solve(A, rhs)[:m]
+
+
+def iterate_diis(system, state: State, hist: DiisHistory, alpha: float = 1.0):
+    """One iteration with DIIS (Sec. 4.2.2): the self-energy that enters Dyson is sum_i c_i Sigma_i over the
+    stored self-energies once hist.start iterations have run (static mixing with alpha before)."""
+    sp = system.spec
+    grid = system.grid
+    Sinf_new, Sig_new, inter = sigma_eval(system.V, state.G, sp.kmesh, grid)
+    Sinf_old = state.Sinf if state.Sinf is not None else np.zeros_like(Sinf_new)
+    Sig_old = state.Sig if state.Sig is not None else np.zeros_like(Sig_new)
+    hist.xs.append((Sinf_new, Sig_new))
+    hist.rs.append((Sinf_new - Sinf_old, Sig_new - Sig_old))
+    if len(hist.xs) > hist.size:
+        hist.xs.pop(0)
+        hist.rs.pop(0)
+    if hist.n >= hist.start and len(hist.xs) >= 2:
+        c = diis_coefficients(hist.rs)
+        Sinf = sum(ci * x[0] for ci, x in zip(c, hist.xs))
+        Sig = sum(ci * x[1] for ci, x in zip(c, hist.xs))
+    else:
+        c = None
+        Sinf = mix(Sinf_new, state.Sinf, alpha)
+        Sig = mix(Sig_new, state.Sig, alpha)
+    hist.n += 1
+    G, mu, n = solve_dyson(system.H0, system.S, Sinf, Sig, grid, sp.nspin, state.mu, system.n_target)
+    e = energy(G, system.H0, Sinf, Sig, sp.beta)
+    dsig = float(np.max(np.abs(Sig - Sig_old)))
+    herm = float(np.max(np.abs(Sig - np.conj(np.swapaxes(Sig, -1, -2)))))
+    report = dict(e, n_elec=n, mu=mu, max_dsigma=dsig, herm_err=herm, diis_coef=c)
+    return State(G, Sinf, Sig, mu), report, inter

@@ -62,6 +62,12 @@ class System(ctypes.Structure):
                 ("n_target", ctypes.c_double), ("ws", ctypes.c_void_p)]
 
 
+class Diis(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_int32), ("start", ctypes.c_int32), ("count", ctypes.c_int32),
+                ("next", ctypes.c_int32), ("iter", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("B", (ctypes.c_double * 16) * 16), ("coef", ctypes.c_double * 16)]
+
+
 OPT_TUNE = 1
 OPT_GRAPH = 2
 
@@ -69,6 +75,7 @@ EXPORTS = ["green_plan_create", "green_plan_destroy", "green_workspace_bytes", "
            "green_gw_screen", "green_gw_selfenergy", "green_hf_static", "green_dyson", "green_gw_iterate",
            "green_plan_set_option", "green_plan_tuning_report", "green_batch_workspace_bytes",
            "green_gw_iterate_batched", "green_batch_create", "green_batch_iterate", "green_batch_destroy",
+           "green_diis_history_bytes", "green_gw_iterate_diis",
            "green_strerror"]
 
 
@@ -115,6 +122,11 @@ def _load():
     lib.green_batch_iterate.restype = i32
     lib.green_batch_destroy.argtypes = [vp]
     lib.green_batch_destroy.restype = None
+    lib.green_diis_history_bytes.argtypes = [vp, i32]
+    lib.green_diis_history_bytes.restype = ctypes.c_size_t
+    lib.green_gw_iterate_diis.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(dbl), dbl, dbl,
+                                          ctypes.POINTER(Diis), vp, ctypes.c_size_t, ctypes.POINTER(Report), vp, vp]
+    lib.green_gw_iterate_diis.restype = i32
     lib.green_strerror.argtypes = [i32]
     lib.green_strerror.restype = ctypes.c_char_p
     return lib

@@ -60,8 +60,9 @@ struct green_plan {
   std::vector<double> tau, wf, wb;
   std::vector<double2> TF_t2w, TF_w2t, TB_t2w, TB_w2t, Emass;
   std::vector<int32_t> kadd, ksub, kneg;  // [q][k]: k+q, k-q; [q]: -q
+  std::vector<int32_t> qcan;              // momenta q with -q >= q (one of each +-q pair)
   // workspace regions
-  Region r_TF_t2w, r_TF_w2t, r_TB_t2w, r_TB_w2t, r_Emass, r_wf, r_kadd, r_ksub, r_status, r_scal, r_partial;
+  Region r_TF_t2w, r_TF_w2t, r_TB_t2w, r_TB_w2t, r_Emass, r_wf, r_kadd, r_ksub, r_qcan, r_status, r_scal, r_partial;
   Region r_P, r_Pw, r_T1, r_T2, r_gam, r_gamT, r_D, r_Sinfn, r_Sign, r_Sw, r_A, r_tr, r_split, r_Vx, r_Ptx, r_Gx;
   size_t ws_bytes = 0;
   void* bound_ws = nullptr;
@@ -186,6 +187,7 @@ int ensure_bound(green_plan* p, void* ws, hipStream_t s) {
   HIP_TRY(up(p->r_wf, p->wf.data()));
   HIP_TRY(up(p->r_kadd, p->kadd.data()));
   HIP_TRY(up(p->r_ksub, p->ksub.data()));
+  HIP_TRY(up(p->r_qcan, p->qcan.data()));
   HIP_TRY(hipMemsetAsync(static_cast<char*>(ws) + p->r_status.off, 0, p->r_status.bytes, s));
   HIP_TRY(hipStreamSynchronize(s));
   p->bound_ws = ws;
@@ -495,8 +497,13 @@ int run_polarization(green_plan* p, const void* V, const void* G, void* P0, void
     Gs = at<void>(ws, p->r_Gx);
     sGs = span_ws(ws, p->r_Gx);
   }
+  // P~0^{-q}(tau) = P~0^q(beta - tau)^T exactly (substitute k -> k + q and cycle the trace), and the grid is
+  // symmetric (tau_{ntau-1-t} = beta - tau_t): only q <= -q are contracted, the partner slab is a transposed,
+  // tau-reversed copy, and for q = -q only the first half of the tau nodes is contracted.
   for (int q = 0; q < nk; ++q) {
     const int qn = p->kneg[q];
+    if (qn < q) continue;
+    const int t_end = qn == q ? ntau / 2 : ntau;
     const void *Vq = eptr(V, green::kC64, q * slab), *Vqn = eptr(V, green::kC64, qn * slab);
     green::Span sVs = span(V, ex.V);
     if (bf) {
@@ -508,8 +515,8 @@ int run_polarization(green_plan* p, const void* V, const void* G, void* P0, void
       Vqn = qn != q ? eptr(Vx, green::kCB16, slab) : Vx;
       sVs = span_ws(ws, p->r_Vx);
     }
-    for (int t0 = 0; t0 < ntau; t0 += p->tc) {
-      const int tcn = std::min(p->tc, ntau - t0);
+    for (int t0 = 0; t0 < t_end; t0 += p->tc) {
+      const int tcn = std::min(p->tc, t_end - t0);
       for (int sp = 0; sp < ns; ++sp) {
         // T1[tt][k][(Q,d)][b] = sum_a V^{k,k+q}_{da}(Q) G^{k+q}_{ab}(tau_tt): one GEMM per k with the tau
         // nodes of the chunk folded into N = (tt, b), so each V block is read once per chunk
@@ -535,6 +542,14 @@ int run_polarization(green_plan* p, const void* V, const void* G, void* P0, void
                        cplx(sp == 0 ? 0.0 : 1.0), s, p->prec, green::kC64, bf ? p->big_p0 : 0));
       }
     }
+    {
+      const double2* src = Pp + (int64_t)q * ntau * naux * naux;
+      double2* dst = Pp + (int64_t)qn * ntau * naux * naux;
+      const int lo = qn == q ? ntau / 2 : 0;
+      GREEN_TRY(aux(s, [=](hipStream_t st_) {
+        return green::launch_transpose_reverse(src, dst, naux, ntau, lo, ntau, st_);
+      }));
+    }
     GREEN_TRY(progress("polarization", q, nk, s));
   }
   return GREEN_OK;
@@ -543,27 +558,42 @@ int run_polarization(green_plan* p, const void* V, const void* G, void* P0, void
 // ---------------------------------------------------------------- screening
 int run_screen(green_plan* p, const void* P0, void* Pt, void* ws, hipStream_t s) {
   const green_dims& d = p->d;
-  const int nk = p->nk, naux = d.naux, ntau = d.ntau, nwb = d.nw_b;
+  const int naux = d.naux, ntau = d.ntau, nwb = d.nw_b;
   const int64_t nP = (int64_t)naux * naux;
   const Extents ex = extents(p);
   double2* Pw = at<double2>(ws, p->r_Pw);
   const green::Span sPw = span_ws(ws, p->r_Pw);
+  // The screening commutes with P(tau) -> P(beta - tau)^T (the bosonic transforms map it to P(i W) -> P(-i W)^T
+  // on the symmetric grids, and [I - P]^{-1} P commutes with the transpose), so P~^{-q}(tau) = P~^q(beta - tau)^T:
+  // only one q of each +-q pair is screened, its partner is a transposed, tau-reversed copy.
+  const int nc = (int)p->qcan.size();
+  const int32_t* qc = at<int32_t>(ws, p->r_qcan);
+  const int32_t* hqc = p->qcan.data();
   // P0(i W_m) = sum_t TB_t2w[m][t] P0(tau_t)
   GREEN_TRY(gemm(green::Site::Transform, "screen.t2w", op(at<double2>(ws, p->r_TB_t2w), flat(ntau), flat(1), bnone()),
-                 span_ws(ws, p->r_TB_t2w), op(P0, flat(nP), flat(1), bflat((int64_t)ntau * nP)), span(P0, ex.P), Pw,
-                 sPw, flat(nP), flat(1), bflat((int64_t)nwb * nP), nwb, (int)nP, ntau, nk, cplx(1), cplx(0), s));
+                 span_ws(ws, p->r_TB_t2w), op(P0, flat(nP), flat(1), btwo(nc, (int64_t)ntau * nP, qc, 0, hqc)),
+                 span(P0, ex.P), Pw, sPw, flat(nP), flat(1), bflat((int64_t)nwb * nP), nwb, (int)nP, ntau, nc, cplx(1),
+                 cplx(0), s));
   // P~(i W) = [I - P0]^{-1} P0 = [I - P0]^{-1} - I
-  if ((int64_t)nk * nwb * nP * 16 > (int64_t)p->r_Pw.bytes) return GREEN_EINVAL;
-  GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::launch_one_minus(Pw, naux, (int64_t)nk * nwb, st_); }));
+  if ((int64_t)nc * nwb * nP * 16 > (int64_t)p->r_Pw.bytes) return GREEN_EINVAL;
+  GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::launch_one_minus(Pw, naux, (int64_t)nc * nwb, st_); }));
   GREEN_TRY(aux(s, [=](hipStream_t st_) {
-    return green::zinv_batched(Pw, naux, nP, nk * nwb, at<int>(ws, p->r_status), st_);
+    return green::zinv_batched(Pw, naux, nP, nc * nwb, at<int>(ws, p->r_status), st_);
   }));
-  GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::launch_minus_one(Pw, naux, (int64_t)nk * nwb, st_); }));
+  GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::launch_minus_one(Pw, naux, (int64_t)nc * nwb, st_); }));
   // P~(tau_t) = sum_m TB_w2t[t][m] P~(i W_m)
   GREEN_TRY(gemm(green::Site::Transform, "screen.w2t", op(at<double2>(ws, p->r_TB_w2t), flat(nwb), flat(1), bnone()),
                  span_ws(ws, p->r_TB_w2t), op(Pw, flat(nP), flat(1), bflat((int64_t)nwb * nP)), sPw, Pt,
-                 span(Pt, ex.P), flat(nP), flat(1), bflat((int64_t)ntau * nP), ntau, (int)nP, nwb, nk, cplx(1),
-                 cplx(0), s));
+                 span(Pt, ex.P), flat(nP), flat(1), btwo(nc, (int64_t)ntau * nP, qc, 0, hqc), ntau, (int)nP, nwb, nc,
+                 cplx(1), cplx(0), s));
+  double2* Ptp = static_cast<double2*>(Pt);
+  for (int i = 0; i < nc; ++i) {
+    const int q = hqc[i], qn = p->kneg[q];
+    if (qn == q) continue;
+    const double2* src = Ptp + (int64_t)q * ntau * nP;
+    double2* dst = Ptp + (int64_t)qn * ntau * nP;
+    GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::launch_transpose_reverse(src, dst, naux, ntau, 0, ntau, st_); }));
+  }
   return GREEN_OK;
 }
 
@@ -945,7 +975,7 @@ using MarkFn = std::function<hipError_t(int)>;
 // Sigma^inf and Sigma~(tau) from (V, G) into the workspace, then mixed into the caller's Sinf and Sigma
 // with weight alpha; max |Sigma~_new - Sigma~_old| lands in the scalar slot 8.
 int sigma_eval(green_plan* p, const void* V, const void* G, void* Sinf, void* Sigma, double alpha, void* ws,
-               hipStream_t s, const MarkFn* mark) {
+               hipStream_t s, const MarkFn* mark, bool mix = true) {
   const green_dims& d = p->d;
   const int64_t nG = (int64_t)d.nao * d.nao;
   const int64_t nsig = (int64_t)d.nspin * d.ntau * p->nk * nG, ninf = (int64_t)d.nspin * p->nk * nG;
@@ -963,6 +993,7 @@ int sigma_eval(green_plan* p, const void* V, const void* G, void* Sinf, void* Si
   GREEN_TRY(m(3));
   GREEN_TRY(run_selfenergy(p, V, G, P, Sign, ws, s));
   GREEN_TRY(m(4));
+  if (!mix) return GREEN_OK;
   double2* Si = static_cast<double2*>(Sinf);
   double2* Sg = static_cast<double2*>(Sigma);
   GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::launch_mix(Si, Sinfn, alpha, ninf, nullptr, nullptr, st_); }));
@@ -1045,6 +1076,47 @@ struct green_batch {
   }
 };
 
+// Pulay's constrained least squares for the DIIS coefficients: [[B, 1], [1^T, 0]] [c, l] = [0, 1] with B
+// scaled by its largest diagonal element; Gaussian elimination with partial pivoting.  False if singular.
+bool diis_solve(const double* B, int ld, int m, double* c) {
+  double A[17][18];
+  double dmax = 0.0;
+  for (int i = 0; i < m; ++i) dmax = std::max(dmax, B[i * ld + i]);
+  if (!(dmax > 0.0) || !std::isfinite(dmax)) return false;
+  const int n = m + 1;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j <= n; ++j) A[i][j] = 0.0;
+  for (int i = 0; i < m; ++i) {
+    for (int j = 0; j < m; ++j) A[i][j] = B[i * ld + j] / dmax;
+    A[i][m] = 1.0;
+    A[m][i] = 1.0;
+  }
+  A[m][n] = 1.0;  // right-hand side column
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (std::fabs(A[r][col]) > std::fabs(A[piv][col])) piv = r;
+    if (!(std::fabs(A[piv][col]) > 1e-300)) return false;
+    if (piv != col)
+      for (int j = 0; j <= n; ++j) std::swap(A[piv][j], A[col][j]);
+    for (int r = col + 1; r < n; ++r) {
+      const double f = A[r][col] / A[col][col];
+      for (int j = col; j <= n; ++j) A[r][j] -= f * A[col][j];
+    }
+  }
+  double x[17];
+  for (int i = n - 1; i >= 0; --i) {
+    double acc = A[i][n];
+    for (int j = i + 1; j < n; ++j) acc -= A[i][j] * x[j];
+    x[i] = acc / A[i][i];
+  }
+  for (int i = 0; i < m; ++i) {
+    if (!std::isfinite(x[i])) return false;
+    c[i] = x[i];
+  }
+  return true;
+}
+
 // ====================================================================== exported
 extern "C" {
 
@@ -1115,6 +1187,8 @@ int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, 
       p->ksub[(size_t)q * nk + k] = kflat(d.kmesh, a - qa, b - qb, c - qc);
     }
   }
+  for (int q = 0; q < nk; ++q)
+    if (p->kneg[q] >= q) p->qcan.push_back(q);
   // ---- workspace layout
   const int64_t nao = d.nao, naux = d.naux, ns = d.nspin;
   const int64_t nG = nao * nao, nV = naux * nG, nP = naux * naux;
@@ -1140,11 +1214,12 @@ int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, 
   take(p->r_wf, (size_t)nwf * 8);
   take(p->r_kadd, (size_t)nk * nk * 4);
   take(p->r_ksub, (size_t)nk * nk * 4);
+  take(p->r_qcan, p->qcan.size() * 4);
   take(p->r_status, 64);
   take(p->r_scal, 64 * 8);
   take(p->r_partial, 1024 * 8);
   take(p->r_P, (size_t)nk * ntau * nP * 16);
-  take(p->r_Pw, (size_t)nk * nwb * nP * 16);
+  take(p->r_Pw, p->qcan.size() * nwb * nP * 16);
   const size_t tbuf = std::max<size_t>((size_t)tc * nk * nV * isz, (size_t)ns * ntau * nk * nG * 16);
   take(p->r_T1, tbuf);
   take(p->r_T2, std::max<size_t>((size_t)tc * nk * nV * isz, (size_t)nk * nV * 16));
@@ -1299,6 +1374,103 @@ int green_gw_iterate(green_plan* p, const void* V, const void* H0, const void* S
     }
   if (!std::isfinite(rep->e_tot) || !std::isfinite(rep->max_dsigma) || !std::isfinite(rep->herm_err))
     return GREEN_ENAN;
+  return GREEN_OK;
+}
+
+size_t green_diis_history_bytes(const green_plan* p, int size) {
+  if (!p || size < 2 || size > 16) return 0;
+  const int64_t nG = (int64_t)p->d.nao * p->d.nao;
+  const int64_t nv = (int64_t)p->d.nspin * p->nk * nG * (1 + p->d.ntau);  // Sigma^inf and Sigma~(tau)
+  return (size_t)size * 2 * nv * sizeof(double2);
+}
+
+int green_gw_iterate_diis(green_plan* p, const void* V, const void* H0, const void* S, void* G, void* Sinf,
+                          void* Sigma, double* mu, double n_target, double alpha, green_diis* dst, void* hist,
+                          size_t hist_bytes, green_report* rep, void* ws, void* stream) {
+  GREEN_TRY(check_plan(p, ws));
+  if (!V || !H0 || !S || !G || !Sinf || !Sigma || !mu || !rep || !dst || !hist || !std::isfinite(*mu))
+    return GREEN_EINVAL;
+  if (!(alpha > 0.0 && alpha < 2.0)) return GREEN_EINVAL;
+  if (dst->size < 2 || dst->size > 16 || dst->start < 0 || dst->count < 0 || dst->count > dst->size ||
+      dst->next < 0 || dst->next >= dst->size || dst->iter < 0)
+    return GREEN_EINVAL;
+  if (hist_bytes < green_diis_history_bytes(p, dst->size)) return GREEN_ENOMEM;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PlanScope scope(p);
+  GREEN_TRY(ensure_bound(p, ws, s));
+  std::memset(rep, 0, sizeof(*rep));
+  const bool dry = green::dryrun();
+  GREEN_TRY(ensure_events(p));
+  const MarkFn mark = [&](int i) { return dry ? hipSuccess : hipEventRecord(p->ev[i], s); };
+  HIP_TRY(mark(0));
+  // Sigma[G]: x_n = (Sinf_new, Sigma_new) in the workspace, the caller's arrays still hold the input self-energy
+  GREEN_TRY(sigma_eval(p, V, G, Sinf, Sigma, alpha, ws, s, &mark, false));
+  const green_dims& d = p->d;
+  const int64_t nG = (int64_t)d.nao * d.nao;
+  const int64_t ninf = (int64_t)d.nspin * p->nk * nG, nsig = ninf * d.ntau, nv = ninf + nsig;
+  double2* Sinfn = at<double2>(ws, p->r_Sinfn);
+  double2* Sign = at<double2>(ws, p->r_Sign);
+  double* scal = at<double>(ws, p->r_scal);
+  double* part = at<double>(ws, p->r_partial);
+  double2* Hb = static_cast<double2*>(hist);
+  const int slot = dst->next;
+  double2* x = Hb + (int64_t)slot * 2 * nv;  // x_n = [Sinf_new | Sigma_new]
+  double2* r = x + nv;                        // r_n = x_n - (input self-energy)
+  const int count = std::min(dst->count + 1, dst->size);
+  // ring order, oldest first
+  int slots[16];
+  for (int j = 0; j < count; ++j) slots[j] = (slot - (count - 1) + j + dst->size) % dst->size;
+  double brow[16] = {0.0};
+  if (!dry) {
+    HIP_TRY(hipMemcpyAsync(x, Sinfn, ninf * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(x + ninf, Sign, nsig * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(green::launch_sub(r, x, static_cast<const double2*>(Sinf), ninf, s));
+    HIP_TRY(green::launch_sub(r + ninf, x + ninf, static_cast<const double2*>(Sigma), nsig, s));
+    // new row of the Gram matrix, one fixed-order dot product per stored residual
+    for (int j = 0; j < count; ++j) {
+      const double2* rj = Hb + (int64_t)slots[j] * 2 * nv + nv;
+      HIP_TRY(green::launch_dot_re(r, rj, nv, part, scal + 16 + j, s));
+    }
+    HIP_TRY(hipMemcpyAsync(brow, scal + 16, count * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  for (int j = 0; j < count; ++j) {
+    dst->B[slot][slots[j]] = brow[j];
+    dst->B[slots[j]][slot] = brow[j];
+  }
+  dst->count = count;
+  dst->next = (slot + 1) % dst->size;
+  const bool extrapolate = dst->iter >= dst->start && count >= 2;
+  for (int j = 0; j < 16; ++j) dst->coef[j] = 0.0;
+  if (extrapolate) {
+    double Bm[16 * 16], c[16];
+    for (int i = 0; i < count; ++i)
+      for (int j = 0; j < count; ++j) Bm[i * 16 + j] = dst->B[slots[i]][slots[j]];
+    if (!dry && !diis_solve(Bm, 16, count, c)) return GREEN_ESINGULAR;
+    if (dry)
+      for (int j = 0; j < count; ++j) c[j] = j == count - 1 ? 1.0 : 0.0;
+    green::CombineCoefs cf{};
+    cf.m = count;
+    for (int j = 0; j < count; ++j) {
+      cf.slot[j] = slots[j];
+      cf.c[j] = c[j];
+      dst->coef[j] = c[j];
+    }
+    if (!dry) {
+      HIP_TRY(green::launch_combine(static_cast<double2*>(Sinf), Hb, 2 * nv, ninf, cf, nullptr, nullptr, s));
+      HIP_TRY(green::launch_combine(static_cast<double2*>(Sigma), Hb + ninf, 2 * nv, nsig, cf, part, scal + 8, s));
+    }
+  } else if (!dry) {
+    HIP_TRY(green::launch_mix(static_cast<double2*>(Sinf), Sinfn, alpha, ninf, nullptr, nullptr, s));
+    HIP_TRY(green::launch_mix(static_cast<double2*>(Sigma), Sign, alpha, nsig, part, scal + 8, s));
+  }
+  dst->iter += 1;
+  HIP_TRY(mark(5));
+  GREEN_TRY(close_iteration(p, H0, S, G, Sinf, Sigma, mu, n_target, rep, ws, s, &mark));
+  if (dry) return GREEN_OK;
+  for (int i = 0; i < 7; ++i) HIP_TRY(hipEventElapsedTime(&rep->ms[i], p->ev[i], p->ev[i + 1]));
+  HIP_TRY(hipEventElapsedTime(&rep->ms[7], p->ev[0], p->ev[7]));
+  if (!std::isfinite(rep->e_tot) || !std::isfinite(rep->max_dsigma)) return GREEN_ENAN;
   return GREEN_OK;
 }
 

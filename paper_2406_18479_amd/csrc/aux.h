@@ -7,6 +7,10 @@ namespace green {
 
 hipError_t launch_density(const double2* G, double2* gam, double2* gamT, int ns, int ntau, int nk, int nao,
                           hipStream_t s);
+// dst[t] = src[nt - 1 - t]^T for t in [t_lo, t_hi) (n x n complex matrices; src and dst may be the same
+// array when the two t ranges do not overlap).
+hipError_t launch_transpose_reverse(const double2* src, double2* dst, int n, int nt, int t_lo, int t_hi,
+                                   hipStream_t s);
 hipError_t launch_one_minus(double2* A, int n, int64_t batch, hipStream_t s);
 hipError_t launch_minus_one(double2* A, int n, int64_t batch, hipStream_t s);
 hipError_t launch_dyson_form(double2* A, const double2* S, const double2* H0, const double2* Sinf,
@@ -21,5 +25,17 @@ hipError_t launch_mix(double2* S, const double2* Snew, double alpha, int64_t n, 
                       hipStream_t s);
 hipError_t launch_herm(const double2* X, int64_t nmat, int nao, double* partial, double* out, hipStream_t s);
 hipError_t launch_zero(double2* X, int64_t n, hipStream_t s);
+
+// DIIS: *out = sum Re(conj(a) b) (fixed-order reduction through partial[mix_blocks(n)]); r = x - old;
+// out = sum_j c_j base[slot_j * stride + .] with *out_max = max |out_new - out_old|.
+struct CombineCoefs {
+  int32_t m;
+  int32_t slot[16];
+  double c[16];
+};
+hipError_t launch_dot_re(const double2* a, const double2* b, int64_t n, double* partial, double* out, hipStream_t s);
+hipError_t launch_sub(double2* r, const double2* x, const double2* old, int64_t n, hipStream_t s);
+hipError_t launch_combine(double2* out, const double2* base, int64_t stride, int64_t n, const CombineCoefs& cf,
+                          double* partial, double* out_max, hipStream_t s);
 
 }  // namespace green

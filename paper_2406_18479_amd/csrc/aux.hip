@@ -52,6 +52,29 @@ __global__ void k_density(const double2* __restrict__ G, double2* __restrict__ g
 }
 
 // A[b] = I - A[b]  (n x n, batch stride n*n)
+// dst[t][j][i] = src[nt - 1 - t][i][j] for t in [t_lo, t_hi): one 32 x 32 tile of one t per block, transposed
+// through LDS so that both the reads and the writes are row-contiguous.
+__global__ __launch_bounds__(256) void k_transpose_reverse(const double2* __restrict__ src, double2* __restrict__ dst,
+                                                           int n, int nt, int t_lo) {
+  __shared__ double2 tile[32][33];
+  const int tiles = (n + 31) / 32;
+  const int ti = blockIdx.x % tiles, tj = blockIdx.x / tiles;  // source tile rows ti, columns tj
+  const int t = t_lo + blockIdx.y;
+  const int64_t nn = (int64_t)n * n;
+  const double2* S = src + (int64_t)(nt - 1 - t) * nn;
+  double2* D = dst + (int64_t)t * nn;
+  const int c = threadIdx.x & 31, r0 = threadIdx.x >> 5;
+  for (int r = r0; r < 32; r += 8) {
+    const int i = 32 * ti + r, j = 32 * tj + c;
+    if (i < n && j < n) tile[r][c] = S[(int64_t)i * n + j];
+  }
+  __syncthreads();
+  for (int r = r0; r < 32; r += 8) {
+    const int j = 32 * tj + r, i = 32 * ti + c;  // destination row j, column i
+    if (i < n && j < n) D[(int64_t)j * n + i] = tile[c][r];
+  }
+}
+
 __global__ void k_one_minus(double2* __restrict__ A, int n, int64_t batch) {
   const int64_t nn = (int64_t)n * n;
   const int64_t total = nn * batch;
@@ -197,6 +220,61 @@ __global__ __launch_bounds__(256) void k_max_partials(const double* __restrict__
   if (threadIdx.x == 0) *out = mx;
 }
 
+// DIIS helpers.  partial[block] = sum Re(conj(a) b) over a grid-strided range (fixed grid: deterministic).
+__global__ __launch_bounds__(256) void k_dot_re(const double2* __restrict__ a, const double2* __restrict__ b,
+                                                int64_t n, double* __restrict__ partial) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+    const double2 u = a[x], v = b[x];
+    acc += u.x * v.x + u.y * v.y;
+  }
+  acc = block_reduce(acc, AddD(), sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partial, int n,
+                                                      double* __restrict__ out) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < n; b += blockDim.x) acc += partial[b];
+  acc = block_reduce(acc, AddD(), sh);
+  if (threadIdx.x == 0) *out = acc;
+}
+
+// r = x - old (old == nullptr: r = x)
+__global__ void k_sub(double2* __restrict__ r, const double2* __restrict__ x, const double2* __restrict__ old,
+                      int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double2 v = x[i];
+    const double2 o = old ? old[i] : make_double2(0.0, 0.0);
+    r[i] = make_double2(v.x - o.x, v.y - o.y);
+  }
+}
+
+// out[i] = sum_j c_j base[slot_j * stride + i] (j in order); partial[block] = max |out_new - out_old|
+__global__ __launch_bounds__(256) void k_combine(double2* __restrict__ out, const double2* __restrict__ base,
+                                                 int64_t stride, int64_t n, CombineCoefs cf,
+                                                 double* __restrict__ partial) {
+  __shared__ double sh[256];
+  double mx = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double re = 0.0, im = 0.0;
+    for (int j = 0; j < cf.m; ++j) {
+      const double2 v = base[cf.slot[j] * stride + i];
+      re += cf.c[j] * v.x;
+      im += cf.c[j] * v.y;
+    }
+    const double2 o = out[i];
+    const double dx = re - o.x, dy = im - o.y;
+    const double d = sqrt(dx * dx + dy * dy);
+    mx = (d > mx || d != d) ? d : mx;
+    out[i] = make_double2(re, im);
+  }
+  mx = block_reduce(mx, MaxD(), sh);
+  if (partial && threadIdx.x == 0) partial[blockIdx.x] = mx;
+}
+
 __global__ void k_zero(double2* __restrict__ X, int64_t n) {
   for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
     X[x] = make_double2(0.0, 0.0);
@@ -215,6 +293,16 @@ hipError_t launch_density(const double2* G, double2* gam, double2* gamT, int ns,
                           hipStream_t s) {
   const int64_t n = (int64_t)ns * nk * nao * nao;
   hipLaunchKernelGGL(k_density, dim3(grid_for(n)), dim3(256), 0, s, G, gam, gamT, ns, ntau, nk, nao);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_reverse(const double2* src, double2* dst, int n, int nt, int t_lo, int t_hi,
+                                   hipStream_t s) {
+  if (n <= 0 || t_hi <= t_lo) return hipSuccess;
+  if (t_lo < 0 || t_hi > nt) return hipErrorInvalidValue;
+  const int tiles = (n + 31) / 32;
+  k_transpose_reverse<<<dim3((unsigned)(tiles * tiles), (unsigned)(t_hi - t_lo)), dim3(256), 0, s>>>(src, dst, n, nt,
+                                                                                                    t_lo);
   return hipGetLastError();
 }
 
@@ -263,6 +351,28 @@ hipError_t launch_herm(const double2* X, int64_t nmat, int nao, double* partial,
   const int nb = mix_blocks(nmat * nao * nao);
   hipLaunchKernelGGL(k_herm, dim3(nb), dim3(256), 0, s, X, nmat, nao, partial);
   hipLaunchKernelGGL(k_max_partials, dim3(1), dim3(256), 0, s, partial, nb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot_re(const double2* a, const double2* b, int64_t n, double* partial, double* out,
+                         hipStream_t s) {
+  const int nb = mix_blocks(n);
+  hipLaunchKernelGGL(k_dot_re, dim3(nb), dim3(256), 0, s, a, b, n, partial);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partial, nb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub(double2* r, const double2* x, const double2* old, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub, dim3(grid_for(n)), dim3(256), 0, s, r, x, old, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine(double2* out, const double2* base, int64_t stride, int64_t n, const CombineCoefs& cf,
+                          double* partial, double* out_max, hipStream_t s) {
+  if (cf.m < 1 || cf.m > 16) return hipErrorInvalidValue;
+  const int nb = mix_blocks(n);
+  hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), 0, s, out, base, stride, n, cf, partial);
+  if (partial && out_max) hipLaunchKernelGGL(k_max_partials, dim3(1), dim3(256), 0, s, partial, nb, out_max);
   return hipGetLastError();
 }
 

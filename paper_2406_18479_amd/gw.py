@@ -145,6 +145,21 @@ class Plan:
                                         ctypes.byref(ev), self.ws.data_ptr(), _stream(self.device)), "green_dyson")
         return G, m.value, n.value, ev.value
 
+    def iterate_diis(self, diis, V, H0, S, G, Sinf, Sigma, mu, n_target, alpha=1.0):
+        """One iteration with DIIS (a DiisState of this plan); G, Sinf, Sigma updated in place."""
+        m = ctypes.c_double(mu)
+        rep = _lib.Report()
+        _lib.check(_lib.LIB.green_gw_iterate_diis(self._h, _ptr(V, self.shape_V, "V", self.device),
+                                                  _ptr(H0, self.shape_H, "H0", self.device),
+                                                  _ptr(S, self.shape_S, "S", self.device),
+                                                  _ptr(G, self.shape_G, "G", self.device),
+                                                  _ptr(Sinf, self.shape_H, "Sinf", self.device),
+                                                  _ptr(Sigma, self.shape_G, "Sigma", self.device), ctypes.byref(m),
+                                                  float(n_target), float(alpha), ctypes.byref(diis.c),
+                                                  diis.history.data_ptr(), diis.bytes, ctypes.byref(rep),
+                                                  self.ws.data_ptr(), _stream(self.device)), "green_gw_iterate_diis")
+        return m.value, rep.as_dict()
+
     def iterate(self, V, H0, S, G, Sinf, Sigma, mu, n_target, alpha=1.0):
         """One self-consistent iteration; G, Sinf, Sigma are updated in place.  Returns (mu, report dict)."""
         m = ctypes.c_double(mu)
@@ -158,6 +173,23 @@ class Plan:
                                              float(n_target), float(alpha), ctypes.byref(rep), self.ws.data_ptr(),
                                              _stream(self.device)), "green_gw_iterate")
         return m.value, rep.as_dict()
+
+
+class DiisState:
+    """DIIS state and device history of one plan (green_gw_iterate_diis)."""
+
+    def __init__(self, plan, size=5, start=2):
+        self.c = _lib.Diis()
+        self.c.size, self.c.start = int(size), int(start)
+        self.bytes = int(_lib.LIB.green_diis_history_bytes(plan._h, int(size)))
+        if self.bytes == 0:
+            raise ValueError("DIIS size must be in [2, 16]")
+        with torch.cuda.device(plan.device):
+            self.history = torch.empty(self.bytes, dtype=torch.uint8, device=plan.device)
+
+    @property
+    def coefficients(self):
+        return [self.c.coef[i] for i in range(self.c.count)]
 
 
 def _systems_array(plans, systems):

@@ -120,3 +120,29 @@ def test_plan_options_and_tuning_report(lib):
         assert buf.value == b""  # nothing tuned without device runs
     finally:
         lib.LIB.green_plan_destroy(h)
+
+
+def test_diis_iteration_in_bounds_and_argument_checks(lib):
+    h = _plan(lib, CASES[1], 0)
+    try:
+        L = lib.LIB
+        need = L.green_diis_history_bytes(h, 5)
+        assert need > 0 and L.green_diis_history_bytes(h, 1) == 0 and L.green_diis_history_bytes(h, 17) == 0
+        ptr = [BASE + i * STEP for i in range(10)]
+        V, G, H0, S, Sinf, Sig, ws, hist = ptr[:8]
+        st = lib.Diis()
+        st.size, st.start = 5, 1
+        rep = lib.Report()
+        mu = ctypes.c_double(0.0)
+        for it in range(7):
+            assert L.green_gw_iterate_diis(h, V, H0, S, G, Sinf, Sig, ctypes.byref(mu), 3.0, 1.0, ctypes.byref(st),
+                                           hist, need, ctypes.byref(rep), ws, None) == 0
+            assert st.count == min(it + 1, 5) and st.iter == it + 1 and st.next == (it + 1) % 5
+        assert L.green_gw_iterate_diis(h, V, H0, S, G, Sinf, Sig, ctypes.byref(mu), 3.0, 1.0, ctypes.byref(st),
+                                       hist, need - 1, ctypes.byref(rep), ws, None) == -2  # short history
+        bad = lib.Diis()
+        bad.size = 1
+        assert L.green_gw_iterate_diis(h, V, H0, S, G, Sinf, Sig, ctypes.byref(mu), 3.0, 1.0, ctypes.byref(bad),
+                                       hist, need, ctypes.byref(rep), ws, None) == -1
+    finally:
+        lib.LIB.green_plan_destroy(h)

@@ -364,6 +364,22 @@ def test_screening_residual(physical):
     assert np.max(np.abs(res)) < 1e-14 * max(1.0, np.max(np.abs(Ptw)))
 
 
+def test_screened_partner_momentum_identity():
+    """P~^{-q}(tau) = P~^q(beta - tau)^T after the bosonic transforms and the screening, for inputs without
+    time-reversal symmetry (the identity follows from relabelling k -> k + q in the trace and the reflection
+    symmetry of the grid; the GPU path screens one q of each +-q pair and copies the partner)."""
+    sp = configs.tiny(kmesh=(3, 2, 1), nao=4, naux=6, ntau=16, beta=10.0, seed=93, v_scale=0.3)
+    s = systems.make_system(sp)
+    neg = systems.k_neg(sp.kmesh)
+    P0 = gw.polarization(s.V, s.G0, sp.kmesh)
+    Pt = gw.from_bosonic(gw.screen(gw.to_bosonic(P0, s.grid.TB_t2w)), s.grid.TB_w2t)
+    sc = np.max(np.abs(Pt))
+    assert any(neg[q] != q for q in range(sp.nk))
+    for q in range(sp.nk):
+        assert np.max(np.abs(Pt[neg[q]] - np.swapaxes(Pt[q][::-1], -1, -2))) < 1e-13 * sc
+        assert np.max(np.abs(P0[neg[q]] - np.swapaxes(P0[q][::-1], -1, -2))) < 1e-13 * np.max(np.abs(P0))
+
+
 def test_selfenergy_symmetries(physical):
     """Hermiticity, causality (diagonal <= 0 with S = I) and time reversal Sigma^{-k} = conj Sigma^k."""
     s, Sinf, Sig, _ = physical
@@ -386,3 +402,66 @@ def test_iteration_runs_and_contracts():
         assert abs(rep["n_elec"] - s.n_target) < 1e-11
         d.append(rep["max_dsigma"])
     assert d[-1] < 1e-2 * d[1]
+
+
+# ============================================================================ DIIS (Sec. 4.2.2)
+def test_diis_two_vector_closed_form():
+    """Two residuals: the constrained minimiser of |c r1 + (1 - c) r2| is c = (B22 - B12)/(B11 - 2 B12 + B22)."""
+    rng = np.random.default_rng(3)
+    r1 = (rng.normal(size=(2, 3)) + 1j * rng.normal(size=(2, 3)), rng.normal(size=4) + 1j * rng.normal(size=4))
+    r2 = (rng.normal(size=(2, 3)) + 1j * rng.normal(size=(2, 3)), rng.normal(size=4) + 1j * rng.normal(size=4))
+    dot = lambda a, b: sum(np.vdot(x, y).real for x, y in zip(a, b))  # noqa: E731
+    B11, B22, B12 = dot(r1, r1), dot(r2, r2), dot(r1, r2)
+    c = gw.diis_coefficients([r1, r2])
+    assert abs(c[0] - (B22 - B12) / (B11 - 2 * B12 + B22)) < 1e-13
+    assert abs(c.sum() - 1.0) < 1e-14
+    # it is the minimum: any other affine combination has a larger residual norm
+    f = lambda t: dot(tuple(t * a + (1 - t) * b for a, b in zip(r1, r2)), tuple(t * a + (1 - t) * b for a, b in zip(r1, r2)))  # noqa: E731
+    assert f(c[0]) <= min(f(c[0] + 1e-3), f(c[0] - 1e-3))
+
+
+def test_diis_solves_a_linear_fixed_point_in_dim_plus_one_steps():
+    """With an unlimited subspace, DIIS on a linear map g(x) = A x + b (vectors x_i = g(y_i), residuals
+    r_i = g(y_i) - y_i, next input y = sum c_i x_i) is a Krylov (GMRES-equivalent) method and reaches the
+    fixed point after at most D + 1 evaluations, D the dimension of the space the coefficients span: the
+    coefficients are real, so a complex d-vector counts as D = 2d real dimensions."""
+    rng = np.random.default_rng(4)
+    d = 5
+    A = 0.3 * (rng.normal(size=(d, d)) + 1j * rng.normal(size=(d, d)))
+    b = rng.normal(size=d) + 1j * rng.normal(size=d)
+    xstar = np.linalg.solve(np.eye(d) - A, b)
+    y = np.zeros(d, dtype=complex)
+    xs, rs = [], []
+    for it in range(2 * d + 1):
+        gx = A @ y + b
+        xs.append((gx,))
+        rs.append((gx - y,))
+        c = gw.diis_coefficients(rs) if len(rs) >= 2 else np.array([1.0])
+        y = sum(ci * x[0] for ci, x in zip(c, xs))
+        if it == 2 * d - 2:
+            assert np.max(np.abs(y - xstar)) > 1e-6 * np.max(np.abs(xstar))  # not earlier
+    assert np.max(np.abs(y - xstar)) < 1e-9 * np.max(np.abs(xstar))
+
+
+def test_diis_iteration_converges_faster_than_plain():
+    """DIIS reaches the same fixed point as the plain iteration in fewer iterations, and converges at a
+    stronger coupling where the plain iteration oscillates."""
+    def run(s, diis, n_max=25, tol=1e-9):
+        st = gw.State(s.G0, None, None, 0.0)
+        hist = gw.DiisHistory(size=5, start=2)
+        for it in range(n_max):
+            st, rep, _ = gw.iterate_diis(s, st, hist) if diis else gw.iterate(s, st)
+            if rep["max_dsigma"] < tol:
+                return it + 1, rep
+        return n_max + 1, rep
+    s = systems.make_system(configs.tiny(kmesh=(1, 1, 1), nao=6, naux=20, ntau=24, beta=20.0, seed=97))
+    n_plain, rp = run(s, False)
+    n_diis, rd = run(s, True)
+    assert n_diis < n_plain <= 25
+    assert abs(rp["e_tot"] - rd["e_tot"]) < 1e-8
+    s = systems.make_system(configs.tiny(kmesh=(1, 1, 1), nao=6, naux=20, ntau=24, beta=20.0, seed=97,
+                                         v_scale=0.2))
+    n_plain, rp = run(s, False)
+    n_diis, rd = run(s, True)
+    assert n_plain > 25 and rp["max_dsigma"] > 1e-3
+    assert n_diis <= 25
