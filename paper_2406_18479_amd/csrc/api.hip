@@ -657,13 +657,14 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
     }
     for (int t0 = 0; t0 < ntau; t0 += p->tc) {
       const int tcn = std::min(p->tc, ntau - t0);
-      // X[tt][k][Q'][(i,a)] = sum_Q P~^q_{QQ'}(tau) V^{k,k-q}_{ia}(Q)
+      // X[tt][k][Q'][(i,a)] = sum_Q P~^q_{QQ'}(tau) V^{k,k-q}_{ia}(Q): the V slab is shared by the tau nodes
+      // of the chunk, so they are stacked into the rows, M = (tt, Q') (no partial tiles at each naux edge)
       GREEN_TRY(gemm(green::Site::Sig_PV, "Sigma.PV",
-                     bf ? op(eptr(Ptx, green::kCB16, (int64_t)t0 * nP), flat(naux), flat(1), bflat(nP), green::kCB16)
-                        : op(Pp + ((int64_t)q * ntau + t0) * nP, flat(1), flat(naux), bflat(nP)),
+                     bf ? op(eptr(Ptx, green::kCB16, (int64_t)t0 * nP), flat(naux), flat(1), bnone(), green::kCB16)
+                        : op(Pp + ((int64_t)q * ntau + t0) * nP, two(naux, 1, nP), flat(naux), bnone()),
                      bf ? sPtx : sP, op(Vqn, flat(nG), two((int32_t)nG, 1, nV), bnone(), mixed ? vt : green::kC64),
-                     sVa, T1, sT1, flat(nG), two((int32_t)nG, 1, nV), bflat((int64_t)nk * nV), naux,
-                     (int)(nk * nG), naux, tcn, cplx(1), cplx(0), s, p->prec, xt, bf ? 1 : 0));
+                     sVa, T1, sT1, two(naux, nG, (int64_t)nk * nV), two((int32_t)nG, 1, nV), bnone(), tcn * naux,
+                     (int)(nk * nG), naux, 1, cplx(1), cplx(0), s, p->prec, xt, bf ? 1 : 0));
       for (int sp = 0; sp < ns; ++sp) {
         // Y[tt][k][(Q',i)][b] = sum_a X[tt][k][(Q',i)][a] G^{k-q}_{ab}(tau)
         GREEN_TRY(gemm(green::Site::Sig_XG, "Sigma.XG", op(T1, flat(nao), flat(1), bflat(nV), xt), sT1,
