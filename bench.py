@@ -149,6 +149,7 @@ def run_precision(system, prec, steps, warmup, chunk_bytes=0, tune=False, graph=
               flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    report = plan.tuning_report()
     plan.close()
     del plan, H0, S, G, Sinf, Sig
     torch.cuda.empty_cache()
@@ -174,12 +175,41 @@ def run_precision(system, prec, steps, warmup, chunk_bytes=0, tune=False, graph=
         "last": reps[-1],
         "first": first,
         "tune_iterations": tuned,
+        "p0_kernel": p0_kernel_name(prec, report),
     }
 
 
 KERNEL_NAME = {"fp64": "zgemm_f64_kernel<2,2,Site::P0_Contract>",
                "fp32": "zgemm_mx_kernel<1,2,2,Site::P0_Contract>",
                "bf16x3": "zgemm_bt_kernel<3,3,false,Site::P0_Contract>"}
+# large tiles of the split-BF16 kernel by its `big` selector: (FM, FN) of a 64 FM x 32 FN tile
+BIG_TILE = {1: (3, 3), 2: (3, 2), 3: (5, 2), 4: (7, 2)}
+DMA_TILE = {5: (5, 2), 6: (3, 4)}  # the LDS-DMA kernel's tiles
+
+
+def p0_kernel_name(prec: str, report: str) -> str:
+    """Template name of the kernel that runs the P~0 contraction: the default one, or the autotuner's
+    choice for the shape with the most tau nodes per launch."""
+    import re
+    best = None
+    for line in report.splitlines():
+        m = re.match(r"P0_Contract\s+M=(\d+) N=(\d+) K=(\d+) batch=(\d+) prec=\d+: shape=(\d+) big=(\d+)", line)
+        if m and (best is None or int(m.group(4)) > best[0]):
+            best = (int(m.group(4)), int(m.group(1)), int(m.group(2)), int(m.group(5)), int(m.group(6)))
+    if best is None:
+        return KERNEL_NAME[prec]
+    _, M, N, shape, big = best
+    if prec == "bf16x3" and big in BIG_TILE:
+        fm, fn = BIG_TILE[big]
+        return f"zgemm_bt_kernel<{fm},{fn},false,Site::P0_Contract>"
+    if prec == "bf16x3" and big in DMA_TILE:
+        fm, fn = DMA_TILE[big]
+        return f"zgemm_bd_kernel<{fm},{fn},Site::P0_Contract>"
+    wm, wn = ((shape - 1) // 2 + 1, (shape - 1) % 2 + 1) if 1 <= shape <= 4 else (1 if M <= 32 else 2,
+                                                                                    1 if N <= 32 else 2)
+    if prec == "fp64":
+        return f"zgemm_f64_kernel<{wm},{wn},Site::P0_Contract>"
+    return f"zgemm_mx_kernel<{1 if prec == 'fp32' else 2},{wm},{wn},Site::P0_Contract>"
 
 
 def run_batch(args):
@@ -436,10 +466,10 @@ def main():
                        for p, r in res.items()},
         "energy": {"e_tot": h["last"]["e_tot"], "e_corr": h["last"]["e_corr"], "mu": h["last"]["mu"],
                    "n_elec": h["last"]["n_elec"], "max_dsigma": h["last"]["max_dsigma"]},
-        "roofline": {"bound": "mfma", "kernel": KERNEL_NAME[head], "achieved": round(achieved, 4), "peak": peak,
+        "roofline": {"bound": "mfma", "kernel": h["p0_kernel"], "achieved": round(achieved, 4), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                      "mfma_frac": round(achieved * MFMA_PER_ALG[head] / peak, 4),
-                     "traffic": measured_traffic(spec.name, head, KERNEL_NAME[head]) if args.tune else None,
+                     "traffic": measured_traffic(spec.name, head, h["p0_kernel"]),
                      "launches": k["launches"], "avg_launch_ms": round(k["ms"] / max(k["launches"], 1), 4),
                      "flops_per_launch": k["flops"] / max(k["launches"], 1)},
         "cpu_baseline": None,

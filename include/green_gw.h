@@ -223,13 +223,24 @@ int green_gw_iterate_diis(green_plan* plan, const void* V, const void* H0, const
  *                   (V, G, Sinf, Sigma, ws, alpha) stay the same; not while tuning is pending and not
  *                   on the default (null) stream, which cannot be captured: there it runs eagerly.  The
  *                   per-stage times are then not separated: ms[0] holds the replay, ms[1..4] are 0.
+ *   GREEN_OPT_P0_TILE  split-BF16 plans: output tile of the P~0 contraction over k and orbital pairs
+ *                   (the sum of Eq. tilde_P0_tau) before any autotuning: 1 = 192 x 96, 2 = 192 x 64,
+ *                   3 = 320 x 64, 4 = 448 x 64 rows x columns of P~0(q, tau), register-staged; 5 = 320 x 64,
+ *                   6 = 192 x 128 fed by LDS DMA (even nao; else as 1).  The plan starts with the
+ *                   register-staged one that pads naux x naux least (192 x 96 counted at 90% of its area).
+ *   GREEN_OPT_STAGE1_TILE  split-BF16 plans: tile of the V G products that feed it: 0 = 64 x 64,
+ *                   1 = 192 x 96 (default), 2 = 192 x 64.
+ *                   Both only change the summation blocking; results agree to rounding.
  * Returns GREEN_EINVAL for an unknown option or value. */
 #define GREEN_OPT_TUNE 1
 #define GREEN_OPT_GRAPH 2
+#define GREEN_OPT_P0_TILE 3
+#define GREEN_OPT_STAGE1_TILE 4
 int green_plan_set_option(green_plan* plan, int option, int value);
 
-/* Text table of the autotuner's decisions (one line per contraction shape) into buf (host, len bytes,
- * NUL-terminated; GREEN_ENOMEM when truncated). */
+/* Text table of the autotuner's decisions into buf (host, len bytes, NUL-terminated; GREEN_ENOMEM when
+ * truncated): per contraction shape a line with the chosen kernel and, once tuned, a line with every
+ * candidate's time as shape/large tile/split-K count/tile-row band=microseconds. */
 int green_plan_tuning_report(const green_plan* plan, char* buf, size_t len);
 
 /* One system of a batched iteration: the arguments of green_gw_iterate (device pointers; mu host,

@@ -36,7 +36,7 @@ struct TuneKey {
   bool operator<(const TuneKey& o) const { return std::lexicographical_compare(v, v + 11, o.v, o.v + 11); }
 };
 struct TuneCand {
-  int32_t shape, big, ksplit;
+  int32_t shape, big, ksplit, band;
 };
 struct TuneEntry {
   std::vector<TuneCand> cands;
@@ -56,7 +56,9 @@ struct green_plan {
   int prec = GREEN_FP64;
   int tc = 1;  // tau nodes per contraction chunk
   int big_stage1 = 1;  // split-BF16 stage-1 kernel: 0 = 64 x 64 tiles, 1 = 192 x 96, 2 = 192 x 64
-  int big_p0 = 1;      // split-BF16 P~0 stage-2 kernel: 1 = 192 x 96 tiles, 2 = 192 x 64
+  int big_p0 = 1;      // split-BF16 P~0 stage-2 kernel: 1 = 192 x 96 tiles, 2 = 192 x 64, 3 = 320 x 64, 4 = 448 x 64,
+                       // LDS-DMA 5 = 320 x 64, 6 = 192 x 128
+                       // (set at plan creation from naux)
   std::vector<double> tau, wf, wb;
   std::vector<double2> TF_t2w, TF_w2t, TB_t2w, TB_w2t, Emass;
   std::vector<int32_t> kadd, ksub, kneg;  // [q][k]: k+q, k-q; [q]: -q
@@ -294,34 +296,54 @@ void apply_cand(ZGemm& g, const TuneCand& c) {
   g.shape = c.shape;
   g.big = c.big;
   g.ksplit = c.ksplit;
+  g.band = c.band;
   g.partial = c.ksplit > 1 ? tl_split.ptr : nullptr;
 }
 
-// Candidates for one contraction: the large-tile kernel (both tile widths) where the operands allow it,
+// Candidates for one contraction: the large-tile kernel (each tile shape) where the operands allow it,
 // the 256-thread kernel at the size-picked tile and at 64 x 64, each at the default split-K count, twice
-// and half of it.  The first candidate is the default choice.
+// and half of it (large tiles also at whole waves of workgroups).  The first candidate is the default.
 std::vector<TuneCand> tune_candidates(const ZGemm& g0) {
   std::vector<TuneCand> out;
   auto add = [&](int shape, int big) {
     ZGemm g = g0;
     g.shape = shape;
     g.big = big;
-    if (big && green::zgemm_variant(g).family != 3) return;
+    const int fam = green::zgemm_variant(g).family;
+    if (big && fam != (big >= 5 ? 4 : 3)) return;
     g.ksplit = 1;
     const int ks0 = choose_ksplit(g);
-    const int opts[3] = {ks0, std::min(2 * ks0, 32), ks0 / 2};
+    // large tiles run one workgroup per CU: also the split-K counts that fill one, two and three waves
+    // of the 256 CUs as closely as possible from below
+    int bm, bn, threads;
+    green::zgemm_tile(g, &bm, &bn, &threads);
+    const int64_t tiles = (int64_t)((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn) * g.batch;
+    int opts[6] = {ks0, std::min(2 * ks0, 32), ks0 / 2, 0, 0, 0};
+    if (threads == 512)
+      for (int w = 1; w <= 3; ++w) opts[2 + w] = (int)std::min<int64_t>(256 * w / tiles, 32);
     for (int ks : opts) {
       if (ks < 1 || ks > std::max(1, g.K / 16)) continue;
       if (ks > 1 && (int64_t)ks * g.batch * g.M * g.N > tl_split.cap) continue;
       bool dup = false;
-      for (const TuneCand& c : out) dup = dup || (c.shape == shape && c.big == big && c.ksplit == ks);
-      if (!dup) out.push_back(TuneCand{shape, big, ks});
+      for (const TuneCand& c : out)
+        dup = dup || (c.shape == shape && c.big == big && c.ksplit == ks && c.band == 0);
+      if (!dup) out.push_back(TuneCand{shape, big, ks, 0});
     }
+    // large tiles over many tile rows: bands of 4 and 16 tile rows at the default split-K count
+    if (threads == 512 && ks0 >= 1 && ks0 <= std::max(1, g.K / 16))
+      for (int b : {4, 16})
+        if ((g.M + bm - 1) / bm > b && (g.N + bn - 1) / bn > 1) out.push_back(TuneCand{shape, big, ks0, b});
   };
   add(g0.shape, g0.big);  // the default (size-picked tile, requested large tile)
   if (g0.prec == 2) {
     add(0, 1);
     add(0, 2);
+    // tall 320- and 448-row tiles where M needs more than one 192-row (320-row) tile
+    if (g0.M > 192) add(0, 3);
+    if (g0.M > 320) add(0, 4);
+    // LDS-DMA tiles (where the operands allow them)
+    add(0, 5);
+    add(0, 6);
   }
   add(0, 0);
   add(4, 0);
@@ -360,6 +382,7 @@ int gemm(green::Site site, const char* label, const ZOp& A, const green::Span& s
   g.ctype = ctype;
   g.big = big;
   g.shape = 0;
+  g.band = 0;
   g.ksplit = 1;
   g.ksplit = choose_ksplit(g);
   g.partial = g.ksplit > 1 ? tl_split.ptr : nullptr;
@@ -622,6 +645,8 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
   const int xt = bf ? green::kCB16 : (mixed ? green::kC32 : green::kC64);      // X and Y
   const int gt = bf ? green::kCB16 : green::kC64;                              // G and the V of stage 3
   const int stage = p->prec == GREEN_FP64 ? 0 : (bf ? 2 : 1);
+  // split-BF16 plans with an even naux run stage 1 on the LDS-DMA kernel (K-contiguous V slab)
+  const bool vt_dma = bf && naux % 2 == 0;
   void* Vx = at<void>(ws, p->r_Vx);
   const green::Span sVx = span_ws(ws, p->r_Vx);
   void* Ptx = at<void>(ws, p->r_Ptx);
@@ -641,12 +666,18 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
     green::Span sVa = span(V, ex.V), sVb = span(V, ex.V);
     if (mixed) {
       if ((int64_t)p->r_Vx.bytes < (bf ? 2 : 1) * slab * green::elem_bytes(vt)) return GREEN_EINVAL;
-      GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64(static_cast<const double2*>(Vqn), Vx, vt, slab, st_); }));
+      if (vt_dma) {
+        // V^{k,k-q} stored [k][(i,a)][Q]: the contraction index Q runs contiguously for the LDS-DMA kernel
+        GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64_tr(static_cast<const double2*>(Vqn), Vx, vt, naux, (int)nG, nk, st_); }));
+      } else {
+        GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64(static_cast<const double2*>(Vqn), Vx, vt, slab, st_); }));
+      }
       Vqn = Vx;
       sVa = sVx;
       if (bf) {
-        if (q != qn) GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64(static_cast<const double2*>(Vq), eptr(Vx, vt, slab), vt, slab, st_); }));
-        Vq = q != qn ? eptr(Vx, vt, slab) : Vx;
+        const bool own = q != qn || vt_dma;  // stage 3 needs its own (untransposed) slab
+        if (own) GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64(static_cast<const double2*>(Vq), eptr(Vx, vt, slab), vt, slab, st_); }));
+        Vq = own ? eptr(Vx, vt, slab) : Vx;
         sVb = sVx;
       }
     }
@@ -662,9 +693,11 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
       GREEN_TRY(gemm(green::Site::Sig_PV, "Sigma.PV",
                      bf ? op(eptr(Ptx, green::kCB16, (int64_t)t0 * nP), flat(naux), flat(1), bnone(), green::kCB16)
                         : op(Pp + ((int64_t)q * ntau + t0) * nP, two(naux, 1, nP), flat(naux), bnone()),
-                     bf ? sPtx : sP, op(Vqn, flat(nG), two((int32_t)nG, 1, nV), bnone(), mixed ? vt : green::kC64),
+                     bf ? sPtx : sP,
+                     vt_dma ? op(Vqn, flat(1), flat(naux), bnone(), green::kCB16)
+                            : op(Vqn, flat(nG), two((int32_t)nG, 1, nV), bnone(), mixed ? vt : green::kC64),
                      sVa, T1, sT1, two(naux, nG, (int64_t)nk * nV), two((int32_t)nG, 1, nV), bnone(), tcn * naux,
-                     (int)(nk * nG), naux, 1, cplx(1), cplx(0), s, p->prec, xt, bf ? 1 : 0));
+                     (int)(nk * nG), naux, 1, cplx(1), cplx(0), s, p->prec, xt, bf ? (vt_dma ? 6 : 1) : 0));
       for (int sp = 0; sp < ns; ++sp) {
         // Y[tt][k][(Q',i)][b] = sum_a X[tt][k][(Q',i)][a] G^{k-q}_{ab}(tau)
         GREEN_TRY(gemm(green::Site::Sig_XG, "Sigma.XG", op(T1, flat(nao), flat(1), bflat(nV), xt), sT1,
@@ -1199,8 +1232,20 @@ int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, 
   int tc = (int)std::max<size_t>(1, chunk_bytes / per_t);
   tc = std::min(tc, ntau);
   p->tc = tc;
-  if (const char* e = std::getenv("GREEN_STAGE1_BIG")) p->big_stage1 = std::atoi(e);
-  if (const char* e = std::getenv("GREEN_P0_BIG")) p->big_p0 = std::atoi(e);
+  // default tile of the split-BF16 P~0 contraction (naux x naux outputs): the least padded area, the
+  // 192 x 96 tile (highest arithmetic intensity) counted at 90% of its area
+  {
+    static const int tile[4][2] = {{192, 96}, {192, 64}, {320, 64}, {448, 64}};
+    double best = 0;
+    for (int b = 0; b < 4; ++b) {
+      const double a = (double)((naux + tile[b][0] - 1) / tile[b][0] * tile[b][0]) *
+                       ((naux + tile[b][1] - 1) / tile[b][1] * tile[b][1]) * (b == 0 ? 0.9 : 1.0);
+      if (b == 0 || a < best) {
+        best = a;
+        p->big_p0 = b + 1;
+      }
+    }
+  }
   size_t off = 0;
   auto take = [&](Region& r, size_t bytes) {
     r.off = off;
@@ -1489,6 +1534,16 @@ int green_plan_set_option(green_plan* p, int option, int value) {
       p->use_graph = value;
       if (!value) drop_graph(p);
       return GREEN_OK;
+    case GREEN_OPT_P0_TILE:
+      if (value < 1 || value > 6) return GREEN_EINVAL;
+      p->big_p0 = value;
+      drop_graph(p);
+      return GREEN_OK;
+    case GREEN_OPT_STAGE1_TILE:
+      if (value < 0 || value > 2) return GREEN_EINVAL;
+      p->big_stage1 = value;
+      drop_graph(p);
+      return GREEN_OK;
     default:
       return GREEN_EINVAL;
   }
@@ -1510,9 +1565,21 @@ int green_plan_tuning_report(const green_plan* p, char* buf, size_t len) {
     } else {
       const TuneCand& c = e.cands[e.chosen];
       std::snprintf(line, sizeof(line),
-                    "%-12s M=%d N=%d K=%d batch=%d prec=%d: shape=%d big=%d ksplit=%d %.1f us (default %.1f us)\n",
-                    names[site], k.v[1], k.v[2], k.v[3], k.v[4], k.v[5], c.shape, c.big, c.ksplit,
+                    "%-12s M=%d N=%d K=%d batch=%d prec=%d: shape=%d big=%d ksplit=%d band=%d %.1f us (default %.1f us)\n",
+                    names[site], k.v[1], k.v[2], k.v[3], k.v[4], k.v[5], c.shape, c.big, c.ksplit, c.band,
                     1000.0 * e.ms[e.chosen], 1000.0 * e.ms[0]);
+      out += line;
+      // every candidate's time: shape/big/ksplit/band=us
+      std::string all = "    candidates:";
+      for (size_t i = 0; i < e.cands.size(); ++i) {
+        char item[64];
+        std::snprintf(item, sizeof(item), " %d/%d/%d/%d=%.0f", e.cands[i].shape, e.cands[i].big, e.cands[i].ksplit,
+                      e.cands[i].band, 1000.0 * e.ms[i]);
+        all += item;
+      }
+      all += "\n";
+      out += all;
+      continue;
     }
     out += line;
   }

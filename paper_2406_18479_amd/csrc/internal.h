@@ -85,8 +85,12 @@ struct ZGemm {
   int32_t prec;   // 0: FP64 MFMA, 1: FP32 MFMA, 2: split BF16 (hi + lo, three products) MFMA; prec 1 and 2
                   // accumulate in FP32 within a K slice, slices are combined in FP64
   int32_t ctype;  // ElemType of C (kCB16 requires beta == 0); prec 0 requires kC64 operands and output
-  int32_t big;    // prec 2 with kCB16 operands: 1 = 192 x 96 tiles, 2 = 192 x 64 tiles (large-tile kernel)
+  int32_t big;    // prec 2 with kCB16 operands, large-tile kernel: 1 = 192 x 96 tiles, 2 = 192 x 64,
+                  // 3 = 320 x 64, 4 = 448 x 64 (3 and 4 need a K-contiguous B); LDS-DMA kernel (K-contiguous
+                  // A and B, even K and strides, else as 1): 5 = 320 x 64, 6 = 192 x 128
   int32_t shape;  // 256-thread kernels: 0 = by size, 1..4 = 32x32, 32x64, 64x32, 64x64 tiles
+  int32_t band;   // large-tile kernel: 0 = output tiles in column order; b > 0 = bands of b tile rows,
+                  // each walked column by column (the A rows of a band stay in L2)
 };
 
 // Kernel variant a descriptor launches: family 0 FP64, 1 FP32, 2 split BF16 (256 threads), 3 split BF16
@@ -120,6 +124,8 @@ struct Span {
 hipError_t convert_c64(const double2* in, void* out, int32_t etype, int64_t n, hipStream_t s);
 // out[b][j][i] = round(in[b][i][j]) for `batch` n x n matrices (kC32 or kCB16)
 hipError_t convert_c64_t(const double2* in, void* out, int32_t etype, int n, int64_t batch, hipStream_t s);
+// out[b][c][r] = in[b][r][c] rounded to kC32 or kCB16 (rows x cols matrices, batch of them).
+hipError_t convert_c64_tr(const double2* in, void* out, int32_t etype, int rows, int cols, int batch, hipStream_t s);
 
 // Host-side bounds check of a GEMM descriptor against the buffers its operands point into (conservative:
 // the box spanned by the index maps).  Returns false and fills `why` when an access could leave a buffer.

@@ -661,31 +661,107 @@ struct KCur {
   }
 };
 
-// word index of (row r, complex k) in a 32-word LDS plane row with swizzled 16-byte chunks
-__device__ __forceinline__ int bt_word(int r, int k) { return r * 32 + ((((k >> 2) ^ (r >> 1)) & 7) << 2) + (k & 3); }
+// K depth of a large tile: 32 complex when both double-buffered planes of the A and B tiles fit the
+// 160 KB LDS at that depth, else 16.
+constexpr int bt_bk(int FM, int FN) { return (64 * FM + 32 * FN) * 32 * 16 <= 160 * 1024 ? 32 : 16; }
 
-template <int FM, int FN, bool BNC>
-__device__ __forceinline__ void bt_body(const ZGemm& g, int64_t bid0, int64_t nblk) {
-  constexpr int BM = 64 * FM, BN = 32 * FN, BK = 32;
-  constexpr int EA = BM * BK / 512;
-  constexpr int EB = BN * BK / 512;
-  __shared__ uint32_t As[2][2][BM * 32];
-  __shared__ uint32_t Bs[2][2][BN * 32];
+// word index of (row r, complex k) in a BK-word LDS plane row with swizzled 16-byte chunks: the 16 rows
+// of one fragment read at one K offset land on 16 distinct 16-byte bank groups
+template <int BK>
+__device__ __forceinline__ int bt_word(int r, int k) {
+  if constexpr (BK == 32) return r * 32 + ((((k >> 2) ^ (r >> 1)) & 7) << 2) + (k & 3);
+  else return r * 16 + ((((k >> 2) ^ (r >> 2)) & 3) << 2) + (k & 3);
+}
 
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
+// Output tile of a large-tile workgroup: XCD-aware renumbering, then (batch, K slice, tile); tiles in
+// column order, or in bands of g.band tile rows each walked column by column.
+struct LargeTile {
+  int32_t batch, slice, m0, n0;
+};
+__device__ __forceinline__ LargeTile large_tile(const ZGemm& g, int64_t bid0, int64_t nblk, int BM, int BN) {
   const int tiles_m = (g.M + BM - 1) / BM;
   const int tiles_n = (g.N + BN - 1) / BN;
   const int64_t per_batch = (int64_t)tiles_m * tiles_n;
   const int64_t bid = xcd_block(bid0, nblk);
   const int64_t group = bid / per_batch;
   const int32_t tile = (int32_t)(bid - group * per_batch);
-  const int32_t batch = (int32_t)(group / g.ksplit);
-  const int32_t slice = (int32_t)(group - (int64_t)batch * g.ksplit);
-  const int tm = tile % tiles_m;
-  const int tn = tile / tiles_m;
-  const int m0 = tm * BM, n0 = tn * BN;
+  LargeTile t;
+  t.batch = (int32_t)(group / g.ksplit);
+  t.slice = (int32_t)(group - (int64_t)t.batch * g.ksplit);
+  int tm = tile % tiles_m;
+  int tn = tile / tiles_m;
+  if (g.band > 0 && g.band < tiles_m) {
+    const int32_t per = g.band * tiles_n;
+    const int32_t bi = tile / per, r = tile - bi * per;
+    const int gb = min(g.band, tiles_m - bi * g.band);
+    tn = r / gb;
+    tm = bi * g.band + (r - tn * gb);
+  }
+  t.m0 = tm * BM;
+  t.n0 = tn * BN;
+  return t;
+}
+
+// Epilogue of a large tile: a wave's FM x FN fragments (16 x 16 each, rows from mw, columns from nw) to
+// the split-K partial sums (FP64) or through the C maps.
+template <int FM, int FN>
+__device__ __forceinline__ void large_tile_store(const ZGemm& g, const f4 (&acc_re)[FM][FN], const f4 (&acc_im)[FM][FN],
+                                                 int32_t batch, int32_t slice, int mw, int nw, int lane) {
+  if (g.ksplit > 1) {
+    double2* __restrict__ Pp = g.partial + ((int64_t)slice * g.batch + batch) * (int64_t)g.M * g.N;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = mw + 16 * i + 4 * (lane >> 4) + r;
+        if (gm >= g.M) continue;
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const int gn = nw + 16 * j + (lane & 15);
+          if (gn < g.N)
+            Pp[(int64_t)gm * g.N + gn] = make_double2((double)acc_re[i][j][r], (double)acc_im[i][j][r]);
+        }
+      }
+    return;
+  }
+  const int64_t cb = batch_off(g.cb, batch);
+  int64_t coff[FN];
+#pragma unroll
+  for (int j = 0; j < FN; ++j) {
+    const int gn = nw + 16 * j + (lane & 15);
+    coff[j] = gn < g.N ? map_idx(g.cc, gn) : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gm = mw + 16 * i + 4 * (lane >> 4) + r;
+      if (gm >= g.M) continue;
+      const int64_t roff = cb + map_idx(g.cr, gm);
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int gn = nw + 16 * j + (lane & 15);
+        if (gn < g.N) store_cf(g, roff + coff[j], acc_re[i][j][r], acc_im[i][j][r]);
+      }
+    }
+}
+
+template <int FM, int FN, bool BNC>
+__device__ __forceinline__ void bt_body(const ZGemm& g, int64_t bid0, int64_t nblk) {
+  constexpr int BM = 64 * FM, BN = 32 * FN, BK = bt_bk(FM, FN);
+  constexpr int EA = BM * BK / 512;
+  constexpr int EB = BN * BK / 512;
+  constexpr int RS = 512 / BK;  // rows staged per pass of the 512 threads
+  static_assert(BK == 16 || BK == 32, "large-tile K depth");
+  __shared__ uint32_t As[2][2][BM * BK];
+  __shared__ uint32_t Bs[2][2][BN * BK];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const LargeTile lt = large_tile(g, bid0, nblk, BM, BN);
+  const int32_t batch = lt.batch, slice = lt.slice;
+  const int m0 = lt.m0, n0 = lt.n0;
   const int kchunk = ((g.K + g.ksplit - 1) / g.ksplit + BK - 1) / BK * BK;
   const int kbeg = slice * kchunk;
   const int kend = min(g.K, kbeg + kchunk);
@@ -697,15 +773,15 @@ __device__ __forceinline__ void bt_body(const ZGemm& g, int64_t bid0, int64_t nb
   // read the slice's first K index: every load stays in bounds and carries no branch; such elements
   // are zeroed when staged.
   const int a_k = tid & (BK - 1);
-  const int a_r0 = tid >> 5;  // rows a_r0 + 16 e
-  // K-contiguous B: like A (32 consecutive K of 16 columns per wave).  N-contiguous B: a wave stages
+  const int a_r0 = tid / BK;  // rows a_r0 + RS e
+  // K-contiguous B: like A (BK consecutive K of 512 / BK columns per wave).  N-contiguous B: a wave stages
   // 16 consecutive columns at 4 consecutive K, so its LDS writes fall on distinct banks.
   int b_n[EB], b_k[EB];
 #pragma unroll
   for (int e = 0; e < EB; ++e) {
     if constexpr (b_kc) {
       b_k[e] = tid & (BK - 1);
-      b_n[e] = (tid >> 5) + 16 * e;
+      b_n[e] = tid / BK + RS * e;
     } else {
       const int c = wave * EB + e;
       b_n[e] = 16 * (c % (BN / 16)) + (lane & 15);
@@ -735,7 +811,7 @@ __device__ __forceinline__ void bt_body(const ZGemm& g, int64_t bid0, int64_t nb
     const int64_t ao = ak ? acur.off : a_first;
     uint32_t m = ak ? 1u : 0u;
 #pragma unroll
-    for (int e = 0; e < EA; ++e) ra[e] = Ap[(int64_t)min(m0 + a_r0 + 16 * e, g.M - 1) * a_rs + ao];
+    for (int e = 0; e < EA; ++e) ra[e] = Ap[(int64_t)min(m0 + a_r0 + RS * e, g.M - 1) * a_rs + ao];
     if constexpr (b_kc) {
       const bool bk = bcur.k < kend;
       const int64_t bo = bk ? bcur.off : b_first;
@@ -759,15 +835,15 @@ __device__ __forceinline__ void bt_body(const ZGemm& g, int64_t bid0, int64_t nb
   auto stage = [&](int buf) {
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
-      const bool keep = (m0 + a_r0 + 16 * e < g.M) && (okm & 1u);
-      const int w = bt_word(a_r0 + 16 * e, a_k);
+      const bool keep = (m0 + a_r0 + RS * e < g.M) && (okm & 1u);
+      const int w = bt_word<BK>(a_r0 + RS * e, a_k);
       As[buf][0][w] = keep ? (ra[e].x ^ aflip) : 0u;
       As[buf][1][w] = keep ? (ra[e].y ^ aflip) : 0u;
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
       const bool keep = (n0 + b_n[e] < g.N) && (okm & (2u << e));
-      const int w = bt_word(b_n[e], b_k[e]);
+      const int w = bt_word<BK>(b_n[e], b_k[e]);
       Bs[buf][0][w] = keep ? (rb[e].x ^ bflip) : 0u;
       Bs[buf][1][w] = keep ? (rb[e].y ^ bflip) : 0u;
     }
@@ -789,13 +865,13 @@ __device__ __forceinline__ void bt_body(const ZGemm& g, int64_t bid0, int64_t nb
       u4 bh[FN], bl[FN];
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
-        const int w = bt_word(colb + 16 * j + (lane & 15), kq);
+        const int w = bt_word<BK>(colb + 16 * j + (lane & 15), kq);
         bh[j] = *reinterpret_cast<const u4*>(&Bs[buf][0][w]);
         bl[j] = *reinterpret_cast<const u4*>(&Bs[buf][1][w]);
       }
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
-        const int w = bt_word(rowb + 16 * i + (lane & 15), kq);
+        const int w = bt_word<BK>(rowb + 16 * i + (lane & 15), kq);
         const u4 ah = *reinterpret_cast<const u4*>(&As[buf][0][w]);
         const u4 al = *reinterpret_cast<const u4*>(&As[buf][1][w]);
         const bf8 anh = as_bf8(neg_im(ah)), anl = as_bf8(neg_im(al));
@@ -815,9 +891,10 @@ __device__ __forceinline__ void bt_body(const ZGemm& g, int64_t bid0, int64_t nb
     }
   };
 
-  // The next step's elements are staged into the other LDS buffer between the two MFMA K steps of the
-  // current one (that buffer was last read before the previous barrier), and the loads of the step
-  // after are issued right behind, so every load has a full iteration to land.
+  // The next step's elements are staged into the other LDS buffer (last read before the previous
+  // barrier) between the two MFMA K steps of the current one (BK = 32) or ahead of its one K step
+  // (BK = 16), and the loads of the step after are issued right behind, so every load has a full
+  // iteration to land.
   if (nkt > 0) {
     load();
     stage(0);
@@ -825,51 +902,191 @@ __device__ __forceinline__ void bt_body(const ZGemm& g, int64_t bid0, int64_t nb
     if (nkt > 1) load();
     for (int it = 0; it < nkt; ++it) {
       const int buf = it & 1;
-      compute(buf, 0);
+      if constexpr (BK == 32) compute(buf, 0);
       if (it + 1 < nkt) stage(buf ^ 1);
       if (it + 2 < nkt) load();
-      compute(buf, 1);
+      compute(buf, BK == 32 ? 1 : 0);
       __syncthreads();
     }
   }
 
-  if (g.ksplit > 1) {
-    double2* __restrict__ Pp = g.partial + ((int64_t)slice * g.batch + batch) * (int64_t)g.M * g.N;
+  large_tile_store<FM, FN>(g, acc_re, acc_im, batch, slice, m0 + rowb, n0 + colb, lane);
+}
+
+// Split-BF16 large tiles fed by LDS DMA (K-contiguous A and B).  The tile (64 FM x 32 FN, 8 waves as
+// 4 x 2, fragments as in the kernel above) advances 16 complex K per stage over a ring of three LDS
+// stages: the global -> LDS copies of stage t + 2 are issued right after the barrier that opens stage
+// t, so two stages of loads are always in flight and no register holds staged data.
+//
+// LDS rows hold the 16 complex K of one A row (B column) as 8 chunks of 16 bytes (2 complex, hi/lo
+// interleaved as in memory); chunk c of row r sits at slot c ^ ((r >> 1) & 7), which puts the 16 rows
+// of a fragment read on 16 distinct 16-byte bank groups.  One DMA instruction moves 1 KB: 8 rows of a
+// stage, lane l writing slot l & 7 of row l >> 3 (so it reads the chunk that belongs there).  Rows
+// (columns) beyond M (N) read row M-1 (column N-1); chunks past the slice's K end read the stage's
+// first chunk and are zeroed in LDS once landed.  Requirements (checked on the host): K even, K maps
+// flat or with an even extent of at least 16, even element strides, 16-byte aligned operands.
+constexpr int kDmaStages = 3;
+
+// wait until at most N vector-memory operations of this wave are outstanding (loads return in order)
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+// workgroup barrier; memory operations are not moved across it, the counter waits are explicit
+__device__ __forceinline__ void barrier_only() { asm volatile("s_barrier" ::: "memory"); }
+
+__device__ __forceinline__ int bd_slot(int r, int c) { return c ^ ((r >> 1) & 7); }
+
+// One wave-wide 16-byte-per-lane copy global -> LDS (lane l lands at lds + 16 l bytes).  The LDS target is
+// passed as a bare LDS address, so the compiler does not pair these copies with the fragment reads (it
+// would otherwise wait for every copy in flight before each read); the waits are explicit.
+__device__ __forceinline__ void dma16(const void* src, uint32_t* lds) {
+  __builtin_amdgcn_global_load_lds(const_cast<void*>(src),
+                                   (__attribute__((address_space(3))) void*)(uintptr_t)(uint32_t)(uintptr_t)lds, 16, 0,
+                                   0);
+}
+
+template <int FM, int FN>
+__device__ __forceinline__ void bd_body(const ZGemm& g, int64_t bid0, int64_t nblk) {
+  constexpr int BM = 64 * FM, BN = 32 * FN, BK = 16;
+  constexpr int DA = BM / 64, DB = BN / 64;  // DMA instructions per wave and stage
+  static_assert(BN % 64 == 0, "B tile of whole DMA groups");
+  constexpr int D = DA + DB;
+  __shared__ __attribute__((aligned(16))) uint32_t A0[BM * 32], A1[BM * 32], A2[BM * 32];
+  __shared__ __attribute__((aligned(16))) uint32_t B0[BN * 32], B1[BN * 32], B2[BN * 32];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const LargeTile lt = large_tile(g, bid0, nblk, BM, BN);
+  const int32_t batch = lt.batch, slice = lt.slice;
+  const int m0 = lt.m0, n0 = lt.n0;
+  const int kchunk = ((g.K + g.ksplit - 1) / g.ksplit + BK - 1) / BK * BK;
+  const int kbeg = slice * kchunk;
+  const int kend = min(g.K, kbeg + kchunk);
+  const int nkt = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+
+  const uint2* __restrict__ Ap = reinterpret_cast<const uint2*>(g.A.p) + batch_off(g.A.b, batch);
+  const uint2* __restrict__ Bp = reinterpret_cast<const uint2*>(g.B.p) + batch_off(g.B.b, batch);
+  // per lane and DMA instruction: row (column) offset and the chunk it carries
+  int64_t a_ro[DA], b_co[DB];
+  int a_c[DA], b_c[DB];
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int gm = m0 + rowb + 16 * i + 4 * (lane >> 4) + r;
-        if (gm >= g.M) continue;
-#pragma unroll
-        for (int j = 0; j < FN; ++j) {
-          const int gn = n0 + colb + 16 * j + (lane & 15);
-          if (gn < g.N)
-            Pp[(int64_t)gm * g.N + gn] = make_double2((double)acc_re[i][j][r], (double)acc_im[i][j][r]);
-        }
-      }
-    return;
+  for (int j = 0; j < DA; ++j) {
+    const int r = 8 * (wave * DA + j) + (lane >> 3);
+    a_ro[j] = map_idx(g.A.r, min(m0 + r, g.M - 1));
+    a_c[j] = bd_slot(r, lane & 7);
   }
-  const int64_t cb = batch_off(g.cb, batch);
-  int64_t coff[FN];
 #pragma unroll
-  for (int j = 0; j < FN; ++j) {
-    const int gn = n0 + colb + 16 * j + (lane & 15);
-    coff[j] = gn < g.N ? map_idx(g.cc, gn) : 0;
+  for (int j = 0; j < DB; ++j) {
+    const int r = 8 * (wave * DB + j) + (lane >> 3);
+    b_co[j] = map_idx(g.B.c, min(n0 + r, g.N - 1));
+    b_c[j] = bd_slot(r, lane & 7);
   }
+  // stage K cursors (uniform): offset of the stage's first complex under each K map
+  KCur acur, bcur;
+  acur.init(g.A.c, kbeg);
+  bcur.init(g.B.r, kbeg);
+  const int64_t a_din = (int64_t)BK * g.A.c.s_in, a_wrap = g.A.c.s_out - (int64_t)g.A.c.ext * g.A.c.s_in;
+  const int64_t b_din = (int64_t)BK * g.B.r.s_in, b_wrap = g.B.r.s_out - (int64_t)g.B.r.ext * g.B.r.s_in;
+  // offset of complex k0 + 2c (k0 = the cursor's; unit K stride), or of k0 when that lies past the
+  // slice's end
+  auto chunk_off = [&](const KCur& cur, const IdxMap& m, int64_t wrap, int c) -> int64_t {
+    const int lo = cur.lo + 2 * c;
+    const int64_t off = cur.off + 2 * c + (lo >= m.ext ? wrap : 0);
+    return cur.k + 2 * c < kend ? off : cur.off;
+  };
+  auto issue = [&](uint32_t* As, uint32_t* Bs) {
+#pragma unroll
+    for (int j = 0; j < DA; ++j)
+      dma16(Ap + a_ro[j] + chunk_off(acur, g.A.c, a_wrap, a_c[j]), As + (wave * DA + j) * 256);
+#pragma unroll
+    for (int j = 0; j < DB; ++j)
+      dma16(Bp + b_co[j] + chunk_off(bcur, g.B.r, b_wrap, b_c[j]), Bs + (wave * DB + j) * 256);
+    acur.step(g.A.c, BK, a_din, a_wrap);
+    bcur.step(g.B.r, BK, b_din, b_wrap);
+  };
+
+  f4 acc_re[FM][FN], acc_im[FM][FN];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int gm = m0 + rowb + 16 * i + 4 * (lane >> 4) + r;
-      if (gm >= g.M) continue;
-      const int64_t roff = cb + map_idx(g.cr, gm);
+    for (int j = 0; j < FN; ++j) {
+      acc_re[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      acc_im[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+  const int wm = wave & 3, wn = wave >> 2;
+  const int rowb = wm * 16 * FM, colb = wn * 16 * FN;
+  const int g4 = lane >> 4, r16 = lane & 15;
+  // hi and lo words of this lane's 4 complex K (chunks 2 g4 and 2 g4 + 1) of LDS row r
+  auto frag = [&](const uint32_t* P, int r, u4& hi, u4& lo) {
+    const u4 x = *reinterpret_cast<const u4*>(P + r * 32 + 4 * bd_slot(r, 2 * g4));
+    const u4 y = *reinterpret_cast<const u4*>(P + r * 32 + 4 * bd_slot(r, 2 * g4 + 1));
+    hi = u4{x.x, x.z, y.x, y.z};
+    lo = u4{x.y, x.w, y.y, y.w};
+  };
+  auto compute = [&](const uint32_t* As, const uint32_t* Bs) {
+    u4 bh[FN], bl[FN];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) frag(Bs, colb + 16 * j + r16, bh[j], bl[j]);
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+      u4 ah, al;
+      frag(As, rowb + 16 * i + r16, ah, al);
+      const bf8 anh = as_bf8(neg_im(ah)), anl = as_bf8(neg_im(al));
+      const bf8 aph = as_bf8(ah), apl = as_bf8(al);
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
-        const int gn = n0 + colb + 16 * j + (lane & 15);
-        if (gn < g.N) store_cf(g, roff + coff[j], acc_re[i][j][r], acc_im[i][j][r]);
+        const bf8 bph = as_bf8(bh[j]), bpl = as_bf8(bl[j]);
+        const bf8 bsh = as_bf8(swap_re_im(bh[j])), bsl = as_bf8(swap_re_im(bl[j]));
+        acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(anh, bph, acc_re[i][j], 0, 0, 0);
+        acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aph, bsh, acc_im[i][j], 0, 0, 0);
+        acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(anh, bpl, acc_re[i][j], 0, 0, 0);
+        acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aph, bsl, acc_im[i][j], 0, 0, 0);
+        acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(anl, bph, acc_re[i][j], 0, 0, 0);
+        acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(apl, bsh, acc_im[i][j], 0, 0, 0);
       }
     }
+  };
+  // chunks past the slice's K end in a landed stage -> 0 (every row of both tiles)
+  const int kvalid_last = (kend - kbeg) - BK * (nkt - 1);  // complex K of the last stage, even
+  auto zero_tail = [&](uint32_t* As, uint32_t* Bs) {
+    for (int x = tid; x < (BM + BN) * 8; x += 512) {
+      const int r = x >> 3, c = x & 7;
+      if (2 * c < kvalid_last) continue;
+      uint32_t* P = r < BM ? As + r * 32 : Bs + (r - BM) * 32;
+      const int rr = r < BM ? r : r - BM;
+      *reinterpret_cast<u4*>(P + 4 * bd_slot(rr, c)) = u4{0u, 0u, 0u, 0u};
+    }
+  };
+  // one stage: own copies landed -> barrier (all copies landed, previous stage's buffer free) -> issue
+  // stage t + 2 into that buffer -> MFMA
+  auto step = [&](uint32_t* As, uint32_t* Bs, uint32_t* An, uint32_t* Bn, int t) {
+    if (t + 1 < nkt) wait_vm<D>();
+    else wait_vm<0>();
+    if (t == nkt - 1 && kvalid_last < BK) {
+      __syncthreads();
+      zero_tail(As, Bs);
+      __syncthreads();
+    } else {
+      barrier_only();
+    }
+    if (t + 2 < nkt) issue(An, Bn);
+    compute(As, Bs);
+  };
+  if (nkt > 0) {
+    issue(A0, B0);
+    if (nkt > 1) issue(A1, B1);
+    for (int it = 0; it < nkt; it += kDmaStages) {
+      step(A0, B0, A2, B2, it);
+      if (it + 1 < nkt) step(A1, B1, A0, B0, it + 1);
+      if (it + 2 < nkt) step(A2, B2, A1, B1, it + 2);
+    }
+  }
+  // every wave is done with the LDS stages before any wave of a persistent group starts another tile
+  __syncthreads();
+  large_tile_store<FM, FN>(g, acc_re, acc_im, batch, slice, m0 + rowb, n0 + colb, lane);
 }
 
 // Second pass of split-K: C = alpha * sum_slices partial + beta * C, slices added in order.
@@ -910,6 +1127,10 @@ template <int FM, int FN, bool BNC, Site SITE>
 __global__ __launch_bounds__(512) void zgemm_bt_kernel(const ZGemm g) {
   bt_body<FM, FN, BNC>(g, blockIdx.x, gridDim.x);
 }
+template <int FM, int FN, Site SITE>
+__global__ __launch_bounds__(512) void zgemm_bd_kernel(const ZGemm g) {
+  bd_body<FM, FN>(g, blockIdx.x, gridDim.x);
+}
 
 struct GroupArgs {
   const ZGemm* gs;       // device array of n descriptors
@@ -941,6 +1162,10 @@ template <int FM, int FN, bool BNC>
 __global__ __launch_bounds__(512) void zgemm_bt_group(const GroupArgs a) {
   group_loop(a, [](const ZGemm& g, int64_t b, int64_t n) { bt_body<FM, FN, BNC>(g, b, n); });
 }
+template <int FM, int FN>
+__global__ __launch_bounds__(512) void zgemm_bd_group(const GroupArgs a) {
+  group_loop(a, [](const ZGemm& g, int64_t b, int64_t n) { bd_body<FM, FN>(g, b, n); });
+}
 // split-K second pass of a group: descriptor blockIdx.y, elements strided over blockIdx.x
 __global__ __launch_bounds__(256) void zgemm_splitk_reduce_group(const ZGemm* __restrict__ gs) {
   const ZGemm& g = gs[blockIdx.y];
@@ -956,6 +1181,37 @@ __global__ void k_convert_c64_t(const double2* __restrict__ in, void* __restrict
     const int e = (int)(x - b * nn);
     const int j = e / n, i = e - (e / n) * n;  // output element (j, i) <- input (i, j)
     const double2 v = in[b * nn + (int64_t)i * n + j];
+    if (t == kC32) {
+      reinterpret_cast<float2*>(out)[x] = make_float2((float)v.x, (float)v.y);
+    } else {
+      uint2 w;
+      split_pair(v.x, v.y, w.x, w.y);
+      reinterpret_cast<uint2*>(out)[x] = w;
+    }
+  }
+}
+
+// out[b][c][r] = rounded in[b][r][c] for rows x cols matrices: 32 x 32 tiles staged through LDS so that
+// both the FP64 reads (along c) and the rounded writes (along r) are coalesced.
+__global__ __launch_bounds__(256) void k_convert_c64_tr(const double2* __restrict__ in, void* __restrict__ out,
+                                                        int32_t t, int rows, int cols) {
+  __shared__ double2 tile[32][33];
+  const int64_t b = blockIdx.z;
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const double2* src = in + b * rows * (int64_t)cols;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = r0 + ty + 8 * i, c = c0 + tx;
+    if (r < rows && c < cols) tile[ty + 8 * i][tx] = src[(int64_t)r * cols + c];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int c = c0 + ty + 8 * i, r = r0 + tx;
+    if (r >= rows || c >= cols) continue;
+    const double2 v = tile[tx][ty + 8 * i];
+    const int64_t x = b * rows * (int64_t)cols + (int64_t)c * rows + r;
     if (t == kC32) {
       reinterpret_cast<float2*>(out)[x] = make_float2((float)v.x, (float)v.y);
     } else {
@@ -1087,7 +1343,7 @@ bool zgemm_in_bounds(const ZGemm& g, const Span& a, const Span& b, const Span& c
 // The large-tile kernel needs pre-split operands, a K-contiguous A, and B either K-contiguous or
 // N-contiguous with the tile width dividing the 512 threads.
 static bool big_ok(const ZGemm& g) {
-  if (g.big != 1 && g.big != 2) return false;
+  if (g.big < 1 || g.big > 4) return false;
   if (g.A.etype != kCB16 || g.B.etype != kCB16) return false;
   if (!(g.A.c.s_in == 1 && g.A.c.ext >= 16)) return false;
   const bool b_nc = g.B.c.s_in == 1 && g.B.c.ext >= 16;
@@ -1097,18 +1353,60 @@ static bool big_ok(const ZGemm& g) {
   if (g.A.r.ext != kFlat) return false;
   if (!b_nc && g.B.c.ext != kFlat) return false;
   if (b_nc && g.B.r.ext != kFlat) return false;
+  // the tall K-depth-16 tiles are built for a K-contiguous B only
+  if (g.big >= 3 && b_nc) return false;
   return true;
 }
 
+// Large tiles (64 FM x 32 FN) by g.big: 1 = 192 x 96, 2 = 192 x 64, 3 = 320 x 64, 4 = 448 x 64.  The tall
+// ones cover an M of 257..320 (448) in one tile row with at most 1/16 of it padding.
+static void big_tile(int big, int* fm, int* fn) {
+  static const int t[4][2] = {{3, 3}, {3, 2}, {5, 2}, {7, 2}};
+  *fm = t[big - 1][0];
+  *fn = t[big - 1][1];
+}
+
+// The LDS-DMA kernel: split-BF16 K-contiguous operands, even K, K maps flat or of even extent >= 16,
+// even element strides and 16-byte aligned bases (every 2-complex chunk is one aligned 16-byte copy).
+static bool even_map(const IdxMap& m) { return m.s_in % 2 == 0 && (m.ext == kFlat || m.s_out % 2 == 0); }
+static bool even_batch(const BatchMap& b) { return b.s_lo % 2 == 0 && b.s_hi % 2 == 0; }
+static bool dma_ok(const ZGemm& g) {
+  if (g.big < 5 || g.big > 6) return false;
+  if (g.A.etype != kCB16 || g.B.etype != kCB16 || g.A.conj || g.B.conj) return false;
+  if (g.A.c.s_in != 1 || g.B.r.s_in != 1 || g.K % 2 != 0) return false;
+  for (const IdxMap* m : {&g.A.c, &g.B.r})
+    if (m->ext != kFlat && (m->ext % 2 != 0 || m->ext < 16 || m->s_out % 2 != 0)) return false;
+  if (!even_map(g.A.r) || !even_map(g.B.c) || !even_batch(g.A.b) || !even_batch(g.B.b)) return false;
+  return ((uintptr_t)g.A.p % 16 == 0) && ((uintptr_t)g.B.p % 16 == 0);
+}
+
+// LDS-DMA tiles by g.big: 5 = 320 x 64, 6 = 192 x 128.
+static void dma_tile(int big, int* fm, int* fn) {
+  static const int t[2][2] = {{5, 2}, {3, 4}};
+  *fm = t[big - 5][0];
+  *fn = t[big - 5][1];
+}
+
 // Kernel variant of a descriptor: family (0: FP64, 1: FP32, 2: split BF16 64-wide tiles, 3: split BF16
-// large tiles) and tile parameters.  g.shape (1..4) forces a 32/64-wide tile of the 256-thread kernels,
+// large tiles, 4: split BF16 large tiles fed by LDS DMA) and tile parameters.  g.shape (1..4) forces a 32/64-wide tile of the 256-thread kernels,
 // 0 picks 32 along a dimension of at most 32, else 64.
 Variant zgemm_variant(const ZGemm& g) {
   Variant v{};
-  if (g.prec == 2 && big_ok(g)) {
+  if (g.prec == 2 && dma_ok(g)) {
+    v.family = 4;
+    dma_tile(g.big, &v.p1, &v.p2);
+    v.bnc = false;
+    v.threads = 512;
+    v.bm = 64 * v.p1;
+    v.bn = 32 * v.p2;
+    return v;
+  }
+  // an LDS-DMA tile the operands do not allow falls back to the 192 x 96 register-staged tile
+  ZGemm gb = g;
+  if (gb.big >= 5) gb.big = 1;
+  if (g.prec == 2 && big_ok(gb)) {
     v.family = 3;
-    v.p1 = 3;
-    v.p2 = g.big == 1 ? 3 : 2;
+    big_tile(gb.big, &v.p1, &v.p2);
     v.bnc = g.B.c.s_in == 1 && g.B.c.ext >= 16;
     v.threads = 512;
     v.bm = 64 * v.p1;
@@ -1184,6 +1482,17 @@ void launch_bt(const ZGemm& g, dim3 grid, hipStream_t s) {
   }
 }
 
+template <int FM, int FN>
+void launch_bd(const ZGemm& g, dim3 grid, hipStream_t s) {
+  switch (g.site) {
+    case Site::P0_VG: zgemm_bd_kernel<FM, FN, Site::P0_VG><<<grid, dim3(512), 0, s>>>(g); break;
+    case Site::P0_VGrev: zgemm_bd_kernel<FM, FN, Site::P0_VGrev><<<grid, dim3(512), 0, s>>>(g); break;
+    case Site::P0_Contract: zgemm_bd_kernel<FM, FN, Site::P0_Contract><<<grid, dim3(512), 0, s>>>(g); break;
+    case Site::Sig_PV: zgemm_bd_kernel<FM, FN, Site::Sig_PV><<<grid, dim3(512), 0, s>>>(g); break;
+    default: zgemm_bd_kernel<FM, FN, Site::Generic><<<grid, dim3(512), 0, s>>>(g); break;
+  }
+}
+
 void launch_single(const Variant& v, const ZGemm& g, dim3 grid, hipStream_t s) {
   const int sh = (v.p1 - 1) * 2 + (v.p2 - 1);
   switch (v.family) {
@@ -1205,8 +1514,14 @@ void launch_single(const Variant& v, const ZGemm& g, dim3 grid, hipStream_t s) {
       else if (sh == 2) launch_mx<2, 2, 1>(g, grid, s);
       else launch_mx<2, 2, 2>(g, grid, s);
       break;
+    case 4:
+      if (v.p1 == 5) launch_bd<5, 2>(g, grid, s);
+      else launch_bd<3, 4>(g, grid, s);
+      break;
     default:
-      if (v.p2 == 3) {
+      if (v.p1 == 5) launch_bt<5, 2, false>(g, grid, s);
+      else if (v.p1 == 7) launch_bt<7, 2, false>(g, grid, s);
+      else if (v.p2 == 3) {
         if (v.bnc) launch_bt<3, 3, true>(g, grid, s);
         else launch_bt<3, 3, false>(g, grid, s);
       } else {
@@ -1239,8 +1554,14 @@ void launch_group(const Variant& v, const GroupArgs& a, dim3 grid, hipStream_t s
       else if (sh == 2) zgemm_mx_group<2, 2, 1><<<grid, b256, 0, s>>>(a);
       else zgemm_mx_group<2, 2, 2><<<grid, b256, 0, s>>>(a);
       break;
+    case 4:
+      if (v.p1 == 5) zgemm_bd_group<5, 2><<<grid, b512, 0, s>>>(a);
+      else zgemm_bd_group<3, 4><<<grid, b512, 0, s>>>(a);
+      break;
     default:
-      if (v.p2 == 3) {
+      if (v.p1 == 5) zgemm_bt_group<5, 2, false><<<grid, b512, 0, s>>>(a);
+      else if (v.p1 == 7) zgemm_bt_group<7, 2, false><<<grid, b512, 0, s>>>(a);
+      else if (v.p2 == 3) {
         if (v.bnc) zgemm_bt_group<3, 3, true><<<grid, b512, 0, s>>>(a);
         else zgemm_bt_group<3, 3, false><<<grid, b512, 0, s>>>(a);
       } else {
@@ -1308,6 +1629,16 @@ hipError_t convert_c64_t(const double2* in, void* out, int32_t etype, int n, int
   int64_t nb = (tot + 255) / 256;
   if (nb > 65536) nb = 65536;
   k_convert_c64_t<<<dim3((unsigned)nb), dim3(256), 0, s>>>(in, out, etype, n, batch);
+  return hipGetLastError();
+}
+
+hipError_t convert_c64_tr(const double2* in, void* out, int32_t etype, int rows, int cols, int batch, hipStream_t s) {
+  if (rows <= 0 || cols <= 0 || batch <= 0) return hipSuccess;
+  if (etype != kC32 && etype != kCB16) return hipErrorInvalidValue;
+  if (batch > 65535 || (rows + 31) / 32 > 65535) return hipErrorInvalidValue;
+  if (dryrun()) return hipSuccess;
+  k_convert_c64_tr<<<dim3((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32), (unsigned)batch), dim3(256), 0,
+                     s>>>(in, out, etype, rows, cols);
   return hipGetLastError();
 }
 

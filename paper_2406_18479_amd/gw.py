@@ -79,8 +79,10 @@ class Plan:
         return (self.nk, self.nao, self.nao)
 
     def set_option(self, option: str, value: int) -> None:
-        """option "tune" (0, 1, 2) or "graph" (0, 1); see green_plan_set_option."""
-        code = {"tune": _lib.OPT_TUNE, "graph": _lib.OPT_GRAPH}[option]
+        """option "tune" (0, 1, 2), "graph" (0, 1), "p0_tile" (1..4) or "stage1_tile" (0..2);
+        see green_plan_set_option."""
+        code = {"tune": _lib.OPT_TUNE, "graph": _lib.OPT_GRAPH, "p0_tile": _lib.OPT_P0_TILE,
+                "stage1_tile": _lib.OPT_STAGE1_TILE}[option]
         _lib.check(_lib.LIB.green_plan_set_option(self._h, code, int(value)), "green_plan_set_option")
 
     def tuning_report(self) -> str:

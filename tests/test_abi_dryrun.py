@@ -114,6 +114,13 @@ def test_plan_options_and_tuning_report(lib):
         assert L.green_plan_set_option(h, lib.OPT_TUNE, 3) == -1
         assert L.green_plan_set_option(h, lib.OPT_GRAPH, 1) == 0
         assert L.green_plan_set_option(h, lib.OPT_GRAPH, 2) == -1
+        for v in (1, 2, 3, 4, 5, 6):
+            assert L.green_plan_set_option(h, lib.OPT_P0_TILE, v) == 0
+        assert L.green_plan_set_option(h, lib.OPT_P0_TILE, 0) == -1
+        assert L.green_plan_set_option(h, lib.OPT_P0_TILE, 7) == -1
+        for v in (0, 1, 2):
+            assert L.green_plan_set_option(h, lib.OPT_STAGE1_TILE, v) == 0
+        assert L.green_plan_set_option(h, lib.OPT_STAGE1_TILE, 3) == -1
         assert L.green_plan_set_option(h, 99, 0) == -1
         buf = ctypes.create_string_buffer(4096)
         assert L.green_plan_tuning_report(h, buf, len(buf)) == 0

@@ -107,30 +107,40 @@ def test_graph_replay_equals_eager(prec):
 
 @pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
 def test_autotuner_settles_and_keeps_results(prec):
-    """Tuning tries every candidate of every shape once, keeps the fastest, and the tuned plan computes
-    the same iteration as the default plan up to summation order."""
+    """Tuning tries every candidate of every shape once, keeps the fastest, and every candidate computes
+    the same contraction: each tuning iteration (a mix of trial kernels: tile shapes, split-K counts,
+    tile-row bands) and the tuned plan give the default plan's iteration up to summation order."""
+    import re
     _require_gpu()
     s = systems.make_system(configs.tiny(kmesh=(2, 2, 1), nao=26, naux=120, ntau=20, beta=30.0, seed=421))
     p0, p1 = plan(s, prec), plan(s, prec)
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    ya = state(s, p0)
+    ra = iterate(p0, ya)
+    Sa = host(ya["Sigma"])
+
+    def same(y, r):
+        assert np.max(np.abs(host(y["Sigma"]) - Sa)) <= tol * np.max(np.abs(Sa))
+        assert abs(r["e_tot"] - ra["e_tot"]) <= (1e-11 if prec == "fp64" else 1e-7)
+
     p1.set_option("tune", 1)
-    y = state(s, p1)
     for it in range(40):
-        iterate(p1, y)
+        y = state(s, p1)
+        same(y, iterate(p1, y))
         rep = p1.tuning_report()
         if rep and "tuning" not in rep:
             break
     print("[gpu-case] tuned after", it + 1, "iterations\n" + rep, flush=True)
     assert rep and "tuning" not in rep
+    assert "band=" in rep
+    if prec == "bf16x3":  # the large-tile candidates include tile-row bands
+        assert re.search(r" \d+/\d+/\d+/4=", rep)
     for line in rep.strip().splitlines():
-        best = float(line.split("ksplit=")[1].split()[1])
-        default = float(line.split("(default ")[1].split()[0])
-        assert best <= default
-    ya, yb = state(s, p0), state(s, p1)
-    ra, rb = iterate(p0, ya), iterate(p1, yb)
-    Sa, Sb = host(ya["Sigma"]), host(yb["Sigma"])
-    tol = 1e-12 if prec == "fp64" else 1e-6
-    assert np.max(np.abs(Sa - Sb)) <= tol * np.max(np.abs(Sa))
-    assert abs(ra["e_tot"] - rb["e_tot"]) <= (1e-11 if prec == "fp64" else 1e-7)
+        m = re.search(r"band=\d+ ([0-9.]+) us \(default ([0-9.]+) us\)", line)
+        if m:
+            assert float(m.group(1)) <= float(m.group(2))
+    yb = state(s, p1)
+    same(yb, iterate(p1, yb))
 
 
 @pytest.mark.parametrize("prec", ["fp64", "bf16x3"])

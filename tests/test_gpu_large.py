@@ -54,6 +54,24 @@ def test_polarization_sampled_tau(periodic3):
     assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("tile", [3, 4])
+def test_polarization_tall_tiles_sampled_tau(periodic3, tile):
+    """Split-BF16 P~0 with the 320- and 448-row output tiles at full size, sampled tau nodes against the
+    oracle (same relative bound as the other split-BF16 contractions)."""
+    s = periodic3
+    sp = s.spec
+    say("polarization 3x3x3 bf16x3 p0_tile", tile)
+    p = _plan(s, "bf16x3")
+    p.set_option("p0_tile", tile)
+    P = p.polarization(s.V_dev, torch.from_numpy(s.G0).to("cuda:0"))
+    ts = [1, 70]
+    got = P[:, ts].cpu().numpy()
+    del P, p
+    torch.cuda.empty_cache()
+    ref = ogw.polarization(s.V, s.G0, sp.kmesh, ts=ts)
+    assert np.max(np.abs(got - ref)) <= 4e-5 * np.max(np.abs(ref))
+
+
 def test_selfenergy_sampled_k_tau(periodic3):
     from synth import device
     s = periodic3

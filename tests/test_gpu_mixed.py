@@ -67,6 +67,24 @@ def test_mixed_polarization_and_selfenergy(c, prec):
     assert rel(Smx, S64) <= REL[prec]
 
 
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6])
+def test_split_bf16_p0_tiles(tile):
+    """Every output tile of the split-BF16 P~0 contraction (register-staged 192 x 96, 192 x 64, 320 x 64,
+    448 x 64; LDS-DMA 320 x 64, 192 x 128) on an naux that leaves ragged tiles along both P~0 dimensions
+    and a K (= nk nao^2 = 200) whose orbital-pair blocks (100) and end fall inside 16-wide K stages, against
+    the FP64 path."""
+    _require_gpu()
+    s = systems.make_system(configs.tiny(kmesh=(2, 1, 1), nao=10, naux=350, ntau=6, beta=8.0, seed=204,
+                                         v_scale=0.5 / 10 ** 0.5))
+    print("[gpu-case] split-BF16 P0 tile", tile, flush=True)
+    V, G = dev(s.V), dev(s.G0)
+    p64, pmx = plan(s, "fp64"), plan(s, "bf16x3")
+    pmx.set_option("p0_tile", tile)
+    P64 = host(p64.polarization(V, G))
+    Pmx = host(pmx.polarization(V, G))
+    assert rel(Pmx, P64) <= REL["bf16x3"]
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_mixed_iteration_periodic_2x2x2(prec):
     """One iteration of the 2x2x2 workload from identical inputs: |dE| <= 1e-6 Eh, max|dSigma| <= 1e-5 Eh."""
