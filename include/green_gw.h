@@ -231,11 +231,16 @@ int green_gw_iterate_diis(green_plan* plan, const void* V, const void* H0, const
  *   GREEN_OPT_STAGE1_TILE  split-BF16 plans: tile of the V G products that feed it: 0 = 64 x 64,
  *                   1 = 192 x 96 (default), 2 = 192 x 64.
  *                   Both only change the summation blocking; results agree to rounding.
+ *   GREEN_OPT_SIGMA_FUSED  split-BF16 plans with an even nao <= 64: 1 (default) runs the two contractions
+ *                   of Eq. tilde_Sigma_tau after P~^T V (over the orbital a with G(tau), then over (Q', b)
+ *                   with V) in one kernel that keeps their intermediate in registers; 0 runs them as two
+ *                   contractions through HBM.  GREEN_EINVAL where the plan does not allow 1.
  * Returns GREEN_EINVAL for an unknown option or value. */
 #define GREEN_OPT_TUNE 1
 #define GREEN_OPT_GRAPH 2
 #define GREEN_OPT_P0_TILE 3
 #define GREEN_OPT_STAGE1_TILE 4
+#define GREEN_OPT_SIGMA_FUSED 5
 int green_plan_set_option(green_plan* plan, int option, int value);
 
 /* Text table of the autotuner's decisions into buf (host, len bytes, NUL-terminated; GREEN_ENOMEM when

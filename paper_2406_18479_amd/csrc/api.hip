@@ -59,13 +59,14 @@ struct green_plan {
   int big_p0 = 1;      // split-BF16 P~0 stage-2 kernel: 1 = 192 x 96 tiles, 2 = 192 x 64, 3 = 320 x 64, 4 = 448 x 64,
                        // LDS-DMA 5 = 320 x 64, 6 = 192 x 128
                        // (set at plan creation from naux)
+  bool fuse_sig = false;  // split-BF16 plans, nao even and <= 64: Sigma~ stages 2 and 3 in one kernel
   std::vector<double> tau, wf, wb;
   std::vector<double2> TF_t2w, TF_w2t, TB_t2w, TB_w2t, Emass;
   std::vector<int32_t> kadd, ksub, kneg;  // [q][k]: k+q, k-q; [q]: -q
   std::vector<int32_t> qcan;              // momenta q with -q >= q (one of each +-q pair)
   // workspace regions
   Region r_TF_t2w, r_TF_w2t, r_TB_t2w, r_TB_w2t, r_Emass, r_wf, r_kadd, r_ksub, r_qcan, r_status, r_scal, r_partial;
-  Region r_P, r_Pw, r_T1, r_T2, r_gam, r_gamT, r_D, r_Sinfn, r_Sign, r_Sw, r_A, r_tr, r_split, r_Vx, r_Ptx, r_Gx;
+  Region r_P, r_Pw, r_T1, r_T2, r_gam, r_gamT, r_D, r_Sinfn, r_Sign, r_Sw, r_A, r_tr, r_split, r_Vx, r_Ptx, r_Gx, r_GTx;
   size_t ws_bytes = 0;
   void* bound_ws = nullptr;
   hipEvent_t ev[kNumEvents]{};
@@ -647,6 +648,8 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
   const int stage = p->prec == GREEN_FP64 ? 0 : (bf ? 2 : 1);
   // split-BF16 plans with an even naux run stage 1 on the LDS-DMA kernel (K-contiguous V slab)
   const bool vt_dma = bf && naux % 2 == 0;
+  // ... and with an even nao <= 64, stages 2 and 3 in one kernel on G^T and per-block transposed V slabs
+  const bool fused = bf && p->fuse_sig;
   void* Vx = at<void>(ws, p->r_Vx);
   const green::Span sVx = span_ws(ws, p->r_Vx);
   void* Ptx = at<void>(ws, p->r_Ptx);
@@ -658,6 +661,10 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
     GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64(static_cast<const double2*>(G), at<void>(ws, p->r_Gx), green::kCB16, ex.G, st_); }));
     Gs = at<void>(ws, p->r_Gx);
     sGs = span_ws(ws, p->r_Gx);
+  }
+  if (fused) {
+    if ((int64_t)p->r_GTx.bytes < ex.G * 8) return GREEN_EINVAL;
+    GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64_tr(static_cast<const double2*>(G), at<void>(ws, p->r_GTx), green::kCB16, nao, nao, ns * ntau * nk, st_); }));
   }
   for (int q = 0; q < nk; ++q) {
     const int qn = p->kneg[q];
@@ -676,8 +683,13 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
       sVa = sVx;
       if (bf) {
         const bool own = q != qn || vt_dma;  // stage 3 needs its own (untransposed) slab
-        if (own) GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64(static_cast<const double2*>(Vq), eptr(Vx, vt, slab), vt, slab, st_); }));
-        Vq = own ? eptr(Vx, vt, slab) : Vx;
+        if (fused) {
+          // V^{k-q,k}_{bj}(Q') stored [k][Q'][j][b] for the fused stages 2 and 3
+          GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64_tr(static_cast<const double2*>(Vq), eptr(Vx, vt, slab), vt, nao, nao, nk * naux, st_); }));
+        } else if (own) {
+          GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64(static_cast<const double2*>(Vq), eptr(Vx, vt, slab), vt, slab, st_); }));
+        }
+        Vq = own || fused ? eptr(Vx, vt, slab) : Vx;
         sVb = sVx;
       }
     }
@@ -698,7 +710,52 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
                             : op(Vqn, flat(nG), two((int32_t)nG, 1, nV), bnone(), mixed ? vt : green::kC64),
                      sVa, T1, sT1, two(naux, nG, (int64_t)nk * nV), two((int32_t)nG, 1, nV), bnone(), tcn * naux,
                      (int)(nk * nG), naux, 1, cplx(1), cplx(0), s, p->prec, xt, bf ? (vt_dma ? 6 : 1) : 0));
-      for (int sp = 0; sp < ns; ++sp) {
+      for (int sp = 0; sp < ns && fused; ++sp) {
+        // Sigma[s][t][k][i][j] += -(1/nk) sum_{Q',b} (sum_a X[tt][k][Q'][i][a] G^{k-q}_{ab}(tau)) V^{k-q,k}_{bj}(Q'):
+        // Q' slices of FP64 partial sums, added in slice order
+        const int64_t blocks = (int64_t)tcn * nk;
+        int qs = (int)std::min<int64_t>(16, std::max<int64_t>(1, (2560 + blocks - 1) / blocks));
+        qs = std::min(qs, naux);
+        while (qs > 1 && (int64_t)qs * nk * nG * tcn > tl_split.cap) --qs;
+        if ((int64_t)qs * nk * nG * tcn > tl_split.cap) return GREEN_EINVAL;
+        // every element the kernel reads lies inside its region
+        if ((int64_t)tcn * nk * nV * 8 > (int64_t)p->r_T1.bytes || (int64_t)p->r_Vx.bytes < 2 * slab * 8 ||
+            ((int64_t)sp * ntau + t0 + tcn) * nk * nG * 8 > (int64_t)p->r_GTx.bytes)
+          return GREEN_EINVAL;
+        green::XgvArgs xa{};
+        xa.X = static_cast<const uint2*>(static_cast<const void*>(T1));
+        xa.GT = static_cast<const uint2*>(at<void>(ws, p->r_GTx)) + ((int64_t)sp * ntau + t0) * nk * nG;
+        xa.VT = static_cast<const uint2*>(Vq);
+        xa.kk = ksub + q * nk;
+        xa.partial = tl_split.ptr;
+        xa.nao = nao;
+        xa.naux = naux;
+        xa.nk = nk;
+        xa.tcn = tcn;
+        xa.qsplit = qs;
+        xa.x_tt = (int64_t)nk * nV;
+        xa.x_k = nV;
+        xa.g_tt = (int64_t)nk * nG;
+        // the split-K pass: rows j, columns (tt, i), batch k; Sigma[s][t0 + tt][k][i][j]
+        ZGemm rd{};
+        rd.site = green::Site::Sig_YV;
+        rd.M = nao;
+        rd.N = tcn * nao;
+        rd.K = naux;
+        rd.batch = nk;
+        rd.C = Sp + ((int64_t)sp * ntau + t0) * nk * nG;
+        rd.cr = flat(1);
+        rd.cc = two(nao, nao, (int64_t)nk * nG);
+        rd.cb = bflat(nG);
+        rd.alpha = cplx(-1.0 / nk);
+        rd.beta = cplx(1.0);
+        rd.ksplit = qs;
+        rd.partial = tl_split.ptr;
+        rd.prec = 2;
+        rd.ctype = green::kC64;
+        GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::sigma_xgv(xa, rd, st_); }));
+      }
+      for (int sp = 0; sp < ns && !fused; ++sp) {
         // Y[tt][k][(Q',i)][b] = sum_a X[tt][k][(Q',i)][a] G^{k-q}_{ab}(tau)
         GREEN_TRY(gemm(green::Site::Sig_XG, "Sigma.XG", op(T1, flat(nao), flat(1), bflat(nV), xt), sT1,
                        op(eptr(Gs, gt, ((int64_t)sp * ntau + t0) * nk * nG), flat(nao), flat(1),
@@ -1281,6 +1338,8 @@ int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, 
   take(p->r_Vx, prec == GREEN_FP64 ? 0 : (size_t)(prec == GREEN_BF16X3 ? 2 : 1) * nk * nV * 8);
   take(p->r_Gx, prec == GREEN_BF16X3 ? (size_t)ns * ntau * nk * nG * 8 : 0);
   take(p->r_Ptx, prec == GREEN_BF16X3 ? (size_t)ntau * nP * 8 : 0);
+  p->fuse_sig = prec == GREEN_BF16X3 && nao % 2 == 0 && nao <= 64;
+  take(p->r_GTx, p->fuse_sig ? (size_t)ns * ntau * nk * nG * 8 : 0);
   p->ws_bytes = off;
   if (count_ops(p) != GREEN_OK) {
     delete p;
@@ -1542,6 +1601,12 @@ int green_plan_set_option(green_plan* p, int option, int value) {
     case GREEN_OPT_STAGE1_TILE:
       if (value < 0 || value > 2) return GREEN_EINVAL;
       p->big_stage1 = value;
+      drop_graph(p);
+      return GREEN_OK;
+    case GREEN_OPT_SIGMA_FUSED:
+      if (value < 0 || value > 1) return GREEN_EINVAL;
+      if (value && (p->prec != GREEN_BF16X3 || p->d.nao % 2 != 0 || p->d.nao > 64)) return GREEN_EINVAL;
+      p->fuse_sig = value != 0;
       drop_graph(p);
       return GREEN_OK;
     default:

@@ -1089,6 +1089,209 @@ __device__ __forceinline__ void bd_body(const ZGemm& g, int64_t bid0, int64_t nb
   large_tile_store<FM, FN>(g, acc_re, acc_im, batch, slice, m0 + rowb, n0 + colb, lane);
 }
 
+// Sigma~ stages 2 and 3 fused (split BF16).  For each (tt, k) of one tau chunk (one q, one spin):
+//   S^T[j][i] = sum_{Q'} sum_b VT[k][Q'][j][b] Y^T[b][i],   Y^T[b][i] = sum_a GT[tt][k][b][a] X[tt][k][Q'][i][a]
+// (Y = X G, S = Y V).  Y never leaves the registers: the 16 x 16 FP32 accumulator tile of Y^T that a lane
+// holds (rows b = 4 (l >> 4) + r, column i = l & 15) is exactly its B operand of the second product (four
+// consecutive K = b of column i), so it is split to BF16 hi + lo in place.  A workgroup owns (tt, k, slice of
+// Q'); wave w owns the columns i in [16 w, 16 w + 16).  G^T and the V^T block of the current Q' sit in LDS
+// (rows padded to 16 NB with zeros), the next Q' block is loaded into registers while the current one is
+// contracted.  Slices write FP64 partial sums [slice][k][j][tt][i] that the split-K pass adds in order.
+template <int NB>
+__device__ __forceinline__ int xgv_word(int r, int c) {
+  constexpr int CH = 8 * NB;  // 16-byte chunks per row (16 NB complex)
+  constexpr int F = CH < 16 ? CH - 1 : 15;
+  return (r * CH + (c ^ (r & F))) * 4;
+}
+
+template <int NB>
+__global__ __launch_bounds__(64 * NB) void sigma_xgv_kernel(const XgvArgs a) {
+  constexpr int R = 16 * NB;       // padded rows and K of each block
+  constexpr int NT = 64 * NB;      // threads
+  constexpr int VPT = (R * R / 2 + NT - 1) / NT;  // 16-byte chunks of a V^T block per thread
+  __shared__ __attribute__((aligned(16))) uint32_t Gs[R * R * 2];
+  __shared__ __attribute__((aligned(16))) uint32_t Vs0[R * R * 2];
+  __shared__ __attribute__((aligned(16))) uint32_t Vs1[R * R * 2];
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int g4 = lane >> 4, r16 = lane & 15;
+  const int nao = a.nao, nch = nao / 2;  // nao even: a row of a block is nch 16-byte chunks
+  const int64_t nG = (int64_t)nao * nao, nV = (int64_t)a.naux * nG;
+  const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
+  const int tt = (int)(bid % a.tcn);
+  const int64_t rest = bid / a.tcn;
+  const int sl = (int)(rest % a.qsplit);
+  const int k = (int)(rest / a.qsplit);
+  const int kk = a.kk[k];
+  const int qc = (a.naux + a.qsplit - 1) / a.qsplit;
+  const int q0 = min(a.naux, sl * qc), q1 = min(a.naux, q0 + qc);
+
+  for (int x = tid; x < R * R / 2; x += NT) {
+    reinterpret_cast<u4*>(Gs)[x] = u4{0u, 0u, 0u, 0u};
+    reinterpret_cast<u4*>(Vs0)[x] = u4{0u, 0u, 0u, 0u};
+    reinterpret_cast<u4*>(Vs1)[x] = u4{0u, 0u, 0u, 0u};
+  }
+  __syncthreads();
+  {
+    const u4* src = reinterpret_cast<const u4*>(a.GT + tt * a.g_tt + (int64_t)kk * nG);
+    for (int x = tid; x < nao * nch; x += NT) {
+      const int r = x / nch, c = x - (x / nch) * nch;
+      *reinterpret_cast<u4*>(&Gs[xgv_word<NB>(r, c)]) = src[x];
+    }
+  }
+  // V^T block of one Q' (rows j, K = b) through registers
+  u4 vr[VPT];
+  const uint2* vbase = a.VT + (int64_t)kk * nV;
+  auto vload = [&](int qp) {
+    const u4* src = reinterpret_cast<const u4*>(vbase + (int64_t)qp * nG);
+#pragma unroll
+    for (int e = 0; e < VPT; ++e) {
+      const int x = tid + e * NT;
+      vr[e] = src[min(x, nao * nch - 1)];
+    }
+  };
+  auto vstore = [&](uint32_t* V) {
+#pragma unroll
+    for (int e = 0; e < VPT; ++e) {
+      const int x = tid + e * NT;
+      if (x < nao * nch) {
+        const int r = x / nch, c = x - (x / nch) * nch;
+        *reinterpret_cast<u4*>(&V[xgv_word<NB>(r, c)]) = vr[e];
+      }
+    }
+  };
+  // B operand of the first product: X^T (K = a, column i = 16 w + r16): complex a = 16 ab + 4 g4 .. + 3 of
+  // row i, as two 16-byte chunks; a >= nao reads 0 (i >= nao reads row nao - 1: its results are not stored)
+  const int icl = min(16 * w + r16, nao - 1);
+  u4 xr[NB][2], xn[NB][2];
+  auto xload = [&](int qp, u4 (&xv)[NB][2]) {
+    const uint2* row = a.X + tt * a.x_tt + (int64_t)k * a.x_k + (int64_t)qp * nG + (int64_t)icl * nao;
+#pragma unroll
+    for (int ab = 0; ab < NB; ++ab)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int a0 = 16 * ab + 4 * g4 + 2 * h;
+        const u4 v = *reinterpret_cast<const u4*>(row + (a0 < nao ? a0 : 0));
+        xv[ab][h] = a0 < nao ? v : u4{0u, 0u, 0u, 0u};
+      }
+  };
+  // A operand fragment: row r, K block kb (complex 16 kb + 4 g4 .. + 3) as hi and lo words
+  auto frag = [&](const uint32_t* P, int r, int kb, u4& hi, u4& lo) {
+    const u4 x = *reinterpret_cast<const u4*>(&P[xgv_word<NB>(r, 8 * kb + 2 * g4)]);
+    const u4 y = *reinterpret_cast<const u4*>(&P[xgv_word<NB>(r, 8 * kb + 2 * g4 + 1)]);
+    hi = u4{x.x, x.z, y.x, y.z};
+    lo = u4{x.y, x.w, y.y, y.w};
+  };
+  f4 s_re[NB], s_im[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    s_re[j] = f4{0.f, 0.f, 0.f, 0.f};
+    s_im[j] = f4{0.f, 0.f, 0.f, 0.f};
+  }
+  // one Q': Y^T = G^T X^T, then S^T += V^T Y^T (B operands conjugated (re, -im) for the real part and swapped
+  // (im, re) for the imaginary part, three split products each)
+  auto contract = [&](const uint32_t* V) {
+    f4 y_re[NB], y_im[NB];
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb) {
+      y_re[bb] = f4{0.f, 0.f, 0.f, 0.f};
+      y_im[bb] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int ab = 0; ab < NB; ++ab) {
+      const u4 bh = u4{xr[ab][0].x, xr[ab][0].z, xr[ab][1].x, xr[ab][1].z};
+      const u4 bl = u4{xr[ab][0].y, xr[ab][0].w, xr[ab][1].y, xr[ab][1].w};
+      const bf8 bch = as_bf8(neg_im(bh)), bcl = as_bf8(neg_im(bl));
+      const bf8 bsh = as_bf8(swap_re_im(bh)), bsl = as_bf8(swap_re_im(bl));
+#pragma unroll
+      for (int bb = 0; bb < NB; ++bb) {
+        u4 ah, al;
+        frag(Gs, 16 * bb + r16, ab, ah, al);
+        const bf8 xh = as_bf8(ah), xl = as_bf8(al);
+        y_re[bb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, bch, y_re[bb], 0, 0, 0);
+        y_im[bb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, bsh, y_im[bb], 0, 0, 0);
+        y_re[bb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, bcl, y_re[bb], 0, 0, 0);
+        y_im[bb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, bsl, y_im[bb], 0, 0, 0);
+        y_re[bb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, bch, y_re[bb], 0, 0, 0);
+        y_im[bb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, bsh, y_im[bb], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb) {
+      uint32_t h0, h1, h2, h3, l0, l1, l2, l3;
+      split_pair_f(y_re[bb][0], y_im[bb][0], h0, l0);
+      split_pair_f(y_re[bb][1], y_im[bb][1], h1, l1);
+      split_pair_f(y_re[bb][2], y_im[bb][2], h2, l2);
+      split_pair_f(y_re[bb][3], y_im[bb][3], h3, l3);
+      const u4 yh = u4{h0, h1, h2, h3}, yl = u4{l0, l1, l2, l3};
+      const bf8 ych = as_bf8(neg_im(yh)), ycl = as_bf8(neg_im(yl));
+      const bf8 ysh = as_bf8(swap_re_im(yh)), ysl = as_bf8(swap_re_im(yl));
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb) {
+        u4 ah, al;
+        frag(V, 16 * jb + r16, bb, ah, al);
+        const bf8 vh = as_bf8(ah), vl = as_bf8(al);
+        s_re[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vh, ych, s_re[jb], 0, 0, 0);
+        s_im[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vh, ysh, s_im[jb], 0, 0, 0);
+        s_re[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vh, ycl, s_re[jb], 0, 0, 0);
+        s_im[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vh, ysl, s_im[jb], 0, 0, 0);
+        s_re[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vl, ych, s_re[jb], 0, 0, 0);
+        s_im[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vl, ysh, s_im[jb], 0, 0, 0);
+      }
+    }
+  };
+  if (q0 < q1) {
+    vload(q0);
+    xload(q0, xr);
+    vstore(Vs0);
+    __syncthreads();
+    for (int qp = q0; qp < q1; qp += 2) {
+      // even step: V^T in Vs0, the next block goes to Vs1 (last read before the previous barrier)
+      const bool n1 = qp + 1 < q1;
+      if (n1) {
+        vload(qp + 1);
+        xload(qp + 1, xn);
+      }
+      contract(Vs0);
+      if (n1) vstore(Vs1);
+      __syncthreads();
+      if (!n1) break;
+#pragma unroll
+      for (int ab = 0; ab < NB; ++ab) {
+        xr[ab][0] = xn[ab][0];
+        xr[ab][1] = xn[ab][1];
+      }
+      // odd step: V^T in Vs1, the next block goes to Vs0
+      const bool n2 = qp + 2 < q1;
+      if (n2) {
+        vload(qp + 2);
+        xload(qp + 2, xn);
+      }
+      contract(Vs1);
+      if (n2) vstore(Vs0);
+      __syncthreads();
+#pragma unroll
+      for (int ab = 0; ab < NB; ++ab) {
+        xr[ab][0] = xn[ab][0];
+        xr[ab][1] = xn[ab][1];
+      }
+    }
+  }
+  // S^T[j = 16 jb + 4 g4 + r][i = 16 w + r16] -> partial[((sl nk + k) nao + j) (tcn nao) + tt nao + i]
+  const int i = 16 * w + r16;
+  if (i < nao) {
+    const int64_t ncol = (int64_t)a.tcn * nao;
+    double2* P = a.partial + ((int64_t)sl * a.nk + k) * nao * ncol + (int64_t)tt * nao + i;
+#pragma unroll
+    for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = 16 * jb + 4 * g4 + r;
+        if (j < nao) P[(int64_t)j * ncol] = make_double2((double)s_re[jb][r], (double)s_im[jb][r]);
+      }
+  }
+}
+
 // Second pass of split-K: C = alpha * sum_slices partial + beta * C, slices added in order.
 __device__ __forceinline__ void splitk_body(const ZGemm& g, int64_t x0, int64_t stride) {
   const int64_t mn = (int64_t)g.M * g.N;
@@ -1629,6 +1832,22 @@ hipError_t convert_c64_t(const double2* in, void* out, int32_t etype, int n, int
   int64_t nb = (tot + 255) / 256;
   if (nb > 65536) nb = 65536;
   k_convert_c64_t<<<dim3((unsigned)nb), dim3(256), 0, s>>>(in, out, etype, n, batch);
+  return hipGetLastError();
+}
+
+hipError_t sigma_xgv(const XgvArgs& a, const ZGemm& reduce, hipStream_t s) {
+  if (a.tcn <= 0 || a.nk <= 0 || a.naux <= 0) return hipSuccess;
+  if (a.nao <= 0 || a.nao > 64 || a.nao % 2 != 0 || a.qsplit < 1 || reduce.ksplit != a.qsplit || !a.partial)
+    return hipErrorInvalidValue;
+  if (dryrun()) return hipSuccess;
+  const dim3 grid((unsigned)((int64_t)a.tcn * a.nk * a.qsplit));
+  if (a.nao <= 16) sigma_xgv_kernel<1><<<grid, dim3(64), 0, s>>>(a);
+  else if (a.nao <= 32) sigma_xgv_kernel<2><<<grid, dim3(128), 0, s>>>(a);
+  else sigma_xgv_kernel<4><<<grid, dim3(256), 0, s>>>(a);
+  const int64_t total = (int64_t)reduce.M * reduce.N * reduce.batch;
+  int64_t nb = (total + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  zgemm_splitk_reduce<<<dim3((unsigned)nb), dim3(256), 0, s>>>(reduce);
   return hipGetLastError();
 }
 

@@ -79,10 +79,10 @@ class Plan:
         return (self.nk, self.nao, self.nao)
 
     def set_option(self, option: str, value: int) -> None:
-        """option "tune" (0, 1, 2), "graph" (0, 1), "p0_tile" (1..4) or "stage1_tile" (0..2);
-        see green_plan_set_option."""
+        """option "tune" (0, 1, 2), "graph" (0, 1), "p0_tile" (1..6), "stage1_tile" (0..2) or
+        "sigma_fused" (0, 1); see green_plan_set_option."""
         code = {"tune": _lib.OPT_TUNE, "graph": _lib.OPT_GRAPH, "p0_tile": _lib.OPT_P0_TILE,
-                "stage1_tile": _lib.OPT_STAGE1_TILE}[option]
+                "stage1_tile": _lib.OPT_STAGE1_TILE, "sigma_fused": _lib.OPT_SIGMA_FUSED}[option]
         _lib.check(_lib.LIB.green_plan_set_option(self._h, code, int(value)), "green_plan_set_option")
 
     def tuning_report(self) -> str:

@@ -121,6 +121,8 @@ def test_plan_options_and_tuning_report(lib):
         for v in (0, 1, 2):
             assert L.green_plan_set_option(h, lib.OPT_STAGE1_TILE, v) == 0
         assert L.green_plan_set_option(h, lib.OPT_STAGE1_TILE, 3) == -1
+        assert L.green_plan_set_option(h, lib.OPT_SIGMA_FUSED, 0) == 0
+        assert L.green_plan_set_option(h, lib.OPT_SIGMA_FUSED, 2) == -1
         assert L.green_plan_set_option(h, 99, 0) == -1
         buf = ctypes.create_string_buffer(4096)
         assert L.green_plan_tuning_report(h, buf, len(buf)) == 0

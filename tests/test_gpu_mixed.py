@@ -85,6 +85,33 @@ def test_split_bf16_p0_tiles(tile):
     assert rel(Pmx, P64) <= REL["bf16x3"]
 
 
+FUSED = [dict(kmesh=(2, 1, 1), nao=6, naux=40, ntau=10, seed=205),     # one 16-row block
+         dict(kmesh=(3, 1, 1), nao=26, naux=90, ntau=8, seed=206),     # two blocks, padded
+         dict(kmesh=(2, 1, 1), nao=40, naux=75, ntau=6, seed=207),     # four blocks, the last one empty
+         dict(kmesh=(1, 1, 1), nao=64, naux=33, ntau=6, seed=208)]     # four full blocks, odd naux
+
+
+@pytest.mark.parametrize("c", FUSED, ids=lambda c: f"nao{c['nao']}_naux{c['naux']}")
+def test_sigma_fused_stages(c):
+    """Split-BF16 self-energy with stages 2 and 3 fused (intermediate in registers) against the same plan
+    with the two stages through HBM (same roundings of the intermediate, other summation order) and
+    against the FP64 path."""
+    _require_gpu()
+    s = systems.make_system(configs.tiny(kmesh=c["kmesh"], nao=c["nao"], naux=c["naux"], ntau=c["ntau"], beta=8.0,
+                                         seed=c["seed"], v_scale=0.5 / c["nao"] ** 0.5))
+    print("[gpu-case] fused sigma stages", c, flush=True)
+    V, G = dev(s.V), dev(s.G0)
+    Pt = dev(systems.random_polarization(9, s.spec.nk, s.spec.ntau, s.spec.naux, scale=0.1))
+    p64, pmx = plan(s, "fp64"), plan(s, "bf16x3")
+    S64 = host(p64.selfenergy(V, G, Pt))
+    pmx.set_option("sigma_fused", 1)
+    Sf = host(pmx.selfenergy(V, G, Pt))
+    pmx.set_option("sigma_fused", 0)
+    Su = host(pmx.selfenergy(V, G, Pt))
+    assert rel(Sf, Su) <= 1e-5
+    assert rel(Sf, S64) <= REL["bf16x3"]
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_mixed_iteration_periodic_2x2x2(prec):
     """One iteration of the 2x2x2 workload from identical inputs: |dE| <= 1e-6 Eh, max|dSigma| <= 1e-5 Eh."""
