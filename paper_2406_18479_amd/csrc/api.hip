@@ -59,7 +59,7 @@ struct green_plan {
   int big_p0 = 1;      // split-BF16 P~0 stage-2 kernel: 1 = 192 x 96 tiles, 2 = 192 x 64, 3 = 320 x 64, 4 = 448 x 64,
                        // LDS-DMA 5 = 320 x 64, 6 = 192 x 128
                        // (set at plan creation from naux)
-  bool fuse_sig = false;  // split-BF16 plans, nao even and <= 64: Sigma~ stages 2 and 3 in one kernel
+  bool fuse_sig = false;  // split-BF16 plans, nao % 4 == 0 and <= 64: Sigma~ stages 2 and 3 in one kernel
   std::vector<double> tau, wf, wb;
   std::vector<double2> TF_t2w, TF_w2t, TB_t2w, TB_w2t, Emass;
   std::vector<int32_t> kadd, ksub, kneg;  // [q][k]: k+q, k-q; [q]: -q
@@ -648,7 +648,8 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
   const int stage = p->prec == GREEN_FP64 ? 0 : (bf ? 2 : 1);
   // split-BF16 plans with an even naux run stage 1 on the LDS-DMA kernel (K-contiguous V slab)
   const bool vt_dma = bf && naux % 2 == 0;
-  // ... and with an even nao <= 64, stages 2 and 3 in one kernel on G^T and per-block transposed V slabs
+  // ... and with nao a multiple of 4 up to 64, stages 2 and 3 in one kernel on G^T and per-block transposed
+  // V slabs
   const bool fused = bf && p->fuse_sig;
   void* Vx = at<void>(ws, p->r_Vx);
   const green::Span sVx = span_ws(ws, p->r_Vx);
@@ -685,7 +686,7 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
         const bool own = q != qn || vt_dma;  // stage 3 needs its own (untransposed) slab
         if (fused) {
           // V^{k-q,k}_{bj}(Q') stored [k][Q'][j][b] for the fused stages 2 and 3
-          GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64_tr(static_cast<const double2*>(Vq), eptr(Vx, vt, slab), vt, nao, nao, nk * naux, st_); }));
+          GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64_tr(static_cast<const double2*>(Vq), eptr(Vx, vt, slab), vt, nao, nao, nk * naux, st_, true); }));
         } else if (own) {
           GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64(static_cast<const double2*>(Vq), eptr(Vx, vt, slab), vt, slab, st_); }));
         }
@@ -714,10 +715,11 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
         // Sigma[s][t][k][i][j] += -(1/nk) sum_{Q',b} (sum_a X[tt][k][Q'][i][a] G^{k-q}_{ab}(tau)) V^{k-q,k}_{bj}(Q'):
         // Q' slices of FP64 partial sums, added in slice order
         const int64_t blocks = (int64_t)tcn * nk;
+        const int hv = green::xgv_halves(nao);
         int qs = (int)std::min<int64_t>(16, std::max<int64_t>(1, (2560 + blocks - 1) / blocks));
         qs = std::min(qs, naux);
-        while (qs > 1 && (int64_t)qs * nk * nG * tcn > tl_split.cap) --qs;
-        if ((int64_t)qs * nk * nG * tcn > tl_split.cap) return GREEN_EINVAL;
+        while (qs > 1 && (int64_t)qs * hv * nk * nG * tcn > tl_split.cap) --qs;
+        if ((int64_t)qs * hv * nk * nG * tcn > tl_split.cap) return GREEN_EINVAL;
         // every element the kernel reads lies inside its region
         if ((int64_t)tcn * nk * nV * 8 > (int64_t)p->r_T1.bytes || (int64_t)p->r_Vx.bytes < 2 * slab * 8 ||
             ((int64_t)sp * ntau + t0 + tcn) * nk * nG * 8 > (int64_t)p->r_GTx.bytes)
@@ -749,7 +751,7 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
         rd.cb = bflat(nG);
         rd.alpha = cplx(-1.0 / nk);
         rd.beta = cplx(1.0);
-        rd.ksplit = qs;
+        rd.ksplit = qs * hv;
         rd.partial = tl_split.ptr;
         rd.prec = 2;
         rd.ctype = green::kC64;
@@ -1338,7 +1340,7 @@ int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, 
   take(p->r_Vx, prec == GREEN_FP64 ? 0 : (size_t)(prec == GREEN_BF16X3 ? 2 : 1) * nk * nV * 8);
   take(p->r_Gx, prec == GREEN_BF16X3 ? (size_t)ns * ntau * nk * nG * 8 : 0);
   take(p->r_Ptx, prec == GREEN_BF16X3 ? (size_t)ntau * nP * 8 : 0);
-  p->fuse_sig = prec == GREEN_BF16X3 && nao % 2 == 0 && nao <= 64;
+  p->fuse_sig = prec == GREEN_BF16X3 && nao % 4 == 0 && nao <= 64;
   take(p->r_GTx, p->fuse_sig ? (size_t)ns * ntau * nk * nG * 8 : 0);
   p->ws_bytes = off;
   if (count_ops(p) != GREEN_OK) {
@@ -1605,7 +1607,7 @@ int green_plan_set_option(green_plan* p, int option, int value) {
       return GREEN_OK;
     case GREEN_OPT_SIGMA_FUSED:
       if (value < 0 || value > 1) return GREEN_EINVAL;
-      if (value && (p->prec != GREEN_BF16X3 || p->d.nao % 2 != 0 || p->d.nao > 64)) return GREEN_EINVAL;
+      if (value && (p->prec != GREEN_BF16X3 || p->d.nao % 4 != 0 || p->d.nao > 64)) return GREEN_EINVAL;
       p->fuse_sig = value != 0;
       drop_graph(p);
       return GREEN_OK;

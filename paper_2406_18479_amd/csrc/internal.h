@@ -124,23 +124,28 @@ struct Span {
 hipError_t convert_c64(const double2* in, void* out, int32_t etype, int64_t n, hipStream_t s);
 // out[b][j][i] = round(in[b][i][j]) for `batch` n x n matrices (kC32 or kCB16)
 hipError_t convert_c64_t(const double2* in, void* out, int32_t etype, int n, int64_t batch, hipStream_t s);
-// Sigma~ stages 2 and 3 fused for one tau chunk (split BF16, nao even and at most 64):
+// Sigma~ stages 2 and 3 fused for one tau chunk (split BF16, nao a multiple of 4 and at most 64):
 //   partial[slice][k][j][tt][i] = sum over the slice's Q' of sum_{a,b} X[tt][k][Q'][i][a] GT[tt][kk(k)][b][a]
 //                                  VT[kk(k)][Q'][j][b]
-// then `reduce` (a split-K pass with ksplit = qsplit: rows j, columns (tt, i), batch k) adds the slices in
-// order into Sigma with its alpha and beta.
+// then `reduce` (a split-K pass with ksplit = qsplit * xgv_halves(nao): rows j, columns (tt, i), batch k) adds
+// the partial sums in order into Sigma with its alpha and beta.
 struct XgvArgs {
   const uint2* X;      // element tt * x_tt + k * x_k + Q' * nao^2 + i * nao + a
   const uint2* GT;     // element tt * g_tt + kk * nao^2 + b * nao + a
-  const uint2* VT;     // element kk * naux * nao^2 + Q' * nao^2 + j * nao + b
+  const uint2* VT;     // element kk * naux * nao^2 + Q' * nao^2 + j * nao + b, rows j in 4-element groups of
+                       // hi words then lo words (convert_c64_tr with quad)
   const int32_t* kk;   // device: k -> block index of G and V
-  double2* partial;    // qsplit * nk * nao * tcn * nao elements
+  double2* partial;    // qsplit * xgv_halves(nao) * nk * nao * tcn * nao elements
   int32_t nao, naux, nk, tcn, qsplit;
   int64_t x_tt, x_k, g_tt;
 };
+// partial sums per Q' slice of the fused kernel (its b blocks split over that many waves)
+int xgv_halves(int nao);
 hipError_t sigma_xgv(const XgvArgs& a, const ZGemm& reduce, hipStream_t s);
-// out[b][c][r] = in[b][r][c] rounded to kC32 or kCB16 (rows x cols matrices, batch of them).
-hipError_t convert_c64_tr(const double2* in, void* out, int32_t etype, int rows, int cols, int batch, hipStream_t s);
+// out[b][c][r] = in[b][r][c] rounded to kC32 or kCB16 (rows x cols matrices, batch of them).  quad (kCB16,
+// rows % 4 == 0): each output row holds its elements in groups of 4 as 4 hi words then 4 lo words.
+hipError_t convert_c64_tr(const double2* in, void* out, int32_t etype, int rows, int cols, int batch, hipStream_t s,
+                          bool quad = false);
 
 // Host-side bounds check of a GEMM descriptor against the buffers its operands point into (conservative:
 // the box spanned by the index maps).  Returns false and fills `why` when an access could leave a buffer.

@@ -1094,26 +1094,46 @@ __device__ __forceinline__ void bd_body(const ZGemm& g, int64_t bid0, int64_t nb
 // (Y = X G, S = Y V).  Y never leaves the registers: the 16 x 16 FP32 accumulator tile of Y^T that a lane
 // holds (rows b = 4 (l >> 4) + r, column i = l & 15) is exactly its B operand of the second product (four
 // consecutive K = b of column i), so it is split to BF16 hi + lo in place.  A workgroup owns (tt, k, slice of
-// Q'); wave w owns the columns i in [16 w, 16 w + 16).  G^T and the V^T block of the current Q' sit in LDS
-// (rows padded to 16 NB with zeros), the next Q' block is loaded into registers while the current one is
-// contracted.  Slices write FP64 partial sums [slice][k][j][tt][i] that the split-K pass adds in order.
+// Q'); H waves share each 16-column block of i (wave w: columns 16 (w % NB) + ..., part h = w / NB of the
+// b blocks), each summing over its own b blocks.  G^T and a ring of three V^T blocks sit in LDS (rows padded
+// to 16 NB); the V^T block (LDS DMA) and the X rows (registers) of Q' + 2 are in flight while Q' is
+// contracted.  Each (Q' slice, h) writes FP64 partial sums [slice H + h][k][j][tt][i] that the split-K pass
+// adds in order.
+//
+// LDS rows of a block: K in groups of 4 complex, each group as a 16-byte unit of its 4 hi words then one of
+// its 4 lo words (unit 2 g + 0 / 1), so that a fragment read is one 16-byte load per plane; unit u of row r
+// sits at slot u ^ (r & F) (the 16 rows of a fragment read hit 16 distinct 16-byte bank groups).
 template <int NB>
-__device__ __forceinline__ int xgv_word(int r, int c) {
-  constexpr int CH = 8 * NB;  // 16-byte chunks per row (16 NB complex)
+__device__ __forceinline__ int xgv_word(int r, int u) {
+  constexpr int CH = 8 * NB;  // 16-byte units per row (16 NB complex)
   constexpr int F = CH < 16 ? CH - 1 : 15;
-  return (r * CH + (c ^ (r & F))) * 4;
+  return (r * CH + (u ^ (r & F))) * 4;
+}
+// complex 2 c, 2 c + 1 of row r (memory order: hi0, lo0, hi1, lo1) into their group's hi and lo units
+template <int NB>
+__device__ __forceinline__ void xgv_put(uint32_t* P, int r, int c, u4 v) {
+  const int g = c >> 1, pos = 2 * (c & 1);
+  *reinterpret_cast<uint2*>(&P[xgv_word<NB>(r, 2 * g) + pos]) = make_uint2(v.x, v.z);
+  *reinterpret_cast<uint2*>(&P[xgv_word<NB>(r, 2 * g + 1) + pos]) = make_uint2(v.y, v.w);
 }
 
-template <int NB>
-__global__ __launch_bounds__(64 * NB) void sigma_xgv_kernel(const XgvArgs a) {
+template <int NB, int H>
+__global__ __launch_bounds__(64 * NB * H) void sigma_xgv_kernel(const XgvArgs a) {
   constexpr int R = 16 * NB;       // padded rows and K of each block
-  constexpr int NT = 64 * NB;      // threads
-  constexpr int VPT = (R * R / 2 + NT - 1) / NT;  // 16-byte chunks of a V^T block per thread
+  constexpr int NT = 64 * NB * H;  // threads
+  constexpr int BH = NB / H;       // b blocks per wave
+  static_assert(NB % H == 0, "b blocks split evenly");
+  constexpr int CH = 8 * NB;            // 16-byte units per LDS row
+  constexpr int F = CH < 16 ? CH - 1 : 15;
+  constexpr int RPI = 64 / CH;          // LDS rows per DMA instruction (1 KB)
+  constexpr int DV = 2 * NB / H;        // DMA instructions per wave and V^T block
+  constexpr int NX = 2 * NB;            // 16-byte X loads per lane and Q'
   __shared__ __attribute__((aligned(16))) uint32_t Gs[R * R * 2];
   __shared__ __attribute__((aligned(16))) uint32_t Vs0[R * R * 2];
   __shared__ __attribute__((aligned(16))) uint32_t Vs1[R * R * 2];
+  __shared__ __attribute__((aligned(16))) uint32_t Vs2[R * R * 2];
 
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, w = (tid >> 6) % NB, h = (tid >> 6) / NB;
   const int g4 = lane >> 4, r16 = lane & 15;
   const int nao = a.nao, nch = nao / 2;  // nao even: a row of a block is nch 16-byte chunks
   const int64_t nG = (int64_t)nao * nao, nV = (int64_t)a.naux * nG;
@@ -1130,40 +1150,39 @@ __global__ __launch_bounds__(64 * NB) void sigma_xgv_kernel(const XgvArgs a) {
     reinterpret_cast<u4*>(Gs)[x] = u4{0u, 0u, 0u, 0u};
     reinterpret_cast<u4*>(Vs0)[x] = u4{0u, 0u, 0u, 0u};
     reinterpret_cast<u4*>(Vs1)[x] = u4{0u, 0u, 0u, 0u};
+    reinterpret_cast<u4*>(Vs2)[x] = u4{0u, 0u, 0u, 0u};
   }
   __syncthreads();
   {
     const u4* src = reinterpret_cast<const u4*>(a.GT + tt * a.g_tt + (int64_t)kk * nG);
     for (int x = tid; x < nao * nch; x += NT) {
       const int r = x / nch, c = x - (x / nch) * nch;
-      *reinterpret_cast<u4*>(&Gs[xgv_word<NB>(r, c)]) = src[x];
+      xgv_put<NB>(Gs, r, c, src[x]);
     }
   }
-  // V^T block of one Q' (rows j, K = b) through registers
-  u4 vr[VPT];
-  const uint2* vbase = a.VT + (int64_t)kk * nV;
-  auto vload = [&](int qp) {
-    const u4* src = reinterpret_cast<const u4*>(vbase + (int64_t)qp * nG);
+  // V^T block of one Q' (rows j, K = b; stored in memory in the LDS unit order: per group of 4 complex b, 16
+  // bytes of hi words then 16 of lo words) copied by LDS DMA: instruction d of this wave fills LDS rows
+  // RPI (wave DV + d) + l / CH, lane l the slot l % CH, i.e. unit (l % CH) ^ (row & F) of that row.  Units
+  // past the row (K padding) and rows past nao read unit 0 of row 0: finite values, multiplied by Y^T rows
+  // that are exactly 0 (b >= nao) or feeding outputs that are not stored (j >= nao).
+  const char* vbase = reinterpret_cast<const char*>(a.VT + (int64_t)kk * nV);
+  int voff[DV];
 #pragma unroll
-    for (int e = 0; e < VPT; ++e) {
-      const int x = tid + e * NT;
-      vr[e] = src[min(x, nao * nch - 1)];
-    }
-  };
-  auto vstore = [&](uint32_t* V) {
+  for (int d = 0; d < DV; ++d) {
+    const int row = RPI * ((tid >> 6) * DV + d) + lane / CH;
+    const int u = (lane % CH) ^ (row & F);
+    voff[d] = row < nao && u < nch ? (row * nao + 2 * u) * 8 : 0;
+  }
+  auto vissue = [&](int qp, uint32_t* V) {
+    const char* blk = vbase + (int64_t)qp * nG * 8;
 #pragma unroll
-    for (int e = 0; e < VPT; ++e) {
-      const int x = tid + e * NT;
-      if (x < nao * nch) {
-        const int r = x / nch, c = x - (x / nch) * nch;
-        *reinterpret_cast<u4*>(&V[xgv_word<NB>(r, c)]) = vr[e];
-      }
-    }
+    for (int d = 0; d < DV; ++d) dma16(blk + voff[d], V + ((tid >> 6) * DV + d) * 256);
   };
   // B operand of the first product: X^T (K = a, column i = 16 w + r16): complex a = 16 ab + 4 g4 .. + 3 of
-  // row i, as two 16-byte chunks; a >= nao reads 0 (i >= nao reads row nao - 1: its results are not stored)
+  // row i, as two 16-byte chunks.  a >= nao reads a = 0 (finite; G^T is 0 there) and i >= nao reads row
+  // nao - 1 (its results are not stored), so the loaded registers are used as they land.
   const int icl = min(16 * w + r16, nao - 1);
-  u4 xr[NB][2], xn[NB][2];
+  u4 x0[NB][2], x1[NB][2], x2[NB][2];  // X of three consecutive Q' (loaded two Q' ahead)
   auto xload = [&](int qp, u4 (&xv)[NB][2]) {
     const uint2* row = a.X + tt * a.x_tt + (int64_t)k * a.x_k + (int64_t)qp * nG + (int64_t)icl * nao;
 #pragma unroll
@@ -1171,16 +1190,13 @@ __global__ __launch_bounds__(64 * NB) void sigma_xgv_kernel(const XgvArgs a) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int a0 = 16 * ab + 4 * g4 + 2 * h;
-        const u4 v = *reinterpret_cast<const u4*>(row + (a0 < nao ? a0 : 0));
-        xv[ab][h] = a0 < nao ? v : u4{0u, 0u, 0u, 0u};
+        xv[ab][h] = *reinterpret_cast<const u4*>(row + (a0 < nao ? a0 : 0));
       }
   };
   // A operand fragment: row r, K block kb (complex 16 kb + 4 g4 .. + 3) as hi and lo words
   auto frag = [&](const uint32_t* P, int r, int kb, u4& hi, u4& lo) {
-    const u4 x = *reinterpret_cast<const u4*>(&P[xgv_word<NB>(r, 8 * kb + 2 * g4)]);
-    const u4 y = *reinterpret_cast<const u4*>(&P[xgv_word<NB>(r, 8 * kb + 2 * g4 + 1)]);
-    hi = u4{x.x, x.z, y.x, y.z};
-    lo = u4{x.y, x.w, y.y, y.w};
+    hi = *reinterpret_cast<const u4*>(&P[xgv_word<NB>(r, 8 * kb + 2 * g4)]);
+    lo = *reinterpret_cast<const u4*>(&P[xgv_word<NB>(r, 8 * kb + 2 * g4 + 1)]);
   };
   f4 s_re[NB], s_im[NB];
 #pragma unroll
@@ -1190,98 +1206,102 @@ __global__ __launch_bounds__(64 * NB) void sigma_xgv_kernel(const XgvArgs a) {
   }
   // one Q': Y^T = G^T X^T, then S^T += V^T Y^T (B operands conjugated (re, -im) for the real part and swapped
   // (im, re) for the imaginary part, three split products each)
-  auto contract = [&](const uint32_t* V) {
-    f4 y_re[NB], y_im[NB];
+  auto contract = [&](const uint32_t* V, const u4 (&xr)[NB][2]) {
+    f4 y_re[BH], y_im[BH];
 #pragma unroll
-    for (int bb = 0; bb < NB; ++bb) {
+    for (int bb = 0; bb < BH; ++bb) {
       y_re[bb] = f4{0.f, 0.f, 0.f, 0.f};
       y_im[bb] = f4{0.f, 0.f, 0.f, 0.f};
     }
+    // NB + BH steps (product 1 over the K blocks ab, product 2 over the b blocks bb), each on one group of
+    // fragments from LDS; the next step's group is read before this step's MFMAs (double-buffered), so
+    // LDS latency overlaps the matrix cores
+    u4 fh[2][NB], fl[2][NB];
+    auto read_group = [&](int st, u4 (&hh)[NB], u4 (&ll)[NB]) {
+      if (st < NB) {
 #pragma unroll
-    for (int ab = 0; ab < NB; ++ab) {
-      const u4 bh = u4{xr[ab][0].x, xr[ab][0].z, xr[ab][1].x, xr[ab][1].z};
-      const u4 bl = u4{xr[ab][0].y, xr[ab][0].w, xr[ab][1].y, xr[ab][1].w};
-      const bf8 bch = as_bf8(neg_im(bh)), bcl = as_bf8(neg_im(bl));
-      const bf8 bsh = as_bf8(swap_re_im(bh)), bsl = as_bf8(swap_re_im(bl));
+        for (int bb = 0; bb < BH; ++bb) frag(Gs, 16 * (h * BH + bb) + r16, st, hh[bb], ll[bb]);
+      } else {
 #pragma unroll
-      for (int bb = 0; bb < NB; ++bb) {
-        u4 ah, al;
-        frag(Gs, 16 * bb + r16, ab, ah, al);
-        const bf8 xh = as_bf8(ah), xl = as_bf8(al);
-        y_re[bb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, bch, y_re[bb], 0, 0, 0);
-        y_im[bb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, bsh, y_im[bb], 0, 0, 0);
-        y_re[bb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, bcl, y_re[bb], 0, 0, 0);
-        y_im[bb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, bsl, y_im[bb], 0, 0, 0);
-        y_re[bb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, bch, y_re[bb], 0, 0, 0);
-        y_im[bb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, bsh, y_im[bb], 0, 0, 0);
+        for (int jb = 0; jb < NB; ++jb) frag(V, 16 * jb + r16, h * BH + (st - NB), hh[jb], ll[jb]);
       }
-    }
+    };
+    read_group(0, fh[0], fl[0]);
 #pragma unroll
-    for (int bb = 0; bb < NB; ++bb) {
-      uint32_t h0, h1, h2, h3, l0, l1, l2, l3;
-      split_pair_f(y_re[bb][0], y_im[bb][0], h0, l0);
-      split_pair_f(y_re[bb][1], y_im[bb][1], h1, l1);
-      split_pair_f(y_re[bb][2], y_im[bb][2], h2, l2);
-      split_pair_f(y_re[bb][3], y_im[bb][3], h3, l3);
-      const u4 yh = u4{h0, h1, h2, h3}, yl = u4{l0, l1, l2, l3};
-      const bf8 ych = as_bf8(neg_im(yh)), ycl = as_bf8(neg_im(yl));
-      const bf8 ysh = as_bf8(swap_re_im(yh)), ysl = as_bf8(swap_re_im(yl));
+    for (int st = 0; st < NB + BH; ++st) {
+      if (st + 1 < NB + BH) read_group(st + 1, fh[(st + 1) & 1], fl[(st + 1) & 1]);
+      const u4(&gh)[NB] = fh[st & 1];
+      const u4(&gl)[NB] = fl[st & 1];
+      if (st < NB) {
+        const int ab = st;
+        const u4 bh = u4{xr[ab][0].x, xr[ab][0].z, xr[ab][1].x, xr[ab][1].z};
+        const u4 bl = u4{xr[ab][0].y, xr[ab][0].w, xr[ab][1].y, xr[ab][1].w};
+        const bf8 bch = as_bf8(neg_im(bh)), bcl = as_bf8(neg_im(bl));
+        const bf8 bsh = as_bf8(swap_re_im(bh)), bsl = as_bf8(swap_re_im(bl));
 #pragma unroll
-      for (int jb = 0; jb < NB; ++jb) {
-        u4 ah, al;
-        frag(V, 16 * jb + r16, bb, ah, al);
-        const bf8 vh = as_bf8(ah), vl = as_bf8(al);
-        s_re[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vh, ych, s_re[jb], 0, 0, 0);
-        s_im[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vh, ysh, s_im[jb], 0, 0, 0);
-        s_re[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vh, ycl, s_re[jb], 0, 0, 0);
-        s_im[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vh, ysl, s_im[jb], 0, 0, 0);
-        s_re[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vl, ych, s_re[jb], 0, 0, 0);
-        s_im[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vl, ysh, s_im[jb], 0, 0, 0);
+        for (int bb = 0; bb < BH; ++bb) {
+          const bf8 xh = as_bf8(gh[bb]), xl = as_bf8(gl[bb]);
+          y_re[bb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, bch, y_re[bb], 0, 0, 0);
+          y_im[bb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, bsh, y_im[bb], 0, 0, 0);
+          y_re[bb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, bcl, y_re[bb], 0, 0, 0);
+          y_im[bb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, bsl, y_im[bb], 0, 0, 0);
+          y_re[bb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, bch, y_re[bb], 0, 0, 0);
+          y_im[bb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, bsh, y_im[bb], 0, 0, 0);
+        }
+      } else {
+        const int bb = st - NB;
+        uint32_t h0, h1, h2, h3, l0, l1, l2, l3;
+        split_pair_f(y_re[bb][0], y_im[bb][0], h0, l0);
+        split_pair_f(y_re[bb][1], y_im[bb][1], h1, l1);
+        split_pair_f(y_re[bb][2], y_im[bb][2], h2, l2);
+        split_pair_f(y_re[bb][3], y_im[bb][3], h3, l3);
+        const u4 yh = u4{h0, h1, h2, h3}, yl = u4{l0, l1, l2, l3};
+        const bf8 ych = as_bf8(neg_im(yh)), ycl = as_bf8(neg_im(yl));
+        const bf8 ysh = as_bf8(swap_re_im(yh)), ysl = as_bf8(swap_re_im(yl));
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) {
+          const bf8 vh = as_bf8(gh[jb]), vl = as_bf8(gl[jb]);
+          s_re[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vh, ych, s_re[jb], 0, 0, 0);
+          s_im[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vh, ysh, s_im[jb], 0, 0, 0);
+          s_re[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vh, ycl, s_re[jb], 0, 0, 0);
+          s_im[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vh, ysl, s_im[jb], 0, 0, 0);
+          s_re[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vl, ych, s_re[jb], 0, 0, 0);
+          s_im[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vl, ysh, s_im[jb], 0, 0, 0);
+        }
       }
     }
   };
+  // one Q' t: this wave's copies of V^T(t) and loads of X(t) landed (in flight behind them: those of t + 1)
+  // -> barrier (every wave's copies landed; every wave done with step t - 1, whose LDS slot is refilled
+  // next) -> V^T and X of t + 2 issued -> contraction
+  // Two groups are always in flight: past the slice's end the copies and loads repeat its last Q' into a
+  // slot and registers nothing reads, so the counter waits are the same in every step.
+  auto step = [&](int t, const uint32_t* V, uint32_t* V2, const u4 (&xr)[NB][2], u4 (&x2ahead)[NB][2]) {
+    wait_vm<DV + NX>();
+    barrier_only();
+    vissue(min(t + 2, q1 - 1), V2);
+    xload(min(t + 2, q1 - 1), x2ahead);
+    contract(V, xr);
+  };
   if (q0 < q1) {
-    vload(q0);
-    xload(q0, xr);
-    vstore(Vs0);
-    __syncthreads();
-    for (int qp = q0; qp < q1; qp += 2) {
-      // even step: V^T in Vs0, the next block goes to Vs1 (last read before the previous barrier)
-      const bool n1 = qp + 1 < q1;
-      if (n1) {
-        vload(qp + 1);
-        xload(qp + 1, xn);
-      }
-      contract(Vs0);
-      if (n1) vstore(Vs1);
-      __syncthreads();
-      if (!n1) break;
-#pragma unroll
-      for (int ab = 0; ab < NB; ++ab) {
-        xr[ab][0] = xn[ab][0];
-        xr[ab][1] = xn[ab][1];
-      }
-      // odd step: V^T in Vs1, the next block goes to Vs0
-      const bool n2 = qp + 2 < q1;
-      if (n2) {
-        vload(qp + 2);
-        xload(qp + 2, xn);
-      }
-      contract(Vs1);
-      if (n2) vstore(Vs0);
-      __syncthreads();
-#pragma unroll
-      for (int ab = 0; ab < NB; ++ab) {
-        xr[ab][0] = xn[ab][0];
-        xr[ab][1] = xn[ab][1];
-      }
+    vissue(q0, Vs0);
+    xload(q0, x0);
+    vissue(min(q0 + 1, q1 - 1), Vs1);
+    xload(min(q0 + 1, q1 - 1), x1);
+    for (int qp = q0; qp < q1; qp += 3) {
+      step(qp, Vs0, Vs2, x0, x2);
+      if (qp + 1 >= q1) break;
+      step(qp + 1, Vs1, Vs0, x1, x0);
+      if (qp + 2 >= q1) break;
+      step(qp + 2, Vs2, Vs1, x2, x1);
     }
+    wait_vm<0>();  // no copy into LDS outlives the workgroup
   }
   // S^T[j = 16 jb + 4 g4 + r][i = 16 w + r16] -> partial[((sl nk + k) nao + j) (tcn nao) + tt nao + i]
   const int i = 16 * w + r16;
   if (i < nao) {
     const int64_t ncol = (int64_t)a.tcn * nao;
-    double2* P = a.partial + ((int64_t)sl * a.nk + k) * nao * ncol + (int64_t)tt * nao + i;
+    double2* P = a.partial + ((int64_t)(sl * H + h) * a.nk + k) * nao * ncol + (int64_t)tt * nao + i;
 #pragma unroll
     for (int jb = 0; jb < NB; ++jb)
 #pragma unroll
@@ -1395,9 +1415,10 @@ __global__ void k_convert_c64_t(const double2* __restrict__ in, void* __restrict
 }
 
 // out[b][c][r] = rounded in[b][r][c] for rows x cols matrices: 32 x 32 tiles staged through LDS so that
-// both the FP64 reads (along c) and the rounded writes (along r) are coalesced.
+// both the FP64 reads (along c) and the rounded writes (along r) are coalesced.  quad (kCB16, rows % 4 == 0):
+// each output row stores its elements in groups of 4 as the 4 hi words, then the 4 lo words.
 __global__ __launch_bounds__(256) void k_convert_c64_tr(const double2* __restrict__ in, void* __restrict__ out,
-                                                        int32_t t, int rows, int cols) {
+                                                        int32_t t, int rows, int cols, int quad) {
   __shared__ double2 tile[32][33];
   const int64_t b = blockIdx.z;
   const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
@@ -1420,7 +1441,13 @@ __global__ __launch_bounds__(256) void k_convert_c64_tr(const double2* __restric
     } else {
       uint2 w;
       split_pair(v.x, v.y, w.x, w.y);
-      reinterpret_cast<uint2*>(out)[x] = w;
+      if (quad) {
+        uint32_t* o = reinterpret_cast<uint32_t*>(out) + 2 * (x - r) + 8 * (r >> 2) + (r & 3);
+        o[0] = w.x;
+        o[4] = w.y;
+      } else {
+        reinterpret_cast<uint2*>(out)[x] = w;
+      }
     }
   }
 }
@@ -1835,15 +1862,18 @@ hipError_t convert_c64_t(const double2* in, void* out, int32_t etype, int n, int
   return hipGetLastError();
 }
 
+int xgv_halves(int nao) { return nao > 16 && nao <= 32 ? 2 : 1; }
+
 hipError_t sigma_xgv(const XgvArgs& a, const ZGemm& reduce, hipStream_t s) {
   if (a.tcn <= 0 || a.nk <= 0 || a.naux <= 0) return hipSuccess;
-  if (a.nao <= 0 || a.nao > 64 || a.nao % 2 != 0 || a.qsplit < 1 || reduce.ksplit != a.qsplit || !a.partial)
+  if (a.nao <= 0 || a.nao > 64 || a.nao % 4 != 0 || a.qsplit < 1 || reduce.ksplit != a.qsplit * xgv_halves(a.nao) ||
+      !a.partial)
     return hipErrorInvalidValue;
   if (dryrun()) return hipSuccess;
   const dim3 grid((unsigned)((int64_t)a.tcn * a.nk * a.qsplit));
-  if (a.nao <= 16) sigma_xgv_kernel<1><<<grid, dim3(64), 0, s>>>(a);
-  else if (a.nao <= 32) sigma_xgv_kernel<2><<<grid, dim3(128), 0, s>>>(a);
-  else sigma_xgv_kernel<4><<<grid, dim3(256), 0, s>>>(a);
+  if (a.nao <= 16) sigma_xgv_kernel<1, 1><<<grid, dim3(64), 0, s>>>(a);
+  else if (a.nao <= 32) sigma_xgv_kernel<2, 2><<<grid, dim3(256), 0, s>>>(a);
+  else sigma_xgv_kernel<4, 1><<<grid, dim3(256), 0, s>>>(a);
   const int64_t total = (int64_t)reduce.M * reduce.N * reduce.batch;
   int64_t nb = (total + 255) / 256;
   if (nb > 65536) nb = 65536;
@@ -1851,13 +1881,15 @@ hipError_t sigma_xgv(const XgvArgs& a, const ZGemm& reduce, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t convert_c64_tr(const double2* in, void* out, int32_t etype, int rows, int cols, int batch, hipStream_t s) {
+hipError_t convert_c64_tr(const double2* in, void* out, int32_t etype, int rows, int cols, int batch, hipStream_t s,
+                          bool quad) {
   if (rows <= 0 || cols <= 0 || batch <= 0) return hipSuccess;
   if (etype != kC32 && etype != kCB16) return hipErrorInvalidValue;
+  if (quad && (etype != kCB16 || rows % 4 != 0)) return hipErrorInvalidValue;
   if (batch > 65535 || (rows + 31) / 32 > 65535) return hipErrorInvalidValue;
   if (dryrun()) return hipSuccess;
   k_convert_c64_tr<<<dim3((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32), (unsigned)batch), dim3(256), 0,
-                     s>>>(in, out, etype, rows, cols);
+                     s>>>(in, out, etype, rows, cols, quad ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -85,8 +85,8 @@ def test_split_bf16_p0_tiles(tile):
     assert rel(Pmx, P64) <= REL["bf16x3"]
 
 
-FUSED = [dict(kmesh=(2, 1, 1), nao=6, naux=40, ntau=10, seed=205),     # one 16-row block
-         dict(kmesh=(3, 1, 1), nao=26, naux=90, ntau=8, seed=206),     # two blocks, padded
+FUSED = [dict(kmesh=(2, 1, 1), nao=8, naux=40, ntau=10, seed=205),     # one 16-row block
+         dict(kmesh=(3, 1, 1), nao=28, naux=90, ntau=8, seed=206),     # two blocks, padded
          dict(kmesh=(2, 1, 1), nao=40, naux=75, ntau=6, seed=207),     # four blocks, the last one empty
          dict(kmesh=(1, 1, 1), nao=64, naux=33, ntau=6, seed=208)]     # four full blocks, odd naux
 
