@@ -188,6 +188,21 @@ BIG_TILE = {1: (3, 3), 2: (3, 2), 3: (5, 2), 4: (7, 2)}
 DMA_TILE = {5: (5, 2), 6: (3, 4)}  # the LDS-DMA kernel's tiles
 
 
+def default_big(site: str, naux: int) -> int:
+    """Large tile an untuned split-BF16 plan uses: Sigma~ stage 1 runs the LDS-DMA 192 x 128 tile on the
+    transposed V slab (even naux), the P~0 sum the register-staged tile that pads naux x naux least (192 x 96
+    counted at 90 % of its area, 320 x 64 on the LDS-DMA kernel), as the library's plan creation picks them."""
+    if site == "Sig_PV":
+        return 6 if naux % 2 == 0 else 1
+    best, pick = None, 1
+    for b, (fm, fn) in BIG_TILE.items():
+        bm, bn = 64 * fm, 32 * fn
+        a = -(-naux // bm) * bm * (-(-naux // bn) * bn) * (0.9 if b == 1 else 1.0)
+        if best is None or a < best:
+            best, pick = a, b
+    return 5 if pick == 3 else pick  # 320 x 64 on the LDS-DMA kernel
+
+
 def clocked_kernel_name(site: str, prec: str, report: str, naux: int) -> str:
     """Template name of the kernel that runs a clocked contraction (the P~0 sum over k and orbital pairs,
     or Sigma~ stage 1): the autotuner's choice for the shape with the most tau nodes per launch, else the
@@ -200,10 +215,9 @@ def clocked_kernel_name(site: str, prec: str, report: str, naux: int) -> str:
             best = (int(m.group(1)) * int(m.group(4)), int(m.group(1)), int(m.group(2)), int(m.group(5)),
                     int(m.group(6)))
     if best is None:
-        if site == "P0_Contract":
-            return KERNEL_NAME[prec]
-        big = {"bf16x3": 6 if naux % 2 == 0 else 1}.get(prec, 0)
-        best = (0, 2 * 32, 2 * 32, 0, big)
+        if prec != "bf16x3":
+            return KERNEL_NAME[prec].replace("P0_Contract", site)
+        best = (0, 64, 64, 0, default_big(site, naux))
     _, M, N, shape, big = best
     # Sigma~ stage 1 reads an N-contiguous V slab unless naux is even (then a transposed one)
     bnc = "true" if site == "Sig_PV" and naux % 2 else "false"

@@ -226,8 +226,9 @@ int green_gw_iterate_diis(green_plan* plan, const void* V, const void* H0, const
  *   GREEN_OPT_P0_TILE  split-BF16 plans: output tile of the P~0 contraction over k and orbital pairs
  *                   (the sum of Eq. tilde_P0_tau) before any autotuning: 1 = 192 x 96, 2 = 192 x 64,
  *                   3 = 320 x 64, 4 = 448 x 64 rows x columns of P~0(q, tau), register-staged; 5 = 320 x 64,
- *                   6 = 192 x 128 fed by LDS DMA (even nao; else as 1).  The plan starts with the
- *                   register-staged one that pads naux x naux least (192 x 96 counted at 90% of its area).
+ *                   6 = 192 x 128 fed by LDS DMA (even nao; else as 3 and 1).  The plan starts with the
+ *                   tile that pads naux x naux least (192 x 96 counted at 90% of its area), 320 x 64 on the
+ *                   LDS-DMA kernel.
  *   GREEN_OPT_STAGE1_TILE  split-BF16 plans: tile of the V G products that feed it: 0 = 64 x 64,
  *                   1 = 192 x 96 (default), 2 = 192 x 64.
  *                   Both only change the summation blocking; results agree to rounding.

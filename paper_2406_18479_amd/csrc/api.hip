@@ -1292,7 +1292,8 @@ int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, 
   tc = std::min(tc, ntau);
   p->tc = tc;
   // default tile of the split-BF16 P~0 contraction (naux x naux outputs): the least padded area, the
-  // 192 x 96 tile (highest arithmetic intensity) counted at 90% of its area
+  // 192 x 96 tile (highest arithmetic intensity) counted at 90% of its area; 320 x 64 runs on the LDS-DMA
+  // kernel where the operands allow it
   {
     static const int tile[4][2] = {{192, 96}, {192, 64}, {320, 64}, {448, 64}};
     double best = 0;
@@ -1304,6 +1305,7 @@ int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, 
         p->big_p0 = b + 1;
       }
     }
+    if (p->big_p0 == 3) p->big_p0 = 5;
   }
   size_t off = 0;
   auto take = [&](Region& r, size_t bytes) {

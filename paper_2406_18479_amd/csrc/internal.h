@@ -87,7 +87,7 @@ struct ZGemm {
   int32_t ctype;  // ElemType of C (kCB16 requires beta == 0); prec 0 requires kC64 operands and output
   int32_t big;    // prec 2 with kCB16 operands, large-tile kernel: 1 = 192 x 96 tiles, 2 = 192 x 64,
                   // 3 = 320 x 64, 4 = 448 x 64 (3 and 4 need a K-contiguous B); LDS-DMA kernel (K-contiguous
-                  // A and B, even K and strides, else as 1): 5 = 320 x 64, 6 = 192 x 128
+                  // A and B, even K and strides, else as 3 and 1): 5 = 320 x 64, 6 = 192 x 128
   int32_t shape;  // 256-thread kernels: 0 = by size, 1..4 = 32x32, 32x64, 64x32, 64x64 tiles
   int32_t band;   // large-tile kernel: 0 = output tiles in column order; b > 0 = bands of b tile rows,
                   // each walked column by column (the A rows of a band stay in L2)

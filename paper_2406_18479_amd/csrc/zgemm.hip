@@ -1631,9 +1631,10 @@ Variant zgemm_variant(const ZGemm& g) {
     v.bn = 32 * v.p2;
     return v;
   }
-  // an LDS-DMA tile the operands do not allow falls back to the 192 x 96 register-staged tile
+  // an LDS-DMA tile the operands do not allow falls back to a register-staged one: 320 x 64 to the same
+  // tile, 192 x 128 to 192 x 96
   ZGemm gb = g;
-  if (gb.big >= 5) gb.big = 1;
+  if (gb.big >= 5) gb.big = gb.big == 5 ? 3 : 1;
   if (g.prec == 2 && big_ok(gb)) {
     v.family = 3;
     big_tile(gb.big, &v.p1, &v.p2);
