@@ -622,7 +622,7 @@ __device__ __forceinline__ void mx_body(const ZGemm& g, int64_t bid) {
 // along N), each wave owning FM x FN blocks of 16 x 16, so a tile is (64 FM) x (32 FN).  Operands are
 // stored pre-split (kCB16) and go to LDS unchanged, 32 complex K per stage (two MFMA K steps), double
 // buffered (147 KB of LDS at 192 x 96).  The LDS rows are 128 bytes per plane with the 16-byte chunks
-// XOR-swizzled by row, so the fragment reads of 16 rows at one K offset hit distinct banks.  A is
+// XOR-swizzled by row, so the fragment reads of 16 rows at one K offset run without bank conflicts.  A is
 // K-contiguous with a flat row map; B is K-contiguous with a flat column map, or N-contiguous with a flat
 // K map.  Workgroups are renumbered so that each XCD (8 on MI355X, blocks dispatched round-robin)
 // processes a contiguous range of tiles, whose operands then share its L2.
@@ -665,12 +665,16 @@ struct KCur {
 // 160 KB LDS at that depth, else 16.
 constexpr int bt_bk(int FM, int FN) { return (64 * FM + 32 * FN) * 32 * 16 <= 160 * 1024 ? 32 : 16; }
 
-// word index of (row r, complex k) in a BK-word LDS plane row with swizzled 16-byte chunks: the 16 rows
-// of one fragment read at one K offset land on 16 distinct 16-byte bank groups
+// XOR pattern of the 16-byte chunks of row r for LDS rows of 64 or 128 bytes: with it the fragment reads (16
+// rows at one chunk column per 16 lanes) run without bank conflicts on gfx950 (measured with
+// SQ_LDS_BANK_CONFLICT; plain r & 7 or (r >> 1) & 7 leave 4 conflict cycles per read)
+__device__ __forceinline__ int row_xor(int r) { return (r & 7) ^ ((r >> 3) & 1); }
+
+// word index of (row r, complex k) in a BK-word LDS plane row with swizzled 16-byte chunks
 template <int BK>
 __device__ __forceinline__ int bt_word(int r, int k) {
-  if constexpr (BK == 32) return r * 32 + ((((k >> 2) ^ (r >> 1)) & 7) << 2) + (k & 3);
-  else return r * 16 + ((((k >> 2) ^ (r >> 2)) & 3) << 2) + (k & 3);
+  if constexpr (BK == 32) return r * 32 + ((((k >> 2) ^ row_xor(r)) & 7) << 2) + (k & 3);
+  else return r * 16 + ((((k >> 2) ^ row_xor(r)) & 3) << 2) + (k & 3);
 }
 
 // Output tile of a large-tile workgroup: XCD-aware renumbering, then (batch, K slice, tile); tiles in
@@ -919,8 +923,8 @@ __device__ __forceinline__ void bt_body(const ZGemm& g, int64_t bid0, int64_t nb
 // t, so two stages of loads are always in flight and no register holds staged data.
 //
 // LDS rows hold the 16 complex K of one A row (B column) as 8 chunks of 16 bytes (2 complex, hi/lo
-// interleaved as in memory); chunk c of row r sits at slot c ^ ((r >> 1) & 7), which puts the 16 rows
-// of a fragment read on 16 distinct 16-byte bank groups.  One DMA instruction moves 1 KB: 8 rows of a
+// interleaved as in memory); chunk c of row r sits at slot c ^ row_xor(r), which keeps the fragment
+// reads free of bank conflicts.  One DMA instruction moves 1 KB: 8 rows of a
 // stage, lane l writing slot l & 7 of row l >> 3 (so it reads the chunk that belongs there).  Rows
 // (columns) beyond M (N) read row M-1 (column N-1); chunks past the slice's K end read the stage's
 // first chunk and are zeroed in LDS once landed.  Requirements (checked on the host): K even, K maps
@@ -936,7 +940,7 @@ __device__ __forceinline__ void wait_vm() {
 // workgroup barrier; memory operations are not moved across it, the counter waits are explicit
 __device__ __forceinline__ void barrier_only() { asm volatile("s_barrier" ::: "memory"); }
 
-__device__ __forceinline__ int bd_slot(int r, int c) { return c ^ ((r >> 1) & 7); }
+__device__ __forceinline__ int bd_slot(int r, int c) { return c ^ row_xor(r); }
 
 // One wave-wide 16-byte-per-lane copy global -> LDS (lane l lands at lds + 16 l bytes).  The LDS target is
 // passed as a bare LDS address, so the compiler does not pair these copies with the fragment reads (it
@@ -1102,12 +1106,12 @@ __device__ __forceinline__ void bd_body(const ZGemm& g, int64_t bid0, int64_t nb
 //
 // LDS rows of a block: K in groups of 4 complex, each group as a 16-byte unit of its 4 hi words then one of
 // its 4 lo words (unit 2 g + 0 / 1), so that a fragment read is one 16-byte load per plane; unit u of row r
-// sits at slot u ^ (r & F) (the 16 rows of a fragment read hit 16 distinct 16-byte bank groups).
+// sits at slot u ^ (r & 15) for rows of 256 or 512 bytes and u ^ row_xor(r) for rows of 128 bytes (the
+// patterns that keep the fragment reads free of bank conflicts).
 template <int NB>
 __device__ __forceinline__ int xgv_word(int r, int u) {
   constexpr int CH = 8 * NB;  // 16-byte units per row (16 NB complex)
-  constexpr int F = CH < 16 ? CH - 1 : 15;
-  return (r * CH + (u ^ (r & F))) * 4;
+  return (r * CH + (u ^ (CH >= 16 ? (r & 15) : row_xor(r)))) * 4;
 }
 // complex 2 c, 2 c + 1 of row r (memory order: hi0, lo0, hi1, lo1) into their group's hi and lo units
 template <int NB>
@@ -1124,7 +1128,6 @@ __global__ __launch_bounds__(64 * NB * H) void sigma_xgv_kernel(const XgvArgs a)
   constexpr int BH = NB / H;       // b blocks per wave
   static_assert(NB % H == 0, "b blocks split evenly");
   constexpr int CH = 8 * NB;            // 16-byte units per LDS row
-  constexpr int F = CH < 16 ? CH - 1 : 15;
   constexpr int RPI = 64 / CH;          // LDS rows per DMA instruction (1 KB)
   constexpr int DV = 2 * NB / H;        // DMA instructions per wave and V^T block
   constexpr int NX = 2 * NB;            // 16-byte X loads per lane and Q'
@@ -1162,7 +1165,7 @@ __global__ __launch_bounds__(64 * NB * H) void sigma_xgv_kernel(const XgvArgs a)
   }
   // V^T block of one Q' (rows j, K = b; stored in memory in the LDS unit order: per group of 4 complex b, 16
   // bytes of hi words then 16 of lo words) copied by LDS DMA: instruction d of this wave fills LDS rows
-  // RPI (wave DV + d) + l / CH, lane l the slot l % CH, i.e. unit (l % CH) ^ (row & F) of that row.  Units
+  // RPI (wave DV + d) + l / CH, lane l the slot l % CH, i.e. the unit xgv_word places there.  Units
   // past the row (K padding) and rows past nao read unit 0 of row 0: finite values, multiplied by Y^T rows
   // that are exactly 0 (b >= nao) or feeding outputs that are not stored (j >= nao).
   const char* vbase = reinterpret_cast<const char*>(a.VT + (int64_t)kk * nV);
@@ -1170,7 +1173,7 @@ __global__ __launch_bounds__(64 * NB * H) void sigma_xgv_kernel(const XgvArgs a)
 #pragma unroll
   for (int d = 0; d < DV; ++d) {
     const int row = RPI * ((tid >> 6) * DV + d) + lane / CH;
-    const int u = (lane % CH) ^ (row & F);
+    const int u = (lane % CH) ^ (CH >= 16 ? (row & 15) : row_xor(row));
     voff[d] = row < nao && u < nch ? (row * nao + 2 * u) * 8 : 0;
   }
   auto vissue = [&](int qp, uint32_t* V) {
