@@ -1001,13 +1001,35 @@ __device__ __forceinline__ void bd_body(const ZGemm& g, int64_t bid0, int64_t nb
     const int64_t off = cur.off + 2 * c + (lo >= m.ext ? wrap : 0);
     return cur.k + 2 * c < kend ? off : cur.off;
   };
+  // A stage whose 16 K all lie before the slice's end, under a K map that is flat or whose extent is a
+  // multiple of 16 (stages start at multiples of 16, so they never straddle a wrap), needs no per-lane
+  // checks: each lane adds its fixed chunk offset to the stage's uniform one.
+  const bool a_whole = g.A.c.ext == kFlat || g.A.c.ext % BK == 0;
+  const bool b_whole = g.B.r.ext == kFlat || g.B.r.ext % BK == 0;
+  int64_t a_lane[DA], b_lane[DB];
+#pragma unroll
+  for (int j = 0; j < DA; ++j) a_lane[j] = a_ro[j] + 2 * a_c[j];
+#pragma unroll
+  for (int j = 0; j < DB; ++j) b_lane[j] = b_co[j] + 2 * b_c[j];
   auto issue = [&](uint32_t* As, uint32_t* Bs) {
+    if (a_whole && acur.k + BK <= kend) {
+      const uint2* base = Ap + acur.off;
 #pragma unroll
-    for (int j = 0; j < DA; ++j)
-      dma16(Ap + a_ro[j] + chunk_off(acur, g.A.c, a_wrap, a_c[j]), As + (wave * DA + j) * 256);
+      for (int j = 0; j < DA; ++j) dma16(base + a_lane[j], As + (wave * DA + j) * 256);
+    } else {
 #pragma unroll
-    for (int j = 0; j < DB; ++j)
-      dma16(Bp + b_co[j] + chunk_off(bcur, g.B.r, b_wrap, b_c[j]), Bs + (wave * DB + j) * 256);
+      for (int j = 0; j < DA; ++j)
+        dma16(Ap + a_ro[j] + chunk_off(acur, g.A.c, a_wrap, a_c[j]), As + (wave * DA + j) * 256);
+    }
+    if (b_whole && bcur.k + BK <= kend) {
+      const uint2* base = Bp + bcur.off;
+#pragma unroll
+      for (int j = 0; j < DB; ++j) dma16(base + b_lane[j], Bs + (wave * DB + j) * 256);
+    } else {
+#pragma unroll
+      for (int j = 0; j < DB; ++j)
+        dma16(Bp + b_co[j] + chunk_off(bcur, g.B.r, b_wrap, b_c[j]), Bs + (wave * DB + j) * 256);
+    }
     acur.step(g.A.c, BK, a_din, a_wrap);
     bcur.step(g.B.r, BK, b_din, b_wrap);
   };
