@@ -175,8 +175,8 @@ def run_precision(system, prec, steps, warmup, chunk_bytes=0, tune=False, graph=
         "last": reps[-1],
         "first": first,
         "tune_iterations": tuned,
-        "kernel_names": [clocked_kernel_name("P0_Contract", prec, report, spec.naux),
-                         clocked_kernel_name("Sig_PV", prec, report, spec.naux)],
+        "kernel_names": [clocked_kernel_name("P0_Contract", prec, report, spec.naux, spec.nao),
+                         clocked_kernel_name("Sig_PV", prec, report, spec.naux, spec.nao)],
     }
 
 
@@ -203,7 +203,7 @@ def default_big(site: str, naux: int) -> int:
     return 5 if pick == 3 else pick  # 320 x 64 on the LDS-DMA kernel
 
 
-def clocked_kernel_name(site: str, prec: str, report: str, naux: int) -> str:
+def clocked_kernel_name(site: str, prec: str, report: str, naux: int, nao: int) -> str:
     """Template name of the kernel that runs a clocked contraction (the P~0 sum over k and orbital pairs,
     or Sigma~ stage 1): the autotuner's choice for the shape with the most tau nodes per launch, else the
     default one."""
@@ -226,7 +226,9 @@ def clocked_kernel_name(site: str, prec: str, report: str, naux: int) -> str:
         return f"zgemm_bt_kernel<{fm},{fn},{bnc},Site::{site}>"
     if prec == "bf16x3" and big in DMA_TILE:
         fm, fn = DMA_TILE[big]
-        return f"zgemm_bd_kernel<{fm},{fn},Site::{site}>"
+        # operands in groups of 4 (hi, then lo words) where the contraction extent allows it
+        quad = site == "Sig_PV" and naux % 4 == 0
+        return f"zgemm_bd_kernel<{fm},{fn},{'true' if quad else 'false'},Site::{site}>"
     wm, wn = ((shape - 1) // 2 + 1, (shape - 1) % 2 + 1) if 1 <= shape <= 4 else (1 if M <= 32 else 2,
                                                                                     1 if N <= 32 else 2)
     if prec == "fp64":

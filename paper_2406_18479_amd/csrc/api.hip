@@ -311,7 +311,7 @@ std::vector<TuneCand> tune_candidates(const ZGemm& g0) {
     g.shape = shape;
     g.big = big;
     const int fam = green::zgemm_variant(g).family;
-    if (big && fam != (big >= 5 ? 4 : 3)) return;
+    if (fam < 0 || (big && fam != (big >= 5 ? 4 : 3))) return;
     g.ksplit = 1;
     const int ks0 = choose_ksplit(g);
     // large tiles run one workgroup per CU: also the split-K counts that fill one, two and three waves
@@ -512,7 +512,9 @@ int run_polarization(green_plan* p, const void* V, const void* G, void* P0, void
   const bool bf = p->prec == GREEN_BF16X3;
   const int stage1 = p->prec == GREEN_FP64 ? 0 : (bf ? 2 : 1);
   const int st = bf ? green::kCB16 : green::kC64;  // storage of the stage-1 operands
-  const int tt = inter_type(p->prec);              // storage of the stage-2 operands
+  // storage of the stage-2 operands (kept interleaved: writing them in groups of 4 from the stage-1 epilogue
+  // costs more in scattered 4-byte stores than the grouped reads save)
+  const int tt = inter_type(p->prec);
   const void* Gs = G;
   green::Span sGs = span(G, ex.G);
   if (bf) {
@@ -648,6 +650,10 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
   const int stage = p->prec == GREEN_FP64 ? 0 : (bf ? 2 : 1);
   // split-BF16 plans with an even naux run stage 1 on the LDS-DMA kernel (K-contiguous V slab)
   const bool vt_dma = bf && naux % 2 == 0;
+  // with naux a multiple of 4 both of its operands hold the contraction index Q in groups of 4 (hi words, then
+  // lo words), the order the LDS-DMA kernel reads its fragments in
+  const bool pq = vt_dma && naux % 4 == 0;
+  const int pvt = pq ? green::kCB16Q : green::kCB16;
   // ... and with nao a multiple of 4 up to 64, stages 2 and 3 in one kernel on G^T and per-block transposed
   // V slabs
   const bool fused = bf && p->fuse_sig;
@@ -676,7 +682,7 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
       if ((int64_t)p->r_Vx.bytes < (bf ? 2 : 1) * slab * green::elem_bytes(vt)) return GREEN_EINVAL;
       if (vt_dma) {
         // V^{k,k-q} stored [k][(i,a)][Q]: the contraction index Q runs contiguously for the LDS-DMA kernel
-        GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64_tr(static_cast<const double2*>(Vqn), Vx, vt, naux, (int)nG, nk, st_); }));
+        GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64_tr(static_cast<const double2*>(Vqn), Vx, vt, naux, (int)nG, nk, st_, pq); }));
       } else {
         GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64(static_cast<const double2*>(Vqn), Vx, vt, slab, st_); }));
       }
@@ -697,17 +703,20 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
     if (bf) {
       // P~^q(tau)^T rounded to split BF16 for the large-tile kernel (K-contiguous rows)
       if ((int64_t)p->r_Ptx.bytes < (int64_t)ntau * nP * 8) return GREEN_EINVAL;
-      GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64_t(Pp + (int64_t)q * ntau * nP, Ptx, green::kCB16, naux, ntau, st_); }));
+      if (pq)
+        GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64_tr(Pp + (int64_t)q * ntau * nP, Ptx, green::kCB16, naux, naux, ntau, st_, true); }));
+      else
+        GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64_t(Pp + (int64_t)q * ntau * nP, Ptx, green::kCB16, naux, ntau, st_); }));
     }
     for (int t0 = 0; t0 < ntau; t0 += p->tc) {
       const int tcn = std::min(p->tc, ntau - t0);
       // X[tt][k][Q'][(i,a)] = sum_Q P~^q_{QQ'}(tau) V^{k,k-q}_{ia}(Q): the V slab is shared by the tau nodes
       // of the chunk, so they are stacked into the rows, M = (tt, Q') (no partial tiles at each naux edge)
       GREEN_TRY(gemm(green::Site::Sig_PV, "Sigma.PV",
-                     bf ? op(eptr(Ptx, green::kCB16, (int64_t)t0 * nP), flat(naux), flat(1), bnone(), green::kCB16)
+                     bf ? op(eptr(Ptx, pvt, (int64_t)t0 * nP), flat(naux), flat(1), bnone(), pvt)
                         : op(Pp + ((int64_t)q * ntau + t0) * nP, two(naux, 1, nP), flat(naux), bnone()),
                      bf ? sPtx : sP,
-                     vt_dma ? op(Vqn, flat(1), flat(naux), bnone(), green::kCB16)
+                     vt_dma ? op(Vqn, flat(1), flat(naux), bnone(), pvt)
                             : op(Vqn, flat(nG), two((int32_t)nG, 1, nV), bnone(), mixed ? vt : green::kC64),
                      sVa, T1, sT1, two(naux, nG, (int64_t)nk * nV), two((int32_t)nG, 1, nV), bnone(), tcn * naux,
                      (int)(nk * nG), naux, 1, cplx(1), cplx(0), s, p->prec, xt, bf ? (vt_dma ? 6 : 1) : 0));

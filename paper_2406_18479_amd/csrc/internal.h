@@ -39,6 +39,9 @@ enum ElemType : int32_t {
   kC64 = 0,   // double2 (re, im)                                         16 bytes
   kC32 = 1,   // float2 (re, im)                                           8 bytes
   kCB16 = 2,  // uint2 {hi, lo}: bf16 pairs (re | im << 16), x = hi + lo   8 bytes
+  kCB16Q = 3, // as kCB16, elements grouped by 4 from the pointer passed: for element e the words at
+              // 2 (e & ~3) + (e & 3) (hi) and that + 4 (lo), i.e. 16 bytes of hi words then 16 of lo words
+              // per group.  Operands of this type are read by the LDS-DMA kernel only.
 };
 static inline int64_t elem_bytes(int32_t t) { return t == kC64 ? 16 : 8; }
 
@@ -96,8 +99,9 @@ struct ZGemm {
 // Kernel variant a descriptor launches: family 0 FP64, 1 FP32, 2 split BF16 (256 threads), 3 split BF16
 // large tiles (512 threads); tile (bm, bn) = (32 p1, 32 p2) or (64 p1, 32 p2) for family 3.
 struct Variant {
-  int32_t family, p1, p2;
-  bool bnc;  // family 3: B is N-contiguous
+  int32_t family, p1, p2;  // family -1: no kernel reads these operands
+  bool bnc;   // family 3: B is N-contiguous
+  bool quad;  // family 4: kCB16Q operands
   int32_t threads, bm, bn;
 };
 Variant zgemm_variant(const ZGemm& g);

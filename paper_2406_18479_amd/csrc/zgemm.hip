@@ -319,6 +319,16 @@ __device__ __forceinline__ void split_pair_f(float re, float im, uint32_t& hi, u
   hi = hr | (hm << 16);
   lo = bf16_bits(re - bf16_value(hr)) | (bf16_bits(im - bf16_value(hm)) << 16);
 }
+// a split-BF16 element of C (kCB16: 8 contiguous bytes; kCB16Q: its hi and lo words in its group of 4)
+__device__ __forceinline__ void store_split(const ZGemm& g, int64_t off, uint2 w) {
+  if (g.ctype == kCB16Q) {
+    uint32_t* W = reinterpret_cast<uint32_t*>(g.C) + 2 * (off & ~(int64_t)3) + (off & 3);
+    W[0] = w.x;
+    W[4] = w.y;
+  } else {
+    reinterpret_cast<uint2*>(g.C)[off] = w;
+  }
+}
 // C element store by the descriptor's ctype: v is the raw sum, alpha/beta applied here
 __device__ __forceinline__ void store_c(const ZGemm& g, int64_t off, double2 v) {
   double2 o;
@@ -344,7 +354,7 @@ __device__ __forceinline__ void store_c(const ZGemm& g, int64_t off, double2 v) 
   } else {
     uint2 w;
     split_pair(o.x, o.y, w.x, w.y);
-    reinterpret_cast<uint2*>(g.C)[off] = w;
+    store_split(g, off, w);
   }
 }
 
@@ -352,12 +362,12 @@ __device__ __forceinline__ void store_c(const ZGemm& g, int64_t off, double2 v) 
 // split in FP32 (the accumulator carries FP32 precision; hi + lo keeps 2^-17 of it); other outputs go through
 // the FP64 path below.
 __device__ __forceinline__ void store_cf(const ZGemm& g, int64_t off, float re, float im) {
-  if (g.ctype == kCB16) {
+  if (g.ctype == kCB16 || g.ctype == kCB16Q) {
     const float ar = (float)g.alpha.x, ai = (float)g.alpha.y;
     const float o_re = ar * re - ai * im, o_im = ar * im + ai * re;
     uint2 w;
     split_pair_f(o_re, o_im, w.x, w.y);
-    reinterpret_cast<uint2*>(g.C)[off] = w;
+    store_split(g, off, w);
   } else {
     store_c(g, off, make_double2((double)re, (double)im));
   }
@@ -951,7 +961,7 @@ __device__ __forceinline__ void dma16(const void* src, uint32_t* lds) {
                                    0);
 }
 
-template <int FM, int FN>
+template <int FM, int FN, bool Q>
 __device__ __forceinline__ void bd_body(const ZGemm& g, int64_t bid0, int64_t nblk) {
   constexpr int BM = 64 * FM, BN = 32 * FN, BK = 16;
   constexpr int DA = BM / 64, DB = BN / 64;  // DMA instructions per wave and stage
@@ -994,12 +1004,14 @@ __device__ __forceinline__ void bd_body(const ZGemm& g, int64_t bid0, int64_t nb
   bcur.init(g.B.r, kbeg);
   const int64_t a_din = (int64_t)BK * g.A.c.s_in, a_wrap = g.A.c.s_out - (int64_t)g.A.c.ext * g.A.c.s_in;
   const int64_t b_din = (int64_t)BK * g.B.r.s_in, b_wrap = g.B.r.s_out - (int64_t)g.B.r.ext * g.B.r.s_in;
-  // offset of complex k0 + 2c (k0 = the cursor's; unit K stride), or of k0 when that lies past the
-  // slice's end
+  // offset of 16-byte chunk c of the stage at the cursor (unit K stride): complex k0 + 2c (kCB16) or, for
+  // kCB16Q, the hi (c even) or lo (c odd) words of the group at complex k0 + 4 (c / 2), which sit at the same
+  // 8-byte element offset k0 + 2c; the stage's first chunk when that group lies past the slice's end
   auto chunk_off = [&](const KCur& cur, const IdxMap& m, int64_t wrap, int c) -> int64_t {
-    const int lo = cur.lo + 2 * c;
+    const int dk = Q ? 4 * (c >> 1) : 2 * c;
+    const int lo = cur.lo + dk;
     const int64_t off = cur.off + 2 * c + (lo >= m.ext ? wrap : 0);
-    return cur.k + 2 * c < kend ? off : cur.off;
+    return cur.k + dk < kend ? off : cur.off;
   };
   // A stage whose 16 K all lie before the slice's end, under a K map that is flat or whose extent is a
   // multiple of 16 (stages start at multiples of 16, so they never straddle a wrap), needs no per-lane
@@ -1049,8 +1061,13 @@ __device__ __forceinline__ void bd_body(const ZGemm& g, int64_t bid0, int64_t nb
   auto frag = [&](const uint32_t* P, int r, u4& hi, u4& lo) {
     const u4 x = *reinterpret_cast<const u4*>(P + r * 32 + 4 * bd_slot(r, 2 * g4));
     const u4 y = *reinterpret_cast<const u4*>(P + r * 32 + 4 * bd_slot(r, 2 * g4 + 1));
-    hi = u4{x.x, x.z, y.x, y.z};
-    lo = u4{x.y, x.w, y.y, y.w};
+    if constexpr (Q) {
+      hi = x;
+      lo = y;
+    } else {
+      hi = u4{x.x, x.z, y.x, y.z};
+      lo = u4{x.y, x.w, y.y, y.w};
+    }
   };
   auto compute = [&](const uint32_t* As, const uint32_t* Bs) {
     u4 bh[FN], bl[FN];
@@ -1080,7 +1097,7 @@ __device__ __forceinline__ void bd_body(const ZGemm& g, int64_t bid0, int64_t nb
   auto zero_tail = [&](uint32_t* As, uint32_t* Bs) {
     for (int x = tid; x < (BM + BN) * 8; x += 512) {
       const int r = x >> 3, c = x & 7;
-      if (2 * c < kvalid_last) continue;
+      if ((Q ? 4 * (c >> 1) : 2 * c) < kvalid_last) continue;
       uint32_t* P = r < BM ? As + r * 32 : Bs + (r - BM) * 32;
       const int rr = r < BM ? r : r - BM;
       *reinterpret_cast<u4*>(P + 4 * bd_slot(rr, c)) = u4{0u, 0u, 0u, 0u};
@@ -1375,9 +1392,9 @@ template <int FM, int FN, bool BNC, Site SITE>
 __global__ __launch_bounds__(512) void zgemm_bt_kernel(const ZGemm g) {
   bt_body<FM, FN, BNC>(g, blockIdx.x, gridDim.x);
 }
-template <int FM, int FN, Site SITE>
+template <int FM, int FN, bool Q, Site SITE>
 __global__ __launch_bounds__(512) void zgemm_bd_kernel(const ZGemm g) {
-  bd_body<FM, FN>(g, blockIdx.x, gridDim.x);
+  bd_body<FM, FN, Q>(g, blockIdx.x, gridDim.x);
 }
 
 struct GroupArgs {
@@ -1410,9 +1427,9 @@ template <int FM, int FN, bool BNC>
 __global__ __launch_bounds__(512) void zgemm_bt_group(const GroupArgs a) {
   group_loop(a, [](const ZGemm& g, int64_t b, int64_t n) { bt_body<FM, FN, BNC>(g, b, n); });
 }
-template <int FM, int FN>
+template <int FM, int FN, bool Q>
 __global__ __launch_bounds__(512) void zgemm_bd_group(const GroupArgs a) {
-  group_loop(a, [](const ZGemm& g, int64_t b, int64_t n) { bd_body<FM, FN>(g, b, n); });
+  group_loop(a, [](const ZGemm& g, int64_t b, int64_t n) { bd_body<FM, FN, Q>(g, b, n); });
 }
 // split-K second pass of a group: descriptor blockIdx.y, elements strided over blockIdx.x
 __global__ __launch_bounds__(256) void zgemm_splitk_reduce_group(const ZGemm* __restrict__ gs) {
@@ -1540,7 +1557,7 @@ bool check_operand(const char* name, const void* p, int32_t etype, const Range& 
     std::snprintf(why, why_len, "%s: no extent", name);
     return false;
   }
-  if (etype < kC64 || etype > kCB16) {
+  if (etype < kC64 || etype > kCB16Q) {
     std::snprintf(why, why_len, "%s: bad element type", name);
     return false;
   }
@@ -1550,7 +1567,10 @@ bool check_operand(const char* name, const void* p, int32_t etype, const Range& 
     std::snprintf(why, why_len, "%s: misaligned", name);
     return false;
   }
-  const int64_t lo = base + (r1.lo + r2.lo + rb.lo) * esz, hi = base + (r1.hi + r2.hi + rb.hi) * esz + esz;
+  // kCB16Q: the last element's whole group of 4 (groups counted from the pointer)
+  const int64_t last = r1.hi + r2.hi + rb.hi;
+  const int64_t lo = base + (r1.lo + r2.lo + rb.lo) * esz,
+                hi = base + (etype == kCB16Q ? ((last | 3) + 1) * esz : last * esz + esz);
   if (lo < 0 || hi > sp.bytes) {
     std::snprintf(why, why_len, "%s: touches bytes [%lld, %lld) of a %lld-byte buffer", name, (long long)lo,
                   (long long)hi, (long long)sp.bytes);
@@ -1586,7 +1606,7 @@ bool zgemm_in_bounds(const ZGemm& g, const Span& a, const Span& b, const Span& c
     std::snprintf(why, why_len, "FP64 contraction with non-FP64 operands");
     return false;
   }
-  if (g.ctype == kCB16 && (g.beta.x != 0.0 || g.beta.y != 0.0)) {
+  if ((g.ctype == kCB16 || g.ctype == kCB16Q) && (g.beta.x != 0.0 || g.beta.y != 0.0)) {
     std::snprintf(why, why_len, "split-BF16 output cannot accumulate");
     return false;
   }
@@ -1625,13 +1645,21 @@ static void big_tile(int big, int* fm, int* fn) {
 // even element strides and 16-byte aligned bases (every 2-complex chunk is one aligned 16-byte copy).
 static bool even_map(const IdxMap& m) { return m.s_in % 2 == 0 && (m.ext == kFlat || m.s_out % 2 == 0); }
 static bool even_batch(const BatchMap& b) { return b.s_lo % 2 == 0 && b.s_hi % 2 == 0; }
+// kCB16Q operands (both or neither) need every row and every K block to start a group of 4: K, extents
+// and strides multiples of 4.
+static bool quad_map(const IdxMap& m) { return m.s_in % 4 == 0 && (m.ext == kFlat || m.s_out % 4 == 0); }
 static bool dma_ok(const ZGemm& g) {
   if (g.big < 5 || g.big > 6) return false;
-  if (g.A.etype != kCB16 || g.B.etype != kCB16 || g.A.conj || g.B.conj) return false;
-  if (g.A.c.s_in != 1 || g.B.r.s_in != 1 || g.K % 2 != 0) return false;
+  const bool q = g.A.etype == kCB16Q;
+  if ((g.A.etype != kCB16 && !q) || g.B.etype != g.A.etype || g.A.conj || g.B.conj) return false;
+  const int u = q ? 4 : 2;  // K granule of one 16-byte copy
+  if (g.A.c.s_in != 1 || g.B.r.s_in != 1 || g.K % u != 0) return false;
   for (const IdxMap* m : {&g.A.c, &g.B.r})
-    if (m->ext != kFlat && (m->ext % 2 != 0 || m->ext < 16 || m->s_out % 2 != 0)) return false;
+    if (m->ext != kFlat && (m->ext % u != 0 || m->ext < 16 || m->s_out % u != 0)) return false;
   if (!even_map(g.A.r) || !even_map(g.B.c) || !even_batch(g.A.b) || !even_batch(g.B.b)) return false;
+  if (q && (!quad_map(g.A.r) || !quad_map(g.B.c) || g.A.b.s_lo % 4 || g.A.b.s_hi % 4 || g.B.b.s_lo % 4 ||
+            g.B.b.s_hi % 4))
+    return false;
   return ((uintptr_t)g.A.p % 16 == 0) && ((uintptr_t)g.B.p % 16 == 0);
 }
 
@@ -1651,9 +1679,16 @@ Variant zgemm_variant(const ZGemm& g) {
     v.family = 4;
     dma_tile(g.big, &v.p1, &v.p2);
     v.bnc = false;
+    v.quad = g.A.etype == kCB16Q;
     v.threads = 512;
     v.bm = 64 * v.p1;
     v.bn = 32 * v.p2;
+    return v;
+  }
+  if (g.A.etype == kCB16Q || g.B.etype == kCB16Q) {  // only the LDS-DMA kernel reads grouped operands
+    v.family = -1;
+    v.threads = 512;
+    v.bm = v.bn = 64;
     return v;
   }
   // an LDS-DMA tile the operands do not allow falls back to a register-staged one: 320 x 64 to the same
@@ -1685,7 +1720,7 @@ Variant zgemm_variant(const ZGemm& g) {
 }
 
 bool same_variant(const Variant& a, const Variant& b) {
-  return a.family == b.family && a.p1 == b.p1 && a.p2 == b.p2 && a.bnc == b.bnc;
+  return a.family == b.family && a.p1 == b.p1 && a.p2 == b.p2 && a.bnc == b.bnc && a.quad == b.quad;
 }
 
 void zgemm_tile(const ZGemm& g, int* bm, int* bn, int* threads) {
@@ -1738,14 +1773,12 @@ void launch_bt(const ZGemm& g, dim3 grid, hipStream_t s) {
   }
 }
 
-template <int FM, int FN>
+template <int FM, int FN, bool Q>
 void launch_bd(const ZGemm& g, dim3 grid, hipStream_t s) {
   switch (g.site) {
-    case Site::P0_VG: zgemm_bd_kernel<FM, FN, Site::P0_VG><<<grid, dim3(512), 0, s>>>(g); break;
-    case Site::P0_VGrev: zgemm_bd_kernel<FM, FN, Site::P0_VGrev><<<grid, dim3(512), 0, s>>>(g); break;
-    case Site::P0_Contract: zgemm_bd_kernel<FM, FN, Site::P0_Contract><<<grid, dim3(512), 0, s>>>(g); break;
-    case Site::Sig_PV: zgemm_bd_kernel<FM, FN, Site::Sig_PV><<<grid, dim3(512), 0, s>>>(g); break;
-    default: zgemm_bd_kernel<FM, FN, Site::Generic><<<grid, dim3(512), 0, s>>>(g); break;
+    case Site::P0_Contract: zgemm_bd_kernel<FM, FN, Q, Site::P0_Contract><<<grid, dim3(512), 0, s>>>(g); break;
+    case Site::Sig_PV: zgemm_bd_kernel<FM, FN, Q, Site::Sig_PV><<<grid, dim3(512), 0, s>>>(g); break;
+    default: zgemm_bd_kernel<FM, FN, Q, Site::Generic><<<grid, dim3(512), 0, s>>>(g); break;
   }
 }
 
@@ -1771,8 +1804,13 @@ void launch_single(const Variant& v, const ZGemm& g, dim3 grid, hipStream_t s) {
       else launch_mx<2, 2, 2>(g, grid, s);
       break;
     case 4:
-      if (v.p1 == 5) launch_bd<5, 2>(g, grid, s);
-      else launch_bd<3, 4>(g, grid, s);
+      if (v.p1 == 5) {
+        if (v.quad) launch_bd<5, 2, true>(g, grid, s);
+        else launch_bd<5, 2, false>(g, grid, s);
+      } else {
+        if (v.quad) launch_bd<3, 4, true>(g, grid, s);
+        else launch_bd<3, 4, false>(g, grid, s);
+      }
       break;
     default:
       if (v.p1 == 5) launch_bt<5, 2, false>(g, grid, s);
@@ -1811,8 +1849,13 @@ void launch_group(const Variant& v, const GroupArgs& a, dim3 grid, hipStream_t s
       else zgemm_mx_group<2, 2, 2><<<grid, b256, 0, s>>>(a);
       break;
     case 4:
-      if (v.p1 == 5) zgemm_bd_group<5, 2><<<grid, b512, 0, s>>>(a);
-      else zgemm_bd_group<3, 4><<<grid, b512, 0, s>>>(a);
+      if (v.p1 == 5) {
+        if (v.quad) zgemm_bd_group<5, 2, true><<<grid, b512, 0, s>>>(a);
+        else zgemm_bd_group<5, 2, false><<<grid, b512, 0, s>>>(a);
+      } else {
+        if (v.quad) zgemm_bd_group<3, 4, true><<<grid, b512, 0, s>>>(a);
+        else zgemm_bd_group<3, 4, false><<<grid, b512, 0, s>>>(a);
+      }
       break;
     default:
       if (v.p1 == 5) zgemm_bt_group<5, 2, false><<<grid, b512, 0, s>>>(a);
@@ -1832,7 +1875,7 @@ bool launchable(const ZGemm& g) {
   if (g.ksplit < 1 || g.prec < 0 || g.prec > 2) return false;
   if (g.prec == 0 && (g.A.etype != kC64 || g.B.etype != kC64 || g.ctype != kC64)) return false;
   if (g.ksplit > 1 && !g.partial) return false;
-  return true;
+  return zgemm_variant(g).family >= 0;
 }
 
 }  // namespace

@@ -67,16 +67,16 @@ def test_mixed_polarization_and_selfenergy(c, prec):
     assert rel(Smx, S64) <= REL[prec]
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6])
-def test_split_bf16_p0_tiles(tile):
+@pytest.mark.parametrize("tile,nao", [(1, 10), (2, 10), (3, 10), (4, 10), (5, 10), (6, 10), (5, 12), (6, 12)])
+def test_split_bf16_p0_tiles(tile, nao):
     """Every output tile of the split-BF16 P~0 contraction (register-staged 192 x 96, 192 x 64, 320 x 64,
-    448 x 64; LDS-DMA 320 x 64, 192 x 128) on an naux that leaves ragged tiles along both P~0 dimensions
-    and a K (= nk nao^2 = 200) whose orbital-pair blocks (100) and end fall inside 16-wide K stages, against
-    the FP64 path."""
+    448 x 64; LDS-DMA 320 x 64, 192 x 128) on an naux that leaves ragged tiles along both P~0 dimensions,
+    against the FP64 path.  nao = 10: K = nk nao^2 = 200, whose orbital-pair blocks (100) and end fall inside
+    16-wide K stages; nao = 12: blocks of 144 that are whole stages."""
     _require_gpu()
-    s = systems.make_system(configs.tiny(kmesh=(2, 1, 1), nao=10, naux=350, ntau=6, beta=8.0, seed=204,
-                                         v_scale=0.5 / 10 ** 0.5))
-    print("[gpu-case] split-BF16 P0 tile", tile, flush=True)
+    s = systems.make_system(configs.tiny(kmesh=(2, 1, 1), nao=nao, naux=350, ntau=6, beta=8.0, seed=204,
+                                         v_scale=0.5 / nao ** 0.5))
+    print("[gpu-case] split-BF16 P0 tile", tile, "nao", nao, flush=True)
     V, G = dev(s.V), dev(s.G0)
     p64, pmx = plan(s, "fp64"), plan(s, "bf16x3")
     pmx.set_option("p0_tile", tile)
