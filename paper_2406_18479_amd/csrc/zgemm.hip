@@ -745,11 +745,37 @@ __device__ __forceinline__ void large_tile_store(const ZGemm& g, const f4 (&acc_
     const int gn = nw + 16 * j + (lane & 15);
     coff[j] = gn < g.N ? map_idx(g.cc, gn) : 0;
   }
+  // Split-BF16 output whose rows are contiguous (unit row stride, blocks of rows a multiple of 4, even
+  // strides, 16-byte aligned): a lane's 4 consecutive rows of one column are 32 contiguous bytes, written as
+  // two 16-byte stores
+  const bool vec = g.ctype == kCB16 && g.cr.s_in == 1 && (g.cr.ext == kFlat || (g.cr.ext % 4 == 0 && g.cr.s_out % 2 == 0)) &&
+                   g.cc.s_in % 2 == 0 && (g.cc.ext == kFlat || g.cc.s_out % 2 == 0) && cb % 2 == 0 &&
+                   reinterpret_cast<uintptr_t>(g.C) % 16 == 0;
+  const float ar = (float)g.alpha.x, ai = (float)g.alpha.y;
 #pragma unroll
-  for (int i = 0; i < FM; ++i)
+  for (int i = 0; i < FM; ++i) {
+    const int gm0 = mw + 16 * i + 4 * (lane >> 4);
+    if (vec && gm0 + 3 < g.M) {
+      const int64_t roff = cb + map_idx(g.cr, gm0);
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int gn = nw + 16 * j + (lane & 15);
+        if (gn >= g.N) continue;
+        uint32_t h[4], l[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float re = acc_re[i][j][r], im = acc_im[i][j][r];
+          split_pair_f(ar * re - ai * im, ar * im + ai * re, h[r], l[r]);
+        }
+        u4* dst = reinterpret_cast<u4*>(reinterpret_cast<uint2*>(g.C) + roff + coff[j]);
+        dst[0] = u4{h[0], l[0], h[1], l[1]};
+        dst[1] = u4{h[2], l[2], h[3], l[3]};
+      }
+      continue;
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int gm = mw + 16 * i + 4 * (lane >> 4) + r;
+      const int gm = gm0 + r;
       if (gm >= g.M) continue;
       const int64_t roff = cb + map_idx(g.cr, gm);
 #pragma unroll
@@ -758,6 +784,7 @@ __device__ __forceinline__ void large_tile_store(const ZGemm& g, const f4 (&acc_
         if (gn < g.N) store_cf(g, roff + coff[j], acc_re[i][j][r], acc_im[i][j][r]);
       }
     }
+  }
 }
 
 template <int FM, int FN, bool BNC>
