@@ -86,8 +86,35 @@ def tune_plan(plan, step, max_iters=60):
     return i + 1
 
 
+def time_kpath(plan, system, H0, S, Sinf, Sig, mu, npath):
+    """Sec. 2.4 post-processing after the last iteration: Sinf and Sigma~ interpolated onto npath points of
+    the straight path Gamma -> (1/2, 1/2, 1/2), then Dyson on the path at the kept chemical potential (H0 on
+    the path stands in as the Gamma-point H0; S = I).  Returns the two times in ms."""
+    import numpy as np
+    import torch
+    from paper_2406_18479_amd.gw import Plan
+    spec = system.spec
+    t = np.linspace(0.0, 0.5, npath)
+    path = np.stack([t, t, t], axis=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Sinf_p, Sig_p = plan.kpath_interpolate(path, Sinf, Sig)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pp = Plan((npath, 1, 1), spec.nao, 4, system.grid, nspin=spec.nspin, prec="fp64")
+    H0p = H0[:, :1].expand(spec.nspin, npath, spec.nao, spec.nao).contiguous()
+    Sp = torch.eye(spec.nao, dtype=torch.complex128, device=H0.device).expand(npath, spec.nao, spec.nao).contiguous()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    pp.dyson(H0p, Sp, Sinf_p, Sig_p, mu, n_target=-1.0)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    pp.close()
+    return {"points": npath, "interpolation_ms": round((t1 - t0) * 1e3, 3), "dyson_ms": round((t3 - t2) * 1e3, 3)}
+
+
 def run_precision(system, prec, steps, warmup, chunk_bytes=0, tune=False, graph=False, accuracy_point=True,
-                  sample_max_bytes=1 << 30):
+                  sample_max_bytes=1 << 30, kpath_points=0):
     """Time `steps` iterations (after `warmup`) at one contraction precision; returns a summary dict."""
     import numpy as np
     import torch
@@ -150,6 +177,7 @@ def run_precision(system, prec, steps, warmup, chunk_bytes=0, tune=False, graph=
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     report = plan.tuning_report()
+    kpath = time_kpath(plan, system, H0, S, Sinf, Sig, mu, kpath_points) if kpath_points > 0 else None
     plan.close()
     del plan, H0, S, G, Sinf, Sig
     torch.cuda.empty_cache()
@@ -175,6 +203,7 @@ def run_precision(system, prec, steps, warmup, chunk_bytes=0, tune=False, graph=
         "last": reps[-1],
         "first": first,
         "tune_iterations": tuned,
+        "kpath": kpath,
         "kernel_names": [clocked_kernel_name("P0_Contract", prec, report, spec.naux, spec.nao),
                          clocked_kernel_name("Sig_PV", prec, report, spec.naux, spec.nao)],
     }
@@ -396,6 +425,9 @@ def main():
                     help="skip the FP64 reference run (profiling runs of one precision; no accuracy fields)")
     ap.add_argument("--chunk-mib", type=int, default=0,
                     help="workspace bound for the contraction intermediates (0: library default)")
+    ap.add_argument("--kpath", type=int, default=0,
+                    help="after the timed steps, interpolate the self-energy onto this many k-path points and "
+                         "solve Dyson there (Sec. 2.4 post-processing), timed separately")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -436,7 +468,8 @@ def main():
     side = torch.cuda.Stream() if args.graph else torch.cuda.current_stream()
     with torch.cuda.stream(side):
         res = {p: run_precision(system, p, args.steps, args.warmup, args.chunk_mib << 20, tune=args.tune,
-                                graph=args.graph, accuracy_point=not args.no_reference) for p in precs}
+                                graph=args.graph, accuracy_point=not args.no_reference,
+                                kpath_points=args.kpath) for p in precs}
     if args.save_sample:
         np.savez(args.save_sample, **{f"{p}_{k}": np.asarray(v) for p, r in res.items() for k, v in r["first"].items()},
                  **{f"{p}_s_per_iteration": r["s_per_iteration"] for p, r in res.items()})
@@ -490,7 +523,8 @@ def main():
                            "p0_contraction_mfma_frac": round(r["kern"][0]["tflops"] * MFMA_PER_ALG[p]
                                                              / PEAK_TFLOPS[p], 4),
                            "sigma_contraction_mfma_frac": round(r["kern"][1]["tflops"] * MFMA_PER_ALG[p]
-                                                                / PEAK_TFLOPS[p], 4)}
+                                                                / PEAK_TFLOPS[p], 4),
+                           **({"kpath": r["kpath"]} if r["kpath"] else {})}
                        for p, r in res.items()},
         "energy": {"e_tot": h["last"]["e_tot"], "e_corr": h["last"]["e_corr"], "mu": h["last"]["mu"],
                    "n_elec": h["last"]["n_elec"], "max_dsigma": h["last"]["max_dsigma"]},

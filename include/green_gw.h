@@ -174,6 +174,21 @@ int green_hf_static(green_plan* plan, const void* V, const void* G, void* Sinf, 
 int green_dyson(green_plan* plan, const void* H0, const void* S, const void* Sinf, const void* Sigma, double n_target,
                 double* mu, void* G, double* n_out, int32_t* evals_out, void* ws, void* stream);
 
+/* k-path interpolation of the self-energy (Sec. 2.4, k-path interpolation): every momentum-dependent input
+ * X(k) on the plan's Monkhorst-Pack mesh is taken to real space, X(R) = (1/nk) sum_k X(k) e^{-i k.R}, and
+ * back onto the npath points khat, X(khat) = sum_R X(R) e^{i khat.R}, for X = Sinf and Sigma~(tau_t).
+ * R runs over the lattice vectors of the Born-von Karman supercell centred on 0 (-n/2 .. n/2 per direction
+ * of mesh extent n); at an even n the zone-boundary terms R = -n/2 and +n/2 carry weight 1/2 each, so the
+ * interpolant reproduces the mesh values at mesh points.  kfrac: host [npath][3], fractional coordinates of
+ * khat (k.R = 2 pi sum_d kfrac_d R_d; mesh point (a, b, c) is (a/n0, b/n1, c/n2)).
+ * Inputs Sinf [nspin][nk][nao][nao], Sigma [nspin][ntau][nk][nao][nao]; outputs Sinf_path
+ * [nspin][npath][nao][nao], Sigma_path [nspin][ntau][npath][nao][nao] (device).  The Green's function on the
+ * path follows from green_dyson on a plan whose mesh is (npath, 1, 1), with H0 and S evaluated on the path by
+ * the caller and n_target < 0 (the chemical potential of the mesh calculation kept).  npath * nk * 16 bytes
+ * must fit the plan's contraction workspace.  Synchronises `stream`. */
+int green_kpath_interpolate(green_plan* plan, const double* kfrac, int npath, const void* Sinf, const void* Sigma,
+                            void* Sinf_path, void* Sigma_path, void* ws, void* stream);
+
 /* One self-consistent iteration (Sec. 2.3):
  *   (1) Sinf_new = HF(G), Sigma_new = GW(G) [polarization, screen, selfenergy];
  *   (2) mixing Sinf = alpha Sinf_new + (1-alpha) Sinf, Sigma = alpha Sigma_new + (1-alpha) Sigma

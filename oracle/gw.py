@@ -20,6 +20,8 @@ with plain NumPy matrix products, in complex128:
   O11 Dyson G(i omega) and G(tau)                            (Eq. dyson)
   O12 Galitskii-Migdal energy (diagnostic; the paper names total energies
       but prints no formula)
+  O13 k-path interpolation of Sigma^inf and Sigma~ (Sec. 2.4): to real
+      space over the mesh, back onto arbitrary k
 
 Readings of the text (each listed with its reason in the design notes):
   * G1  In Eq. tilde_P0_tau the factor G^k(-tau) is the stored value at
@@ -386,6 +388,41 @@ def energy(G: np.ndarray, H0: np.ndarray, Sinf: np.ndarray, Sig: np.ndarray, bet
 
 
 # --------------------------------------------------------------------------- one iteration
+# --------------------------------------------------------------------------- O13: k-path interpolation
+def lattice_vectors(kmesh):
+    """Reading K1 of Sec. 2.4: the lattice vectors R of the Born-von Karman supercell centred on 0, with the
+    weight of each; along a direction of even mesh extent n the zone-boundary vectors R = -n/2 and +n/2 both
+    appear with weight 1/2 (the sum of the weights along a direction is n)."""
+    axes = []
+    for n in kmesh:
+        h = n // 2
+        axes.append([(R, 0.5 if (n % 2 == 0 and abs(R) == h) else 1.0) for R in range(-h, h + 1)
+                     if n % 2 == 0 or abs(R) <= h])
+    return [((a, b, c), wa * wb * wc) for a, wa in axes[0] for b, wb in axes[1] for c, wc in axes[2]]
+
+
+def kpath_interpolate(X: np.ndarray, kmesh, kfrac) -> np.ndarray:
+    """O13, Sec. 2.4: X(R) = (1/N_k) sum_k X(k) e^{-i k.R}, then X(khat) = sum_R X(R) e^{i khat.R}.
+
+    X: [..., nk, nao, nao] on the mesh (mesh point (a, b, c) = fractional (a/n0, b/n1, c/n2)); kfrac:
+    [npath][3] fractional coordinates; k.R = 2 pi sum_d k_d R_d.  Returns [..., npath, nao, nao]."""
+    km = KMesh(kmesh)
+    nk = len(km.pts)
+    kf = np.asarray(kfrac, dtype=np.float64).reshape(-1, 3)
+    kpts = np.array([[a / kmesh[0], b / kmesh[1], c / kmesh[2]] for (a, b, c) in km.pts])
+    out_shape = X.shape[:-3] + (kf.shape[0],) + X.shape[-2:]
+    out = np.zeros(out_shape, dtype=np.complex128)
+    for R, w in lattice_vectors(kmesh):
+        Rv = np.array(R, dtype=np.float64)
+        XR = np.zeros(X.shape[:-3] + X.shape[-2:], dtype=np.complex128)
+        for k in range(nk):
+            XR += X[..., k, :, :] * np.exp(-2j * np.pi * (kpts[k] @ Rv))
+        XR /= nk
+        for p in range(kf.shape[0]):
+            out[..., p, :, :] += w * XR * np.exp(2j * np.pi * (kf[p] @ Rv))
+    return out
+
+
 @dataclasses.dataclass
 class State:
     G: np.ndarray

@@ -78,7 +78,7 @@ EXPORTS = ["green_plan_create", "green_plan_destroy", "green_workspace_bytes", "
            "green_gw_screen", "green_gw_selfenergy", "green_hf_static", "green_dyson", "green_gw_iterate",
            "green_plan_set_option", "green_plan_tuning_report", "green_batch_workspace_bytes",
            "green_gw_iterate_batched", "green_batch_create", "green_batch_iterate", "green_batch_destroy",
-           "green_diis_history_bytes", "green_gw_iterate_diis",
+           "green_diis_history_bytes", "green_gw_iterate_diis", "green_kpath_interpolate",
            "green_strerror"]
 
 
@@ -106,6 +106,8 @@ def _load():
     lib.green_dyson.argtypes = [vp, vp, vp, vp, vp, dbl, ctypes.POINTER(dbl), vp, ctypes.POINTER(dbl),
                                 ctypes.POINTER(ctypes.c_int32), vp, vp]
     lib.green_dyson.restype = i32
+    lib.green_kpath_interpolate.argtypes = [vp, ctypes.POINTER(dbl), i32, vp, vp, vp, vp, vp, vp]
+    lib.green_kpath_interpolate.restype = i32
     lib.green_gw_iterate.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(dbl), dbl, dbl,
                                      ctypes.POINTER(Report), vp, vp]
     lib.green_gw_iterate.restype = i32

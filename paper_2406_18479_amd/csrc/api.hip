@@ -1422,6 +1422,77 @@ int green_dyson(green_plan* p, const void* H0, const void* S, const void* Sinf, 
   return run_dyson(p, H0, S, Sinf, Sigma, n_target, mu, G, n_out, evals_out, ws, s);
 }
 
+// ---------------------------------------------------------------- k-path interpolation (Sec. 2.4)
+// W[p][k] = (1/N_k) sum_R w(R) exp(2 pi i (khat_p - k) . R) over the R of the Born-von Karman supercell centred
+// on 0; at an even mesh extent the zone-boundary term is split evenly between R = -n/2 and +n/2 (w = 1/2).
+// The sum factorises over the three directions.
+static void kpath_weights(const int32_t* mesh, const double* kfrac, int npath, std::vector<double2>& W) {
+  const int nk = mesh[0] * mesh[1] * mesh[2];
+  W.assign((size_t)npath * nk, make_double2(0.0, 0.0));
+  std::vector<double2> f[3];
+  for (int p = 0; p < npath; ++p) {
+    for (int d = 0; d < 3; ++d) {
+      const int n = mesh[d];
+      f[d].assign(n, make_double2(0.0, 0.0));
+      for (int m = 0; m < n; ++m) {
+        double re = 0.0, im = 0.0;
+        for (int R = -(n / 2); R <= n / 2; ++R) {
+          const double w = (n % 2 == 0 && (R == n / 2 || R == -(n / 2))) ? 0.5 : 1.0;
+          const double ph = 2.0 * M_PI * (kfrac[3 * p + d] - (double)m / n) * R;
+          re += w * std::cos(ph);
+          im += w * std::sin(ph);
+        }
+        f[d][m] = make_double2(re / n, im / n);
+      }
+    }
+    for (int a = 0; a < mesh[0]; ++a)
+      for (int b = 0; b < mesh[1]; ++b)
+        for (int c = 0; c < mesh[2]; ++c) {
+          const double2 x = f[0][a], y = f[1][b], z = f[2][c];
+          const double2 xy = make_double2(x.x * y.x - x.y * y.y, x.x * y.y + x.y * y.x);
+          W[(size_t)p * nk + (a * mesh[1] + b) * mesh[2] + c] =
+              make_double2(xy.x * z.x - xy.y * z.y, xy.x * z.y + xy.y * z.x);
+        }
+  }
+}
+
+int green_kpath_interpolate(green_plan* p, const double* kfrac, int npath, const void* Sinf, const void* Sigma,
+                            void* Sinf_path, void* Sigma_path, void* ws, void* stream) {
+  GREEN_TRY(check_plan(p, ws));
+  if (!kfrac || npath <= 0 || !Sinf || !Sigma || !Sinf_path || !Sigma_path) return GREEN_EINVAL;
+  for (int i = 0; i < 3 * npath; ++i)
+    if (!std::isfinite(kfrac[i])) return GREEN_EINVAL;
+  const green_dims& d = p->d;
+  const int nk = p->nk, ns = d.nspin, ntau = d.ntau;
+  const int64_t nG = (int64_t)d.nao * d.nao;
+  if ((size_t)npath * nk * sizeof(double2) > p->r_T1.bytes) return GREEN_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PlanScope scope(p);
+  GREEN_TRY(ensure_bound(p, ws, s));
+  std::vector<double2> W;
+  kpath_weights(d.kmesh, kfrac, npath, W);
+  double2* Wd = at<double2>(ws, p->r_T1);
+  if (!green::dryrun()) {
+    HIP_TRY(hipMemcpyAsync(Wd, W.data(), W.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+  }
+  const Extents ex = extents(p);
+  const green::Span sW = span_ws(ws, p->r_T1);
+  const int64_t pathG = (int64_t)npath * nG;
+  // Sinf_path[s][p] = sum_k W[p][k] Sinf[s][k]
+  GREEN_TRY(gemm(green::Site::Transform, "kpath.Sinf", op(Wd, flat(nk), flat(1), bnone()), sW,
+                 op(Sinf, flat(nG), flat(1), bflat((int64_t)nk * nG)), span(Sinf, ex.H), Sinf_path,
+                 span(Sinf_path, (int64_t)ns * pathG), flat(nG), flat(1), bflat(pathG), npath, (int)nG, nk, ns,
+                 cplx(1), cplx(0), s));
+  // Sigma_path[s][t][p] = sum_k W[p][k] Sigma~[s][t][k]
+  GREEN_TRY(gemm(green::Site::Transform, "kpath.Sigma", op(Wd, flat(nk), flat(1), bnone()), sW,
+                 op(Sigma, flat(nG), flat(1), bflat((int64_t)nk * nG)), span(Sigma, ex.Sig), Sigma_path,
+                 span(Sigma_path, (int64_t)ns * ntau * pathG), flat(nG), flat(1), bflat(pathG), npath, (int)nG,
+                 nk, ns * ntau, cplx(1), cplx(0), s));
+  if (green::dryrun()) return GREEN_OK;
+  HIP_TRY(hipStreamSynchronize(s));  // W lives in the workspace only for this call
+  return GREEN_OK;
+}
+
 int green_gw_iterate(green_plan* p, const void* V, const void* H0, const void* S, void* G, void* Sinf, void* Sigma,
                      double* mu, double n_target, double alpha, green_report* rep, void* ws, void* stream) {
   GREEN_TRY(check_plan(p, ws));

@@ -147,6 +147,23 @@ class Plan:
                                         ctypes.byref(ev), self.ws.data_ptr(), _stream(self.device)), "green_dyson")
         return G, m.value, n.value, ev.value
 
+    def kpath_interpolate(self, kfrac, Sinf, Sigma):
+        """Sinf and Sigma~(tau) interpolated from the mesh onto the points kfrac ([npath][3] fractional
+        coordinates); returns (Sinf_path [nspin][npath][nao][nao], Sigma_path [nspin][ntau][npath][nao][nao]).
+        The Green's function on the path: dyson() of a plan with kmesh (npath, 1, 1)."""
+        import numpy as np
+        kf = np.ascontiguousarray(np.asarray(kfrac, dtype=np.float64).reshape(-1, 3))
+        npath = kf.shape[0]
+        ns, nt, nao = self.nspin, self.ntau, self.nao
+        Sinf_p = torch.empty((ns, npath, nao, nao), dtype=torch.complex128, device=self.device)
+        Sig_p = torch.empty((ns, nt, npath, nao, nao), dtype=torch.complex128, device=self.device)
+        _lib.check(_lib.LIB.green_kpath_interpolate(
+            self._h, kf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), npath,
+            _ptr(Sinf, self.shape_H, "Sinf", self.device), _ptr(Sigma, self.shape_G, "Sigma", self.device),
+            Sinf_p.data_ptr(), Sig_p.data_ptr(), self.ws.data_ptr(), _stream(self.device)),
+            "green_kpath_interpolate")
+        return Sinf_p, Sig_p
+
     def iterate_diis(self, diis, V, H0, S, G, Sinf, Sigma, mu, n_target, alpha=1.0):
         """One iteration with DIIS (a DiisState of this plan); G, Sinf, Sigma updated in place."""
         m = ctypes.c_double(mu)

@@ -155,3 +155,21 @@ def test_diis_iteration_in_bounds_and_argument_checks(lib):
                                        hist, need, ctypes.byref(rep), ws, None) == -1
     finally:
         lib.LIB.green_plan_destroy(h)
+
+
+def test_kpath_interpolation_in_bounds_and_argument_checks(lib):
+    """k-path interpolation: both contractions validated against their buffers; bad arguments rejected."""
+    L = lib.LIB
+    for c in (CASES[1], CASES[4]):
+        h = _plan(lib, c, 0)
+        try:
+            Sinf, Sig, Sp, Sgp, ws = [BASE + i * STEP for i in range(5)]
+            npath = 40
+            k = (ctypes.c_double * (3 * npath))(*[0.01 * i for i in range(3 * npath)])
+            assert L.green_kpath_interpolate(h, k, npath, Sinf, Sig, Sp, Sgp, ws, None) == 0
+            assert L.green_kpath_interpolate(h, k, 0, Sinf, Sig, Sp, Sgp, ws, None) == -1
+            assert L.green_kpath_interpolate(h, k, npath, None, Sig, Sp, Sgp, ws, None) == -1
+            k[5] = float("nan")
+            assert L.green_kpath_interpolate(h, k, npath, Sinf, Sig, Sp, Sgp, ws, None) == -1
+        finally:
+            L.green_plan_destroy(h)

@@ -465,3 +465,58 @@ def test_diis_iteration_converges_faster_than_plain():
     n_diis, rd = run(s, True)
     assert n_plain > 25 and rp["max_dsigma"] > 1e-3
     assert n_diis <= 25
+
+
+# ----------------------------------------------------------------------------------------------- k-path
+@pytest.mark.parametrize("kmesh", [(2, 3, 1), (4, 1, 3)])
+def test_kpath_interpolation_reproduces_mesh_values(kmesh):
+    """At mesh points the interpolant of Sec. 2.4 (R over the centred supercell, zone-boundary terms split)
+    returns the mesh values exactly."""
+    rng = np.random.default_rng(11)
+    nk = int(np.prod(kmesh))
+    X = rng.normal(size=(2, nk, 3, 3)) + 1j * rng.normal(size=(2, nk, 3, 3))
+    pts = [(a / kmesh[0], b / kmesh[1], c / kmesh[2]) for a in range(kmesh[0]) for b in range(kmesh[1])
+           for c in range(kmesh[2])]
+    Y = gw.kpath_interpolate(X, kmesh, pts)
+    assert np.max(np.abs(Y - X)) < 1e-13
+
+
+@pytest.mark.parametrize("kmesh", [(3, 3, 1), (4, 4, 2)])
+def test_kpath_interpolation_exact_for_band_limited_functions(kmesh):
+    """X(k) = sum_R C_R e^{2 pi i k.R} with every R strictly inside the supercell is interpolated exactly at
+    arbitrary k (closed form)."""
+    rng = np.random.default_rng(12)
+    Rs = [R for R in itertools.product(*[range(-((n - 1) // 2), (n - 1) // 2 + 1) for n in kmesh])
+          if all(abs(r) < n / 2 for r, n in zip(R, kmesh))]
+    C = {R: rng.normal(size=(2, 2)) + 1j * rng.normal(size=(2, 2)) for R in Rs}
+
+    def f(k):
+        return sum(C[R] * np.exp(2j * np.pi * np.dot(k, R)) for R in Rs)
+    mesh = [(a / kmesh[0], b / kmesh[1], c / kmesh[2]) for a in range(kmesh[0]) for b in range(kmesh[1])
+            for c in range(kmesh[2])]
+    X = np.stack([f(np.array(k)) for k in mesh])
+    path = rng.uniform(-1.0, 1.0, size=(9, 3))
+    Y = gw.kpath_interpolate(X, kmesh, path)
+    ref = np.stack([f(k) for k in path])
+    assert np.max(np.abs(Y - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_kpath_interpolation_against_fft():
+    """The real-space coefficients X(R) = (1/N_k) sum_k X(k) e^{-i k.R} are NumPy's forward FFT over the mesh
+    axes divided by N_k; summing them back with the boundary weights matches the oracle at arbitrary k."""
+    kmesh = (4, 3, 2)
+    rng = np.random.default_rng(13)
+    nk = int(np.prod(kmesh))
+    X = rng.normal(size=(nk, 2, 2)) + 1j * rng.normal(size=(nk, 2, 2))
+    XR = np.fft.fftn(X.reshape(kmesh + (2, 2)), axes=(0, 1, 2)) / nk  # index R mod n
+    path = rng.uniform(0.0, 1.0, size=(5, 3))
+    ref = np.zeros((5, 2, 2), dtype=complex)
+    for R in itertools.product(*[range(-(n // 2), n // 2 + 1) for n in kmesh]):
+        w = np.prod([0.5 if (n % 2 == 0 and abs(r) == n // 2) else 1.0 for r, n in zip(R, kmesh)])
+        if any(n % 2 == 1 and abs(r) > n // 2 for r, n in zip(R, kmesh)):
+            continue
+        idx = tuple(r % n for r, n in zip(R, kmesh))
+        for p in range(5):
+            ref[p] += w * XR[idx] * np.exp(2j * np.pi * np.dot(path[p], R))
+    Y = gw.kpath_interpolate(X, kmesh, path)
+    assert np.max(np.abs(Y - ref)) < 1e-13 * np.max(np.abs(ref))
