@@ -22,14 +22,19 @@ with plain NumPy matrix products, in complex128:
       but prints no formula)
   O13 k-path interpolation of Sigma^inf and Sigma~ (Sec. 2.4): to real
       space over the mesh, back onto arbitrary k
+  O14 GF2 second-order self-energy, direct minus exchange    (Eq. sigma2)
 
 Readings of the text (each listed with its reason in the design notes):
   * G1  In Eq. tilde_P0_tau the factor G^k(-tau) is the stored value at
         beta - tau.  With the antiperiodic G(-tau) = -G(beta-tau) fixed by
         Eq. dos_tau the printed sign would anti-screen; read this way the
         bubble equals the direct term of Eq. sigma2 (pinned in the tests).
+  * G2  In Eq. sigma2 the momentum delta is Nk times a Kronecker delta, so
+        the prefactor is effectively 1/Nk^2 (as in Eqs. sigma_gw and
+        tilde_P0_tau); G(-tau) there is the antiperiodic -G(beta - tau).
   * G3  Spin-restricted runs (nspin = 1) hold one spin channel; the spin sums
-        in Eq. tilde_P0_tau and in the Hartree term become a factor 2.
+        in Eq. tilde_P0_tau, the Hartree term and the direct term of Eq.
+        sigma2 become a factor 2.
   * G7  The frequency -> tau maps are the grid's least-squares inverses.
   * G8  Node 0 is tau = 0^+, node ntau-1 is beta^-, G(0^-) = -G(beta^-).
   * G9  The one-body term of Eq. dyson is H^(0); Sigma^inf is recomputed
@@ -222,6 +227,54 @@ def selfenergy(V: np.ndarray, G: np.ndarray, Pt: np.ndarray, kmesh, ts=None, ks=
                     Ycat = np.swapaxes(Y, 0, 1).reshape(nao, naux * nao)  # [i][(Q', b)]
                     out[s, it, ik] += Ycat @ Bcat
     out *= -1.0 / nk
+    return out
+
+
+# --------------------------------------------------------------------------- O14
+def gf2_selfenergy(V: np.ndarray, G: np.ndarray, kmesh, ts=None, ks=None) -> np.ndarray:
+    """O14, Eq. sigma2 with reading G2 (prefactor 1/Nk^2, k3 = k1 + k2 - k, G(-tau) = -G(beta - tau)):
+
+    Sigma~(2)^k_{s,ij}(tau) = -(1/Nk^2) sum_{k1 k2} sum_{QQ'} [direct - exchange]_{ij}
+      direct   = sum_{s'} [V^{k k1}(Q) G^{k1}_s(tau) V^{k1 k}(Q')]
+                          * Tr[V^{k3 k2}(Q) G^{k2}_{s'}(tau) V^{k2 k3}(Q') G^{k3}_{s'}(-tau)]
+      exchange = V^{k k1}(Q) G^{k1}_s(tau) V^{k1 k3}(Q') G^{k3}_s(-tau) V^{k3 k2}(Q) G^{k2}_s(tau) V^{k2 k}(Q')
+    (the orbital sums of Eq. sigma2 written as matrix products and a trace; the spin sum of the direct
+    term doubled for a restricted run).  For every (Q, Q') the matrix chain is formed whole and the pairs
+    are summed last.  Returns Sigma[s][t][k][i][j] over ts x ks.
+    """
+    km = KMesh(kmesh)
+    ns, ntau, nk, nao, _ = G.shape
+    ts = list(range(ntau)) if ts is None else list(ts)
+    ks = list(range(nk)) if ks is None else list(ks)
+    w = spin_weight(ns)
+    out = np.zeros((ns, len(ts), len(ks), nao, nao), dtype=np.complex128)
+    for ik, k in enumerate(ks):
+        for k1 in range(nk):
+            for k2 in range(nk):
+                k3 = km.sub(km.add(k1, k2), k)
+                Va = V_pair(V, km, k, k1)    # V^{k k1}(Q)
+                Vb = V_pair(V, km, k1, k)    # V^{k1 k}(Q')
+                Vc = V_pair(V, km, k3, k2)   # V^{k3 k2}(Q)
+                Vd = V_pair(V, km, k2, k3)   # V^{k2 k3}(Q')
+                Ve = V_pair(V, km, k1, k3)   # V^{k1 k3}(Q')
+                Vf = V_pair(V, km, k2, k)    # V^{k2 k}(Q')
+                for it, t in enumerate(ts):
+                    tm = ntau - 1 - t  # beta - tau on the symmetric grid
+                    # bubble Tr[V^{k3 k2}(Q) G^{k2}(tau) V^{k2 k3}(Q') G^{k3}(-tau)], summed over spins
+                    D = np.zeros((V.shape[2], V.shape[2]), dtype=np.complex128)
+                    for sp in range(ns):
+                        L = np.matmul(Vc, G[sp, t, k2])          # [Q][m][l]
+                        R = np.matmul(Vd, -G[sp, tm, k3])        # [Q'][l][m]
+                        D += w * np.einsum("Qml,Plm->QP", L, R)
+                    for s in range(ns):
+                        A1 = np.matmul(Va, G[s, t, k1])                        # [Q][i][q]
+                        direct = np.matmul(A1[:, None], Vb[None, :])           # [Q][Q'][i][j]
+                        direct = np.einsum("QP,QPij->ij", D, direct)
+                        ch = np.matmul(A1[:, None], np.matmul(Ve, -G[s, tm, k3])[None, :])  # [Q][Q'][i][m]
+                        ch = np.matmul(ch, np.matmul(Vc, G[s, t, k2])[:, None])            # [Q][Q'][i][l]
+                        ch = np.matmul(ch, Vf[None, :])                                   # [Q][Q'][i][j]
+                        out[s, it, ik] += direct - ch.sum(axis=(0, 1))
+    out *= -1.0 / nk ** 2
     return out
 
 

@@ -284,6 +284,130 @@ def test_two_level_worked_example():
     assert abs(E["e_corr"] - (-2.0 * v ** 4 / (ea - ei))) < 1e-11
 
 
+@pytest.mark.parametrize("kmesh,nspin,nao", [((1, 1, 1), 1, 3), ((3, 1, 1), 2, 2), ((2, 2, 1), 1, 2)])
+def test_gf2_brute_force(kmesh, nspin, nao):
+    """Eq. sigma2 as printed, with explicit loops over every momentum, orbital, spin and auxiliary index,
+    the lattice delta read as Nk times a Kronecker delta and G(-tau) = -G(beta - tau)."""
+    sp = configs.tiny(kmesh=kmesh, nao=nao, naux=2, ntau=6, beta=3.0, nspin=nspin, seed=83)
+    s = systems.make_system(sp)
+    km = _km(kmesh)
+    G = systems.random_green(19, nspin, sp.ntau, sp.nk, nao, scale=0.4)
+    nk, ntau = sp.nk, sp.ntau
+    Sig = gw.gf2_selfenergy(s.V, G, kmesh)
+    spins = [(sq, 1.0) for sq in range(nspin)] if nspin == 2 else [(0, 1.0), (0, 1.0)]  # sigma' channels
+    for sig, k, t in [(0, 0, 1), (nspin - 1, nk - 1, 4), (0, nk // 2, 0)]:
+        ref = np.zeros((nao, nao), dtype=complex)
+        for k1, k2, k3 in itertools.product(range(nk), repeat=3):
+            if km.add(k, k3) != km.add(k1, k2):
+                continue
+            for Q, Qp in itertools.product(range(sp.naux), repeat=2):
+                V1 = gw.V_pair(s.V, km, k1, k)[Qp]   # V^{k1 k}_{qj}(Q')
+                V2 = gw.V_pair(s.V, km, k2, k3)[Qp]  # V^{k2 k3}_{ln}(Q')
+                V3 = gw.V_pair(s.V, km, k2, k)[Qp]   # V^{k2 k}_{lj}(Q')
+                V4 = gw.V_pair(s.V, km, k1, k3)[Qp]  # V^{k1 k3}_{qn}(Q')
+                V5 = gw.V_pair(s.V, km, k, k1)[Q]    # V^{k k1}_{ip}(Q)
+                V6 = gw.V_pair(s.V, km, k3, k2)[Q]   # V^{k3 k2}_{mk}(Q)
+                for ic, (sp2, _) in enumerate(spins):
+                    same = (ic == 0) if nspin == 1 else (sp2 == sig)
+                    G1 = G[sig, t, k1]
+                    G2 = G[sp2, t, k2]
+                    G3 = -G[sp2, ntau - 1 - t, k3]  # G^{k3}_{sigma'}(-tau)
+                    for i, j in itertools.product(range(nao), repeat=2):
+                        acc = 0.0
+                        for kk, l, m, n, p_, qq in itertools.product(range(nao), repeat=6):
+                            bra = V1[qq, j] * V2[l, n] - (V3[l, j] * V4[qq, n] if same else 0.0)
+                            acc += bra * V5[i, p_] * V6[m, kk] * G1[p_, qq] * G2[kk, l] * G3[n, m]
+                        ref[i, j] += acc
+        ref *= -nk / nk ** 3  # 1/Nk^3 times the lattice delta Nk
+        assert np.allclose(Sig[sig, t, k], ref, atol=1e-15, rtol=1e-12)
+
+
+def test_gf2_single_orbital_closed_form():
+    """One orbital, one k, restricted: the exchange term is half the direct one, so
+    Sigma~(2)(tau) = -u^2 G(tau)^2 G(-tau) = u^2 G(tau)^2 G(beta - tau) with u = sum_Q V_Q^2."""
+    sp = configs.tiny(kmesh=(1, 1, 1), nao=1, naux=3, ntau=8, beta=4.0, seed=5)
+    s = systems.make_system(sp)
+    G = systems.random_green(23, 1, sp.ntau, 1, 1, scale=0.5)
+    Sig = gw.gf2_selfenergy(s.V, G, (1, 1, 1))
+    u = np.sum(s.V[0, 0, :, 0, 0] ** 2)
+    g = G[0, :, 0, 0, 0]
+    ref = u ** 2 * g ** 2 * g[::-1]
+    assert np.allclose(Sig[0, :, 0, 0, 0], ref, atol=1e-15, rtol=1e-12)
+
+
+def _gapped_molecule(seed=3):
+    rng = np.random.default_rng(seed)
+    e = np.array([-0.9, -0.55, -0.3, 0.3, 0.6, 1.0])
+    n = len(e)
+    U = np.linalg.qr(rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n)))[0]
+    H0 = ((U * e) @ U.conj().T)[None, None]
+    Z = (rng.normal(size=(4, n, n)) + 1j * rng.normal(size=(4, n, n))) * 0.1
+    V = (0.5 * (Z + np.conj(np.swapaxes(Z, 1, 2))))[None, None]
+    return e, U, H0, V
+
+
+def test_gf2_mp2_limit():
+    """Gapped G0, Nk = 1, beta = 100: E_corr[Sigma(2)[G0], G0] -> 2 E_MP2 with the exchange term,
+    E_MP2 = sum_{ij occ, ab virt} (ia|jb) [2 (ai|bj) - (bi|aj)] / (e_i + e_j - e_a - e_b),
+    (pq|rs) = sum_Q V_pq(Q) V_rs(Q) in the eigenbasis of H0."""
+    beta, ntau = 100.0, 104
+    g = gridmod.make_grid(ntau, beta)
+    e, U, H0, V = _gapped_molecule()
+    n = len(e)
+    S = np.eye(n, dtype=complex)[None]
+    G0 = systems.noninteracting_G(H0, S, g.tau, beta, 0.0)
+    Sig = gw.gf2_selfenergy(V, G0, (1, 1, 1))
+    E = gw.energy(G0, H0, np.zeros_like(H0), Sig, beta)
+    Vmo = np.einsum("ia,Qij,jb->Qab", U.conj(), V[0, 0], U)
+    occ, vir = [0, 1, 2], [3, 4, 5]
+    emp2 = 0.0
+    for i, j, a, b in itertools.product(occ, occ, vir, vir):
+        iajb = np.sum(Vmo[:, i, a] * Vmo[:, j, b])
+        aibj = np.sum(Vmo[:, a, i] * Vmo[:, b, j])
+        biaj = np.sum(Vmo[:, b, i] * Vmo[:, a, j])
+        emp2 += (iajb * (2.0 * aibj - biaj)).real / (e[i] + e[j] - e[a] - e[b])
+    assert abs(E["e_corr"] - 2.0 * emp2) < 1e-9 * abs(emp2) + 1e-13
+
+
+def test_gf2_two_level_worked_example():
+    """One occupied and one virtual level, one auxiliary function with V_ia = V_ai = v: the exchange term
+    cancels half of the direct one, E_corr -> -v^4 / (e_a - e_i) (twice MP2's -v^4 / (2 (e_a - e_i)))."""
+    beta, ntau = 100.0, 104
+    g = gridmod.make_grid(ntau, beta)
+    ei, ea, v = -0.5, 0.4, 0.3
+    H0 = np.diag([ei, ea]).astype(complex)[None, None]
+    V = np.array([[[0.0, v], [v, 0.0]]], dtype=complex)[None, None]
+    S = np.eye(2, dtype=complex)[None]
+    G0 = systems.noninteracting_G(H0, S, g.tau, beta, 0.0)
+    Sig = gw.gf2_selfenergy(V, G0, (1, 1, 1))
+    E = gw.energy(G0, H0, np.zeros_like(H0), Sig, beta)
+    assert abs(E["e_corr"] - (-v ** 4 / (ea - ei))) < 1e-11
+
+
+def test_gf2_direct_part_is_the_first_order_bubble():
+    """The direct part of Eq. sigma2 is the first-order bubble: Sigma(2) plus (1/Nk^2) times the exchange
+    part, the latter contracted from explicit four-index integrals (ab|cd) = sum_Q V_ab(Q) V_cd(Q), equals
+    O7 fed P~ := P0."""
+    sp = configs.tiny(kmesh=(2, 1, 1), nao=3, naux=4, ntau=6, beta=3.0, seed=29)
+    s = systems.make_system(sp)
+    km = _km(sp.kmesh)
+    G = systems.random_green(41, 1, sp.ntau, sp.nk, sp.nao, scale=0.4)
+    nk, ntau, nao = sp.nk, sp.ntau, sp.nao
+    Sig2 = gw.gf2_selfenergy(s.V, G, sp.kmesh)
+    first = gw.selfenergy(s.V, G, gw.polarization(s.V, G, sp.kmesh), sp.kmesh)
+    for k, t in [(0, 2), (1, 5)]:
+        ex = np.zeros((nao, nao), dtype=complex)
+        for k1, k2 in itertools.product(range(nk), repeat=2):
+            k3 = km.sub(km.add(k1, k2), k)
+            # four-index integrals (ab|cd) = sum_Q V_ab(Q) V_cd(Q) of the exchange chain
+            U1 = np.einsum("Qip,Qmk->ipmk", gw.V_pair(s.V, km, k, k1), gw.V_pair(s.V, km, k3, k2))
+            U2 = np.einsum("Qqn,Qlj->qnlj", gw.V_pair(s.V, km, k1, k3), gw.V_pair(s.V, km, k2, k))
+            ex += np.einsum("ipmk,qnlj,pq,kl,nm->ij", U1, U2, G[0, t, k1], G[0, t, k2],
+                            -G[0, ntau - 1 - t, k3])
+        # Sigma(2) = -(1/Nk^2)(direct - exchange)  =>  Sigma(2) - (1/Nk^2) exchange = first order
+        assert np.allclose(Sig2[0, t, k] - ex / nk ** 2, first[0, t, k], atol=1e-15, rtol=1e-12)
+
+
 def test_energy_integral_closed_form():
     """int_0^beta Tr[F(tau) H(beta - tau)] for F = e^{-x tau}, H = e^{-y tau} (1x1): closed form."""
     beta, ntau = 20.0, 64
