@@ -113,6 +113,56 @@ def time_kpath(plan, system, H0, S, Sinf, Sig, mu, npath):
     return {"points": npath, "interpolation_ms": round((t1 - t0) * 1e3, 3), "dyson_ms": round((t3 - t2) * 1e3, 3)}
 
 
+def gf2_flops(nk, nao, naux, ntau, nspin) -> float:
+    """Algorithmic real flops of one GF2 self-energy (Eq. sigma2): the direct term (the P~0 and Sigma~
+    contractions) plus the exchange term, per spin and tau node 2 nk^2 naux nao^3 (V G products) +
+    2 nk^3 naux nao^4 (auxiliary sums) + nk^3 nao^5 (final sum) complex MACs, x 8 (4M)."""
+    ex = nspin * ntau * (2 * nk * nk * naux * nao ** 3 + 2 * nk ** 3 * naux * nao ** 4 + nk ** 3 * nao ** 5)
+    return contraction_flops(nk, nao, naux, ntau, nspin) + 8.0 * ex
+
+
+def time_gf2(precs, steps, tune=True):
+    """GF2 self-energy (Eq. sigma2) on the 2x2x2 workload (nao 26, naux 180, ntau 104), inputs in HBM: each
+    precision tuned in one untimed call, then `steps` calls timed; the error of each precision against FP64."""
+    import numpy as np
+    import torch
+    from paper_2406_18479_amd.gw import Plan
+    from synth import configs, systems
+    from synth import device as dgen
+    spec = configs.PERIODIC_2
+    system = systems.make_system(spec, with_V=False)
+    V = dgen.make_V(spec, device="cuda:0")
+    G = torch.from_numpy(np.ascontiguousarray(system.G0)).to("cuda:0")
+    flops = gf2_flops(spec.nk, spec.nao, spec.naux, spec.ntau, spec.nspin)
+    out = {"workload": spec.name, "flops_per_call": flops, "precisions": {}}
+    ref = None
+    for prec in ["fp64"] + [p for p in precs if p != "fp64"]:
+        plan = Plan(spec.kmesh, spec.nao, spec.naux, system.grid, nspin=spec.nspin, prec=prec)
+        plan.set_option("gf2", 1)
+        Sig = torch.empty(plan.shape_G, dtype=torch.complex128, device="cuda:0")
+        if tune:
+            plan.set_option("tune", 1)
+            plan.gf2_selfenergy(V, G, Sig)
+            plan.set_option("tune", 0)
+        plan.gf2_selfenergy(V, G, Sig)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.gf2_selfenergy(V, G, Sig)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        r = {"ms_per_call": round(dt * 1e3, 3), "tflops": round(flops / dt / 1e12, 3)}
+        if ref is None:
+            ref = Sig.clone()
+        else:
+            r["max_dsigma_vs_fp64"] = float((Sig - ref).abs().max())
+        out["precisions"][prec] = r
+        print(f"[bench] GF2 {prec}: {r}", file=sys.stderr, flush=True)
+        del plan, Sig
+        torch.cuda.empty_cache()
+    return out
+
+
 def run_precision(system, prec, steps, warmup, chunk_bytes=0, tune=False, graph=False, accuracy_point=True,
                   sample_max_bytes=1 << 30, kpath_points=0):
     """Time `steps` iterations (after `warmup`) at one contraction precision; returns a summary dict."""
@@ -428,6 +478,9 @@ def main():
     ap.add_argument("--kpath", type=int, default=0,
                     help="after the timed steps, interpolate the self-energy onto this many k-path points and "
                          "solve Dyson there (Sec. 2.4 post-processing), timed separately")
+    ap.add_argument("--gf2", action="store_true",
+                    help="also time the GF2 self-energy (Eq. sigma2) on the 2x2x2 workload, each precision")
+    ap.add_argument("--gf2-only", action="store_true", help="time only the GF2 self-energy (prints its JSON)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -452,6 +505,10 @@ def main():
         del src, dst
     import torch
 
+    if args.gf2_only:
+        print(json.dumps({"gf2": time_gf2([p for p in args.precisions.split(",") if p], max(args.steps, 1),
+                                          tune=args.tune)}), flush=True)
+        return
     if args.workload == "batch16":
         print(json.dumps(run_batch(args)), flush=True)
         return
@@ -539,6 +596,11 @@ def main():
     if not args.no_cpu_baseline:
         system.V = system.V_dev.cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(system, args.cpu_baseline_seconds)
+    if args.gf2:
+        del res, h
+        system.V_dev = None
+        torch.cuda.empty_cache()
+        out["gf2"] = time_gf2(precs, max(args.steps, 1), tune=args.tune)
     print(json.dumps(out), flush=True)
 
 

@@ -155,6 +155,21 @@ int green_gw_screen(green_plan* plan, const void* P0, void* Pt, void* ws, void* 
 int green_gw_selfenergy(green_plan* plan, const void* V, const void* G, const void* Pt, void* Sigma, void* ws,
                         void* stream);
 
+/* GF2 second-order self-energy (Eq. sigma2), for plans with GREEN_OPT_GF2 set:
+ *   Sigma~(2)^k_{s,ij}(tau) = -(1/nk^2) sum_{k1,k2} sum_{QQ'} [direct - exchange]_{ij},   k3 = k1 + k2 - k,
+ *   direct   = sum_{s'} [V^{k,k1}(Q) G^{k1}_s(tau) V^{k1,k}(Q')] Tr[V^{k3,k2}(Q) G^{k2}_{s'}(tau) V^{k2,k3}(Q') G^{k3}_{s'}(-tau)],
+ *   exchange = V^{k,k1}(Q) G^{k1}_s(tau) V^{k1,k3}(Q') G^{k3}_s(-tau) V^{k3,k2}(Q) G^{k2}_s(tau) V^{k2,k}(Q'),
+ * with G(-tau) = -G(beta - tau) (antiperiodic), the momentum delta of Eq. sigma2 taken as nk times a Kronecker
+ * delta (hence 1/nk^2), and the spin sum of a restricted plan (nspin = 1) doubled.  The direct term is the
+ * first-order bubble: green_gw_polarization followed by green_gw_selfenergy with P~ := P~0.  The exchange term
+ * is contracted per tau node: the products V G of every momentum pair, then per triple (k, k1, k2) the
+ * auxiliary sums X = sum_Q [V G](Q) x [V G](Q) and Z = sum_Q' [V G(beta - tau)](Q') x V(Q') (nao^4 each), then
+ * sum over (k1, k2) and three orbitals of X Z; cost O(nk^3 ntau (naux nao^4 + nao^5)), in the plan's
+ * arithmetic (FP32 and split-BF16 plans round the operands of these contractions and accumulate in FP32).
+ * V, G: inputs (device).  Sigma: output [nspin][ntau][nk][nao][nao] (device, overwritten).  The P~0 region
+ * of ws is overwritten.  GREEN_EINVAL if GREEN_OPT_GF2 is not set.  Async. */
+int green_gf2_selfenergy(green_plan* plan, const void* V, const void* G, void* Sigma, void* ws, void* stream);
+
 /* Hartree-Fock static self-energy, Eq. sigma_inf, from G(0^-) = -G(beta^-):
  *   Sinf^k_s = (1/nk) sum_{k' s' Q} V^{k,k}(Q) Tr[G^{k'}_{s'}(0^-) V^{k',k'}(Q)]
  *            - (1/nk) sum_{k' Q} V^{k,k'}(Q) G^{k'}_s(0^-) V^{k',k}(Q)
@@ -190,7 +205,8 @@ int green_kpath_interpolate(green_plan* plan, const double* kfrac, int npath, co
                             void* Sinf_path, void* Sigma_path, void* ws, void* stream);
 
 /* One self-consistent iteration (Sec. 2.3):
- *   (1) Sinf_new = HF(G), Sigma_new = GW(G) [polarization, screen, selfenergy];
+ *   (1) Sinf_new = HF(G), Sigma_new = GW(G) [polarization, screen, selfenergy] (with GREEN_OPT_GF2:
+ *       Sigma_new = GF2(G) [polarization, selfenergy with P~ := P~0, exchange term]);
  *   (2) mixing Sinf = alpha Sinf_new + (1-alpha) Sinf, Sigma = alpha Sigma_new + (1-alpha) Sigma
  *       (alpha = 1: no mixing; Sinf / Sigma are read only when alpha != 1);
  *   (3) chemical potential for n_target (kept if n_target < 0);
@@ -248,15 +264,23 @@ int green_gw_iterate_diis(green_plan* plan, const void* V, const void* H0, const
  *                   1 = 192 x 96 (default), 2 = 192 x 64.
  *                   Both only change the summation blocking; results agree to rounding.
  *   GREEN_OPT_SIGMA_FUSED  split-BF16 plans with nao a multiple of 4 up to 64: 1 (default) runs the two contractions
- *                   of Eq. tilde_Sigma_tau after P~^T V (over the orbital a with G(tau), then over (Q', b)
+ *                   of Eqs. sigma_gw and tilde_W_DF2 after P~^T V (over the orbital a with G(tau), then over (Q', b)
  *                   with V) in one kernel that keeps their intermediate in registers; 0 runs them as two
  *                   contractions through HBM.  GREEN_EINVAL where the plan does not allow 1.
+ *   GREEN_OPT_GF2   1: the dynamic self-energy is the GF2 one of Eq. sigma2 (green_gf2_selfenergy) instead of
+ *                   GW: green_gw_iterate and green_gw_iterate_diis skip the screening and add the exchange
+ *                   term, and green_gf2_selfenergy is enabled.  The first time it is set the workspace grows
+ *                   by the GF2 intermediates (two nk^2 x naux x nao^2 products V G and two chunks of four-index
+ *                   products of nao^4 complex FP64 per momentum triple, each chunk at most chunk_bytes / 2 but
+ *                   at least one triple): query green_workspace_bytes after setting it and bind a workspace of
+ *                   that size.  0 (default): GW (the workspace keeps its size).
  * Returns GREEN_EINVAL for an unknown option or value. */
 #define GREEN_OPT_TUNE 1
 #define GREEN_OPT_GRAPH 2
 #define GREEN_OPT_P0_TILE 3
 #define GREEN_OPT_STAGE1_TILE 4
 #define GREEN_OPT_SIGMA_FUSED 5
+#define GREEN_OPT_GF2 6
 int green_plan_set_option(green_plan* plan, int option, int value);
 
 /* Text table of the autotuner's decisions into buf (host, len bytes, NUL-terminated; GREEN_ENOMEM when

@@ -484,9 +484,12 @@ class State:
     mu: float
 
 
-def sigma_eval(V, G, kmesh, grid):
-    """Sigma^inf and Sigma~ of G (steps O1 - O7); also returns the intermediates."""
+def sigma_eval(V, G, kmesh, grid, method="gw"):
+    """Sigma^inf and Sigma~ of G (steps O1 - O7; method "gf2": O14 in place of O3 - O7); also returns the
+    intermediates."""
     Sinf = sigma_inf(V, G, kmesh)
+    if method == "gf2":
+        return Sinf, gf2_selfenergy(V, G, kmesh), {}
     P0 = polarization(V, G, kmesh)
     Pw = to_bosonic(P0, grid.TB_t2w)
     Ptw = screen(Pw)
@@ -512,11 +515,12 @@ def solve_dyson(H0, S, Sinf, Sig, grid, nspin, mu0, n_target):
     return G, mu, n
 
 
-def iterate(system, state: State, alpha: float = 1.0):
-    """One self-consistency iteration (Sec. 2.3): Sigma[G], mixing, mu, Dyson, energy."""
+def iterate(system, state: State, alpha: float = 1.0, method: str = "gw"):
+    """One self-consistency iteration (Sec. 2.3): Sigma[G] (GW, or GF2 with method "gf2"), mixing, mu,
+    Dyson, energy."""
     sp = system.spec
     grid = system.grid
-    Sinf_new, Sig_new, inter = sigma_eval(system.V, state.G, sp.kmesh, grid)
+    Sinf_new, Sig_new, inter = sigma_eval(system.V, state.G, sp.kmesh, grid, method)
     Sinf = mix(Sinf_new, state.Sinf, alpha)
     Sig = mix(Sig_new, state.Sig, alpha)
     G, mu, n = solve_dyson(system.H0, system.S, Sinf, Sig, grid, sp.nspin, state.mu, system.n_target)

@@ -73,13 +73,14 @@ OPT_GRAPH = 2
 OPT_P0_TILE = 3
 OPT_STAGE1_TILE = 4
 OPT_SIGMA_FUSED = 5
+OPT_GF2 = 6
 
 EXPORTS = ["green_plan_create", "green_plan_destroy", "green_workspace_bytes", "green_gw_polarization",
            "green_gw_screen", "green_gw_selfenergy", "green_hf_static", "green_dyson", "green_gw_iterate",
            "green_plan_set_option", "green_plan_tuning_report", "green_batch_workspace_bytes",
            "green_gw_iterate_batched", "green_batch_create", "green_batch_iterate", "green_batch_destroy",
            "green_diis_history_bytes", "green_gw_iterate_diis", "green_kpath_interpolate",
-           "green_strerror"]
+           "green_gf2_selfenergy", "green_strerror"]
 
 
 def _load():
@@ -101,6 +102,8 @@ def _load():
     lib.green_gw_screen.restype = i32
     lib.green_gw_selfenergy.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.green_gw_selfenergy.restype = i32
+    lib.green_gf2_selfenergy.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.green_gf2_selfenergy.restype = i32
     lib.green_hf_static.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.green_hf_static.restype = i32
     lib.green_dyson.argtypes = [vp, vp, vp, vp, vp, dbl, ctypes.POINTER(dbl), vp, ctypes.POINTER(dbl),

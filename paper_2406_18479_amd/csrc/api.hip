@@ -60,6 +60,12 @@ struct green_plan {
                        // LDS-DMA 5 = 320 x 64, 6 = 192 x 128
                        // (set at plan creation from naux)
   bool fuse_sig = false;  // split-BF16 plans, nao % 4 == 0 and <= 64: Sigma~ stages 2 and 3 in one kernel
+  bool gf2 = false;       // the dynamic self-energy is GF2 (Eq. sigma2) instead of GW
+  size_t chunk_bytes = 0;
+  // GF2 exchange: per momentum triple (k, k1, k2), flattened ((k nk) + k1) nk + k2, the blocks of the V G
+  // products and of V it reads: [0] V^{k,k1} G^{k1}(tau), [1] V^{k1,k3} G^{k3}(beta - tau), [2] V^{k3,k2} G^{k2}(tau),
+  // [3] V^{k2,k}, with k3 = k1 + k2 - k (block index q nk + a of the pair V^{a,a+q})
+  std::vector<int32_t> g2tab;
   std::vector<double> tau, wf, wb;
   std::vector<double2> TF_t2w, TF_w2t, TB_t2w, TB_w2t, Emass;
   std::vector<int32_t> kadd, ksub, kneg;  // [q][k]: k+q, k-q; [q]: -q
@@ -67,6 +73,7 @@ struct green_plan {
   // workspace regions
   Region r_TF_t2w, r_TF_w2t, r_TB_t2w, r_TB_w2t, r_Emass, r_wf, r_kadd, r_ksub, r_qcan, r_status, r_scal, r_partial;
   Region r_P, r_Pw, r_T1, r_T2, r_gam, r_gamT, r_D, r_Sinfn, r_Sign, r_Sw, r_A, r_tr, r_split, r_Vx, r_Ptx, r_Gx, r_GTx;
+  Region r_g2tab, r_Fp, r_Fm, r_X2, r_Z2;  // GF2 (empty until GREEN_OPT_GF2 is set)
   size_t ws_bytes = 0;
   void* bound_ws = nullptr;
   hipEvent_t ev[kNumEvents]{};
@@ -191,6 +198,7 @@ int ensure_bound(green_plan* p, void* ws, hipStream_t s) {
   HIP_TRY(up(p->r_kadd, p->kadd.data()));
   HIP_TRY(up(p->r_ksub, p->ksub.data()));
   HIP_TRY(up(p->r_qcan, p->qcan.data()));
+  if (p->r_g2tab.bytes) HIP_TRY(up(p->r_g2tab, p->g2tab.data()));
   HIP_TRY(hipMemsetAsync(static_cast<char*>(ws) + p->r_status.off, 0, p->r_status.bytes, s));
   HIP_TRY(hipStreamSynchronize(s));
   p->bound_ws = ws;
@@ -788,6 +796,120 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
   return GREEN_OK;
 }
 
+// ---------------------------------------------------------------- GF2 exchange term
+// Adds the exchange part of Eq. sigma2 to Sig (G(-tau) = -G(beta - tau), prefactor 1/nk^2):
+//   Sig[s][t][k] += -(1/nk^2) sum_{k1,k2} sum_{QQ'} F(k,k1)(Q) Fm(k1,k3)(Q') F(k3,k2)(Q) V^{k2,k}(Q'),
+//   F(a,b) = V^{a,b} G^b_s(tau), Fm(a,b) = V^{a,b} G^b_s(beta - tau), k3 = k1 + k2 - k
+// (the minus of the prefactor against the minus of the exchange term, and the minus of G(-tau)).  Per tau
+// node the V G products of every momentum pair are formed once; per triple (k, k1, k2) the auxiliary
+// indices are summed first, X[(i,q)][(m,l)] = sum_Q F(k,k1)_{iq}(Q) F(k3,k2)_{ml}(Q) and
+// Z[(q,m)][(l,j)] = sum_Q' Fm(k1,k3)_{qm}(Q') V^{k2,k}_{lj}(Q'), then Sig_ij += X[i][(q,m,l)] Z[(q,m,l)][j]
+// summed over the triples of a chunk as one contraction.
+int run_gf2_exchange(green_plan* p, const void* V, const void* G, void* Sig, void* ws, hipStream_t s) {
+  const green_dims& d = p->d;
+  const int nk = p->nk, nao = d.nao, naux = d.naux, ntau = d.ntau, ns = d.nspin;
+  const int64_t nG = (int64_t)nao * nao, nV = (int64_t)naux * nG, nG2 = nG * nG, n3 = nG * nao;
+  const int nk2 = nk * nk;
+  const Extents ex = extents(p);
+  if (!p->gf2 || p->r_g2tab.bytes == 0) return GREEN_EINVAL;
+  const int32_t* kadd = at<int32_t>(ws, p->r_kadd);
+  const int32_t* hadd = p->kadd.data();
+  const int32_t* tab = at<int32_t>(ws, p->r_g2tab);
+  const int32_t* htab = p->g2tab.data();
+  const int64_t ntrip = (int64_t)nk2 * nk;
+  double2* Fp = at<double2>(ws, p->r_Fp);
+  double2* Fm = at<double2>(ws, p->r_Fm);
+  double2* X = at<double2>(ws, p->r_X2);
+  double2* Z = at<double2>(ws, p->r_Z2);
+  const green::Span sV = span(V, ex.V), sG = span(G, ex.G), sS = span(Sig, ex.Sig);
+  const green::Span sFp = span_ws(ws, p->r_Fp), sFm = span_ws(ws, p->r_Fm), sX = span_ws(ws, p->r_X2),
+                    sZ = span_ws(ws, p->r_Z2);
+  // triples per chunk: whole k (all nk^2 pairs) when they fit, else a run of pairs of one k; the contraction
+  // depth (pairs) * nao^3 stays below 2^31
+  const int64_t cap = (int64_t)(p->r_X2.bytes / (nG2 * 16));
+  int64_t pc_max = std::min<int64_t>(cap, (int64_t)nk2);
+  pc_max = std::min<int64_t>(pc_max, ((int64_t)1 << 31) / n3 - 1);
+  if (pc_max < 1) return GREEN_EINVAL;
+  const int prec = p->prec;
+  for (int sp = 0; sp < ns; ++sp)
+    for (int t = 0; t < ntau; ++t) {
+      // F[q][a] = V[q][a] G^{a+q}(tau) and Fm with G(beta - tau): rows (Q, i), one batch entry per pair
+      for (int rev = 0; rev < 2; ++rev) {
+        const int tn = rev ? ntau - 1 - t : t;
+        GREEN_TRY(gemm(green::Site::GF2_VG, rev ? "GF2.VGrev" : "GF2.VG", op(V, flat(nao), flat(1), bflat(nV)), sV,
+                       op(static_cast<const double2*>(G) + ((int64_t)sp * ntau + tn) * nk * nG, flat(nao), flat(1),
+                          btwo(nk2, nG, kadd, 0, hadd)),
+                       sG, rev ? Fm : Fp, rev ? sFm : sFp, flat(nao), flat(1), bflat(nV), naux * nao, nao, nao, nk2,
+                       cplx(1), cplx(0), s, prec));
+      }
+      for (int k0 = 0; k0 < nk;) {
+        // chunk: kc whole momenta k (pc = nk^2 pairs each), or pairs [p0, p0 + pc) of one k
+        const int kc = pc_max == nk2 ? (int)std::min<int64_t>(nk - k0, std::max<int64_t>(1, cap / nk2)) : 1;
+        for (int p0 = 0; p0 < nk2;) {
+          const int pc = pc_max == nk2 ? nk2 : (int)std::min<int64_t>(nk2 - p0, pc_max);
+          const int64_t b0 = (int64_t)k0 * nk2 + p0, nb = (int64_t)kc * pc;
+          if (b0 + nb > ntrip || nb * nG2 * 16 > (int64_t)p->r_X2.bytes) return GREEN_EINVAL;
+          auto tb = [&](int which) { return btwo(green::kFlat, nV, tab + which * ntrip + b0, 0, htab + which * ntrip + b0); };
+          // X[b][(i,q)][(m,l)] = sum_Q F(k,k1)[Q][(i,q)] F(k3,k2)[Q][(m,l)]
+          GREEN_TRY(gemm(green::Site::GF2_Pair, "GF2.X", op(Fp, flat(1), flat(nG), tb(0)), sFp,
+                         op(Fp, flat(nG), flat(1), tb(2)), sFp, X, sX, flat(nG), flat(1), bflat(nG2), (int)nG, (int)nG,
+                         naux, (int)nb, cplx(1), cplx(0), s, prec));
+          // Z[b][(q,m)][(l,j)] = sum_Q' Fm(k1,k3)[Q'][(q,m)] V^{k2,k}[Q'][(l,j)]
+          GREEN_TRY(gemm(green::Site::GF2_Pair, "GF2.Z", op(Fm, flat(1), flat(nG), tb(1)), sFm,
+                         op(V, flat(nG), flat(1), tb(3)), sV, Z, sZ, flat(nG), flat(1), bflat(nG2), (int)nG, (int)nG,
+                         naux, (int)nb, cplx(1), cplx(0), s, prec));
+          // Sig[s][t][k0 + kk][i][j] += -(1/nk^2) sum_{pair,(q,m,l)} X[kk pc + pair][i][(q,m,l)] Z[kk pc + pair][(q,m,l)][j]
+          GREEN_TRY(gemm(green::Site::GF2_Contract, "GF2.contract",
+                         op(X, flat(n3), two((int32_t)n3, 1, nG2), bflat((int64_t)pc * nG2)), sX,
+                         op(Z, two((int32_t)n3, nao, nG2), flat(1), bflat((int64_t)pc * nG2)), sZ,
+                         static_cast<double2*>(Sig) + (((int64_t)sp * ntau + t) * nk + k0) * nG, sS, flat(nao), flat(1),
+                         bflat(nG), nao, nao, (int)(pc * n3), kc, cplx(-1.0 / ((double)nk * nk)), cplx(1.0), s, prec));
+          p0 += pc;
+        }
+        k0 += kc;
+      }
+    }
+  return GREEN_OK;
+}
+
+// GF2 workspace and index tables (appended to the plan's workspace the first time GF2 is enabled).
+void enable_gf2(green_plan* p) {
+  if (p->r_g2tab.bytes) return;
+  const green_dims& d = p->d;
+  const int nk = p->nk;
+  const int64_t nG = (int64_t)d.nao * d.nao, nV = (int64_t)d.naux * nG, nG2 = nG * nG;
+  const int64_t ntrip = (int64_t)nk * nk * nk;
+  p->g2tab.assign(4 * ntrip, 0);
+  for (int k = 0; k < nk; ++k)
+    for (int k1 = 0; k1 < nk; ++k1)
+      for (int k2 = 0; k2 < nk; ++k2) {
+        const int64_t b = ((int64_t)k * nk + k1) * nk + k2;
+        const int k3 = p->ksub[(size_t)k * nk + p->kadd[(size_t)k2 * nk + k1]];  // (k1 + k2) - k
+        auto blk = [&](int a, int bb) { return p->ksub[(size_t)a * nk + bb] * nk + a; };  // pair V^{a,bb}: q = bb - a
+        p->g2tab[b] = blk(k, k1);
+        p->g2tab[ntrip + b] = blk(k1, k3);
+        p->g2tab[2 * ntrip + b] = blk(k3, k2);
+        p->g2tab[3 * ntrip + b] = blk(k2, k);
+      }
+  // four-index chunks: half the contraction budget each, between one triple and all of them
+  const int64_t per = nG2 * 16;
+  const int64_t want = std::max<int64_t>(1, (int64_t)(p->chunk_bytes / 2) / per);
+  const int64_t trips = std::min<int64_t>(ntrip, want);
+  size_t off = p->ws_bytes;
+  auto take = [&](Region& r, size_t bytes) {
+    r.off = off;
+    r.bytes = bytes;
+    off += (bytes + 255) & ~(size_t)255;
+  };
+  take(p->r_g2tab, (size_t)(4 * ntrip * 4));
+  take(p->r_Fp, (size_t)nk * nk * nV * 16);
+  take(p->r_Fm, (size_t)nk * nk * nV * 16);
+  take(p->r_X2, (size_t)(trips * per));
+  take(p->r_Z2, (size_t)(trips * per));
+  p->ws_bytes = off;
+  p->bound_ws = nullptr;  // the tables are uploaded on the next call
+}
+
 // ---------------------------------------------------------------- Hartree-Fock
 int run_hf(green_plan* p, const void* V, const void* G, void* Sinf, void* ws, hipStream_t s) {
   const green_dims& d = p->d;
@@ -1091,9 +1213,12 @@ int sigma_eval(green_plan* p, const void* V, const void* G, void* Sinf, void* Si
   GREEN_TRY(m(1));
   GREEN_TRY(run_polarization(p, V, G, P, ws, s));
   GREEN_TRY(m(2));
-  GREEN_TRY(run_screen(p, P, P, ws, s));
+  // GF2: no screening, the bubble enters the self-energy bare (the direct term of Eq. sigma2), then the
+  // exchange term is added
+  if (!p->gf2) GREEN_TRY(run_screen(p, P, P, ws, s));
   GREEN_TRY(m(3));
   GREEN_TRY(run_selfenergy(p, V, G, P, Sign, ws, s));
+  if (p->gf2) GREEN_TRY(run_gf2_exchange(p, V, G, Sign, ws, s));
   GREEN_TRY(m(4));
   if (!mix) return GREEN_OK;
   double2* Si = static_cast<double2*>(Sinf);
@@ -1295,6 +1420,7 @@ int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, 
   const int64_t nao = d.nao, naux = d.naux, ns = d.nspin;
   const int64_t nG = nao * nao, nV = naux * nG, nP = naux * naux;
   if (chunk_bytes == 0) chunk_bytes = (size_t)8 << 30;
+  p->chunk_bytes = chunk_bytes;
   const size_t isz = prec == GREEN_FP64 ? 16 : 8;  // bytes of a stored contraction intermediate
   const size_t per_t = (size_t)2 * nk * nV * isz;
   int tc = (int)std::max<size_t>(1, chunk_bytes / per_t);
@@ -1401,6 +1527,18 @@ int green_gw_selfenergy(green_plan* p, const void* V, const void* G, const void*
   PlanScope scope(p);
   GREEN_TRY(ensure_bound(p, ws, s));
   return run_selfenergy(p, V, G, Pt, Sigma, ws, s);
+}
+
+int green_gf2_selfenergy(green_plan* p, const void* V, const void* G, void* Sigma, void* ws, void* stream) {
+  GREEN_TRY(check_plan(p, ws));
+  if (!V || !G || !Sigma || !p->gf2) return GREEN_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PlanScope scope(p);
+  GREEN_TRY(ensure_bound(p, ws, s));
+  double2* P = at<double2>(ws, p->r_P);
+  GREEN_TRY(run_polarization(p, V, G, P, ws, s));
+  GREEN_TRY(run_selfenergy(p, V, G, P, Sigma, ws, s));
+  return run_gf2_exchange(p, V, G, Sigma, ws, s);
 }
 
 int green_hf_static(green_plan* p, const void* V, const void* G, void* Sinf, void* ws, void* stream) {
@@ -1687,6 +1825,12 @@ int green_plan_set_option(green_plan* p, int option, int value) {
       p->big_stage1 = value;
       drop_graph(p);
       return GREEN_OK;
+    case GREEN_OPT_GF2:
+      if (value < 0 || value > 1) return GREEN_EINVAL;
+      if (value) enable_gf2(p);
+      p->gf2 = value != 0;
+      drop_graph(p);
+      return count_ops(p);
     case GREEN_OPT_SIGMA_FUSED:
       if (value < 0 || value > 1) return GREEN_EINVAL;
       if (value && (p->prec != GREEN_BF16X3 || p->d.nao % 4 != 0 || p->d.nao > 64)) return GREEN_EINVAL;
@@ -1702,12 +1846,12 @@ int green_plan_tuning_report(const green_plan* p, char* buf, size_t len) {
   if (!p || !buf || len == 0) return GREEN_EINVAL;
   std::string out;
   static const char* names[] = {"Generic", "P0_VG", "P0_VGrev", "P0_Contract", "Sig_PV", "Sig_XG", "Sig_YV",
-                                "HF", "Transform"};
+                                "HF", "Transform", "GF2_VG", "GF2_Pair", "GF2_Contract"};
   for (const auto& kv : p->tuner) {
     const TuneKey& k = kv.first;
     const TuneEntry& e = kv.second;
     char line[256];
-    const int site = k.v[0] >= 0 && k.v[0] <= 8 ? k.v[0] : 0;
+    const int site = k.v[0] >= 0 && k.v[0] <= 11 ? k.v[0] : 0;
     if (!e.done) {
       std::snprintf(line, sizeof(line), "%-12s M=%d N=%d K=%d batch=%d prec=%d: tuning (%d of %zu tried)\n",
                     names[site], k.v[1], k.v[2], k.v[3], k.v[4], k.v[5], e.trial, e.cands.size());

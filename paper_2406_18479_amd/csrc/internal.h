@@ -67,6 +67,9 @@ enum class Site : int32_t {
   Sig_YV,       // Sigma~ stage 3: Y V^{k-q,k} summed over (Q', b)
   HF,           // Hartree-Fock terms
   Transform,    // Matsubara transforms and the energy quadrature
+  GF2_VG,       // GF2 exchange: V^{a,a+q}(Q) G^{a+q} for every momentum pair
+  GF2_Pair,     // GF2 exchange: four-index products summed over one auxiliary index
+  GF2_Contract, // GF2 exchange: sum over (k1, k2) and three orbitals into Sigma
 };
 
 // C[b] = alpha * op(A[b]) * op(B[b]) + beta * C[b]   (A: M x K, B: K x N, complex FP64).

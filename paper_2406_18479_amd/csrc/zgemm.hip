@@ -1774,6 +1774,9 @@ namespace {
     case Site::Sig_YV: X(Sig_YV); break;           \
     case Site::HF: X(HF); break;                   \
     case Site::Transform: X(Transform); break;     \
+    case Site::GF2_VG: X(GF2_VG); break;           \
+    case Site::GF2_Pair: X(GF2_Pair); break;       \
+    case Site::GF2_Contract: X(GF2_Contract); break; \
     default: X(Generic); break;                    \
   }
 

@@ -79,11 +79,19 @@ class Plan:
         return (self.nk, self.nao, self.nao)
 
     def set_option(self, option: str, value: int) -> None:
-        """option "tune" (0, 1, 2), "graph" (0, 1), "p0_tile" (1..6), "stage1_tile" (0..2) or
-        "sigma_fused" (0, 1); see green_plan_set_option."""
+        """option "tune" (0, 1, 2), "graph" (0, 1), "p0_tile" (1..6), "stage1_tile" (0..2), "sigma_fused"
+        (0, 1) or "gf2" (0, 1); see green_plan_set_option.  The workspace is re-allocated when the option
+        grows it (GF2)."""
         code = {"tune": _lib.OPT_TUNE, "graph": _lib.OPT_GRAPH, "p0_tile": _lib.OPT_P0_TILE,
-                "stage1_tile": _lib.OPT_STAGE1_TILE, "sigma_fused": _lib.OPT_SIGMA_FUSED}[option]
+                "stage1_tile": _lib.OPT_STAGE1_TILE, "sigma_fused": _lib.OPT_SIGMA_FUSED,
+                "gf2": _lib.OPT_GF2}[option]
         _lib.check(_lib.LIB.green_plan_set_option(self._h, code, int(value)), "green_plan_set_option")
+        need = int(_lib.LIB.green_workspace_bytes(self._h))
+        if need != self.ws_bytes:
+            self.ws_bytes = need
+            self.ws = None
+            with torch.cuda.device(self.device):
+                self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
 
     def tuning_report(self) -> str:
         buf = ctypes.create_string_buffer(1 << 16)
@@ -124,6 +132,15 @@ class Plan:
                                                 _ptr(Pt, self.shape_P, "Pt", self.device),
                                                 _ptr(Sigma, self.shape_G, "Sigma", self.device), self.ws.data_ptr(),
                                                 _stream(self.device)), "green_gw_selfenergy")
+        return Sigma
+
+    def gf2_selfenergy(self, V, G, Sigma=None):
+        """GF2 self-energy of Eq. sigma2 (direct minus exchange); needs set_option("gf2", 1)."""
+        Sigma = torch.empty(self.shape_G, dtype=torch.complex128, device=self.device) if Sigma is None else Sigma
+        _lib.check(_lib.LIB.green_gf2_selfenergy(self._h, _ptr(V, self.shape_V, "V", self.device),
+                                                 _ptr(G, self.shape_G, "G", self.device),
+                                                 _ptr(Sigma, self.shape_G, "Sigma", self.device), self.ws.data_ptr(),
+                                                 _stream(self.device)), "green_gf2_selfenergy")
         return Sigma
 
     def hf_static(self, V, G, Sinf=None):

@@ -173,3 +173,36 @@ def test_kpath_interpolation_in_bounds_and_argument_checks(lib):
             assert L.green_kpath_interpolate(h, k, npath, Sinf, Sig, Sp, Sgp, ws, None) == -1
         finally:
             L.green_plan_destroy(h)
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("ci", [0, 1, 2, 5, 6])
+def test_gf2_in_bounds_and_argument_checks(lib, ci, prec):
+    """GF2 (Eq. sigma2): the option grows the workspace; every contraction of the exchange term, in whole-k
+    and in partial-k chunks (chunk=1: one momentum triple per chunk), stays inside its buffers, standalone
+    and inside the iteration; the entry point is refused without the option."""
+    c = CASES[ci]
+    L = lib.LIB
+    h = _plan(lib, c, prec)
+    try:
+        V, G, Sig, H0, S, Sinf, ws = [BASE + i * STEP for i in range(7)]
+        assert L.green_gf2_selfenergy(h, V, G, Sig, ws, None) == -1
+        ws0 = L.green_workspace_bytes(h)
+        assert L.green_plan_set_option(h, lib.OPT_GF2, 2) == -1
+        assert L.green_plan_set_option(h, lib.OPT_GF2, 1) == 0
+        nk = int(np.prod(c["kmesh"]))
+        nG2 = c["nao"] ** 4
+        grow = L.green_workspace_bytes(h) - ws0
+        assert grow >= 2 * nk * nk * c["naux"] * c["nao"] ** 2 * 16 + 2 * nG2 * 16
+        assert L.green_gf2_selfenergy(h, V, G, Sig, ws, None) == 0
+        assert L.green_gf2_selfenergy(h, None, G, Sig, ws, None) == -1
+        rep = lib.Report()
+        mu = ctypes.c_double(0.0)
+        assert L.green_gw_iterate(h, V, H0, S, G, Sinf, Sig, ctypes.byref(mu), 3.0, 1.0, ctypes.byref(rep), ws,
+                                  None) == 0
+        # back to GW: the workspace keeps its size, the GF2 entry point is refused again
+        assert L.green_plan_set_option(h, lib.OPT_GF2, 0) == 0
+        assert L.green_workspace_bytes(h) == ws0 + grow
+        assert L.green_gf2_selfenergy(h, V, G, Sig, ws, None) == -1
+    finally:
+        L.green_plan_destroy(h)
