@@ -286,8 +286,9 @@ int progress(const char* stage, int q, int nq, hipStream_t s) {
 }
 
 // Split the K range when the output tiles alone cannot fill the GPU (256 CUs): aim for ~2048
-// workgroups, keep every slice at least 64 deep, and fit the partial sums into the scratch region.
-int choose_ksplit(const ZGemm& g) {
+// workgroups, keep every slice at least 64 deep, at most `cap` slices, and fit the partial sums into the
+// scratch region.
+int choose_ksplit(const ZGemm& g, int cap = 32) {
   const int M = g.M, N = g.N, K = g.K, batch = g.batch;
   int bm, bn, threads;
   green::zgemm_tile(g, &bm, &bn, &threads);
@@ -295,7 +296,7 @@ int choose_ksplit(const ZGemm& g) {
   // 256-thread tiles: aim for ~2048 workgroups; 512-thread large tiles (one per CU): ~1024
   const int64_t target = threads == 512 ? 1024 : 2048;
   if (tiles >= target / 2) return 1;
-  int ks = (int)std::min<int64_t>((target + tiles - 1) / tiles, 32);
+  int ks = (int)std::min<int64_t>((target + tiles - 1) / tiles, cap);
   ks = std::min(ks, std::max(1, K / 64));
   while (ks > 1 && (int64_t)ks * batch * M * N > tl_split.cap) --ks;
   return std::max(ks, 1);
@@ -343,7 +344,10 @@ std::vector<TuneCand> tune_candidates(const ZGemm& g0) {
       for (int b : {4, 16})
         if ((g.M + bm - 1) / bm > b && (g.N + bn - 1) / bn > 1) out.push_back(TuneCand{shape, big, ks0, b});
   };
-  add(g0.shape, g0.big);  // the default (size-picked tile, requested large tile)
+  // the default as launched untuned first (its split-K count may exceed what add() picks), then the
+  // size-picked tile and the requested large tile
+  if (green::zgemm_variant(g0).family >= 0) out.push_back(TuneCand{g0.shape, g0.big, g0.ksplit, 0});
+  add(g0.shape, g0.big);
   if (g0.prec == 2) {
     add(0, 1);
     add(0, 2);
@@ -372,7 +376,7 @@ ZOp op(const void* ptr, IdxMap r, IdxMap c, BatchMap b, int etype = green::kC64,
 
 int gemm(green::Site site, const char* label, const ZOp& A, const green::Span& sa, const ZOp& B, const green::Span& sb, void* C,
          const green::Span& sc, IdxMap cr, IdxMap cc, BatchMap cb, int M, int N, int K, int batch, double2 alpha,
-         double2 beta, hipStream_t s, int prec = 0, int ctype = green::kC64, int big = 0) {
+         double2 beta, hipStream_t s, int prec = 0, int ctype = green::kC64, int big = 0, int ks_cap = 32) {
   ZGemm g;
   g.site = site;
   g.M = M;
@@ -393,7 +397,7 @@ int gemm(green::Site site, const char* label, const ZOp& A, const green::Span& s
   g.shape = 0;
   g.band = 0;
   g.ksplit = 1;
-  g.ksplit = choose_ksplit(g);
+  g.ksplit = choose_ksplit(g, ks_cap);
   g.partial = g.ksplit > 1 ? tl_split.ptr : nullptr;
   char why[256];
   if (g.ksplit > 1 && (int64_t)g.ksplit * batch * M * N > tl_split.cap) return GREEN_EINVAL;
@@ -817,30 +821,46 @@ int run_gf2_exchange(green_plan* p, const void* V, const void* G, void* Sig, voi
   const int32_t* tab = at<int32_t>(ws, p->r_g2tab);
   const int32_t* htab = p->g2tab.data();
   const int64_t ntrip = (int64_t)nk2 * nk;
-  double2* Fp = at<double2>(ws, p->r_Fp);
-  double2* Fm = at<double2>(ws, p->r_Fm);
-  double2* X = at<double2>(ws, p->r_X2);
-  double2* Z = at<double2>(ws, p->r_Z2);
+  // Split-BF16 plans keep the pair products, V and the four-index products in split BF16, the operand of the
+  // auxiliary sums that runs along the rows transposed (Q contiguous), so those sums run on the large-tile
+  // kernel: F (Q-major) and F^T ([pair][(i,q)][Q]) share the first region, F'^T and the rounded V the second.
+  const bool bf = p->prec == GREEN_BF16X3;
+  const int et = bf ? green::kCB16 : green::kC64;
+  const int64_t half = (int64_t)nk2 * nV;  // elements of one pair-product array
+  void* Fp = at<void>(ws, p->r_Fp);
+  void* Fm = at<void>(ws, p->r_Fm);
+  void* FpT = bf ? eptr(Fp, et, half) : nullptr;
+  void* Vr = bf ? eptr(Fm, et, half) : nullptr;
+  void* X = at<void>(ws, p->r_X2);
+  void* Z = at<void>(ws, p->r_Z2);
   const green::Span sV = span(V, ex.V), sG = span(G, ex.G), sS = span(Sig, ex.Sig);
   const green::Span sFp = span_ws(ws, p->r_Fp), sFm = span_ws(ws, p->r_Fm), sX = span_ws(ws, p->r_X2),
                     sZ = span_ws(ws, p->r_Z2);
+  if (bf) {
+    if ((int64_t)p->r_Fm.bytes < 2 * half * 8) return GREEN_EINVAL;
+    GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64(static_cast<const double2*>(V), Vr, green::kCB16, half, st_); }));
+  }
   // triples per chunk: whole k (all nk^2 pairs) when they fit, else a run of pairs of one k; the contraction
   // depth (pairs) * nao^3 stays below 2^31
-  const int64_t cap = (int64_t)(p->r_X2.bytes / (nG2 * 16));
+  const int64_t cap = (int64_t)(p->r_X2.bytes / (nG2 * green::elem_bytes(et)));
   int64_t pc_max = std::min<int64_t>(cap, (int64_t)nk2);
   pc_max = std::min<int64_t>(pc_max, ((int64_t)1 << 31) / n3 - 1);
   if (pc_max < 1) return GREEN_EINVAL;
   const int prec = p->prec;
   for (int sp = 0; sp < ns; ++sp)
     for (int t = 0; t < ntau; ++t) {
-      // F[q][a] = V[q][a] G^{a+q}(tau) and Fm with G(beta - tau): rows (Q, i), one batch entry per pair
-      for (int rev = 0; rev < 2; ++rev) {
+      // F[q][a] = V[q][a] G^{a+q}(tau) and F' with G(beta - tau): rows (Q, i), one batch entry per pair
+      // (split BF16: F as given and transposed, F' transposed only)
+      for (int pass = 0; pass < (bf ? 3 : 2); ++pass) {
+        const bool rev = bf ? pass == 2 : pass == 1;
+        const bool tr = bf && pass >= 1;
         const int tn = rev ? ntau - 1 - t : t;
+        void* C = rev ? Fm : (tr ? FpT : Fp);
         GREEN_TRY(gemm(green::Site::GF2_VG, rev ? "GF2.VGrev" : "GF2.VG", op(V, flat(nao), flat(1), bflat(nV)), sV,
                        op(static_cast<const double2*>(G) + ((int64_t)sp * ntau + tn) * nk * nG, flat(nao), flat(1),
                           btwo(nk2, nG, kadd, 0, hadd)),
-                       sG, rev ? Fm : Fp, rev ? sFm : sFp, flat(nao), flat(1), bflat(nV), naux * nao, nao, nao, nk2,
-                       cplx(1), cplx(0), s, prec));
+                       sG, C, rev ? sFm : sFp, tr ? two(nao, (int64_t)nao * naux, 1) : flat(nao),
+                       tr ? flat(naux) : flat(1), bflat(nV), naux * nao, nao, nao, nk2, cplx(1), cplx(0), s, prec, et));
       }
       for (int k0 = 0; k0 < nk;) {
         // chunk: kc whole momenta k (pc = nk^2 pairs each), or pairs [p0, p0 + pc) of one k
@@ -848,22 +868,27 @@ int run_gf2_exchange(green_plan* p, const void* V, const void* G, void* Sig, voi
         for (int p0 = 0; p0 < nk2;) {
           const int pc = pc_max == nk2 ? nk2 : (int)std::min<int64_t>(nk2 - p0, pc_max);
           const int64_t b0 = (int64_t)k0 * nk2 + p0, nb = (int64_t)kc * pc;
-          if (b0 + nb > ntrip || nb * nG2 * 16 > (int64_t)p->r_X2.bytes) return GREEN_EINVAL;
+          if (b0 + nb > ntrip || nb * nG2 * green::elem_bytes(et) > (int64_t)p->r_X2.bytes) return GREEN_EINVAL;
           auto tb = [&](int which) { return btwo(green::kFlat, nV, tab + which * ntrip + b0, 0, htab + which * ntrip + b0); };
           // X[b][(i,q)][(m,l)] = sum_Q F(k,k1)[Q][(i,q)] F(k3,k2)[Q][(m,l)]
-          GREEN_TRY(gemm(green::Site::GF2_Pair, "GF2.X", op(Fp, flat(1), flat(nG), tb(0)), sFp,
-                         op(Fp, flat(nG), flat(1), tb(2)), sFp, X, sX, flat(nG), flat(1), bflat(nG2), (int)nG, (int)nG,
-                         naux, (int)nb, cplx(1), cplx(0), s, prec));
-          // Z[b][(q,m)][(l,j)] = sum_Q' Fm(k1,k3)[Q'][(q,m)] V^{k2,k}[Q'][(l,j)]
-          GREEN_TRY(gemm(green::Site::GF2_Pair, "GF2.Z", op(Fm, flat(1), flat(nG), tb(1)), sFm,
-                         op(V, flat(nG), flat(1), tb(3)), sV, Z, sZ, flat(nG), flat(1), bflat(nG2), (int)nG, (int)nG,
-                         naux, (int)nb, cplx(1), cplx(0), s, prec));
-          // Sig[s][t][k0 + kk][i][j] += -(1/nk^2) sum_{pair,(q,m,l)} X[kk pc + pair][i][(q,m,l)] Z[kk pc + pair][(q,m,l)][j]
+          GREEN_TRY(gemm(green::Site::GF2_Pair, "GF2.X",
+                         bf ? op(FpT, flat(naux), flat(1), tb(0), et) : op(Fp, flat(1), flat(nG), tb(0)), sFp,
+                         op(Fp, flat(nG), flat(1), tb(2), et), sFp, X, sX, flat(nG), flat(1), bflat(nG2), (int)nG,
+                         (int)nG, naux, (int)nb, cplx(1), cplx(0), s, prec, et, bf ? 1 : 0));
+          // Z[b][(q,m)][(l,j)] = sum_Q' F'(k1,k3)[Q'][(q,m)] V^{k2,k}[Q'][(l,j)]
+          GREEN_TRY(gemm(green::Site::GF2_Pair, "GF2.Z",
+                         bf ? op(Fm, flat(naux), flat(1), tb(1), et) : op(Fm, flat(1), flat(nG), tb(1)), sFm,
+                         bf ? op(Vr, flat(nG), flat(1), tb(3), et) : op(V, flat(nG), flat(1), tb(3)), bf ? sFm : sV,
+                         Z, sZ, flat(nG), flat(1), bflat(nG2), (int)nG, (int)nG, naux, (int)nb, cplx(1), cplx(0), s,
+                         prec, et, bf ? 1 : 0));
+          // Sig[s][t][k0 + kk][i][j] += -(1/nk^2) sum_{pair,(q,m,l)} X[kk pc + pair][i][(q,m,l)] Z[kk pc + pair][(q,m,l)][j]:
+          // a few nao x nao outputs over a very deep K, so up to 256 K slices fill the GPU
           GREEN_TRY(gemm(green::Site::GF2_Contract, "GF2.contract",
-                         op(X, flat(n3), two((int32_t)n3, 1, nG2), bflat((int64_t)pc * nG2)), sX,
-                         op(Z, two((int32_t)n3, nao, nG2), flat(1), bflat((int64_t)pc * nG2)), sZ,
+                         op(X, flat(n3), two((int32_t)n3, 1, nG2), bflat((int64_t)pc * nG2), et), sX,
+                         op(Z, two((int32_t)n3, nao, nG2), flat(1), bflat((int64_t)pc * nG2), et), sZ,
                          static_cast<double2*>(Sig) + (((int64_t)sp * ntau + t) * nk + k0) * nG, sS, flat(nao), flat(1),
-                         bflat(nG), nao, nao, (int)(pc * n3), kc, cplx(-1.0 / ((double)nk * nk)), cplx(1.0), s, prec));
+                         bflat(nG), nao, nao, (int)(pc * n3), kc, cplx(-1.0 / ((double)nk * nk)), cplx(1.0), s, prec,
+                         green::kC64, 0, 256));
           p0 += pc;
         }
         k0 += kc;

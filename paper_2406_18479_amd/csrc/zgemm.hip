@@ -1799,6 +1799,7 @@ void launch_bt(const ZGemm& g, dim3 grid, hipStream_t s) {
     case Site::P0_VGrev: zgemm_bt_kernel<FM, FN, BNC, Site::P0_VGrev><<<grid, dim3(512), 0, s>>>(g); break;
     case Site::P0_Contract: zgemm_bt_kernel<FM, FN, BNC, Site::P0_Contract><<<grid, dim3(512), 0, s>>>(g); break;
     case Site::Sig_PV: zgemm_bt_kernel<FM, FN, BNC, Site::Sig_PV><<<grid, dim3(512), 0, s>>>(g); break;
+    case Site::GF2_Pair: zgemm_bt_kernel<FM, FN, BNC, Site::GF2_Pair><<<grid, dim3(512), 0, s>>>(g); break;
     default: zgemm_bt_kernel<FM, FN, BNC, Site::Generic><<<grid, dim3(512), 0, s>>>(g); break;
   }
 }

@@ -76,10 +76,15 @@ def test_gf2_selfenergy_parity(c):
     assert np.max(np.abs(ref - direct)) > 1e-2 * np.max(np.abs(ref))
 
 
+MIXED = [CASES[1], dict(kmesh=(2, 1, 1), nao=13, naux=37, ntau=6, nspin=1, chunk=0, seed=606)]
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-def test_gf2_mixed_precision(prec):
+@pytest.mark.parametrize("c", MIXED, ids=lambda c: f"k{c['kmesh']}_nao{c['nao']}_naux{c['naux']}")
+def test_gf2_mixed_precision(c, prec):
+    """Split-BF16 plans run the auxiliary sums on the large-tile kernel (nao^2 = 169 rows and columns, a K of 37
+    in two slices of 32); FP32 plans on the 256-thread kernel."""
     _require_gpu()
-    c = CASES[1]
     s = _system(c)
     sp = s.spec
     say("gf2", prec, c)
