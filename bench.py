@@ -40,7 +40,13 @@ def contraction_flops(nk, nao, naux, ntau, nspin) -> float:
 def workloads():
     from synth import configs
     return {"molecule": configs.MOLECULE, "periodic2": configs.PERIODIC_2, "periodic3": configs.PERIODIC_3,
-            "large4": configs.LARGE_4}
+            "periodic3tr": configs.PERIODIC_3_TR, "large4": configs.LARGE_4}
+
+
+def time_reversal_symmetric(spec) -> bool:
+    """Synthetic systems built with V^{-k1,-k2} = conj V^{k1,k2} and H0(-k) = conj H0(k) (S = I): the plan may
+    contract the self-energy for half of the momenta and conjugate the rest."""
+    return bool(spec.v_time_reversal and spec.f_time_reversal)
 
 
 def cpu_baseline(system, target_s: float):
@@ -151,7 +157,8 @@ def time_gf2(precs, steps, tune=True):
             plan.gf2_selfenergy(V, G, Sig)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
-        r = {"ms_per_call": round(dt * 1e3, 3), "tflops": round(flops / dt / 1e12, 3)}
+        r = {"ms_per_call": round(dt * 1e3, 3), "tflops": round(flops / dt / 1e12, 3),
+             "frac_of_peak": round(flops / dt / 1e12 / PEAK_TFLOPS[prec], 4)}
         if ref is None:
             ref = Sig.clone()
         else:
@@ -182,6 +189,8 @@ def run_precision(system, prec, steps, warmup, chunk_bytes=0, tune=False, graph=
 
     spec = system.spec
     plan = Plan(spec.kmesh, spec.nao, spec.naux, system.grid, nspin=spec.nspin, prec=prec, chunk_bytes=chunk_bytes)
+    if time_reversal_symmetric(spec):
+        plan.set_option("time_reversal", 1)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")  # noqa: E731
     V = system.V_dev
     H0, S = dev(system.H0), dev(system.S)
@@ -478,8 +487,8 @@ def main():
     ap.add_argument("--kpath", type=int, default=0,
                     help="after the timed steps, interpolate the self-energy onto this many k-path points and "
                          "solve Dyson there (Sec. 2.4 post-processing), timed separately")
-    ap.add_argument("--gf2", action="store_true",
-                    help="also time the GF2 self-energy (Eq. sigma2) on the 2x2x2 workload, each precision")
+    ap.add_argument("--no-gf2", dest="gf2", action="store_false",
+                    help="skip the GF2 self-energy (Eq. sigma2) timing on the 2x2x2 workload that follows the GW run")
     ap.add_argument("--gf2-only", action="store_true", help="time only the GF2 self-energy (prints its JSON)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain device-to-device copy of this many MiB (counter calibration)")
@@ -567,7 +576,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": spec.name, "nk": spec.nk, "kmesh": list(spec.kmesh), "nao": spec.nao,
                    "naux": spec.naux, "ntau": spec.ntau, "nspin": spec.nspin, "beta": spec.beta,
-                   "precision": head, "tuned": bool(args.tune), "graph": bool(args.graph)},
+                   "precision": head, "tuned": bool(args.tune), "graph": bool(args.graph),
+                   "time_reversal": time_reversal_symmetric(spec)},
         "s_per_iteration": round(h["s_per_iteration"], 6),
         "fp64_s_per_iteration": round(fp64_spi, 6) if fp64_spi else None,
         "speedup_vs_fp64": round(fp64_spi / h["s_per_iteration"], 3) if fp64_spi else None,

@@ -274,6 +274,15 @@ int green_gw_iterate_diis(green_plan* plan, const void* V, const void* H0, const
  *                   products of nao^4 complex FP64 per momentum triple, each chunk at most chunk_bytes / 2 but
  *                   at least one triple): query green_workspace_bytes after setting it and bind a workspace of
  *                   that size.  0 (default): GW (the workspace keeps its size).
+ *   GREEN_OPT_TIME_REVERSAL  1: the caller's system is time-reversal symmetric, V^{-k1,-k2}(Q) = conj V^{k1,k2}(Q)
+ *                   and G^{-k}_s(tau) = conj G^k_s(tau) (which holds for G from green_dyson when H0(-k) =
+ *                   conj H0(k) and S(-k) = conj S(k)); then P~0^{-q}(tau) = conj P~0^q(tau), which with the +-q
+ *                   identity gives P~0^q(beta - tau) = P~0^q(tau)^H, and Sigma~^{-k} = conj Sigma~^k.  So
+ *                   green_gw_polarization contracts the first half of the tau nodes only (the second half is
+ *                   the conjugate transpose), and green_gw_selfenergy only the momenta k with -k >= k (flat
+ *                   index), each partner written as the complex conjugate; the same inside the iterations and
+ *                   the direct term of green_gf2_selfenergy.  Results on inputs without the symmetry are wrong,
+ *                   not flagged.  0 (default): every tau node and every k is contracted.
  * Returns GREEN_EINVAL for an unknown option or value. */
 #define GREEN_OPT_TUNE 1
 #define GREEN_OPT_GRAPH 2
@@ -281,6 +290,7 @@ int green_gw_iterate_diis(green_plan* plan, const void* V, const void* H0, const
 #define GREEN_OPT_STAGE1_TILE 4
 #define GREEN_OPT_SIGMA_FUSED 5
 #define GREEN_OPT_GF2 6
+#define GREEN_OPT_TIME_REVERSAL 7
 int green_plan_set_option(green_plan* plan, int option, int value);
 
 /* Text table of the autotuner's decisions into buf (host, len bytes, NUL-terminated; GREEN_ENOMEM when

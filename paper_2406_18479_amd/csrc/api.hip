@@ -70,10 +70,15 @@ struct green_plan {
   std::vector<double2> TF_t2w, TF_w2t, TB_t2w, TB_w2t, Emass;
   std::vector<int32_t> kadd, ksub, kneg;  // [q][k]: k+q, k-q; [q]: -q
   std::vector<int32_t> qcan;              // momenta q with -q >= q (one of each +-q pair)
+  // time reversal: the self-energy is contracted for the momenta k with -k >= k (kcan) only, the others are
+  // the complex conjugates of their partners; ksubc[q][kk] = kcan[kk] - q
+  bool trev = false;
+  std::vector<int32_t> kcan, ksubc;
   // workspace regions
   Region r_TF_t2w, r_TF_w2t, r_TB_t2w, r_TB_w2t, r_Emass, r_wf, r_kadd, r_ksub, r_qcan, r_status, r_scal, r_partial;
   Region r_P, r_Pw, r_T1, r_T2, r_gam, r_gamT, r_D, r_Sinfn, r_Sign, r_Sw, r_A, r_tr, r_split, r_Vx, r_Ptx, r_Gx, r_GTx;
   Region r_g2tab, r_Fp, r_Fm, r_X2, r_Z2;  // GF2 (empty until GREEN_OPT_GF2 is set)
+  Region r_kneg, r_kcan, r_ksubc;
   size_t ws_bytes = 0;
   void* bound_ws = nullptr;
   hipEvent_t ev[kNumEvents]{};
@@ -199,6 +204,9 @@ int ensure_bound(green_plan* p, void* ws, hipStream_t s) {
   HIP_TRY(up(p->r_ksub, p->ksub.data()));
   HIP_TRY(up(p->r_qcan, p->qcan.data()));
   if (p->r_g2tab.bytes) HIP_TRY(up(p->r_g2tab, p->g2tab.data()));
+  HIP_TRY(up(p->r_kneg, p->kneg.data()));
+  HIP_TRY(up(p->r_kcan, p->kcan.data()));
+  HIP_TRY(up(p->r_ksubc, p->ksubc.data()));
   HIP_TRY(hipMemsetAsync(static_cast<char*>(ws) + p->r_status.off, 0, p->r_status.bytes, s));
   HIP_TRY(hipStreamSynchronize(s));
   p->bound_ws = ws;
@@ -538,10 +546,12 @@ int run_polarization(green_plan* p, const void* V, const void* G, void* P0, void
   // P~0^{-q}(tau) = P~0^q(beta - tau)^T exactly (substitute k -> k + q and cycle the trace), and the grid is
   // symmetric (tau_{ntau-1-t} = beta - tau_t): only q <= -q are contracted, the partner slab is a transposed,
   // tau-reversed copy, and for q = -q only the first half of the tau nodes is contracted.
+  // With time reversal also P~0^{-q}(tau) = conj P~0^q(tau), so P~0^q(beta - tau) = P~0^q(tau)^H: every q is
+  // contracted on the first half of the tau nodes only, the second half is the conjugate transpose.
   for (int q = 0; q < nk; ++q) {
     const int qn = p->kneg[q];
     if (qn < q) continue;
-    const int t_end = qn == q ? ntau / 2 : ntau;
+    const int t_end = (qn == q || p->trev) ? ntau / 2 : ntau;
     const void *Vq = eptr(V, green::kC64, q * slab), *Vqn = eptr(V, green::kC64, qn * slab);
     green::Span sVs = span(V, ex.V);
     if (bf) {
@@ -579,6 +589,12 @@ int run_polarization(green_plan* p, const void* V, const void* G, void* P0, void
                        bflat((int64_t)naux * naux), naux, naux, (int)(nk * nG), tcn, cplx(-w / nk),
                        cplx(sp == 0 ? 0.0 : 1.0), s, p->prec, green::kC64, bf ? p->big_p0 : 0));
       }
+    }
+    if (p->trev && qn != q) {
+      double2* Pq = Pp + (int64_t)q * ntau * naux * naux;
+      GREEN_TRY(aux(s, [=](hipStream_t st_) {
+        return green::launch_transpose_reverse(Pq, Pq, naux, ntau, ntau / 2, ntau, st_, true);
+      }));
     }
     {
       const double2* src = Pp + (int64_t)q * ntau * naux * naux;
@@ -644,6 +660,16 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
   const Extents ex = extents(p);
   const int32_t* ksub = at<int32_t>(ws, p->r_ksub);
   const int32_t* hsub = p->ksub.data();
+  // With time reversal only the momenta kcan[kk] (-k >= k) are contracted: X, Y and the partial sums hold
+  // kk = 0 .. nkx - 1, Sigma~ of the others is the complex conjugate of its partner's (filled at the end).
+  const bool tr = p->trev;
+  const int nkx = tr ? (int)p->kcan.size() : nk;
+  const int32_t* kcan = at<int32_t>(ws, p->r_kcan);
+  const int32_t* hcan = p->kcan.data();
+  // k - q of each contracted momentum, and the Sigma~ block each one writes
+  auto ktab = [&](int q) { return tr ? at<int32_t>(ws, p->r_ksubc) + (size_t)q * nkx : ksub + (size_t)q * nk; };
+  auto hktab = [&](int q) { return tr ? p->ksubc.data() + (size_t)q * nkx : hsub + (size_t)q * nk; };
+  const green::BatchMap sig_b = tr ? btwo(nkx, nG, kcan, 0, hcan) : bflat(nG);
   double2* T1 = at<double2>(ws, p->r_T1);
   double2* T2 = at<double2>(ws, p->r_T2);
   const green::Span sP = span(Pt, ex.P), sS = span(Sig, ex.Sig);
@@ -724,39 +750,43 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
       const int tcn = std::min(p->tc, ntau - t0);
       // X[tt][k][Q'][(i,a)] = sum_Q P~^q_{QQ'}(tau) V^{k,k-q}_{ia}(Q): the V slab is shared by the tau nodes
       // of the chunk, so they are stacked into the rows, M = (tt, Q') (no partial tiles at each naux edge)
+      // (time reversal: one batch entry per contracted momentum, N = (i,a))
+      const green::BatchMap vb = tr ? btwo(nkx, nV, kcan, 0, hcan) : bnone();
       GREEN_TRY(gemm(green::Site::Sig_PV, "Sigma.PV",
                      bf ? op(eptr(Ptx, pvt, (int64_t)t0 * nP), flat(naux), flat(1), bnone(), pvt)
                         : op(Pp + ((int64_t)q * ntau + t0) * nP, two(naux, 1, nP), flat(naux), bnone()),
                      bf ? sPtx : sP,
-                     vt_dma ? op(Vqn, flat(1), flat(naux), bnone(), pvt)
-                            : op(Vqn, flat(nG), two((int32_t)nG, 1, nV), bnone(), mixed ? vt : green::kC64),
-                     sVa, T1, sT1, two(naux, nG, (int64_t)nk * nV), two((int32_t)nG, 1, nV), bnone(), tcn * naux,
-                     (int)(nk * nG), naux, 1, cplx(1), cplx(0), s, p->prec, xt, bf ? (vt_dma ? 6 : 1) : 0));
+                     vt_dma ? op(Vqn, flat(1), flat(naux), vb, pvt)
+                            : op(Vqn, flat(nG), tr ? flat(1) : two((int32_t)nG, 1, nV), vb,
+                                 mixed ? vt : green::kC64),
+                     sVa, T1, sT1, two(naux, nG, (int64_t)nkx * nV), tr ? flat(1) : two((int32_t)nG, 1, nV),
+                     tr ? bflat(nV) : bnone(), tcn * naux, (int)(tr ? nG : nk * nG), naux, tr ? nkx : 1, cplx(1),
+                     cplx(0), s, p->prec, xt, bf ? (vt_dma ? 6 : 1) : 0));
       for (int sp = 0; sp < ns && fused; ++sp) {
         // Sigma[s][t][k][i][j] += -(1/nk) sum_{Q',b} (sum_a X[tt][k][Q'][i][a] G^{k-q}_{ab}(tau)) V^{k-q,k}_{bj}(Q'):
         // Q' slices of FP64 partial sums, added in slice order
-        const int64_t blocks = (int64_t)tcn * nk;
+        const int64_t blocks = (int64_t)tcn * nkx;
         const int hv = green::xgv_halves(nao);
         int qs = (int)std::min<int64_t>(16, std::max<int64_t>(1, (2560 + blocks - 1) / blocks));
         qs = std::min(qs, naux);
-        while (qs > 1 && (int64_t)qs * hv * nk * nG * tcn > tl_split.cap) --qs;
-        if ((int64_t)qs * hv * nk * nG * tcn > tl_split.cap) return GREEN_EINVAL;
+        while (qs > 1 && (int64_t)qs * hv * nkx * nG * tcn > tl_split.cap) --qs;
+        if ((int64_t)qs * hv * nkx * nG * tcn > tl_split.cap) return GREEN_EINVAL;
         // every element the kernel reads lies inside its region
-        if ((int64_t)tcn * nk * nV * 8 > (int64_t)p->r_T1.bytes || (int64_t)p->r_Vx.bytes < 2 * slab * 8 ||
+        if ((int64_t)tcn * nkx * nV * 8 > (int64_t)p->r_T1.bytes || (int64_t)p->r_Vx.bytes < 2 * slab * 8 ||
             ((int64_t)sp * ntau + t0 + tcn) * nk * nG * 8 > (int64_t)p->r_GTx.bytes)
           return GREEN_EINVAL;
         green::XgvArgs xa{};
         xa.X = static_cast<const uint2*>(static_cast<const void*>(T1));
         xa.GT = static_cast<const uint2*>(at<void>(ws, p->r_GTx)) + ((int64_t)sp * ntau + t0) * nk * nG;
         xa.VT = static_cast<const uint2*>(Vq);
-        xa.kk = ksub + q * nk;
+        xa.kk = ktab(q);
         xa.partial = tl_split.ptr;
         xa.nao = nao;
         xa.naux = naux;
-        xa.nk = nk;
+        xa.nk = nkx;
         xa.tcn = tcn;
         xa.qsplit = qs;
-        xa.x_tt = (int64_t)nk * nV;
+        xa.x_tt = (int64_t)nkx * nV;
         xa.x_k = nV;
         xa.g_tt = (int64_t)nk * nG;
         // the split-K pass: rows j, columns (tt, i), batch k; Sigma[s][t0 + tt][k][i][j]
@@ -765,11 +795,11 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
         rd.M = nao;
         rd.N = tcn * nao;
         rd.K = naux;
-        rd.batch = nk;
+        rd.batch = nkx;
         rd.C = Sp + ((int64_t)sp * ntau + t0) * nk * nG;
         rd.cr = flat(1);
         rd.cc = two(nao, nao, (int64_t)nk * nG);
-        rd.cb = bflat(nG);
+        rd.cb = sig_b;
         rd.alpha = cplx(-1.0 / nk);
         rd.beta = cplx(1.0);
         rd.ksplit = qs * hv;
@@ -782,20 +812,26 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
         // Y[tt][k][(Q',i)][b] = sum_a X[tt][k][(Q',i)][a] G^{k-q}_{ab}(tau)
         GREEN_TRY(gemm(green::Site::Sig_XG, "Sigma.XG", op(T1, flat(nao), flat(1), bflat(nV), xt), sT1,
                        op(eptr(Gs, gt, ((int64_t)sp * ntau + t0) * nk * nG), flat(nao), flat(1),
-                          btwo(nk, nG, ksub + q * nk, (int64_t)nk * nG, hsub + q * nk), gt),
-                       sGs, T2, sT2, flat(nao), flat(1), bflat(nV), naux * nao, nao, nao, tcn * nk, cplx(1), cplx(0),
+                          btwo(nkx, nG, ktab(q), (int64_t)nk * nG, hktab(q)), gt),
+                       sGs, T2, sT2, flat(nao), flat(1), bflat(nV), naux * nao, nao, nao, tcn * nkx, cplx(1), cplx(0),
                        s, stage, xt, bf ? 2 : 0));
         // Sigma[s][t][k][i][j] += -(1/nk) sum_{(Q',b)} Y[tt][k][Q'][i][b] V^{k-q,k}_{bj}(Q'): one GEMM per k
         // with the tau nodes folded into M = (tt, i), so each V block is read once per chunk
         GREEN_TRY(gemm(green::Site::Sig_YV, "Sigma.YV",
-                       op(T2, two(nao, nao, (int64_t)nk * nV), two(nao, 1, nG), bflat(nV), xt), sT2,
-                       op(Vq, two(nao, nao, nG), flat(1), btwo(nk, nV, ksub + q * nk, 0, hsub + q * nk), gt), sVb,
+                       op(T2, two(nao, nao, (int64_t)nkx * nV), two(nao, 1, nG), bflat(nV), xt), sT2,
+                       op(Vq, two(nao, nao, nG), flat(1), btwo(nkx, nV, ktab(q), 0, hktab(q)), gt), sVb,
                        Sp + ((int64_t)sp * ntau + t0) * nk * nG, sS, two(nao, nao, (int64_t)nk * nG), flat(1),
-                       bflat(nG), tcn * nao, nao, naux * nao, nk, cplx(-1.0 / nk), cplx(1.0), s, stage,
+                       sig_b, tcn * nao, nao, naux * nao, nkx, cplx(-1.0 / nk), cplx(1.0), s, stage,
                        green::kC64));
       }
     }
     GREEN_TRY(progress("self-energy", q, nk, s));
+  }
+  if (tr) {
+    const int32_t* kneg = at<int32_t>(ws, p->r_kneg);
+    GREEN_TRY(aux(s, [=](hipStream_t st_) {
+      return green::launch_conj_partner(Sp, (int64_t)ns * ntau, nk, nG, kneg, st_);
+    }));
   }
   return GREEN_OK;
 }
@@ -1441,6 +1477,11 @@ int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, 
   }
   for (int q = 0; q < nk; ++q)
     if (p->kneg[q] >= q) p->qcan.push_back(q);
+  p->kcan = p->qcan;  // the same set of momenta
+  const int nkh = (int)p->kcan.size();
+  p->ksubc.resize((size_t)nk * nkh);
+  for (int q = 0; q < nk; ++q)
+    for (int kk = 0; kk < nkh; ++kk) p->ksubc[(size_t)q * nkh + kk] = p->ksub[(size_t)q * nk + p->kcan[kk]];
   // ---- workspace layout
   const int64_t nao = d.nao, naux = d.naux, ns = d.nspin;
   const int64_t nG = nao * nao, nV = naux * nG, nP = naux * naux;
@@ -1482,6 +1523,9 @@ int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, 
   take(p->r_kadd, (size_t)nk * nk * 4);
   take(p->r_ksub, (size_t)nk * nk * 4);
   take(p->r_qcan, p->qcan.size() * 4);
+  take(p->r_kneg, (size_t)nk * 4);
+  take(p->r_kcan, (size_t)nkh * 4);
+  take(p->r_ksubc, (size_t)nk * nkh * 4);
   take(p->r_status, 64);
   take(p->r_scal, 64 * 8);
   take(p->r_partial, 1024 * 8);
@@ -1850,6 +1894,11 @@ int green_plan_set_option(green_plan* p, int option, int value) {
       p->big_stage1 = value;
       drop_graph(p);
       return GREEN_OK;
+    case GREEN_OPT_TIME_REVERSAL:
+      if (value < 0 || value > 1) return GREEN_EINVAL;
+      p->trev = value != 0;
+      drop_graph(p);
+      return count_ops(p);
     case GREEN_OPT_GF2:
       if (value < 0 || value > 1) return GREEN_EINVAL;
       if (value) enable_gf2(p);

@@ -7,10 +7,13 @@ namespace green {
 
 hipError_t launch_density(const double2* G, double2* gam, double2* gamT, int ns, int ntau, int nk, int nao,
                           hipStream_t s);
-// dst[t] = src[nt - 1 - t]^T for t in [t_lo, t_hi) (n x n complex matrices; src and dst may be the same
-// array when the two t ranges do not overlap).
+// dst[t] = src[nt - 1 - t]^T (conj: the conjugate transpose) for t in [t_lo, t_hi) (n x n complex matrices;
+// src and dst may be the same array when the two t ranges do not overlap).
 hipError_t launch_transpose_reverse(const double2* src, double2* dst, int n, int nt, int t_lo, int t_hi,
-                                   hipStream_t s);
+                                   hipStream_t s, bool conj = false);
+// Time-reversal partners: for every block b < nblk and momentum k with kneg[k] < k,
+// X[b][k] = conj(X[b][kneg[k]]) element by element (blocks of nk matrices of ne elements; kneg on the device).
+hipError_t launch_conj_partner(double2* X, int64_t nblk, int nk, int64_t ne, const int32_t* kneg, hipStream_t s);
 hipError_t launch_one_minus(double2* A, int n, int64_t batch, hipStream_t s);
 hipError_t launch_minus_one(double2* A, int n, int64_t batch, hipStream_t s);
 hipError_t launch_dyson_form(double2* A, const double2* S, const double2* H0, const double2* Sinf,

@@ -52,10 +52,10 @@ __global__ void k_density(const double2* __restrict__ G, double2* __restrict__ g
 }
 
 // A[b] = I - A[b]  (n x n, batch stride n*n)
-// dst[t][j][i] = src[nt - 1 - t][i][j] for t in [t_lo, t_hi): one 32 x 32 tile of one t per block, transposed
-// through LDS so that both the reads and the writes are row-contiguous.
+// dst[t][j][i] = src[nt - 1 - t][i][j] (conjugated if conj) for t in [t_lo, t_hi): one 32 x 32 tile of one t
+// per block, transposed through LDS so that both the reads and the writes are row-contiguous.
 __global__ __launch_bounds__(256) void k_transpose_reverse(const double2* __restrict__ src, double2* __restrict__ dst,
-                                                           int n, int nt, int t_lo) {
+                                                           int n, int nt, int t_lo, int conj) {
   __shared__ double2 tile[32][33];
   const int tiles = (n + 31) / 32;
   const int ti = blockIdx.x % tiles, tj = blockIdx.x / tiles;  // source tile rows ti, columns tj
@@ -71,7 +71,10 @@ __global__ __launch_bounds__(256) void k_transpose_reverse(const double2* __rest
   __syncthreads();
   for (int r = r0; r < 32; r += 8) {
     const int j = 32 * tj + r, i = 32 * ti + c;  // destination row j, column i
-    if (i < n && j < n) D[(int64_t)j * n + i] = tile[c][r];
+    if (i < n && j < n) {
+      const double2 v = tile[c][r];
+      D[(int64_t)j * n + i] = conj ? make_double2(v.x, -v.y) : v;
+    }
   }
 }
 
@@ -280,6 +283,20 @@ __global__ void k_zero(double2* __restrict__ X, int64_t n) {
     X[x] = make_double2(0.0, 0.0);
 }
 
+__global__ void k_conj_partner(double2* __restrict__ X, int64_t nblk, int nk, int64_t ne,
+                               const int32_t* __restrict__ kneg) {
+  const int64_t n = nblk * nk * ne;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = x % ne;
+    const int64_t bk = x / ne;
+    const int k = (int)(bk % nk);
+    const int kn = kneg[k];
+    if (kn >= k) continue;
+    const double2 v = X[(bk - k + kn) * ne + e];
+    X[x] = make_double2(v.x, -v.y);
+  }
+}
+
 inline unsigned grid_for(int64_t n) {
   int64_t b = (n + 255) / 256;
   if (b > 65536) b = 65536;
@@ -297,12 +314,19 @@ hipError_t launch_density(const double2* G, double2* gam, double2* gamT, int ns,
 }
 
 hipError_t launch_transpose_reverse(const double2* src, double2* dst, int n, int nt, int t_lo, int t_hi,
-                                   hipStream_t s) {
+                                   hipStream_t s, bool conj) {
   if (n <= 0 || t_hi <= t_lo) return hipSuccess;
   if (t_lo < 0 || t_hi > nt) return hipErrorInvalidValue;
   const int tiles = (n + 31) / 32;
   k_transpose_reverse<<<dim3((unsigned)(tiles * tiles), (unsigned)(t_hi - t_lo)), dim3(256), 0, s>>>(src, dst, n, nt,
-                                                                                                    t_lo);
+                                                                                                    t_lo, conj ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_conj_partner(double2* X, int64_t nblk, int nk, int64_t ne, const int32_t* kneg, hipStream_t s) {
+  const int64_t n = nblk * nk * ne;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_conj_partner, dim3(grid_for(n)), dim3(256), 0, s, X, nblk, nk, ne, kneg);
   return hipGetLastError();
 }
 

@@ -80,11 +80,11 @@ class Plan:
 
     def set_option(self, option: str, value: int) -> None:
         """option "tune" (0, 1, 2), "graph" (0, 1), "p0_tile" (1..6), "stage1_tile" (0..2), "sigma_fused"
-        (0, 1) or "gf2" (0, 1); see green_plan_set_option.  The workspace is re-allocated when the option
-        grows it (GF2)."""
+        (0, 1), "gf2" (0, 1) or "time_reversal" (0, 1); see green_plan_set_option.  The workspace is
+        re-allocated when the option grows it (GF2)."""
         code = {"tune": _lib.OPT_TUNE, "graph": _lib.OPT_GRAPH, "p0_tile": _lib.OPT_P0_TILE,
                 "stage1_tile": _lib.OPT_STAGE1_TILE, "sigma_fused": _lib.OPT_SIGMA_FUSED,
-                "gf2": _lib.OPT_GF2}[option]
+                "gf2": _lib.OPT_GF2, "time_reversal": _lib.OPT_TIME_REVERSAL}[option]
         _lib.check(_lib.LIB.green_plan_set_option(self._h, code, int(value)), "green_plan_set_option")
         need = int(_lib.LIB.green_workspace_bytes(self._h))
         if need != self.ws_bytes:

@@ -19,6 +19,10 @@ PERIODIC_2 = SystemSpec("periodic_k2x2x2_nao26_naux180_ntau104", (2, 2, 2), nao=
                         beta=100.0, seed=18480)
 PERIODIC_3 = SystemSpec("periodic_k3x3x3_nao52_naux300_ntau136", (3, 3, 3), nao=52, naux=300, ntau=136,
                         beta=100.0, seed=18481)
+# the same shapes with time-reversal-symmetric inputs (V^{-k1,-k2}(Q) = conj V^{k1,k2}(Q), H0(-k) = conj H0(k)),
+# as in a non-magnetic crystal
+PERIODIC_3_TR = SystemSpec("periodic_k3x3x3_nao52_naux300_ntau136_tr", (3, 3, 3), nao=52, naux=300, ntau=136,
+                           beta=100.0, seed=18481, v_time_reversal=True)
 LARGE_4 = SystemSpec("periodic_k4x4x4_nao78_naux420_ntau160_uhf", (4, 4, 4), nao=78, naux=420, ntau=160,
                      beta=200.0, nspin=2, seed=18483)
 

@@ -15,7 +15,7 @@ import numpy as np
 import torch
 
 from . import rng
-from .systems import SystemSpec, k_add_table
+from .systems import SystemSpec, k_add_table, k_neg, k_sub_table
 
 _MASK64 = (1 << 64) - 1
 
@@ -63,11 +63,36 @@ def _block(spec: SystemSpec, k1: int, k2: int, env: torch.Tensor, device) -> tor
     return Z * env[:, None, None]
 
 
+def _impose_time_reversal(spec: SystemSpec, V: torch.Tensor) -> None:
+    """In place, the group average of synth.systems (same terms in the same order): every block becomes
+    (a + b + c + d) / 4 over {itself, the dagger of the swapped pair, the conjugate of the negated pair, the
+    transpose of the negated swapped pair}, so V^{-k1,-k2}(Q) = conj V^{k1,k2}(Q) and the Hermitian pairing
+    hold to rounding.  Works orbit by orbit from saved originals."""
+    nk = spec.nk
+    neg = k_neg(spec.kmesh)
+    sub = k_sub_table(spec.kmesh)
+
+    def at(k1, k2):
+        return V[int(sub[k2, k1]), k1]  # V^{k1,k2} is stored at [q = k2 - k1][k1]
+
+    done = set()
+    for k1 in range(nk):
+        for k2 in range(nk):
+            if (k1, k2) in done:
+                continue
+            orbit = {(k1, k2), (k2, k1), (int(neg[k1]), int(neg[k2])), (int(neg[k2]), int(neg[k1]))}
+            orig = {m: at(*m).clone() for m in orbit}
+            for (a1, a2) in orbit:
+                a = orig[(a1, a2)]
+                b = orig[(a2, a1)].transpose(1, 2).conj()
+                c = orig[(int(neg[a1]), int(neg[a2]))].conj()
+                d = orig[(int(neg[a2]), int(neg[a1]))].transpose(1, 2)
+                at(a1, a2).copy_(0.25 * (a + b + c + d))
+            done |= orbit
+
+
 def make_V(spec: SystemSpec, device="cuda:0", out: torch.Tensor | None = None) -> torch.Tensor:
-    """V[q][k] = V^{k,k+q}(Q) on `device`, identical in construction to synth.systems.make_V
-    (no time-reversal variant)."""
-    if spec.v_time_reversal:
-        raise NotImplementedError("the time-reversal-symmetric variant is generated on the host")
+    """V[q][k] = V^{k,k+q}(Q) on `device`, identical in construction to synth.systems.make_V."""
     nk = spec.nk
     add = k_add_table(spec.kmesh)
     env = (spec.amp * torch.exp(-spec.v_decay * torch.arange(spec.naux, dtype=torch.float64))).to(device)
@@ -83,6 +108,8 @@ def make_V(spec: SystemSpec, device="cuda:0", out: torch.Tensor | None = None) -
                 out[q, k] = _block(spec, k, k2, env, device)
             else:
                 out[q, k] = _block(spec, k2, k, env, device).conj().transpose(1, 2)
+    if spec.v_time_reversal:
+        _impose_time_reversal(spec, out)
     return out
 
 

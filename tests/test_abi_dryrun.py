@@ -206,3 +206,24 @@ def test_gf2_in_bounds_and_argument_checks(lib, ci, prec):
         assert L.green_gf2_selfenergy(h, V, G, Sig, ws, None) == -1
     finally:
         L.green_plan_destroy(h)
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("ci", [0, 1, 3, 4, 5, 6])
+def test_time_reversal_in_bounds(lib, ci, prec):
+    """Time reversal (only k with -k >= k contracted, partners conjugated): every contraction of the
+    self-energy stays inside its buffers, standalone and inside the iteration, up to the 4x4x4 shape."""
+    c = CASES[ci]
+    L = lib.LIB
+    h = _plan(lib, c, prec)
+    try:
+        V, G, Pt, Sig, H0, S, Sinf, ws = [BASE + i * STEP for i in range(8)]
+        assert L.green_plan_set_option(h, lib.OPT_TIME_REVERSAL, 2) == -1
+        assert L.green_plan_set_option(h, lib.OPT_TIME_REVERSAL, 1) == 0
+        assert L.green_gw_selfenergy(h, V, G, Pt, Sig, ws, None) == 0
+        rep = lib.Report()
+        mu = ctypes.c_double(0.0)
+        assert L.green_gw_iterate(h, V, H0, S, G, Sinf, Sig, ctypes.byref(mu), 3.0, 1.0, ctypes.byref(rep), ws,
+                                  None) == 0
+    finally:
+        L.green_plan_destroy(h)

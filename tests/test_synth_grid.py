@@ -181,3 +181,23 @@ def test_device_generator_matches_host():
     Vh = systems.make_V(sp)
     Vd = device.make_V(sp, device="cpu").numpy()
     assert np.max(np.abs(Vh - Vd)) < 1e-14 * np.max(np.abs(Vh))
+
+
+def test_device_generator_time_reversal_variant():
+    """The time-reversal-symmetric V from the torch generator matches the NumPy one to rounding and satisfies
+    V^{-k1,-k2}(Q) = conj V^{k1,k2}(Q) and V^{k2,k1}(Q) = V^{k1,k2}(Q)^dagger to rounding."""
+    from synth import device
+    for kmesh in [(3, 2, 1), (2, 2, 2)]:
+        sp = configs.tiny(kmesh=kmesh, nao=3, naux=5, ntau=8, seed=23, v_time_reversal=True)
+        Vh = systems.make_V(sp)
+        Vd = device.make_V(sp, device="cpu").numpy()
+        scale = np.max(np.abs(Vh))
+        assert np.max(np.abs(Vh - Vd)) < 1e-14 * scale
+        sub, neg = systems.k_sub_table(kmesh), systems.k_neg(kmesh)
+
+        def blk(k1, k2):
+            return Vd[sub[k2, k1], k1]
+        for k1 in range(sp.nk):
+            for k2 in range(sp.nk):
+                assert np.max(np.abs(blk(neg[k1], neg[k2]) - np.conj(blk(k1, k2)))) < 1e-15 * scale
+                assert np.max(np.abs(blk(k2, k1) - np.conj(np.swapaxes(blk(k1, k2), 1, 2)))) < 1e-15 * scale
