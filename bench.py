@@ -119,6 +119,38 @@ def time_kpath(plan, system, H0, S, Sinf, Sig, mu, npath):
     return {"points": npath, "interpolation_ms": round((t1 - t0) * 1e3, 3), "dyson_ms": round((t3 - t2) * 1e3, 3)}
 
 
+def time_reversal_leg(steps, warmup, tune=True):
+    """The 3x3x3 shapes on time-reversal-symmetric inputs (plans with the time-reversal option): FP64 and split
+    BF16, each tuned, one accuracy iteration, `warmup` + `steps` timed; returns a summary for the JSON line."""
+    import numpy as np
+    import torch
+    from synth import configs, systems
+    from synth import device as dgen
+    spec = configs.PERIODIC_3_TR
+    system = systems.make_system(spec, with_V=False)
+    system.V_dev = dgen.make_V(spec, device="cuda:0")
+    res = {p: run_precision(system, p, steps, warmup, tune=tune) for p in ("fp64", "bf16x3")}
+    ref = res["fp64"]["first"]
+    out = {"workload": spec.name, "precisions": {}}
+    for p, r in res.items():
+        dom = max(range(2), key=lambda i: r["kern"][i]["ms"])
+        k = r["kern"][dom]
+        out["precisions"][p] = {
+            "s_per_iteration": round(r["s_per_iteration"], 6),
+            "sigma_eval_tflops": round(r["sigma_eval_tflops"], 4),
+            "d_energy_eh": abs(r["first"]["e_tot"] - ref["e_tot"]),
+            "max_dsigma_vs_fp64_eh": float(np.max(np.abs(r["first"]["sigma"] - ref["sigma"]))),
+            "stage_ms": r["stage_ms"],
+            "dominant_kernel": {"kernel": r["kernel_names"][dom], "achieved_tflops": round(k["tflops"], 4),
+                                "frac": round(k["tflops"] / PEAK_TFLOPS[p], 4),
+                                "avg_launch_ms": round(k["ms"] / max(k["launches"], 1), 4)}}
+    out["speedup_vs_fp64"] = round(res["fp64"]["s_per_iteration"] / res["bf16x3"]["s_per_iteration"], 3)
+    system.V_dev = None
+    del res
+    torch.cuda.empty_cache()
+    return out
+
+
 def gf2_flops(nk, nao, naux, ntau, nspin) -> float:
     """Algorithmic real flops of one GF2 self-energy (Eq. sigma2): the direct term (the P~0 and Sigma~
     contractions) plus the exchange term, per spin and tau node 2 nk^2 naux nao^3 (V G products) +
@@ -487,8 +519,12 @@ def main():
     ap.add_argument("--kpath", type=int, default=0,
                     help="after the timed steps, interpolate the self-energy onto this many k-path points and "
                          "solve Dyson there (Sec. 2.4 post-processing), timed separately")
-    ap.add_argument("--no-gf2", dest="gf2", action="store_false",
-                    help="skip the GF2 self-energy (Eq. sigma2) timing on the 2x2x2 workload that follows the GW run")
+    ap.add_argument("--tr", dest="tr_leg", action="store_true",
+                    help="after the GW run, also run the time-reversal-symmetric 3x3x3 inputs with the time-reversal "
+                         "option (FP64 and split BF16) into a `time_reversal` object (standalone: --workload periodic3tr)")
+    ap.add_argument("--gf2", dest="gf2", action="store_true",
+                    help="after the GW run, also time the GF2 self-energy (Eq. sigma2) on the 2x2x2 workload into a "
+                         "`gf2` object (standalone: --gf2-only)")
     ap.add_argument("--gf2-only", action="store_true", help="time only the GF2 self-energy (prints its JSON)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain device-to-device copy of this many MiB (counter calibration)")
@@ -606,10 +642,13 @@ def main():
     if not args.no_cpu_baseline:
         system.V = system.V_dev.cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(system, args.cpu_baseline_seconds)
-    if args.gf2:
+    if args.tr_leg or args.gf2:
         del res, h
         system.V_dev = None
         torch.cuda.empty_cache()
+    if args.tr_leg and args.workload == "periodic3":
+        out["time_reversal"] = time_reversal_leg(args.steps, args.warmup, tune=args.tune)
+    if args.gf2:
         out["gf2"] = time_gf2(precs, max(args.steps, 1), tune=args.tune)
     print(json.dumps(out), flush=True)
 
