@@ -54,8 +54,9 @@ __global__ void k_density(const double2* __restrict__ G, double2* __restrict__ g
 // A[b] = I - A[b]  (n x n, batch stride n*n)
 // dst[t][j][i] = src[nt - 1 - t][i][j] (conjugated if conj) for t in [t_lo, t_hi): one 32 x 32 tile of one t
 // per block, transposed through LDS so that both the reads and the writes are row-contiguous.
-__global__ __launch_bounds__(256) void k_transpose_reverse(const double2* __restrict__ src, double2* __restrict__ dst,
-                                                           int n, int nt, int t_lo, int conj) {
+// (src and dst may be one array, read and written on disjoint t ranges: no __restrict__.)
+__global__ __launch_bounds__(256) void k_transpose_reverse(const double2* src, double2* dst, int n, int nt, int t_lo,
+                                                           int conj) {
   __shared__ double2 tile[32][33];
   const int tiles = (n + 31) / 32;
   const int ti = blockIdx.x % tiles, tj = blockIdx.x / tiles;  // source tile rows ti, columns tj

@@ -76,12 +76,17 @@ def test_all_launches_in_bounds(lib, c, prec):
         lib.LIB.green_plan_destroy(h)
 
 
+@pytest.mark.parametrize("opts", ["plain", "options"])
 @pytest.mark.parametrize("prec", [0, 2], ids=["fp64", "bf16x3"])
-def test_batched_iteration_in_bounds(lib, prec):
+def test_batched_iteration_in_bounds(lib, prec, opts):
     """The batched iteration records every system's contractions with the same validation and
-    groups them; with fake addresses nothing is launched."""
+    groups them; with fake addresses nothing is launched.  "options": one system with time reversal, one
+    with the GF2 self-energy."""
     cases = [CASES[0], CASES[1], CASES[5], CASES[6]]
     hs = [_plan(lib, c, prec) for c in cases]
+    if opts == "options":
+        assert lib.LIB.green_plan_set_option(hs[1], lib.OPT_TIME_REVERSAL, 1) == 0
+        assert lib.LIB.green_plan_set_option(hs[2], lib.OPT_GF2, 1) == 0
     try:
         n = len(hs)
         handles = (ctypes.c_void_p * n)(*[h.value for h in hs])
