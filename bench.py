@@ -470,7 +470,8 @@ def run_batch(args):
         "sequential_fp64_s_per_iteration": round(seq, 6),
         "speedup_vs_sequential_fp64": round(seq / h["s_per_iteration"], 3),
         "aggregate_flops_per_iteration": flops,
-        "precisions": {q: {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items() if k != "first"}
+        "precisions": {q: {k: (round(v, 6) if isinstance(v, float) and not k.startswith(("d_", "max_d")) else v)
+                           for k, v in r.items() if k != "first"}
                        for q, r in res.items()},
         "roofline": None,
         "cpu_baseline": None,
