@@ -146,7 +146,7 @@ struct XgvArgs {
   int32_t nao, naux, nk, tcn, qsplit;
   int64_t x_tt, x_k, g_tt;
 };
-// partial sums per Q' slice of the fused kernel (its b blocks split over that many waves)
+// partial sums per Q' slice of the fused kernel (its b blocks split over that many waves: 2 for nao > 16)
 int xgv_halves(int nao);
 hipError_t sigma_xgv(const XgvArgs& a, const ZGemm& reduce, hipStream_t s);
 // out[b][c][r] = in[b][r][c] rounded to kC32 or kCB16 (rows x cols matrices, batch of them).  quad (kCB16,

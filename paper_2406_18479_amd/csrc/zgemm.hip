@@ -1962,7 +1962,7 @@ hipError_t convert_c64_t(const double2* in, void* out, int32_t etype, int n, int
   return hipGetLastError();
 }
 
-int xgv_halves(int nao) { return nao > 16 && nao <= 32 ? 2 : 1; }
+int xgv_halves(int nao) { return nao > 16 ? 2 : 1; }
 
 hipError_t sigma_xgv(const XgvArgs& a, const ZGemm& reduce, hipStream_t s) {
   if (a.tcn <= 0 || a.nk <= 0 || a.naux <= 0) return hipSuccess;
@@ -1973,7 +1973,7 @@ hipError_t sigma_xgv(const XgvArgs& a, const ZGemm& reduce, hipStream_t s) {
   const dim3 grid((unsigned)((int64_t)a.tcn * a.nk * a.qsplit));
   if (a.nao <= 16) sigma_xgv_kernel<1, 1><<<grid, dim3(64), 0, s>>>(a);
   else if (a.nao <= 32) sigma_xgv_kernel<2, 2><<<grid, dim3(256), 0, s>>>(a);
-  else sigma_xgv_kernel<4, 1><<<grid, dim3(256), 0, s>>>(a);
+  else sigma_xgv_kernel<4, 2><<<grid, dim3(512), 0, s>>>(a);
   const int64_t total = (int64_t)reduce.M * reduce.N * reduce.batch;
   int64_t nb = (total + 255) / 256;
   if (nb > 65536) nb = 65536;
