@@ -281,7 +281,7 @@ int green_gw_iterate_diis(green_plan* plan, const void* V, const void* H0, const
  *                   green_gw_polarization contracts the first half of the tau nodes only (the second half is
  *                   the conjugate transpose), and green_gw_selfenergy only the momenta k with -k >= k (flat
  *                   index), each partner written as the complex conjugate; the same inside the iterations and
- *                   the direct term of green_gf2_selfenergy.  Results on inputs without the symmetry are wrong,
+ *                   in green_gf2_selfenergy (both terms).  Results on inputs without the symmetry are wrong,
  *                   not flagged.  0 (default): every tau node and every k is contracted.
  * Returns GREEN_EINVAL for an unknown option or value. */
 #define GREEN_OPT_TUNE 1

@@ -854,9 +854,16 @@ int run_gf2_exchange(green_plan* p, const void* V, const void* G, void* Sig, voi
   if (!p->gf2 || p->r_g2tab.bytes == 0) return GREEN_EINVAL;
   const int32_t* kadd = at<int32_t>(ws, p->r_kadd);
   const int32_t* hadd = p->kadd.data();
-  const int32_t* tab = at<int32_t>(ws, p->r_g2tab);
-  const int32_t* htab = p->g2tab.data();
   const int64_t ntrip = (int64_t)nk2 * nk;
+  // time reversal: only the triples of the momenta k with -k >= k (second half of the tables), the partners'
+  // Sigma~ conjugated at the end
+  const bool tr = p->trev;
+  const int nkx = tr ? (int)p->kcan.size() : nk;
+  const int64_t ntab = (int64_t)nkx * nk2;
+  const int32_t* tab = at<int32_t>(ws, p->r_g2tab) + (tr ? 4 * ntrip : 0);
+  const int32_t* htab = p->g2tab.data() + (tr ? 4 * ntrip : 0);
+  const int32_t* kcan = at<int32_t>(ws, p->r_kcan);
+  const int32_t* hcan = p->kcan.data();
   // Split-BF16 plans keep the pair products, V and the four-index products in split BF16, the operand of the
   // auxiliary sums that runs along the rows transposed (Q contiguous), so those sums run on the large-tile
   // kernel: F (Q-major) and F^T ([pair][(i,q)][Q]) share the first region, F'^T and the rounded V the second.
@@ -898,14 +905,14 @@ int run_gf2_exchange(green_plan* p, const void* V, const void* G, void* Sig, voi
                        sG, C, rev ? sFm : sFp, tr ? two(nao, (int64_t)nao * naux, 1) : flat(nao),
                        tr ? flat(naux) : flat(1), bflat(nV), naux * nao, nao, nao, nk2, cplx(1), cplx(0), s, prec, et));
       }
-      for (int k0 = 0; k0 < nk;) {
+      for (int k0 = 0; k0 < nkx;) {
         // chunk: kc whole momenta k (pc = nk^2 pairs each), or pairs [p0, p0 + pc) of one k
-        const int kc = pc_max == nk2 ? (int)std::min<int64_t>(nk - k0, std::max<int64_t>(1, cap / nk2)) : 1;
+        const int kc = pc_max == nk2 ? (int)std::min<int64_t>(nkx - k0, std::max<int64_t>(1, cap / nk2)) : 1;
         for (int p0 = 0; p0 < nk2;) {
           const int pc = pc_max == nk2 ? nk2 : (int)std::min<int64_t>(nk2 - p0, pc_max);
           const int64_t b0 = (int64_t)k0 * nk2 + p0, nb = (int64_t)kc * pc;
-          if (b0 + nb > ntrip || nb * nG2 * green::elem_bytes(et) > (int64_t)p->r_X2.bytes) return GREEN_EINVAL;
-          auto tb = [&](int which) { return btwo(green::kFlat, nV, tab + which * ntrip + b0, 0, htab + which * ntrip + b0); };
+          if (b0 + nb > ntab || nb * nG2 * green::elem_bytes(et) > (int64_t)p->r_X2.bytes) return GREEN_EINVAL;
+          auto tb = [&](int which) { return btwo(green::kFlat, nV, tab + which * ntab + b0, 0, htab + which * ntab + b0); };
           // X[b][(i,q)][(m,l)] = sum_Q F(k,k1)[Q][(i,q)] F(k3,k2)[Q][(m,l)]
           GREEN_TRY(gemm(green::Site::GF2_Pair, "GF2.X",
                          bf ? op(FpT, flat(naux), flat(1), tb(0), et) : op(Fp, flat(1), flat(nG), tb(0)), sFp,
@@ -922,14 +929,21 @@ int run_gf2_exchange(green_plan* p, const void* V, const void* G, void* Sig, voi
           GREEN_TRY(gemm(green::Site::GF2_Contract, "GF2.contract",
                          op(X, flat(n3), two((int32_t)n3, 1, nG2), bflat((int64_t)pc * nG2), et), sX,
                          op(Z, two((int32_t)n3, nao, nG2), flat(1), bflat((int64_t)pc * nG2), et), sZ,
-                         static_cast<double2*>(Sig) + (((int64_t)sp * ntau + t) * nk + k0) * nG, sS, flat(nao), flat(1),
-                         bflat(nG), nao, nao, (int)(pc * n3), kc, cplx(-1.0 / ((double)nk * nk)), cplx(1.0), s, prec,
-                         green::kC64, 0, 256));
+                         static_cast<double2*>(Sig) + (((int64_t)sp * ntau + t) * nk + (tr ? 0 : k0)) * nG, sS,
+                         flat(nao), flat(1), tr ? btwo(kc, nG, kcan + k0, 0, hcan + k0) : bflat(nG), nao, nao,
+                         (int)(pc * n3), kc, cplx(-1.0 / ((double)nk * nk)), cplx(1.0), s, prec, green::kC64, 0,
+                         256));
           p0 += pc;
         }
         k0 += kc;
       }
     }
+  if (tr) {
+    const int32_t* kneg = at<int32_t>(ws, p->r_kneg);
+    GREEN_TRY(aux(s, [=](hipStream_t st_) {
+      return green::launch_conj_partner(static_cast<double2*>(Sig), (int64_t)ns * ntau, nk, nG, kneg, st_);
+    }));
+  }
   return GREEN_OK;
 }
 
@@ -952,6 +966,14 @@ void enable_gf2(green_plan* p) {
         p->g2tab[2 * ntrip + b] = blk(k3, k2);
         p->g2tab[3 * ntrip + b] = blk(k2, k);
       }
+  // the same rows for the momenta k with -k >= k only (time reversal), after the full tables
+  const int nkh = (int)p->kcan.size();
+  const int64_t nh = (int64_t)nkh * nk * nk;
+  p->g2tab.resize(4 * ntrip + 4 * nh);
+  for (int w = 0; w < 4; ++w)
+    for (int kk = 0; kk < nkh; ++kk)
+      for (int64_t pr = 0; pr < (int64_t)nk * nk; ++pr)
+        p->g2tab[4 * ntrip + w * nh + kk * (int64_t)nk * nk + pr] = p->g2tab[w * ntrip + (int64_t)p->kcan[kk] * nk * nk + pr];
   // four-index chunks: half the contraction budget each, between one triple and all of them
   const int64_t per = nG2 * 16;
   const int64_t want = std::max<int64_t>(1, (int64_t)(p->chunk_bytes / 2) / per);
@@ -962,7 +984,7 @@ void enable_gf2(green_plan* p) {
     r.bytes = bytes;
     off += (bytes + 255) & ~(size_t)255;
   };
-  take(p->r_g2tab, (size_t)(4 * ntrip * 4));
+  take(p->r_g2tab, p->g2tab.size() * 4);
   take(p->r_Fp, (size_t)nk * nk * nV * 16);
   take(p->r_Fm, (size_t)nk * nk * nV * 16);
   take(p->r_X2, (size_t)(trips * per));

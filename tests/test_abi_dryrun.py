@@ -180,9 +180,10 @@ def test_kpath_interpolation_in_bounds_and_argument_checks(lib):
             L.green_plan_destroy(h)
 
 
+@pytest.mark.parametrize("trev", [0, 1], ids=["all_k", "time_reversal"])
 @pytest.mark.parametrize("prec", [0, 1, 2], ids=["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("ci", [0, 1, 2, 5, 6])
-def test_gf2_in_bounds_and_argument_checks(lib, ci, prec):
+def test_gf2_in_bounds_and_argument_checks(lib, ci, prec, trev):
     """GF2 (Eq. sigma2): the option grows the workspace; every contraction of the exchange term, in whole-k
     and in partial-k chunks (chunk=1: one momentum triple per chunk), stays inside its buffers, standalone
     and inside the iteration; the entry point is refused without the option."""
@@ -192,6 +193,7 @@ def test_gf2_in_bounds_and_argument_checks(lib, ci, prec):
     try:
         V, G, Sig, H0, S, Sinf, ws = [BASE + i * STEP for i in range(7)]
         assert L.green_gf2_selfenergy(h, V, G, Sig, ws, None) == -1
+        assert L.green_plan_set_option(h, lib.OPT_TIME_REVERSAL, trev) == 0
         ws0 = L.green_workspace_bytes(h)
         assert L.green_plan_set_option(h, lib.OPT_GF2, 2) == -1
         assert L.green_plan_set_option(h, lib.OPT_GF2, 1) == 0

@@ -119,3 +119,25 @@ def test_time_reversal_polarization_matches_oracle(c):
     say("time reversal polarization", c)
     got = host(_plan(s, "fp64", True).polarization(dev(s.V), dev(s.G0)))
     assert rel(got, ogw.polarization(s.V, s.G0, sp.kmesh)) <= 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_time_reversal_gf2(prec):
+    """GF2 (Eq. sigma2) with the option: both terms contracted for k with -k >= k, partners conjugated; FP64
+    against the oracle at 1e-10, split BF16 against the same plan without the option at 1e-6."""
+    _require_gpu()
+    c = CASES[0]
+    s = _system(c)
+    sp = s.spec
+    say("time reversal gf2", prec, c)
+    V, G = dev(s.V), dev(s.G0)
+    p = _plan(s, prec, True)
+    p.set_option("gf2", 1)
+    got = host(p.gf2_selfenergy(V, G))
+    _partners_exact(got, sp.kmesh)
+    if prec == "fp64":
+        assert rel(got, ogw.gf2_selfenergy(s.V, s.G0, sp.kmesh)) <= 1e-10
+    else:
+        q = _plan(s, prec, False)
+        q.set_option("gf2", 1)
+        assert rel(got, host(q.gf2_selfenergy(V, G))) <= 1e-6
