@@ -896,14 +896,15 @@ int run_gf2_exchange(green_plan* p, const void* V, const void* G, void* Sig, voi
       // (split BF16: F as given and transposed, F' transposed only)
       for (int pass = 0; pass < (bf ? 3 : 2); ++pass) {
         const bool rev = bf ? pass == 2 : pass == 1;
-        const bool tr = bf && pass >= 1;
+        const bool trans = bf && pass >= 1;  // stored transposed, [pair][(i,q)][Q]
         const int tn = rev ? ntau - 1 - t : t;
-        void* C = rev ? Fm : (tr ? FpT : Fp);
+        void* C = rev ? Fm : (trans ? FpT : Fp);
         GREEN_TRY(gemm(green::Site::GF2_VG, rev ? "GF2.VGrev" : "GF2.VG", op(V, flat(nao), flat(1), bflat(nV)), sV,
                        op(static_cast<const double2*>(G) + ((int64_t)sp * ntau + tn) * nk * nG, flat(nao), flat(1),
                           btwo(nk2, nG, kadd, 0, hadd)),
-                       sG, C, rev ? sFm : sFp, tr ? two(nao, (int64_t)nao * naux, 1) : flat(nao),
-                       tr ? flat(naux) : flat(1), bflat(nV), naux * nao, nao, nao, nk2, cplx(1), cplx(0), s, prec, et));
+                       sG, C, rev ? sFm : sFp, trans ? two(nao, (int64_t)nao * naux, 1) : flat(nao),
+                       trans ? flat(naux) : flat(1), bflat(nV), naux * nao, nao, nao, nk2, cplx(1), cplx(0), s, prec,
+                       et));
       }
       for (int k0 = 0; k0 < nkx;) {
         // chunk: kc whole momenta k (pc = nk^2 pairs each), or pairs [p0, p0 + pc) of one k
