@@ -167,3 +167,33 @@ def test_batch_handle_graph_replay_equals_per_system(prec):
                     assert np.array_equal(host(y1[key]), host(y2[key])), (it, i, key)
                 assert y1["mu"] == y2["mu"] and ra[i]["e_tot"] == rb[i]["e_tot"]
         batch.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_batched_iteration_with_options(prec):
+    """A batch mixing a time-reversal plan (on time-reversal-symmetric inputs), a GF2 plan and a plain plan
+    equals the per-system iterations bit for bit."""
+    _require_gpu()
+    from paper_2406_18479_amd.gw import iterate_batched
+    specs = [configs.tiny(kmesh=(3, 1, 1), nao=8, naux=24, ntau=12, beta=10.0, seed=411, v_time_reversal=True),
+             configs.tiny(kmesh=(2, 1, 1), nao=6, naux=18, ntau=12, beta=10.0, seed=412),
+             configs.tiny(kmesh=(1, 1, 1), nao=10, naux=40, ntau=16, beta=20.0, seed=413)]
+    sys_ = [systems.make_system(sp) for sp in specs]
+
+    def plans():
+        ps = [plan(s, prec) for s in sys_]
+        ps[0].set_option("time_reversal", 1)
+        ps[1].set_option("gf2", 1)
+        return ps
+    pa, pb = plans(), plans()
+    ya = [state(s, p) for s, p in zip(sys_, pa)]
+    yb = [state(s, p) for s, p in zip(sys_, pb)]
+    for it in range(2):
+        print(f"[gpu-case] batched iteration with options {it} {prec}", flush=True)
+        ra = [iterate(p, y) for p, y in zip(pa, ya)]
+        mus, rb = iterate_batched(pb, yb)
+        for i, (y1, y2) in enumerate(zip(ya, yb)):
+            y2["mu"] = mus[i]
+            for key in ("G", "Sigma", "Sinf"):
+                assert np.array_equal(host(y1[key]), host(y2[key])), (it, i, key)
+            assert ra[i]["e_tot"] == rb[i]["e_tot"]
