@@ -283,6 +283,13 @@ int green_gw_iterate_diis(green_plan* plan, const void* V, const void* H0, const
  *                   index), each partner written as the complex conjugate; the same inside the iterations and
  *                   in green_gf2_selfenergy (both terms).  Results on inputs without the symmetry are wrong,
  *                   not flagged.  0 (default): every tau node and every k is contracted.
+ *   GREEN_OPT_V_HALF  1: Hermitian half store of V.  Since V^{k2,k1}(Q) = V^{k1,k2}(Q)^dagger, the slab of q
+ *                   (V[q][k] = V^{k,k+q}) follows from that of -q: the caller passes only the slabs of the
+ *                   canonical q (-q >= q, flat index), in increasing q, as V[nqc][nk][naux][nao][nao] (the 3x3x3 mesh:
+ *                   14 of 27 slabs, 4x4x4: 36 of 64).  The other slabs are written into the workspace one at a time
+ *                   when used (the workspace grows by one slab, nk naux nao^2 complex: query green_workspace_bytes
+ *                   after setting it).  Results equal those of the full store bit for bit when the full V has the
+ *                   exact pairing.  Not with GREEN_OPT_GF2 (GREEN_EINVAL): its exchange term reads every slab at once.
  * Returns GREEN_EINVAL for an unknown option or value. */
 #define GREEN_OPT_TUNE 1
 #define GREEN_OPT_GRAPH 2
@@ -291,6 +298,7 @@ int green_gw_iterate_diis(green_plan* plan, const void* V, const void* H0, const
 #define GREEN_OPT_SIGMA_FUSED 5
 #define GREEN_OPT_GF2 6
 #define GREEN_OPT_TIME_REVERSAL 7
+#define GREEN_OPT_V_HALF 8
 int green_plan_set_option(green_plan* plan, int option, int value);
 
 /* Text table of the autotuner's decisions into buf (host, len bytes, NUL-terminated; GREEN_ENOMEM when

@@ -75,6 +75,7 @@ OPT_STAGE1_TILE = 4
 OPT_SIGMA_FUSED = 5
 OPT_GF2 = 6
 OPT_TIME_REVERSAL = 7
+OPT_V_HALF = 8
 
 EXPORTS = ["green_plan_create", "green_plan_destroy", "green_workspace_bytes", "green_gw_polarization",
            "green_gw_screen", "green_gw_selfenergy", "green_hf_static", "green_dyson", "green_gw_iterate",

@@ -74,11 +74,16 @@ struct green_plan {
   // the complex conjugates of their partners; ksubc[q][kk] = kcan[kk] - q
   bool trev = false;
   std::vector<int32_t> kcan, ksubc;
+  // Hermitian half store of V: the caller passes the slabs of the canonical q only (in qcan order); qslot[q] is
+  // the slab of q there, -1 for the others (built from their partners on use)
+  bool vhalf = false;
+  std::vector<int32_t> qslot;
   // workspace regions
   Region r_TF_t2w, r_TF_w2t, r_TB_t2w, r_TB_w2t, r_Emass, r_wf, r_kadd, r_ksub, r_qcan, r_status, r_scal, r_partial;
   Region r_P, r_Pw, r_T1, r_T2, r_gam, r_gamT, r_D, r_Sinfn, r_Sign, r_Sw, r_A, r_tr, r_split, r_Vx, r_Ptx, r_Gx, r_GTx;
   Region r_g2tab, r_Fp, r_Fm, r_X2, r_Z2;  // GF2 (empty until GREEN_OPT_GF2 is set)
   Region r_kneg, r_kcan, r_ksubc;
+  Region r_Vh;  // one partner slab of the half store (empty until GREEN_OPT_V_HALF is set)
   size_t ws_bytes = 0;
   void* bound_ws = nullptr;
   hipEvent_t ev[kNumEvents]{};
@@ -503,13 +508,36 @@ Extents extents(const green_plan* p) {
   const green_dims& d = p->d;
   const int64_t nk = p->nk, nG = (int64_t)d.nao * d.nao, nV = (int64_t)d.naux * nG;
   Extents e;
-  e.V = nk * nk * nV;
+  e.V = (p->vhalf ? (int64_t)p->qcan.size() : nk) * nk * nV;
   e.G = (int64_t)d.nspin * d.ntau * nk * nG;
   e.P = nk * d.ntau * (int64_t)d.naux * d.naux;
   e.H = (int64_t)d.nspin * nk * nG;
   e.S = nk * nG;
   e.Sig = e.G;
   return e;
+}
+
+// V slab of momentum transfer q, V[q][k] = V^{k,k+q}: the caller's array, or with the Hermitian half store the
+// slot of a canonical q, or for the others the partner V^{k,k+q} = (V^{k+q,k})^dagger = (V[-q][k+q])^dagger
+// written into the workspace (one slab at a time: of q and -q at most one is not canonical).
+int v_slab(green_plan* p, const void* V, int q, void* ws, hipStream_t s, const void** ptr, green::Span* sp) {
+  const int nk = p->nk, naux = p->d.naux, nao = p->d.nao;
+  const int64_t slab = (int64_t)nk * naux * nao * nao;
+  const Extents ex = extents(p);
+  if (!p->vhalf || p->qslot[q] >= 0) {
+    *ptr = eptr(V, green::kC64, (p->vhalf ? p->qslot[q] : q) * slab);
+    *sp = span(V, ex.V);
+    return GREEN_OK;
+  }
+  const int qn = p->kneg[q];
+  if (p->qslot[qn] < 0 || (int64_t)p->r_Vh.bytes < slab * 16) return GREEN_EINVAL;
+  const double2* in = static_cast<const double2*>(V) + p->qslot[qn] * slab;
+  double2* out = at<double2>(ws, p->r_Vh);
+  const int32_t* kmap = at<int32_t>(ws, p->r_kadd) + (size_t)q * nk;
+  GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::launch_herm_partner(in, out, nk, naux, nao, kmap, st_); }));
+  *ptr = out;
+  *sp = span_ws(ws, p->r_Vh);
+  return GREEN_OK;
 }
 
 // ---------------------------------------------------------------- polarization
@@ -552,8 +580,10 @@ int run_polarization(green_plan* p, const void* V, const void* G, void* P0, void
     const int qn = p->kneg[q];
     if (qn < q) continue;
     const int t_end = (qn == q || p->trev) ? ntau / 2 : ntau;
-    const void *Vq = eptr(V, green::kC64, q * slab), *Vqn = eptr(V, green::kC64, qn * slab);
-    green::Span sVs = span(V, ex.V);
+    const void *Vq = nullptr, *Vqn = nullptr;
+    green::Span sVs{}, sVn{};
+    GREEN_TRY(v_slab(p, V, q, ws, s, &Vq, &sVs));
+    GREEN_TRY(v_slab(p, V, qn, ws, s, &Vqn, &sVn));
     if (bf) {
       void* Vx = at<void>(ws, p->r_Vx);
       GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64(static_cast<const double2*>(Vq), Vx, green::kCB16, slab, st_); }));
@@ -561,7 +591,7 @@ int run_polarization(green_plan* p, const void* V, const void* G, void* P0, void
                                               green::kCB16, slab, st_); }));
       Vq = Vx;
       Vqn = qn != q ? eptr(Vx, green::kCB16, slab) : Vx;
-      sVs = span_ws(ws, p->r_Vx);
+      sVs = sVn = span_ws(ws, p->r_Vx);
     }
     for (int t0 = 0; t0 < t_end; t0 += p->tc) {
       const int tcn = std::min(p->tc, t_end - t0);
@@ -576,7 +606,7 @@ int run_polarization(green_plan* p, const void* V, const void* G, void* P0, void
         // T2[tt][k][Q'][d][b] = sum_c V^{k+q,k}_{bc}(Q') G^k_{cd}(beta - tau_tt)   (stored transposed in (b, d));
         // N = (tt, d), G(beta - tau) walks the grid backwards
         GREEN_TRY(gemm(green::Site::P0_VGrev, "P0.VGrev",
-                       op(Vqn, flat(nao), flat(1), btwo(nk, nV, kadd + q * nk, 0, hadd + q * nk), st), sVs,
+                       op(Vqn, flat(nao), flat(1), btwo(nk, nV, kadd + q * nk, 0, hadd + q * nk), st), sVn,
                        op(eptr(Gs, st, ((int64_t)sp * ntau + (ntau - 1 - t0)) * nk * nG), flat(nao),
                           two(nao, 1, -(int64_t)nk * nG), btwo(nk, nG, nullptr, 0), st),
                        sGs, T2, sT2, two(nao, 1, nG), two(nao, nao, (int64_t)nk * nV), bflat(nV), naux * nao,
@@ -713,9 +743,11 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
   }
   for (int q = 0; q < nk; ++q) {
     const int qn = p->kneg[q];
-    const void* Vqn = eptr(V, green::kC64, qn * slab);  // V^{k,k-q}: X = P~^T V
-    const void* Vq = eptr(V, green::kC64, q * slab);    // V^{k-q,k}: Sigma += Y V
-    green::Span sVa = span(V, ex.V), sVb = span(V, ex.V);
+    const void* Vqn = nullptr;  // V^{k,k-q}: X = P~^T V
+    const void* Vq = nullptr;   // V^{k-q,k}: Sigma += Y V
+    green::Span sVa{}, sVb{};
+    GREEN_TRY(v_slab(p, V, qn, ws, s, &Vqn, &sVa));
+    GREEN_TRY(v_slab(p, V, q, ws, s, &Vq, &sVb));
     if (mixed) {
       if ((int64_t)p->r_Vx.bytes < (bf ? 2 : 1) * slab * green::elem_bytes(vt)) return GREEN_EINVAL;
       if (vt_dma) {
@@ -851,7 +883,7 @@ int run_gf2_exchange(green_plan* p, const void* V, const void* G, void* Sig, voi
   const int64_t nG = (int64_t)nao * nao, nV = (int64_t)naux * nG, nG2 = nG * nG, n3 = nG * nao;
   const int nk2 = nk * nk;
   const Extents ex = extents(p);
-  if (!p->gf2 || p->r_g2tab.bytes == 0) return GREEN_EINVAL;
+  if (!p->gf2 || p->r_g2tab.bytes == 0 || p->vhalf) return GREEN_EINVAL;  // needs every V slab at once
   const int32_t* kadd = at<int32_t>(ws, p->r_kadd);
   const int32_t* hadd = p->kadd.data();
   const int64_t ntrip = (int64_t)nk2 * nk;
@@ -998,7 +1030,7 @@ void enable_gf2(green_plan* p) {
 int run_hf(green_plan* p, const void* V, const void* G, void* Sinf, void* ws, hipStream_t s) {
   const green_dims& d = p->d;
   const int nk = p->nk, nao = d.nao, naux = d.naux, ntau = d.ntau, ns = d.nspin;
-  const int64_t nG = (int64_t)nao * nao, nV = (int64_t)naux * nG, slab = (int64_t)nk * nV;
+  const int64_t nG = (int64_t)nao * nao, nV = (int64_t)naux * nG;
   const Extents ex = extents(p);
   const int32_t* ksub = at<int32_t>(ws, p->r_ksub);
   const int32_t* hsub = p->ksub.data();
@@ -1025,13 +1057,17 @@ int run_hf(green_plan* p, const void* V, const void* G, void* Sinf, void* ws, hi
   // exchange: Sinf[s][k] -= (1/nk) sum_q sum_Q V^{k,k-q}(Q) gamma^{k-q} V^{k-q,k}(Q)
   for (int q = 0; q < nk; ++q) {
     const int qn = p->kneg[q];
+    const void *Vn = nullptr, *Vq = nullptr;
+    green::Span sVn{}, sVq{};
+    GREEN_TRY(v_slab(p, V, qn, ws, s, &Vn, &sVn));
+    GREEN_TRY(v_slab(p, V, q, ws, s, &Vq, &sVq));
     for (int sp = 0; sp < ns; ++sp) {
-      GREEN_TRY(gemm(green::Site::HF, "HF.Vgamma", op(Vp + qn * slab, flat(nao), flat(1), bflat(nV)), sV,
+      GREEN_TRY(gemm(green::Site::HF, "HF.Vgamma", op(Vn, flat(nao), flat(1), bflat(nV)), sVn,
                      op(gam + (int64_t)sp * nk * nG, flat(nao), flat(1), btwo(nk, nG, ksub + q * nk, 0, hsub + q * nk)),
                      sGam, T2, sT2, flat(nao), flat(1), bflat(nV), naux * nao, nao, nao, nk, cplx(1), cplx(0), s));
       GREEN_TRY(gemm(green::Site::HF, "HF.exchange", op(T2, flat(nao), two(nao, 1, nG), bflat(nV)), sT2,
-                     op(Vp + q * slab, two(nao, nao, nG), flat(1), btwo(nk, nV, ksub + q * nk, 0, hsub + q * nk)),
-                     sV, Sp + (int64_t)sp * nk * nG, sH, flat(nao), flat(1), bflat(nG), nao, nao, naux * nao, nk,
+                     op(Vq, two(nao, nao, nG), flat(1), btwo(nk, nV, ksub + q * nk, 0, hsub + q * nk)),
+                     sVq, Sp + (int64_t)sp * nk * nG, sH, flat(nao), flat(1), bflat(nG), nao, nao, naux * nao, nk,
                      cplx(-1.0 / nk), cplx(1.0), s));
     }
   }
@@ -1501,6 +1537,8 @@ int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, 
   for (int q = 0; q < nk; ++q)
     if (p->kneg[q] >= q) p->qcan.push_back(q);
   p->kcan = p->qcan;  // the same set of momenta
+  p->qslot.assign(nk, -1);
+  for (size_t i = 0; i < p->qcan.size(); ++i) p->qslot[p->qcan[i]] = (int32_t)i;
   const int nkh = (int)p->kcan.size();
   p->ksubc.resize((size_t)nk * nkh);
   for (int q = 0; q < nk; ++q)
@@ -1623,7 +1661,7 @@ int green_gw_selfenergy(green_plan* p, const void* V, const void* G, const void*
 
 int green_gf2_selfenergy(green_plan* p, const void* V, const void* G, void* Sigma, void* ws, void* stream) {
   GREEN_TRY(check_plan(p, ws));
-  if (!V || !G || !Sigma || !p->gf2) return GREEN_EINVAL;
+  if (!V || !G || !Sigma || !p->gf2 || p->vhalf) return GREEN_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
   PlanScope scope(p);
   GREEN_TRY(ensure_bound(p, ws, s));
@@ -1917,6 +1955,18 @@ int green_plan_set_option(green_plan* p, int option, int value) {
       p->big_stage1 = value;
       drop_graph(p);
       return GREEN_OK;
+    case GREEN_OPT_V_HALF:
+      if (value < 0 || value > 1) return GREEN_EINVAL;
+      if (value && p->gf2) return GREEN_EINVAL;
+      if (value && p->r_Vh.bytes == 0) {
+        const size_t bytes = (size_t)p->nk * p->d.naux * p->d.nao * p->d.nao * 16;
+        p->r_Vh.off = p->ws_bytes;
+        p->r_Vh.bytes = bytes;
+        p->ws_bytes += (bytes + 255) & ~(size_t)255;
+      }
+      p->vhalf = value != 0;
+      drop_graph(p);
+      return count_ops(p);
     case GREEN_OPT_TIME_REVERSAL:
       if (value < 0 || value > 1) return GREEN_EINVAL;
       p->trev = value != 0;
@@ -1924,6 +1974,7 @@ int green_plan_set_option(green_plan* p, int option, int value) {
       return count_ops(p);
     case GREEN_OPT_GF2:
       if (value < 0 || value > 1) return GREEN_EINVAL;
+      if (value && p->vhalf) return GREEN_EINVAL;
       if (value) enable_gf2(p);
       p->gf2 = value != 0;
       drop_graph(p);

@@ -14,6 +14,9 @@ hipError_t launch_transpose_reverse(const double2* src, double2* dst, int n, int
 // Time-reversal partners: for every block b < nblk and momentum k with kneg[k] < k,
 // X[b][k] = conj(X[b][kneg[k]]) element by element (blocks of nk matrices of ne elements; kneg on the device).
 hipError_t launch_conj_partner(double2* X, int64_t nblk, int nk, int64_t ne, const int32_t* kneg, hipStream_t s);
+// Hermitian partner slab: out[k][Q][i][j] = conj(in[kmap[k]][Q][j][i]) for k < nk (naux blocks of nao x nao per k).
+hipError_t launch_herm_partner(const double2* in, double2* out, int nk, int naux, int nao, const int32_t* kmap,
+                               hipStream_t s);
 hipError_t launch_one_minus(double2* A, int n, int64_t batch, hipStream_t s);
 hipError_t launch_minus_one(double2* A, int n, int64_t batch, hipStream_t s);
 hipError_t launch_dyson_form(double2* A, const double2* S, const double2* H0, const double2* Sinf,

@@ -298,6 +298,31 @@ __global__ void k_conj_partner(double2* __restrict__ X, int64_t nblk, int nk, in
   }
 }
 
+// 32 x 32 tiles of one (k, Q) block per workgroup, transposed through LDS (both sides row-contiguous).
+__global__ __launch_bounds__(256) void k_herm_partner(const double2* __restrict__ in, double2* __restrict__ out,
+                                                      int naux, int nao, const int32_t* __restrict__ kmap) {
+  __shared__ double2 tile[32][33];
+  const int tiles = (nao + 31) / 32;
+  const int ti = blockIdx.x % tiles, tj = blockIdx.x / tiles;  // source tile rows ti, columns tj
+  const int Q = blockIdx.y, k = blockIdx.z;
+  const int64_t nG = (int64_t)nao * nao;
+  const double2* S = in + ((int64_t)kmap[k] * naux + Q) * nG;
+  double2* D = out + ((int64_t)k * naux + Q) * nG;
+  const int c = threadIdx.x & 31, r0 = threadIdx.x >> 5;
+  for (int r = r0; r < 32; r += 8) {
+    const int i = 32 * ti + r, j = 32 * tj + c;
+    if (i < nao && j < nao) tile[r][c] = S[(int64_t)i * nao + j];
+  }
+  __syncthreads();
+  for (int r = r0; r < 32; r += 8) {
+    const int j = 32 * tj + r, i = 32 * ti + c;  // destination row j, column i
+    if (i < nao && j < nao) {
+      const double2 v = tile[c][r];
+      D[(int64_t)j * nao + i] = make_double2(v.x, -v.y);
+    }
+  }
+}
+
 inline unsigned grid_for(int64_t n) {
   int64_t b = (n + 255) / 256;
   if (b > 65536) b = 65536;
@@ -328,6 +353,16 @@ hipError_t launch_conj_partner(double2* X, int64_t nblk, int nk, int64_t ne, con
   const int64_t n = nblk * nk * ne;
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_conj_partner, dim3(grid_for(n)), dim3(256), 0, s, X, nblk, nk, ne, kneg);
+  return hipGetLastError();
+}
+
+hipError_t launch_herm_partner(const double2* in, double2* out, int nk, int naux, int nao, const int32_t* kmap,
+                               hipStream_t s) {
+  if (nk <= 0 || naux <= 0 || nao <= 0) return hipSuccess;
+  if (nk > 65535 || naux > 65535) return hipErrorInvalidValue;
+  const int tiles = (nao + 31) / 32;
+  k_herm_partner<<<dim3((unsigned)(tiles * tiles), (unsigned)naux, (unsigned)nk), dim3(256), 0, s>>>(in, out, naux,
+                                                                                                    nao, kmap);
   return hipGetLastError();
 }
 

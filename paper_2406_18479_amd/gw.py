@@ -59,8 +59,21 @@ class Plan:
 
     # shapes
     @property
+    def canonical_q(self):
+        """Momentum transfers q with -q >= q (flat index), in increasing order: the slabs of the half store."""
+        m = self.kmesh
+        out = []
+        for q in range(self.nk):
+            a, b, c = q // (m[1] * m[2]), (q // m[2]) % m[1], q % m[2]
+            qn = (((-a) % m[0]) * m[1] + (-b) % m[1]) * m[2] + (-c) % m[2]
+            if qn >= q:
+                out.append(q)
+        return out
+
+    @property
     def shape_V(self):
-        return (self.nk, self.nk, self.naux, self.nao, self.nao)
+        nq = len(self.canonical_q) if getattr(self, "v_half", False) else self.nk
+        return (nq, self.nk, self.naux, self.nao, self.nao)
 
     @property
     def shape_G(self):
@@ -80,12 +93,14 @@ class Plan:
 
     def set_option(self, option: str, value: int) -> None:
         """option "tune" (0, 1, 2), "graph" (0, 1), "p0_tile" (1..6), "stage1_tile" (0..2), "sigma_fused"
-        (0, 1), "gf2" (0, 1) or "time_reversal" (0, 1); see green_plan_set_option.  The workspace is
-        re-allocated when the option grows it (GF2)."""
+        (0, 1), "gf2" (0, 1), "time_reversal" (0, 1) or "v_half" (0, 1: V holds the canonical-q slabs only,
+        shape_V follows); see green_plan_set_option.  The workspace is re-allocated when the option grows it."""
         code = {"tune": _lib.OPT_TUNE, "graph": _lib.OPT_GRAPH, "p0_tile": _lib.OPT_P0_TILE,
                 "stage1_tile": _lib.OPT_STAGE1_TILE, "sigma_fused": _lib.OPT_SIGMA_FUSED,
-                "gf2": _lib.OPT_GF2, "time_reversal": _lib.OPT_TIME_REVERSAL}[option]
+                "gf2": _lib.OPT_GF2, "time_reversal": _lib.OPT_TIME_REVERSAL, "v_half": _lib.OPT_V_HALF}[option]
         _lib.check(_lib.LIB.green_plan_set_option(self._h, code, int(value)), "green_plan_set_option")
+        if option == "v_half":
+            self.v_half = bool(value)
         need = int(_lib.LIB.green_workspace_bytes(self._h))
         if need != self.ws_bytes:
             self.ws_bytes = need

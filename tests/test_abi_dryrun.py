@@ -234,3 +234,31 @@ def test_time_reversal_in_bounds(lib, ci, prec):
                                   None) == 0
     finally:
         L.green_plan_destroy(h)
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("ci", [0, 1, 3, 4, 5, 6])
+def test_v_half_store_in_bounds(lib, ci, prec):
+    """Hermitian half store of V: with only the canonical-q slabs passed, every contraction of every entry point
+    stays inside the smaller V (partner slabs come from the workspace), with and without time reversal; GF2 is
+    refused with it."""
+    c = CASES[ci]
+    L = lib.LIB
+    h = _plan(lib, c, prec)
+    try:
+        V, G, P0, Pt, Sig, H0, S, Sinf, G2, ws = [BASE + i * STEP for i in range(10)]
+        ws0 = L.green_workspace_bytes(h)
+        assert L.green_plan_set_option(h, lib.OPT_V_HALF, 1) == 0
+        assert L.green_workspace_bytes(h) > ws0
+        assert L.green_plan_set_option(h, lib.OPT_GF2, 1) == -1
+        for trev in (0, 1):
+            assert L.green_plan_set_option(h, lib.OPT_TIME_REVERSAL, trev) == 0
+            assert L.green_gw_polarization(h, V, G, P0, ws, None) == 0
+            assert L.green_gw_selfenergy(h, V, G, Pt, Sig, ws, None) == 0
+            assert L.green_hf_static(h, V, G, Sinf, ws, None) == 0
+            rep = lib.Report()
+            mu = ctypes.c_double(0.0)
+            assert L.green_gw_iterate(h, V, H0, S, G, Sinf, Sig, ctypes.byref(mu), 3.0, 1.0, ctypes.byref(rep), ws,
+                                      None) == 0
+    finally:
+        L.green_plan_destroy(h)
