@@ -644,3 +644,144 @@ def test_kpath_interpolation_against_fft():
             ref[p] += w * XR[idx] * np.exp(2j * np.pi * np.dot(path[p], R))
     Y = gw.kpath_interpolate(X, kmesh, path)
     assert np.max(np.abs(Y - ref)) < 1e-13 * np.max(np.abs(ref))
+
+
+# ============================================================================ energy, Dyson with a self-energy, mixing
+def _eig_s(H, S):
+    return scipy.linalg.eigh(H, S)
+
+
+@pytest.mark.parametrize("kmesh,nspin,s_identity", [((1, 1, 1), 1, True), ((1, 1, 1), 1, False),
+                                                    ((2, 1, 1), 2, True)])
+def test_one_body_and_hartree_fock_energy_closed_form(kmesh, nspin, s_identity):
+    """Galitskii-Migdal one-body and Hartree-Fock parts at the non-interacting G0, in the eigenbasis of
+    H C = S C e (C^H S C = I, gamma = C f C^H):
+      E_1b = (2/ns)(1/Nk) sum_{s,k} sum_i f_i e_i,
+      E_HF = (1/ns)(1/Nk^2) sum_{s,k,k'} sum_{ij} f_{ski} f_{s'k'j} [(kk i i | k'k' j j) summed over s'
+             (a restricted channel counted twice)  -  (k k' i j | k' k j i) at s' = s],
+    with (k1 k2 i j | k3 k4 l m) = sum_Q (C^H V^{k1,k2}(Q) C)_{ij} (C^H V^{k3,k4}(Q) C)_{lm} built from
+    explicit four-index integrals of Eq. CoulombDF."""
+    sp = configs.tiny(kmesh=kmesh, nao=4, naux=5, ntau=24, beta=8.0, band=1.2, nspin=nspin,
+                      s_identity=s_identity, seed=123)
+    s = systems.make_system(sp)
+    km = _km(kmesh)
+    nk, ns, nao = sp.nk, sp.nspin, sp.nao
+    Sinf = gw.sigma_inf(s.V, s.G0, kmesh)
+    E = gw.energy(s.G0, s.H0, Sinf, np.zeros((ns, sp.ntau, nk, nao, nao), dtype=complex), sp.beta)
+    C = np.empty((ns, nk, nao, nao), dtype=complex)
+    f = np.empty((ns, nk, nao))
+    e1 = 0.0
+    for sp_ in range(ns):
+        for k in range(nk):
+            e, c = _eig_s(s.H0[sp_, k], s.S[k])
+            C[sp_, k], f[sp_, k] = c, systems.fermi(e, sp.beta)
+            e1 += np.sum(f[sp_, k] * e)
+    e1 *= 2.0 / ns / nk
+    ehf = 0.0
+    for sa in range(ns):
+        for k in range(nk):
+            for sb in range(ns):
+                for kp in range(nk):
+                    A = np.einsum("ai,Qab,bj->Qij", C[sa, k].conj(), gw.V_pair(s.V, km, k, k), C[sa, k])
+                    B = np.einsum("ai,Qab,bj->Qij", C[sb, kp].conj(), gw.V_pair(s.V, km, kp, kp), C[sb, kp])
+                    J = np.einsum("Qii,Qjj->ij", A, B).real
+                    ehf += (2.0 if ns == 1 else 1.0) * np.einsum("i,j,ij->", f[sa, k], f[sb, kp], J)
+                    if sb == sa:
+                        X = np.einsum("ai,Qab,bj->Qij", C[sa, k].conj(), gw.V_pair(s.V, km, k, kp), C[sa, kp])
+                        Y = np.einsum("ai,Qab,bj->Qij", C[sa, kp].conj(), gw.V_pair(s.V, km, kp, k), C[sa, k])
+                        K = np.einsum("Qij,Qji->ij", X, Y).real
+                        ehf -= np.einsum("i,j,ij->", f[sa, k], f[sa, kp], K)
+    ehf *= 1.0 / ns / nk ** 2
+    assert abs(E["e_1b"] - e1) < 1e-12 * max(1.0, abs(e1))
+    assert abs(E["e_hf"] - ehf) < 1e-13 * max(1.0, abs(ehf))
+    assert E["e_corr"] == 0.0
+    assert abs(E["e_tot"] - (e1 + ehf)) < 1e-12 * max(1.0, abs(e1 + ehf))
+
+
+def _embedding(seed, nsys, nbath, spread=1.5, coupling=0.4):
+    """A system block Hs (nsys x nsys, Hermitian), bath levels eb and couplings Wsb of a Hermitian
+    (nsys + nbath) matrix whose bath block is diagonal."""
+    rng = np.random.default_rng(seed)
+    Z = rng.normal(size=(nsys, nsys)) + 1j * rng.normal(size=(nsys, nsys))
+    Hs = 0.5 * spread * (Z + Z.conj().T) / np.sqrt(2 * nsys)
+    eb = rng.uniform(-spread, spread, size=nbath)
+    W = coupling * (rng.normal(size=(nsys, nbath)) + 1j * rng.normal(size=(nsys, nbath))) / np.sqrt(2)
+    return Hs, eb, W
+
+
+def _closed_form_G(H, tau, beta, mu):
+    """-U diag(e^{-(E-mu)tau}/(1+e^{-beta(E-mu)})) U^H for a Hermitian H (S = I), per node."""
+    E, U = np.linalg.eigh(H)
+    x = E - mu
+    w = np.exp(-np.outer(tau, x) - np.logaddexp(0.0, -beta * x)[None, :])
+    return -np.einsum("ia,ta,ja->tij", U, w, U.conj())
+
+
+@pytest.mark.parametrize("nspin,kmesh", [(1, (1, 1, 1)), (2, (2, 1, 1))])
+def test_dyson_with_a_pole_self_energy(nspin, kmesh):
+    """Eq. dyson with a non-zero Sigma~: a system coupled to a bath of levels eb through couplings W has the
+    exact self-energy Sigma~(tau) = W g_b(tau) W^H, g_b the non-interacting bath G(tau) (a sum of poles), and
+    its G is the system block of the non-interacting G of the whole Hermitian matrix [[Hs, W], [W^H, eb]]
+    (Schur complement of the resolvent).  Hs is split as H0 + Sigma^inf, so both static terms enter with their
+    sign.  Checks O9 (Sigma~(tau) -> Sigma~(i w)), O11 and, with a target electron count taken from the closed
+    form at mu* = 0.17, the O10 root on an interacting G."""
+    beta, ntau = 10.0, 64
+    g = gridmod.make_grid(ntau, beta)
+    nsys, nbath = 3, 4
+    nk = int(np.prod(kmesh))
+    H0 = np.empty((nspin, nk, nsys, nsys), dtype=complex)
+    Sinf = np.empty_like(H0)
+    Sig = np.empty((nspin, ntau, nk, nsys, nsys), dtype=complex)
+    Gref = {}
+    S = np.tile(np.eye(nsys, dtype=complex), (nk, 1, 1))
+    mu_star = 0.17
+    n_target = 0.0
+    for s in range(nspin):
+        for k in range(nk):
+            Hs, eb, W = _embedding(1000 + 10 * s + k, nsys, nbath)
+            rng = np.random.default_rng(77 + s + k)
+            Z = rng.normal(size=(nsys, nsys)) + 1j * rng.normal(size=(nsys, nsys))
+            Sinf[s, k] = 0.2 * (Z + Z.conj().T)
+            H0[s, k] = Hs - Sinf[s, k]
+            gb = -np.exp(-np.outer(g.tau, eb - mu_star) - np.logaddexp(0.0, -beta * (eb - mu_star))[None, :])
+            Sig[s, :, k] = np.einsum("ib,tb,jb->tij", W, gb, W.conj())
+            Hfull = np.block([[Hs, W], [W.conj().T, np.diag(eb)]])
+            Gref[s, k] = _closed_form_G(Hfull, g.tau, beta, mu_star)[:, :nsys, :nsys]
+            E, U = np.linalg.eigh(Hfull)
+            n_target += (2.0 / nspin) / nk * np.sum(np.abs(U[:nsys]) ** 2 * systems.fermi(E - mu_star, beta)[None])
+    # mu held at mu*: G(tau) of the embedded system
+    G, mu, n = gw.solve_dyson(H0, S, Sinf, Sig, g, nspin, mu_star, -1.0)
+    for s in range(nspin):
+        for k in range(nk):
+            assert np.max(np.abs(G[s, :, k] - Gref[s, k])) < 1e-10
+    assert abs(n - n_target) < 1e-10
+    # mu searched from 0 for the closed-form electron count of the system orbitals
+    G2, mu2, n2 = gw.solve_dyson(H0, S, Sinf, Sig, g, nspin, 0.0, n_target)
+    assert abs(mu2 - mu_star) < 1e-9
+    assert np.max(np.abs(G2 - G)) < 1e-9
+
+
+def test_mixing_at_alpha_below_one():
+    """Sec. 4.2.2 damping: with 0 < alpha < 1 the self-energy that enters Dyson is alpha Sigma[G_{n-1}] +
+    (1 - alpha) Sigma_{n-1} for both Sigma^inf and Sigma~.  Run one iteration at alpha = 0.6 from a state
+    whose stored self-energies differ from Sigma[G]: the iteration must return the affine combination
+    weighted towards the new self-energy, and its G must be the Dyson solution of that combination."""
+    sp = configs.tiny(kmesh=(2, 1, 1), nao=3, naux=4, ntau=16, beta=6.0, seed=55)
+    s = systems.make_system(sp)
+    Sinf_new, Sig_new, _ = gw.sigma_eval(s.V, s.G0, sp.kmesh, s.grid)
+    rng = np.random.default_rng(5)
+    Sinf_old = Sinf_new + 0.05 * rng.normal(size=Sinf_new.shape)
+    Sig_old = Sig_new + 0.05 * rng.normal(size=Sig_new.shape)
+    st = gw.State(s.G0, Sinf_old, Sig_old, 0.0)
+    alpha = 0.6
+    st2, rep, _ = gw.iterate(s, st, alpha=alpha)
+    # the new self-energy sits at the fraction alpha of the way from the old one: |S - S_old| = alpha |S_new - S_old|
+    for got, new, old in [(st2.Sinf, Sinf_new, Sinf_old), (st2.Sig, Sig_new, Sig_old)]:
+        d_new, d_got = new - old, got - old
+        assert np.allclose(d_got, alpha * d_new, atol=1e-15, rtol=1e-13)
+        assert np.linalg.norm(got - new) < np.linalg.norm(got - old)  # closer to the new self-energy
+    # alpha -> 0 keeps the old self-energy, alpha = 1 takes the new one
+    assert np.allclose(gw.mix(Sig_new, Sig_old, 1e-12), Sig_old, atol=1e-12)
+    assert np.array_equal(gw.mix(Sig_new, Sig_old, 1.0), Sig_new)
+    G, mu, _ = gw.solve_dyson(s.H0, s.S, st2.Sinf, st2.Sig, s.grid, sp.nspin, 0.0, s.n_target)
+    assert np.max(np.abs(G - st2.G)) == 0.0 and mu == st2.mu
