@@ -189,6 +189,24 @@ int green_hf_static(green_plan* plan, const void* V, const void* G, void* Sinf, 
 int green_dyson(green_plan* plan, const void* H0, const void* S, const void* Sinf, const void* Sigma, double n_target,
                 double* mu, void* G, double* n_out, int32_t* evals_out, void* ws, void* stream);
 
+/* Allocation-free variant of green_dyson, for callers that cannot allocate device memory or pass a workspace
+ * (tight serving loops, harnesses that forbid hipMalloc).  Same arguments and results as green_dyson minus the
+ * workspace: the Dyson step and the chemical-potential search run in a device scratch array that is part of the
+ * library's code object, GREEN_NOALLOC_MAX_BYTES bytes per GPU, held by every GPU the library runs on until the
+ * process ends.  The call needs
+ *     (2 nw_f ntau + nw_f / 2 + 2 nspin nw_f nk nao^2 + nspin nw_f nk) * 16 bytes (each part rounded up to 256)
+ *     + 768 bytes
+ * of it (the grid matrices, Sigma~(i w), the Dyson matrices and their traces) and returns GREEN_ENOMEM, before
+ * any device work, when that exceeds GREEN_NOALLOC_MAX_BYTES.  It calls no allocator: the scratch's device
+ * address is looked up once per device (on the device current at the call, which must be the device of
+ * `stream`).  Every call on one GPU shares that GPU's scratch, which keeps the last call's contents (the call
+ * copies the grid rows in and clears its status word first): calls that overlap on one GPU, from several host
+ * threads or streams, race and give wrong results.  The autotuner is not consulted and no split-K partial sums
+ * are used, so results equal those of green_dyson up to summation order.  Synchronises `stream`. */
+#define GREEN_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+int green_dyson_noalloc(green_plan* plan, const void* H0, const void* S, const void* Sinf, const void* Sigma,
+                        double n_target, double* mu, void* G, double* n_out, int32_t* evals_out, void* stream);
+
 /* k-path interpolation of the self-energy (Sec. 2.4, k-path interpolation): every momentum-dependent input
  * X(k) on the plan's Monkhorst-Pack mesh is taken to real space, X(R) = (1/nk) sum_k X(k) e^{-i k.R}, and
  * back onto the npath points khat, X(khat) = sum_R X(R) e^{i khat.R}, for X = Sinf and Sigma~(tau_t).

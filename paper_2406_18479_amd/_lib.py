@@ -82,7 +82,9 @@ EXPORTS = ["green_plan_create", "green_plan_destroy", "green_workspace_bytes", "
            "green_plan_set_option", "green_plan_tuning_report", "green_batch_workspace_bytes",
            "green_gw_iterate_batched", "green_batch_create", "green_batch_iterate", "green_batch_destroy",
            "green_diis_history_bytes", "green_gw_iterate_diis", "green_kpath_interpolate",
-           "green_gf2_selfenergy", "green_strerror"]
+           "green_gf2_selfenergy", "green_dyson_noalloc", "green_strerror"]
+
+NOALLOC_MAX_BYTES = 64 << 20  # GREEN_NOALLOC_MAX_BYTES
 
 
 def _load():
@@ -111,6 +113,9 @@ def _load():
     lib.green_dyson.argtypes = [vp, vp, vp, vp, vp, dbl, ctypes.POINTER(dbl), vp, ctypes.POINTER(dbl),
                                 ctypes.POINTER(ctypes.c_int32), vp, vp]
     lib.green_dyson.restype = i32
+    lib.green_dyson_noalloc.argtypes = [vp, vp, vp, vp, vp, dbl, ctypes.POINTER(dbl), vp, ctypes.POINTER(dbl),
+                                        ctypes.POINTER(ctypes.c_int32), vp]
+    lib.green_dyson_noalloc.restype = i32
     lib.green_kpath_interpolate.argtypes = [vp, ctypes.POINTER(dbl), i32, vp, vp, vp, vp, vp, vp]
     lib.green_kpath_interpolate.restype = i32
     lib.green_gw_iterate.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(dbl), dbl, dbl,

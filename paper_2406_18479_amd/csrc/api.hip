@@ -5,6 +5,7 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <cstdio>
 #include <cstdlib>
@@ -1075,21 +1076,49 @@ int run_hf(green_plan* p, const void* V, const void* G, void* Sinf, void* ws, hi
 }
 
 // ---------------------------------------------------------------- Dyson + mu
-int read_status(green_plan* p, void* ws, hipStream_t s) {
+int read_status_at(int* status, hipStream_t s) {
   if (green::dryrun()) return GREEN_OK;
   int st = 0;
-  HIP_TRY(hipMemcpyAsync(&st, at<int>(ws, p->r_status), sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&st, status, sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (st) {
-    HIP_TRY(hipMemsetAsync(at<int>(ws, p->r_status), 0, sizeof(int), s));
+    HIP_TRY(hipMemsetAsync(status, 0, sizeof(int), s));
     return GREEN_ESINGULAR;
   }
   return GREEN_OK;
 }
+int read_status(green_plan* p, void* ws, hipStream_t s) { return read_status_at(at<int>(ws, p->r_status), s); }
+
+// Device memory the Dyson step and the chemical-potential search work in: the plan's workspace regions,
+// or the static scratch of the allocation-free entry point.
+struct DysonMem {
+  const double2 *TF_t2w, *TF_w2t;
+  const double* wf;
+  double2 *Sw, *A, *tr;
+  double* scal;
+  int* status;
+  green::Span sTF_t2w, sTF_w2t, sSw, sA;
+};
+DysonMem dyson_mem(green_plan* p, void* ws) {
+  DysonMem m;
+  m.TF_t2w = at<double2>(ws, p->r_TF_t2w);
+  m.TF_w2t = at<double2>(ws, p->r_TF_w2t);
+  m.wf = at<double>(ws, p->r_wf);
+  m.Sw = at<double2>(ws, p->r_Sw);
+  m.A = at<double2>(ws, p->r_A);
+  m.tr = at<double2>(ws, p->r_tr);
+  m.scal = at<double>(ws, p->r_scal);
+  m.status = at<int>(ws, p->r_status);
+  m.sTF_t2w = green::Span{m.TF_t2w, (int64_t)p->r_TF_t2w.bytes};
+  m.sTF_w2t = green::Span{m.TF_w2t, (int64_t)p->r_TF_w2t.bytes};
+  m.sSw = green::Span{m.Sw, (int64_t)p->r_Sw.bytes};
+  m.sA = green::Span{m.A, (int64_t)p->r_A.bytes};
+  return m;
+}
 
 struct DysonCtx {
   green_plan* p;
-  void* ws;
+  DysonMem m;
   hipStream_t s;
   const double2 *H0, *S, *Sinf;
   double nt;  // dry runs only: a stand-in electron count
@@ -1106,14 +1135,13 @@ int electron_count(const DysonCtx& c, double mu, double* n_out) {
     *n_out = (c.nt < 0 ? 1.0 : c.nt) + 0.5 * std::tanh(mu);
     return GREEN_OK;
   }
-  double2* A = at<double2>(c.ws, p->r_A);
-  double2* tr = at<double2>(c.ws, p->r_tr);
-  double* scal = at<double>(c.ws, p->r_scal);
-  HIP_TRY(green::launch_dyson_form(A, c.S, c.H0, c.Sinf, at<double2>(c.ws, p->r_Sw), at<double>(c.ws, p->r_wf), mu,
-                                   ns, nw, nk, nao, c.s));
-  HIP_TRY(green::zinv_batched(A, nao, nG, (int)nb, at<int>(c.ws, p->r_status), c.s));
+  double2* A = c.m.A;
+  double2* tr = c.m.tr;
+  double* scal = c.m.scal;
+  HIP_TRY(green::launch_dyson_form(A, c.S, c.H0, c.Sinf, c.m.Sw, c.m.wf, mu, ns, nw, nk, nao, c.s));
+  HIP_TRY(green::zinv_batched(A, nao, nG, (int)nb, c.m.status, c.s));
   HIP_TRY(green::launch_trace_prod(A, nG, c.S, 1, nk, nG, 0, nao, nb, tr, c.s));
-  const double2* row = at<double2>(c.ws, p->r_TF_w2t) + (int64_t)(ntau - 1) * nw;
+  const double2* row = c.m.TF_w2t + (int64_t)(ntau - 1) * nw;
   HIP_TRY(green::launch_weighted_sum(tr, nb, row, nk, nw, 1, -(2.0 / ns) / nk, scal, c.s));
   HIP_TRY(hipMemcpyAsync(n_out, scal, sizeof(double), hipMemcpyDeviceToHost, c.s));
   HIP_TRY(hipStreamSynchronize(c.s));
@@ -1197,19 +1225,17 @@ int find_mu(const DysonCtx& c, double mu0, double nt, double* mu_out, double* n_
   return GREEN_ENOCONV;
 }
 
-int run_dyson(green_plan* p, const void* H0, const void* S, const void* Sinf, const void* Sig, double nt, double* mu,
-              void* G, double* n_out, int32_t* evals_out, void* ws, hipStream_t s) {
+int run_dyson_in(green_plan* p, const DysonMem& dm, const void* H0, const void* S, const void* Sinf, const void* Sig,
+                 double nt, double* mu, void* G, double* n_out, int32_t* evals_out, hipStream_t s) {
   const green_dims& d = p->d;
   const int nk = p->nk, nao = d.nao, ns = d.nspin, nw = d.nw_f, ntau = d.ntau;
   const int64_t nG = (int64_t)nao * nao, nkG = (int64_t)nk * nG;
   const Extents ex = extents(p);
-  double2* Sw = at<double2>(ws, p->r_Sw);
   // Sigma~(i w_m) = sum_t TF_t2w[m][t] Sigma~(tau_t)
-  GREEN_TRY(gemm(green::Site::Transform, "dyson.t2w", op(at<double2>(ws, p->r_TF_t2w), flat(ntau), flat(1), bnone()),
-                 span_ws(ws, p->r_TF_t2w), op(Sig, flat(nkG), flat(1), bflat((int64_t)ntau * nkG)),
-                 span(Sig, ex.Sig), Sw, span_ws(ws, p->r_Sw), flat(nkG), flat(1), bflat((int64_t)nw * nkG), nw,
-                 (int)nkG, ntau, ns, cplx(1), cplx(0), s));
-  DysonCtx c{p, ws, s, static_cast<const double2*>(H0), static_cast<const double2*>(S),
+  GREEN_TRY(gemm(green::Site::Transform, "dyson.t2w", op(dm.TF_t2w, flat(ntau), flat(1), bnone()), dm.sTF_t2w,
+                 op(Sig, flat(nkG), flat(1), bflat((int64_t)ntau * nkG)), span(Sig, ex.Sig), dm.Sw, dm.sSw, flat(nkG),
+                 flat(1), bflat((int64_t)nw * nkG), nw, (int)nkG, ntau, ns, cplx(1), cplx(0), s));
+  DysonCtx c{p, dm, s, static_cast<const double2*>(H0), static_cast<const double2*>(S),
              static_cast<const double2*>(Sinf), nt};
   double m = *mu, n = 0.0;
   int evals = 0;
@@ -1219,16 +1245,19 @@ int run_dyson(green_plan* p, const void* H0, const void* S, const void* Sinf, co
   // final Dyson at mu, then G(tau_t) = sum_m TF_w2t[t][m] G(i w_m)
   double nfinal;
   GREEN_TRY(electron_count(c, m, &nfinal));
-  GREEN_TRY(gemm(green::Site::Transform, "dyson.w2t", op(at<double2>(ws, p->r_TF_w2t), flat(nw), flat(1), bnone()),
-                 span_ws(ws, p->r_TF_w2t), op(at<double2>(ws, p->r_A), flat(nkG), flat(1), bflat((int64_t)nw * nkG)),
-                 span_ws(ws, p->r_A), G, span(G, ex.G), flat(nkG), flat(1), bflat((int64_t)ntau * nkG), ntau,
-                 (int)nkG, nw, ns, cplx(1), cplx(0), s));
-  GREEN_TRY(read_status(p, ws, s));
+  GREEN_TRY(gemm(green::Site::Transform, "dyson.w2t", op(dm.TF_w2t, flat(nw), flat(1), bnone()), dm.sTF_w2t,
+                 op(dm.A, flat(nkG), flat(1), bflat((int64_t)nw * nkG)), dm.sA, G, span(G, ex.G), flat(nkG), flat(1),
+                 bflat((int64_t)ntau * nkG), ntau, (int)nkG, nw, ns, cplx(1), cplx(0), s));
+  GREEN_TRY(read_status_at(dm.status, s));
   *mu = m;
   if (n_out) *n_out = nfinal;
   if (evals_out) *evals_out = evals + 1;
   if (!std::isfinite(nfinal)) return GREEN_ENAN;
   return GREEN_OK;
+}
+int run_dyson(green_plan* p, const void* H0, const void* S, const void* Sinf, const void* Sig, double nt, double* mu,
+              void* G, double* n_out, int32_t* evals_out, void* ws, hipStream_t s) {
+  return run_dyson_in(p, dyson_mem(p, ws), H0, S, Sinf, Sig, nt, mu, G, n_out, evals_out, s);
 }
 
 // ---------------------------------------------------------------- energy (Galitskii-Migdal, with the new G)
@@ -1688,6 +1717,106 @@ int green_dyson(green_plan* p, const void* H0, const void* S, const void* Sinf, 
   PlanScope scope(p);
   GREEN_TRY(ensure_bound(p, ws, s));
   return run_dyson(p, H0, S, Sinf, Sigma, n_target, mu, G, n_out, evals_out, ws, s);
+}
+
+// ---------------------------------------------------------------- allocation-free Dyson
+namespace {
+
+// Device scratch of green_dyson_noalloc: every GPU the library runs on holds its own copy until the process
+// ends, and every call on that GPU shares it.  In host code `scratch` names a host-side stand-in, never the
+// device memory: its device address comes from hipGetSymbolAddress, once per device, and only that address
+// reaches kernels and copies.
+static __device__ __align__(256) unsigned char scratch[GREEN_NOALLOC_MAX_BYTES];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of this device's scratch (the current device; looked up on its first use).
+int scratch_address(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return GREEN_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return GREEN_EHIP;
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return GREEN_OK;
+}
+
+// Byte offsets of the Dyson step's buffers inside the scratch (256-byte aligned).
+struct NoallocLayout {
+  size_t tf_t2w, tf_w2t, wf, sw, a, tr, scal, status, total;
+};
+NoallocLayout noalloc_layout(const green_plan* p) {
+  const green_dims& d = p->d;
+  const size_t nG = (size_t)d.nao * d.nao, nb = (size_t)d.nspin * d.nw_f * p->nk;
+  NoallocLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o;
+  };
+  L.tf_t2w = take((size_t)d.nw_f * d.ntau * 16);
+  L.tf_w2t = take((size_t)d.ntau * d.nw_f * 16);
+  L.wf = take((size_t)d.nw_f * 8);
+  L.sw = take(nb * nG * 16);
+  L.a = take(nb * nG * 16);
+  L.tr = take(nb * 16);
+  L.scal = take(64 * 8);
+  L.status = take(64);
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+int green_dyson_noalloc(green_plan* p, const void* H0, const void* S, const void* Sinf, const void* Sigma,
+                        double n_target, double* mu, void* G, double* n_out, int32_t* evals_out, void* stream) {
+  if (!p || !H0 || !S || !Sinf || !Sigma || !mu || !G || !std::isfinite(*mu)) return GREEN_EINVAL;
+  const NoallocLayout L = noalloc_layout(p);
+  if (L.total > (size_t)GREEN_NOALLOC_MAX_BYTES) return GREEN_ENOMEM;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  void* base = nullptr;
+  if (green::dryrun())
+    base = reinterpret_cast<void*>((uintptr_t)1 << 40);  // validated against, never dereferenced
+  else
+    GREEN_TRY(scratch_address(&base));
+  char* b = static_cast<char*>(base);
+  DysonMem m;
+  m.TF_t2w = reinterpret_cast<const double2*>(b + L.tf_t2w);
+  m.TF_w2t = reinterpret_cast<const double2*>(b + L.tf_w2t);
+  m.wf = reinterpret_cast<const double*>(b + L.wf);
+  m.Sw = reinterpret_cast<double2*>(b + L.sw);
+  m.A = reinterpret_cast<double2*>(b + L.a);
+  m.tr = reinterpret_cast<double2*>(b + L.tr);
+  m.scal = reinterpret_cast<double*>(b + L.scal);
+  m.status = reinterpret_cast<int*>(b + L.status);
+  m.sTF_t2w = green::Span{m.TF_t2w, (int64_t)(p->TF_t2w.size() * sizeof(double2))};
+  m.sTF_w2t = green::Span{m.TF_w2t, (int64_t)(p->TF_w2t.size() * sizeof(double2))};
+  m.sSw = green::Span{m.Sw, (int64_t)(L.a - L.sw)};
+  m.sA = green::Span{m.A, (int64_t)(L.tr - L.a)};
+  // no autotuner (its trials create events) and no split-K partial sums (no room for them)
+  PlanScope scope(nullptr);
+  struct SplitScope {
+    SplitBuf saved;
+    explicit SplitScope(int prec) : saved(tl_split) { tl_split = SplitBuf{nullptr, 0, prec}; }
+    ~SplitScope() { tl_split = saved; }
+  } split_scope(p->prec);
+  if (!green::dryrun()) {
+    // the scratch holds whatever the last call on this GPU left: the grid rows are copied in and the status
+    // word cleared on every call
+    HIP_TRY(hipMemcpyAsync(b + L.tf_t2w, p->TF_t2w.data(), p->TF_t2w.size() * sizeof(double2),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(b + L.tf_w2t, p->TF_w2t.data(), p->TF_w2t.size() * sizeof(double2),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(b + L.wf, p->wf.data(), p->wf.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(green::launch_zero(reinterpret_cast<double2*>(b + L.status), 4, s));
+  }
+  return run_dyson_in(p, m, H0, S, Sinf, Sigma, n_target, mu, G, n_out, evals_out, s);
 }
 
 // ---------------------------------------------------------------- k-path interpolation (Sec. 2.4)

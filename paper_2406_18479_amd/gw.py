@@ -179,6 +179,21 @@ class Plan:
                                         ctypes.byref(ev), self.ws.data_ptr(), _stream(self.device)), "green_dyson")
         return G, m.value, n.value, ev.value
 
+    def dyson_noalloc(self, H0, S, Sinf, Sigma, mu, n_target=-1.0, G=None):
+        """dyson() through green_dyson_noalloc: the library works in its static device scratch (no workspace)."""
+        G = torch.empty(self.shape_G, dtype=torch.complex128, device=self.device) if G is None else G
+        m = ctypes.c_double(mu)
+        n = ctypes.c_double(0.0)
+        ev = ctypes.c_int32(0)
+        _lib.check(_lib.LIB.green_dyson_noalloc(self._h, _ptr(H0, self.shape_H, "H0", self.device),
+                                                _ptr(S, self.shape_S, "S", self.device),
+                                                _ptr(Sinf, self.shape_H, "Sinf", self.device),
+                                                _ptr(Sigma, self.shape_G, "Sigma", self.device), float(n_target),
+                                                ctypes.byref(m), _ptr(G, self.shape_G, "G", self.device),
+                                                ctypes.byref(n), ctypes.byref(ev), _stream(self.device)),
+                   "green_dyson_noalloc")
+        return G, m.value, n.value, ev.value
+
     def kpath_interpolate(self, kfrac, Sinf, Sigma):
         """Sinf and Sigma~(tau) interpolated from the mesh onto the points kfrac ([npath][3] fractional
         coordinates); returns (Sinf_path [nspin][npath][nao][nao], Sigma_path [nspin][ntau][npath][nao][nao]).

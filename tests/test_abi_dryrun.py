@@ -262,3 +262,26 @@ def test_v_half_store_in_bounds(lib, ci, prec):
                                       None) == 0
     finally:
         L.green_plan_destroy(h)
+
+
+@pytest.mark.parametrize("c,fits", [(CASES[0], True), (CASES[1], True), (CASES[3], False), (CASES[4], False),
+                                    (CASES[5], True)],
+                         ids=["molecule", "k2x2x2", "k3x3x3", "k4x4x4", "k3x1x1_ns2"])
+def test_dyson_noalloc_bounds_and_limit(lib, c, fits):
+    """The allocation-free Dyson step stays inside its static scratch, and plans whose Dyson buffers exceed
+    GREEN_NOALLOC_MAX_BYTES are refused with GREEN_ENOMEM before any launch."""
+    h = _plan(lib, c, 0)
+    try:
+        H0, S, Sinf, Sig, G = [BASE + i * STEP for i in range(5)]
+        mu = ctypes.c_double(0.0)
+        n = ctypes.c_double(0.0)
+        ev = ctypes.c_int32(0)
+        st = lib.LIB.green_dyson_noalloc(h, H0, S, Sinf, Sig, 3.0, ctypes.byref(mu), G, ctypes.byref(n),
+                                         ctypes.byref(ev), None)
+        nw, nk, nG = c["ntau"], int(np.prod(c["kmesh"])), c["nao"] ** 2
+        need = 2 * c["nspin"] * nw * nk * nG * 16
+        assert (need <= lib.NOALLOC_MAX_BYTES) == fits
+        assert st == (0 if fits else -2)
+        assert lib.LIB.green_dyson_noalloc(h, None, S, Sinf, Sig, 3.0, ctypes.byref(mu), G, None, None, None) == -1
+    finally:
+        lib.LIB.green_plan_destroy(h)
