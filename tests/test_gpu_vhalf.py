@@ -56,7 +56,7 @@ CASES = [dict(kmesh=(3, 2, 1), nao=8, naux=20, ntau=8, nspin=1, seed=801),
          dict(kmesh=(3, 1, 2), nao=5, naux=13, ntau=6, nspin=2, seed=802)]  # (a 2x2x2 mesh has every q = -q)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("c", CASES, ids=lambda c: f"k{c['kmesh']}_nao{c['nao']}_ns{c['nspin']}")
 def test_half_store_equals_full_store(c, prec):
     _require_gpu()
