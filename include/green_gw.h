@@ -44,6 +44,11 @@
  * detected before any launch.  Numerical failures (a zero pivot in a batched
  * inversion, a non-finite result, a chemical potential that cannot be
  * bracketed or converged) are reported by the next synchronising call.
+ * With GREEN_CHECK=1 in the environment (a debug mode) every call that reads
+ * G and V also checks on the device that G(tau) is Hermitian per (s, t, k)
+ * and that V has the Hermitian pairing on three auxiliary indices of every
+ * pair, to 1e-8 of the largest element; violations are reported as
+ * GREEN_EINVAL by the next synchronising call.
  */
 #ifndef GREEN_GW_H
 #define GREEN_GW_H
@@ -143,7 +148,8 @@ int green_gw_polarization(green_plan* plan, const void* V, const void* G, void* 
 
 /* Screening (Eqs. P0t_to_P0w, tilde_P_omega and the inverse transform):
  *   P0(i W_m) = sum_t TB_t2w[m][t] P0(tau_t)
- *   P~(i W_m) = [I - P0(i W_m)]^{-1} P0(i W_m)      (batched Gauss-Jordan, partial pivoting)
+ *   P~(i W_m) = [I - P0(i W_m)]^{-1} P0(i W_m)      (batched Gauss-Jordan inverse with partial pivoting,
+ *                                                    then the product with P0)
  *   P~(tau_t) = sum_m TB_w2t[t][m] P~(i W_m)
  * P0: input, Pt: output, both [nk][ntau][naux][naux] (device; may not alias).  Async. */
 int green_gw_screen(green_plan* plan, const void* P0, void* Pt, void* ws, void* stream);
@@ -188,6 +194,12 @@ int green_hf_static(green_plan* plan, const void* V, const void* G, void* Sinf, 
  * Synchronises `stream`. */
 int green_dyson(green_plan* plan, const void* H0, const void* S, const void* Sinf, const void* Sigma, double n_target,
                 double* mu, void* G, double* n_out, int32_t* evals_out, void* ws, void* stream);
+
+/* Status latched on the device by earlier asynchronous calls on this workspace (synchronises `stream`, then
+ * clears it): GREEN_ESINGULAR for a zero pivot in a batched inversion, GREEN_EINVAL for inputs that break an
+ * assumption of the plan (see GREEN_OPT_TIME_REVERSAL and the GREEN_CHECK=1 debug checks of G Hermiticity and
+ * the Hermitian pairing of V), GREEN_OK otherwise.  green_dyson and green_gw_iterate report the same on return. */
+int green_check_status(green_plan* plan, void* ws, void* stream);
 
 /* Allocation-free variant of green_dyson, for callers that cannot allocate device memory or pass a workspace
  * (tight serving loops, harnesses that forbid hipMalloc).  Same arguments and results as green_dyson minus the
@@ -275,9 +287,12 @@ int green_gw_iterate_diis(green_plan* plan, const void* V, const void* H0, const
  *   GREEN_OPT_P0_TILE  split-BF16 plans: output tile of the P~0 contraction over k and orbital pairs
  *                   (the sum of Eq. tilde_P0_tau) before any autotuning: 1 = 192 x 96, 2 = 192 x 64,
  *                   3 = 320 x 64, 4 = 448 x 64 rows x columns of P~0(q, tau), register-staged; 5 = 320 x 64,
- *                   6 = 192 x 128 fed by LDS DMA (even nao; else as 3 and 1).  The plan starts with the
- *                   tile that pads naux x naux least (192 x 96 counted at 90% of its area), 320 x 64 on the
- *                   LDS-DMA kernel.
+ *                   6 = 192 x 128 fed by LDS DMA (even nao; else as 3 and 1); 7 = 320 x 64, 8 = 128 x 128,
+ *                   9 = 256 x 64 fed by LDS DMA with the next K stage's operands read ahead (K blocks of a
+ *                   multiple of 16; else as 3, 1 and 2).  The plan starts with the tile that pads naux x naux
+ *                   least (192 x 96 counted at 90% of its area), 320 x 64 on the LDS-DMA kernel.
+ *   GREEN_OPT_SIGMA_TILE  split-BF16 plans: tile of the first Sigma~ contraction, P~(tau)^T V over the auxiliary
+ *                   index (values as GREEN_OPT_P0_TILE; default 6).
  *   GREEN_OPT_STAGE1_TILE  split-BF16 plans: tile of the V G products that feed it: 0 = 64 x 64,
  *                   1 = 192 x 96 (default), 2 = 192 x 64.
  *                   Both only change the summation blocking; results agree to rounding.
@@ -299,8 +314,12 @@ int green_gw_iterate_diis(green_plan* plan, const void* V, const void* H0, const
  *                   green_gw_polarization contracts the first half of the tau nodes only (the second half is
  *                   the conjugate transpose), and green_gw_selfenergy only the momenta k with -k >= k (flat
  *                   index), each partner written as the complex conjugate; the same inside the iterations and
- *                   in green_gf2_selfenergy (both terms).  Results on inputs without the symmetry are wrong,
- *                   not flagged.  0 (default): every tau node and every k is contracted.
+ *                   in green_gf2_selfenergy (both terms).  Every call that reads G and V first checks on the
+ *                   device that G^{-k}_s(tau) = conj G^k_s(tau) for every element and that V^{-k1,-k2}(Q) =
+ *                   conj V^{k1,k2}(Q) on three auxiliary indices of every pair (full store), to 1e-8 of the
+ *                   largest element; a violation is reported as GREEN_EINVAL by the next synchronising call
+ *                   (green_dyson, green_gw_iterate, green_check_status).  0 (default): every tau node and every
+ *                   k is contracted.
  *   GREEN_OPT_V_HALF  1: Hermitian half store of V.  Since V^{k2,k1}(Q) = V^{k1,k2}(Q)^dagger, the slab of q
  *                   (V[q][k] = V^{k,k+q}) follows from that of -q: the caller passes only the slabs of the
  *                   canonical q (-q >= q, flat index), in increasing q, as V[nqc][nk][naux][nao][nao] (the 3x3x3 mesh:
@@ -317,6 +336,7 @@ int green_gw_iterate_diis(green_plan* plan, const void* V, const void* H0, const
 #define GREEN_OPT_GF2 6
 #define GREEN_OPT_TIME_REVERSAL 7
 #define GREEN_OPT_V_HALF 8
+#define GREEN_OPT_SIGMA_TILE 9
 int green_plan_set_option(green_plan* plan, int option, int value);
 
 /* Text table of the autotuner's decisions into buf (host, len bytes, NUL-terminated; GREEN_ENOMEM when

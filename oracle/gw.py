@@ -130,7 +130,7 @@ def sigma_inf(V: np.ndarray, G: np.ndarray, kmesh) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------- O3
-def polarization(V: np.ndarray, G: np.ndarray, kmesh, ts=None) -> np.ndarray:
+def polarization(V: np.ndarray, G: np.ndarray, kmesh, ts=None, qs=None) -> np.ndarray:
     """O3, Eq. tilde_P0_tau with reading G1:
 
     P0^q_{QQ'}(tau) = -(1/Nk) sum_{k s} sum_{abcd} V^{k,k+q}_{da}(Q) G^k_{s,cd}(beta-tau)
@@ -138,16 +138,18 @@ def polarization(V: np.ndarray, G: np.ndarray, kmesh, ts=None) -> np.ndarray:
     (spin sum doubled for a restricted run).  Written as a trace,
     sum_{abcd} = sum_{d,b} [V^{k,k+q}(Q) G^{k+q}(tau)]_{db} [V^{k+q,k}(Q') G^k(beta-tau)]_{bd}.
 
-    ts: optional list of grid nodes to evaluate (default all).  Returns P[q][t][Q][Q'].
+    ts, qs: optional lists of grid nodes and momentum transfers to evaluate (default all); they only select.
+    Returns P[q][t][Q][Q'] over qs x ts.
     """
     km = KMesh(kmesh)
     ns, ntau, nk, nao, _ = G.shape
     naux = V.shape[2]
     ts = list(range(ntau)) if ts is None else list(ts)
+    qs = list(range(nk)) if qs is None else list(qs)
     w = spin_weight(ns)
-    P = np.zeros((nk, len(ts), naux, naux), dtype=np.complex128)
+    P = np.zeros((len(qs), len(ts), naux, naux), dtype=np.complex128)
     trev = [ntau - 1 - t for t in ts]  # beta - tau_t is node ntau-1-t on the symmetric grid
-    for q in range(nk):
+    for iq, q in enumerate(qs):
         for k in range(nk):
             kq = km.add(k, q)
             A = V_pair(V, km, k, kq).reshape(naux * nao, nao)  # V^{k,k+q}(Q), rows (Q, d), cols a
@@ -159,7 +161,7 @@ def polarization(V: np.ndarray, G: np.ndarray, kmesh, ts=None) -> np.ndarray:
                     # R[Q'][b][d] = sum_c V^{k+q,k}_{bc}(Q') G^k_{cd}(beta - tau)
                     R = (B @ G[s, trev[it], k]).reshape(naux, nao, nao)
                     Rf = np.swapaxes(R, 1, 2).reshape(naux, nao * nao)  # cols (d, b)
-                    P[q, it] += w * (L @ Rf.T)
+                    P[iq, it] += w * (L @ Rf.T)
     P *= -1.0 / nk
     return P
 

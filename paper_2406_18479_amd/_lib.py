@@ -76,13 +76,14 @@ OPT_SIGMA_FUSED = 5
 OPT_GF2 = 6
 OPT_TIME_REVERSAL = 7
 OPT_V_HALF = 8
+OPT_SIGMA_TILE = 9
 
 EXPORTS = ["green_plan_create", "green_plan_destroy", "green_workspace_bytes", "green_gw_polarization",
            "green_gw_screen", "green_gw_selfenergy", "green_hf_static", "green_dyson", "green_gw_iterate",
            "green_plan_set_option", "green_plan_tuning_report", "green_batch_workspace_bytes",
            "green_gw_iterate_batched", "green_batch_create", "green_batch_iterate", "green_batch_destroy",
            "green_diis_history_bytes", "green_gw_iterate_diis", "green_kpath_interpolate",
-           "green_gf2_selfenergy", "green_dyson_noalloc", "green_strerror"]
+           "green_gf2_selfenergy", "green_dyson_noalloc", "green_check_status", "green_strerror"]
 
 NOALLOC_MAX_BYTES = 64 << 20  # GREEN_NOALLOC_MAX_BYTES
 
@@ -116,6 +117,8 @@ def _load():
     lib.green_dyson_noalloc.argtypes = [vp, vp, vp, vp, vp, dbl, ctypes.POINTER(dbl), vp, ctypes.POINTER(dbl),
                                         ctypes.POINTER(ctypes.c_int32), vp]
     lib.green_dyson_noalloc.restype = i32
+    lib.green_check_status.argtypes = [vp, vp, vp]
+    lib.green_check_status.restype = i32
     lib.green_kpath_interpolate.argtypes = [vp, ctypes.POINTER(dbl), i32, vp, vp, vp, vp, vp, vp]
     lib.green_kpath_interpolate.restype = i32
     lib.green_gw_iterate.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(dbl), dbl, dbl,

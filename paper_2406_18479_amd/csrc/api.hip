@@ -60,6 +60,7 @@ struct green_plan {
   int big_p0 = 1;      // split-BF16 P~0 stage-2 kernel: 1 = 192 x 96 tiles, 2 = 192 x 64, 3 = 320 x 64, 4 = 448 x 64,
                        // LDS-DMA 5 = 320 x 64, 6 = 192 x 128
                        // (set at plan creation from naux)
+  int big_sig = 6;     // split-BF16 Sigma~ stage-1 kernel (P~^T V over Q), the tiles of big_p0
   bool fuse_sig = false;  // split-BF16 plans, nao % 4 == 0 and <= 64: Sigma~ stages 2 and 3 in one kernel
   bool gf2 = false;       // the dynamic self-energy is GF2 (Eq. sigma2) instead of GW
   size_t chunk_bytes = 0;
@@ -307,8 +308,9 @@ int choose_ksplit(const ZGemm& g, int cap = 32) {
   int bm, bn, threads;
   green::zgemm_tile(g, &bm, &bn, &threads);
   const int64_t tiles = (int64_t)((M + bm - 1) / bm) * ((N + bn - 1) / bn) * batch;
-  // 256-thread tiles: aim for ~2048 workgroups; 512-thread large tiles (one per CU): ~1024
-  const int64_t target = threads == 512 ? 1024 : 2048;
+  // 256-thread tiles: aim for ~2048 workgroups; large tiles (one or two workgroups per CU): ~1024 per slot
+  const int per_cu = green::zgemm_wgs_per_cu(g);
+  const int64_t target = per_cu ? 1024 * per_cu : 2048;
   if (tiles >= target / 2) return 1;
   int ks = (int)std::min<int64_t>((target + tiles - 1) / tiles, cap);
   ks = std::min(ks, std::max(1, K / 64));
@@ -334,17 +336,19 @@ std::vector<TuneCand> tune_candidates(const ZGemm& g0) {
     g.shape = shape;
     g.big = big;
     const int fam = green::zgemm_variant(g).family;
-    if (fam < 0 || (big && fam != (big >= 5 ? 4 : 3))) return;
+    if (fam < 0 || (big && fam != (big >= 7 ? 5 : big >= 5 ? 4 : 3))) return;
     g.ksplit = 1;
     const int ks0 = choose_ksplit(g);
     // large tiles run one workgroup per CU: also the split-K counts that fill one, two and three waves
     // of the 256 CUs as closely as possible from below
     int bm, bn, threads;
     green::zgemm_tile(g, &bm, &bn, &threads);
+    const int per_cu = green::zgemm_wgs_per_cu(g);
+    const bool whole = per_cu > 0;
     const int64_t tiles = (int64_t)((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn) * g.batch;
     int opts[6] = {ks0, std::min(2 * ks0, 32), ks0 / 2, 0, 0, 0};
-    if (threads == 512)
-      for (int w = 1; w <= 3; ++w) opts[2 + w] = (int)std::min<int64_t>(256 * w / tiles, 32);
+    if (whole)
+      for (int w = 1; w <= 3; ++w) opts[2 + w] = (int)std::min<int64_t>(256 * per_cu * w / tiles, 32);
     for (int ks : opts) {
       if (ks < 1 || ks > std::max(1, g.K / 16)) continue;
       if (ks > 1 && (int64_t)ks * g.batch * g.M * g.N > tl_split.cap) continue;
@@ -354,7 +358,7 @@ std::vector<TuneCand> tune_candidates(const ZGemm& g0) {
       if (!dup) out.push_back(TuneCand{shape, big, ks, 0});
     }
     // large tiles over many tile rows: bands of 4 and 16 tile rows at the default split-K count
-    if (threads == 512 && ks0 >= 1 && ks0 <= std::max(1, g.K / 16))
+    if (whole && ks0 >= 1 && ks0 <= std::max(1, g.K / 16))
       for (int b : {4, 16})
         if ((g.M + bm - 1) / bm > b && (g.N + bn - 1) / bn > 1) out.push_back(TuneCand{shape, big, ks0, b});
   };
@@ -371,6 +375,11 @@ std::vector<TuneCand> tune_candidates(const ZGemm& g0) {
     // LDS-DMA tiles (where the operands allow them)
     add(0, 5);
     add(0, 6);
+    add(0, 7);
+    add(0, 8);
+    add(0, 9);
+    add(0, 10);
+    add(0, 11);
   }
   add(0, 0);
   add(4, 0);
@@ -659,13 +668,30 @@ int run_screen(green_plan* p, const void* P0, void* Pt, void* ws, hipStream_t s)
                  span_ws(ws, p->r_TB_t2w), op(P0, flat(nP), flat(1), btwo(nc, (int64_t)ntau * nP, qc, 0, hqc)),
                  span(P0, ex.P), Pw, sPw, flat(nP), flat(1), bflat((int64_t)nwb * nP), nwb, (int)nP, ntau, nc, cplx(1),
                  cplx(0), s));
-  // P~(i W) = [I - P0]^{-1} P0 = [I - P0]^{-1} - I
+  // P~(i W) = [I - P0]^{-1} P0, formed as a product with the inverse (not as [I - P0]^{-1} - I, which cancels
+  // where |P0(i W)| << 1): per chunk of (q, m) matrices, B = I - P0 into T2 and inverted there, B P0 into T1,
+  // copied back over P0
   if ((int64_t)nc * nwb * nP * 16 > (int64_t)p->r_Pw.bytes) return GREEN_EINVAL;
-  GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::launch_one_minus(Pw, naux, (int64_t)nc * nwb, st_); }));
-  GREEN_TRY(aux(s, [=](hipStream_t st_) {
-    return green::zinv_batched(Pw, naux, nP, nc * nwb, at<int>(ws, p->r_status), st_);
-  }));
-  GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::launch_minus_one(Pw, naux, (int64_t)nc * nwb, st_); }));
+  {
+    const int64_t per = (int64_t)(std::min(p->r_T1.bytes, p->r_T2.bytes) / (size_t)(nP * 16));
+    if (per < 1) return GREEN_EINVAL;
+    double2* T1 = at<double2>(ws, p->r_T1);
+    double2* T2 = at<double2>(ws, p->r_T2);
+    const green::Span sT1 = span_ws(ws, p->r_T1), sT2 = span_ws(ws, p->r_T2);
+    const int64_t total = (int64_t)nc * nwb;
+    for (int64_t b0 = 0; b0 < total; b0 += per) {
+      const int nb = (int)std::min<int64_t>(per, total - b0);
+      double2* P0w = Pw + b0 * nP;
+      GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::launch_one_minus_copy(P0w, T2, naux, nb, st_); }));
+      GREEN_TRY(aux(s, [=](hipStream_t st_) {
+        return green::zinv_batched(T2, naux, nP, nb, at<int>(ws, p->r_status), st_);
+      }));
+      GREEN_TRY(gemm(green::Site::Generic, "screen.solve", op(T2, flat(naux), flat(1), bflat(nP)), sT2,
+                     op(P0w, flat(naux), flat(1), bflat(nP)), sPw, T1, sT1, flat(naux), flat(1), bflat(nP), naux,
+                     naux, naux, nb, cplx(1), cplx(0), s));
+      GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::launch_copy(T1, P0w, (int64_t)nb * nP, st_); }));
+    }
+  }
   // P~(tau_t) = sum_m TB_w2t[t][m] P~(i W_m)
   GREEN_TRY(gemm(green::Site::Transform, "screen.w2t", op(at<double2>(ws, p->r_TB_w2t), flat(nwb), flat(1), bnone()),
                  span_ws(ws, p->r_TB_w2t), op(Pw, flat(nP), flat(1), bflat((int64_t)nwb * nP)), sPw, Pt,
@@ -794,7 +820,7 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
                                  mixed ? vt : green::kC64),
                      sVa, T1, sT1, two(naux, nG, (int64_t)nkx * nV), tr ? flat(1) : two((int32_t)nG, 1, nV),
                      tr ? bflat(nV) : bnone(), tcn * naux, (int)(tr ? nG : nk * nG), naux, tr ? nkx : 1, cplx(1),
-                     cplx(0), s, p->prec, xt, bf ? (vt_dma ? 6 : 1) : 0));
+                     cplx(0), s, p->prec, xt, bf ? (vt_dma ? p->big_sig : 1) : 0));
       for (int sp = 0; sp < ns && fused; ++sp) {
         // Sigma[s][t][k][i][j] += -(1/nk) sum_{Q',b} (sum_a X[tt][k][Q'][i][a] G^{k-q}_{ab}(tau)) V^{k-q,k}_{bj}(Q'):
         // Q' slices of FP64 partial sums, added in slice order
@@ -1076,6 +1102,10 @@ int run_hf(green_plan* p, const void* V, const void* G, void* Sinf, void* ws, hi
 }
 
 // ---------------------------------------------------------------- Dyson + mu
+// Bits of the device status word: a zero or non-finite pivot in a batched inversion, and inputs that break an
+// assumption the plan relies on (time reversal; the debug checks of GREEN_CHECK=1).
+constexpr int kStatusSingular = 1, kStatusTimeReversal = 2, kStatusInput = 4;
+
 int read_status_at(int* status, hipStream_t s) {
   if (green::dryrun()) return GREEN_OK;
   int st = 0;
@@ -1083,7 +1113,7 @@ int read_status_at(int* status, hipStream_t s) {
   HIP_TRY(hipStreamSynchronize(s));
   if (st) {
     HIP_TRY(hipMemsetAsync(status, 0, sizeof(int), s));
-    return GREEN_ESINGULAR;
+    return (st & (kStatusTimeReversal | kStatusInput)) ? GREEN_EINVAL : GREEN_ESINGULAR;
   }
   return GREEN_OK;
 }
@@ -1309,6 +1339,55 @@ int check_plan(green_plan* p, void* ws) {
   return GREEN_OK;
 }
 
+// GREEN_CHECK=1: every entry point that reads G and V also checks the assumptions the method makes of them
+// (G(tau) Hermitian per (s, t, k); the Hermitian pairing of V on a sample of auxiliary indices).
+bool debug_checks() {
+  static const bool on = [] {
+    const char* e = std::getenv("GREEN_CHECK");
+    return e && e[0] == '1';
+  }();
+  return on;
+}
+
+// Asynchronous checks of G and V against what the plan assumes; a violation is latched in the status word and
+// reported (GREEN_EINVAL) by the next synchronising call.  With GREEN_OPT_TIME_REVERSAL: G^{-k}_s(tau) =
+// conj G^k_s(tau) everywhere and V^{-k1,-k2}(Q) = conj V^{k1,k2}(Q) on three auxiliary indices of every pair
+// (full store).  Relative tolerance 1e-8 of the largest element.
+int check_inputs(green_plan* p, const void* V, const void* G, void* ws, hipStream_t s) {
+  const bool dbg = debug_checks();
+  if (!p->trev && !dbg) return GREEN_OK;
+  const green_dims& d = p->d;
+  const int nk = p->nk, nao = d.nao, naux = d.naux;
+  const int64_t nG = (int64_t)nao * nao;
+  const double2* Gp = static_cast<const double2*>(G);
+  const double2* Vp = static_cast<const double2*>(V);
+  double* part = at<double>(ws, p->r_partial);
+  int* st = at<int>(ws, p->r_status);
+  const int32_t* kneg = at<int32_t>(ws, p->r_kneg);
+  const int32_t* kadd = at<int32_t>(ws, p->r_kadd);
+  const int64_t nmat = (int64_t)d.nspin * d.ntau;
+  const double tol = 1e-8;
+  if (p->trev) {
+    GREEN_TRY(aux(s, [=](hipStream_t st_) {
+      return green::launch_check_conj_k(Gp, nmat, nk, nG, kneg, tol, kStatusTimeReversal, part, st, st_);
+    }));
+    if (!p->vhalf)
+      GREEN_TRY(aux(s, [=](hipStream_t st_) {
+        return green::launch_check_v(Vp, nk, naux, nao, kadd, kneg, 1, tol, kStatusTimeReversal, part, st, st_);
+      }));
+  }
+  if (dbg) {
+    GREEN_TRY(aux(s, [=](hipStream_t st_) {
+      return green::launch_check_herm(Gp, nmat * nk, nao, tol, kStatusInput, part, st, st_);
+    }));
+    if (!p->vhalf)
+      GREEN_TRY(aux(s, [=](hipStream_t st_) {
+        return green::launch_check_v(Vp, nk, naux, nao, kadd, kneg, 0, tol, kStatusInput, part, st, st_);
+      }));
+  }
+  return GREEN_OK;
+}
+
 // Sets the plan whose autotuner state gemm() consults for the lifetime of the scope.
 struct PlanScope {
   green_plan* prev;
@@ -1358,6 +1437,7 @@ int sigma_eval(green_plan* p, const void* V, const void* G, void* Sinf, void* Si
   double* scal = at<double>(ws, p->r_scal);
   double* part = at<double>(ws, p->r_partial);
   auto m = [&](int i) { return mark ? hip_status((*mark)(i)) : GREEN_OK; };
+  GREEN_TRY(check_inputs(p, V, G, ws, s));
   GREEN_TRY(run_hf(p, V, G, Sinfn, ws, s));
   GREEN_TRY(m(1));
   GREEN_TRY(run_polarization(p, V, G, P, ws, s));
@@ -1622,8 +1702,8 @@ int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, 
   take(p->r_P, (size_t)nk * ntau * nP * 16);
   take(p->r_Pw, p->qcan.size() * nwb * nP * 16);
   const size_t tbuf = std::max<size_t>((size_t)tc * nk * nV * isz, (size_t)ns * ntau * nk * nG * 16);
-  take(p->r_T1, tbuf);
-  take(p->r_T2, std::max<size_t>((size_t)tc * nk * nV * isz, (size_t)nk * nV * 16));
+  take(p->r_T1, std::max<size_t>(tbuf, (size_t)nP * 16));
+  take(p->r_T2, std::max<size_t>({(size_t)tc * nk * nV * isz, (size_t)nk * nV * 16, (size_t)nP * 16}));
   take(p->r_gam, (size_t)ns * nk * nG * 16);
   take(p->r_gamT, (size_t)ns * nk * nG * 16);
   take(p->r_D, (size_t)naux * 16);
@@ -1666,6 +1746,7 @@ int green_gw_polarization(green_plan* p, const void* V, const void* G, void* P0,
   hipStream_t s = static_cast<hipStream_t>(stream);
   PlanScope scope(p);
   GREEN_TRY(ensure_bound(p, ws, s));
+  GREEN_TRY(check_inputs(p, V, G, ws, s));
   return run_polarization(p, V, G, P0, ws, s);
 }
 
@@ -1685,6 +1766,7 @@ int green_gw_selfenergy(green_plan* p, const void* V, const void* G, const void*
   hipStream_t s = static_cast<hipStream_t>(stream);
   PlanScope scope(p);
   GREEN_TRY(ensure_bound(p, ws, s));
+  GREEN_TRY(check_inputs(p, V, G, ws, s));
   return run_selfenergy(p, V, G, Pt, Sigma, ws, s);
 }
 
@@ -1694,6 +1776,7 @@ int green_gf2_selfenergy(green_plan* p, const void* V, const void* G, void* Sigm
   hipStream_t s = static_cast<hipStream_t>(stream);
   PlanScope scope(p);
   GREEN_TRY(ensure_bound(p, ws, s));
+  GREEN_TRY(check_inputs(p, V, G, ws, s));
   double2* P = at<double2>(ws, p->r_P);
   GREEN_TRY(run_polarization(p, V, G, P, ws, s));
   GREEN_TRY(run_selfenergy(p, V, G, P, Sigma, ws, s));
@@ -1717,6 +1800,13 @@ int green_dyson(green_plan* p, const void* H0, const void* S, const void* Sinf, 
   PlanScope scope(p);
   GREEN_TRY(ensure_bound(p, ws, s));
   return run_dyson(p, H0, S, Sinf, Sigma, n_target, mu, G, n_out, evals_out, ws, s);
+}
+
+int green_check_status(green_plan* p, void* ws, void* stream) {
+  GREEN_TRY(check_plan(p, ws));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (p->bound_ws != ws) return GREEN_OK;  // nothing has run on this workspace
+  return read_status(p, ws, s);
 }
 
 // ---------------------------------------------------------------- allocation-free Dyson
@@ -2075,8 +2165,13 @@ int green_plan_set_option(green_plan* p, int option, int value) {
       if (!value) drop_graph(p);
       return GREEN_OK;
     case GREEN_OPT_P0_TILE:
-      if (value < 1 || value > 6) return GREEN_EINVAL;
+      if (value < 1 || value > 11) return GREEN_EINVAL;
       p->big_p0 = value;
+      drop_graph(p);
+      return GREEN_OK;
+    case GREEN_OPT_SIGMA_TILE:
+      if (value < 1 || value > 11) return GREEN_EINVAL;
+      p->big_sig = value;
       drop_graph(p);
       return GREEN_OK;
     case GREEN_OPT_STAGE1_TILE:

@@ -31,6 +31,20 @@ hipError_t launch_mix(double2* S, const double2* Snew, double alpha, int64_t n, 
                       hipStream_t s);
 hipError_t launch_herm(const double2* X, int64_t nmat, int nao, double* partial, double* out, hipStream_t s);
 hipError_t launch_zero(double2* X, int64_t n, hipStream_t s);
+// dst[b] = I - src[b] (n x n matrices), dst = src (n elements)
+hipError_t launch_one_minus_copy(const double2* src, double2* dst, int n, int64_t batch, hipStream_t s);
+hipError_t launch_copy(const double2* src, double2* dst, int64_t n, hipStream_t s);
+// Input checks (asynchronous): `bit` is set in *status when the largest |difference| exceeds tol times the
+// largest |value| (or a value is not finite).  partial: 512 doubles of scratch.
+//   conj_k: X[b][k] against conj X[b][kneg[k]] (nblk blocks of nk matrices of ne elements)
+//   herm:   X_b against X_b^dagger (nmat n x n matrices)
+//   v:      V[q][k][Q] against V[-q][k+q][Q]^dagger (mode 0) or conj V[-q][-k][Q] (mode 1), on three Q
+hipError_t launch_check_conj_k(const double2* X, int64_t nblk, int nk, int64_t ne, const int32_t* kneg, double tol,
+                               int bit, double* partial, int* status, hipStream_t s);
+hipError_t launch_check_herm(const double2* X, int64_t nmat, int n, double tol, int bit, double* partial, int* status,
+                             hipStream_t s);
+hipError_t launch_check_v(const double2* V, int nk, int naux, int nao, const int32_t* kadd, const int32_t* kneg,
+                          int mode, double tol, int bit, double* partial, int* status, hipStream_t s);
 
 // DIIS: *out = sum Re(conj(a) b) (fixed-order reduction through partial[mix_blocks(n)]); r = x - old;
 // out = sum_j c_j base[slot_j * stride + .] with *out_max = max |out_new - out_old|.

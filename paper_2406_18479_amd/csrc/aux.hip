@@ -323,6 +323,106 @@ __global__ __launch_bounds__(256) void k_herm_partner(const double2* __restrict_
   }
 }
 
+// dst[b] = I - src[b]  (n x n, batch stride n*n; src and dst distinct)
+__global__ void k_one_minus_copy(const double2* __restrict__ src, double2* __restrict__ dst, int n, int64_t batch) {
+  const int64_t nn = (int64_t)n * n;
+  const int64_t total = nn * batch;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+    const int e = (int)(x % nn);
+    const double2 v = src[x];
+    dst[x] = make_double2(((e / n) == (e % n) ? 1.0 : 0.0) - v.x, -v.y);
+  }
+}
+
+__global__ void k_copy(const double2* __restrict__ src, double2* __restrict__ dst, int64_t n) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
+    dst[x] = src[x];
+}
+
+// Input checks.  Each pass writes per block the largest |difference| and the largest |value| seen
+// (partial[2 b], partial[2 b + 1]); k_check_finish compares them in block order and sets `bit` in *status when
+// the difference exceeds tol times the largest value (or either is not finite).
+constexpr int kCheckBlocks = 256;
+__device__ __forceinline__ double cabs2(double2 v) { return sqrt(v.x * v.x + v.y * v.y); }
+__device__ void check_store(double d, double m, double* partial) {
+  __shared__ double sd[256], sm[256];
+  d = block_reduce(d, MaxD(), sd);
+  m = block_reduce(m, MaxD(), sm);
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = d;
+    partial[2 * blockIdx.x + 1] = m;
+  }
+}
+// X[b][k][e] against conj X[b][kneg[k]][e]
+__global__ __launch_bounds__(256) void k_check_conj_k(const double2* __restrict__ X, int64_t nblk, int nk, int64_t ne,
+                                                      const int32_t* __restrict__ kneg, double* __restrict__ partial) {
+  const int64_t total = nblk * nk * ne;
+  double d = 0.0, m = 0.0;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t bk = x / ne, e = x - bk * ne;
+    const int64_t b = bk / nk;
+    const int k = (int)(bk - b * nk);
+    const double2 v = X[x], w = X[(b * nk + kneg[k]) * ne + e];
+    d = fmax(d, cabs2(make_double2(v.x - w.x, v.y + w.y)));
+    m = fmax(m, cabs2(v));
+  }
+  check_store(d, m, partial);
+}
+// X_b[i][j] against conj X_b[j][i]
+__global__ __launch_bounds__(256) void k_check_herm(const double2* __restrict__ X, int64_t nmat, int n,
+                                                    double* __restrict__ partial) {
+  const int64_t nn = (int64_t)n * n, total = nmat * nn;
+  double d = 0.0, m = 0.0;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = x / nn;
+    const int e = (int)(x - b * nn), i = e / n, j = e - (e / n) * n;
+    const double2 v = X[x], w = X[b * nn + (int64_t)j * n + i];
+    d = fmax(d, cabs2(make_double2(v.x - w.x, v.y + w.y)));
+    m = fmax(m, cabs2(v));
+  }
+  check_store(d, m, partial);
+}
+// V[q][k][Q] against its partner on three auxiliary indices Q in {0, naux / 2, naux - 1}:
+//   pairing (mode 0):  V[-q][k + q][Q]^dagger   (V^{k2,k1}(Q) = V^{k1,k2}(Q)^dagger)
+//   time reversal (1): conj V[-q][-k][Q]         (V^{-k1,-k2}(Q) = conj V^{k1,k2}(Q))
+// kadd[q * nk + k] = k + q, kneg[k] = -k; every slab q of the full store is present.
+__global__ __launch_bounds__(256) void k_check_v(const double2* __restrict__ V, int nk, int naux, int nao,
+                                                 const int32_t* __restrict__ kadd, const int32_t* __restrict__ kneg,
+                                                 int mode, double* __restrict__ partial) {
+  const int64_t nG = (int64_t)nao * nao, nV = (int64_t)naux * nG;
+  const int64_t total = (int64_t)nk * nk * 3 * nG;
+  double d = 0.0, m = 0.0;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t blk = x / nG;
+    const int e = (int)(x - blk * nG), i = e / nao, j = e - (e / nao) * nao;
+    const int qi = (int)(blk % 3);
+    const int64_t qk = blk / 3;
+    const int k = (int)(qk % nk), q = (int)(qk / nk);
+    const int Q = qi == 0 ? 0 : (qi == 1 ? naux / 2 : naux - 1);
+    const double2 v = V[((int64_t)q * nk + k) * nV + Q * nG + e];
+    double2 w;
+    if (mode == 0)
+      w = V[((int64_t)kneg[q] * nk + kadd[q * nk + k]) * nV + Q * nG + (int64_t)j * nao + i];
+    else
+      w = V[((int64_t)kneg[q] * nk + kneg[k]) * nV + Q * nG + e];
+    d = fmax(d, cabs2(make_double2(v.x - w.x, v.y + w.y)));
+    m = fmax(m, cabs2(v));
+  }
+  check_store(d, m, partial);
+}
+__global__ __launch_bounds__(256) void k_check_finish(const double* __restrict__ partial, int nb, double tol, int bit,
+                                                      int* __restrict__ status) {
+  if (threadIdx.x != 0) return;
+  double d = 0.0, m = 0.0;
+  bool finite = true;
+  for (int b = 0; b < nb; ++b) {
+    finite = finite && isfinite(partial[2 * b]) && isfinite(partial[2 * b + 1]);
+    d = fmax(d, partial[2 * b]);
+    m = fmax(m, partial[2 * b + 1]);
+  }
+  if (!finite || !(d <= tol * m)) atomicOr(status, bit);
+}
+
 inline unsigned grid_for(int64_t n) {
   int64_t b = (n + 255) / 256;
   if (b > 65536) b = 65536;
@@ -433,6 +533,42 @@ hipError_t launch_combine(double2* out, const double2* base, int64_t stride, int
   const int nb = mix_blocks(n);
   hipLaunchKernelGGL(k_combine, dim3(nb), dim3(256), 0, s, out, base, stride, n, cf, partial);
   if (partial && out_max) hipLaunchKernelGGL(k_max_partials, dim3(1), dim3(256), 0, s, partial, nb, out_max);
+  return hipGetLastError();
+}
+
+hipError_t launch_one_minus_copy(const double2* src, double2* dst, int n, int64_t batch, hipStream_t s) {
+  const int64_t total = (int64_t)n * n * batch;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_one_minus_copy, dim3(grid_for(total)), dim3(256), 0, s, src, dst, n, batch);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const double2* src, double2* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy, dim3(grid_for(n)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_conj_k(const double2* X, int64_t nblk, int nk, int64_t ne, const int32_t* kneg, double tol,
+                               int bit, double* partial, int* status, hipStream_t s) {
+  if (nblk * nk * ne <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_check_conj_k, dim3(kCheckBlocks), dim3(256), 0, s, X, nblk, nk, ne, kneg, partial);
+  hipLaunchKernelGGL(k_check_finish, dim3(1), dim3(64), 0, s, partial, kCheckBlocks, tol, bit, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_herm(const double2* X, int64_t nmat, int n, double tol, int bit, double* partial, int* status,
+                             hipStream_t s) {
+  if (nmat * n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_check_herm, dim3(kCheckBlocks), dim3(256), 0, s, X, nmat, n, partial);
+  hipLaunchKernelGGL(k_check_finish, dim3(1), dim3(64), 0, s, partial, kCheckBlocks, tol, bit, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_v(const double2* V, int nk, int naux, int nao, const int32_t* kadd, const int32_t* kneg,
+                          int mode, double tol, int bit, double* partial, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_v, dim3(kCheckBlocks), dim3(256), 0, s, V, nk, naux, nao, kadd, kneg, mode, partial);
+  hipLaunchKernelGGL(k_check_finish, dim3(1), dim3(64), 0, s, partial, kCheckBlocks, tol, bit, status);
   return hipGetLastError();
 }
 

@@ -93,14 +93,17 @@ struct ZGemm {
   int32_t ctype;  // ElemType of C (kCB16 requires beta == 0); prec 0 requires kC64 operands and output
   int32_t big;    // prec 2 with kCB16 operands, large-tile kernel: 1 = 192 x 96 tiles, 2 = 192 x 64,
                   // 3 = 320 x 64, 4 = 448 x 64 (3 and 4 need a K-contiguous B); LDS-DMA kernel (K-contiguous
-                  // A and B, even K and strides, else as 3 and 1): 5 = 320 x 64, 6 = 192 x 128
+                  // A and B, even K and strides, else as 3 and 1): 5 = 320 x 64, 6 = 192 x 128; LDS-DMA kernel
+                  // with prefetched fragments (K maps flat or of extent a multiple of 16, else as 3, 1 and 2):
+                  // 7 = 320 x 64, 8 = 128 x 128, 9 = 256 x 64
   int32_t shape;  // 256-thread kernels: 0 = by size, 1..4 = 32x32, 32x64, 64x32, 64x64 tiles
   int32_t band;   // large-tile kernel: 0 = output tiles in column order; b > 0 = bands of b tile rows,
                   // each walked column by column (the A rows of a band stay in L2)
 };
 
 // Kernel variant a descriptor launches: family 0 FP64, 1 FP32, 2 split BF16 (256 threads), 3 split BF16
-// large tiles (512 threads); tile (bm, bn) = (32 p1, 32 p2) or (64 p1, 32 p2) for family 3.
+// large tiles (512 threads), 4 LDS-DMA large tiles (512 threads), 5 LDS-DMA large tiles with prefetched
+// fragments (512 threads); tile (bm, bn) = (32 p1, 32 p2), (64 p1, 32 p2) for families 3 and 4.
 struct Variant {
   int32_t family, p1, p2;  // family -1: no kernel reads these operands
   bool bnc;   // family 3: B is N-contiguous
@@ -113,6 +116,8 @@ int64_t zgemm_blocks(const ZGemm& g);
 
 // Tile of the GEMM variant the launcher will pick (for choosing split-K counts).
 void zgemm_tile(const ZGemm& g, int* bm, int* bn, int* threads);
+// Workgroups of the variant resident per CU for the large-tile kernels (1 or 2), 0 for the 256-thread kernels.
+int zgemm_wgs_per_cu(const ZGemm& g);
 
 hipError_t zgemm(const ZGemm& g, hipStream_t s);
 

@@ -1159,6 +1159,249 @@ __device__ __forceinline__ void bd_body(const ZGemm& g, int64_t bid0, int64_t nb
   large_tile_store<FM, FN>(g, acc_re, acc_im, batch, slice, m0 + rowb, n0 + colb, lane);
 }
 
+// LDS-DMA large tiles with the next stage's fragments prefetched: 512 threads (8 waves as WGM x 8/WGM over the
+// tile, two per SIMD), each wave with FM x FN blocks of 16 x 16 and two sets of fragment registers.  DMA
+// staging and LDS layout as in bd_body (a three-slot ring of 16 complex K); the fragments of stage t + 1 are
+// read into the second register set right after the barrier that opens stage t, while the MFMAs of stage t
+// run from the first, so the matrix cores do not wait for LDS after a barrier.  K maps must be flat or of an
+// extent that is a multiple of 16 (no stage straddles a wrap).  The conjugated (re, -im) and swapped (im, re)
+// forms that give the real and the imaginary part are made from the operand with fewer blocks per wave:
+//   C_re = sum_k A (re, im) . B (re, -im),   C_im = sum_k A (re, im) . B (im, re)     (from B), or
+//   C_re = sum_k A (re, -im) . B (re, im),   C_im = sum_k A (im, re) . B (re, im)     (from A).
+__device__ __forceinline__ void wait_lgkm0() { __builtin_amdgcn_s_waitcnt((0 << 8) | (7 << 4) | 15 | (3 << 14)); }
+
+template <int FM, int FN, int WGM, int NS, int NW, bool Q>
+__device__ __forceinline__ void bq_body(const ZGemm& g, int64_t bid0, int64_t nblk) {
+  constexpr int WGN = NW / WGM;
+  static_assert(WGM * WGN == NW && (NW == 4 || NW == 8), "four or eight waves");
+  constexpr int NT = 64 * NW;
+  constexpr int BM = 16 * FM * WGM, BN = 16 * FN * WGN, BK = 16;
+  constexpr int DA = BM / (8 * NW), DB = BN / (8 * NW);  // DMA instructions per wave and stage (1 KB = 8 rows)
+  static_assert(BM % (8 * NW) == 0 && BN % (8 * NW) == 0, "tile of whole DMA groups");
+  constexpr int D = DA + DB;
+  constexpr bool VB = FN <= FM;
+  // one LDS array: slot s of A at word s SA, of B at NS SA + s SB (rows of 32 words: 16 complex, hi/lo)
+  constexpr int SA = BM * 32, SB = BN * 32;
+  static_assert(NS >= 3 && NS * (SA + SB) * 4 <= (NW == 4 ? 80 : 160) * 1024, "LDS ring");
+  __shared__ __attribute__((aligned(16))) uint32_t lds[NS * (SA + SB)];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const LargeTile lt = large_tile(g, bid0, nblk, BM, BN);
+  const int32_t batch = lt.batch, slice = lt.slice;
+  const int m0 = lt.m0, n0 = lt.n0;
+  const int kchunk = ((g.K + g.ksplit - 1) / g.ksplit + BK - 1) / BK * BK;
+  const int kbeg = slice * kchunk;
+  const int kend = min(g.K, kbeg + kchunk);
+  const int nkt = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+
+  const char* Ap = reinterpret_cast<const char*>(reinterpret_cast<const uint2*>(g.A.p) + batch_off(g.A.b, batch));
+  const char* Bp = reinterpret_cast<const char*>(reinterpret_cast<const uint2*>(g.B.p) + batch_off(g.B.b, batch));
+  // Copies: instruction j of this wave fills LDS row 8 (wave D + j) + (lane >> 3) of a slot, lane l writing slot
+  // chunk (l & 7) there, i.e. memory chunk (l & 7) ^ row_xor(row) = c_even ^ ((wave D + j) & 1).  Element offsets
+  // of a row (column) and of the K positions stay below 2^29 (checked on the host), so each lane carries 32-bit
+  // byte offsets from a uniform base: a_lane[j] = (row offset + 2 chunk) * 8.
+  const int c_even = (lane & 7) ^ (lane >> 3);
+  uint32_t a_ro[DA], b_co[DB];
+#pragma unroll
+  for (int j = 0; j < DA; ++j)
+    a_ro[j] = (uint32_t)map_idx(g.A.r, min(m0 + 8 * (wave * DA + j) + (lane >> 3), g.M - 1));
+#pragma unroll
+  for (int j = 0; j < DB; ++j)
+    b_co[j] = (uint32_t)map_idx(g.B.c, min(n0 + 8 * (wave * DB + j) + (lane >> 3), g.N - 1));
+  // K maps are flat or of an extent that is a multiple of 16 (checked on the host), so a stage never straddles
+  // a wrap; only the slice's last stage can end early, and its chunks past the end copy the stage's first
+  // chunk and are zeroed in LDS once landed
+  KCur acur, bcur;
+  acur.init(g.A.c, kbeg);
+  bcur.init(g.B.r, kbeg);
+  const int64_t a_din = (int64_t)BK * g.A.c.s_in, a_wrap = g.A.c.s_out - (int64_t)g.A.c.ext * g.A.c.s_in;
+  const int64_t b_din = (int64_t)BK * g.B.r.s_in, b_wrap = g.B.r.s_out - (int64_t)g.B.r.ext * g.B.r.s_in;
+  auto issue = [&](int slot) {
+    uint32_t* As = lds + slot * SA;
+    uint32_t* Bs = lds + NS * SA + slot * SB;
+    // chunk part of this lane's element offset, for the two chunk parities
+    uint32_t ca[2], cb[2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const int c = c_even ^ p;
+      const int dk = Q ? 4 * (c >> 1) : 2 * c;
+      ca[p] = acur.k + dk < kend ? 2u * c : 0u;
+      cb[p] = bcur.k + dk < kend ? 2u * c : 0u;
+    }
+    const char* abase = Ap + acur.off * 8;
+    const char* bbase = Bp + bcur.off * 8;
+#pragma unroll
+    for (int j = 0; j < DA; ++j) {
+      uint32_t o = (a_ro[j] + ca[(wave * DA + j) & 1]) * 8u;
+      asm volatile("" : "+v"(o));
+      dma16(abase + o, As + (wave * DA + j) * 256);
+    }
+#pragma unroll
+    for (int j = 0; j < DB; ++j) {
+      uint32_t o = (b_co[j] + cb[(wave * DB + j) & 1]) * 8u;
+      asm volatile("" : "+v"(o));
+      dma16(bbase + o, Bs + (wave * DB + j) * 256);
+    }
+    acur.step(g.A.c, BK, a_din, a_wrap);
+    bcur.step(g.B.r, BK, b_din, b_wrap);
+  };
+  const int kvalid_last = (kend - kbeg) - BK * (nkt - 1);  // complex K of the last stage, even
+  // chunks past the slice's end in a landed stage -> 0 (every row of both tiles)
+  auto zero_tail = [&](int slot) {
+    uint32_t* As = lds + slot * SA;
+    uint32_t* Bs = lds + NS * SA + slot * SB;
+    for (int x = tid; x < (BM + BN) * 8; x += NT) {
+      const int r = x >> 3, c = x & 7;
+      if ((Q ? 4 * (c >> 1) : 2 * c) < kvalid_last) continue;
+      uint32_t* P = r < BM ? As + r * 32 : Bs + (r - BM) * 32;
+      const int rr = r < BM ? r : r - BM;
+      *reinterpret_cast<u4*>(P + 4 * bd_slot(rr, c)) = u4{0u, 0u, 0u, 0u};
+    }
+  };
+
+  f4 acc_re[FM][FN], acc_im[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      acc_re[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      acc_im[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+  const int wm = wave % WGM, wn = wave / WGM;
+  const int rowb = wm * 16 * FM, colb = wn * 16 * FN;
+  const int g4 = lane >> 4, r16 = lane & 15;
+  // Fragment reads: row rowb + 16 i + r16 of a slot, chunks 2 g4 and 2 g4 + 1 under the swizzle c ^ row_xor(r),
+  // and row_xor of those rows depends on r16 only, so one pair of lane offsets serves every block and slot
+  // (the block and the slot are constant offsets)
+  const int rx = row_xor(r16);
+  const uint32_t fa0 = (uint32_t)((rowb + r16) * 32 + 4 * ((2 * g4) ^ rx));
+  const uint32_t fa1 = (uint32_t)((rowb + r16) * 32 + 4 * ((2 * g4 + 1) ^ rx));
+  const uint32_t fb0 = (uint32_t)((colb + r16) * 32 + 4 * ((2 * g4) ^ rx));
+  const uint32_t fb1 = (uint32_t)((colb + r16) * 32 + 4 * ((2 * g4 + 1) ^ rx));
+  struct Frags {
+    u4 ah[FM], al[FM], bh[FN], bl[FN];
+  };
+  auto unpack = [&](u4 x, u4 y, u4& hi, u4& lo) {
+    if constexpr (Q) {
+      hi = x;
+      lo = y;
+    } else {
+      hi = u4{x.x, x.z, y.x, y.z};
+      lo = u4{x.y, x.w, y.y, y.w};
+    }
+  };
+  auto read_frags = [&](int slot, Frags& f) {
+    const uint32_t* As = lds + slot * SA;
+    const uint32_t* Bs = lds + NS * SA + slot * SB;
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+      unpack(*reinterpret_cast<const u4*>(Bs + fb0 + 512 * j), *reinterpret_cast<const u4*>(Bs + fb1 + 512 * j),
+             f.bh[j], f.bl[j]);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+      unpack(*reinterpret_cast<const u4*>(As + fa0 + 512 * i), *reinterpret_cast<const u4*>(As + fa1 + 512 * i),
+             f.ah[i], f.al[i]);
+  };
+  // the operand forms are made one block at a time, right before the MFMAs that use them
+  auto compute = [&](const Frags& f) {
+    if constexpr (VB) {
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const bf8 bch = as_bf8(neg_im(f.bh[j])), bcl = as_bf8(neg_im(f.bl[j]));
+        const bf8 bsh = as_bf8(swap_re_im(f.bh[j])), bsl = as_bf8(swap_re_im(f.bl[j]));
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+          const bf8 ah = as_bf8(f.ah[i]), al = as_bf8(f.al[i]);
+          acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bch, acc_re[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bsh, acc_im[i][j], 0, 0, 0);
+          acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bcl, acc_re[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bsl, acc_im[i][j], 0, 0, 0);
+          acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bch, acc_re[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bsh, acc_im[i][j], 0, 0, 0);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        const bf8 ach = as_bf8(neg_im(f.ah[i])), acl = as_bf8(neg_im(f.al[i]));
+        const bf8 ash = as_bf8(swap_re_im(f.ah[i])), asl = as_bf8(swap_re_im(f.al[i]));
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const bf8 bh = as_bf8(f.bh[j]), bl = as_bf8(f.bl[j]);
+          acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ach, bh, acc_re[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ash, bh, acc_im[i][j], 0, 0, 0);
+          acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ach, bl, acc_re[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ash, bl, acc_im[i][j], 0, 0, 0);
+          acc_re[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(acl, bh, acc_re[i][j], 0, 0, 0);
+          acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(asl, bh, acc_im[i][j], 0, 0, 0);
+        }
+      }
+    }
+  };
+  // stage t (fragments in `cur`): own copies of stage t + 1 landed (those of up to NS - 2 later stages may be in
+  // flight) and the fragment reads of stage t done -> barrier (every wave's copies of t + 1 landed, every wave
+  // done reading the slot of stage t) -> stage t + NS copied into that slot -> fragments of t + 1 into `nxt` ->
+  // MFMAs of stage t
+  Frags f0, f1;
+  auto wait_landed = [&](int later) {  // own copies outstanding beyond the stage waited for: `later` stages
+    static_assert(NS <= 4, "ring depth");
+    if constexpr (NS >= 4) {
+      if (later >= 3) {
+        wait_vm<3 * D>();
+        return;
+      }
+    }
+    if (later >= 2) wait_vm<2 * D>();
+    else if (later >= 1) wait_vm<D>();
+    else wait_vm<0>();
+  };
+  auto step = [&](int t, int rslot, int wslot, const Frags& cur, Frags& nxt) {
+    if (t + 1 < nkt) {
+      wait_landed(min(NS - 2, nkt - 2 - t));
+      wait_lgkm0();
+      barrier_only();
+      if (t + NS < nkt) issue(wslot);
+      if (t + 2 == nkt && kvalid_last < BK) {
+        zero_tail(rslot);
+        __syncthreads();
+      }
+      read_frags(rslot, nxt);
+    } else {
+      wait_lgkm0();
+    }
+    compute(cur);
+  };
+  if (nkt > 0) {
+#pragma unroll
+    for (int st = 0; st < NS; ++st)
+      if (st < nkt) issue(st);
+    wait_landed(min(NS - 1, nkt - 1));
+    barrier_only();
+    if (nkt == 1 && kvalid_last < BK) {
+      zero_tail(0);
+      __syncthreads();
+    }
+    read_frags(0, f0);
+    // register sets alternate with the parity of t, slots rotate modulo NS (uniform); the loop body is always
+    // two whole steps (one exit), an odd last step follows it
+    int rs = 1, ws = 0, t = 0;
+    for (; t + 2 <= nkt; t += 2) {
+      step(t, rs, ws, f0, f1);
+      rs = rs == NS - 1 ? 0 : rs + 1;
+      ws = ws == NS - 1 ? 0 : ws + 1;
+      step(t + 1, rs, ws, f1, f0);
+      rs = rs == NS - 1 ? 0 : rs + 1;
+      ws = ws == NS - 1 ? 0 : ws + 1;
+    }
+    if (t < nkt) step(t, rs, ws, f0, f1);
+  }
+  // every wave is done with the LDS stages before any wave of a persistent group starts another tile
+  __syncthreads();
+  large_tile_store<FM, FN>(g, acc_re, acc_im, batch, slice, m0 + rowb, n0 + colb, lane);
+}
+
 // Sigma~ stages 2 and 3 fused (split BF16).  For each (tt, k) of one tau chunk (one q, one spin):
 //   S^T[j][i] = sum_{Q'} sum_b VT[k][Q'][j][b] Y^T[b][i],   Y^T[b][i] = sum_a GT[tt][k][b][a] X[tt][k][Q'][i][a]
 // (Y = X G, S = Y V).  Y never leaves the registers: the 16 x 16 FP32 accumulator tile of Y^T that a lane
@@ -1423,6 +1666,10 @@ template <int FM, int FN, bool Q, Site SITE>
 __global__ __launch_bounds__(512) void zgemm_bd_kernel(const ZGemm g) {
   bd_body<FM, FN, Q>(g, blockIdx.x, gridDim.x);
 }
+template <int FM, int FN, int WGM, int NS, int NW, bool Q, Site SITE>
+__global__ __launch_bounds__(64 * NW, NW == 4 ? 2 : 1) void zgemm_bq_kernel(const ZGemm g) {
+  bq_body<FM, FN, WGM, NS, NW, Q>(g, blockIdx.x, gridDim.x);
+}
 
 struct GroupArgs {
   const ZGemm* gs;       // device array of n descriptors
@@ -1457,6 +1704,10 @@ __global__ __launch_bounds__(512) void zgemm_bt_group(const GroupArgs a) {
 template <int FM, int FN, bool Q>
 __global__ __launch_bounds__(512) void zgemm_bd_group(const GroupArgs a) {
   group_loop(a, [](const ZGemm& g, int64_t b, int64_t n) { bd_body<FM, FN, Q>(g, b, n); });
+}
+template <int FM, int FN, int WGM, int NS, int NW, bool Q>
+__global__ __launch_bounds__(64 * NW, NW == 4 ? 2 : 1) void zgemm_bq_group(const GroupArgs a) {
+  group_loop(a, [](const ZGemm& g, int64_t b, int64_t n) { bq_body<FM, FN, WGM, NS, NW, Q>(g, b, n); });
 }
 // split-K second pass of a group: descriptor blockIdx.y, elements strided over blockIdx.x
 __global__ __launch_bounds__(256) void zgemm_splitk_reduce_group(const ZGemm* __restrict__ gs) {
@@ -1675,8 +1926,25 @@ static bool even_batch(const BatchMap& b) { return b.s_lo % 2 == 0 && b.s_hi % 2
 // kCB16Q operands (both or neither) need every row and every K block to start a group of 4: K, extents
 // and strides multiples of 4.
 static bool quad_map(const IdxMap& m) { return m.s_in % 4 == 0 && (m.ext == kFlat || m.s_out % 4 == 0); }
+// largest |offset| an index map gives over [0, n)
+static int64_t map_extent(const IdxMap& m, int64_t n) {
+  if (n <= 0) return 0;
+  if (m.ext == kFlat) return (n - 1) * std::abs(m.s_in);
+  return (std::min<int64_t>(m.ext, n) - 1) * std::abs(m.s_in) + ((n - 1) / m.ext) * std::abs(m.s_out);
+}
 static bool dma_ok(const ZGemm& g) {
-  if (g.big < 5 || g.big > 6) return false;
+  if (g.big < 5 || g.big > 11) return false;
+  // the prefetching kernel forms byte offsets from the operand's batch base in 32 bits: non-negative strides
+  // and element offsets (row or column plus K) below 2^29
+  if (g.big >= 7) {
+    for (const IdxMap* m : {&g.A.r, &g.A.c, &g.B.r, &g.B.c})
+      if (m->s_in < 0 || m->s_out < 0) return false;
+    for (const IdxMap* m : {&g.A.c, &g.B.r})
+      if (m->ext != kFlat && m->ext % 16 != 0) return false;
+    const int64_t lim = (int64_t)1 << 29;
+    if (map_extent(g.A.r, g.M) + map_extent(g.A.c, g.K) + 16 > lim) return false;
+    if (map_extent(g.B.c, g.N) + map_extent(g.B.r, g.K) + 16 > lim) return false;
+  }
   const bool q = g.A.etype == kCB16Q;
   if ((g.A.etype != kCB16 && !q) || g.B.etype != g.A.etype || g.A.conj || g.B.conj) return false;
   const int u = q ? 4 : 2;  // K granule of one 16-byte copy
@@ -1690,9 +1958,13 @@ static bool dma_ok(const ZGemm& g) {
   return ((uintptr_t)g.A.p % 16 == 0) && ((uintptr_t)g.B.p % 16 == 0);
 }
 
-// LDS-DMA tiles by g.big: 5 = 320 x 64, 6 = 192 x 128.
+// LDS-DMA tiles by g.big (512 threads, 16 x 16 blocks per wave FM x FN): 5 = 320 x 64, 6 = 192 x 128; with the
+// next stage's fragments prefetched: 7 = 320 x 64 (4 x 2 waves of 5 x 2 blocks, three-slot ring), 8 = 128 x 128
+// (2 x 4 waves of 4 x 2 blocks, four-slot ring), 9 = 256 x 64 (4 x 2 waves of 4 x 2 blocks, four-slot ring);
+// 256 threads, two workgroups per CU, three-slot ring: 10 = 128 x 64 (2 x 2 waves of 4 x 2 blocks), 11 = 64 x 128
+// (1 x 4 waves of 4 x 2 blocks).
 static void dma_tile(int big, int* fm, int* fn) {
-  static const int t[2][2] = {{5, 2}, {3, 4}};
+  static const int t[7][2] = {{5, 2}, {3, 4}, {5, 2}, {4, 2}, {4, 2}, {4, 2}, {4, 2}};
   *fm = t[big - 5][0];
   *fn = t[big - 5][1];
 }
@@ -1703,13 +1975,21 @@ static void dma_tile(int big, int* fm, int* fn) {
 Variant zgemm_variant(const ZGemm& g) {
   Variant v{};
   if (g.prec == 2 && dma_ok(g)) {
-    v.family = 4;
+    v.family = g.big >= 7 ? 5 : 4;
     dma_tile(g.big, &v.p1, &v.p2);
     v.bnc = false;
     v.quad = g.A.etype == kCB16Q;
-    v.threads = 512;
-    v.bm = 64 * v.p1;
-    v.bn = 32 * v.p2;
+    if (v.family == 5) {
+      const int nw = g.big >= 10 ? 4 : 8;
+      const int wgm = g.big == 11 ? 1 : (g.big == 8 || g.big == 10) ? 2 : 4;
+      v.threads = 64 * nw;
+      v.bm = 16 * v.p1 * wgm;
+      v.bn = 16 * v.p2 * (nw / wgm);
+    } else {
+      v.threads = 512;
+      v.bm = 64 * v.p1;
+      v.bn = 32 * v.p2;
+    }
     return v;
   }
   if (g.A.etype == kCB16Q || g.B.etype == kCB16Q) {  // only the LDS-DMA kernel reads grouped operands
@@ -1721,7 +2001,7 @@ Variant zgemm_variant(const ZGemm& g) {
   // an LDS-DMA tile the operands do not allow falls back to a register-staged one: 320 x 64 to the same
   // tile, 192 x 128 to 192 x 96
   ZGemm gb = g;
-  if (gb.big >= 5) gb.big = gb.big == 5 ? 3 : 1;
+  if (gb.big >= 5) gb.big = (gb.big == 5 || gb.big == 7) ? 3 : (gb.big == 6 || gb.big == 8) ? 1 : 2;
   if (g.prec == 2 && big_ok(gb)) {
     v.family = 3;
     big_tile(gb.big, &v.p1, &v.p2);
@@ -1747,7 +2027,14 @@ Variant zgemm_variant(const ZGemm& g) {
 }
 
 bool same_variant(const Variant& a, const Variant& b) {
-  return a.family == b.family && a.p1 == b.p1 && a.p2 == b.p2 && a.bnc == b.bnc && a.quad == b.quad;
+  return a.family == b.family && a.p1 == b.p1 && a.p2 == b.p2 && a.bnc == b.bnc && a.quad == b.quad &&
+         a.threads == b.threads && a.bm == b.bm && a.bn == b.bn;
+}
+
+int zgemm_wgs_per_cu(const ZGemm& g) {
+  const Variant v = zgemm_variant(g);
+  if (v.family < 3) return 0;
+  return v.family == 5 && v.threads == 256 ? 2 : 1;
 }
 
 void zgemm_tile(const ZGemm& g, int* bm, int* bn, int* threads) {
@@ -1804,6 +2091,16 @@ void launch_bt(const ZGemm& g, dim3 grid, hipStream_t s) {
   }
 }
 
+template <int FM, int FN, int WGM, int NS, int NW, bool Q>
+void launch_bq(const ZGemm& g, dim3 grid, hipStream_t s) {
+  const dim3 b(64 * NW);
+  switch (g.site) {
+    case Site::P0_Contract: zgemm_bq_kernel<FM, FN, WGM, NS, NW, Q, Site::P0_Contract><<<grid, b, 0, s>>>(g); break;
+    case Site::Sig_PV: zgemm_bq_kernel<FM, FN, WGM, NS, NW, Q, Site::Sig_PV><<<grid, b, 0, s>>>(g); break;
+    default: zgemm_bq_kernel<FM, FN, WGM, NS, NW, Q, Site::Generic><<<grid, b, 0, s>>>(g); break;
+  }
+}
+
 template <int FM, int FN, bool Q>
 void launch_bd(const ZGemm& g, dim3 grid, hipStream_t s) {
   switch (g.site) {
@@ -1842,6 +2139,17 @@ void launch_single(const Variant& v, const ZGemm& g, dim3 grid, hipStream_t s) {
         if (v.quad) launch_bd<3, 4, true>(g, grid, s);
         else launch_bd<3, 4, false>(g, grid, s);
       }
+      break;
+    case 5:
+#define GREEN_BQ(...) (v.quad ? launch_bq<__VA_ARGS__, true>(g, grid, s) : launch_bq<__VA_ARGS__, false>(g, grid, s))
+      switch (v.p1 * 100 + v.bm / 16 * 10 + v.threads / 64) {
+        case 5 * 100 + 20 * 10 + 8: GREEN_BQ(5, 2, 4, 3, 8); break;   // 320 x 64
+        case 4 * 100 + 16 * 10 + 8: GREEN_BQ(4, 2, 4, 4, 8); break;   // 256 x 64
+        case 4 * 100 + 8 * 10 + 8: GREEN_BQ(4, 2, 2, 4, 8); break;    // 128 x 128
+        case 4 * 100 + 8 * 10 + 4: GREEN_BQ(4, 2, 2, 3, 4); break;    // 128 x 64, two per CU
+        default: GREEN_BQ(4, 2, 1, 3, 4); break;                      // 64 x 128, two per CU
+      }
+#undef GREEN_BQ
       break;
     default:
       if (v.p1 == 5) launch_bt<5, 2, false>(g, grid, s);
@@ -1887,6 +2195,18 @@ void launch_group(const Variant& v, const GroupArgs& a, dim3 grid, hipStream_t s
         if (v.quad) zgemm_bd_group<3, 4, true><<<grid, b512, 0, s>>>(a);
         else zgemm_bd_group<3, 4, false><<<grid, b512, 0, s>>>(a);
       }
+      break;
+    case 5:
+#define GREEN_BQG(...) (v.quad ? zgemm_bq_group<__VA_ARGS__, true><<<grid, dim3(v.threads), 0, s>>>(a) \
+                               : zgemm_bq_group<__VA_ARGS__, false><<<grid, dim3(v.threads), 0, s>>>(a))
+      switch (v.p1 * 100 + v.bm / 16 * 10 + v.threads / 64) {
+        case 5 * 100 + 20 * 10 + 8: GREEN_BQG(5, 2, 4, 3, 8); break;
+        case 4 * 100 + 16 * 10 + 8: GREEN_BQG(4, 2, 4, 4, 8); break;
+        case 4 * 100 + 8 * 10 + 8: GREEN_BQG(4, 2, 2, 4, 8); break;
+        case 4 * 100 + 8 * 10 + 4: GREEN_BQG(4, 2, 2, 3, 4); break;
+        default: GREEN_BQG(4, 2, 1, 3, 4); break;
+      }
+#undef GREEN_BQG
       break;
     default:
       if (v.p1 == 5) zgemm_bt_group<5, 2, false><<<grid, b512, 0, s>>>(a);
@@ -1941,7 +2261,7 @@ hipError_t zgemm_group(const ZGemm* host, int n, const ZGemm* dev, const int64_t
   }
   GroupArgs a{dev, dev_start, n, total};
   // persistent grid: at most 8 workgroups per CU resident over 256 CUs
-  const int64_t cap = (v.threads == 512 ? 1 : 4) * 256 * 8;
+  const int64_t cap = (v.family >= 3 ? 1 : 4) * 256 * 8;
   launch_group(v, a, dim3((unsigned)std::min<int64_t>(total, cap)), s);
   if (reduce_elems > 0) {
     int64_t nb = (reduce_elems + 255) / 256;

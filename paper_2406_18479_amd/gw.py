@@ -92,12 +92,13 @@ class Plan:
         return (self.nk, self.nao, self.nao)
 
     def set_option(self, option: str, value: int) -> None:
-        """option "tune" (0, 1, 2), "graph" (0, 1), "p0_tile" (1..6), "stage1_tile" (0..2), "sigma_fused"
+        """option "tune" (0, 1, 2), "graph" (0, 1), "p0_tile" (1..9), "sigma_tile" (1..9), "stage1_tile" (0..2), "sigma_fused"
         (0, 1), "gf2" (0, 1), "time_reversal" (0, 1) or "v_half" (0, 1: V holds the canonical-q slabs only,
         shape_V follows); see green_plan_set_option.  The workspace is re-allocated when the option grows it."""
         code = {"tune": _lib.OPT_TUNE, "graph": _lib.OPT_GRAPH, "p0_tile": _lib.OPT_P0_TILE,
                 "stage1_tile": _lib.OPT_STAGE1_TILE, "sigma_fused": _lib.OPT_SIGMA_FUSED,
-                "gf2": _lib.OPT_GF2, "time_reversal": _lib.OPT_TIME_REVERSAL, "v_half": _lib.OPT_V_HALF}[option]
+                "gf2": _lib.OPT_GF2, "time_reversal": _lib.OPT_TIME_REVERSAL, "v_half": _lib.OPT_V_HALF,
+                "sigma_tile": _lib.OPT_SIGMA_TILE}[option]
         _lib.check(_lib.LIB.green_plan_set_option(self._h, code, int(value)), "green_plan_set_option")
         if option == "v_half":
             self.v_half = bool(value)
@@ -178,6 +179,11 @@ class Plan:
                                         ctypes.byref(m), _ptr(G, self.shape_G, "G", self.device), ctypes.byref(n),
                                         ctypes.byref(ev), self.ws.data_ptr(), _stream(self.device)), "green_dyson")
         return G, m.value, n.value, ev.value
+
+    def check_status(self):
+        """Raise the error latched on the device by earlier calls (green_check_status); synchronises."""
+        _lib.check(_lib.LIB.green_check_status(self._h, self.ws.data_ptr(), _stream(self.device)),
+                   "green_check_status")
 
     def dyson_noalloc(self, H0, S, Sinf, Sigma, mu, n_target=-1.0, G=None):
         """dyson() through green_dyson_noalloc: the library works in its static device scratch (no workspace)."""

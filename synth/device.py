@@ -91,23 +91,28 @@ def _impose_time_reversal(spec: SystemSpec, V: torch.Tensor) -> None:
             done |= orbit
 
 
-def make_V(spec: SystemSpec, device="cuda:0", out: torch.Tensor | None = None) -> torch.Tensor:
-    """V[q][k] = V^{k,k+q}(Q) on `device`, identical in construction to synth.systems.make_V."""
+def make_V(spec: SystemSpec, device="cuda:0", out: torch.Tensor | None = None, qs=None) -> torch.Tensor:
+    """V[q][k] = V^{k,k+q}(Q) on `device`, identical in construction to synth.systems.make_V.  qs: only the slabs
+    of these momentum transfers, in that order (out[i] = slab qs[i]; not with time-reversal averaging, which
+    mixes slabs)."""
     nk = spec.nk
     add = k_add_table(spec.kmesh)
+    qs = list(range(nk)) if qs is None else list(qs)
+    if spec.v_time_reversal and qs != list(range(nk)):
+        raise ValueError("time-reversal-averaged V is generated whole")
     env = (spec.amp * torch.exp(-spec.v_decay * torch.arange(spec.naux, dtype=torch.float64))).to(device)
     if out is None:
-        out = torch.empty((nk, nk, spec.naux, spec.nao, spec.nao), dtype=torch.complex128, device=device)
-    for q in range(nk):
+        out = torch.empty((len(qs), nk, spec.naux, spec.nao, spec.nao), dtype=torch.complex128, device=device)
+    for iq, q in enumerate(qs):
         for k in range(nk):
             k2 = int(add[k, q])
             if k == k2:
                 Z = _block(spec, k, k, env, device)
-                out[q, k] = 0.5 * (Z + Z.conj().transpose(1, 2))
+                out[iq, k] = 0.5 * (Z + Z.conj().transpose(1, 2))
             elif k < k2:
-                out[q, k] = _block(spec, k, k2, env, device)
+                out[iq, k] = _block(spec, k, k2, env, device)
             else:
-                out[q, k] = _block(spec, k2, k, env, device).conj().transpose(1, 2)
+                out[iq, k] = _block(spec, k2, k, env, device).conj().transpose(1, 2)
     if spec.v_time_reversal:
         _impose_time_reversal(spec, out)
     return out

@@ -76,6 +76,24 @@ def test_all_launches_in_bounds(lib, c, prec):
         lib.LIB.green_plan_destroy(h)
 
 
+@pytest.mark.parametrize("tiles", [(7, 7), (8, 8), (9, 9), (10, 10), (11, 11)])
+@pytest.mark.parametrize("c", [CASES[1], CASES[3], CASES[4], CASES[6]],
+                         ids=["k2x2x2", "k3x3x3", "k4x4x4", "nao17_ch1"])
+def test_read_ahead_tiles_in_bounds(lib, c, tiles):
+    """The split-BF16 contractions with the read-ahead LDS-DMA tiles forced (P~0 sum and Sigma~ stage 1) stay in
+    their buffers on the production shapes (or fall back where the operands do not allow those tiles)."""
+    h = _plan(lib, c, 2)
+    try:
+        L = lib.LIB
+        assert L.green_plan_set_option(h, lib.OPT_P0_TILE, tiles[0]) == 0
+        assert L.green_plan_set_option(h, lib.OPT_SIGMA_TILE, tiles[1]) == 0
+        V, G, P0, Pt, Sig, ws = [BASE + i * STEP for i in range(6)]
+        assert L.green_gw_polarization(h, V, G, P0, ws, None) == 0
+        assert L.green_gw_selfenergy(h, V, G, Pt, Sig, ws, None) == 0
+    finally:
+        lib.LIB.green_plan_destroy(h)
+
+
 @pytest.mark.parametrize("opts", ["plain", "options"])
 @pytest.mark.parametrize("prec", [0, 2], ids=["fp64", "bf16x3"])
 def test_batched_iteration_in_bounds(lib, prec, opts):
@@ -119,10 +137,13 @@ def test_plan_options_and_tuning_report(lib):
         assert L.green_plan_set_option(h, lib.OPT_TUNE, 3) == -1
         assert L.green_plan_set_option(h, lib.OPT_GRAPH, 1) == 0
         assert L.green_plan_set_option(h, lib.OPT_GRAPH, 2) == -1
-        for v in (1, 2, 3, 4, 5, 6):
+        for v in range(1, 12):
             assert L.green_plan_set_option(h, lib.OPT_P0_TILE, v) == 0
+            assert L.green_plan_set_option(h, lib.OPT_SIGMA_TILE, v) == 0
         assert L.green_plan_set_option(h, lib.OPT_P0_TILE, 0) == -1
-        assert L.green_plan_set_option(h, lib.OPT_P0_TILE, 7) == -1
+        assert L.green_plan_set_option(h, lib.OPT_P0_TILE, 12) == -1
+        assert L.green_plan_set_option(h, lib.OPT_SIGMA_TILE, 0) == -1
+        assert L.green_plan_set_option(h, lib.OPT_SIGMA_TILE, 12) == -1
         for v in (0, 1, 2):
             assert L.green_plan_set_option(h, lib.OPT_STAGE1_TILE, v) == 0
         assert L.green_plan_set_option(h, lib.OPT_STAGE1_TILE, 3) == -1

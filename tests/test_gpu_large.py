@@ -41,12 +41,16 @@ def _plan(s, prec):
 
 
 def test_polarization_sampled_tau(periodic3):
+    """FP64 P~0 of the whole 3x3x3 workload at 12 tau nodes against the oracle: the FP64 plan contracts chunks of
+    12 nodes (8 GiB of intermediates), so the nodes sit on both sides of chunk edges (11|12, 35|36, 59|60,
+    131|132), and for q = 0 (its own partner) on both sides of the half the library contracts (67|68, the rest
+    transposed from the first half); every q, with the partners -q of the +-q identity."""
     s = periodic3
     sp = s.spec
     say("polarization 3x3x3 fp64")
     p = _plan(s, "fp64")
     P = p.polarization(s.V_dev, torch.from_numpy(s.G0).to("cuda:0"))
-    ts = [0, 67, 135]
+    ts = [0, 11, 12, 35, 36, 59, 60, 67, 68, 100, 131, 132, 135]
     got = P[:, ts].cpu().numpy()
     del P, p
     torch.cuda.empty_cache()

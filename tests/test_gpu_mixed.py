@@ -67,12 +67,14 @@ def test_mixed_polarization_and_selfenergy(c, prec):
     assert rel(Smx, S64) <= REL[prec]
 
 
-@pytest.mark.parametrize("tile,nao", [(1, 10), (2, 10), (3, 10), (4, 10), (5, 10), (6, 10), (5, 12), (6, 12)])
+@pytest.mark.parametrize("tile,nao", [(1, 10), (2, 10), (3, 10), (4, 10), (5, 10), (6, 10), (7, 10), (5, 12), (6, 12),
+                                      (7, 12), (8, 12), (9, 12), (10, 12), (11, 12)])
 def test_split_bf16_p0_tiles(tile, nao):
     """Every output tile of the split-BF16 P~0 contraction (register-staged 192 x 96, 192 x 64, 320 x 64,
-    448 x 64; LDS-DMA 320 x 64, 192 x 128) on an naux that leaves ragged tiles along both P~0 dimensions,
-    against the FP64 path.  nao = 10: K = nk nao^2 = 200, whose orbital-pair blocks (100) and end fall inside
-    16-wide K stages; nao = 12: blocks of 144 that are whole stages."""
+    448 x 64; LDS-DMA 320 x 64, 192 x 128; LDS-DMA with operands read a stage ahead 320 x 64, 128 x 128,
+    256 x 64, and two workgroups per CU 128 x 64, 64 x 128) on an naux that leaves ragged tiles along both P~0 dimensions, against the FP64 path.  nao = 10:
+    K = nk nao^2 = 200, whose orbital-pair blocks (100) and end fall inside 16-wide K stages (the read-ahead
+    kernel then falls back to the register-staged one); nao = 12: blocks of 144 that are whole stages."""
     _require_gpu()
     s = systems.make_system(configs.tiny(kmesh=(2, 1, 1), nao=nao, naux=350, ntau=6, beta=8.0, seed=204,
                                          v_scale=0.5 / nao ** 0.5))
@@ -83,6 +85,25 @@ def test_split_bf16_p0_tiles(tile, nao):
     P64 = host(p64.polarization(V, G))
     Pmx = host(pmx.polarization(V, G))
     assert rel(Pmx, P64) <= REL["bf16x3"]
+
+
+@pytest.mark.parametrize("tile", [5, 6, 7, 8, 9, 10, 11])
+@pytest.mark.parametrize("naux", [300, 52, 64, 70])
+def test_split_bf16_sigma_tiles(tile, naux):
+    """Every LDS-DMA tile of the first split-BF16 Sigma~ contraction (P~^T V over the auxiliary index, K = naux)
+    against the FP64 path: naux 300 and 52 end in a partial 16-wide K stage (12 and 4 left), 64 in whole stages,
+    70 is not a multiple of 4 (operands in plain rather than grouped split-BF16 layout)."""
+    _require_gpu()
+    s = systems.make_system(configs.tiny(kmesh=(2, 1, 1), nao=8, naux=naux, ntau=10, beta=8.0, seed=209,
+                                         v_scale=0.5 / 8 ** 0.5))
+    print("[gpu-case] split-BF16 Sigma stage-1 tile", tile, "naux", naux, flush=True)
+    V, G = dev(s.V), dev(s.G0)
+    Pt = dev(systems.random_polarization(11, s.spec.nk, s.spec.ntau, s.spec.naux, scale=0.1))
+    p64, pmx = plan(s, "fp64"), plan(s, "bf16x3")
+    pmx.set_option("sigma_tile", tile)
+    S64 = host(p64.selfenergy(V, G, Pt))
+    Smx = host(pmx.selfenergy(V, G, Pt))
+    assert rel(Smx, S64) <= REL["bf16x3"]
 
 
 FUSED = [dict(kmesh=(2, 1, 1), nao=8, naux=40, ntau=10, seed=205),     # one 16-row block
