@@ -37,6 +37,19 @@ def contraction_flops(nk, nao, naux, ntau, nspin) -> float:
     return 2.0 * 8.0 * cmac
 
 
+def executed_fraction(spec) -> float:
+    """Share of the algorithmic contraction flops the library executes: P~0 is contracted for one q of each +-q
+    pair (half the tau nodes where q = -q), and with time reversal on half the tau nodes of every q and Sigma~ for
+    the momenta k with -k >= k only."""
+    from synth.systems import k_neg
+    neg = k_neg(spec.kmesh)
+    nk = spec.nk
+    tr = time_reversal_symmetric(spec)
+    p0 = sum((0.5 if (neg[q] == q or tr) else 1.0) for q in range(nk) if neg[q] >= q) / nk
+    sig = sum(1 for k in range(nk) if neg[k] >= k) / nk if tr else 1.0
+    return 0.5 * (p0 + sig)
+
+
 def workloads():
     from synth import configs
     return {"molecule": configs.MOLECULE, "periodic2": configs.PERIODIC_2, "periodic3": configs.PERIODIC_3,
@@ -49,34 +62,120 @@ def time_reversal_symmetric(spec) -> bool:
     return bool(spec.v_time_reversal and spec.f_time_reversal)
 
 
-def cpu_baseline(system, target_s: float):
-    """Time the FP64 oracle's two contractions on a bounded sample of tau nodes (all q, all k)."""
-    import numpy as np
-    from oracle import gw as ogw
+def _host_threads() -> int:
     try:
         from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 0) for i in threadpool_info()] + [1])
+        return max([i.get("num_threads", 0) for i in threadpool_info()] + [1])
     except Exception:  # pragma: no cover
-        cores = os.cpu_count() or 1
-    sp = system.spec
-    Pt_stub = None
+        return os.cpu_count() or 1
+
+
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "host"
+
+
+def oracle_full_iteration(spec) -> float:
+    """Wall seconds of one whole FP64 oracle iteration (Sigma^inf, P~0, screening, Sigma~, mu search, Dyson,
+    energy) from the closed-form starting G, on the host cores."""
+    from oracle import gw as ogw
+    from synth import systems
+    s = systems.make_system(spec)
+    t0 = time.perf_counter()
+    ogw.iterate(s, ogw.State(s.G0, None, None, 0.0))
+    return time.perf_counter() - t0
+
+
+def oracle_contraction_sample(spec, V_slab, G0, target_s: float):
+    """The oracle's two contractions on a sample of the workload: P~0 of one momentum transfer q (all k) and
+    Sigma~ of one k summed over one q, each at a set of tau nodes sized to about target_s in total; returns the
+    measured seconds, the sample's algorithmic flops and the extrapolated seconds of both whole contractions.
+    V_slab(q) gives V[q] on the host (nk x naux x nao x nao)."""
+    import numpy as np
+    from oracle import gw as ogw
+    sp = spec
+    nk, ntau = sp.nk, sp.ntau
+    km = ogw.KMesh(sp.kmesh)
+    q = 1 if nk > 1 else 0
+    qn, k = km.sub(0, q), 0
+    slabs = {q: V_slab(q)}
+    if qn != q:
+        slabs[qn] = V_slab(qn)
+
+    class Slabs:
+        shape = (nk, nk, sp.naux, sp.nao, sp.nao)
+
+        def __getitem__(self, idx):
+            return slabs[idx[0]][idx[1]]
+
+    V = Slabs()
+    Pt = None
 
     def run(ts):
-        nonlocal Pt_stub
+        nonlocal Pt
         t0 = time.perf_counter()
-        P = ogw.polarization(system.V, system.G0, sp.kmesh, ts=ts)
-        ogw.selfenergy(system.V, system.G0, P, sp.kmesh, ts=ts)
+        P = ogw.polarization(V, G0, sp.kmesh, ts=ts, qs=[q])
+        Pt = np.zeros((nk,) + P.shape[1:], dtype=np.complex128)
+        Pt[q] = P[0]
+        # Sigma~^k for k = 0 summed over the transfer q reads V^{k,k-q} = V[-q][k] and V^{k-q,k} = V[q][k-q]
+        ogw.selfenergy(V, G0, Pt, sp.kmesh, ts=ts, ks=[k], qs=[q])
         return time.perf_counter() - t0
 
     one = run([0])
-    nt = int(max(1, min(sp.ntau, target_s / max(one, 1e-6))))
-    ts = list(np.linspace(0, sp.ntau - 1, nt).round().astype(int))
+    nt = int(max(1, min(ntau, target_s / max(one, 1e-6))))
+    ts = sorted(set(np.linspace(0, ntau - 1, nt).round().astype(int).tolist()))
     dt = run(ts)
-    flops = contraction_flops(sp.nk, sp.nao, sp.naux, len(ts), sp.nspin)
-    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"P~0 and Sigma~ contractions of the FP64 NumPy oracle at {len(ts)} of {sp.ntau} tau nodes "
-                      f"(all q, all k) of the same workload, {dt:.1f} s on {platform.processor() or 'host'}",
-            "seconds": dt}
+    # per (q, k, tau, spin): naux^2 nao^2 + 2 naux nao^3 complex MACs for each contraction; the sample did nk of
+    # them for P~0 (one q) and one for Sigma~ (one k, one q), at len(ts) nodes
+    unit = sp.nspin * (sp.naux ** 2 * sp.nao ** 2 + 2 * sp.naux * sp.nao ** 3) * 8.0
+    flops = unit * len(ts) * (nk + 1)
+    full_s = dt * (2.0 * nk * nk * ntau) / ((nk + 1) * len(ts))
+    return dt, flops, full_s, len(ts)
+
+
+def cpu_baseline(system, target_s: float, full_configs=True):
+    """The FP64 oracle on the host cores: the contraction rate on a bounded sample of this workload (the reported
+    value, TFLOP/s), its extrapolation to one iteration of this workload, and whole oracle iterations of the
+    molecule and 2x2x2 workloads (measured)."""
+    import numpy as np
+    from synth import configs
+    sp = system.spec
+    if getattr(system, "V_dev", None) is None:
+        def V_slab(q):
+            return system.V[q]
+    elif getattr(system, "v_half", False):
+        # half store: the canonical slabs in increasing q; the others from V^{k,k+q} = (V^{k+q,k})^dagger
+        from synth.systems import k_add_table, k_neg
+        canon = [q for q in range(sp.nk) if k_neg(sp.kmesh)[q] >= q]
+        add = k_add_table(sp.kmesh)
+
+        def V_slab(q):
+            if q in canon:
+                return system.V_dev[canon.index(q)].cpu().numpy()
+            qn = int(k_neg(sp.kmesh)[q])
+            part = system.V_dev[canon.index(qn)].cpu().numpy()
+            return np.stack([np.conj(np.swapaxes(part[int(add[k, q])], -1, -2)) for k in range(sp.nk)])
+    else:
+        def V_slab(q):
+            return system.V_dev[q].cpu().numpy()
+    dt, flops, full_s, nts = oracle_contraction_sample(sp, V_slab, system.G0, target_s)
+    out = {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": _host_threads(), "kind": "oracle",
+           "cpu_model": _cpu_model(),
+           "sample": f"P~0 of one momentum transfer (all k) and Sigma~ of one k over one transfer, FP64 NumPy oracle, "
+                     f"at {nts} of {sp.ntau} tau nodes of the {sp.name} workload: {dt:.1f} s",
+           "seconds": dt,
+           "s_per_iteration": {sp.name: {"seconds": round(full_s, 3), "how": "extrapolated from the sample (the two "
+                                         "contractions; the rest of an iteration is < 1 % of them at this size)"}}}
+    if full_configs:
+        for c in (configs.MOLECULE, configs.PERIODIC_2):
+            out["s_per_iteration"][c.name] = {"seconds": round(oracle_full_iteration(c), 3),
+                                              "how": "measured, one whole oracle iteration"}
+    return out
 
 
 def tune_plan(plan, step, max_iters=60):
@@ -223,6 +322,8 @@ def run_precision(system, prec, steps, warmup, chunk_bytes=0, tune=False, graph=
     plan = Plan(spec.kmesh, spec.nao, spec.naux, system.grid, nspin=spec.nspin, prec=prec, chunk_bytes=chunk_bytes)
     if time_reversal_symmetric(spec):
         plan.set_option("time_reversal", 1)
+    if getattr(system, "v_half", False):
+        plan.set_option("v_half", 1)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")  # noqa: E731
     V = system.V_dev
     H0, S = dev(system.H0), dev(system.S)
@@ -511,10 +612,12 @@ def main():
                     help="replay the Sigma evaluation from a HIP graph (runs on a non-default stream)")
     ap.add_argument("--precisions", default="fp64,fp32,bf16x3",
                     help="comma list; fp64 is always run first as the accuracy reference")
-    ap.add_argument("--cpu-baseline-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-baseline-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reference", action="store_true",
                     help="skip the FP64 reference run (profiling runs of one precision; no accuracy fields)")
+    ap.add_argument("--v-half", action="store_true",
+                    help="pass V as the Hermitian half store (the canonical-q slabs only; GREEN_OPT_V_HALF)")
     ap.add_argument("--chunk-mib", type=int, default=0,
                     help="workspace bound for the contraction intermediates (0: library default)")
     ap.add_argument("--kpath", type=int, default=0,
@@ -562,16 +665,23 @@ def main():
     spec = workloads()[args.workload]
     system = systems.make_system(spec, with_V=False)
     t0 = time.perf_counter()
-    system.V_dev = dgen.make_V(spec, device="cuda:0")  # generated in HBM (same draws as the host generator)
+    system.v_half = bool(args.v_half)
+    canon = [q for q in range(spec.nk) if systems.k_neg(spec.kmesh)[q] >= q]
+    # generated in HBM (same draws as the host generator)
+    system.V_dev = dgen.make_V(spec, device="cuda:0", qs=canon if args.v_half else None)
     torch.cuda.synchronize()
     print(f"[bench] {spec.name}: V ({system.V_dev.numel() * 16 / 1e9:.1f} GB) generated on the device in "
           f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     asked = [p for p in args.precisions.split(",") if p]
     precs = asked if args.no_reference else ["fp64"] + [p for p in asked if p != "fp64"]
     side = torch.cuda.Stream() if args.graph else torch.cuda.current_stream()
+    # the headline precision (the last one asked for, split BF16 by default) runs the requested steps; the
+    # reference precisions before it at most 2 timed steps after at most 1 warm-up
+    head_asked = asked[-1]
     with torch.cuda.stream(side):
-        res = {p: run_precision(system, p, args.steps, args.warmup, args.chunk_mib << 20, tune=args.tune,
-                                graph=args.graph, accuracy_point=not args.no_reference,
+        res = {p: run_precision(system, p, args.steps if p == head_asked else min(args.steps, 2),
+                                args.warmup if p == head_asked else min(args.warmup, 1), args.chunk_mib << 20,
+                                tune=args.tune, graph=args.graph, accuracy_point=not args.no_reference,
                                 kpath_points=args.kpath) for p in precs}
     if args.save_sample:
         np.savez(args.save_sample, **{f"{p}_{k}": np.asarray(v) for p, r in res.items() for k, v in r["first"].items()},
@@ -614,7 +724,9 @@ def main():
         "config": {"workload": spec.name, "nk": spec.nk, "kmesh": list(spec.kmesh), "nao": spec.nao,
                    "naux": spec.naux, "ntau": spec.ntau, "nspin": spec.nspin, "beta": spec.beta,
                    "precision": head, "tuned": bool(args.tune), "graph": bool(args.graph),
-                   "time_reversal": time_reversal_symmetric(spec)},
+                   "time_reversal": time_reversal_symmetric(spec), "v_half_store": bool(args.v_half)},
+        "flop_basis": "algorithmic: both contractions over every q, k and tau (4M counting)",
+        "executed_tflops": round(h["sigma_eval_tflops"] * executed_fraction(spec), 4),
         "s_per_iteration": round(h["s_per_iteration"], 6),
         "fp64_s_per_iteration": round(fp64_spi, 6) if fp64_spi else None,
         "speedup_vs_fp64": round(fp64_spi / h["s_per_iteration"], 3) if fp64_spi else None,
@@ -641,8 +753,8 @@ def main():
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
-        system.V = system.V_dev.cpu().numpy()
-        out["cpu_baseline"] = cpu_baseline(system, args.cpu_baseline_seconds)
+        out["cpu_baseline"] = cpu_baseline(system, args.cpu_baseline_seconds,
+                                           full_configs=args.workload in ("periodic3", "periodic2", "molecule"))
     if args.tr_leg or args.gf2:
         del res, h
         system.V_dev = None

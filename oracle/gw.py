@@ -199,23 +199,25 @@ def from_bosonic(Pw: np.ndarray, TB_w2t: np.ndarray) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------- O7
-def selfenergy(V: np.ndarray, G: np.ndarray, Pt: np.ndarray, kmesh, ts=None, ks=None) -> np.ndarray:
+def selfenergy(V: np.ndarray, G: np.ndarray, Pt: np.ndarray, kmesh, ts=None, ks=None, qs=None) -> np.ndarray:
     """O7, Eqs. sigma_gw and tilde_W_DF2 (W~ evaluated on tau through P~(tau)):
 
     Sigma~^k_{s,ij}(tau) = -(1/Nk) sum_q sum_ab G^{k-q}_{s,ab}(tau)
                             sum_{QQ'} V^{k,k-q}_{ia}(Q) P~^q_{QQ'}(tau) V^{k-q,k}_{bj}(Q')
     evaluated as X(Q') = sum_Q P~_{QQ'} V^{k,k-q}(Q), then sum_{Q'} X(Q') G^{k-q} V^{k-q,k}(Q').
 
-    Pt[q][t'] holds the nodes in ts (or all nodes).  Returns Sigma[s][t][k][i][j] over ts x ks.
+    Pt[q][t'] holds the nodes in ts (or all nodes).  qs: optional subset of the momentum transfers summed over (a
+    selection only; the default is the whole sum).  Returns Sigma[s][t][k][i][j] over ts x ks.
     """
     km = KMesh(kmesh)
     ns, ntau, nk, nao, _ = G.shape
     naux = V.shape[2]
     ts = list(range(ntau)) if ts is None else list(ts)
     ks = list(range(nk)) if ks is None else list(ks)
+    qs = list(range(nk)) if qs is None else list(qs)
     out = np.zeros((ns, len(ts), len(ks), nao, nao), dtype=np.complex128)
     for ik, k in enumerate(ks):
-        for q in range(nk):
+        for q in qs:
             kmq = km.sub(k, q)
             A = V_pair(V, km, k, kmq)  # V^{k,k-q}(Q)  [Q][i][a]
             B = V_pair(V, km, kmq, k)  # V^{k-q,k}(Q') [Q'][b][j]
