@@ -1509,6 +1509,7 @@ int count_ops(green_plan* p) {
 struct BatchGroup {
   size_t first, count;  // descriptors [first, first + count)
   size_t start_off;     // tile offsets [start_off, start_off + count]
+  bool solo = false;    // one contraction that fills the GPU on its own: its own (non-persistent) launch
 };
 
 struct green_batch {
@@ -2306,6 +2307,25 @@ int green_batch_create(int nsys, green_plan* const* plans, const green_system* s
       const auto& ops = bt->ops[i];
       if (r < ops.size() && ops[r].is_gemm && ops[r].g.M > 0 && ops[r].g.N > 0) pending.push_back(i);
     }
+    // a contraction whose tiles fill every CU at least twice runs as its own launch (the direct kernel keeps its
+    // full rate); the others of the round share persistent launches per kernel variant
+    {
+      std::vector<int> rest;
+      for (int i : pending) {
+        const ZGemm& g = bt->ops[i][r].g;
+        const int per_cu = green::zgemm_wgs_per_cu(g);
+        if (green::zgemm_blocks(g) >= 2 * 256 * (int64_t)(per_cu ? per_cu : 4)) {
+          BatchGroup gr{bt->descs.size(), 1, starts.size(), true};
+          bt->descs.push_back(g);
+          starts.push_back(0);
+          starts.push_back(green::zgemm_blocks(g));
+          bt->groups[r].push_back(gr);
+        } else {
+          rest.push_back(i);
+        }
+      }
+      pending.swap(rest);
+    }
     while (!pending.empty()) {
       const green::Variant v = green::zgemm_variant(bt->ops[pending[0]][r].g);
       BatchGroup gr{bt->descs.size(), 0, starts.size()};
@@ -2362,9 +2382,13 @@ int green_batch_iterate(green_batch* bt, green_system* sys, green_report* reps, 
   // replay round by round: one persistent launch per kernel variant, auxiliary launches per system
   auto replay = [&]() -> int {
     for (size_t r = 0; r < bt->groups.size(); ++r) {
-      for (const BatchGroup& gr : bt->groups[r])
-        HIP_TRY(green::zgemm_group(bt->descs.data() + gr.first, (int)gr.count, bt->ddesc + gr.first,
-                                   bt->dstart + gr.start_off, s));
+      for (const BatchGroup& gr : bt->groups[r]) {
+        if (gr.solo)
+          HIP_TRY(green::zgemm(bt->descs[gr.first], s));
+        else
+          HIP_TRY(green::zgemm_group(bt->descs.data() + gr.first, (int)gr.count, bt->ddesc + gr.first,
+                                     bt->dstart + gr.start_off, s));
+      }
       for (int i = 0; i < nsys; ++i)
         if (r < bt->ops[i].size() && !bt->ops[i][r].is_gemm && !dry) HIP_TRY(bt->ops[i][r].aux(s));
     }

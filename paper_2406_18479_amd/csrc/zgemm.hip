@@ -1690,7 +1690,7 @@ __device__ __forceinline__ void group_loop(const GroupArgs& a, F&& body) {
   }
 }
 template <int WM, int WN>
-__global__ __launch_bounds__(256) void zgemm_f64_group(const GroupArgs a) {
+__global__ __launch_bounds__(256, 2) void zgemm_f64_group(const GroupArgs a) {
   group_loop(a, [](const ZGemm& g, int64_t b, int64_t) { f64_body<WM, WN>(g, b); });
 }
 template <int MODE, int WM, int WN>
