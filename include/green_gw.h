@@ -288,8 +288,9 @@ int green_gw_iterate_diis(green_plan* plan, const void* V, const void* H0, const
  *                   (the sum of Eq. tilde_P0_tau) before any autotuning: 1 = 192 x 96, 2 = 192 x 64,
  *                   3 = 320 x 64, 4 = 448 x 64 rows x columns of P~0(q, tau), register-staged; 5 = 320 x 64,
  *                   6 = 192 x 128 fed by LDS DMA (even nao; else as 3 and 1); 7 = 320 x 64, 8 = 128 x 128,
- *                   9 = 256 x 64 fed by LDS DMA with the next K stage's operands read ahead (K blocks of a
- *                   multiple of 16; else as 3, 1 and 2).  The plan starts with the tile that pads naux x naux
+ *                   9 = 256 x 64 fed by LDS DMA with the next K stage's operands read ahead, 10 = 128 x 64 and
+ *                   11 = 64 x 128 the same with 4 waves, two workgroups per CU (K blocks of a multiple of 16;
+ *                   else 7 and 10 as 3, 8 and 11 as 1, 9 as 2).  The plan starts with the tile that pads naux x naux
  *                   least (192 x 96 counted at 90% of its area), 320 x 64 on the LDS-DMA kernel.
  *   GREEN_OPT_SIGMA_TILE  split-BF16 plans: tile of the first Sigma~ contraction, P~(tau)^T V over the auxiliary
  *                   index (values as GREEN_OPT_P0_TILE; default 6).
@@ -338,6 +339,35 @@ int green_gw_iterate_diis(green_plan* plan, const void* V, const void* H0, const
 #define GREEN_OPT_V_HALF 8
 #define GREEN_OPT_SIGMA_TILE 9
 int green_plan_set_option(green_plan* plan, int option, int value);
+
+/* Point-group symmetry of the k mesh (symmetry among the method's features, Sec. 3: the space-group operations
+ * of a crystal reduce the momenta to an irreducible set).  Here the operations act on momenta alone: the orbital
+ * and auxiliary bases transform trivially, so the caller's system must satisfy H0(R k) = H0(k), S(R k) = S(k),
+ * V^{R k1, R k2}(Q) = V^{k1,k2}(Q) and G^{R k}_s(tau) = G^k_s(tau) for every operation R.  Then P~0^{R q} =
+ * P~0^q (the sum over k of Eq. tilde_P0_tau re-indexed by R), the screening keeps it, and Sigma~^{R k} = Sigma~^k
+ * (the sum over q of Eq. sigma_gw re-indexed).  With the +-q identity P~0^{-q}(tau) = P~0^q(beta - tau)^T, the
+ * polarization and the screening are contracted for one orbit of each pair {O, -O} of momentum orbits (at its
+ * smallest flat index; the first half of the tau nodes only where -q lies in the orbit of q), the self-energy for
+ * one momentum per orbit (with GREEN_OPT_TIME_REVERSAL one orbit of each pair {O, -O}), each over every k or q;
+ * the other momenta are written as copies (transposed, tau-reversed copies for -O; complex conjugates under time
+ * reversal).  The Hartree-Fock terms, the Dyson step and the energies still run over every k.  The same in the
+ * iterations and in green_gf2_selfenergy.
+ *   rot     host, nops x 9 int32: operation r is the integer matrix R_r (row-major) acting on the integer mesh
+ *           coordinates of a momentum, k = (i0, i1, i2) -> R_r k taken modulo the mesh (flat index (i0 m1 + i1) m2
+ *           + i2); the identity need not be listed, and the orbits are those of the group the operations generate.
+ *   nops    0 (rot may be NULL): no point group (the default).  At most GREEN_MAX_KPOINT_OPS.
+ *   counts  optional host int32[2]: the number of contracted transfers (polarization, screening) and of
+ *           contracted momenta (self-energy), e.g. 4 and 4 for the full cubic group on a 3x3x3 mesh.
+ * Every call that reads G and V first checks on the device that G of every momentum equals that of the
+ * contracted momentum it is filled from (or its conjugate under time reversal) and that V^{R k1, R k2}(Q) =
+ * V^{k1,k2}(Q) for every operation on three auxiliary indices of every pair (full store), to 1e-8 of the largest
+ * element; a violation is reported as GREEN_EINVAL by the next synchronising call.  The self-energy step alone
+ * (green_gw_selfenergy) also needs P~^{R q} = P~^q of its input, which is not checked.
+ * GREEN_EINVAL (plan unchanged) when an operation does not map the mesh onto itself (R_ij m_j must be a
+ * multiple of m_i, and k -> R k one to one).  The workspace grows by the operations' tables the first time (query
+ * green_workspace_bytes after the call). */
+#define GREEN_MAX_KPOINT_OPS 192
+int green_plan_set_kpoint_symmetry(green_plan* plan, const int32_t* rot, int nops, int32_t* counts);
 
 /* Text table of the autotuner's decisions into buf (host, len bytes, NUL-terminated; GREEN_ENOMEM when
  * truncated): per contraction shape a line with the chosen kernel and, once tuned, a line with every

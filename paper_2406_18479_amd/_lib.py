@@ -83,9 +83,11 @@ EXPORTS = ["green_plan_create", "green_plan_destroy", "green_workspace_bytes", "
            "green_plan_set_option", "green_plan_tuning_report", "green_batch_workspace_bytes",
            "green_gw_iterate_batched", "green_batch_create", "green_batch_iterate", "green_batch_destroy",
            "green_diis_history_bytes", "green_gw_iterate_diis", "green_kpath_interpolate",
-           "green_gf2_selfenergy", "green_dyson_noalloc", "green_check_status", "green_strerror"]
+           "green_gf2_selfenergy", "green_dyson_noalloc", "green_check_status", "green_plan_set_kpoint_symmetry",
+           "green_strerror"]
 
 NOALLOC_MAX_BYTES = 64 << 20  # GREEN_NOALLOC_MAX_BYTES
+MAX_KPOINT_OPS = 192  # GREEN_MAX_KPOINT_OPS
 
 
 def _load():
@@ -126,6 +128,9 @@ def _load():
     lib.green_gw_iterate.restype = i32
     lib.green_plan_set_option.argtypes = [vp, i32, i32]
     lib.green_plan_set_option.restype = i32
+    lib.green_plan_set_kpoint_symmetry.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), i32,
+                                                   ctypes.POINTER(ctypes.c_int32)]
+    lib.green_plan_set_kpoint_symmetry.restype = i32
     lib.green_plan_tuning_report.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
     lib.green_plan_tuning_report.restype = i32
     lib.green_batch_workspace_bytes.argtypes = [i32, ctypes.POINTER(vp)]

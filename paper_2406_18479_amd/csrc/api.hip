@@ -72,19 +72,30 @@ struct green_plan {
   std::vector<double2> TF_t2w, TF_w2t, TB_t2w, TB_w2t, Emass;
   std::vector<int32_t> kadd, ksub, kneg;  // [q][k]: k+q, k-q; [q]: -q
   std::vector<int32_t> qcan;              // momenta q with -q >= q (one of each +-q pair)
-  // time reversal: the self-energy is contracted for the momenta k with -k >= k (kcan) only, the others are
-  // the complex conjugates of their partners; ksubc[q][kk] = kcan[kk] - q
+  // time reversal: the self-energy of -k is the complex conjugate of that of k
   bool trev = false;
-  std::vector<int32_t> kcan, ksubc;
+  // point group acting on the k mesh (green_plan_set_kpoint_symmetry): krot[r][k] = R_r k; korb[k] = the
+  // smallest momentum of the orbit of k (k itself without the group)
+  bool ksym = false;
+  int nrot = 0;
+  std::vector<int32_t> krot, korb;
+  // contracted momentum transfers qc of P~0 and the screening (one orbit of each pair {O, -O}, at its smallest
+  // momentum; without the group, the q with -q >= q); for the others P~^q is the copy (qrel 1) or the transposed,
+  // tau-reversed copy (qrel 2) of P~^{qsrc[q]}
+  std::vector<int32_t> qc, qsrc, qrel;
+  // contracted momenta kc of the self-energy (one per orbit, and with time reversal one orbit of each pair
+  // {O, -O}; all k when neither applies); kfill[k] = k (contracted), the source momentum (copy) or the source + nk
+  // (complex conjugate); ksubc[q][kk] = kc[kk] - q
+  std::vector<int32_t> kc, kfill, ksubc;
   // Hermitian half store of V: the caller passes the slabs of the canonical q only (in qcan order); qslot[q] is
   // the slab of q there, -1 for the others (built from their partners on use)
   bool vhalf = false;
   std::vector<int32_t> qslot;
   // workspace regions
-  Region r_TF_t2w, r_TF_w2t, r_TB_t2w, r_TB_w2t, r_Emass, r_wf, r_kadd, r_ksub, r_qcan, r_status, r_scal, r_partial;
+  Region r_TF_t2w, r_TF_w2t, r_TB_t2w, r_TB_w2t, r_Emass, r_wf, r_kadd, r_ksub, r_status, r_scal, r_partial;
   Region r_P, r_Pw, r_T1, r_T2, r_gam, r_gamT, r_D, r_Sinfn, r_Sign, r_Sw, r_A, r_tr, r_split, r_Vx, r_Ptx, r_Gx, r_GTx;
   Region r_g2tab, r_Fp, r_Fm, r_X2, r_Z2;  // GF2 (empty until GREEN_OPT_GF2 is set)
-  Region r_kneg, r_kcan, r_ksubc;
+  Region r_kneg, r_kc, r_ksubc, r_qc, r_kfill, r_krot;
   Region r_Vh;  // one partner slab of the half store (empty until GREEN_OPT_V_HALF is set)
   size_t ws_bytes = 0;
   void* bound_ws = nullptr;
@@ -201,6 +212,12 @@ int ensure_bound(green_plan* p, void* ws, hipStream_t s) {
   auto up = [&](const Region& r, const void* src) {
     return hipMemcpyAsync(static_cast<char*>(ws) + r.off, src, r.bytes, hipMemcpyHostToDevice, s);
   };
+  // index tables that may fill only part of their region
+  auto upv = [&](const Region& r, const std::vector<int32_t>& v) {
+    const size_t bytes = std::min(v.size() * 4, r.bytes);
+    if (bytes == 0) return hipSuccess;
+    return hipMemcpyAsync(static_cast<char*>(ws) + r.off, v.data(), bytes, hipMemcpyHostToDevice, s);
+  };
   HIP_TRY(up(p->r_TF_t2w, p->TF_t2w.data()));
   HIP_TRY(up(p->r_TF_w2t, p->TF_w2t.data()));
   HIP_TRY(up(p->r_TB_t2w, p->TB_t2w.data()));
@@ -209,11 +226,13 @@ int ensure_bound(green_plan* p, void* ws, hipStream_t s) {
   HIP_TRY(up(p->r_wf, p->wf.data()));
   HIP_TRY(up(p->r_kadd, p->kadd.data()));
   HIP_TRY(up(p->r_ksub, p->ksub.data()));
-  HIP_TRY(up(p->r_qcan, p->qcan.data()));
   if (p->r_g2tab.bytes) HIP_TRY(up(p->r_g2tab, p->g2tab.data()));
   HIP_TRY(up(p->r_kneg, p->kneg.data()));
-  HIP_TRY(up(p->r_kcan, p->kcan.data()));
-  HIP_TRY(up(p->r_ksubc, p->ksubc.data()));
+  HIP_TRY(upv(p->r_kc, p->kc));
+  HIP_TRY(upv(p->r_ksubc, p->ksubc));
+  HIP_TRY(upv(p->r_qc, p->qc));
+  HIP_TRY(upv(p->r_kfill, p->kfill));
+  HIP_TRY(upv(p->r_krot, p->krot));
   HIP_TRY(hipMemsetAsync(static_cast<char*>(ws) + p->r_status.off, 0, p->r_status.bytes, s));
   HIP_TRY(hipStreamSynchronize(s));
   p->bound_ws = ws;
@@ -527,6 +546,61 @@ Extents extents(const green_plan* p) {
   return e;
 }
 
+// GF2 exchange tables of the contracted momenta kc (after the full tables: the four rows of every triple whose
+// first momentum is contracted, in kc order).  The region holds room for every k.
+void build_gf2_tail(green_plan* p) {
+  if (p->g2tab.empty()) return;
+  const int nk = p->nk;
+  const int64_t ntrip = (int64_t)nk * nk * nk, nk2 = (int64_t)nk * nk;
+  const int nkc = (int)p->kc.size();
+  const int64_t nh = (int64_t)nkc * nk2;
+  for (int w = 0; w < 4; ++w)
+    for (int kk = 0; kk < nkc; ++kk)
+      for (int64_t pr = 0; pr < nk2; ++pr)
+        p->g2tab[4 * ntrip + w * nh + kk * nk2 + pr] = p->g2tab[w * ntrip + (int64_t)p->kc[kk] * nk2 + pr];
+}
+
+// Contracted sets and fill rules from the point group (if any) and time reversal.
+//   Transfers: P~0^{R q} = P~0^q for R in the group (the sum over k is re-indexed by R), and
+//   P~0^{-q}(tau) = P~0^q(beta - tau)^T always, so of each pair of orbits {O, -O} one is contracted, at its
+//   smallest momentum c; the rest of O are copies of P~^c, the momenta of -O transposed, tau-reversed copies.
+//   Momenta of the self-energy: Sigma~^{R k} = Sigma~^k; with time reversal Sigma~^{-k} = conj Sigma~^k as well.
+void build_contracted_sets(green_plan* p) {
+  const int nk = p->nk;
+  std::vector<int32_t> orb(nk);
+  for (int k = 0; k < nk; ++k) orb[k] = p->ksym ? p->korb[k] : k;
+  p->qc.clear();
+  p->qsrc.assign(nk, 0);
+  p->qrel.assign(nk, 0);
+  for (int q = 0; q < nk; ++q) {
+    const int c = std::min(orb[q], orb[p->kneg[orb[q]]]);
+    p->qsrc[q] = c;
+    if (q == c) {
+      p->qc.push_back(q);
+      p->qrel[q] = 0;
+    } else {
+      p->qrel[q] = orb[q] == c ? 1 : 2;
+    }
+  }
+  p->kc.clear();
+  p->kfill.assign(nk, 0);
+  for (int k = 0; k < nk; ++k) {
+    const int c = p->trev ? std::min(orb[k], orb[p->kneg[orb[k]]]) : orb[k];
+    if (k == c) {
+      p->kc.push_back(k);
+      p->kfill[k] = k;
+    } else {
+      p->kfill[k] = orb[k] == c ? c : c + nk;
+    }
+  }
+  const int nkc = (int)p->kc.size();
+  p->ksubc.resize((size_t)nk * nkc);
+  for (int q = 0; q < nk; ++q)
+    for (int kk = 0; kk < nkc; ++kk) p->ksubc[(size_t)q * nkc + kk] = p->ksub[(size_t)q * nk + p->kc[kk]];
+  build_gf2_tail(p);
+  p->bound_ws = nullptr;  // the tables are uploaded on the next call
+}
+
 // V slab of momentum transfer q, V[q][k] = V^{k,k+q}: the caller's array, or with the Hermitian half store the
 // slot of a canonical q, or for the others the partner V^{k,k+q} = (V^{k+q,k})^dagger = (V[-q][k+q])^dagger
 // written into the workspace (one slab at a time: of q and -q at most one is not canonical).
@@ -547,6 +621,25 @@ int v_slab(green_plan* p, const void* V, int q, void* ws, hipStream_t s, const v
   GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::launch_herm_partner(in, out, nk, naux, nao, kmap, st_); }));
   *ptr = out;
   *sp = span_ws(ws, p->r_Vh);
+  return GREEN_OK;
+}
+
+// P[q][t] of the transfers that are not contracted, from the contracted ones: copies (qrel 1) or transposed,
+// tau-reversed copies P[q][t] = P[qsrc][ntau - 1 - t]^T (qrel 2).
+int fill_transfers(green_plan* p, double2* P, hipStream_t s) {
+  const int nk = p->nk, naux = p->d.naux, ntau = p->d.ntau;
+  const int64_t slab = (int64_t)ntau * naux * naux;
+  for (int q = 0; q < nk; ++q) {
+    if (p->qrel[q] == 0) continue;
+    const double2* src = P + (int64_t)p->qsrc[q] * slab;
+    double2* dst = P + (int64_t)q * slab;
+    if (p->qrel[q] == 1)
+      GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::launch_copy(src, dst, slab, st_); }));
+    else
+      GREEN_TRY(aux(s, [=](hipStream_t st_) {
+        return green::launch_transpose_reverse(src, dst, naux, ntau, 0, ntau, st_);
+      }));
+  }
   return GREEN_OK;
 }
 
@@ -582,14 +675,18 @@ int run_polarization(green_plan* p, const void* V, const void* G, void* P0, void
     sGs = span_ws(ws, p->r_Gx);
   }
   // P~0^{-q}(tau) = P~0^q(beta - tau)^T exactly (substitute k -> k + q and cycle the trace), and the grid is
-  // symmetric (tau_{ntau-1-t} = beta - tau_t): only q <= -q are contracted, the partner slab is a transposed,
-  // tau-reversed copy, and for q = -q only the first half of the tau nodes is contracted.
+  // symmetric (tau_{ntau-1-t} = beta - tau_t): only the transfers qc are contracted (q <= -q; with a point group
+  // one orbit of each pair {O, -O}), the others are filled from them at the end; where -q lies in the orbit of q
+  // (q = -q without a group) only the first half of the tau nodes is contracted, the second half is the
+  // transposed, tau-reversed first half.
   // With time reversal also P~0^{-q}(tau) = conj P~0^q(tau), so P~0^q(beta - tau) = P~0^q(tau)^H: every q is
   // contracted on the first half of the tau nodes only, the second half is the conjugate transpose.
-  for (int q = 0; q < nk; ++q) {
+  const int nqc = (int)p->qc.size();
+  for (int iq = 0; iq < nqc; ++iq) {
+    const int q = p->qc[iq];
     const int qn = p->kneg[q];
-    if (qn < q) continue;
-    const int t_end = (qn == q || p->trev) ? ntau / 2 : ntau;
+    const bool self = p->qsrc[qn] == q && p->qrel[qn] != 2;  // -q in the orbit of q (or q itself)
+    const int t_end = (self || p->trev) ? ntau / 2 : ntau;
     const void *Vq = nullptr, *Vqn = nullptr;
     green::Span sVs{}, sVn{};
     GREEN_TRY(v_slab(p, V, q, ws, s, &Vq, &sVs));
@@ -630,23 +727,16 @@ int run_polarization(green_plan* p, const void* V, const void* G, void* P0, void
                        cplx(sp == 0 ? 0.0 : 1.0), s, p->prec, green::kC64, bf ? p->big_p0 : 0));
       }
     }
-    if (p->trev && qn != q) {
+    if (t_end < ntau) {
       double2* Pq = Pp + (int64_t)q * ntau * naux * naux;
+      const bool cj = !self;  // time reversal
       GREEN_TRY(aux(s, [=](hipStream_t st_) {
-        return green::launch_transpose_reverse(Pq, Pq, naux, ntau, ntau / 2, ntau, st_, true);
+        return green::launch_transpose_reverse(Pq, Pq, naux, ntau, ntau / 2, ntau, st_, cj);
       }));
     }
-    {
-      const double2* src = Pp + (int64_t)q * ntau * naux * naux;
-      double2* dst = Pp + (int64_t)qn * ntau * naux * naux;
-      const int lo = qn == q ? ntau / 2 : 0;
-      GREEN_TRY(aux(s, [=](hipStream_t st_) {
-        return green::launch_transpose_reverse(src, dst, naux, ntau, lo, ntau, st_);
-      }));
-    }
-    GREEN_TRY(progress("polarization", q, nk, s));
+    GREEN_TRY(progress("polarization", iq, nqc, s));
   }
-  return GREEN_OK;
+  return fill_transfers(p, Pp, s);
 }
 
 // ---------------------------------------------------------------- screening
@@ -658,11 +748,11 @@ int run_screen(green_plan* p, const void* P0, void* Pt, void* ws, hipStream_t s)
   double2* Pw = at<double2>(ws, p->r_Pw);
   const green::Span sPw = span_ws(ws, p->r_Pw);
   // The screening commutes with P(tau) -> P(beta - tau)^T (the bosonic transforms map it to P(i W) -> P(-i W)^T
-  // on the symmetric grids, and [I - P]^{-1} P commutes with the transpose), so P~^{-q}(tau) = P~^q(beta - tau)^T:
-  // only one q of each +-q pair is screened, its partner is a transposed, tau-reversed copy.
-  const int nc = (int)p->qcan.size();
-  const int32_t* qc = at<int32_t>(ws, p->r_qcan);
-  const int32_t* hqc = p->qcan.data();
+  // on the symmetric grids, and [I - P]^{-1} P commutes with the transpose), so P~^{-q}(tau) = P~^q(beta - tau)^T,
+  // and with copies: only the contracted transfers qc are screened, the others are filled from them as P~0 was.
+  const int nc = (int)p->qc.size();
+  const int32_t* qc = at<int32_t>(ws, p->r_qc);
+  const int32_t* hqc = p->qc.data();
   // P0(i W_m) = sum_t TB_t2w[m][t] P0(tau_t)
   GREEN_TRY(gemm(green::Site::Transform, "screen.t2w", op(at<double2>(ws, p->r_TB_t2w), flat(ntau), flat(1), bnone()),
                  span_ws(ws, p->r_TB_t2w), op(P0, flat(nP), flat(1), btwo(nc, (int64_t)ntau * nP, qc, 0, hqc)),
@@ -697,15 +787,7 @@ int run_screen(green_plan* p, const void* P0, void* Pt, void* ws, hipStream_t s)
                  span_ws(ws, p->r_TB_w2t), op(Pw, flat(nP), flat(1), bflat((int64_t)nwb * nP)), sPw, Pt,
                  span(Pt, ex.P), flat(nP), flat(1), btwo(nc, (int64_t)ntau * nP, qc, 0, hqc), ntau, (int)nP, nwb, nc,
                  cplx(1), cplx(0), s));
-  double2* Ptp = static_cast<double2*>(Pt);
-  for (int i = 0; i < nc; ++i) {
-    const int q = hqc[i], qn = p->kneg[q];
-    if (qn == q) continue;
-    const double2* src = Ptp + (int64_t)q * ntau * nP;
-    double2* dst = Ptp + (int64_t)qn * ntau * nP;
-    GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::launch_transpose_reverse(src, dst, naux, ntau, 0, ntau, st_); }));
-  }
-  return GREEN_OK;
+  return fill_transfers(p, static_cast<double2*>(Pt), s);
 }
 
 // ---------------------------------------------------------------- self-energy
@@ -717,12 +799,13 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
   const Extents ex = extents(p);
   const int32_t* ksub = at<int32_t>(ws, p->r_ksub);
   const int32_t* hsub = p->ksub.data();
-  // With time reversal only the momenta kcan[kk] (-k >= k) are contracted: X, Y and the partial sums hold
-  // kk = 0 .. nkx - 1, Sigma~ of the others is the complex conjugate of its partner's (filled at the end).
-  const bool tr = p->trev;
-  const int nkx = tr ? (int)p->kcan.size() : nk;
-  const int32_t* kcan = at<int32_t>(ws, p->r_kcan);
-  const int32_t* hcan = p->kcan.data();
+  // With time reversal or a point group only the momenta kc[kk] are contracted: X, Y and the partial sums hold
+  // kk = 0 .. nkx - 1, Sigma~ of the others is a copy or the complex conjugate of a contracted one's (filled at
+  // the end).
+  const bool tr = p->trev || p->ksym;
+  const int nkx = tr ? (int)p->kc.size() : nk;
+  const int32_t* kcan = at<int32_t>(ws, p->r_kc);
+  const int32_t* hcan = p->kc.data();
   // k - q of each contracted momentum, and the Sigma~ block each one writes
   auto ktab = [&](int q) { return tr ? at<int32_t>(ws, p->r_ksubc) + (size_t)q * nkx : ksub + (size_t)q * nk; };
   auto hktab = [&](int q) { return tr ? p->ksubc.data() + (size_t)q * nkx : hsub + (size_t)q * nk; };
@@ -887,10 +970,8 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
     GREEN_TRY(progress("self-energy", q, nk, s));
   }
   if (tr) {
-    const int32_t* kneg = at<int32_t>(ws, p->r_kneg);
-    GREEN_TRY(aux(s, [=](hipStream_t st_) {
-      return green::launch_conj_partner(Sp, (int64_t)ns * ntau, nk, nG, kneg, st_);
-    }));
+    const int32_t* kfill = at<int32_t>(ws, p->r_kfill);
+    GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::launch_fill_k(Sp, (int64_t)ns * ntau, nk, nG, kfill, st_); }));
   }
   return GREEN_OK;
 }
@@ -914,15 +995,15 @@ int run_gf2_exchange(green_plan* p, const void* V, const void* G, void* Sig, voi
   const int32_t* kadd = at<int32_t>(ws, p->r_kadd);
   const int32_t* hadd = p->kadd.data();
   const int64_t ntrip = (int64_t)nk2 * nk;
-  // time reversal: only the triples of the momenta k with -k >= k (second half of the tables), the partners'
-  // Sigma~ conjugated at the end
-  const bool tr = p->trev;
-  const int nkx = tr ? (int)p->kcan.size() : nk;
+  // time reversal or a point group: only the triples of the contracted momenta kc (after the full tables), the
+  // others' Sigma~ copied or conjugated at the end
+  const bool tr = p->trev || p->ksym;
+  const int nkx = tr ? (int)p->kc.size() : nk;
   const int64_t ntab = (int64_t)nkx * nk2;
   const int32_t* tab = at<int32_t>(ws, p->r_g2tab) + (tr ? 4 * ntrip : 0);
   const int32_t* htab = p->g2tab.data() + (tr ? 4 * ntrip : 0);
-  const int32_t* kcan = at<int32_t>(ws, p->r_kcan);
-  const int32_t* hcan = p->kcan.data();
+  const int32_t* kcan = at<int32_t>(ws, p->r_kc);
+  const int32_t* hcan = p->kc.data();
   // Split-BF16 plans keep the pair products, V and the four-index products in split BF16, the operand of the
   // auxiliary sums that runs along the rows transposed (Q contiguous), so those sums run on the large-tile
   // kernel: F (Q-major) and F^T ([pair][(i,q)][Q]) share the first region, F'^T and the rounded V the second.
@@ -999,9 +1080,9 @@ int run_gf2_exchange(green_plan* p, const void* V, const void* G, void* Sig, voi
       }
     }
   if (tr) {
-    const int32_t* kneg = at<int32_t>(ws, p->r_kneg);
+    const int32_t* kfill = at<int32_t>(ws, p->r_kfill);
     GREEN_TRY(aux(s, [=](hipStream_t st_) {
-      return green::launch_conj_partner(static_cast<double2*>(Sig), (int64_t)ns * ntau, nk, nG, kneg, st_);
+      return green::launch_fill_k(static_cast<double2*>(Sig), (int64_t)ns * ntau, nk, nG, kfill, st_);
     }));
   }
   return GREEN_OK;
@@ -1026,14 +1107,9 @@ void enable_gf2(green_plan* p) {
         p->g2tab[2 * ntrip + b] = blk(k3, k2);
         p->g2tab[3 * ntrip + b] = blk(k2, k);
       }
-  // the same rows for the momenta k with -k >= k only (time reversal), after the full tables
-  const int nkh = (int)p->kcan.size();
-  const int64_t nh = (int64_t)nkh * nk * nk;
-  p->g2tab.resize(4 * ntrip + 4 * nh);
-  for (int w = 0; w < 4; ++w)
-    for (int kk = 0; kk < nkh; ++kk)
-      for (int64_t pr = 0; pr < (int64_t)nk * nk; ++pr)
-        p->g2tab[4 * ntrip + w * nh + kk * (int64_t)nk * nk + pr] = p->g2tab[w * ntrip + (int64_t)p->kcan[kk] * nk * nk + pr];
+  // the same rows for the contracted momenta only, after the full tables (room for every k)
+  p->g2tab.resize(8 * ntrip);
+  build_gf2_tail(p);
   // four-index chunks: half the contraction budget each, between one triple and all of them
   const int64_t per = nG2 * 16;
   const int64_t want = std::max<int64_t>(1, (int64_t)(p->chunk_bytes / 2) / per);
@@ -1103,8 +1179,8 @@ int run_hf(green_plan* p, const void* V, const void* G, void* Sinf, void* ws, hi
 
 // ---------------------------------------------------------------- Dyson + mu
 // Bits of the device status word: a zero or non-finite pivot in a batched inversion, and inputs that break an
-// assumption the plan relies on (time reversal; the debug checks of GREEN_CHECK=1).
-constexpr int kStatusSingular = 1, kStatusTimeReversal = 2, kStatusInput = 4;
+// assumption the plan relies on (time reversal, the point group; the debug checks of GREEN_CHECK=1).
+constexpr int kStatusSingular = 1, kStatusTimeReversal = 2, kStatusInput = 4, kStatusSymmetry = 8;
 
 int read_status_at(int* status, hipStream_t s) {
   if (green::dryrun()) return GREEN_OK;
@@ -1113,7 +1189,7 @@ int read_status_at(int* status, hipStream_t s) {
   HIP_TRY(hipStreamSynchronize(s));
   if (st) {
     HIP_TRY(hipMemsetAsync(status, 0, sizeof(int), s));
-    return (st & (kStatusTimeReversal | kStatusInput)) ? GREEN_EINVAL : GREEN_ESINGULAR;
+    return (st & (kStatusTimeReversal | kStatusInput | kStatusSymmetry)) ? GREEN_EINVAL : GREEN_ESINGULAR;
   }
   return GREEN_OK;
 }
@@ -1352,10 +1428,12 @@ bool debug_checks() {
 // Asynchronous checks of G and V against what the plan assumes; a violation is latched in the status word and
 // reported (GREEN_EINVAL) by the next synchronising call.  With GREEN_OPT_TIME_REVERSAL: G^{-k}_s(tau) =
 // conj G^k_s(tau) everywhere and V^{-k1,-k2}(Q) = conj V^{k1,k2}(Q) on three auxiliary indices of every pair
-// (full store).  Relative tolerance 1e-8 of the largest element.
+// (full store).  With a point group: G^k_s(tau) equal to G of the contracted momentum it is filled from (copy, or
+// conjugate under time reversal) everywhere, and V^{R k1, R k2}(Q) = V^{k1,k2}(Q) for every operation on three
+// auxiliary indices of every pair (full store).  Relative tolerance 1e-8 of the largest element.
 int check_inputs(green_plan* p, const void* V, const void* G, void* ws, hipStream_t s) {
   const bool dbg = debug_checks();
-  if (!p->trev && !dbg) return GREEN_OK;
+  if (!p->trev && !p->ksym && !dbg) return GREEN_OK;
   const green_dims& d = p->d;
   const int nk = p->nk, nao = d.nao, naux = d.naux;
   const int64_t nG = (int64_t)nao * nao;
@@ -1367,10 +1445,22 @@ int check_inputs(green_plan* p, const void* V, const void* G, void* ws, hipStrea
   const int32_t* kadd = at<int32_t>(ws, p->r_kadd);
   const int64_t nmat = (int64_t)d.nspin * d.ntau;
   const double tol = 1e-8;
-  if (p->trev) {
+  if (p->trev || p->ksym) {
+    // G of every momentum that is not contracted against its source (orbit copies, time-reversal conjugates)
+    const int32_t* kfill = at<int32_t>(ws, p->r_kfill);
+    const int bit = p->ksym ? kStatusSymmetry : kStatusTimeReversal;
     GREEN_TRY(aux(s, [=](hipStream_t st_) {
-      return green::launch_check_conj_k(Gp, nmat, nk, nG, kneg, tol, kStatusTimeReversal, part, st, st_);
+      return green::launch_check_k(Gp, nmat, nk, nG, kfill, tol, bit, part, st, st_);
     }));
+  }
+  if (p->ksym && !p->vhalf) {
+    const int32_t* krot = at<int32_t>(ws, p->r_krot);
+    const int nrot = p->nrot;
+    GREEN_TRY(aux(s, [=](hipStream_t st_) {
+      return green::launch_check_v_rot(Vp, nk, naux, nao, krot, nrot, tol, kStatusSymmetry, part, st, st_);
+    }));
+  }
+  if (p->trev) {
     if (!p->vhalf)
       GREEN_TRY(aux(s, [=](hipStream_t st_) {
         return green::launch_check_v(Vp, nk, naux, nao, kadd, kneg, 1, tol, kStatusTimeReversal, part, st, st_);
@@ -1646,13 +1736,9 @@ int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, 
   }
   for (int q = 0; q < nk; ++q)
     if (p->kneg[q] >= q) p->qcan.push_back(q);
-  p->kcan = p->qcan;  // the same set of momenta
   p->qslot.assign(nk, -1);
   for (size_t i = 0; i < p->qcan.size(); ++i) p->qslot[p->qcan[i]] = (int32_t)i;
-  const int nkh = (int)p->kcan.size();
-  p->ksubc.resize((size_t)nk * nkh);
-  for (int q = 0; q < nk; ++q)
-    for (int kk = 0; kk < nkh; ++kk) p->ksubc[(size_t)q * nkh + kk] = p->ksub[(size_t)q * nk + p->kcan[kk]];
+  build_contracted_sets(p);
   // ---- workspace layout
   const int64_t nao = d.nao, naux = d.naux, ns = d.nspin;
   const int64_t nG = nao * nao, nV = naux * nG, nP = naux * naux;
@@ -1693,10 +1779,11 @@ int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, 
   take(p->r_wf, (size_t)nwf * 8);
   take(p->r_kadd, (size_t)nk * nk * 4);
   take(p->r_ksub, (size_t)nk * nk * 4);
-  take(p->r_qcan, p->qcan.size() * 4);
   take(p->r_kneg, (size_t)nk * 4);
-  take(p->r_kcan, (size_t)nkh * 4);
-  take(p->r_ksubc, (size_t)nk * nkh * 4);
+  take(p->r_kc, (size_t)nk * 4);
+  take(p->r_ksubc, (size_t)nk * nk * 4);
+  take(p->r_qc, (size_t)nk * 4);
+  take(p->r_kfill, (size_t)nk * 4);
   take(p->r_status, 64);
   take(p->r_scal, 64 * 8);
   take(p->r_partial, 1024 * 8);
@@ -2195,6 +2282,7 @@ int green_plan_set_option(green_plan* p, int option, int value) {
     case GREEN_OPT_TIME_REVERSAL:
       if (value < 0 || value > 1) return GREEN_EINVAL;
       p->trev = value != 0;
+      build_contracted_sets(p);
       drop_graph(p);
       return count_ops(p);
     case GREEN_OPT_GF2:
@@ -2213,6 +2301,65 @@ int green_plan_set_option(green_plan* p, int option, int value) {
     default:
       return GREEN_EINVAL;
   }
+}
+
+int green_plan_set_kpoint_symmetry(green_plan* p, const int32_t* rot, int nops, int32_t* counts) {
+  if (!p || nops < 0 || nops > GREEN_MAX_KPOINT_OPS || (nops > 0 && !rot)) return GREEN_EINVAL;
+  const int nk = p->nk;
+  const int32_t* m = p->d.kmesh;
+  std::vector<int32_t> krot((size_t)nops * nk);
+  for (int r = 0; r < nops; ++r) {
+    const int32_t* R = rot + 9 * r;
+    // well defined modulo the mesh: R maps m_j e_j into the lattice of mesh periods
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        if (((int64_t)R[3 * i + j] * m[j]) % m[i] != 0) return GREEN_EINVAL;
+    std::vector<char> hit(nk, 0);
+    for (int k = 0; k < nk; ++k) {
+      int a, b, c;
+      kpoint(m, k, a, b, c);
+      int x[3];
+      for (int i = 0; i < 3; ++i) {
+        const int64_t v = (int64_t)R[3 * i] * a + (int64_t)R[3 * i + 1] * b + (int64_t)R[3 * i + 2] * c;
+        x[i] = (int)(((v % m[i]) + m[i]) % m[i]);
+      }
+      const int img = kflat(m, x[0], x[1], x[2]);
+      if (hit[img]) return GREEN_EINVAL;  // not one to one
+      hit[img] = 1;
+      krot[(size_t)r * nk + k] = img;
+    }
+  }
+  // orbits of the generated group: k joined with R k for every operation, labelled by the smallest member
+  std::vector<int32_t> root(nk);
+  for (int k = 0; k < nk; ++k) root[k] = k;
+  auto find = [&](int k) {
+    while (root[k] != k) k = root[k] = root[root[k]];
+    return k;
+  };
+  for (int r = 0; r < nops; ++r)
+    for (int k = 0; k < nk; ++k) {
+      const int a = find(k), b = find(krot[(size_t)r * nk + k]);
+      if (a != b) root[std::max(a, b)] = std::min(a, b);
+    }
+  std::vector<int32_t> orb(nk);
+  for (int k = 0; k < nk; ++k) orb[k] = find(k);
+  if (nops > 0 && p->r_krot.bytes < krot.size() * 4) {
+    const size_t bytes = (size_t)GREEN_MAX_KPOINT_OPS * nk * 4;
+    p->r_krot.off = p->ws_bytes;
+    p->r_krot.bytes = bytes;
+    p->ws_bytes += (bytes + 255) & ~(size_t)255;
+  }
+  p->ksym = nops > 0;
+  p->nrot = nops;
+  p->krot.swap(krot);
+  p->korb.swap(orb);
+  build_contracted_sets(p);
+  drop_graph(p);
+  if (counts) {
+    counts[0] = (int32_t)p->qc.size();
+    counts[1] = (int32_t)p->kc.size();
+  }
+  return count_ops(p);
 }
 
 int green_plan_tuning_report(const green_plan* p, char* buf, size_t len) {

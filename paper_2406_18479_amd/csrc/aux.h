@@ -11,9 +11,10 @@ hipError_t launch_density(const double2* G, double2* gam, double2* gamT, int ns,
 // src and dst may be the same array when the two t ranges do not overlap).
 hipError_t launch_transpose_reverse(const double2* src, double2* dst, int n, int nt, int t_lo, int t_hi,
                                    hipStream_t s, bool conj = false);
-// Time-reversal partners: for every block b < nblk and momentum k with kneg[k] < k,
-// X[b][k] = conj(X[b][kneg[k]]) element by element (blocks of nk matrices of ne elements; kneg on the device).
-hipError_t launch_conj_partner(double2* X, int64_t nblk, int nk, int64_t ne, const int32_t* kneg, hipStream_t s);
+// Momenta that are not contracted: for every block b < nblk and momentum k with kfill[k] != k,
+// X[b][k] = X[b][kfill[k]] (kfill[k] < nk, a symmetry copy) or conj X[b][kfill[k] - nk] (time reversal), element by
+// element (blocks of nk matrices of ne elements; kfill on the device, every source has kfill[src] == src).
+hipError_t launch_fill_k(double2* X, int64_t nblk, int nk, int64_t ne, const int32_t* kfill, hipStream_t s);
 // Hermitian partner slab: out[k][Q][i][j] = conj(in[kmap[k]][Q][j][i]) for k < nk (naux blocks of nao x nao per k).
 hipError_t launch_herm_partner(const double2* in, double2* out, int nk, int naux, int nao, const int32_t* kmap,
                                hipStream_t s);
@@ -36,15 +37,18 @@ hipError_t launch_one_minus_copy(const double2* src, double2* dst, int n, int64_
 hipError_t launch_copy(const double2* src, double2* dst, int64_t n, hipStream_t s);
 // Input checks (asynchronous): `bit` is set in *status when the largest |difference| exceeds tol times the
 // largest |value| (or a value is not finite).  partial: 512 doubles of scratch.
-//   conj_k: X[b][k] against conj X[b][kneg[k]] (nblk blocks of nk matrices of ne elements)
+//   k:      X[b][k] against its source under kfill, as launch_fill_k (nblk blocks of nk matrices of ne elements)
 //   herm:   X_b against X_b^dagger (nmat n x n matrices)
 //   v:      V[q][k][Q] against V[-q][k+q][Q]^dagger (mode 0) or conj V[-q][-k][Q] (mode 1), on three Q
-hipError_t launch_check_conj_k(const double2* X, int64_t nblk, int nk, int64_t ne, const int32_t* kneg, double tol,
-                               int bit, double* partial, int* status, hipStream_t s);
+//   v_rot:  V[q][k][Q] against V[R q][R k][Q] for each of nops operations (krot[r nk + k] = R k), on three Q
+hipError_t launch_check_k(const double2* X, int64_t nblk, int nk, int64_t ne, const int32_t* kfill, double tol,
+                          int bit, double* partial, int* status, hipStream_t s);
 hipError_t launch_check_herm(const double2* X, int64_t nmat, int n, double tol, int bit, double* partial, int* status,
                              hipStream_t s);
 hipError_t launch_check_v(const double2* V, int nk, int naux, int nao, const int32_t* kadd, const int32_t* kneg,
                           int mode, double tol, int bit, double* partial, int* status, hipStream_t s);
+hipError_t launch_check_v_rot(const double2* V, int nk, int naux, int nao, const int32_t* krot, int nops, double tol,
+                              int bit, double* partial, int* status, hipStream_t s);
 
 // DIIS: *out = sum Re(conj(a) b) (fixed-order reduction through partial[mix_blocks(n)]); r = x - old;
 // out = sum_j c_j base[slot_j * stride + .] with *out_max = max |out_new - out_old|.

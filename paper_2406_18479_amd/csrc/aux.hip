@@ -284,17 +284,20 @@ __global__ void k_zero(double2* __restrict__ X, int64_t n) {
     X[x] = make_double2(0.0, 0.0);
 }
 
-__global__ void k_conj_partner(double2* __restrict__ X, int64_t nblk, int nk, int64_t ne,
-                               const int32_t* __restrict__ kneg) {
+// Momenta filled from a contracted one: for every block b < nblk and momentum k with kfill[k] != k,
+// X[b][k] = X[b][kfill[k]] (kfill[k] < nk) or conj X[b][kfill[k] - nk] (kfill[k] >= nk).  Sources are contracted
+// momenta (kfill[src] == src), so no block is both read and written.
+__global__ void k_fill_k(double2* __restrict__ X, int64_t nblk, int nk, int64_t ne, const int32_t* __restrict__ kfill) {
   const int64_t n = nblk * nk * ne;
   for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
     const int64_t e = x % ne;
     const int64_t bk = x / ne;
     const int k = (int)(bk % nk);
-    const int kn = kneg[k];
-    if (kn >= k) continue;
-    const double2 v = X[(bk - k + kn) * ne + e];
-    X[x] = make_double2(v.x, -v.y);
+    const int f = kfill[k];
+    if (f == k) continue;
+    const int src = f < nk ? f : f - nk;
+    const double2 v = X[(bk - k + src) * ne + e];
+    X[x] = f < nk ? v : make_double2(v.x, -v.y);
   }
 }
 
@@ -353,17 +356,19 @@ __device__ void check_store(double d, double m, double* partial) {
     partial[2 * blockIdx.x + 1] = m;
   }
 }
-// X[b][k][e] against conj X[b][kneg[k]][e]
-__global__ __launch_bounds__(256) void k_check_conj_k(const double2* __restrict__ X, int64_t nblk, int nk, int64_t ne,
-                                                      const int32_t* __restrict__ kneg, double* __restrict__ partial) {
+// X[b][k][e] against its source under kfill (as k_fill_k: X[b][src] or conj X[b][src])
+__global__ __launch_bounds__(256) void k_check_k(const double2* __restrict__ X, int64_t nblk, int nk, int64_t ne,
+                                                 const int32_t* __restrict__ kfill, double* __restrict__ partial) {
   const int64_t total = nblk * nk * ne;
   double d = 0.0, m = 0.0;
   for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
     const int64_t bk = x / ne, e = x - bk * ne;
     const int64_t b = bk / nk;
     const int k = (int)(bk - b * nk);
-    const double2 v = X[x], w = X[(b * nk + kneg[k]) * ne + e];
-    d = fmax(d, cabs2(make_double2(v.x - w.x, v.y + w.y)));
+    const int f = kfill[k];
+    const int src = f < nk ? f : f - nk;
+    const double2 v = X[x], w = X[(b * nk + src) * ne + e];
+    d = fmax(d, cabs2(make_double2(v.x - w.x, f < nk ? v.y - w.y : v.y + w.y)));
     m = fmax(m, cabs2(v));
   }
   check_store(d, m, partial);
@@ -410,6 +415,31 @@ __global__ __launch_bounds__(256) void k_check_v(const double2* __restrict__ V, 
   }
   check_store(d, m, partial);
 }
+// V[q][k][Q] against V[R q][R k][Q] for every operation R (krot[r * nk + k] = R k) on three auxiliary indices
+// Q in {0, naux / 2, naux - 1} (V^{R k1, R k2}(Q) = V^{k1,k2}(Q)); every slab q of the full store is present.
+__global__ __launch_bounds__(256) void k_check_v_rot(const double2* __restrict__ V, int nk, int naux, int nao,
+                                                     const int32_t* __restrict__ krot, int nops,
+                                                     double* __restrict__ partial) {
+  const int64_t nG = (int64_t)nao * nao, nV = (int64_t)naux * nG;
+  const int64_t total = (int64_t)nops * nk * nk * 3 * nG;
+  double d = 0.0, m = 0.0;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t blk = x / nG;
+    const int e = (int)(x - blk * nG);
+    const int qi = (int)(blk % 3);
+    const int64_t rqk = blk / 3;
+    const int k = (int)(rqk % nk);
+    const int64_t rq = rqk / nk;
+    const int q = (int)(rq % nk), r = (int)(rq / nk);
+    const int Q = qi == 0 ? 0 : (qi == 1 ? naux / 2 : naux - 1);
+    const int32_t* R = krot + (int64_t)r * nk;
+    const double2 v = V[((int64_t)q * nk + k) * nV + Q * nG + e];
+    const double2 w = V[((int64_t)R[q] * nk + R[k]) * nV + Q * nG + e];
+    d = fmax(d, cabs2(make_double2(v.x - w.x, v.y - w.y)));
+    m = fmax(m, cabs2(v));
+  }
+  check_store(d, m, partial);
+}
 __global__ __launch_bounds__(256) void k_check_finish(const double* __restrict__ partial, int nb, double tol, int bit,
                                                       int* __restrict__ status) {
   if (threadIdx.x != 0) return;
@@ -449,10 +479,10 @@ hipError_t launch_transpose_reverse(const double2* src, double2* dst, int n, int
   return hipGetLastError();
 }
 
-hipError_t launch_conj_partner(double2* X, int64_t nblk, int nk, int64_t ne, const int32_t* kneg, hipStream_t s) {
+hipError_t launch_fill_k(double2* X, int64_t nblk, int nk, int64_t ne, const int32_t* kfill, hipStream_t s) {
   const int64_t n = nblk * nk * ne;
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_conj_partner, dim3(grid_for(n)), dim3(256), 0, s, X, nblk, nk, ne, kneg);
+  hipLaunchKernelGGL(k_fill_k, dim3(grid_for(n)), dim3(256), 0, s, X, nblk, nk, ne, kfill);
   return hipGetLastError();
 }
 
@@ -549,10 +579,10 @@ hipError_t launch_copy(const double2* src, double2* dst, int64_t n, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t launch_check_conj_k(const double2* X, int64_t nblk, int nk, int64_t ne, const int32_t* kneg, double tol,
-                               int bit, double* partial, int* status, hipStream_t s) {
+hipError_t launch_check_k(const double2* X, int64_t nblk, int nk, int64_t ne, const int32_t* kfill, double tol,
+                          int bit, double* partial, int* status, hipStream_t s) {
   if (nblk * nk * ne <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_check_conj_k, dim3(kCheckBlocks), dim3(256), 0, s, X, nblk, nk, ne, kneg, partial);
+  hipLaunchKernelGGL(k_check_k, dim3(kCheckBlocks), dim3(256), 0, s, X, nblk, nk, ne, kfill, partial);
   hipLaunchKernelGGL(k_check_finish, dim3(1), dim3(64), 0, s, partial, kCheckBlocks, tol, bit, status);
   return hipGetLastError();
 }
@@ -568,6 +598,14 @@ hipError_t launch_check_herm(const double2* X, int64_t nmat, int n, double tol, 
 hipError_t launch_check_v(const double2* V, int nk, int naux, int nao, const int32_t* kadd, const int32_t* kneg,
                           int mode, double tol, int bit, double* partial, int* status, hipStream_t s) {
   hipLaunchKernelGGL(k_check_v, dim3(kCheckBlocks), dim3(256), 0, s, V, nk, naux, nao, kadd, kneg, mode, partial);
+  hipLaunchKernelGGL(k_check_finish, dim3(1), dim3(64), 0, s, partial, kCheckBlocks, tol, bit, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_v_rot(const double2* V, int nk, int naux, int nao, const int32_t* krot, int nops, double tol,
+                              int bit, double* partial, int* status, hipStream_t s) {
+  if (nops <= 0 || nk <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_check_v_rot, dim3(kCheckBlocks), dim3(256), 0, s, V, nk, naux, nao, krot, nops, partial);
   hipLaunchKernelGGL(k_check_finish, dim3(1), dim3(64), 0, s, partial, kCheckBlocks, tol, bit, status);
   return hipGetLastError();
 }

@@ -92,7 +92,7 @@ class Plan:
         return (self.nk, self.nao, self.nao)
 
     def set_option(self, option: str, value: int) -> None:
-        """option "tune" (0, 1, 2), "graph" (0, 1), "p0_tile" (1..9), "sigma_tile" (1..9), "stage1_tile" (0..2), "sigma_fused"
+        """option "tune" (0, 1, 2), "graph" (0, 1), "p0_tile" (1..11), "sigma_tile" (1..11), "stage1_tile" (0..2), "sigma_fused"
         (0, 1), "gf2" (0, 1), "time_reversal" (0, 1) or "v_half" (0, 1: V holds the canonical-q slabs only,
         shape_V follows); see green_plan_set_option.  The workspace is re-allocated when the option grows it."""
         code = {"tune": _lib.OPT_TUNE, "graph": _lib.OPT_GRAPH, "p0_tile": _lib.OPT_P0_TILE,
@@ -102,12 +102,27 @@ class Plan:
         _lib.check(_lib.LIB.green_plan_set_option(self._h, code, int(value)), "green_plan_set_option")
         if option == "v_half":
             self.v_half = bool(value)
+        self._regrow()
+
+    def _regrow(self) -> None:
         need = int(_lib.LIB.green_workspace_bytes(self._h))
         if need != self.ws_bytes:
             self.ws_bytes = need
             self.ws = None
             with torch.cuda.device(self.device):
                 self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+
+    def set_kpoint_symmetry(self, rotations) -> tuple:
+        """Point group acting on the k mesh (green_plan_set_kpoint_symmetry): `rotations` is a sequence of 3x3
+        integer matrices acting on integer mesh coordinates (empty: none).  Returns the numbers of contracted
+        momentum transfers and of contracted momenta."""
+        rot = np.ascontiguousarray(np.asarray(rotations, dtype=np.int32).reshape(-1, 9))
+        counts = (ctypes.c_int32 * 2)()
+        ptr = rot.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if len(rot) else None
+        _lib.check(_lib.LIB.green_plan_set_kpoint_symmetry(self._h, ptr, len(rot), counts),
+                   "green_plan_set_kpoint_symmetry")
+        self._regrow()
+        return int(counts[0]), int(counts[1])
 
     def tuning_report(self) -> str:
         buf = ctypes.create_string_buffer(1 << 16)
