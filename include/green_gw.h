@@ -297,7 +297,7 @@ int green_gw_iterate_diis(green_plan* plan, const void* V, const void* H0, const
  *   GREEN_OPT_STAGE1_TILE  split-BF16 plans: tile of the V G products that feed it: 0 = 64 x 64,
  *                   1 = 192 x 96 (default), 2 = 192 x 64.
  *                   Both only change the summation blocking; results agree to rounding.
- *   GREEN_OPT_SIGMA_FUSED  split-BF16 plans with nao a multiple of 4 up to 64: 1 (default) runs the two contractions
+ *   GREEN_OPT_SIGMA_FUSED  split-BF16 plans with an even nao up to 80: 1 (default) runs the two contractions
  *                   of Eqs. sigma_gw and tilde_W_DF2 after P~^T V (over the orbital a with G(tau), then over (Q', b)
  *                   with V) in one kernel that keeps their intermediate in registers; 0 runs them as two
  *                   contractions through HBM.  GREEN_EINVAL where the plan does not allow 1.

@@ -61,7 +61,7 @@ struct green_plan {
                        // LDS-DMA 5 = 320 x 64, 6 = 192 x 128
                        // (set at plan creation from naux)
   int big_sig = 6;     // split-BF16 Sigma~ stage-1 kernel (P~^T V over Q), the tiles of big_p0
-  bool fuse_sig = false;  // split-BF16 plans, nao % 4 == 0 and <= 64: Sigma~ stages 2 and 3 in one kernel
+  bool fuse_sig = false;  // split-BF16 plans, even nao up to 80: Sigma~ stages 2 and 3 in one kernel
   bool gf2 = false;       // the dynamic self-energy is GF2 (Eq. sigma2) instead of GW
   size_t chunk_bytes = 0;
   // GF2 exchange: per momentum triple (k, k1, k2), flattened ((k nk) + k1) nk + k2, the blocks of the V G
@@ -546,6 +546,9 @@ Extents extents(const green_plan* p) {
   return e;
 }
 
+// Split-BF16 plans whose Sigma~ stages 2 and 3 can run fused (even nao up to the fused kernel's 80).
+bool fusable(int prec, int nao) { return prec == GREEN_BF16X3 && nao % 2 == 0 && nao <= green::kXgvMaxNao; }
+
 // GF2 exchange tables of the contracted momenta kc (after the full tables: the four rows of every triple whose
 // first momentum is contracted, in kc order).  The region holds room for every k.
 void build_gf2_tail(green_plan* p) {
@@ -871,8 +874,13 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
       if (bf) {
         const bool own = q != qn || vt_dma;  // stage 3 needs its own (untransposed) slab
         if (fused) {
-          // V^{k-q,k}_{bj}(Q') stored [k][Q'][j][b] for the fused stages 2 and 3
-          GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64_tr(static_cast<const double2*>(Vq), eptr(Vx, vt, slab), vt, nao, nao, nk * naux, st_, true); }));
+          // V^{k-q,k}_{bj}(Q') stored [k][Q'][j][b] for the fused stages 2 and 3 (rows of b padded with zeros to a
+          // multiple of 4)
+          const int vs = green::xgv_vrow(nao);
+          if (nao > 64)
+            GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::xgv_vimage(static_cast<const double2*>(Vq), eptr(Vx, vt, slab), nao, (int64_t)nk * naux, st_); }));
+          else
+            GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64_tr(static_cast<const double2*>(Vq), eptr(Vx, vt, slab), vt, nao, nao, nk * naux, st_, true, vs); }));
         } else if (own) {
           GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::convert_c64(static_cast<const double2*>(Vq), eptr(Vx, vt, slab), vt, slab, st_); }));
         }
@@ -914,7 +922,8 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
         while (qs > 1 && (int64_t)qs * hv * nkx * nG * tcn > tl_split.cap) --qs;
         if ((int64_t)qs * hv * nkx * nG * tcn > tl_split.cap) return GREEN_EINVAL;
         // every element the kernel reads lies inside its region
-        if ((int64_t)tcn * nkx * nV * 8 > (int64_t)p->r_T1.bytes || (int64_t)p->r_Vx.bytes < 2 * slab * 8 ||
+        if ((int64_t)tcn * nkx * nV * 8 > (int64_t)p->r_T1.bytes ||
+            (int64_t)p->r_Vx.bytes < (slab + (int64_t)nk * naux * green::xgv_vblock(nao)) * 8 ||
             ((int64_t)sp * ntau + t0 + tcn) * nk * nG * 8 > (int64_t)p->r_GTx.bytes)
           return GREEN_EINVAL;
         green::XgvArgs xa{};
@@ -924,6 +933,7 @@ int run_selfenergy(green_plan* p, const void* V, const void* G, const void* Pt, 
         xa.kk = ktab(q);
         xa.partial = tl_split.ptr;
         xa.nao = nao;
+        xa.vs = green::xgv_vrow(nao);
         xa.naux = naux;
         xa.nk = nkx;
         xa.tcn = tcn;
@@ -1801,10 +1811,13 @@ int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, 
   take(p->r_A, (size_t)ns * nwf * nk * nG * 16);
   take(p->r_tr, (size_t)std::max<int64_t>(ns * nwf * nk, ns * ntau * nk) * 16);
   take(p->r_split, (size_t)1 << 30);
-  take(p->r_Vx, prec == GREEN_FP64 ? 0 : (size_t)(prec == GREEN_BF16X3 ? 2 : 1) * nk * nV * 8);
+  p->fuse_sig = fusable(prec, (int)nao);
+  // split BF16: two rounded V slabs (the second one with rows padded for the fused kernel)
+  take(p->r_Vx, prec == GREEN_FP64 ? 0
+                                   : prec == GREEN_BF16X3 ? (size_t)nk * naux * (nG + green::xgv_vblock((int)nao)) * 8
+                                                          : (size_t)nk * nV * 8);
   take(p->r_Gx, prec == GREEN_BF16X3 ? (size_t)ns * ntau * nk * nG * 8 : 0);
   take(p->r_Ptx, prec == GREEN_BF16X3 ? (size_t)ntau * nP * 8 : 0);
-  p->fuse_sig = prec == GREEN_BF16X3 && nao % 4 == 0 && nao <= 64;
   take(p->r_GTx, p->fuse_sig ? (size_t)ns * ntau * nk * nG * 8 : 0);
   p->ws_bytes = off;
   if (count_ops(p) != GREEN_OK) {
@@ -2294,7 +2307,7 @@ int green_plan_set_option(green_plan* p, int option, int value) {
       return count_ops(p);
     case GREEN_OPT_SIGMA_FUSED:
       if (value < 0 || value > 1) return GREEN_EINVAL;
-      if (value && (p->prec != GREEN_BF16X3 || p->d.nao % 4 != 0 || p->d.nao > 64)) return GREEN_EINVAL;
+      if (value && !fusable(p->prec, p->d.nao)) return GREEN_EINVAL;
       p->fuse_sig = value != 0;
       drop_graph(p);
       return GREEN_OK;

@@ -144,20 +144,35 @@ hipError_t convert_c64_t(const double2* in, void* out, int32_t etype, int n, int
 struct XgvArgs {
   const uint2* X;      // element tt * x_tt + k * x_k + Q' * nao^2 + i * nao + a
   const uint2* GT;     // element tt * g_tt + kk * nao^2 + b * nao + a
-  const uint2* VT;     // element kk * naux * nao^2 + Q' * nao^2 + j * nao + b, rows j in 4-element groups of
-                       // hi words then lo words (convert_c64_tr with quad)
+  const uint2* VT;     // element kk * naux * nao * vs + Q' * nao * vs + j * vs + b, rows j of vs elements (nao
+                       // rounded up to a multiple of 4, zero padded) in 4-element groups of hi words then lo words
+                       // (convert_c64_tr with quad)
   const int32_t* kk;   // device: k -> block index of G and V
   double2* partial;    // qsplit * xgv_halves(nao) * nk * nao * tcn * nao elements
   int32_t nao, naux, nk, tcn, qsplit;
+  int32_t vs;          // row length of the V^T blocks: xgv_vrow(nao)
   int64_t x_tt, x_k, g_tt;
 };
-// partial sums per Q' slice of the fused kernel (its b blocks split over that many waves: 2 for nao > 16)
+// partial sums per Q' slice of the fused kernel (its b blocks split over that many waves: 2 for 16 < nao <= 64)
 int xgv_halves(int nao);
+// largest nao the fused kernel takes (even nao only), the padded row length of its V^T blocks, and the elements
+// (8 bytes each) of one V^T block in memory: nao rows of xgv_vrow(nao) for nao <= 64, the 80 x 80 LDS image
+// (xgv_vimage) above
+constexpr int kXgvMaxNao = 80;
+inline int xgv_vrow(int nao) { return (nao + 3) & ~3; }
+inline int64_t xgv_vblock(int nao) { return nao > 64 ? 80 * 80 : (int64_t)nao * xgv_vrow(nao); }
+// V^T blocks of the fused kernel for 64 < nao <= 80, written as the kernel's LDS image: for each of `blocks`
+// (k, Q') blocks of `in` (nao x nao, element (b, j) at b nao + j, i.e. V^{k-q,k}_{bj}(Q')), 80 rows j of 40
+// 16-byte units, unit (j, s) holding the hi (u even) or lo (u odd) words of the complex b = 4 (u / 2) .. + 3 of
+// row j, u = s with its low three bits XORed with (j >> 1) & 7; zero past nao.
+hipError_t xgv_vimage(const double2* in, void* out, int nao, int64_t blocks, hipStream_t s);
 hipError_t sigma_xgv(const XgvArgs& a, const ZGemm& reduce, hipStream_t s);
 // out[b][c][r] = in[b][r][c] rounded to kC32 or kCB16 (rows x cols matrices, batch of them).  quad (kCB16,
-// rows % 4 == 0): each output row holds its elements in groups of 4 as 4 hi words then 4 lo words.
+// rows % 4 == 0): each output row holds its elements in groups of 4 as 4 hi words then 4 lo words.  rows_out >
+// rows: output rows of rows_out elements, the ones past rows zero (out[b][c][r] over r < rows_out; quad needs
+// rows_out % 4 == 0 instead).
 hipError_t convert_c64_tr(const double2* in, void* out, int32_t etype, int rows, int cols, int batch, hipStream_t s,
-                          bool quad = false);
+                          bool quad = false, int rows_out = 0);
 
 // Host-side bounds check of a GEMM descriptor against the buffers its operands point into (conservative:
 // the box spanned by the index maps).  Returns false and fills `why` when an access could leave a buffer.

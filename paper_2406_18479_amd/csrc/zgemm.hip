@@ -1408,19 +1408,27 @@ __device__ __forceinline__ void bq_body(const ZGemm& g, int64_t bid0, int64_t nb
 // holds (rows b = 4 (l >> 4) + r, column i = l & 15) is exactly its B operand of the second product (four
 // consecutive K = b of column i), so it is split to BF16 hi + lo in place.  A workgroup owns (tt, k, slice of
 // Q'); H waves share each 16-column block of i (wave w: columns 16 (w % NB) + ..., part h = w / NB of the
-// b blocks), each summing over its own b blocks.  G^T and a ring of three V^T blocks sit in LDS (rows padded
-// to 16 NB); the V^T block (LDS DMA) and the X rows (registers) of Q' + 2 are in flight while Q' is
-// contracted.  Each (Q' slice, h) writes FP64 partial sums [slice H + h][k][j][tt][i] that the split-K pass
-// adds in order.
+// b blocks), each summing over its own b blocks.  G^T and a ring of NS V^T blocks sit in LDS (rows padded
+// to 16 NB); the V^T block (LDS DMA) and the X rows (registers) of Q' + NS - 1 are in flight while Q' is
+// contracted (NS = 3, or 2 for the 80-row blocks, whose three slots would not fit 160 KB next to G^T).  Each
+// (Q' slice, h) writes FP64 partial sums [slice H + h][k][j][tt][i] that the split-K pass adds in order.
 //
 // LDS rows of a block: K in groups of 4 complex, each group as a 16-byte unit of its 4 hi words then one of
 // its 4 lo words (unit 2 g + 0 / 1), so that a fragment read is one 16-byte load per plane; unit u of row r
-// sits at slot u ^ (r & 15) for rows of 256 or 512 bytes and u ^ row_xor(r) for rows of 128 bytes (the
-// patterns that keep the fragment reads free of bank conflicts).
+// sits at slot u ^ (r & 15) for rows of 256 or 512 bytes, u ^ row_xor(r) for rows of 128 bytes (the patterns
+// that keep the fragment reads free of bank conflicts), and for rows of 640 bytes (NB = 5) at the XOR of its
+// low three bits with (r >> 1) & 7, which stays inside the unit's aligned group of 8 and gives the 16 rows a
+// fragment read touches 16 different bank offsets.  The map is its own inverse.
+template <int NB>
+__device__ __forceinline__ int xgv_swz(int r, int u) {
+  constexpr int CH = 8 * NB;  // 16-byte units per row (16 NB complex)
+  if constexpr (CH == 8) return u ^ row_xor(r);
+  else if constexpr (CH % 16 == 0 && (CH & (CH - 1)) == 0) return u ^ (r & 15);
+  else return (u & ~7) | ((u & 7) ^ ((r >> 1) & 7));
+}
 template <int NB>
 __device__ __forceinline__ int xgv_word(int r, int u) {
-  constexpr int CH = 8 * NB;  // 16-byte units per row (16 NB complex)
-  return (r * CH + (u ^ (CH >= 16 ? (r & 15) : row_xor(r)))) * 4;
+  return (r * 8 * NB + xgv_swz<NB>(r, u)) * 4;
 }
 // complex 2 c, 2 c + 1 of row r (memory order: hi0, lo0, hi1, lo1) into their group's hi and lo units
 template <int NB>
@@ -1430,25 +1438,25 @@ __device__ __forceinline__ void xgv_put(uint32_t* P, int r, int c, u4 v) {
   *reinterpret_cast<uint2*>(&P[xgv_word<NB>(r, 2 * g + 1) + pos]) = make_uint2(v.y, v.w);
 }
 
-template <int NB, int H>
+template <int NB, int H, int NS>
 __global__ __launch_bounds__(64 * NB * H) void sigma_xgv_kernel(const XgvArgs a) {
   constexpr int R = 16 * NB;       // padded rows and K of each block
   constexpr int NT = 64 * NB * H;  // threads
   constexpr int BH = NB / H;       // b blocks per wave
   static_assert(NB % H == 0, "b blocks split evenly");
+  static_assert(NS == 2 || NS == 3, "V^T ring of two or three slots");
   constexpr int CH = 8 * NB;            // 16-byte units per LDS row
-  constexpr int RPI = 64 / CH;          // LDS rows per DMA instruction (1 KB)
-  constexpr int DV = 2 * NB / H;        // DMA instructions per wave and V^T block
+  constexpr int DV = 2 * NB / H;        // DMA instructions per wave and V^T block (R CH / 64 over NB H waves)
   constexpr int NX = 2 * NB;            // 16-byte X loads per lane and Q'
+  static_assert((1 + NS) * R * R * 8 <= 160 * 1024, "G^T and the V^T ring fit the LDS");
   __shared__ __attribute__((aligned(16))) uint32_t Gs[R * R * 2];
-  __shared__ __attribute__((aligned(16))) uint32_t Vs0[R * R * 2];
-  __shared__ __attribute__((aligned(16))) uint32_t Vs1[R * R * 2];
-  __shared__ __attribute__((aligned(16))) uint32_t Vs2[R * R * 2];
+  __shared__ __attribute__((aligned(16))) uint32_t Vs[NS][R * R * 2];
 
   const int tid = threadIdx.x, lane = tid & 63, w = (tid >> 6) % NB, h = (tid >> 6) / NB;
   const int g4 = lane >> 4, r16 = lane & 15;
   const int nao = a.nao, nch = nao / 2;  // nao even: a row of a block is nch 16-byte chunks
-  const int64_t nG = (int64_t)nao * nao, nV = (int64_t)a.naux * nG;
+  const int vch = a.vs / 2;              // 16-byte chunks of a V^T row
+  const int64_t nG = (int64_t)nao * nao, nVT = (int64_t)nao * a.vs;
   const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
   const int tt = (int)(bid % a.tcn);
   const int64_t rest = bid / a.tcn;
@@ -1460,9 +1468,8 @@ __global__ __launch_bounds__(64 * NB * H) void sigma_xgv_kernel(const XgvArgs a)
 
   for (int x = tid; x < R * R / 2; x += NT) {
     reinterpret_cast<u4*>(Gs)[x] = u4{0u, 0u, 0u, 0u};
-    reinterpret_cast<u4*>(Vs0)[x] = u4{0u, 0u, 0u, 0u};
-    reinterpret_cast<u4*>(Vs1)[x] = u4{0u, 0u, 0u, 0u};
-    reinterpret_cast<u4*>(Vs2)[x] = u4{0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int v = 0; v < NS; ++v) reinterpret_cast<u4*>(Vs[v])[x] = u4{0u, 0u, 0u, 0u};
   }
   __syncthreads();
   {
@@ -1473,42 +1480,83 @@ __global__ __launch_bounds__(64 * NB * H) void sigma_xgv_kernel(const XgvArgs a)
     }
   }
   // V^T block of one Q' (rows j, K = b; stored in memory in the LDS unit order: per group of 4 complex b, 16
-  // bytes of hi words then 16 of lo words) copied by LDS DMA: instruction d of this wave fills LDS rows
-  // RPI (wave DV + d) + l / CH, lane l the slot l % CH, i.e. the unit xgv_word places there.  Units
-  // past the row (K padding) and rows past nao read unit 0 of row 0: finite values, multiplied by Y^T rows
-  // that are exactly 0 (b >= nao) or feeding outputs that are not stored (j >= nao).
-  const char* vbase = reinterpret_cast<const char*>(a.VT + (int64_t)kk * nV);
-  int voff[DV];
+  // bytes of hi words then 16 of lo words) copied by LDS DMA: instruction d of this wave fills the 64 LDS units
+  // 64 (wave DV + d) + l (lane l), unit U being slot U % CH of row U / CH, i.e. the unit xgv_word places
+  // there.  Units past the row (K padding, and the zero padding of the stored rows) and rows past nao read
+  // unit 0 of row 0: finite values, multiplied by Y^T rows that are exactly 0 (b >= nao) or feeding outputs
+  // that are not stored (j >= nao).
+  // (80-row blocks: the blocks are stored as their LDS image, xgv_vimage, so copy d of a lane is the unit at
+  // the same position in memory)
+  const int64_t vblk = NB == 5 ? (int64_t)R * R : nVT;  // elements of one stored block
+  const char* vbase = reinterpret_cast<const char*>(a.VT + (int64_t)kk * a.naux * vblk);
+  int voff[NB == 5 ? 1 : DV];
+  if constexpr (NB != 5) {
 #pragma unroll
-  for (int d = 0; d < DV; ++d) {
-    const int row = RPI * ((tid >> 6) * DV + d) + lane / CH;
-    const int u = (lane % CH) ^ (CH >= 16 ? (row & 15) : row_xor(row));
-    voff[d] = row < nao && u < nch ? (row * nao + 2 * u) * 8 : 0;
+    for (int d = 0; d < DV; ++d) {
+      const int U = 64 * ((tid >> 6) * DV + d) + lane;
+      const int row = U / CH;
+      const int u = xgv_swz<NB>(row, U - row * CH);
+      voff[d] = row < nao && u < vch ? (row * a.vs + 2 * u) * 8 : 0;
+    }
   }
+  // (image copies: a wave-uniform base per copy plus one 32-bit lane offset, kept opaque so that the compiler
+  // does not precompute a 64-bit address per copy)
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  uint32_t loff = lane * 16;
+  asm volatile("" : "+v"(loff));
   auto vissue = [&](int qp, uint32_t* V) {
-    const char* blk = vbase + (int64_t)qp * nG * 8;
+    const char* blk = vbase + (int64_t)qp * vblk * 8;
 #pragma unroll
-    for (int d = 0; d < DV; ++d) dma16(blk + voff[d], V + ((tid >> 6) * DV + d) * 256);
+    for (int d = 0; d < DV; ++d) {
+      if constexpr (NB == 5) dma16(blk + (int64_t)(wv * DV + d) * 1024 + loff, V + (wv * DV + d) * 256);
+      else dma16(blk + voff[d], V + ((tid >> 6) * DV + d) * 256);
+    }
   };
   // B operand of the first product: X^T (K = a, column i = 16 w + r16): complex a = 16 ab + 4 g4 .. + 3 of
   // row i, as two 16-byte chunks.  a >= nao reads a = 0 (finite; G^T is 0 there) and i >= nao reads row
   // nao - 1 (its results are not stored), so the loaded registers are used as they land.
   const int icl = min(16 * w + r16, nao - 1);
-  u4 x0[NB][2], x1[NB][2], x2[NB][2];  // X of three consecutive Q' (loaded two Q' ahead)
+  // X of three consecutive Q' (NS = 3, loaded two Q' ahead) or one register set (NS = 2)
+  u4 x0[NB][2], x1[NB][NS == 3 ? 2 : 1], x2[NB][NS == 3 ? 2 : 1];
+  // (80-row blocks: a uniform block base and one opaque lane offset, the column clamped to nao - 2 per load, so
+  // that no per-load address is kept across Q')
+  uint32_t xlane = (uint32_t)icl * nao + 4 * g4;
+  if constexpr (NB == 5) asm volatile("" : "+v"(xlane));
   auto xload = [&](int qp, u4 (&xv)[NB][2]) {
-    const uint2* row = a.X + tt * a.x_tt + (int64_t)k * a.x_k + (int64_t)qp * nG + (int64_t)icl * nao;
+    if constexpr (NB == 5) {
+      const uint2* blk = a.X + tt * a.x_tt + (int64_t)k * a.x_k + (int64_t)qp * nG;
 #pragma unroll
-    for (int ab = 0; ab < NB; ++ab)
+      for (int ab = 0; ab < NB; ++ab)
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int a0 = 16 * ab + 4 * g4 + 2 * h;
-        xv[ab][h] = *reinterpret_cast<const u4*>(row + (a0 < nao ? a0 : 0));
-      }
+        for (int h = 0; h < 2; ++h) {
+          const uint32_t o = min(xlane + 16 * ab + 2 * h, (uint32_t)icl * nao + nao - 2);
+          xv[ab][h] = *reinterpret_cast<const u4*>(blk + o);
+        }
+    } else {
+      const uint2* row = a.X + tt * a.x_tt + (int64_t)k * a.x_k + (int64_t)qp * nG + (int64_t)icl * nao;
+#pragma unroll
+      for (int ab = 0; ab < NB; ++ab)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int a0 = 16 * ab + 4 * g4 + 2 * h;
+          xv[ab][h] = *reinterpret_cast<const u4*>(row + (a0 < nao ? a0 : 0));
+        }
+    }
   };
   // A operand fragment: row r, K block kb (complex 16 kb + 4 g4 .. + 3) as hi and lo words
+  // (80-row blocks: rows r = 16 b + r16 only, so the swizzle depends on r16 alone and a read is one of two lane
+  // bases plus the constant (16 b CH + 8 kb) 4)
+  const int sw5 = (r16 >> 1) & 7;
+  const int wh5 = (r16 * CH + ((2 * g4) ^ sw5)) * 4, wl5 = (r16 * CH + ((2 * g4 + 1) ^ sw5)) * 4;
   auto frag = [&](const uint32_t* P, int r, int kb, u4& hi, u4& lo) {
-    hi = *reinterpret_cast<const u4*>(&P[xgv_word<NB>(r, 8 * kb + 2 * g4)]);
-    lo = *reinterpret_cast<const u4*>(&P[xgv_word<NB>(r, 8 * kb + 2 * g4 + 1)]);
+    if constexpr (NB == 5) {
+      const int c = ((r - r16) * CH + 8 * kb) * 4;
+      hi = *reinterpret_cast<const u4*>(&P[wh5 + c]);
+      lo = *reinterpret_cast<const u4*>(&P[wl5 + c]);
+    } else {
+      hi = *reinterpret_cast<const u4*>(&P[xgv_word<NB>(r, 8 * kb + 2 * g4)]);
+      lo = *reinterpret_cast<const u4*>(&P[xgv_word<NB>(r, 8 * kb + 2 * g4 + 1)]);
+    }
   };
   f4 s_re[NB], s_im[NB];
 #pragma unroll
@@ -1518,7 +1566,9 @@ __global__ __launch_bounds__(64 * NB * H) void sigma_xgv_kernel(const XgvArgs a)
   }
   // one Q': Y^T = G^T X^T, then S^T += V^T Y^T (B operands conjugated (re, -im) for the real part and swapped
   // (im, re) for the imaginary part, three split products each)
-  auto contract = [&](const uint32_t* V, const u4 (&xr)[NB][2]) {
+  // (NS = 2: xr is refilled with the X rows of Q' xnext once the first product has read it, so one register
+  // set serves; the loads are in flight during the second product)
+  auto contract = [&](const uint32_t* V, u4 (&xr)[NB][2], int xnext) {
     f4 y_re[BH], y_im[BH];
 #pragma unroll
     for (int bb = 0; bb < BH; ++bb) {
@@ -1560,6 +1610,9 @@ __global__ __launch_bounds__(64 * NB * H) void sigma_xgv_kernel(const XgvArgs a)
           y_re[bb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, bch, y_re[bb], 0, 0, 0);
           y_im[bb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, bsh, y_im[bb], 0, 0, 0);
         }
+        if constexpr (NS == 2) {
+          if (st == NB - 1) xload(xnext, xr);
+        }
       } else {
         const int bb = st - NB;
         uint32_t h0, h1, h2, h3, l0, l1, l2, l3;
@@ -1583,29 +1636,44 @@ __global__ __launch_bounds__(64 * NB * H) void sigma_xgv_kernel(const XgvArgs a)
       }
     }
   };
-  // one Q' t: this wave's copies of V^T(t) and loads of X(t) landed (in flight behind them: those of t + 1)
-  // -> barrier (every wave's copies landed; every wave done with step t - 1, whose LDS slot is refilled
-  // next) -> V^T and X of t + 2 issued -> contraction
-  // Two groups are always in flight: past the slice's end the copies and loads repeat its last Q' into a
-  // slot and registers nothing reads, so the counter waits are the same in every step.
-  auto step = [&](int t, const uint32_t* V, uint32_t* V2, const u4 (&xr)[NB][2], u4 (&x2ahead)[NB][2]) {
-    wait_vm<DV + NX>();
-    barrier_only();
-    vissue(min(t + 2, q1 - 1), V2);
-    xload(min(t + 2, q1 - 1), x2ahead);
-    contract(V, xr);
+  // one Q' t: this wave's copies of V^T(t) and loads of X(t) landed (in flight behind them: those of t + 1
+  // when NS = 3) -> barrier (every wave's copies landed; every wave done with step t - 1, whose LDS slot is
+  // refilled next) -> V^T and X of t + NS - 1 issued -> contraction
+  // With NS = 3 two groups are always in flight: past the slice's end the copies and loads repeat its last Q'
+  // into a slot and registers nothing reads, so the counter waits are the same in every step.
+  auto step = [&](int t, const uint32_t* V, uint32_t* V2, u4 (&xr)[NB][2], u4 (&xahead)[NB][2]) {
+    if constexpr (NS == 3) {
+      wait_vm<DV + NX>();
+      barrier_only();
+      vissue(min(t + 2, q1 - 1), V2);
+      xload(min(t + 2, q1 - 1), xahead);
+      contract(V, xr, -1);
+    } else {
+      wait_vm<0>();
+      barrier_only();
+      vissue(min(t + 1, q1 - 1), V2);
+      contract(V, xr, min(t + 1, q1 - 1));
+    }
   };
   if (q0 < q1) {
-    vissue(q0, Vs0);
+    vissue(q0, Vs[0]);
     xload(q0, x0);
-    vissue(min(q0 + 1, q1 - 1), Vs1);
-    xload(min(q0 + 1, q1 - 1), x1);
-    for (int qp = q0; qp < q1; qp += 3) {
-      step(qp, Vs0, Vs2, x0, x2);
-      if (qp + 1 >= q1) break;
-      step(qp + 1, Vs1, Vs0, x1, x0);
-      if (qp + 2 >= q1) break;
-      step(qp + 2, Vs2, Vs1, x2, x1);
+    if constexpr (NS == 3) {
+      vissue(min(q0 + 1, q1 - 1), Vs[1]);
+      xload(min(q0 + 1, q1 - 1), x1);
+      for (int qp = q0; qp < q1; qp += 3) {
+        step(qp, Vs[0], Vs[2], x0, x2);
+        if (qp + 1 >= q1) break;
+        step(qp + 1, Vs[1], Vs[0], x1, x0);
+        if (qp + 2 >= q1) break;
+        step(qp + 2, Vs[2], Vs[1], x2, x1);
+      }
+    } else {
+      for (int qp = q0; qp < q1; qp += 2) {
+        step(qp, Vs[0], Vs[1], x0, x0);
+        if (qp + 1 >= q1) break;
+        step(qp + 1, Vs[1], Vs[0], x0, x0);
+      }
     }
     wait_vm<0>();  // no copy into LDS outlives the workgroup
   }
@@ -1738,7 +1806,7 @@ __global__ void k_convert_c64_t(const double2* __restrict__ in, void* __restrict
 // both the FP64 reads (along c) and the rounded writes (along r) are coalesced.  quad (kCB16, rows % 4 == 0):
 // each output row stores its elements in groups of 4 as the 4 hi words, then the 4 lo words.
 __global__ __launch_bounds__(256) void k_convert_c64_tr(const double2* __restrict__ in, void* __restrict__ out,
-                                                        int32_t t, int rows, int cols, int quad) {
+                                                        int32_t t, int rows, int cols, int quad, int rp) {
   __shared__ double2 tile[32][33];
   const int64_t b = blockIdx.z;
   const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
@@ -1753,9 +1821,9 @@ __global__ __launch_bounds__(256) void k_convert_c64_tr(const double2* __restric
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int c = c0 + ty + 8 * i, r = r0 + tx;
-    if (r >= rows || c >= cols) continue;
-    const double2 v = tile[tx][ty + 8 * i];
-    const int64_t x = b * rows * (int64_t)cols + (int64_t)c * rows + r;
+    if (r >= rp || c >= cols) continue;
+    const double2 v = r < rows ? tile[tx][ty + 8 * i] : make_double2(0.0, 0.0);
+    const int64_t x = b * rp * (int64_t)cols + (int64_t)c * rp + r;
     if (t == kC32) {
       reinterpret_cast<float2*>(out)[x] = make_float2((float)v.x, (float)v.y);
     } else {
@@ -1769,6 +1837,31 @@ __global__ __launch_bounds__(256) void k_convert_c64_tr(const double2* __restric
         reinterpret_cast<uint2*>(out)[x] = w;
       }
     }
+  }
+}
+
+// LDS image of the 80 x 80 V^T blocks of the fused Sigma~ kernel (see xgv_vimage): one thread per 16-byte unit.
+__global__ __launch_bounds__(256) void k_xgv_vimage(const double2* __restrict__ in, u4* __restrict__ out, int nao,
+                                                    int64_t blocks) {
+  const int64_t n = blocks * 80 * 40;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t blk = x / 3200;
+    const int e = (int)(x - blk * 3200), j = e / 40, sl = e - (e / 40) * 40;
+    const int u = (sl & ~7) | ((sl & 7) ^ ((j >> 1) & 7));
+    const int b0 = 4 * (u >> 1), plane = u & 1;
+    const double2* src = in + blk * nao * (int64_t)nao;
+    uint32_t w[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int b = b0 + t;
+      uint32_t hi = 0u, lo = 0u;
+      if (j < nao && b < nao) {
+        const double2 v = src[(int64_t)b * nao + j];
+        split_pair(v.x, v.y, hi, lo);
+      }
+      w[t] = plane ? lo : hi;
+    }
+    out[x] = u4{w[0], w[1], w[2], w[3]};
   }
 }
 
@@ -2282,18 +2375,19 @@ hipError_t convert_c64_t(const double2* in, void* out, int32_t etype, int n, int
   return hipGetLastError();
 }
 
-int xgv_halves(int nao) { return nao > 16 ? 2 : 1; }
+int xgv_halves(int nao) { return nao > 16 && nao <= 64 ? 2 : 1; }
 
 hipError_t sigma_xgv(const XgvArgs& a, const ZGemm& reduce, hipStream_t s) {
   if (a.tcn <= 0 || a.nk <= 0 || a.naux <= 0) return hipSuccess;
-  if (a.nao <= 0 || a.nao > 64 || a.nao % 4 != 0 || a.qsplit < 1 || reduce.ksplit != a.qsplit * xgv_halves(a.nao) ||
-      !a.partial)
+  if (a.nao <= 0 || a.nao > kXgvMaxNao || a.nao % 2 != 0 || a.vs != xgv_vrow(a.nao) || a.qsplit < 1 ||
+      reduce.ksplit != a.qsplit * xgv_halves(a.nao) || !a.partial)
     return hipErrorInvalidValue;
   if (dryrun()) return hipSuccess;
   const dim3 grid((unsigned)((int64_t)a.tcn * a.nk * a.qsplit));
-  if (a.nao <= 16) sigma_xgv_kernel<1, 1><<<grid, dim3(64), 0, s>>>(a);
-  else if (a.nao <= 32) sigma_xgv_kernel<2, 2><<<grid, dim3(256), 0, s>>>(a);
-  else sigma_xgv_kernel<4, 2><<<grid, dim3(512), 0, s>>>(a);
+  if (a.nao <= 16) sigma_xgv_kernel<1, 1, 3><<<grid, dim3(64), 0, s>>>(a);
+  else if (a.nao <= 32) sigma_xgv_kernel<2, 2, 3><<<grid, dim3(256), 0, s>>>(a);
+  else if (a.nao <= 64) sigma_xgv_kernel<4, 2, 3><<<grid, dim3(512), 0, s>>>(a);
+  else sigma_xgv_kernel<5, 1, 2><<<grid, dim3(320), 0, s>>>(a);
   const int64_t total = (int64_t)reduce.M * reduce.N * reduce.batch;
   int64_t nb = (total + 255) / 256;
   if (nb > 65536) nb = 65536;
@@ -2302,14 +2396,25 @@ hipError_t sigma_xgv(const XgvArgs& a, const ZGemm& reduce, hipStream_t s) {
 }
 
 hipError_t convert_c64_tr(const double2* in, void* out, int32_t etype, int rows, int cols, int batch, hipStream_t s,
-                          bool quad) {
+                          bool quad, int rows_out) {
   if (rows <= 0 || cols <= 0 || batch <= 0) return hipSuccess;
+  const int rp = rows_out > rows ? rows_out : rows;
   if (etype != kC32 && etype != kCB16) return hipErrorInvalidValue;
-  if (quad && (etype != kCB16 || rows % 4 != 0)) return hipErrorInvalidValue;
-  if (batch > 65535 || (rows + 31) / 32 > 65535) return hipErrorInvalidValue;
+  if (quad && (etype != kCB16 || rp % 4 != 0)) return hipErrorInvalidValue;
+  if (batch > 65535 || (rp + 31) / 32 > 65535) return hipErrorInvalidValue;
   if (dryrun()) return hipSuccess;
-  k_convert_c64_tr<<<dim3((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32), (unsigned)batch), dim3(256), 0,
-                     s>>>(in, out, etype, rows, cols, quad ? 1 : 0);
+  k_convert_c64_tr<<<dim3((unsigned)((cols + 31) / 32), (unsigned)((rp + 31) / 32), (unsigned)batch), dim3(256), 0,
+                     s>>>(in, out, etype, rows, cols, quad ? 1 : 0, rp);
+  return hipGetLastError();
+}
+
+hipError_t xgv_vimage(const double2* in, void* out, int nao, int64_t blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  if (nao <= 64 || nao > 80 || nao % 2 != 0) return hipErrorInvalidValue;
+  if (dryrun()) return hipSuccess;
+  int64_t nb = (blocks * 3200 + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  k_xgv_vimage<<<dim3((unsigned)nb), dim3(256), 0, s>>>(in, static_cast<u4*>(out), nao, blocks);
   return hipGetLastError();
 }
 

@@ -109,7 +109,10 @@ def test_split_bf16_sigma_tiles(tile, naux):
 FUSED = [dict(kmesh=(2, 1, 1), nao=8, naux=40, ntau=10, seed=205),     # one 16-row block
          dict(kmesh=(3, 1, 1), nao=28, naux=90, ntau=8, seed=206),     # two blocks, padded
          dict(kmesh=(2, 1, 1), nao=40, naux=75, ntau=6, seed=207),     # four blocks, the last one empty
-         dict(kmesh=(1, 1, 1), nao=64, naux=33, ntau=6, seed=208)]     # four full blocks, odd naux
+         dict(kmesh=(1, 1, 1), nao=64, naux=33, ntau=6, seed=208),     # four full blocks, odd naux
+         dict(kmesh=(3, 1, 1), nao=26, naux=60, ntau=8, seed=209),     # V^T rows padded from 26 to 28
+         dict(kmesh=(2, 1, 1), nao=78, naux=40, ntau=6, seed=210),     # 80-row blocks, two-slot ring
+         dict(kmesh=(1, 1, 1), nao=66, naux=31, ntau=6, seed=211)]     # 80-row blocks, mostly padding
 
 
 @pytest.mark.parametrize("c", FUSED, ids=lambda c: f"nao{c['nao']}_naux{c['naux']}")
