@@ -38,22 +38,30 @@ def contraction_flops(nk, nao, naux, ntau, nspin) -> float:
 
 
 def executed_fraction(spec) -> float:
-    """Share of the algorithmic contraction flops the library executes: P~0 is contracted for one q of each +-q
-    pair (half the tau nodes where q = -q), and with time reversal on half the tau nodes of every q and Sigma~ for
-    the momenta k with -k >= k only."""
+    """Share of the algorithmic contraction flops the library executes: P~0 is contracted for one orbit of each
+    pair {O, -O} (one q of each +-q pair without a point group), on half the tau nodes where -q is in the orbit of q
+    or with time reversal, and Sigma~ for one momentum per orbit (per orbit pair with time reversal)."""
+    from synth import symmetry
     from synth.systems import k_neg
     neg = k_neg(spec.kmesh)
     nk = spec.nk
     tr = time_reversal_symmetric(spec)
-    p0 = sum((0.5 if (neg[q] == q or tr) else 1.0) for q in range(nk) if neg[q] >= q) / nk
-    sig = sum(1 for k in range(nk) if neg[k] >= k) / nk if tr else 1.0
-    return 0.5 * (p0 + sig)
+    orb = symmetry.orbit_labels(spec.kmesh, symmetry.operations(spec.point_group)) if spec.point_group else \
+        list(range(nk))
+    p0 = sig = 0.0
+    for q in range(nk):
+        c = min(orb[q], orb[neg[orb[q]]])
+        if q == c:
+            p0 += 0.5 if (orb[neg[q]] == orb[q] or tr) else 1.0
+        ck = min(orb[q], orb[neg[orb[q]]]) if tr else orb[q]
+        sig += 1.0 if q == ck else 0.0
+    return 0.5 * (p0 + sig) / nk
 
 
 def workloads():
     from synth import configs
     return {"molecule": configs.MOLECULE, "periodic2": configs.PERIODIC_2, "periodic3": configs.PERIODIC_3,
-            "periodic3tr": configs.PERIODIC_3_TR, "large4": configs.LARGE_4}
+            "periodic3tr": configs.PERIODIC_3_TR, "periodic3oh": configs.PERIODIC_3_OH, "large4": configs.LARGE_4}
 
 
 def time_reversal_symmetric(spec) -> bool:
@@ -322,6 +330,9 @@ def run_precision(system, prec, steps, warmup, chunk_bytes=0, tune=False, graph=
     plan = Plan(spec.kmesh, spec.nao, spec.naux, system.grid, nspin=spec.nspin, prec=prec, chunk_bytes=chunk_bytes)
     if time_reversal_symmetric(spec):
         plan.set_option("time_reversal", 1)
+    if spec.point_group:
+        from synth import symmetry
+        plan.set_kpoint_symmetry(symmetry.operations(spec.point_group))
     if getattr(system, "v_half", False):
         plan.set_option("v_half", 1)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")  # noqa: E731
@@ -663,12 +674,20 @@ def main():
         return
     from synth import device as dgen
     spec = workloads()[args.workload]
-    system = systems.make_system(spec, with_V=False)
     t0 = time.perf_counter()
-    system.v_half = bool(args.v_half)
     canon = [q for q in range(spec.nk) if systems.k_neg(spec.kmesh)[q] >= q]
-    # generated in HBM (same draws as the host generator)
-    system.V_dev = dgen.make_V(spec, device="cuda:0", qs=canon if args.v_half else None)
+    if spec.point_group:
+        # inputs invariant under the group: H0 and G0 on the host, V averaged over the group in HBM
+        from synth import symmetry
+        system = symmetry.make_symmetric_system(spec, symmetry.operations(spec.point_group), with_V=False)
+        system.V_dev = dgen.make_symmetric_V(spec, symmetry.operations(spec.point_group), device="cuda:0")
+        if args.v_half:
+            system.V_dev = system.V_dev[canon].contiguous()
+    else:
+        system = systems.make_system(spec, with_V=False)
+        # generated in HBM (same draws as the host generator)
+        system.V_dev = dgen.make_V(spec, device="cuda:0", qs=canon if args.v_half else None)
+    system.v_half = bool(args.v_half)
     torch.cuda.synchronize()
     print(f"[bench] {spec.name}: V ({system.V_dev.numel() * 16 / 1e9:.1f} GB) generated on the device in "
           f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
@@ -724,7 +743,8 @@ def main():
         "config": {"workload": spec.name, "nk": spec.nk, "kmesh": list(spec.kmesh), "nao": spec.nao,
                    "naux": spec.naux, "ntau": spec.ntau, "nspin": spec.nspin, "beta": spec.beta,
                    "precision": head, "tuned": bool(args.tune), "graph": bool(args.graph),
-                   "time_reversal": time_reversal_symmetric(spec), "v_half_store": bool(args.v_half)},
+                   "time_reversal": time_reversal_symmetric(spec), "point_group": spec.point_group or None,
+                   "v_half_store": bool(args.v_half)},
         "flop_basis": "algorithmic: both contractions over every q, k and tau (4M counting)",
         "executed_tflops": round(h["sigma_eval_tflops"] * executed_fraction(spec), 4),
         "s_per_iteration": round(h["s_per_iteration"], 6),

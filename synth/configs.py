@@ -23,6 +23,10 @@ PERIODIC_3 = SystemSpec("periodic_k3x3x3_nao52_naux300_ntau136", (3, 3, 3), nao=
 # as in a non-magnetic crystal
 PERIODIC_3_TR = SystemSpec("periodic_k3x3x3_nao52_naux300_ntau136_tr", (3, 3, 3), nao=52, naux=300, ntau=136,
                            beta=100.0, seed=18481, v_time_reversal=True)
+# the 3x3x3 shapes on inputs invariant under the full cubic group (orbitals transforming trivially): the plan
+# contracts 4 of the 27 momenta in each stage
+PERIODIC_3_OH = SystemSpec("periodic_k3x3x3_nao52_naux300_ntau136_oh", (3, 3, 3), nao=52, naux=300, ntau=136,
+                           beta=100.0, seed=18481, point_group="Oh")
 LARGE_4 = SystemSpec("periodic_k4x4x4_nao78_naux420_ntau160_uhf", (4, 4, 4), nao=78, naux=420, ntau=160,
                      beta=200.0, nspin=2, seed=18483)
 
@@ -51,5 +55,5 @@ def tiny(kmesh=(1, 1, 1), nao=3, naux=4, ntau=8, beta=10.0, nspin=1, seed=7, **k
                       ntau=ntau, beta=beta, nspin=nspin, seed=seed, **kw)
 
 
-__all__ = ["CONFIGS", "MOLECULE", "PERIODIC_2", "PERIODIC_3", "LARGE_4", "batch_specs", "tiny",
+__all__ = ["CONFIGS", "MOLECULE", "PERIODIC_2", "PERIODIC_3", "PERIODIC_3_OH", "LARGE_4", "batch_specs", "tiny",
            "np"]

@@ -118,6 +118,30 @@ def make_V(spec: SystemSpec, device="cuda:0", out: torch.Tensor | None = None, q
     return out
 
 
+def make_symmetric_V(spec: SystemSpec, ops, device="cuda:0") -> torch.Tensor:
+    """V of synth.symmetry.make_symmetric_system generated on `device`: the blocks of make_V averaged over the
+    whole group the operations generate (V'^{k1,k2} = mean over R of V^{R k1, R k2}) and rescaled to the norm V had
+    before (equal to the host construction up to summation order)."""
+    from .symmetry import group_closure
+    V = make_V(spec, device=device)
+    nk = spec.nk
+    add = torch.as_tensor(k_add_table(spec.kmesh), device=device)  # add[k, q] = k + q
+    sub = torch.as_tensor(k_sub_table(spec.kmesh), device=device)  # sub[k, q] = k - q
+    ks = torch.arange(nk, device=device)
+    norm0 = torch.linalg.vector_norm(V)
+    acc = torch.zeros_like(V)
+    for g in group_closure(spec.kmesh, ops):
+        gt = torch.as_tensor(g, device=device)
+        # slab [q][k] holds the pair (k, k + q); its image (g k, g(k + q)) sits at [g(k + q) - g k][g k]
+        k1 = gt[ks][None, :].expand(nk, nk)                 # [q][k] -> g k
+        k2 = gt[add[ks][:, :].T]                            # [q][k] -> g(k + q)
+        qi = sub[k2, k1]                                     # g(k + q) - g k
+        acc += V[qi, k1]
+    acc *= norm0 / torch.linalg.vector_norm(acc)
+    del V
+    return acc
+
+
 def random_polarization(seed: int, nk: int, ntau: int, naux: int, scale: float = 0.05, device="cuda:0"):
     """Device twin of synth.systems.random_polarization (same counter streams)."""
     P = torch.empty((nk, ntau, naux, naux), dtype=torch.complex128, device=device)

@@ -40,6 +40,11 @@ def threefold_group() -> list[np.ndarray]:
     return [np.eye(3, dtype=np.int32), c, c @ c]
 
 
+def operations(name: str) -> list[np.ndarray]:
+    """The operations of a named group ("Oh", "C3"; "" gives none)."""
+    return {"": lambda: [], "Oh": cubic_group, "C3": threefold_group}[name]()
+
+
 def act(kmesh, R: np.ndarray) -> np.ndarray:
     """The permutation k -> R k of the flat mesh indices."""
     m = np.asarray(kmesh)
@@ -92,9 +97,10 @@ def _orbit_hermitian(spec: SystemSpec, tag: int, spin: int, k: int, lab, neg, lo
     return random_hermitian_spectrum(spec.seed, tag, spin, k, spec.nao, lo, hi, real)
 
 
-def make_symmetric_system(spec: SystemSpec, ops) -> System:
+def make_symmetric_system(spec: SystemSpec, ops, with_V: bool = True) -> System:
     """A system invariant under the point group the operations generate (plus time reversal when the spec asks
-    for it): H0 and S constant on orbits; V averaged over the group and rescaled to its former norm."""
+    for it): H0 and S constant on orbits; V averaged over the group and rescaled to its former norm (with_V=False:
+    V is left to synth.device.make_symmetric_V)."""
     nk, nao, ns = spec.nk, spec.nao, spec.nspin
     lab = orbit_labels(spec.kmesh, ops)
     neg = k_neg(spec.kmesh)
@@ -108,6 +114,11 @@ def make_symmetric_system(spec: SystemSpec, ops) -> System:
         for k in range(nk):
             Sh[k] = _orbit_hermitian(spec, rng.TAG_S, 0, k, lab, neg, -1.0, 1.0, Sh, spec.f_time_reversal)
     S = np.eye(nao)[None] + 0.1 * Sh
+    grid = make_grid(spec.ntau, spec.beta)
+    G0 = noninteracting_G(H0, S, grid.tau, spec.beta, spec.mu0)
+    n_target = electron_count(H0, S, spec.beta, spec.mu0)
+    if not with_V:
+        return System(spec, grid, H0, S, None, G0, n_target, spec.mu0)
     # V: Hermitian pairing and (optionally) time reversal first, then the group average, which keeps both
     full = {}
     for k1 in range(nk):
@@ -131,7 +142,4 @@ def make_symmetric_system(spec: SystemSpec, ops) -> System:
     for q in range(nk):
         for k in range(nk):
             V[q, k] = avg[(k, int(add[k, q]))] * (norm0 / norm1)
-    grid = make_grid(spec.ntau, spec.beta)
-    G0 = noninteracting_G(H0, S, grid.tau, spec.beta, spec.mu0)
-    n_target = electron_count(H0, S, spec.beta, spec.mu0)
     return System(spec, grid, H0, S, V, G0, n_target, spec.mu0)

@@ -115,6 +115,7 @@ class SystemSpec:
     v_time_reversal: bool = False  # impose V^{-k1,-k2}(Q) = conj V^{k1,k2}(Q)
     s_identity: bool = True  # S = I, else I + 0.1 * (random Hermitian of unit norm)
     mu0: float = 0.0
+    point_group: str = ""  # "" (none), "Oh" or "C3": inputs invariant under that group (synth.symmetry)
 
     @property
     def nk(self) -> int:

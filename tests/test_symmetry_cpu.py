@@ -201,3 +201,16 @@ def test_symmetry_launches_in_bounds(lib, case, prec, trev):
                                       None) == 0
     finally:
         lib.LIB.green_plan_destroy(h)
+
+
+@pytest.mark.parametrize("group,seed", [("Oh", 5), ("C3", 6)])
+def test_device_generator_matches_host(group, seed):
+    """synth.device.make_symmetric_V (the bench's generator, run here with torch on the CPU) builds the same V as
+    the host generator: the same draws averaged over the same group, to rounding."""
+    torch = pytest.importorskip("torch")
+    from synth import device
+    sp = configs.tiny(kmesh=(3, 3, 3), nao=3, naux=4, ntau=8, beta=8.0, seed=seed, v_scale=0.3)
+    h = sym.make_symmetric_system(sp, GROUPS[group]())
+    d = device.make_symmetric_V(sp, GROUPS[group](), device="cpu").numpy()
+    assert _rel(d, h.V) <= 1e-13
+    assert torch is not None
