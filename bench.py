@@ -418,6 +418,10 @@ KERNEL_NAME = {"fp64": "zgemm_f64_kernel<2,2,Site::P0_Contract>",
 # large tiles of the split-BF16 kernel by its `big` selector: (FM, FN) of a 64 FM x 32 FN tile
 BIG_TILE = {1: (3, 3), 2: (3, 2), 3: (5, 2), 4: (7, 2)}
 DMA_TILE = {5: (5, 2), 6: (3, 4)}  # the LDS-DMA kernel's tiles
+# the LDS-DMA kernel with fragments read ahead: (FM, FN, WGM, NS, NW) template arguments by `big`, and the
+# register-staged tile it falls back to when a K map is not flat or of an extent that is a multiple of 16
+READ_AHEAD = {7: (5, 2, 4, 3, 8), 8: (4, 2, 2, 4, 8), 9: (4, 2, 4, 4, 8), 10: (4, 2, 2, 3, 4), 11: (4, 2, 1, 3, 4)}
+READ_AHEAD_FALLBACK = {7: 3, 8: 1, 9: 2, 10: 2, 11: 2}
 
 
 def default_big(site: str, naux: int) -> int:
@@ -453,13 +457,18 @@ def clocked_kernel_name(site: str, prec: str, report: str, naux: int, nao: int) 
     _, M, N, shape, big = best
     # Sigma~ stage 1 reads an N-contiguous V slab unless naux is even (then a transposed one)
     bnc = "true" if site == "Sig_PV" and naux % 2 else "false"
+    quad = site == "Sig_PV" and naux % 4 == 0  # operands in groups of 4 (hi, then lo words)
+    if prec == "bf16x3" and big in READ_AHEAD:
+        # K maps: Sigma~ stage 1 runs over Q (flat), the P~0 sum over (k, orbital pair) blocks of nao^2
+        if site == "Sig_PV" or (nao * nao) % 16 == 0:
+            return "zgemm_bq_kernel<{},{},{},{},{},{},Site::{}>".format(*READ_AHEAD[big], "true" if quad else "false",
+                                                                       site)
+        big = READ_AHEAD_FALLBACK[big]
     if prec == "bf16x3" and big in BIG_TILE:
         fm, fn = BIG_TILE[big]
         return f"zgemm_bt_kernel<{fm},{fn},{bnc},Site::{site}>"
     if prec == "bf16x3" and big in DMA_TILE:
         fm, fn = DMA_TILE[big]
-        # operands in groups of 4 (hi, then lo words) where the contraction extent allows it
-        quad = site == "Sig_PV" and naux % 4 == 0
         return f"zgemm_bd_kernel<{fm},{fn},{'true' if quad else 'false'},Site::{site}>"
     wm, wn = ((shape - 1) // 2 + 1, (shape - 1) % 2 + 1) if 1 <= shape <= 4 else (1 if M <= 32 else 2,
                                                                                     1 if N <= 32 else 2)
