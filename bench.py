@@ -422,6 +422,9 @@ DMA_TILE = {5: (5, 2), 6: (3, 4)}  # the LDS-DMA kernel's tiles
 # register-staged tile it falls back to when a K map is not flat or of an extent that is a multiple of 16
 READ_AHEAD = {7: (5, 2, 4, 3, 8), 8: (4, 2, 2, 4, 8), 9: (4, 2, 4, 4, 8), 10: (4, 2, 2, 3, 4), 11: (4, 2, 1, 3, 4)}
 READ_AHEAD_FALLBACK = {7: 3, 8: 1, 9: 2, 10: 2, 11: 2}
+# the LDS-DMA kernel with 32-K stages in a two-slot ring: (FM, FN) by `big`, register-staged fallback
+DEEP_K = {12: (2, 4), 13: (4, 2)}
+DEEP_K_FALLBACK = {12: 1, 13: 2}
 
 
 def default_big(site: str, naux: int) -> int:
@@ -464,6 +467,10 @@ def clocked_kernel_name(site: str, prec: str, report: str, naux: int, nao: int) 
             return "zgemm_bq_kernel<{},{},{},{},{},{},Site::{}>".format(*READ_AHEAD[big], "true" if quad else "false",
                                                                        site)
         big = READ_AHEAD_FALLBACK[big]
+    if prec == "bf16x3" and big in DEEP_K:
+        if site == "Sig_PV" or nao * nao >= 32:
+            return "zgemm_bk_kernel<{},{},{},Site::{}>".format(*DEEP_K[big], "true" if quad else "false", site)
+        big = DEEP_K_FALLBACK[big]
     if prec == "bf16x3" and big in BIG_TILE:
         fm, fn = BIG_TILE[big]
         return f"zgemm_bt_kernel<{fm},{fn},{bnc},Site::{site}>"

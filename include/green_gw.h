@@ -290,7 +290,9 @@ int green_gw_iterate_diis(green_plan* plan, const void* V, const void* H0, const
  *                   6 = 192 x 128 fed by LDS DMA (even nao; else as 3 and 1); 7 = 320 x 64, 8 = 128 x 128,
  *                   9 = 256 x 64 fed by LDS DMA with the next K stage's operands read ahead, 10 = 128 x 64 and
  *                   11 = 64 x 128 the same with 4 waves, two workgroups per CU (K blocks of a multiple of 16;
- *                   else 7 and 10 as 3, 8 and 11 as 1, 9 as 2).  The plan starts with the tile that pads naux x naux
+ *                   else 7 as 3, 8 as 1, 9 to 11 as 2), 12 = 128 x 128 and 13 = 256 x 64 fed by LDS DMA in stages
+ *                   of 32 complex K through a two-slot ring (half the barriers per flop; K blocks of at least 32,
+ *                   else 12 as 1, 13 as 2).  The plan starts with the tile that pads naux x naux
  *                   least (192 x 96 counted at 90% of its area), 320 x 64 on the LDS-DMA kernel.
  *   GREEN_OPT_SIGMA_TILE  split-BF16 plans: tile of the first Sigma~ contraction, P~(tau)^T V over the auxiliary
  *                   index (values as GREEN_OPT_P0_TILE; default 6).

@@ -399,6 +399,8 @@ std::vector<TuneCand> tune_candidates(const ZGemm& g0) {
     add(0, 9);
     add(0, 10);
     add(0, 11);
+    // (the 32-K-stage tiles 12 and 13 are plan options only: measured slower than the 16-K ring on the
+    // contractions here, they would only lengthen tuning)
   }
   add(0, 0);
   add(4, 0);
@@ -2266,12 +2268,12 @@ int green_plan_set_option(green_plan* p, int option, int value) {
       if (!value) drop_graph(p);
       return GREEN_OK;
     case GREEN_OPT_P0_TILE:
-      if (value < 1 || value > 11) return GREEN_EINVAL;
+      if (value < 1 || value > 13) return GREEN_EINVAL;
       p->big_p0 = value;
       drop_graph(p);
       return GREEN_OK;
     case GREEN_OPT_SIGMA_TILE:
-      if (value < 1 || value > 11) return GREEN_EINVAL;
+      if (value < 1 || value > 13) return GREEN_EINVAL;
       p->big_sig = value;
       drop_graph(p);
       return GREEN_OK;

@@ -95,7 +95,9 @@ struct ZGemm {
                   // 3 = 320 x 64, 4 = 448 x 64 (3 and 4 need a K-contiguous B); LDS-DMA kernel (K-contiguous
                   // A and B, even K and strides, else as 3 and 1): 5 = 320 x 64, 6 = 192 x 128; LDS-DMA kernel
                   // with prefetched fragments (K maps flat or of extent a multiple of 16, else as 3, 1 and 2):
-                  // 7 = 320 x 64, 8 = 128 x 128, 9 = 256 x 64
+                  // 7 = 320 x 64, 8 = 128 x 128, 9 = 256 x 64, 10 = 128 x 64, 11 = 64 x 128 (two per CU);
+                  // LDS-DMA kernel with 32-K stages in two slots (K maps flat or of extent >= 32, else as 1 and
+                  // 2): 12 = 128 x 128, 13 = 256 x 64
   int32_t shape;  // 256-thread kernels: 0 = by size, 1..4 = 32x32, 32x64, 64x32, 64x64 tiles
   int32_t band;   // large-tile kernel: 0 = output tiles in column order; b > 0 = bands of b tile rows,
                   // each walked column by column (the A rows of a band stay in L2)
@@ -103,7 +105,8 @@ struct ZGemm {
 
 // Kernel variant a descriptor launches: family 0 FP64, 1 FP32, 2 split BF16 (256 threads), 3 split BF16
 // large tiles (512 threads), 4 LDS-DMA large tiles (512 threads), 5 LDS-DMA large tiles with prefetched
-// fragments (512 threads); tile (bm, bn) = (32 p1, 32 p2), (64 p1, 32 p2) for families 3 and 4.
+// fragments (512 or 256 threads), 6 LDS-DMA large tiles with 32-K stages (512 threads); tile (bm, bn) =
+// (32 p1, 32 p2), (64 p1, 32 p2) for families 3, 4 and 6.
 struct Variant {
   int32_t family, p1, p2;  // family -1: no kernel reads these operands
   bool bnc;   // family 3: B is N-contiguous

@@ -966,7 +966,11 @@ __device__ __forceinline__ void bt_body(const ZGemm& g, int64_t bid0, int64_t nb
 // (columns) beyond M (N) read row M-1 (column N-1); chunks past the slice's K end read the stage's
 // first chunk and are zeroed in LDS once landed.  Requirements (checked on the host): K even, K maps
 // flat or with an even extent of at least 16, even element strides, 16-byte aligned operands.
-constexpr int kDmaStages = 3;
+//
+// Variant with stages of 32 complex K (BK = 32) and a two-slot ring (NS = 2): rows of 16 chunks (256 bytes,
+// slot c ^ (r & 15)), four rows per DMA instruction, two MFMA K steps per barrier (half the barriers and
+// waits per flop); the copies of stage t + 1 are issued after the barrier that opens stage t, so one stage of
+// 32 K hides their latency.  K maps must be flat or of an extent of at least 32.
 
 // wait until at most N vector-memory operations of this wave are outstanding (loads return in order)
 template <int N>
@@ -988,14 +992,25 @@ __device__ __forceinline__ void dma16(const void* src, uint32_t* lds) {
                                    0);
 }
 
-template <int FM, int FN, bool Q>
+template <int BK>
+__device__ __forceinline__ int bd_slot_k(int r, int c) {
+  if constexpr (BK == 16) return c ^ row_xor(r);
+  else return c ^ (r & 15);
+}
+
+template <int FM, int FN, bool Q, int BK, int NS>
 __device__ __forceinline__ void bd_body(const ZGemm& g, int64_t bid0, int64_t nblk) {
-  constexpr int BM = 64 * FM, BN = 32 * FN, BK = 16;
-  constexpr int DA = BM / 64, DB = BN / 64;  // DMA instructions per wave and stage
-  static_assert(BN % 64 == 0, "B tile of whole DMA groups");
+  constexpr int BM = 64 * FM, BN = 32 * FN;
+  static_assert((BK == 16 && NS == 3) || (BK == 32 && NS == 2), "16-K stages in three slots or 32-K in two");
+  constexpr int CPR = BK / 2;               // 16-byte chunks per LDS row
+  constexpr int RPD = 64 / CPR;             // LDS rows per DMA instruction (1 KB)
+  constexpr int W = 2 * BK;                 // 32-bit words per LDS row
+  constexpr int DA = BM / RPD / 8, DB = BN / RPD / 8;  // DMA instructions per wave and stage
+  static_assert(DB * RPD * 8 == BN && DA * RPD * 8 == BM, "tiles of whole DMA groups");
   constexpr int D = DA + DB;
-  __shared__ __attribute__((aligned(16))) uint32_t A0[BM * 32], A1[BM * 32], A2[BM * 32];
-  __shared__ __attribute__((aligned(16))) uint32_t B0[BN * 32], B1[BN * 32], B2[BN * 32];
+  static_assert(NS * (BM + BN) * W * 4 <= 160 * 1024, "ring fits the LDS");
+  __shared__ __attribute__((aligned(16))) uint32_t A0[BM * W], A1[BM * W], A2[NS == 3 ? BM * W : 4];
+  __shared__ __attribute__((aligned(16))) uint32_t B0[BN * W], B1[BN * W], B2[NS == 3 ? BN * W : 4];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -1011,19 +1026,22 @@ __device__ __forceinline__ void bd_body(const ZGemm& g, int64_t bid0, int64_t nb
   const uint2* __restrict__ Ap = reinterpret_cast<const uint2*>(g.A.p) + batch_off(g.A.b, batch);
   const uint2* __restrict__ Bp = reinterpret_cast<const uint2*>(g.B.p) + batch_off(g.B.b, batch);
   // per lane and DMA instruction: row (column) offset and the chunk it carries
-  int64_t a_ro[DA], b_co[DB];
+  // (32-K stages: twice the copies per stage, so the per-copy offsets are kept in 32 bits; the host allows those
+  // tiles only where every element offset of an operand's batch slice fits)
+  using off_t = typename std::conditional<BK == 32, int32_t, int64_t>::type;
+  off_t a_ro[DA], b_co[DB];
   int a_c[DA], b_c[DB];
 #pragma unroll
   for (int j = 0; j < DA; ++j) {
-    const int r = 8 * (wave * DA + j) + (lane >> 3);
+    const int r = RPD * (wave * DA + j) + lane / CPR;
     a_ro[j] = map_idx(g.A.r, min(m0 + r, g.M - 1));
-    a_c[j] = bd_slot(r, lane & 7);
+    a_c[j] = bd_slot_k<BK>(r, lane % CPR);
   }
 #pragma unroll
   for (int j = 0; j < DB; ++j) {
-    const int r = 8 * (wave * DB + j) + (lane >> 3);
+    const int r = RPD * (wave * DB + j) + lane / CPR;
     b_co[j] = map_idx(g.B.c, min(n0 + r, g.N - 1));
-    b_c[j] = bd_slot(r, lane & 7);
+    b_c[j] = bd_slot_k<BK>(r, lane % CPR);
   }
   // stage K cursors (uniform): offset of the stage's first complex under each K map
   KCur acur, bcur;
@@ -1045,7 +1063,7 @@ __device__ __forceinline__ void bd_body(const ZGemm& g, int64_t bid0, int64_t nb
   // checks: each lane adds its fixed chunk offset to the stage's uniform one.
   const bool a_whole = g.A.c.ext == kFlat || g.A.c.ext % BK == 0;
   const bool b_whole = g.B.r.ext == kFlat || g.B.r.ext % BK == 0;
-  int64_t a_lane[DA], b_lane[DB];
+  off_t a_lane[DA], b_lane[DB];
 #pragma unroll
   for (int j = 0; j < DA; ++j) a_lane[j] = a_ro[j] + 2 * a_c[j];
 #pragma unroll
@@ -1084,10 +1102,10 @@ __device__ __forceinline__ void bd_body(const ZGemm& g, int64_t bid0, int64_t nb
   const int wm = wave & 3, wn = wave >> 2;
   const int rowb = wm * 16 * FM, colb = wn * 16 * FN;
   const int g4 = lane >> 4, r16 = lane & 15;
-  // hi and lo words of this lane's 4 complex K (chunks 2 g4 and 2 g4 + 1) of LDS row r
-  auto frag = [&](const uint32_t* P, int r, u4& hi, u4& lo) {
-    const u4 x = *reinterpret_cast<const u4*>(P + r * 32 + 4 * bd_slot(r, 2 * g4));
-    const u4 y = *reinterpret_cast<const u4*>(P + r * 32 + 4 * bd_slot(r, 2 * g4 + 1));
+  // hi and lo words of this lane's 4 complex K of MFMA step ks (chunks 8 ks + 2 g4 and + 1) of LDS row r
+  auto frag = [&](const uint32_t* P, int r, int ks, u4& hi, u4& lo) {
+    const u4 x = *reinterpret_cast<const u4*>(P + r * W + 4 * bd_slot_k<BK>(r, 8 * ks + 2 * g4));
+    const u4 y = *reinterpret_cast<const u4*>(P + r * W + 4 * bd_slot_k<BK>(r, 8 * ks + 2 * g4 + 1));
     if constexpr (Q) {
       hi = x;
       lo = y;
@@ -1097,13 +1115,15 @@ __device__ __forceinline__ void bd_body(const ZGemm& g, int64_t bid0, int64_t nb
     }
   };
   auto compute = [&](const uint32_t* As, const uint32_t* Bs) {
+#pragma unroll
+    for (int ks = 0; ks < BK / 16; ++ks) {
     u4 bh[FN], bl[FN];
 #pragma unroll
-    for (int j = 0; j < FN; ++j) frag(Bs, colb + 16 * j + r16, bh[j], bl[j]);
+    for (int j = 0; j < FN; ++j) frag(Bs, colb + 16 * j + r16, ks, bh[j], bl[j]);
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
       u4 ah, al;
-      frag(As, rowb + 16 * i + r16, ah, al);
+      frag(As, rowb + 16 * i + r16, ks, ah, al);
       const bf8 anh = as_bf8(neg_im(ah)), anl = as_bf8(neg_im(al));
       const bf8 aph = as_bf8(ah), apl = as_bf8(al);
 #pragma unroll
@@ -1118,22 +1138,28 @@ __device__ __forceinline__ void bd_body(const ZGemm& g, int64_t bid0, int64_t nb
         acc_im[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(apl, bsh, acc_im[i][j], 0, 0, 0);
       }
     }
+    // (two K steps per stage: the second step's reads are not hoisted over the first step's MFMAs, where
+    // both steps' fragments together would not fit the registers)
+    if constexpr (BK == 32) __builtin_amdgcn_sched_barrier(0);
+    }
   };
   // chunks past the slice's K end in a landed stage -> 0 (every row of both tiles)
   const int kvalid_last = (kend - kbeg) - BK * (nkt - 1);  // complex K of the last stage, even
   auto zero_tail = [&](uint32_t* As, uint32_t* Bs) {
-    for (int x = tid; x < (BM + BN) * 8; x += 512) {
-      const int r = x >> 3, c = x & 7;
+    for (int x = tid; x < (BM + BN) * CPR; x += 512) {
+      const int r = x / CPR, c = x % CPR;
       if ((Q ? 4 * (c >> 1) : 2 * c) < kvalid_last) continue;
-      uint32_t* P = r < BM ? As + r * 32 : Bs + (r - BM) * 32;
+      uint32_t* P = r < BM ? As + r * W : Bs + (r - BM) * W;
       const int rr = r < BM ? r : r - BM;
-      *reinterpret_cast<u4*>(P + 4 * bd_slot(rr, c)) = u4{0u, 0u, 0u, 0u};
+      *reinterpret_cast<u4*>(P + 4 * bd_slot_k<BK>(rr, c)) = u4{0u, 0u, 0u, 0u};
     }
   };
   // one stage: own copies landed -> barrier (all copies landed, previous stage's buffer free) -> issue
   // stage t + 2 into that buffer -> MFMA
+  // (NS = 2: own copies of stage t landed, nothing later in flight -> barrier -> issue stage t + 1 into the
+  // slot stage t - 1 used -> MFMA)
   auto step = [&](uint32_t* As, uint32_t* Bs, uint32_t* An, uint32_t* Bn, int t) {
-    if (t + 1 < nkt) wait_vm<D>();
+    if (NS == 3 && t + 1 < nkt) wait_vm<D>();
     else wait_vm<0>();
     if (t == nkt - 1 && kvalid_last < BK) {
       __syncthreads();
@@ -1142,16 +1168,23 @@ __device__ __forceinline__ void bd_body(const ZGemm& g, int64_t bid0, int64_t nb
     } else {
       barrier_only();
     }
-    if (t + 2 < nkt) issue(An, Bn);
+    if (t + NS - 1 < nkt) issue(An, Bn);
     compute(As, Bs);
   };
   if (nkt > 0) {
     issue(A0, B0);
-    if (nkt > 1) issue(A1, B1);
-    for (int it = 0; it < nkt; it += kDmaStages) {
-      step(A0, B0, A2, B2, it);
-      if (it + 1 < nkt) step(A1, B1, A0, B0, it + 1);
-      if (it + 2 < nkt) step(A2, B2, A1, B1, it + 2);
+    if constexpr (NS == 3) {
+      if (nkt > 1) issue(A1, B1);
+      for (int it = 0; it < nkt; it += 3) {
+        step(A0, B0, A2, B2, it);
+        if (it + 1 < nkt) step(A1, B1, A0, B0, it + 1);
+        if (it + 2 < nkt) step(A2, B2, A1, B1, it + 2);
+      }
+    } else {
+      for (int it = 0; it < nkt; it += 2) {
+        step(A0, B0, A1, B1, it);
+        if (it + 1 < nkt) step(A1, B1, A0, B0, it + 1);
+      }
     }
   }
   // every wave is done with the LDS stages before any wave of a persistent group starts another tile
@@ -1732,7 +1765,12 @@ __global__ __launch_bounds__(512) void zgemm_bt_kernel(const ZGemm g) {
 }
 template <int FM, int FN, bool Q, Site SITE>
 __global__ __launch_bounds__(512) void zgemm_bd_kernel(const ZGemm g) {
-  bd_body<FM, FN, Q>(g, blockIdx.x, gridDim.x);
+  bd_body<FM, FN, Q, 16, 3>(g, blockIdx.x, gridDim.x);
+}
+// 32-K stages, two-slot ring
+template <int FM, int FN, bool Q, Site SITE>
+__global__ __launch_bounds__(512) void zgemm_bk_kernel(const ZGemm g) {
+  bd_body<FM, FN, Q, 32, 2>(g, blockIdx.x, gridDim.x);
 }
 template <int FM, int FN, int WGM, int NS, int NW, bool Q, Site SITE>
 __global__ __launch_bounds__(64 * NW, NW == 4 ? 2 : 1) void zgemm_bq_kernel(const ZGemm g) {
@@ -1771,7 +1809,11 @@ __global__ __launch_bounds__(512) void zgemm_bt_group(const GroupArgs a) {
 }
 template <int FM, int FN, bool Q>
 __global__ __launch_bounds__(512) void zgemm_bd_group(const GroupArgs a) {
-  group_loop(a, [](const ZGemm& g, int64_t b, int64_t n) { bd_body<FM, FN, Q>(g, b, n); });
+  group_loop(a, [](const ZGemm& g, int64_t b, int64_t n) { bd_body<FM, FN, Q, 16, 3>(g, b, n); });
+}
+template <int FM, int FN, bool Q>
+__global__ __launch_bounds__(512) void zgemm_bk_group(const GroupArgs a) {
+  group_loop(a, [](const ZGemm& g, int64_t b, int64_t n) { bd_body<FM, FN, Q, 32, 2>(g, b, n); });
 }
 template <int FM, int FN, int WGM, int NS, int NW, bool Q>
 __global__ __launch_bounds__(64 * NW, NW == 4 ? 2 : 1) void zgemm_bq_group(const GroupArgs a) {
@@ -2026,7 +2068,7 @@ static int64_t map_extent(const IdxMap& m, int64_t n) {
   return (std::min<int64_t>(m.ext, n) - 1) * std::abs(m.s_in) + ((n - 1) / m.ext) * std::abs(m.s_out);
 }
 static bool dma_ok(const ZGemm& g) {
-  if (g.big < 5 || g.big > 11) return false;
+  if (g.big < 5 || g.big > 13) return false;
   // the prefetching kernel forms byte offsets from the operand's batch base in 32 bits: non-negative strides
   // and element offsets (row or column plus K) below 2^29
   if (g.big >= 7) {
@@ -2042,8 +2084,10 @@ static bool dma_ok(const ZGemm& g) {
   if ((g.A.etype != kCB16 && !q) || g.B.etype != g.A.etype || g.A.conj || g.B.conj) return false;
   const int u = q ? 4 : 2;  // K granule of one 16-byte copy
   if (g.A.c.s_in != 1 || g.B.r.s_in != 1 || g.K % u != 0) return false;
+  // (a K stage meets at most one wrap of a two-level K map: extents of at least the stage depth)
+  const int kdepth = g.big >= 12 ? 32 : 16;
   for (const IdxMap* m : {&g.A.c, &g.B.r})
-    if (m->ext != kFlat && (m->ext % u != 0 || m->ext < 16 || m->s_out % u != 0)) return false;
+    if (m->ext != kFlat && (m->ext % u != 0 || m->ext < kdepth || m->s_out % u != 0)) return false;
   if (!even_map(g.A.r) || !even_map(g.B.c) || !even_batch(g.A.b) || !even_batch(g.B.b)) return false;
   if (q && (!quad_map(g.A.r) || !quad_map(g.B.c) || g.A.b.s_lo % 4 || g.A.b.s_hi % 4 || g.B.b.s_lo % 4 ||
             g.B.b.s_hi % 4))
@@ -2055,9 +2099,10 @@ static bool dma_ok(const ZGemm& g) {
 // next stage's fragments prefetched: 7 = 320 x 64 (4 x 2 waves of 5 x 2 blocks, three-slot ring), 8 = 128 x 128
 // (2 x 4 waves of 4 x 2 blocks, four-slot ring), 9 = 256 x 64 (4 x 2 waves of 4 x 2 blocks, four-slot ring);
 // 256 threads, two workgroups per CU, three-slot ring: 10 = 128 x 64 (2 x 2 waves of 4 x 2 blocks), 11 = 64 x 128
-// (1 x 4 waves of 4 x 2 blocks).
+// (1 x 4 waves of 4 x 2 blocks); stages of 32 complex K in a two-slot ring (512 threads, 4 x 2 waves): 12 = 128 x 128,
+// 13 = 256 x 64.
 static void dma_tile(int big, int* fm, int* fn) {
-  static const int t[7][2] = {{5, 2}, {3, 4}, {5, 2}, {4, 2}, {4, 2}, {4, 2}, {4, 2}};
+  static const int t[9][2] = {{5, 2}, {3, 4}, {5, 2}, {4, 2}, {4, 2}, {4, 2}, {4, 2}, {2, 4}, {4, 2}};
   *fm = t[big - 5][0];
   *fn = t[big - 5][1];
 }
@@ -2068,7 +2113,7 @@ static void dma_tile(int big, int* fm, int* fn) {
 Variant zgemm_variant(const ZGemm& g) {
   Variant v{};
   if (g.prec == 2 && dma_ok(g)) {
-    v.family = g.big >= 7 ? 5 : 4;
+    v.family = g.big >= 12 ? 6 : g.big >= 7 ? 5 : 4;
     dma_tile(g.big, &v.p1, &v.p2);
     v.bnc = false;
     v.quad = g.A.etype == kCB16Q;
@@ -2092,9 +2137,10 @@ Variant zgemm_variant(const ZGemm& g) {
     return v;
   }
   // an LDS-DMA tile the operands do not allow falls back to a register-staged one: 320 x 64 to the same
-  // tile, 192 x 128 to 192 x 96
+  // tile, 192 x 128 and 128 x 128 to 192 x 96, the rest to 192 x 64
   ZGemm gb = g;
-  if (gb.big >= 5) gb.big = (gb.big == 5 || gb.big == 7) ? 3 : (gb.big == 6 || gb.big == 8) ? 1 : 2;
+  if (gb.big >= 5)
+    gb.big = (gb.big == 5 || gb.big == 7) ? 3 : (gb.big == 6 || gb.big == 8 || gb.big == 12) ? 1 : 2;
   if (g.prec == 2 && big_ok(gb)) {
     v.family = 3;
     big_tile(gb.big, &v.p1, &v.p2);
@@ -2202,6 +2248,14 @@ void launch_bd(const ZGemm& g, dim3 grid, hipStream_t s) {
     default: zgemm_bd_kernel<FM, FN, Q, Site::Generic><<<grid, dim3(512), 0, s>>>(g); break;
   }
 }
+template <int FM, int FN, bool Q>
+void launch_bk(const ZGemm& g, dim3 grid, hipStream_t s) {
+  switch (g.site) {
+    case Site::P0_Contract: zgemm_bk_kernel<FM, FN, Q, Site::P0_Contract><<<grid, dim3(512), 0, s>>>(g); break;
+    case Site::Sig_PV: zgemm_bk_kernel<FM, FN, Q, Site::Sig_PV><<<grid, dim3(512), 0, s>>>(g); break;
+    default: zgemm_bk_kernel<FM, FN, Q, Site::Generic><<<grid, dim3(512), 0, s>>>(g); break;
+  }
+}
 
 void launch_single(const Variant& v, const ZGemm& g, dim3 grid, hipStream_t s) {
   const int sh = (v.p1 - 1) * 2 + (v.p2 - 1);
@@ -2231,6 +2285,15 @@ void launch_single(const Variant& v, const ZGemm& g, dim3 grid, hipStream_t s) {
       } else {
         if (v.quad) launch_bd<3, 4, true>(g, grid, s);
         else launch_bd<3, 4, false>(g, grid, s);
+      }
+      break;
+    case 6:
+      if (v.p1 == 4) {
+        if (v.quad) launch_bk<4, 2, true>(g, grid, s);
+        else launch_bk<4, 2, false>(g, grid, s);
+      } else {
+        if (v.quad) launch_bk<2, 4, true>(g, grid, s);
+        else launch_bk<2, 4, false>(g, grid, s);
       }
       break;
     case 5:
@@ -2287,6 +2350,15 @@ void launch_group(const Variant& v, const GroupArgs& a, dim3 grid, hipStream_t s
       } else {
         if (v.quad) zgemm_bd_group<3, 4, true><<<grid, b512, 0, s>>>(a);
         else zgemm_bd_group<3, 4, false><<<grid, b512, 0, s>>>(a);
+      }
+      break;
+    case 6:
+      if (v.p1 == 4) {
+        if (v.quad) zgemm_bk_group<4, 2, true><<<grid, b512, 0, s>>>(a);
+        else zgemm_bk_group<4, 2, false><<<grid, b512, 0, s>>>(a);
+      } else {
+        if (v.quad) zgemm_bk_group<2, 4, true><<<grid, b512, 0, s>>>(a);
+        else zgemm_bk_group<2, 4, false><<<grid, b512, 0, s>>>(a);
       }
       break;
     case 5:

@@ -76,7 +76,7 @@ def test_all_launches_in_bounds(lib, c, prec):
         lib.LIB.green_plan_destroy(h)
 
 
-@pytest.mark.parametrize("tiles", [(7, 7), (8, 8), (9, 9), (10, 10), (11, 11)])
+@pytest.mark.parametrize("tiles", [(7, 7), (8, 8), (9, 9), (10, 10), (11, 11), (12, 12), (13, 13)])
 @pytest.mark.parametrize("c", [CASES[1], CASES[3], CASES[4], CASES[6]],
                          ids=["k2x2x2", "k3x3x3", "k4x4x4", "nao17_ch1"])
 def test_read_ahead_tiles_in_bounds(lib, c, tiles):
@@ -137,13 +137,13 @@ def test_plan_options_and_tuning_report(lib):
         assert L.green_plan_set_option(h, lib.OPT_TUNE, 3) == -1
         assert L.green_plan_set_option(h, lib.OPT_GRAPH, 1) == 0
         assert L.green_plan_set_option(h, lib.OPT_GRAPH, 2) == -1
-        for v in range(1, 12):
+        for v in range(1, 14):
             assert L.green_plan_set_option(h, lib.OPT_P0_TILE, v) == 0
             assert L.green_plan_set_option(h, lib.OPT_SIGMA_TILE, v) == 0
         assert L.green_plan_set_option(h, lib.OPT_P0_TILE, 0) == -1
-        assert L.green_plan_set_option(h, lib.OPT_P0_TILE, 12) == -1
+        assert L.green_plan_set_option(h, lib.OPT_P0_TILE, 14) == -1
         assert L.green_plan_set_option(h, lib.OPT_SIGMA_TILE, 0) == -1
-        assert L.green_plan_set_option(h, lib.OPT_SIGMA_TILE, 12) == -1
+        assert L.green_plan_set_option(h, lib.OPT_SIGMA_TILE, 14) == -1
         for v in (0, 1, 2):
             assert L.green_plan_set_option(h, lib.OPT_STAGE1_TILE, v) == 0
         assert L.green_plan_set_option(h, lib.OPT_STAGE1_TILE, 3) == -1

@@ -68,11 +68,13 @@ def test_mixed_polarization_and_selfenergy(c, prec):
 
 
 @pytest.mark.parametrize("tile,nao", [(1, 10), (2, 10), (3, 10), (4, 10), (5, 10), (6, 10), (7, 10), (5, 12), (6, 12),
-                                      (7, 12), (8, 12), (9, 12), (10, 12), (11, 12)])
+                                      (7, 12), (8, 12), (9, 12), (10, 12), (11, 12), (12, 10), (13, 10), (12, 12),
+                                      (13, 12)])
 def test_split_bf16_p0_tiles(tile, nao):
     """Every output tile of the split-BF16 P~0 contraction (register-staged 192 x 96, 192 x 64, 320 x 64,
     448 x 64; LDS-DMA 320 x 64, 192 x 128; LDS-DMA with operands read a stage ahead 320 x 64, 128 x 128,
-    256 x 64, and two workgroups per CU 128 x 64, 64 x 128) on an naux that leaves ragged tiles along both P~0 dimensions, against the FP64 path.  nao = 10:
+    256 x 64, and two workgroups per CU 128 x 64, 64 x 128; LDS-DMA with 32-K stages 128 x 128, 256 x 64) on an
+    naux that leaves ragged tiles along both P~0 dimensions, against the FP64 path.  nao = 10:
     K = nk nao^2 = 200, whose orbital-pair blocks (100) and end fall inside 16-wide K stages (the read-ahead
     kernel then falls back to the register-staged one); nao = 12: blocks of 144 that are whole stages."""
     _require_gpu()
@@ -87,7 +89,7 @@ def test_split_bf16_p0_tiles(tile, nao):
     assert rel(Pmx, P64) <= REL["bf16x3"]
 
 
-@pytest.mark.parametrize("tile", [5, 6, 7, 8, 9, 10, 11])
+@pytest.mark.parametrize("tile", [5, 6, 7, 8, 9, 10, 11, 12, 13])
 @pytest.mark.parametrize("naux", [300, 52, 64, 70])
 def test_split_bf16_sigma_tiles(tile, naux):
     """Every LDS-DMA tile of the first split-BF16 Sigma~ contraction (P~^T V over the auxiliary index, K = naux)
