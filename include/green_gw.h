@@ -276,7 +276,8 @@ int green_gw_iterate_diis(green_plan* plan, const void* V, const void* H0, const
  *   GREEN_OPT_TUNE  1: autotune.  Every contraction shape met on later calls is run once with each of
  *                   its candidate kernels (tile shape, large-tile kernel, split-K count; every candidate
  *                   computes the same contraction, differing only in summation order), timed with HIP
- *                   events, and the fastest is kept for all further calls of that shape on this plan.
+ *                   events, and the fastest is kept for all further calls of that shape on this plan (the
+ *                   default unless a candidate is at least 3 % faster).
  *                   Synchronises `stream` once per shape when its last candidate has run.
  *                   2: forget earlier choices and tune again.  0: stop tuning (choices are kept).
  *   GREEN_OPT_GRAPH 1: green_gw_iterate captures its Sigma evaluation (Hartree-Fock, polarization,
