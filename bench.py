@@ -592,6 +592,7 @@ def run_batch(args):
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[head],
         "data": "synthetic",
+        "build": build_record(),
         "config": {"workload": "batch16_uneven_ntau104", "systems": [sp.name for sp in specs], "precision": head,
                    "graph": bool(args.graph), "tuned": bool(args.tune)},
         "s_per_iteration": round(h["s_per_iteration"], 6),
@@ -604,6 +605,16 @@ def run_batch(args):
         "roofline": None,
         "cpu_baseline": None,
     }
+def build_record() -> dict:
+    """Provenance of the HIP library this run loaded: the digest of the sources it was built from (the binding
+    refuses to load a library whose digest differs from the sources beside it), its target and HIP version."""
+    from paper_2406_18479_amd import _lib
+    rec = dict(kv.split("=", 1) for kv in _lib.BUILD_INFO.split())
+    rec["library"] = os.path.relpath(_lib.LIB_PATH, os.path.dirname(os.path.abspath(__file__)))
+    rec["sources_match"] = True
+    return rec
+
+
 # hardware MFMA products issued per algorithmic (4M) flop
 MFMA_PER_ALG = {"fp64": 1.0, "fp32": 1.0, "bf16x3": 3.0}
 
@@ -756,6 +767,7 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[head],
         "data": "synthetic",
+        "build": build_record(),
         "config": {"workload": spec.name, "nk": spec.nk, "kmesh": list(spec.kmesh), "nao": spec.nao,
                    "naux": spec.naux, "ntau": spec.ntau, "nspin": spec.nspin, "beta": spec.beta,
                    "precision": head, "tuned": bool(args.tune), "graph": bool(args.graph),

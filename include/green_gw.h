@@ -372,6 +372,12 @@ int green_plan_set_option(green_plan* plan, int option, int value);
 #define GREEN_MAX_KPOINT_OPS 192
 int green_plan_set_kpoint_symmetry(green_plan* plan, const int32_t* rot, int nops, int32_t* counts);
 
+/* Build provenance: a static NUL-terminated string "sources=<digest> arch=<gfx target> hip=<major.minor>", where
+ * <digest> is the first 16 hex digits of the SHA-256 of the library's source files (csrc/ in name order, then this
+ * header) as the in-tree build computed it.  The Python binding recomputes the digest from the sources beside the
+ * library and refuses to load a library built from other sources. */
+const char* green_build_info(void);
+
 /* Text table of the autotuner's decisions into buf (host, len bytes, NUL-terminated; GREEN_ENOMEM when
  * truncated): per contraction shape a line with the chosen kernel and, once tuned, a line with every
  * candidate's time as shape/large tile/split-K count/tile-row band=microseconds. */

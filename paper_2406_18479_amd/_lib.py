@@ -84,7 +84,7 @@ EXPORTS = ["green_plan_create", "green_plan_destroy", "green_workspace_bytes", "
            "green_gw_iterate_batched", "green_batch_create", "green_batch_iterate", "green_batch_destroy",
            "green_diis_history_bytes", "green_gw_iterate_diis", "green_kpath_interpolate",
            "green_gf2_selfenergy", "green_dyson_noalloc", "green_check_status", "green_plan_set_kpoint_symmetry",
-           "green_strerror"]
+           "green_build_info", "green_strerror"]
 
 NOALLOC_MAX_BYTES = 64 << 20  # GREEN_NOALLOC_MAX_BYTES
 MAX_KPOINT_OPS = 192  # GREEN_MAX_KPOINT_OPS
@@ -152,10 +152,26 @@ def _load():
     lib.green_gw_iterate_diis.restype = i32
     lib.green_strerror.argtypes = [i32]
     lib.green_strerror.restype = ctypes.c_char_p
+    lib.green_build_info.argtypes = []
+    lib.green_build_info.restype = ctypes.c_char_p
     return lib
 
 
 LIB = _load()
+BUILD_INFO = LIB.green_build_info().decode()
+
+
+def _check_provenance() -> None:
+    """The library must have been built from the sources beside it (a stale build would run other kernels)."""
+    from .build import source_digest
+    want = source_digest()
+    got = dict(kv.split("=", 1) for kv in BUILD_INFO.split()).get("sources")
+    if got != want:
+        raise ImportError(f"{LIB_PATH} was built from other sources (library {got}, sources {want}); rebuild with "
+                          "`python -m paper_2406_18479_amd.build`")
+
+
+_check_provenance()
 
 
 def _strerror(code: int) -> str:

@@ -22,6 +22,20 @@ FLAGS = [
 ]
 
 
+def source_digest() -> str:
+    """SHA-256 (first 16 hex digits) of the library's sources: every file under csrc/ and include/green_gw.h, in
+    name order.  Built into the library (green_build_info) and checked by the binding when it loads."""
+    import hashlib
+    h = hashlib.sha256()
+    inc = os.path.join(os.path.dirname(HERE), "include", "green_gw.h")
+    files = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".h"))) + [inc]
+    for path in files:
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def _hipcc() -> str:
     for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", "hipcc"):
         if c and (os.path.isabs(c) and os.path.exists(c) or not os.path.isabs(c)):
@@ -36,9 +50,11 @@ def build_library(verbose: bool = False) -> str:
     hipcc = _hipcc()
     objs = []
     procs = []
+    digest = source_digest()
     for src in SOURCES:
         obj = os.path.join(bdir, src.replace(".hip", ".o"))
-        cmd = [hipcc, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        extra = [f'-DGREEN_SOURCE_DIGEST="{digest}"', f'-DGREEN_TARGET_ARCH="{ARCH}"'] if src == "api.hip" else []
+        cmd = [hipcc, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

@@ -2381,6 +2381,19 @@ int green_plan_set_kpoint_symmetry(green_plan* p, const int32_t* rot, int nops, 
   return count_ops(p);
 }
 
+#ifndef GREEN_SOURCE_DIGEST
+#define GREEN_SOURCE_DIGEST "unknown"
+#endif
+#ifndef GREEN_TARGET_ARCH
+#define GREEN_TARGET_ARCH "unknown"
+#endif
+#define GREEN_STR2(x) #x
+#define GREEN_STR(x) GREEN_STR2(x)
+const char* green_build_info(void) {
+  return "sources=" GREEN_SOURCE_DIGEST " arch=" GREEN_TARGET_ARCH " hip=" GREEN_STR(HIP_VERSION_MAJOR) "." GREEN_STR(
+      HIP_VERSION_MINOR);
+}
+
 int green_plan_tuning_report(const green_plan* p, char* buf, size_t len) {
   if (!p || !buf || len == 0) return GREEN_EINVAL;
   std::string out;

@@ -86,3 +86,20 @@ def test_entry_points_reject_null_plan(lib):
                                     ctypes.byref(rep), None, None) == -1
     assert lib.LIB.green_workspace_bytes(None) == 0
     lib.LIB.green_plan_destroy(None)
+
+
+def test_build_info_names_the_sources_beside_the_library(lib):
+    """The library records the digest of the sources it was built from; the binding loaded it, so the digest
+    equals that of the sources in the tree, and a different digest is refused."""
+    from paper_2406_18479_amd import build
+    info = dict(kv.split("=", 1) for kv in lib.BUILD_INFO.split())
+    assert info["sources"] == build.source_digest()
+    assert info["arch"] == "gfx950"
+    assert re.fullmatch(r"\d+\.\d+", info["hip"])
+    saved = lib.BUILD_INFO
+    try:
+        lib.BUILD_INFO = saved.replace(info["sources"], "0" * 16)
+        with pytest.raises(ImportError, match="other sources"):
+            lib._check_provenance()
+    finally:
+        lib.BUILD_INFO = saved
