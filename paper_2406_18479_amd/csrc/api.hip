@@ -56,7 +56,8 @@ struct green_plan {
   int nk = 0;
   int prec = GREEN_FP64;
   int tc = 1;  // tau nodes per contraction chunk
-  int big_stage1 = 1;  // split-BF16 stage-1 kernel: 0 = 64 x 64 tiles, 1 = 192 x 96, 2 = 192 x 64
+  int big_stage1 = 3;  // split-BF16 stage-1 kernel: 0 = 64 x 64 tiles, 1 = 192 x 96, 2 = 192 x 64, 3 = direct (p0_vg1,
+                      // even nao up to 64; else 1)
   int big_p0 = 1;      // split-BF16 P~0 stage-2 kernel: 1 = 192 x 96 tiles, 2 = 192 x 64, 3 = 320 x 64, 4 = 448 x 64,
                        // LDS-DMA 5 = 320 x 64, 6 = 192 x 128
                        // (set at plan creation from naux)
@@ -93,7 +94,8 @@ struct green_plan {
   std::vector<int32_t> qslot;
   // workspace regions
   Region r_TF_t2w, r_TF_w2t, r_TB_t2w, r_TB_w2t, r_Emass, r_wf, r_kadd, r_ksub, r_status, r_scal, r_partial;
-  Region r_P, r_Pw, r_T1, r_T2, r_gam, r_gamT, r_D, r_Sinfn, r_Sign, r_Sw, r_A, r_tr, r_split, r_Vx, r_Ptx, r_Gx, r_GTx;
+  Region r_P, r_Pw, r_T1, r_T2, r_gam, r_gamT, r_D, r_Sinfn, r_Sign, r_Sw, r_A, r_tr, r_split, r_Vx, r_Ptx, r_Gx, r_GTx,
+      r_Gimg;
   Region r_g2tab, r_Fp, r_Fm, r_X2, r_Z2;  // GF2 (empty until GREEN_OPT_GF2 is set)
   Region r_kneg, r_kc, r_ksubc, r_qc, r_kfill, r_krot;
   Region r_Vh;  // one partner slab of the half store (empty until GREEN_OPT_V_HALF is set)
@@ -683,6 +685,16 @@ int run_polarization(green_plan* p, const void* V, const void* G, void* P0, void
     Gs = at<void>(ws, p->r_Gx);
     sGs = span_ws(ws, p->r_Gx);
   }
+  // split BF16, even nao up to 64: stage 1 by the direct kernel, which reads G from its G^T images
+  const bool direct = bf && p->big_stage1 == 3 && green::vg1_ok(nao);
+  const int64_t img_units = direct ? green::vg1_image_units(nao) : 0;
+  if (direct) {
+    if ((int64_t)p->r_Gimg.bytes < ex.G / nG * img_units * 16) return GREEN_EINVAL;
+    void* img = at<void>(ws, p->r_Gimg);
+    GREEN_TRY(aux(s, [=](hipStream_t st_) {
+      return green::vg1_image(static_cast<const double2*>(G), img, nao, ex.G / nG, st_);
+    }));
+  }
   // P~0^{-q}(tau) = P~0^q(beta - tau)^T exactly (substitute k -> k + q and cycle the trace), and the grid is
   // symmetric (tau_{ntau-1-t} = beta - tau_t): only the transfers qc are contracted (q <= -q; with a point group
   // one orbit of each pair {O, -O}), the others are filled from them at the end; where -q lies in the orbit of q
@@ -712,21 +724,53 @@ int run_polarization(green_plan* p, const void* V, const void* G, void* P0, void
     for (int t0 = 0; t0 < t_end; t0 += p->tc) {
       const int tcn = std::min(p->tc, t_end - t0);
       for (int sp = 0; sp < ns; ++sp) {
+        if (direct) {
+          // T1[tt][k][(Q,d)][b] = sum_a V^{k,k+q}_{da}(Q) G^{k+q}_{ab}(tau_tt) and
+          // T2[tt][k][Q'][d][b] = sum_c V^{k+q,k}_{bc}(Q') G^k_{cd}(beta - tau_tt), each V row read once per chunk
+          // (every element read or written lies inside its region)
+          if ((int64_t)tcn * nk * nV * 8 > (int64_t)std::min(p->r_T1.bytes, p->r_T2.bytes) ||
+              (Vqn != Vq ? 2 : 1) * slab * 8 > (int64_t)p->r_Vx.bytes ||
+              ((int64_t)(sp + 1) * ntau) * nk * img_units * 16 > (int64_t)p->r_Gimg.bytes)
+            return GREEN_EINVAL;
+          green::Vg1Args va{};
+          va.img = static_cast<const char*>(at<void>(ws, p->r_Gimg)) + (int64_t)sp * ntau * nk * img_units * 16;
+          va.tcn = tcn;
+          va.tparts = 0;  // chosen by the launcher
+          va.nk = nk;
+          va.M = naux * nao;
+          va.nao = nao;
+          va.V = static_cast<const uint2*>(Vq);
+          va.vk = nullptr;
+          va.gk = kadd + q * nk;
+          va.T = static_cast<uint2*>(static_cast<void*>(T1));
+          va.t0 = t0;
+          va.tdir = 1;
+          GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::p0_vg1(va, false, st_); }));
+          green::Vg1Args vr = va;
+          vr.V = static_cast<const uint2*>(Vqn);
+          vr.vk = kadd + q * nk;
+          vr.gk = nullptr;
+          vr.T = static_cast<uint2*>(static_cast<void*>(T2));
+          vr.t0 = ntau - 1 - t0;
+          vr.tdir = -1;
+          GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::p0_vg1(vr, true, st_); }));
+        }
         // T1[tt][k][(Q,d)][b] = sum_a V^{k,k+q}_{da}(Q) G^{k+q}_{ab}(tau_tt): one GEMM per k with the tau
         // nodes of the chunk folded into N = (tt, b), so each V block is read once per chunk
-        GREEN_TRY(gemm(green::Site::P0_VG, "P0.VG", op(Vq, flat(nao), flat(1), bflat(nV), st), sVs,
+        if (!direct) GREEN_TRY(gemm(green::Site::P0_VG, "P0.VG", op(Vq, flat(nao), flat(1), bflat(nV), st), sVs,
                        op(eptr(Gs, st, ((int64_t)sp * ntau + t0) * nk * nG), flat(nao), two(nao, 1, (int64_t)nk * nG),
                           btwo(nk, nG, kadd + q * nk, 0, hadd + q * nk), st),
                        sGs, T1, sT1, flat(nao), two(nao, 1, (int64_t)nk * nV), bflat(nV), naux * nao, tcn * nao, nao,
-                       nk, cplx(1), cplx(0), s, stage1, tt, bf ? p->big_stage1 : 0));
+                       nk, cplx(1), cplx(0), s, stage1, tt, bf ? (p->big_stage1 == 3 ? 1 : p->big_stage1) : 0));
         // T2[tt][k][Q'][d][b] = sum_c V^{k+q,k}_{bc}(Q') G^k_{cd}(beta - tau_tt)   (stored transposed in (b, d));
         // N = (tt, d), G(beta - tau) walks the grid backwards
-        GREEN_TRY(gemm(green::Site::P0_VGrev, "P0.VGrev",
+        if (!direct) GREEN_TRY(gemm(green::Site::P0_VGrev, "P0.VGrev",
                        op(Vqn, flat(nao), flat(1), btwo(nk, nV, kadd + q * nk, 0, hadd + q * nk), st), sVn,
                        op(eptr(Gs, st, ((int64_t)sp * ntau + (ntau - 1 - t0)) * nk * nG), flat(nao),
                           two(nao, 1, -(int64_t)nk * nG), btwo(nk, nG, nullptr, 0), st),
                        sGs, T2, sT2, two(nao, 1, nG), two(nao, nao, (int64_t)nk * nV), bflat(nV), naux * nao,
-                       tcn * nao, nao, nk, cplx(1), cplx(0), s, stage1, tt, bf ? p->big_stage1 : 0));
+                       tcn * nao, nao, nk, cplx(1), cplx(0), s, stage1, tt,
+                       bf ? (p->big_stage1 == 3 ? 1 : p->big_stage1) : 0));
         // P0[q][t][Q][Q'] (+)= -(w/nk) sum_{k,(d,b)} T1[tt][k][Q][(d,b)] T2[tt][k][Q'][(d,b)]
         GREEN_TRY(gemm(green::Site::P0_Contract, "P0.contract",
                        op(T1, flat(nG), two((int32_t)nG, 1, nV), bflat((int64_t)nk * nV), tt), sT1,
@@ -1825,6 +1869,9 @@ int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, 
   take(p->r_Gx, prec == GREEN_BF16X3 ? (size_t)ns * ntau * nk * nG * 8 : 0);
   take(p->r_Ptx, prec == GREEN_BF16X3 ? (size_t)ntau * nP * 8 : 0);
   take(p->r_GTx, p->fuse_sig ? (size_t)ns * ntau * nk * nG * 8 : 0);
+  // split BF16 with an even nao up to 64: G^T images of every (spin, t, k) for the direct stage-1 kernel
+  take(p->r_Gimg, prec == GREEN_BF16X3 && green::vg1_ok((int)nao)
+                      ? (size_t)ns * ntau * nk * green::vg1_image_units((int)nao) * 16 : 0);
   p->ws_bytes = off;
   if (count_ops(p) != GREEN_OK) {
     delete p;
@@ -2282,7 +2329,7 @@ int green_plan_set_option(green_plan* p, int option, int value) {
       drop_graph(p);
       return GREEN_OK;
     case GREEN_OPT_STAGE1_TILE:
-      if (value < 0 || value > 2) return GREEN_EINVAL;
+      if (value < 0 || value > 3) return GREEN_EINVAL;
       p->big_stage1 = value;
       drop_graph(p);
       return GREEN_OK;

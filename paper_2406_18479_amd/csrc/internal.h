@@ -170,6 +170,29 @@ inline int64_t xgv_vblock(int nao) { return nao > 64 ? 80 * 80 : (int64_t)nao * 
 // row j, u = s with its low three bits XORed with (j >> 1) & 7; zero past nao.
 hipError_t xgv_vimage(const double2* in, void* out, int nao, int64_t blocks, hipStream_t s);
 hipError_t sigma_xgv(const XgvArgs& a, const ZGemm& reduce, hipStream_t s);
+// Stage 1 of P~0 in split BF16 for one tau chunk, as a dedicated kernel (even nao up to kVg1MaxNao):
+//   rev = false (P0_VG):    T[tt][k][n][g]                = sum_a V[vk(k)][n][a] G[t(tt)][gk(k)][a][g]
+//   rev = true  (P0_VGrev): T[tt][k][n / nao][g][n % nao] = sum_c V[vk(k)][n][c] G[t(tt)][gk(k)][c][g]
+// with t(tt) = t0 + tdir tt, rows n < M = naux nao, g < nao; V and T kCB16, G read from its G^T images
+// (vg1_image: one image of vg1_image_units(nao) 16-byte units per (t, k') of the spin, [t][k'] order).
+struct Vg1Args {
+  const uint2* V;      // element (kv nV + n) nao + a, nV = M nao
+  const int32_t* vk;   // device: k -> kv (nullptr: kv = k)
+  const void* img;     // G^T images, 16-byte aligned
+  const int32_t* gk;   // device: k -> k' (nullptr: k' = k)
+  uint2* T;            // tcn nk M nao elements
+  int32_t t0, tdir;    // image node of chunk node tt: t0 + tdir tt (tdir = 1 or -1)
+  int32_t tcn, tparts; // chunk nodes, and the parts of the chunk given to different workgroups (set by p0_vg1)
+  int32_t nk, M, nao;
+};
+constexpr int kVg1MaxNao = 64;
+int vg1_blocks(int nao);
+bool vg1_ok(int nao);
+int64_t vg1_image_units(int nao);
+// G^T images of `blocks` nao x nao complex FP64 blocks of `in` (rows 16 vg1_blocks(nao) of the transpose, split BF16,
+// zero past nao, swizzled as the kernel's LDS rows)
+hipError_t vg1_image(const double2* in, void* out, int nao, int64_t blocks, hipStream_t s);
+hipError_t p0_vg1(const Vg1Args& a, bool rev, hipStream_t s);
 // out[b][c][r] = in[b][r][c] rounded to kC32 or kCB16 (rows x cols matrices, batch of them).  quad (kCB16,
 // rows % 4 == 0): each output row holds its elements in groups of 4 as 4 hi words then 4 lo words.  rows_out >
 // rows: output rows of rows_out elements, the ones past rows zero (out[b][c][r] over r < rows_out; quad needs

@@ -1725,6 +1725,215 @@ __global__ __launch_bounds__(64 * NB * H) void sigma_xgv_kernel(const XgvArgs a)
   }
 }
 
+// P~0 stage 1 in split BF16 without a tile loop: both V G products of a tau chunk,
+//   P0_VG    T[tt][k][n][g]                 = sum_a V[vk(k)][n][a] G[t(tt)][gk(k)][a][g]        (n = (Q, d), g = b)
+//   P0_VGrev T[tt][k][n / nao][g][n % nao]  = sum_c V[vk(k)][n][c] G[t(tt)][gk(k)][c][g]        (n = (Q', b), g = d)
+// (the second stored transposed in its orbital pair).  A workgroup of four waves owns 256 rows n of one k and
+// a range of the chunk's tau nodes; each wave holds the split-BF16 fragments of its 64 rows (4 blocks of 16,
+// K = nao padded to 16 NB) in registers for the whole range, so V is read once, and per tau node the G^T image
+// of that node (16 NB rows g, K = a; zero past nao) is copied into one of two LDS buffers by LDS DMA while the
+// other is contracted.  The work per node is NB column blocks of 16 g: 6 NB MFMAs per row block (three split
+// products for each of C_re and C_im) on fragments read once from LDS and applied to the four row blocks, then
+// the block's 64 x 16 results are rounded to split BF16 and stored.  The bound is the HBM write of T (8 bytes
+// per complex element against 8 nao complex MACs, all of it at the 16 NB padding of K and g).
+// Products: P0_VG takes V as the A operand and the G^T image as B (B conjugated (re, -im) for the real part,
+// swapped (im, re) for the imaginary part), P0_VGrev the image as A (with those variants) and V as B; either way
+// the result tile has the row/column of the operand given as A.
+// 16-row blocks of V per wave: 2 for P0_VG (all column blocks accumulated at once), 4 for P0_VGrev
+constexpr int vg1_row_blocks(bool rev) { return rev ? 4 : 2; }
+
+template <int NB, bool REV>
+__global__ __launch_bounds__(256, 2) void p0_vg1_kernel(const Vg1Args a) {
+  constexpr int RB = vg1_row_blocks(REV);  // 16-row blocks of V per wave
+  constexpr int CH = 8 * NB;           // 16-byte units per image row
+  constexpr int UNITS = 16 * NB * CH;  // units per image
+  constexpr int NCP = UNITS / 64;      // wave-wide 1 KB copies per image
+  constexpr int CPW = (NCP + 3) / 4;   // copies per wave (the last ones only where NCP is not a multiple of 4)
+  static_assert(2 * UNITS * 16 <= 80 * 1024, "two images fit half of the LDS (two workgroups per CU)");
+  __shared__ __attribute__((aligned(16))) uint32_t Gs[2][UNITS * 4];
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g4 = lane >> 4, r16 = lane & 15;
+  const int nao = a.nao, M = a.M;
+  const int nrw = (M + 64 * RB - 1) / (64 * RB);
+  const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
+  const int rw = (int)(bid % nrw);
+  const int64_t rest = bid / nrw;
+  const int part = (int)(rest % a.tparts);
+  const int k = (int)(rest / a.tparts);
+  const int per = (a.tcn + a.tparts - 1) / a.tparts;
+  const int tb = part * per, te = min(a.tcn, tb + per);
+  if (tb >= te) return;  // uniform over the workgroup, before any barrier
+  const int kv = a.vk ? a.vk[k] : k, kg = a.gk ? a.gk[k] : k;
+  const int64_t nV = (int64_t)M * nao, nG = (int64_t)nao * nao;
+
+  // image of chunk node tt: copy c (c = wv, wv + 4, ...) moves units 64 c .. 64 c + 63, lane l the unit 64 c + l
+  const char* img = reinterpret_cast<const char*>(a.img) + lane * 16;
+  auto issue = [&](int tt, uint32_t* buf) {
+    const char* src = img + ((int64_t)(a.t0 + a.tdir * tt) * a.nk + kg) * (UNITS * 16);
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      const int c = wv + 4 * j;
+      if (NCP % 4 == 0 || c < NCP) dma16(src + c * 1024, buf + c * 256);
+    }
+  };
+  issue(tb, Gs[0]);
+
+  // this wave's rows n0 + 16 rb + r16 (rows past M read row M - 1; their results are not stored); complex
+  // a = 16 s + 4 g4 .. + 3 of a row as two 16-byte loads (a >= nao reads a = 0: finite values facing image
+  // zeros; nao even, so a pair never crosses the row end)
+  const int n0 = (rw * 4 + wv) * 16 * RB;
+  u4 vh[RB][NB], vl[RB][NB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    const int n = min(n0 + 16 * rb + r16, M - 1);
+    const uint2* row = a.V + (int64_t)kv * nV + (int64_t)n * nao;
+#pragma unroll
+    for (int s = 0; s < NB; ++s) {
+      u4 x[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int a0 = 16 * s + 4 * g4 + 2 * h;
+        x[h] = *reinterpret_cast<const u4*>(row + (a0 < nao ? a0 : 0));
+      }
+      vh[rb][s] = u4{x[0].x, x[0].z, x[1].x, x[1].z};
+      vl[rb][s] = u4{x[0].y, x[0].w, x[1].y, x[1].w};
+    }
+  }
+  wait_vm<0>();
+  barrier_only();
+  // byte offsets of this lane's results: P0_VG row n0 + 4 g4 (+ 16 rb + r), column r16 (+ 16 jt); P0_VGrev
+  // column n = n0 + 16 rb + r16 at (n / nao) nao^2 + n % nao, row 4 g4 (+ 16 jt + r)
+  uint32_t vofs0 = (uint32_t)(((int64_t)(n0 + 4 * g4) * nao + r16) * 8);
+  uint32_t vofs[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    const int n = min(n0 + 16 * rb + r16, M - 1), qn = n / nao;
+    vofs[rb] = (uint32_t)(((int64_t)qn * nG + (n - qn * nao) + 4 * g4 * nao) * 8);
+    asm volatile("" : "+v"(vofs[rb]));
+  }
+  asm volatile("" : "+v"(vofs0));
+  const int64_t rstep = (int64_t)nao * 8;  // bytes per row of nao elements
+  // store bounds: P0_VG rows 16 rb + r < M - n0 - 4 g4, columns 16 jt < nao - r16; P0_VGrev columns
+  // 16 rb < M - n0 - r16, rows 16 jt + r < nao - 4 g4
+  const int rlim = REV ? M - n0 - r16 : M - n0 - 4 * g4;
+  const int clim = REV ? nao - 4 * g4 : nao - r16;
+
+  for (int tt = tb; tt < te; ++tt) {
+    const int cur = (tt - tb) & 1;
+    // every wave's copies of this node's image landed (each wave waited for its own before its last stores of
+    // the previous node) and every wave is done with the other buffer
+    if (tt > tb) barrier_only();
+    if (tt + 1 < te) issue(tt + 1, Gs[cur ^ 1]);
+    const uint32_t* G = Gs[cur];
+    char* out = reinterpret_cast<char*>(a.T + (int64_t)tt * a.nk * nV + (int64_t)k * nV);
+    if constexpr (!REV) {
+      // P0_VG: accumulators of every column block live (RB = 2), so that each row's results are stored by
+      // consecutive instructions (a row of nao elements is complete when its lines leave the L2)
+      f4 cre[RB][NB], cim[RB][NB];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int jt = 0; jt < NB; ++jt) {
+          cre[rb][jt] = f4{0.f, 0.f, 0.f, 0.f};
+          cim[rb][jt] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+      for (int s = 0; s < NB; ++s)
+#pragma unroll
+        for (int jt = 0; jt < NB; ++jt) {
+          const int r = 16 * jt + r16;
+          const u4 gh = *reinterpret_cast<const u4*>(&G[xgv_word<NB>(r, 8 * s + 2 * g4)]);
+          const u4 gl = *reinterpret_cast<const u4*>(&G[xgv_word<NB>(r, 8 * s + 2 * g4 + 1)]);
+          const bf8 gch = as_bf8(neg_im(gh)), gcl = as_bf8(neg_im(gl));
+          const bf8 gsh = as_bf8(swap_re_im(gh)), gsl = as_bf8(swap_re_im(gl));
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) {
+            const bf8 xh = as_bf8(vh[rb][s]), xl = as_bf8(vl[rb][s]);
+            f4& cr = cre[rb][jt];
+            f4& ci = cim[rb][jt];
+            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, gch, cr, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, gsh, ci, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, gcl, cr, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, gsl, ci, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, gch, cr, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, gsh, ci, 0, 0, 0);
+          }
+        }
+      // result (n, g) = (n0 + 16 rb + 4 g4 + r, 16 jt + r16): row by row, the NB column blocks in turn.
+      // Address: the output base plus a uniform offset that walks the rows plus a 32-bit lane offset; the bounds
+      // are compared against lane limits kept opaque here, so that the compiler neither precomputes a scalar
+      // address nor an exec mask per store.
+      // (the copies of the next image were issued a whole node of MFMAs ago: waiting for them here, before the
+      // stores, keeps the stores out of the wait)
+      wait_vm<0>();
+      int64_t o = 0;
+      int lim = rlim, glim = clim;
+      asm volatile("" : "+v"(lim), "+v"(glim));
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+          for (int jt = 0; jt < NB; ++jt) {
+            uint32_t hi, lo;
+            split_pair_f(cre[rb][jt][r], cim[rb][jt][r], hi, lo);
+            if (16 * rb + r < lim && 16 * jt < glim)
+              *reinterpret_cast<uint2*>(out + o + 16 * jt * 8 + vofs0) = make_uint2(hi, lo);
+          }
+          o += (r < 3 ? 1 : 13) * rstep;
+          asm volatile("" : "+s"(o));
+        }
+    } else {
+#pragma unroll
+      for (int jt = 0; jt < NB; ++jt) {
+        f4 cre[RB], cim[RB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          cre[rb] = f4{0.f, 0.f, 0.f, 0.f};
+          cim[rb] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int s = 0; s < NB; ++s) {
+          const int r = 16 * jt + r16;
+          const u4 gh = *reinterpret_cast<const u4*>(&G[xgv_word<NB>(r, 8 * s + 2 * g4)]);
+          const u4 gl = *reinterpret_cast<const u4*>(&G[xgv_word<NB>(r, 8 * s + 2 * g4 + 1)]);
+          const bf8 gch = as_bf8(neg_im(gh)), gcl = as_bf8(neg_im(gl));
+          const bf8 gsh = as_bf8(swap_re_im(gh)), gsl = as_bf8(swap_re_im(gl));
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) {
+            const bf8 xh = as_bf8(vh[rb][s]), xl = as_bf8(vl[rb][s]);
+            cre[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gch, xh, cre[rb], 0, 0, 0);
+            cim[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gsh, xh, cim[rb], 0, 0, 0);
+            cre[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gcl, xh, cre[rb], 0, 0, 0);
+            cim[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gsl, xh, cim[rb], 0, 0, 0);
+            cre[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gch, xl, cre[rb], 0, 0, 0);
+            cim[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gsh, xl, cim[rb], 0, 0, 0);
+          }
+        }
+        // result (g, n) = (16 jt + 4 g4 + r, n0 + 16 rb + r16) at (n / nao) nao^2 + g nao + n % nao: for each
+        // row g the row blocks in turn (addressing and bounds as above)
+        if (jt == NB - 1) wait_vm<0>();  // the next image landed (before the node's last stores, as above)
+        int64_t o = (int64_t)16 * jt * rstep;
+        int lim = rlim, glim = clim;
+        asm volatile("" : "+v"(lim), "+v"(glim));
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) {
+            uint32_t hi, lo;
+            split_pair_f(cre[rb][r], cim[rb][r], hi, lo);
+            if (16 * rb < lim && 16 * jt + r < glim) *reinterpret_cast<uint2*>(out + o + vofs[rb]) = make_uint2(hi, lo);
+          }
+          o += rstep;
+          asm volatile("" : "+s"(o));
+        }
+      }
+    }
+  }
+}
+
 // Second pass of split-K: C = alpha * sum_slices partial + beta * C, slices added in order.
 __device__ __forceinline__ void splitk_body(const ZGemm& g, int64_t x0, int64_t stride) {
   const int64_t mn = (int64_t)g.M * g.N;
@@ -1882,14 +2091,20 @@ __global__ __launch_bounds__(256) void k_convert_c64_tr(const double2* __restric
   }
 }
 
-// LDS image of the 80 x 80 V^T blocks of the fused Sigma~ kernel (see xgv_vimage): one thread per 16-byte unit.
-__global__ __launch_bounds__(256) void k_xgv_vimage(const double2* __restrict__ in, u4* __restrict__ out, int nao,
-                                                    int64_t blocks) {
-  const int64_t n = blocks * 80 * 40;
+// LDS image of the transpose of n x n blocks (n = nao <= 16 NB), in the row layout of xgv_word<NB>: for block
+// blk of `in` (element (b, j) at b nao + j), 16 NB rows j of 8 NB 16-byte units, unit u holding the hi (u even)
+// or lo (u odd) words of the complex b = 4 (u / 2) .. + 3 of row j, stored at slot xgv_swz<NB>(j, u) of the row
+// (the swizzle is its own inverse); zero past nao.  One thread per 16-byte unit.  NB = 5: the V^T blocks of the
+// fused Sigma~ kernel (xgv_vimage); NB <= 4: the G^T images of the direct P~0 stage-1 kernel (vg1_image).
+template <int NB>
+__global__ __launch_bounds__(256) void k_tr_image(const double2* __restrict__ in, u4* __restrict__ out, int nao,
+                                                  int64_t blocks) {
+  constexpr int CH = 8 * NB, UNITS = 16 * NB * CH;
+  const int64_t n = blocks * UNITS;
   for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t blk = x / 3200;
-    const int e = (int)(x - blk * 3200), j = e / 40, sl = e - (e / 40) * 40;
-    const int u = (sl & ~7) | ((sl & 7) ^ ((j >> 1) & 7));
+    const int64_t blk = x / UNITS;
+    const int e = (int)(x - blk * UNITS), j = e / CH, sl = e - (e / CH) * CH;
+    const int u = xgv_swz<NB>(j, sl);
     const int b0 = 4 * (u >> 1), plane = u & 1;
     const double2* src = in + blk * nao * (int64_t)nao;
     uint32_t w[4];
@@ -2486,7 +2701,54 @@ hipError_t xgv_vimage(const double2* in, void* out, int nao, int64_t blocks, hip
   if (dryrun()) return hipSuccess;
   int64_t nb = (blocks * 3200 + 255) / 256;
   if (nb > 65536) nb = 65536;
-  k_xgv_vimage<<<dim3((unsigned)nb), dim3(256), 0, s>>>(in, static_cast<u4*>(out), nao, blocks);
+  k_tr_image<5><<<dim3((unsigned)nb), dim3(256), 0, s>>>(in, static_cast<u4*>(out), nao, blocks);
+  return hipGetLastError();
+}
+
+int vg1_blocks(int nao) { return (nao + 15) / 16; }
+bool vg1_ok(int nao) { return nao > 0 && nao % 2 == 0 && nao <= kVg1MaxNao; }
+int64_t vg1_image_units(int nao) { return 128 * (int64_t)vg1_blocks(nao) * vg1_blocks(nao); }
+
+hipError_t vg1_image(const double2* in, void* out, int nao, int64_t blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  if (!vg1_ok(nao)) return hipErrorInvalidValue;
+  if (dryrun()) return hipSuccess;
+  int64_t nb = (blocks * vg1_image_units(nao) + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  u4* o = static_cast<u4*>(out);
+  switch (vg1_blocks(nao)) {
+    case 1: k_tr_image<1><<<dim3((unsigned)nb), dim3(256), 0, s>>>(in, o, nao, blocks); break;
+    case 2: k_tr_image<2><<<dim3((unsigned)nb), dim3(256), 0, s>>>(in, o, nao, blocks); break;
+    case 3: k_tr_image<3><<<dim3((unsigned)nb), dim3(256), 0, s>>>(in, o, nao, blocks); break;
+    default: k_tr_image<4><<<dim3((unsigned)nb), dim3(256), 0, s>>>(in, o, nao, blocks); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t p0_vg1(const Vg1Args& a, bool rev, hipStream_t s) {
+  if (a.tcn <= 0 || a.nk <= 0 || a.M <= 0) return hipSuccess;
+  if (!vg1_ok(a.nao) || a.M % a.nao != 0 || (a.tdir != 1 && a.tdir != -1)) return hipErrorInvalidValue;
+  // the kernel's 32-bit lane offsets address one k's M nao elements
+  if ((int64_t)a.M * a.nao * 8 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  if (dryrun()) return hipSuccess;
+  // workgroups: row groups x momenta x parts of the chunk, the chunk split until about 2048 workgroups (eight
+  // per CU slot pair) or one node per part
+  Vg1Args b = a;
+  const int rows = 64 * vg1_row_blocks(rev);
+  const int64_t nrw = (a.M + rows - 1) / rows;
+  b.tparts = 1;
+  while (b.tparts < a.tcn && nrw * a.nk * b.tparts < 2048) ++b.tparts;
+  const dim3 grid((unsigned)(nrw * a.nk * b.tparts)), block(256);
+  switch (vg1_blocks(a.nao) * 2 + (rev ? 1 : 0)) {
+    case 2: p0_vg1_kernel<1, false><<<grid, block, 0, s>>>(b); break;
+    case 3: p0_vg1_kernel<1, true><<<grid, block, 0, s>>>(b); break;
+    case 4: p0_vg1_kernel<2, false><<<grid, block, 0, s>>>(b); break;
+    case 5: p0_vg1_kernel<2, true><<<grid, block, 0, s>>>(b); break;
+    case 6: p0_vg1_kernel<3, false><<<grid, block, 0, s>>>(b); break;
+    case 7: p0_vg1_kernel<3, true><<<grid, block, 0, s>>>(b); break;
+    case 8: p0_vg1_kernel<4, false><<<grid, block, 0, s>>>(b); break;
+    default: p0_vg1_kernel<4, true><<<grid, block, 0, s>>>(b); break;
+  }
   return hipGetLastError();
 }
 

@@ -92,7 +92,7 @@ class Plan:
         return (self.nk, self.nao, self.nao)
 
     def set_option(self, option: str, value: int) -> None:
-        """option "tune" (0, 1, 2), "graph" (0, 1), "p0_tile" (1..11), "sigma_tile" (1..11), "stage1_tile" (0..2), "sigma_fused"
+        """option "tune" (0, 1, 2), "graph" (0, 1), "p0_tile" (1..13), "sigma_tile" (1..13), "stage1_tile" (0..3), "sigma_fused"
         (0, 1), "gf2" (0, 1), "time_reversal" (0, 1) or "v_half" (0, 1: V holds the canonical-q slabs only,
         shape_V follows); see green_plan_set_option.  The workspace is re-allocated when the option grows it."""
         code = {"tune": _lib.OPT_TUNE, "graph": _lib.OPT_GRAPH, "p0_tile": _lib.OPT_P0_TILE,

@@ -144,9 +144,9 @@ def test_plan_options_and_tuning_report(lib):
         assert L.green_plan_set_option(h, lib.OPT_P0_TILE, 14) == -1
         assert L.green_plan_set_option(h, lib.OPT_SIGMA_TILE, 0) == -1
         assert L.green_plan_set_option(h, lib.OPT_SIGMA_TILE, 14) == -1
-        for v in (0, 1, 2):
+        for v in (0, 1, 2, 3):
             assert L.green_plan_set_option(h, lib.OPT_STAGE1_TILE, v) == 0
-        assert L.green_plan_set_option(h, lib.OPT_STAGE1_TILE, 3) == -1
+        assert L.green_plan_set_option(h, lib.OPT_STAGE1_TILE, 4) == -1
         assert L.green_plan_set_option(h, lib.OPT_SIGMA_FUSED, 0) == 0
         assert L.green_plan_set_option(h, lib.OPT_SIGMA_FUSED, 2) == -1
         assert L.green_plan_set_option(h, 99, 0) == -1

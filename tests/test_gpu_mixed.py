@@ -89,6 +89,35 @@ def test_split_bf16_p0_tiles(tile, nao):
     assert rel(Pmx, P64) <= REL["bf16x3"]
 
 
+STAGE1 = [dict(kmesh=(2, 1, 1), nao=8, naux=40, ntau=10, nspin=1, seed=221),   # 16-wide blocks, ragged rows
+          dict(kmesh=(3, 1, 1), nao=26, naux=50, ntau=8, nspin=2, seed=222),   # 32-wide blocks, two spins
+          dict(kmesh=(2, 2, 1), nao=40, naux=30, ntau=12, nspin=1, seed=223),  # 48-wide blocks
+          dict(kmesh=(2, 1, 1), nao=52, naux=70, ntau=6, nspin=1, seed=224),   # 64-wide blocks, padded
+          dict(kmesh=(1, 1, 1), nao=64, naux=33, ntau=6, nspin=1, seed=225),   # 64-wide blocks, no padding
+          dict(kmesh=(2, 2, 1), nao=64, naux=300, ntau=20, nspin=1, seed=226)]  # 3 tau nodes per workgroup
+
+
+@pytest.mark.parametrize("c", STAGE1, ids=lambda c: f"nao{c['nao']}_naux{c['naux']}_ns{c['nspin']}")
+def test_split_bf16_stage1_direct(c):
+    """The direct P~0 stage-1 kernel (V rows in registers over the tau chunk, G^T per node in LDS) against the
+    192 x 96 tile kernel of the same split-BF16 plan (same products and roundings, other blocking) and against
+    the FP64 path, for every block width (nao up to 16, 32, 48, 64), ragged row counts (naux nao not a
+    multiple of 256), two spins, and a shape whose chunk is split into parts of several tau nodes."""
+    _require_gpu()
+    s = systems.make_system(configs.tiny(kmesh=c["kmesh"], nao=c["nao"], naux=c["naux"], ntau=c["ntau"], beta=8.0,
+                                         nspin=c["nspin"], seed=c["seed"], v_scale=0.5 / c["nao"] ** 0.5))
+    print("[gpu-case] direct stage-1 kernel", c, flush=True)
+    V, G = dev(s.V), dev(s.G0)
+    p64, pmx = plan(s, "fp64"), plan(s, "bf16x3")
+    P64 = host(p64.polarization(V, G))
+    pmx.set_option("stage1_tile", 3)
+    Pd = host(pmx.polarization(V, G))
+    pmx.set_option("stage1_tile", 1)
+    Pt = host(pmx.polarization(V, G))
+    assert rel(Pd, Pt) <= 2e-6
+    assert rel(Pd, P64) <= REL["bf16x3"]
+
+
 @pytest.mark.parametrize("tile", [5, 6, 7, 8, 9, 10, 11, 12, 13])
 @pytest.mark.parametrize("naux", [300, 52, 64, 70])
 def test_split_bf16_sigma_tiles(tile, naux):
