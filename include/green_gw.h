@@ -299,7 +299,7 @@ int green_gw_iterate_diis(green_plan* plan, const void* V, const void* H0, const
  *                   index (values as GREEN_OPT_P0_TILE; default 6).
  *   GREEN_OPT_STAGE1_TILE  split-BF16 plans: kernel of the V G products that feed it: 0 = 64 x 64 tiles,
  *                   1 = 192 x 96 tiles, 2 = 192 x 64 tiles, 3 (default) = the direct kernel (V rows held in
- *                   registers over a tau chunk, G^T of each tau node staged in LDS; even nao up to 64, else 1).
+ *                   registers over a tau chunk, G^T of each tau node staged in LDS; even nao up to 80, else 1).
  *                   Both only change the summation blocking; results agree to rounding.
  *   GREEN_OPT_SIGMA_FUSED  split-BF16 plans with an even nao up to 80: 1 (default) runs the two contractions
  *                   of Eqs. sigma_gw and tilde_W_DF2 after P~^T V (over the orbital a with G(tau), then over (Q', b)

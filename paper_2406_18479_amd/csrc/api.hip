@@ -57,7 +57,7 @@ struct green_plan {
   int prec = GREEN_FP64;
   int tc = 1;  // tau nodes per contraction chunk
   int big_stage1 = 3;  // split-BF16 stage-1 kernel: 0 = 64 x 64 tiles, 1 = 192 x 96, 2 = 192 x 64, 3 = direct (p0_vg1,
-                      // even nao up to 64; else 1)
+                      // even nao up to 80; else 1)
   int big_p0 = 1;      // split-BF16 P~0 stage-2 kernel: 1 = 192 x 96 tiles, 2 = 192 x 64, 3 = 320 x 64, 4 = 448 x 64,
                        // LDS-DMA 5 = 320 x 64, 6 = 192 x 128
                        // (set at plan creation from naux)
@@ -685,7 +685,7 @@ int run_polarization(green_plan* p, const void* V, const void* G, void* P0, void
     Gs = at<void>(ws, p->r_Gx);
     sGs = span_ws(ws, p->r_Gx);
   }
-  // split BF16, even nao up to 64: stage 1 by the direct kernel, which reads G from its G^T images
+  // split BF16, even nao up to 80: stage 1 by the direct kernel, which reads G from its G^T images
   const bool direct = bf && p->big_stage1 == 3 && green::vg1_ok(nao);
   const int64_t img_units = direct ? green::vg1_image_units(nao) : 0;
   if (direct) {
@@ -1869,7 +1869,7 @@ int green_plan_create(const green_dims* dims, const green_grid* grid, int prec, 
   take(p->r_Gx, prec == GREEN_BF16X3 ? (size_t)ns * ntau * nk * nG * 8 : 0);
   take(p->r_Ptx, prec == GREEN_BF16X3 ? (size_t)ntau * nP * 8 : 0);
   take(p->r_GTx, p->fuse_sig ? (size_t)ns * ntau * nk * nG * 8 : 0);
-  // split BF16 with an even nao up to 64: G^T images of every (spin, t, k) for the direct stage-1 kernel
+  // split BF16 with an even nao up to 80: G^T images of every (spin, t, k) for the direct stage-1 kernel
   take(p->r_Gimg, prec == GREEN_BF16X3 && green::vg1_ok((int)nao)
                       ? (size_t)ns * ntau * nk * green::vg1_image_units((int)nao) * 16 : 0);
   p->ws_bytes = off;

@@ -185,7 +185,7 @@ struct Vg1Args {
   int32_t tcn, tparts; // chunk nodes, and the parts of the chunk given to different workgroups (set by p0_vg1)
   int32_t nk, M, nao;
 };
-constexpr int kVg1MaxNao = 64;
+constexpr int kVg1MaxNao = 80;
 int vg1_blocks(int nao);
 bool vg1_ok(int nao);
 int64_t vg1_image_units(int nao);

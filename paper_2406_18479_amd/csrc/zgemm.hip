@@ -1739,24 +1739,28 @@ __global__ __launch_bounds__(64 * NB * H) void sigma_xgv_kernel(const XgvArgs a)
 // Products: P0_VG takes V as the A operand and the G^T image as B (B conjugated (re, -im) for the real part,
 // swapped (im, re) for the imaginary part), P0_VGrev the image as A (with those variants) and V as B; either way
 // the result tile has the row/column of the operand given as A.
-// 16-row blocks of V per wave: 2 for P0_VG (all column blocks accumulated at once), 4 for P0_VGrev
-constexpr int vg1_row_blocks(bool rev) { return rev ? 4 : 2; }
+// 16-row blocks of V per wave: 2 for P0_VG (all column blocks accumulated at once), 4 for P0_VGrev (3 with the
+// 80-row images, whose V fragments take 5/4 of the registers); waves per workgroup: 4 (two workgroups per CU),
+// 8 with the 80-row images (two 51 KB images per workgroup, one workgroup per CU)
+constexpr int vg1_row_blocks(int nb, bool rev) { return rev ? (nb == 5 ? 3 : 4) : 2; }
+constexpr int vg1_waves(int nb) { return nb == 5 ? 8 : 4; }
 
 template <int NB, bool REV>
-__global__ __launch_bounds__(256, 2) void p0_vg1_kernel(const Vg1Args a) {
-  constexpr int RB = vg1_row_blocks(REV);  // 16-row blocks of V per wave
-  constexpr int CH = 8 * NB;           // 16-byte units per image row
-  constexpr int UNITS = 16 * NB * CH;  // units per image
-  constexpr int NCP = UNITS / 64;      // wave-wide 1 KB copies per image
-  constexpr int CPW = (NCP + 3) / 4;   // copies per wave (the last ones only where NCP is not a multiple of 4)
-  static_assert(2 * UNITS * 16 <= 80 * 1024, "two images fit half of the LDS (two workgroups per CU)");
+__global__ __launch_bounds__(64 * vg1_waves(NB), 8 / vg1_waves(NB)) void p0_vg1_kernel(const Vg1Args a) {
+  constexpr int RB = vg1_row_blocks(NB, REV);  // 16-row blocks of V per wave
+  constexpr int W = vg1_waves(NB);             // waves per workgroup
+  constexpr int CH = 8 * NB;                   // 16-byte units per image row
+  constexpr int UNITS = 16 * NB * CH;          // units per image
+  constexpr int NCP = UNITS / 64;              // wave-wide 1 KB copies per image
+  constexpr int CPW = (NCP + W - 1) / W;       // copies per wave (the last ones only where W does not divide NCP)
+  static_assert(2 * UNITS * 16 * (8 / W) <= 160 * 1024, "the workgroups of a CU fit the LDS");
   __shared__ __attribute__((aligned(16))) uint32_t Gs[2][UNITS * 4];
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g4 = lane >> 4, r16 = lane & 15;
   const int nao = a.nao, M = a.M;
-  const int nrw = (M + 64 * RB - 1) / (64 * RB);
+  const int nrw = (M + 16 * RB * W - 1) / (16 * RB * W);
   const int64_t bid = xcd_block(blockIdx.x, gridDim.x);
   const int rw = (int)(bid % nrw);
   const int64_t rest = bid / nrw;
@@ -1768,14 +1772,14 @@ __global__ __launch_bounds__(256, 2) void p0_vg1_kernel(const Vg1Args a) {
   const int kv = a.vk ? a.vk[k] : k, kg = a.gk ? a.gk[k] : k;
   const int64_t nV = (int64_t)M * nao, nG = (int64_t)nao * nao;
 
-  // image of chunk node tt: copy c (c = wv, wv + 4, ...) moves units 64 c .. 64 c + 63, lane l the unit 64 c + l
+  // image of chunk node tt: copy c (c = wv, wv + W, ...) moves units 64 c .. 64 c + 63, lane l the unit 64 c + l
   const char* img = reinterpret_cast<const char*>(a.img) + lane * 16;
   auto issue = [&](int tt, uint32_t* buf) {
     const char* src = img + ((int64_t)(a.t0 + a.tdir * tt) * a.nk + kg) * (UNITS * 16);
 #pragma unroll
     for (int j = 0; j < CPW; ++j) {
-      const int c = wv + 4 * j;
-      if (NCP % 4 == 0 || c < NCP) dma16(src + c * 1024, buf + c * 256);
+      const int c = wv + W * j;
+      if (NCP % W == 0 || c < NCP) dma16(src + c * 1024, buf + c * 256);
     }
   };
   issue(tb, Gs[0]);
@@ -1783,7 +1787,7 @@ __global__ __launch_bounds__(256, 2) void p0_vg1_kernel(const Vg1Args a) {
   // this wave's rows n0 + 16 rb + r16 (rows past M read row M - 1; their results are not stored); complex
   // a = 16 s + 4 g4 .. + 3 of a row as two 16-byte loads (a >= nao reads a = 0: finite values facing image
   // zeros; nao even, so a pair never crosses the row end)
-  const int n0 = (rw * 4 + wv) * 16 * RB;
+  const int n0 = (rw * W + wv) * 16 * RB;
   u4 vh[RB][NB], vl[RB][NB];
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
@@ -1820,6 +1824,23 @@ __global__ __launch_bounds__(256, 2) void p0_vg1_kernel(const Vg1Args a) {
   const int rlim = REV ? M - n0 - r16 : M - n0 - 4 * g4;
   const int clim = REV ? nao - 4 * g4 : nao - r16;
 
+  // image fragment of column block jt, K block s (rows 16 jt + r16, complex 16 s + 4 g4 .. + 3) as hi and lo
+  // words; with the 80-row images the swizzle depends on r16 alone, so a read is one of two lane bases plus a
+  // constant
+  const int sw5 = (r16 >> 1) & 7;
+  const int wh5 = (r16 * CH + ((2 * g4) ^ sw5)) * 4, wl5 = (r16 * CH + ((2 * g4 + 1) ^ sw5)) * 4;
+  auto gfrag = [&](const uint32_t* G, int jt, int s, u4& hi, u4& lo) {
+    if constexpr (NB == 5) {
+      const int c = (16 * jt * CH + 8 * s) * 4;
+      hi = *reinterpret_cast<const u4*>(&G[wh5 + c]);
+      lo = *reinterpret_cast<const u4*>(&G[wl5 + c]);
+    } else {
+      const int r = 16 * jt + r16;
+      hi = *reinterpret_cast<const u4*>(&G[xgv_word<NB>(r, 8 * s + 2 * g4)]);
+      lo = *reinterpret_cast<const u4*>(&G[xgv_word<NB>(r, 8 * s + 2 * g4 + 1)]);
+    }
+  };
+
   for (int tt = tb; tt < te; ++tt) {
     const int cur = (tt - tb) & 1;
     // every wave's copies of this node's image landed (each wave waited for its own before its last stores of
@@ -1843,9 +1864,8 @@ __global__ __launch_bounds__(256, 2) void p0_vg1_kernel(const Vg1Args a) {
       for (int s = 0; s < NB; ++s)
 #pragma unroll
         for (int jt = 0; jt < NB; ++jt) {
-          const int r = 16 * jt + r16;
-          const u4 gh = *reinterpret_cast<const u4*>(&G[xgv_word<NB>(r, 8 * s + 2 * g4)]);
-          const u4 gl = *reinterpret_cast<const u4*>(&G[xgv_word<NB>(r, 8 * s + 2 * g4 + 1)]);
+          u4 gh, gl;
+          gfrag(G, jt, s, gh, gl);
           const bf8 gch = as_bf8(neg_im(gh)), gcl = as_bf8(neg_im(gl));
           const bf8 gsh = as_bf8(swap_re_im(gh)), gsl = as_bf8(swap_re_im(gl));
 #pragma unroll
@@ -1896,9 +1916,8 @@ __global__ __launch_bounds__(256, 2) void p0_vg1_kernel(const Vg1Args a) {
         }
 #pragma unroll
         for (int s = 0; s < NB; ++s) {
-          const int r = 16 * jt + r16;
-          const u4 gh = *reinterpret_cast<const u4*>(&G[xgv_word<NB>(r, 8 * s + 2 * g4)]);
-          const u4 gl = *reinterpret_cast<const u4*>(&G[xgv_word<NB>(r, 8 * s + 2 * g4 + 1)]);
+          u4 gh, gl;
+          gfrag(G, jt, s, gh, gl);
           const bf8 gch = as_bf8(neg_im(gh)), gcl = as_bf8(neg_im(gl));
           const bf8 gsh = as_bf8(swap_re_im(gh)), gsl = as_bf8(swap_re_im(gl));
 #pragma unroll
@@ -2720,7 +2739,8 @@ hipError_t vg1_image(const double2* in, void* out, int nao, int64_t blocks, hipS
     case 1: k_tr_image<1><<<dim3((unsigned)nb), dim3(256), 0, s>>>(in, o, nao, blocks); break;
     case 2: k_tr_image<2><<<dim3((unsigned)nb), dim3(256), 0, s>>>(in, o, nao, blocks); break;
     case 3: k_tr_image<3><<<dim3((unsigned)nb), dim3(256), 0, s>>>(in, o, nao, blocks); break;
-    default: k_tr_image<4><<<dim3((unsigned)nb), dim3(256), 0, s>>>(in, o, nao, blocks); break;
+    case 4: k_tr_image<4><<<dim3((unsigned)nb), dim3(256), 0, s>>>(in, o, nao, blocks); break;
+    default: k_tr_image<5><<<dim3((unsigned)nb), dim3(256), 0, s>>>(in, o, nao, blocks); break;
   }
   return hipGetLastError();
 }
@@ -2734,12 +2754,14 @@ hipError_t p0_vg1(const Vg1Args& a, bool rev, hipStream_t s) {
   // workgroups: row groups x momenta x parts of the chunk, the chunk split until about 2048 workgroups (eight
   // per CU slot pair) or one node per part
   Vg1Args b = a;
-  const int rows = 64 * vg1_row_blocks(rev);
+  const int nb = vg1_blocks(a.nao);
+  const int rows = 16 * vg1_row_blocks(nb, rev) * vg1_waves(nb);
   const int64_t nrw = (a.M + rows - 1) / rows;
+  const int64_t target = 2048 * 4 / vg1_waves(nb);
   b.tparts = 1;
-  while (b.tparts < a.tcn && nrw * a.nk * b.tparts < 2048) ++b.tparts;
-  const dim3 grid((unsigned)(nrw * a.nk * b.tparts)), block(256);
-  switch (vg1_blocks(a.nao) * 2 + (rev ? 1 : 0)) {
+  while (b.tparts < a.tcn && nrw * a.nk * b.tparts < target) ++b.tparts;
+  const dim3 grid((unsigned)(nrw * a.nk * b.tparts)), block(64 * vg1_waves(nb));
+  switch (nb * 2 + (rev ? 1 : 0)) {
     case 2: p0_vg1_kernel<1, false><<<grid, block, 0, s>>>(b); break;
     case 3: p0_vg1_kernel<1, true><<<grid, block, 0, s>>>(b); break;
     case 4: p0_vg1_kernel<2, false><<<grid, block, 0, s>>>(b); break;
@@ -2747,7 +2769,9 @@ hipError_t p0_vg1(const Vg1Args& a, bool rev, hipStream_t s) {
     case 6: p0_vg1_kernel<3, false><<<grid, block, 0, s>>>(b); break;
     case 7: p0_vg1_kernel<3, true><<<grid, block, 0, s>>>(b); break;
     case 8: p0_vg1_kernel<4, false><<<grid, block, 0, s>>>(b); break;
-    default: p0_vg1_kernel<4, true><<<grid, block, 0, s>>>(b); break;
+    case 9: p0_vg1_kernel<4, true><<<grid, block, 0, s>>>(b); break;
+    case 10: p0_vg1_kernel<5, false><<<grid, block, 0, s>>>(b); break;
+    default: p0_vg1_kernel<5, true><<<grid, block, 0, s>>>(b); break;
   }
   return hipGetLastError();
 }

@@ -94,15 +94,19 @@ STAGE1 = [dict(kmesh=(2, 1, 1), nao=8, naux=40, ntau=10, nspin=1, seed=221),   #
           dict(kmesh=(2, 2, 1), nao=40, naux=30, ntau=12, nspin=1, seed=223),  # 48-wide blocks
           dict(kmesh=(2, 1, 1), nao=52, naux=70, ntau=6, nspin=1, seed=224),   # 64-wide blocks, padded
           dict(kmesh=(1, 1, 1), nao=64, naux=33, ntau=6, nspin=1, seed=225),   # 64-wide blocks, no padding
-          dict(kmesh=(2, 2, 1), nao=64, naux=300, ntau=20, nspin=1, seed=226)]  # 3 tau nodes per workgroup
+          dict(kmesh=(2, 2, 1), nao=64, naux=300, ntau=20, nspin=1, seed=226),  # 3 tau nodes per workgroup
+          dict(kmesh=(2, 1, 1), nao=78, naux=40, ntau=6, nspin=2, seed=227),    # 80-wide blocks, two spins
+          dict(kmesh=(1, 1, 1), nao=66, naux=31, ntau=6, nspin=1, seed=228),    # 80-wide blocks, mostly padding
+          dict(kmesh=(2, 2, 1), nao=80, naux=400, ntau=12, nspin=1, seed=229)]  # 80-wide, 4 nodes per workgroup
 
 
 @pytest.mark.parametrize("c", STAGE1, ids=lambda c: f"nao{c['nao']}_naux{c['naux']}_ns{c['nspin']}")
 def test_split_bf16_stage1_direct(c):
     """The direct P~0 stage-1 kernel (V rows in registers over the tau chunk, G^T per node in LDS) against the
     192 x 96 tile kernel of the same split-BF16 plan (same products and roundings, other blocking) and against
-    the FP64 path, for every block width (nao up to 16, 32, 48, 64), ragged row counts (naux nao not a
-    multiple of 256), two spins, and a shape whose chunk is split into parts of several tau nodes."""
+    the FP64 path, for every block width (nao up to 16, 32, 48, 64, 80), ragged row counts (naux nao not a
+    multiple of the rows of a workgroup), two spins, and shapes whose chunk is split into parts of several tau
+    nodes."""
     _require_gpu()
     s = systems.make_system(configs.tiny(kmesh=c["kmesh"], nao=c["nao"], naux=c["naux"], ntau=c["ntau"], beta=8.0,
                                          nspin=c["nspin"], seed=c["seed"], v_scale=0.5 / c["nao"] ** 0.5))
