@@ -619,16 +619,18 @@ def build_record() -> dict:
 MFMA_PER_ALG = {"fp64": 1.0, "fp32": 1.0, "bf16x3": 3.0}
 
 
-def measured_traffic(workload: str, precision: str, kernel: str):
+def measured_traffic(workload: str, precision: str, kernel: str, chunk_mib: int = 0):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary (FETCH_SIZE +
-    WRITE_SIZE, copy-calibrated), when it covers this workload, precision and kernel; else None."""
+    WRITE_SIZE, copy-calibrated), when it covers this workload, precision, kernel and contraction chunk (lines
+    without a chunk_mib key were measured at the default chunk, 0); else None."""
     import glob
     for f in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.md")):
         for line in open(f):
             if line.startswith("traffic_bytes_per_launch:"):
                 tok = line.split()
                 kv = dict(t.split("=", 1) for t in tok[2:])
-                if kv.get("workload") == workload and kv.get("precision") == precision and kv.get("kernel") == kernel:
+                if (kv.get("workload") == workload and kv.get("precision") == precision and kv.get("kernel") == kernel
+                        and int(kv.get("chunk_mib", "0")) == chunk_mib):
                     return float(tok[1])
     return None
 
@@ -772,7 +774,7 @@ def main():
                    "naux": spec.naux, "ntau": spec.ntau, "nspin": spec.nspin, "beta": spec.beta,
                    "precision": head, "tuned": bool(args.tune), "graph": bool(args.graph),
                    "time_reversal": time_reversal_symmetric(spec), "point_group": spec.point_group or None,
-                   "v_half_store": bool(args.v_half)},
+                   "v_half_store": bool(args.v_half), "chunk_mib": args.chunk_mib or None},
         "flop_basis": "algorithmic: both contractions over every q, k and tau (4M counting)",
         "executed_tflops": round(h["sigma_eval_tflops"] * executed_fraction(spec), 4),
         "s_per_iteration": round(h["s_per_iteration"], 6),
@@ -795,7 +797,7 @@ def main():
         "roofline": {"bound": "mfma", "kernel": h["kernel_names"][dom], "achieved": round(achieved, 4), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                      "mfma_frac": round(achieved * MFMA_PER_ALG[head] / peak, 4),
-                     "traffic": measured_traffic(spec.name, head, h["kernel_names"][dom]),
+                     "traffic": measured_traffic(spec.name, head, h["kernel_names"][dom], args.chunk_mib),
                      "launches": k["launches"], "avg_launch_ms": round(k["ms"] / max(k["launches"], 1), 4),
                      "flops_per_launch": k["flops"] / max(k["launches"], 1)},
         "cpu_baseline": None,
