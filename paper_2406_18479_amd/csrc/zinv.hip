@@ -226,7 +226,8 @@ __global__ __launch_bounds__(256) void zinv_kernel(double2* __restrict__ A, int 
 
 // LDS per workgroup for the panel.  Measured on MI355X: a wider panel (up to 150 KiB) cuts the number of
 // full-matrix passes but costs occupancy and lengthens the serial column steps, and was slower for
-// naux = 180 than this 56 KiB budget (which also needs no raised dynamic-LDS limit).
+// naux = 180 than this 56 KiB budget (which also needs no raised dynamic-LDS limit); at naux = 300 (1918 matrices
+// per screening call) 100 and 150 KiB took the call from 82 ms to 100 and 97 ms.
 size_t lds_budget() { return 56 * 1024; }
 
 }  // namespace
