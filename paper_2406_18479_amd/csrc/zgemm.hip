@@ -1728,14 +1728,14 @@ __global__ __launch_bounds__(64 * NB * H) void sigma_xgv_kernel(const XgvArgs a)
 // P~0 stage 1 in split BF16 without a tile loop: both V G products of a tau chunk,
 //   P0_VG    T[tt][k][n][g]                 = sum_a V[vk(k)][n][a] G[t(tt)][gk(k)][a][g]        (n = (Q, d), g = b)
 //   P0_VGrev T[tt][k][n / nao][g][n % nao]  = sum_c V[vk(k)][n][c] G[t(tt)][gk(k)][c][g]        (n = (Q', b), g = d)
-// (the second stored transposed in its orbital pair).  A workgroup of four waves owns 256 rows n of one k and
-// a range of the chunk's tau nodes; each wave holds the split-BF16 fragments of its 64 rows (4 blocks of 16,
-// K = nao padded to 16 NB) in registers for the whole range, so V is read once, and per tau node the G^T image
-// of that node (16 NB rows g, K = a; zero past nao) is copied into one of two LDS buffers by LDS DMA while the
-// other is contracted.  The work per node is NB column blocks of 16 g: 6 NB MFMAs per row block (three split
-// products for each of C_re and C_im) on fragments read once from LDS and applied to the four row blocks, then
-// the block's 64 x 16 results are rounded to split BF16 and stored.  The bound is the HBM write of T (8 bytes
-// per complex element against 8 nao complex MACs, all of it at the 16 NB padding of K and g).
+// (the second stored transposed in its orbital pair).  A workgroup of W waves owns W RB 16 rows n of one k and a
+// range of the chunk's tau nodes; each wave holds the split-BF16 fragments of its RB blocks of 16 rows (K = nao
+// padded to 16 NB) in registers for the whole range, so V is read once per part of the chunk, and per tau node
+// the G^T image of that node (16 NB rows g, K = a; zero past nao) is copied into one of two LDS buffers by LDS
+// DMA while the other is contracted.  The work per node is NB x NB fragment groups (column block of 16 g, K block
+// of 16 complex), each read once from LDS and applied to the RB row blocks with 6 MFMAs (three split products for
+// each of C_re and C_im); the results are rounded to split BF16 and stored.  The bound is the HBM write of T
+// (8 bytes per complex element against 8 nao complex MACs, all of it at the 16 NB padding of K and g).
 // Products: P0_VG takes V as the A operand and the G^T image as B (B conjugated (re, -im) for the real part,
 // swapped (im, re) for the imaginary part), P0_VGrev the image as A (with those variants) and V as B; either way
 // the result tile has the row/column of the operand given as A.
