@@ -97,7 +97,12 @@ STAGE1 = [dict(kmesh=(2, 1, 1), nao=8, naux=40, ntau=10, nspin=1, seed=221),   #
           dict(kmesh=(2, 2, 1), nao=64, naux=300, ntau=20, nspin=1, seed=226),  # 3 tau nodes per workgroup
           dict(kmesh=(2, 1, 1), nao=78, naux=40, ntau=6, nspin=2, seed=227),    # 80-wide blocks, two spins
           dict(kmesh=(1, 1, 1), nao=66, naux=31, ntau=6, nspin=1, seed=228),    # 80-wide blocks, mostly padding
-          dict(kmesh=(2, 2, 1), nao=80, naux=400, ntau=12, nspin=1, seed=229)]  # 80-wide, 4 nodes per workgroup
+          dict(kmesh=(2, 2, 1), nao=80, naux=400, ntau=12, nspin=1, seed=229),  # 80-wide, 4 nodes per workgroup
+          dict(kmesh=(1, 1, 1), nao=2, naux=1, ntau=4, nspin=1, seed=230),     # smallest even nao, one aux row
+          dict(kmesh=(3, 1, 1), nao=16, naux=9, ntau=6, nspin=1, seed=231),    # exactly one 16-wide block
+          dict(kmesh=(2, 1, 1), nao=18, naux=7, ntau=6, nspin=2, seed=232),    # 32-wide, 2 valid in the last block
+          dict(kmesh=(1, 2, 1), nao=48, naux=5, ntau=8, nspin=1, seed=233),    # exactly three blocks
+          dict(kmesh=(2, 1, 1), nao=50, naux=6, ntau=6, nspin=1, seed=234)]    # 64-wide, 2 valid in the last block
 
 
 @pytest.mark.parametrize("c", STAGE1, ids=lambda c: f"nao{c['nao']}_naux{c['naux']}_ns{c['nspin']}")
