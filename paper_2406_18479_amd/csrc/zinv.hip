@@ -227,7 +227,9 @@ __global__ __launch_bounds__(256) void zinv_kernel(double2* __restrict__ A, int 
 // LDS per workgroup for the panel.  Measured on MI355X: a wider panel (up to 150 KiB) cuts the number of
 // full-matrix passes but costs occupancy and lengthens the serial column steps, and was slower for
 // naux = 180 than this 56 KiB budget (which also needs no raised dynamic-LDS limit); at naux = 300 (1918 matrices
-// per screening call) 100 and 150 KiB took the call from 82 ms to 100 and 97 ms.
+// per screening call) 100 and 150 KiB took the call from 82 ms to 100 and 97 ms.  Update blocks of 16 columns
+// instead of kCW = 8 (half the barriers of the update phase) took it to 118 ms: the 32 rows each thread then holds
+// leave one wave per SIMD.
 size_t lds_budget() { return 56 * 1024; }
 
 }  // namespace
