@@ -1218,6 +1218,18 @@ int run_hf(green_plan* p, const void* V, const void* G, void* Sinf, void* ws, hi
                    op(Vp, flat(nG), two((int32_t)nG, 1, nV), bnone()), sV, Sp + (int64_t)sp * nk * nG, sH, flat(0),
                    flat(1), bnone(), 1, (int)(nk * nG), naux, 1, cplx(1), cplx(0), s));
   // exchange: Sinf[s][k] -= (1/nk) sum_q sum_Q V^{k,k-q}(Q) gamma^{k-q} V^{k-q,k}(Q)
+  // With time reversal or a point group it runs for the contracted momenta kk = 0 .. nkx - 1 only, as the
+  // self-energy does: Sigma^inf(R k) = Sigma^inf(k) and Sigma^inf(-k) = conj Sigma^inf(k) hold for the Hartree term
+  // as well (V^{Rk,Rk} = V^{k,k}, V^{-k,-k} = conj V^{k,k}), so the whole of Sigma^inf of the other momenta is filled
+  // from the contracted ones at the end.
+  const bool tr = p->trev || p->ksym;
+  const int nkx = tr ? (int)p->kc.size() : nk;
+  const int32_t* kcan = at<int32_t>(ws, p->r_kc);
+  const int32_t* hcan = p->kc.data();
+  auto ktab = [&](int q) { return tr ? at<int32_t>(ws, p->r_ksubc) + (size_t)q * nkx : ksub + (size_t)q * nk; };
+  auto hktab = [&](int q) { return tr ? p->ksubc.data() + (size_t)q * nkx : hsub + (size_t)q * nk; };
+  const green::BatchMap vn_b = tr ? btwo(nkx, nV, kcan, 0, hcan) : bflat(nV);
+  const green::BatchMap hf_b = tr ? btwo(nkx, nG, kcan, 0, hcan) : bflat(nG);
   for (int q = 0; q < nk; ++q) {
     const int qn = p->kneg[q];
     const void *Vn = nullptr, *Vq = nullptr;
@@ -1225,14 +1237,18 @@ int run_hf(green_plan* p, const void* V, const void* G, void* Sinf, void* ws, hi
     GREEN_TRY(v_slab(p, V, qn, ws, s, &Vn, &sVn));
     GREEN_TRY(v_slab(p, V, q, ws, s, &Vq, &sVq));
     for (int sp = 0; sp < ns; ++sp) {
-      GREEN_TRY(gemm(green::Site::HF, "HF.Vgamma", op(Vn, flat(nao), flat(1), bflat(nV)), sVn,
-                     op(gam + (int64_t)sp * nk * nG, flat(nao), flat(1), btwo(nk, nG, ksub + q * nk, 0, hsub + q * nk)),
-                     sGam, T2, sT2, flat(nao), flat(1), bflat(nV), naux * nao, nao, nao, nk, cplx(1), cplx(0), s));
+      GREEN_TRY(gemm(green::Site::HF, "HF.Vgamma", op(Vn, flat(nao), flat(1), vn_b), sVn,
+                     op(gam + (int64_t)sp * nk * nG, flat(nao), flat(1), btwo(nkx, nG, ktab(q), 0, hktab(q))),
+                     sGam, T2, sT2, flat(nao), flat(1), bflat(nV), naux * nao, nao, nao, nkx, cplx(1), cplx(0), s));
       GREEN_TRY(gemm(green::Site::HF, "HF.exchange", op(T2, flat(nao), two(nao, 1, nG), bflat(nV)), sT2,
-                     op(Vq, two(nao, nao, nG), flat(1), btwo(nk, nV, ksub + q * nk, 0, hsub + q * nk)),
-                     sVq, Sp + (int64_t)sp * nk * nG, sH, flat(nao), flat(1), bflat(nG), nao, nao, naux * nao, nk,
+                     op(Vq, two(nao, nao, nG), flat(1), btwo(nkx, nV, ktab(q), 0, hktab(q))),
+                     sVq, Sp + (int64_t)sp * nk * nG, sH, flat(nao), flat(1), hf_b, nao, nao, naux * nao, nkx,
                      cplx(-1.0 / nk), cplx(1.0), s));
     }
+  }
+  if (tr) {
+    const int32_t* kfill = at<int32_t>(ws, p->r_kfill);
+    GREEN_TRY(aux(s, [=](hipStream_t st_) { return green::launch_fill_k(Sp, (int64_t)ns, nk, nG, kfill, st_); }));
   }
   return GREEN_OK;
 }

@@ -104,6 +104,7 @@ def test_iterations_match_oracle(group, trev, nspin):
         st, orep, _ = ogw.iterate(s, st)
         assert rel(host(Sig), st.Sig) <= 1e-10, it
         assert rel(host(G), st.G) <= 1e-10, it
+        assert rel(host(Sinf), st.Sinf) <= 1e-10, it  # Sigma^inf on the contracted momenta and their fill
         for key in ("e_1b", "e_hf", "e_corr", "e_tot"):
             assert abs(rep[key] - orep[key]) <= 1e-10, (it, key)
 

@@ -84,6 +84,7 @@ def test_time_reversal_iterations_match_oracle(c):
         hs = host(Sig)
         assert rel(hs, st.Sig) <= 1e-10, it
         assert rel(host(G), st.G) <= 1e-10, it
+        assert rel(host(Sinf), st.Sinf) <= 1e-10, it  # Sigma^inf on the contracted momenta and their fill
         _partners_exact(hs, sp.kmesh)
         for key in ("e_1b", "e_hf", "e_corr", "e_tot"):
             assert abs(rep[key] - orep[key]) <= 1e-10, (it, key)
