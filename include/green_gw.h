@@ -277,7 +277,7 @@ int green_gw_iterate_diis(green_plan* plan, const void* V, const void* H0, const
  *                   its candidate kernels (tile shape, large-tile kernel, split-K count; every candidate
  *                   computes the same contraction, differing only in summation order), timed with HIP
  *                   events, and the fastest is kept for all further calls of that shape on this plan (the
- *                   default unless a candidate is at least 3 % faster).
+ *                   default unless a candidate is at least 5 % faster).
  *                   Synchronises `stream` once per shape when its last candidate has run.
  *                   2: forget earlier choices and tune again.  0: stop tuning (choices are kept).
  *   GREEN_OPT_GRAPH 1: green_gw_iterate captures its Sigma evaluation (Hartree-Fock, polarization,

@@ -492,10 +492,11 @@ int gemm(green::Site site, const char* label, const ZOp& A, const green::Span& s
       for (hipEvent_t e : te->ev) (void)hipEventDestroy(e);
       te->ev.clear();
       // the fastest candidate, unless it beats the default (candidate 0, the descriptor as launched untuned) by
-      // less than 3 %: one timing per candidate carries about that much noise, and keeping the default then
-      // keeps the choice stable from run to run
+      // less than 5 %: one timing per candidate carries a few per cent of noise (a candidate measured 3 % faster
+      // once ran 2 % slower in the timed iterations), and keeping the default then keeps the choice stable from
+      // run to run
       const int best = (int)(std::min_element(te->ms.begin(), te->ms.end()) - te->ms.begin());
-      te->chosen = te->ms[best] < 0.97f * te->ms[0] ? best : 0;
+      te->chosen = te->ms[best] < 0.95f * te->ms[0] ? best : 0;
       te->done = true;
     }
     return GREEN_OK;
